@@ -1,0 +1,136 @@
+"""Seeded synthetic inputs for CP decomposition experiments.
+
+This module is shared by the test oracle and by the GPU library's tests and
+benchmark. It only draws random numbers and assembles input tensors; it holds
+none of the decomposition method's arithmetic (no MTTKRP, no solves, no
+perturbation operators).
+
+Workload families (Section 5.1 of the paper, "Sequential Experimental Results"):
+
+* planted tensors built from known factor matrices whose columns have a
+  prescribed collinearity (the paper defines collinearity as the common cosine
+  between distinct columns of each factor);
+* planted tensors built from uniformly distributed factors in [0, 1];
+* planted tensors with i.i.d. standard normal factors.
+
+Noise is added as eta * ||T||_F * E / ||E||_F with E i.i.d. N(0, 1), so the
+relative noise level is exactly eta.  Initial factors for ALS are uniform in
+[0, 1) (Algorithm 1, initialisation step).
+
+Seeds: ``np.random.SeedSequence(seed).spawn(3)`` gives three independent
+streams, used for (planted factors, noise, initial guess) in that order.
+"""
+from __future__ import annotations
+
+import dataclasses
+import numpy as np
+
+__all__ = [
+    "Problem",
+    "streams",
+    "planted_factors",
+    "cp_reconstruct",
+    "add_noise",
+    "init_factors",
+    "make_problem",
+]
+
+
+def streams(seed: int):
+    """Three independent generators (factors, noise, init) derived from one seed."""
+    ss = np.random.SeedSequence(seed).spawn(3)
+    return tuple(np.random.default_rng(s) for s in ss)
+
+
+def planted_factors(shape, rank, rng, dist="normal", collinearity=None):
+    """Factor matrices A^(n) of size s_n x rank.
+
+    dist="normal": i.i.d. N(0, 1) entries.
+    dist="uniform": i.i.d. U[0, 1) entries.
+    collinearity=C (0 <= C < 1): every column is sqrt(C) g + sqrt(1 - C) z_r with
+    one shared N(0, 1) vector g per mode and independent N(0, 1) vectors z_r,
+    then normalised to unit length.  The expected cosine between two columns
+    is C (the realised value fluctuates by O(s^-1/2)).
+    """
+    out = []
+    for s in shape:
+        if collinearity is not None:
+            c = float(collinearity)
+            g = rng.standard_normal((s, 1))
+            z = rng.standard_normal((s, rank))
+            a = np.sqrt(c) * g + np.sqrt(1.0 - c) * z
+            a /= np.linalg.norm(a, axis=0, keepdims=True)
+        elif dist == "normal":
+            a = rng.standard_normal((s, rank))
+        elif dist == "uniform":
+            a = rng.random((s, rank))
+        else:
+            raise ValueError(f"unknown factor distribution {dist!r}")
+        out.append(np.ascontiguousarray(a, dtype=np.float64))
+    return out
+
+
+def _krp_rows(mats):
+    """Row-wise Kronecker (Khatri-Rao) product, first matrix slowest."""
+    out = mats[0]
+    for m in mats[1:]:
+        out = (out[:, None, :] * m[None, :, :]).reshape(-1, m.shape[1])
+    return out
+
+
+def cp_reconstruct(factors):
+    """Dense tensor sum_r a_r^(1) o ... o a_r^(N), row-major (last mode fastest)."""
+    shape = tuple(a.shape[0] for a in factors)
+    if len(factors) == 1:
+        return factors[0].sum(axis=1)
+    rest = _krp_rows(factors[1:])  # (prod s_2..s_N) x R
+    return (factors[0] @ rest.T).reshape(shape)
+
+
+def add_noise(T, eta, rng, chunk=1 << 24):
+    """X = T + eta ||T||_F E / ||E||_F, E i.i.d. N(0, 1); returns a new float64 array."""
+    if eta == 0.0:
+        return np.array(T, dtype=np.float64, copy=True)
+    flat_t = T.reshape(-1)
+    E = np.empty_like(flat_t)
+    for lo in range(0, E.size, chunk):
+        hi = min(E.size, lo + chunk)
+        E[lo:hi] = rng.standard_normal(hi - lo)
+    nt = float(np.sqrt(np.dot(flat_t, flat_t)))
+    ne = float(np.sqrt(np.dot(E, E)))
+    scale = eta * nt / ne
+    E *= scale
+    E += flat_t
+    return E.reshape(T.shape)
+
+
+def init_factors(shape, rank, rng):
+    """Initial guess: uniform [0, 1) entries (Algorithm 1 initialisation)."""
+    return [np.ascontiguousarray(rng.random((s, rank)), dtype=np.float64) for s in shape]
+
+
+@dataclasses.dataclass
+class Problem:
+    X: np.ndarray            # float64 tensor, row-major, last mode fastest
+    planted: list            # planted factors
+    init: list               # initial factors for ALS
+    rank: int                # decomposition rank
+    eta: float               # relative noise level
+    seed: int
+
+    @property
+    def shape(self):
+        return self.X.shape
+
+
+def make_problem(shape, rank, seed, planted_rank=None, eta=1e-3, dist="normal",
+                 collinearity=None):
+    """Planted CP tensor plus noise, and a seeded uniform initial guess."""
+    g_fac, g_noise, g_init = streams(seed)
+    pr = rank if planted_rank is None else planted_rank
+    planted = planted_factors(shape, pr, g_fac, dist=dist, collinearity=collinearity)
+    T = cp_reconstruct(planted)
+    X = add_noise(T, eta, g_noise)
+    del T
+    init = init_factors(shape, rank, g_init)
+    return Problem(X=X, planted=planted, init=init, rank=rank, eta=eta, seed=seed)
