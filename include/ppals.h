@@ -1,0 +1,222 @@
+/*
+ * ppals.h -- C ABI of the MI355X pairwise-perturbation CP-ALS library.
+ *
+ * The library computes CP decompositions of dense tensors with alternating
+ * least squares (ALS, Algorithm 1 of Ma & Solomonik, "Accelerating Alternating
+ * Least Squares for Tensor Decomposition by Pairwise Perturbation") and with
+ * pairwise perturbation (PP-CP-ALS, Algorithm 3).  Notation follows the paper:
+ * X is an order-N tensor of size s_1 x .. x s_N, A^(n) are s_n x R factor
+ * matrices, S^(n) = A^(n)T A^(n), Gamma^(n) is the Hadamard product of the
+ * other modes' S, M^(n) is the MTTKRP right-hand side.
+ *
+ * Layout conventions (all row-major):
+ *   X        s_1 x .. x s_N, last mode fastest, FP64 or FP32 elements.
+ *   X_bf16   same shape, bfloat16 bit patterns (uint16), only for the BF16
+ *            first-level tier; produced by ppals_cast_bf16.
+ *   A[n]     s_n x R doubles (k fastest).  The factors are always FP64; the
+ *            FP32 / BF16 tiers convert them when they enter a contraction.
+ *   S        N consecutive R x R doubles, S[n] = A[n]^T A[n].
+ *
+ * Ownership: every device buffer (X, X_bf16, A[n], S, ws, records) is
+ * allocated and freed by the caller.  The entry points that take a stream
+ * never allocate device memory.  Pointer arrays (A) are host arrays of device
+ * pointers.  A plan is a host object owned by the caller
+ * (ppals_plan_create / ppals_plan_destroy).
+ *
+ * Errors: argument errors are detected on the host before anything is
+ * enqueued and return PPALS_E_ARG / PPALS_E_UNSUPPORTED; a failed launch
+ * returns PPALS_E_HIP.  ppals_last_error() returns a thread-local message for
+ * the last failure.  Numerical conditions found on the device (a Cholesky
+ * factorisation that needed the diagonal shift) are reported in the sweep
+ * record, because the calls are asynchronous.
+ *
+ * Streams: every call that takes a hipStream_t only enqueues work on it and
+ * returns without synchronising, except ppals_run, which drives a whole
+ * decomposition and synchronises once per sweep to read the sweep record.
+ */
+#ifndef PPALS_H
+#define PPALS_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PPALS_OK = 0,
+  PPALS_E_ARG = -1,          /* invalid argument (null pointer, bad size)        */
+  PPALS_E_UNSUPPORTED = -2,  /* valid but not supported (order, rank, dtype mix)  */
+  PPALS_E_HIP = -3,          /* a HIP runtime call or launch failed               */
+  PPALS_E_WORKSPACE = -4,    /* workspace pointer null while bytes are needed      */
+  PPALS_E_STATE = -5         /* pp_sweep before pp_build_operators                 */
+} ppals_status;
+
+typedef enum { PPALS_FP64 = 0, PPALS_FP32 = 1, PPALS_BF16 = 2 } ppals_dtype;
+
+typedef enum { PPALS_SWEEP_ALS = 0, PPALS_SWEEP_PP_INIT = 1, PPALS_SWEEP_PP_APPROX = 2 } ppals_sweep_kind;
+
+#define PPALS_MAX_ORDER 8
+#define PPALS_MAX_RANK 128
+
+/* Problem description.  Supported: 3 <= order <= 8, 1 <= rank <= 128,
+ * dims >= 1.  Precision tiers (tensor_dtype, level1_dtype):
+ *   (FP64, FP64)  every contraction in FP64;
+ *   (FP32, FP32)  contractions in FP32 with FP32 MFMA accumulation;
+ *   (FP32, BF16)  first-level contractions take bfloat16 inputs (X_bf16 and
+ *                 bf16-rounded factors) with FP32 accumulation, the rest FP32.
+ * Gram matrices, Hadamard products, Cholesky solves, norms and the fit are
+ * FP64 in every tier.  use_second_order selects the V^(n,i,j) correction of
+ * the general PP update (Section 3.2.1). */
+typedef struct {
+  int32_t order;
+  int32_t rank;
+  int64_t dims[PPALS_MAX_ORDER];
+  int32_t tensor_dtype;
+  int32_t level1_dtype;
+  int32_t use_second_order;
+  int32_t reserved;
+} ppals_desc;
+
+/* Per-sweep record, written on the device at the end of every sweep call.
+ *   fit_est        1 - sqrt(max(0, ||X||^2 - 2<M^(N), A^(N)> + 1^T(Gamma^(N)*S^(N))1)) / ||X||
+ *                  with M^(N) the right-hand side used for the last mode
+ *                  (approximate in PP sweeps);
+ *   grad_norm[n]   ||G^(n)||_F, G^(n) = (A_old - A_new) Gamma^(n) (Algorithm 1);
+ *   rel_change[n]  ||dA^(n)||_F / ||A^(n)||_F with dA the change over the sweep
+ *                  (ALS) or since the operator build (PP), Algorithm 3;
+ *   chol_status[n] 0: clean Cholesky; 1: factorised Gamma + delta I with
+ *                  delta = R 2^-52 max(diag Gamma); 2: failed after the shift
+ *                  (A^(n) left unchanged). */
+typedef struct {
+  double fit_est;
+  double grad_norm[PPALS_MAX_ORDER];
+  double rel_change[PPALS_MAX_ORDER];
+  int32_t chol_status[PPALS_MAX_ORDER];
+  int32_t sweep_kind;
+  int32_t pad;
+} ppals_sweep_record;
+
+typedef struct ppals_plan ppals_plan;
+
+/* Thread-local text of the last error (never NULL). */
+const char* ppals_last_error(void);
+
+/* Host only; allocates the host plan (schedules of the dimension trees and
+ * the workspace layout).  No device memory is touched. */
+ppals_status ppals_plan_create(const ppals_desc* desc, ppals_plan** out);
+void ppals_plan_destroy(ppals_plan* plan);
+
+/* Bytes of device workspace the plan needs (intermediates of the dimension
+ * trees, the C(N,2) pairwise perturbation operators, staging and scratch). */
+size_t ppals_workspace_bytes(const ppals_plan* plan);
+
+/* Host only: writes a JSON description of the schedules (contractions of the
+ * ALS dimension tree of Section 2.5 and of the PP operator tree of Section
+ * 3.2.3) with their flop counts.  Returns PPALS_E_ARG if len is too small. */
+ppals_status ppals_plan_describe(const ppals_plan* plan, char* buf, size_t len);
+
+/* One CP-ALS sweep (Algorithm 1, loop body) over n = 1..N with the binary
+ * dimension-tree MTTKRP (Section 2.5).  A and S are updated in place; rec
+ * (device pointer) receives the sweep record with sweep_kind = ALS and
+ * rel_change = per-sweep change.  normX2 = ||X||_F^2 (see ppals_tensor_norm2).
+ * X_bf16 is required in the BF16 tier and ignored otherwise. */
+ppals_status cp_als_sweep(ppals_plan* plan, const void* X, const void* X_bf16,
+                          double* const* A, double* S, double normX2, void* ws,
+                          ppals_sweep_record* rec, hipStream_t stream);
+
+/* Pairwise perturbation initialisation (Algorithm 3): A_p := A, dA := 0, and
+ * the operators M_p^(i,j) (i < j) and M_p^(n) are built with the PP dimension
+ * tree of Section 3.2.3.  The operators live in ws. */
+ppals_status pp_build_operators(ppals_plan* plan, const void* X, const void* X_bf16,
+                                double* const* A, void* ws, hipStream_t stream);
+
+/* One approximated sweep (Algorithm 3, inner loop): for n = 1..N the
+ * right-hand side is the general PP update
+ *   M~^(n) = M_p^(n) + sum_{i!=n} M_p^(i,n) x_i dA^(i) + A^(n) W^(n),
+ *   W^(n)  = sum over unordered pairs {i,j} of modes != n of
+ *            (A^(i)T dA^(i)) * (A^(j)T dA^(j)) * Hadamard_{k!=i,j,n} S^(k)
+ * (the last term only if use_second_order), followed by the same normal
+ * equation solve as ALS and dA^(n) = A^(n) - A_p^(n).  rec->sweep_kind is
+ * PP_INIT for the first sweep after a build, PP_APPROX afterwards.
+ * Returns PPALS_E_STATE if no operators were built with this plan. */
+ppals_status pp_sweep(ppals_plan* plan, double* const* A, double* S, double normX2,
+                      void* ws, ppals_sweep_record* rec, hipStream_t stream);
+
+/* Standalone normal-equation solve (Algorithm 1, update and gradient lines):
+ * A_new Gamma = M for `rows` right-hand-side rows, Gamma = L L^T (Cholesky,
+ * with the diagonal-shift retry), then grad_norm = ||(A_old - A_new) Gamma||_F
+ * and A_inout := A_new.  Gamma: R x R doubles; M: rows x R in m_dtype (FP64
+ * or FP32); A_inout: rows x R doubles.  grad_norm_out and chol_status_out are
+ * device pointers (one double, one int32).  ws must hold
+ * ppals_gram_solve_workspace_bytes(R, rows) bytes. */
+size_t ppals_gram_solve_workspace_bytes(int32_t R, int64_t rows);
+ppals_status gram_solve(int32_t R, int64_t rows, const double* Gamma, const void* M,
+                        int32_t m_dtype, double* A_inout, double* grad_norm_out,
+                        int32_t* chol_status_out, void* ws, hipStream_t stream);
+
+/* ||X||_F^2 accumulated in FP64 into *out (device double).  dtype FP64/FP32.
+ * ws must hold ppals_norm2_workspace_bytes() bytes. */
+size_t ppals_norm2_workspace_bytes(void);
+ppals_status ppals_tensor_norm2(const void* X, int32_t dtype, int64_t count, double* out,
+                                void* ws, hipStream_t stream);
+
+/* Round FP32 values to bfloat16 (nearest, ties to even); out holds uint16
+ * bit patterns.  Used to make X_bf16 for the BF16 first-level tier. */
+ppals_status ppals_cast_bf16(const float* in, uint16_t* out, int64_t count, hipStream_t stream);
+
+/* MTTKRP of one mode through the library's contraction kernels, without the
+ * solve: out = X_(n) (Khatri-Rao product of the other factors), s_n x R in
+ * the plan's bulk dtype (FP64 in the FP64 tier, FP32 otherwise).
+ * 0 <= mode < N. */
+ppals_status ppals_mttkrp(ppals_plan* plan, const void* X, const void* X_bf16,
+                          double* const* A, int32_t mode, void* out, void* ws,
+                          hipStream_t stream);
+
+/* First-level contraction alone (Section 2.5): contracts X with the factors
+ * of the modes in the contiguous bit range `contract_mask` (a single mode, or
+ * a leading or trailing block of modes, whose Khatri-Rao product is formed on
+ * the device), producing M^(kept modes) with the kept modes in increasing
+ * order and k last, in the bulk dtype. */
+ppals_status ppals_level1(ppals_plan* plan, const void* X, const void* X_bf16,
+                          double* const* A, uint32_t contract_mask, void* out, void* ws,
+                          hipStream_t stream);
+
+/* Approximated right-hand side M~^(n) for the current factors A (after
+ * pp_build_operators): recomputes dA^(i) = A^(i) - A_p^(i) and
+ * A^(i)T dA^(i) for all modes, then evaluates the general PP update for mode
+ * n into out (s_n x R doubles).  S holds the current Grams. */
+ppals_status ppals_pp_rhs(ppals_plan* plan, double* const* A, const double* S, int32_t mode,
+                          double* out, void* ws, hipStream_t stream);
+
+/* Read back a pairwise perturbation operator M_p^(i,j), i < j (0-based), as
+ * s_i x s_j x R values of the bulk dtype (device-to-device copy). */
+ppals_status ppals_get_operator(ppals_plan* plan, const void* ws, int32_t i, int32_t j,
+                                void* out, hipStream_t stream);
+
+/* Exact residual ||X - [[A]]||_F^2 (Section 5 fit metric), FP64 accumulation,
+ * written to *out (device double).  Costs about one first-level contraction. */
+ppals_status ppals_exact_residual2(ppals_plan* plan, const void* X, double* const* A,
+                                   double* out, void* ws, hipStream_t stream);
+
+/* Whole decomposition driven natively (Algorithm 3 control, or Algorithm 1
+ * when eps <= 0): starts from the factors in A (S is recomputed), runs at most
+ * max_sweeps sweeps and stops early when sum_n ||G^(n)||_F <= delta ||X||_F
+ * (delta <= 0 disables this).  After every sweep the record is copied to
+ * host_records[i] (host memory, max_sweeps entries) and, if sweep_ms is not
+ * NULL, the sweep's device time to sweep_ms[i].  *n_done = sweeps run.  The
+ * switching test is strict: PP is entered (operators rebuilt) after a sweep
+ * whose rel_change is below eps for every mode, and PP sweeps continue while
+ * that holds.  replay (host, may be NULL) forces the sweep kinds instead. */
+ppals_status ppals_run(ppals_plan* plan, const void* X, const void* X_bf16, double* const* A,
+                       double* S, double normX2, void* ws, ppals_sweep_record* rec_dev,
+                       double eps, double delta, int32_t max_sweeps, const int32_t* replay,
+                       ppals_sweep_record* host_records, float* sweep_ms, int32_t* n_done,
+                       hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PPALS_H */

@@ -1,0 +1,281 @@
+"""MI355X pairwise-perturbation CP-ALS: Python binding of libppals.so.
+
+This module only marshals arguments: device buffers are PyTorch tensors
+(memory and streams), every computation runs in the library's HIP kernels.
+The function names mirror the C ABI declared in include/ppals.h:
+cp_als_sweep, pp_build_operators, pp_sweep, gram_solve, plus the auxiliary
+entry points (norm, bf16 cast, MTTKRP, first-level contraction, PP right-hand
+side, operators, exact residual and the native decomposition driver).
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+
+import torch
+
+from . import _lib
+from ._lib import (PPALS_BF16, PPALS_FP32, PPALS_FP64, RECORD_BYTES, SWEEP_ALS,  # noqa: F401
+                   SWEEP_PP_APPROX, SWEEP_PP_INIT, PPALSError, SweepRecord)
+
+_DTYPES = {"f64": PPALS_FP64, "f32": PPALS_FP32, "bf16": PPALS_BF16}
+KIND_NAMES = {SWEEP_ALS: "als", SWEEP_PP_INIT: "pp_init", SWEEP_PP_APPROX: "pp_approx"}
+KIND_CODES = {v: k for k, v in KIND_NAMES.items()}
+
+
+def lib():
+    return _lib.load()
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(t, name, dtype=None, numel=None, min_bytes=None):
+    if t is None:
+        raise ValueError(f"{name} is None")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    if min_bytes is not None and t.numel() * t.element_size() < min_bytes:
+        raise ValueError(f"{name} must hold at least {min_bytes} bytes")
+    return t
+
+
+def _factor_array(plan, A):
+    if len(A) != plan.order:
+        raise ValueError(f"expected {plan.order} factors")
+    for n, a in enumerate(A):
+        _dev(a, f"A[{n}]", torch.float64, plan.dims[n] * plan.rank)
+    return (ctypes.c_void_p * len(A))(*[a.data_ptr() for a in A])
+
+
+class Plan:
+    """Host plan: dimension-tree schedules and the workspace layout."""
+
+    def __init__(self, dims, rank, tensor_dtype="f64", level1_dtype=None, second_order=True):
+        dims = [int(d) for d in dims]
+        if level1_dtype is None:
+            level1_dtype = tensor_dtype
+        d = _lib.Desc()
+        d.order = len(dims)
+        d.rank = int(rank)
+        for i, s in enumerate(dims[:_lib.MAX_ORDER]):
+            d.dims[i] = s
+        d.tensor_dtype = _DTYPES[tensor_dtype]
+        d.level1_dtype = _DTYPES[level1_dtype]
+        d.use_second_order = 1 if second_order else 0
+        h = ctypes.c_void_p()
+        _lib.check(lib().ppals_plan_create(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self.dims = dims
+        self.order = len(dims)
+        self.rank = int(rank)
+        self.tensor_dtype = tensor_dtype
+        self.level1_dtype = level1_dtype
+        self.second_order = bool(second_order)
+        self.torch_dtype = torch.float64 if tensor_dtype == "f64" else torch.float32
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def workspace_bytes(self):
+        return int(lib().ppals_workspace_bytes(self._h))
+
+    def describe(self):
+        buf = ctypes.create_string_buffer(1 << 20)
+        _lib.check(lib().ppals_plan_describe(self._h, buf, len(buf)))
+        return json.loads(buf.value.decode())
+
+    def workspace(self, device="cuda"):
+        return torch.empty(max(1, self.workspace_bytes), dtype=torch.uint8, device=device)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ppals_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _x(self, X, Xb):
+        n = 1
+        for s in self.dims:
+            n *= s
+        _dev(X, "X", self.torch_dtype, n)
+        if self.level1_dtype == "bf16":
+            _dev(Xb, "X_bf16", None, n)
+            if Xb.element_size() != 2:
+                raise ValueError("X_bf16 must hold 2-byte bfloat16 bit patterns")
+            return _p(X), _p(Xb)
+        return _p(X), None
+
+
+def new_record(device="cuda"):
+    return torch.zeros(RECORD_BYTES, dtype=torch.uint8, device=device)
+
+
+def read_record(rec):
+    raw = bytes(rec.detach().to("cpu").numpy().tobytes())
+    r = SweepRecord.from_buffer_copy(raw[:RECORD_BYTES])
+    return record_dict(r)
+
+
+def record_dict(r, order=None):
+    n = _lib.MAX_ORDER if order is None else order
+    return {
+        "fit_est": r.fit_est,
+        "grad_norm": list(r.grad_norm)[:n],
+        "rel_change": list(r.rel_change)[:n],
+        "chol_status": list(r.chol_status)[:n],
+        "kind": KIND_NAMES.get(r.sweep_kind, str(r.sweep_kind)),
+    }
+
+
+def cp_als_sweep(plan, X, X_bf16, A, S, normX2, ws, rec, stream=None):
+    x, xb = plan._x(X, X_bf16)
+    _dev(S, "S", torch.float64, plan.order * plan.rank * plan.rank)
+    _dev(ws, "ws", min_bytes=plan.workspace_bytes)
+    _dev(rec, "rec", min_bytes=RECORD_BYTES)
+    _lib.check(lib().cp_als_sweep(plan.handle, x, xb, _factor_array(plan, A), _p(S), float(normX2),
+                                  _p(ws), _p(rec), _stream(stream)))
+
+
+def pp_build_operators(plan, X, X_bf16, A, ws, stream=None):
+    x, xb = plan._x(X, X_bf16)
+    _dev(ws, "ws", min_bytes=plan.workspace_bytes)
+    _lib.check(lib().pp_build_operators(plan.handle, x, xb, _factor_array(plan, A), _p(ws),
+                                        _stream(stream)))
+
+
+def pp_sweep(plan, A, S, normX2, ws, rec, stream=None):
+    _dev(S, "S", torch.float64, plan.order * plan.rank * plan.rank)
+    _dev(ws, "ws", min_bytes=plan.workspace_bytes)
+    _dev(rec, "rec", min_bytes=RECORD_BYTES)
+    _lib.check(lib().pp_sweep(plan.handle, _factor_array(plan, A), _p(S), float(normX2), _p(ws),
+                              _p(rec), _stream(stream)))
+
+
+def gram_solve_workspace_bytes(R, rows):
+    return int(lib().ppals_gram_solve_workspace_bytes(int(R), int(rows)))
+
+
+def gram_solve(R, rows, Gamma, M, A, grad_out, status_out, ws, stream=None):
+    _dev(Gamma, "Gamma", torch.float64, R * R)
+    if M.dtype not in (torch.float64, torch.float32):
+        raise ValueError("M must be float64 or float32")
+    _dev(M, "M", None, rows * R)
+    _dev(A, "A", torch.float64, rows * R)
+    _dev(grad_out, "grad_out", torch.float64)
+    _dev(status_out, "status_out", torch.int32)
+    _dev(ws, "ws", min_bytes=gram_solve_workspace_bytes(R, rows))
+    mdt = PPALS_FP64 if M.dtype == torch.float64 else PPALS_FP32
+    _lib.check(lib().gram_solve(int(R), int(rows), _p(Gamma), _p(M), mdt, _p(A), _p(grad_out),
+                                _p(status_out), _p(ws), _stream(stream)))
+
+
+def tensor_norm2(X, out, ws=None, stream=None):
+    if X.dtype not in (torch.float64, torch.float32):
+        raise ValueError("X must be float64 or float32")
+    _dev(X, "X")
+    _dev(out, "out", torch.float64)
+    nb = int(lib().ppals_norm2_workspace_bytes())
+    if ws is None:
+        ws = torch.empty(nb, dtype=torch.uint8, device=X.device)
+    _dev(ws, "ws", min_bytes=nb)
+    dt = PPALS_FP64 if X.dtype == torch.float64 else PPALS_FP32
+    _lib.check(lib().ppals_tensor_norm2(_p(X), dt, X.numel(), _p(out), _p(ws), _stream(stream)))
+
+
+def cast_bf16(X32, out, stream=None):
+    _dev(X32, "X", torch.float32)
+    _dev(out, "out", None, X32.numel())
+    if out.element_size() != 2:
+        raise ValueError("out must have 2-byte elements")
+    _lib.check(lib().ppals_cast_bf16(_p(X32), _p(out), X32.numel(), _stream(stream)))
+
+
+def mttkrp(plan, X, X_bf16, A, mode, out, ws, stream=None):
+    x, xb = plan._x(X, X_bf16)
+    _dev(out, "out", torch.float64, plan.dims[mode] * plan.rank)
+    _dev(ws, "ws", min_bytes=plan.workspace_bytes)
+    _lib.check(lib().ppals_mttkrp(plan.handle, x, xb, _factor_array(plan, A), int(mode), _p(out),
+                                  _p(ws), _stream(stream)))
+
+
+def level1(plan, X, X_bf16, A, contract_modes, out, ws, stream=None):
+    x, xb = plan._x(X, X_bf16)
+    mask = 0
+    for m in contract_modes:
+        mask |= 1 << int(m)
+    n = plan.rank
+    for i in range(plan.order):
+        if i not in contract_modes:
+            n *= plan.dims[i]
+    _dev(out, "out", plan.torch_dtype, n)
+    _dev(ws, "ws", min_bytes=plan.workspace_bytes)
+    _lib.check(lib().ppals_level1(plan.handle, x, xb, _factor_array(plan, A), mask, _p(out),
+                                  _p(ws), _stream(stream)))
+
+
+def pp_rhs(plan, A, S, mode, out, ws, stream=None):
+    _dev(S, "S", torch.float64, plan.order * plan.rank * plan.rank)
+    _dev(out, "out", torch.float64, plan.dims[mode] * plan.rank)
+    _dev(ws, "ws", min_bytes=plan.workspace_bytes)
+    _lib.check(lib().ppals_pp_rhs(plan.handle, _factor_array(plan, A), _p(S), int(mode), _p(out),
+                                  _p(ws), _stream(stream)))
+
+
+def get_operator(plan, ws, i, j, out, stream=None):
+    _dev(out, "out", plan.torch_dtype, plan.dims[i] * plan.dims[j] * plan.rank)
+    _lib.check(lib().ppals_get_operator(plan.handle, _p(ws), int(i), int(j), _p(out),
+                                        _stream(stream)))
+
+
+def exact_residual2(plan, X, A, out, ws, stream=None):
+    x, _ = plan._x(X, None) if plan.level1_dtype != "bf16" else (_p(X), None)
+    _dev(out, "out", torch.float64)
+    _lib.check(lib().ppals_exact_residual2(plan.handle, x, _factor_array(plan, A), _p(out), _p(ws),
+                                           _stream(stream)))
+
+
+def run(plan, X, X_bf16, A, S, normX2, ws, rec, eps, max_sweeps, delta=0.0, replay=None,
+        timing=True, stream=None):
+    """Native decomposition driver (Algorithm 3 control; eps <= 0 gives plain ALS).
+
+    Returns (records, sweep_ms): one dict per sweep and the device time of each.
+    """
+    x, xb = plan._x(X, X_bf16)
+    _dev(S, "S", torch.float64, plan.order * plan.rank * plan.rank)
+    _dev(ws, "ws", min_bytes=plan.workspace_bytes)
+    _dev(rec, "rec", min_bytes=RECORD_BYTES)
+    n = int(max_sweeps)
+    recs = (SweepRecord * max(1, n))()
+    ms = (ctypes.c_float * max(1, n))() if timing else None
+    done = ctypes.c_int32(0)
+    rp = None
+    if replay is not None:
+        codes = [KIND_CODES[k] if isinstance(k, str) else int(k) for k in replay]
+        if len(codes) < n:
+            raise ValueError("replay shorter than max_sweeps")
+        rp = (ctypes.c_int32 * len(codes))(*codes)
+    _lib.check(lib().ppals_run(plan.handle, x, xb, _factor_array(plan, A), _p(S), float(normX2),
+                               _p(ws), _p(rec), float(eps), float(delta), n, rp, recs,
+                               ms, ctypes.byref(done), _stream(stream)))
+    out = [record_dict(recs[i], plan.order) for i in range(done.value)]
+    return out, ([float(ms[i]) for i in range(done.value)] if timing else None)

@@ -1,0 +1,112 @@
+"""ctypes declarations for libppals.so (the C ABI in include/ppals.h)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libppals.so")
+
+PPALS_OK = 0
+PPALS_E_ARG = -1
+PPALS_E_UNSUPPORTED = -2
+PPALS_E_HIP = -3
+PPALS_E_WORKSPACE = -4
+PPALS_E_STATE = -5
+
+PPALS_FP64, PPALS_FP32, PPALS_BF16 = 0, 1, 2
+SWEEP_ALS, SWEEP_PP_INIT, SWEEP_PP_APPROX = 0, 1, 2
+MAX_ORDER = 8
+MAX_RANK = 128
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("order", ctypes.c_int32),
+        ("rank", ctypes.c_int32),
+        ("dims", ctypes.c_int64 * MAX_ORDER),
+        ("tensor_dtype", ctypes.c_int32),
+        ("level1_dtype", ctypes.c_int32),
+        ("use_second_order", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class SweepRecord(ctypes.Structure):
+    _fields_ = [
+        ("fit_est", ctypes.c_double),
+        ("grad_norm", ctypes.c_double * MAX_ORDER),
+        ("rel_change", ctypes.c_double * MAX_ORDER),
+        ("chol_status", ctypes.c_int32 * MAX_ORDER),
+        ("sweep_kind", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
+    ]
+
+
+RECORD_BYTES = ctypes.sizeof(SweepRecord)
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_u32 = ctypes.c_uint32
+_dbl = ctypes.c_double
+_sz = ctypes.c_size_t
+_ptrs = ctypes.POINTER(ctypes.c_void_p)
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "ppals_last_error": (ctypes.c_char_p, []),
+    "ppals_plan_create": (_i32, [ctypes.POINTER(Desc), ctypes.POINTER(_vp)]),
+    "ppals_plan_destroy": (None, [_vp]),
+    "ppals_workspace_bytes": (_sz, [_vp]),
+    "ppals_plan_describe": (_i32, [_vp, ctypes.c_char_p, _sz]),
+    "cp_als_sweep": (_i32, [_vp, _vp, _vp, _ptrs, _vp, _dbl, _vp, _vp, _vp]),
+    "pp_build_operators": (_i32, [_vp, _vp, _vp, _ptrs, _vp, _vp]),
+    "pp_sweep": (_i32, [_vp, _ptrs, _vp, _dbl, _vp, _vp, _vp]),
+    "ppals_gram_solve_workspace_bytes": (_sz, [_i32, _i64]),
+    "gram_solve": (_i32, [_i32, _i64, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "ppals_norm2_workspace_bytes": (_sz, []),
+    "ppals_tensor_norm2": (_i32, [_vp, _i32, _i64, _vp, _vp, _vp]),
+    "ppals_cast_bf16": (_i32, [_vp, _vp, _i64, _vp]),
+    "ppals_mttkrp": (_i32, [_vp, _vp, _vp, _ptrs, _i32, _vp, _vp, _vp]),
+    "ppals_level1": (_i32, [_vp, _vp, _vp, _ptrs, _u32, _vp, _vp, _vp]),
+    "ppals_pp_rhs": (_i32, [_vp, _ptrs, _vp, _i32, _vp, _vp, _vp]),
+    "ppals_get_operator": (_i32, [_vp, _vp, _i32, _i32, _vp, _vp]),
+    "ppals_exact_residual2": (_i32, [_vp, _vp, _ptrs, _vp, _vp, _vp]),
+    "ppals_run": (_i32, [_vp, _vp, _vp, _ptrs, _vp, _dbl, _vp, _vp, _dbl, _dbl, _i32,
+                         ctypes.POINTER(_i32), ctypes.POINTER(SweepRecord),
+                         ctypes.POINTER(ctypes.c_float), ctypes.POINTER(_i32), _vp]),
+}
+
+_LIB = None
+
+
+class PPALSError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"ppals status {status}: {msg}")
+        self.status = status
+
+
+def load(path: str | None = None):
+    """Load libppals.so (built in-tree by paper_1811_10573_amd.build); raise if absent."""
+    global _LIB
+    if _LIB is not None and path is None:
+        return _LIB
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(
+            f"{p} is missing: build the HIP library first (python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(p)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path is None:
+        _LIB = lib
+    return lib
+
+
+def check(status: int):
+    if status != PPALS_OK:
+        msg = load().ppals_last_error().decode(errors="replace")
+        raise PPALSError(status, msg)

@@ -1,0 +1,138 @@
+// Shared definitions for the gfx950 kernels and the host library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#define PP_MAXN 8
+#define PP_MAXR 128
+
+namespace ppk {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+enum Dt { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2 };
+
+// Operand of a first-level contraction, laid out for direct MFMA use.
+// K is split into chunks of KC k-values; inside a chunk, step t (KSTEP k-values
+// per MFMA) and n-block c (16 columns) hold 64 lanes x E elements contiguously,
+// so one wave reads its operand for (t, c) as a single linear 64-lane access.
+struct Level1Geom {
+  int64_t M;       // rows of the output (P * Q)
+  int64_t K;       // contracted extent
+  int64_t Q;       // extent of the uncontracted modes after the contracted block
+  int64_t Kpad;    // K rounded up to a multiple of KC
+  int R;           // output columns (rank)
+  int NB;          // 16-column blocks per column slice (1..4)
+  int nslices;     // column slices (rank > 64)
+  int kc_mode;     // 1: contracted block is the fastest (Q == 1) -> K-contiguous rows
+  int ksplit;      // split of K across workgroups
+  int64_t kchunk;  // k-values per split (multiple of KC)
+};
+
+// Khatri-Rao descriptor: value(k, r) = prod_f A_f[digit_f(k)][r], first factor slowest.
+struct KrpDesc {
+  const double* A[PP_MAXN];
+  int64_t dim[PP_MAXN];
+  int nf;
+  int R;
+};
+
+// One column-wise contraction ("multi-TTV") job:
+//   out[p][q][r] (+)= sum_{x in split} T[p][x][q][r] * F[x][r]
+struct TtvJob {
+  const void* T;       // source, FP64 or FP32 elements
+  const double* F;     // weights, X x R doubles
+  double* out;         // destination (FP64), P x Q x R per split slot
+  int64_t P, X, Q;
+  int64_t out_split_stride;  // elements between split slots of out
+  int xsplit;
+  int jblocks;
+  int G;               // x-groups per workgroup
+  int Jb;              // j-width per group (j = q*R + r)
+  int64_t blocks;      // P * jblocks * xsplit
+  int t_is_f32;
+};
+
+#define PP_MAX_JOBS 8
+struct TtvBatch {
+  TtvJob job[PP_MAX_JOBS];
+  int njobs;
+  int R;
+};
+
+}  // namespace ppk
+
+// ---------------------------------------------------------------------------
+// Launchers (defined in the .hip files, called from the host library)
+// ---------------------------------------------------------------------------
+namespace ppk {
+hipError_t launch_prep_operand(const KrpDesc& krp, const Level1Geom& g, int dt, void* out,
+                               hipStream_t s);
+hipError_t launch_level1(const void* X, int dt, const void* B, const Level1Geom& g, void* C,
+                         void* partial, hipStream_t s);
+hipError_t launch_krp_f64(const KrpDesc& krp, int64_t K, double* out, hipStream_t s);
+hipError_t launch_ttv(const TtvBatch& b, hipStream_t s);
+hipError_t launch_combine(double* out, int64_t count, int R, const double* base,
+                          const double* partial, int nslots, int64_t slot_stride,
+                          const double* A, const double* W, hipStream_t s);
+hipError_t launch_sub(double* out, const double* a, const double* b, int64_t n, hipStream_t s);
+hipError_t launch_copy(double* out, const double* a, int64_t n, hipStream_t s);
+hipError_t launch_fill(double* out, double v, int64_t n, hipStream_t s);
+hipError_t launch_reduce_splits_to(void* out, int out_f32, const void* partial, int part_f32,
+                                   int nsplit, int64_t count, hipStream_t s);
+
+struct ModeArgs {
+  int N, R;
+  int n;              // mode whose Gamma/Cholesky to prepare (-1: none)
+  int prev;           // mode to finish (-1: none)
+  int pp;             // 1: PP sweep (W term, dA reference A_p)
+  int second_order;
+  int write_fit;      // 1: compute the fit after finishing prev (last mode)
+  int sweep_kind;
+  int64_t prev_rows;  // s_prev
+  double normX2;
+  double* S;          // N x R x R (caller)
+  double* U;          // N x R x R (ws)
+  double* gamma;      // R x R (ws) Gamma of mode n
+  double* L;          // R x R (ws) Cholesky factor (lower, row-major)
+  double* gamma_save; // R x R (ws) Gamma used by the last solve (for the fit)
+  double* W;          // R x R (ws)
+  double* rowpart;    // rows x 4 partial norms of prev (ws)
+  double* scal;       // scratch scalars (ws)
+  void* rec;          // ppals_sweep_record* (device)
+  int* status;        // int32 per-mode Cholesky status (ws)
+};
+hipError_t launch_mode_begin(const ModeArgs& a, hipStream_t s);
+
+struct SolveArgs {
+  int R;
+  int64_t rows;
+  const double* M;       // rows x R FP64 right-hand side
+  const float* M32;      // alternatively FP32 right-hand side (standalone gram_solve)
+  const double* L;       // R x R
+  const double* gamma;   // R x R
+  double* A;             // rows x R, in/out
+  const double* Aref;    // reference for dA (A_p in PP); NULL -> old A
+  double* dA;            // rows x R output of A_new - ref (may be NULL)
+  double* rowpart;       // rows x 4: ||g||^2, ||dA||^2, ||a||^2, <m, a>
+  const int* status;     // Cholesky status (2 -> leave A unchanged)
+};
+hipError_t launch_solve_rows(const SolveArgs& a, hipStream_t s);
+// S_out = A^T A; if dA: U_out = A^T dA (R x R each)
+hipError_t launch_gram(const double* A, const double* dA, int64_t rows, int R, double* S_out,
+                       double* U_out, hipStream_t s);
+hipError_t launch_norm2(const void* X, int dt, int64_t n, double* partial, int nblocks,
+                        double* out, hipStream_t s);
+hipError_t launch_cast_bf16(const float* in, uint16_t* out, int64_t n, hipStream_t s);
+hipError_t launch_residual2(const void* X, int dt, const double* const* A, const int64_t* dims,
+                            int N, int R, double* partial, int nblocks, double* out,
+                            hipStream_t s);
+hipError_t launch_finish_gram_solve(const double* rowpart, int64_t rows, double* grad_out,
+                                    int32_t* status_out, const int* status, hipStream_t s);
+hipError_t launch_chol_standalone(const double* gamma, int R, double* L, int* status,
+                                  hipStream_t s);
+}  // namespace ppk

@@ -1,0 +1,192 @@
+// Column-wise (Khatri-Rao) multi-TTV contractions: the later levels of the
+// dimension trees (Section 2.5: "batched matrix-vector products") and the
+// first-order pairwise perturbation terms of the general PP update
+// (Section 3.2.1): for every job
+//
+//   out[s][p][q][r] = sum_{x in split s} T[p][x][q][r] * F[x][r]
+//
+// T is an intermediate with the rank index fastest (FP64 or FP32), F an X x R
+// FP64 matrix (a factor, a Khatri-Rao block or dA), out FP64 partial slots.
+// These kernels are HBM-bound: each workgroup streams a contiguous slab of T with
+// 256 threads; when Q*R < 256 the threads are split into G groups that read G
+// consecutive x-rows at once and are reduced through LDS.  Accumulation is FP64.
+#include "common.h"
+
+namespace ppk {
+
+template <typename T>
+__device__ __forceinline__ double ttv_body(const T* __restrict__ src, const double* __restrict__ F,
+                                           int64_t QR, int R, int r, int64_t x0, int64_t x1,
+                                           int G) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int64_t x = x0;
+  const int64_t step = G;
+  for (; x + 3 * step < x1; x += 4 * step) {
+    const double t0 = (double)src[x * QR];
+    const double t1 = (double)src[(x + step) * QR];
+    const double t2 = (double)src[(x + 2 * step) * QR];
+    const double t3 = (double)src[(x + 3 * step) * QR];
+    a0 = fma(t0, F[x * R + r], a0);
+    a1 = fma(t1, F[(x + step) * R + r], a1);
+    a2 = fma(t2, F[(x + 2 * step) * R + r], a2);
+    a3 = fma(t3, F[(x + 3 * step) * R + r], a3);
+  }
+  for (; x < x1; x += step) a0 = fma((double)src[x * QR], F[x * R + r], a0);
+  return (a0 + a1) + (a2 + a3);
+}
+
+__global__ __launch_bounds__(256) void k_ttv(TtvBatch b) {
+  __shared__ double red[256];
+  int64_t bid = blockIdx.x;
+  int jid = 0;
+  while (jid < b.njobs - 1 && bid >= b.job[jid].blocks) {
+    bid -= b.job[jid].blocks;
+    ++jid;
+  }
+  const TtvJob J = b.job[jid];
+  const int R = b.R;
+  const int64_t QR = J.Q * R;
+  const int64_t jb = bid % J.jblocks;
+  const int64_t rest = bid / J.jblocks;
+  const int64_t p = rest % J.P;
+  const int split = (int)(rest / J.P);
+  const int64_t xs = (J.X + J.xsplit - 1) / J.xsplit;
+  const int64_t x0 = (int64_t)split * xs;
+  const int64_t x1 = min(J.X, x0 + xs);
+
+  const int t = threadIdx.x;
+  const int gi = t / J.Jb;
+  const int jj = t - gi * J.Jb;
+  const int64_t j = jb * J.Jb + jj;
+  const bool active = gi < J.G && j < QR;
+  double acc = 0.0;
+  if (active && x0 < x1) {
+    const int r = (int)(j % R);
+    if (J.t_is_f32) {
+      const float* src = (const float*)J.T + p * J.X * QR + j;
+      acc = ttv_body<float>(src, J.F, QR, R, r, x0 + gi, x1, J.G);
+    } else {
+      const double* src = (const double*)J.T + p * J.X * QR + j;
+      acc = ttv_body<double>(src, J.F, QR, R, r, x0 + gi, x1, J.G);
+    }
+  }
+  if (J.G > 1) {
+    red[t] = acc;
+    __syncthreads();
+    if (gi == 0 && j < QR) {
+      double s = acc;
+      for (int g = 1; g < J.G; ++g) s += red[g * J.Jb + jj];
+      acc = s;
+    }
+  }
+  if (gi == 0 && j < QR) J.out[(int64_t)split * J.out_split_stride + p * QR + j] = acc;
+}
+
+// out[idx] = (base ? base[idx] : 0) + sum_slots partial[slot][idx]
+//            + (W ? sum_l A[y][l] W[l][r] : 0),   idx = y*R + r
+__global__ __launch_bounds__(256) void k_combine(double* __restrict__ out, int64_t count, int R,
+                                                 const double* __restrict__ base,
+                                                 const double* __restrict__ partial, int nslots,
+                                                 int64_t slot_stride, const double* __restrict__ A,
+                                                 const double* __restrict__ W) {
+  extern __shared__ double lw[];
+  if (W) {
+    for (int e = threadIdx.x; e < R * R; e += blockDim.x) lw[e] = W[e];
+    __syncthreads();
+  }
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < count;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    double s = base ? base[idx] : 0.0;
+    for (int k = 0; k < nslots; ++k) s += partial[(int64_t)k * slot_stride + idx];
+    if (W) {
+      const int64_t y = idx / R;
+      const int r = (int)(idx - y * R);
+      const double* ar = A + y * R;
+      double v = 0.0;
+      for (int l2 = 0; l2 < R; ++l2) v = fma(ar[l2], lw[l2 * R + r], v);
+      s += v;
+    }
+    out[idx] = s;
+  }
+}
+
+// Khatri-Rao block in FP64: out[k][r] = prod_f A_f[digit_f(k)][r] (first factor slowest)
+__global__ void k_krp_f64(KrpDesc krp, int64_t K, double* __restrict__ out) {
+  const int64_t total = K * krp.R;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(idx % krp.R);
+    int64_t kr = idx / krp.R, dig[PP_MAXN];
+    for (int f = krp.nf - 1; f >= 0; --f) {
+      dig[f] = kr % krp.dim[f];
+      kr /= krp.dim[f];
+    }
+    double v = krp.A[0][dig[0] * krp.R + r];
+    for (int f = 1; f < krp.nf; ++f) v *= krp.A[f][dig[f] * krp.R + r];
+    out[idx] = v;
+  }
+}
+
+__global__ void k_sub(double* __restrict__ out, const double* __restrict__ a,
+                      const double* __restrict__ b, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = b ? a[i] - b[i] : a[i];
+}
+__global__ void k_fill(double* __restrict__ out, double v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = v;
+}
+static int ew_blocks(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+}
+hipError_t launch_sub(double* out, const double* a, const double* b, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub, dim3(ew_blocks(n)), dim3(256), 0, s, out, a, b, n);
+  return hipGetLastError();
+}
+hipError_t launch_copy(double* out, const double* a, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub, dim3(ew_blocks(n)), dim3(256), 0, s, out, a, (const double*)nullptr, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill(double* out, double v, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill, dim3(ew_blocks(n)), dim3(256), 0, s, out, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_ttv(const TtvBatch& b, hipStream_t s) {
+  int64_t total = 0;
+  for (int i = 0; i < b.njobs; ++i) total += b.job[i].blocks;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ttv, dim3((unsigned)total), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine(double* out, int64_t count, int R, const double* base,
+                          const double* partial, int nslots, int64_t slot_stride, const double* A,
+                          const double* W, hipStream_t s) {
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  size_t lds = W ? (size_t)R * R * sizeof(double) : 0;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_combine),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_combine, dim3((unsigned)blocks), dim3(256), lds, s, out, count, R, base,
+                     partial, nslots, slot_stride, A, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_krp_f64(const KrpDesc& krp, int64_t K, double* out, hipStream_t s) {
+  int64_t total = K * krp.R;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_krp_f64, dim3((unsigned)blocks), dim3(256), 0, s, krp, K, out);
+  return hipGetLastError();
+}
+
+}  // namespace ppk

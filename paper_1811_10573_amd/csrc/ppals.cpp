@@ -1,0 +1,1023 @@
+// Host side of the library: plans (dimension-tree schedules and workspace
+// layout), the C ABI entry points and the native PP-CP-ALS driver.
+//
+// Schedules
+//  * ALS sweep (Algorithm 1) with a binary dimension tree (Section 2.5).  For
+//    N = 3 the tree contracts X with A^(3) (first-level GEMM) to get M^(1,2),
+//    from which M^(1) and M^(2) follow by column-wise TTVs; then X with A^(1)
+//    gives M^(2,3) and M^(3).  For N >= 4 the first two levels are combined
+//    (Section 3.2.3, memory footprint): X is contracted with the Khatri-Rao
+//    product of the trailing half of the modes, then of the leading half, and
+//    each half is split recursively with TTVs.
+//  * PP operator build (Section 3.2.3): level 2 holds the three tensors
+//    X x_w A^(w), w in {1,2,3} (first-level GEMMs); level l >= 3 contracts one
+//    mode of a level-(l-1) tensor; the leaves are the C(N,2) operators
+//    M_p^(i,j).  M_p^(n) is one more TTV from a leaf.
+//  * PP sweep (Algorithm 3 inner loop): per mode one batched TTV launch for the
+//    N-1 first-order terms, one combine (M_p^(n) + partials + A^(n) W^(n)), the
+//    FP64 solve and the Grams.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ppals.h"
+#include "common.h"
+
+using namespace ppk;
+
+static thread_local std::string g_err;
+static ppals_status fail(ppals_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(PPALS_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+extern "C" const char* ppals_last_error(void) { return g_err.c_str(); }
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct L1Step {
+  int lo, hi;           // contracted modes [lo, hi)
+  Level1Geom geom;
+  int out_buf;          // intermediate buffer id (bulk dtype), or -1: write FP64 M
+  std::vector<int> kept;
+};
+
+struct TtvStep {
+  int src_buf;                  // buffer id of the source intermediate
+  std::vector<int> src_modes;   // modes of the source (sorted)
+  int bpos, blen;               // contracted block inside src_modes
+  int64_t P, X, Q;
+  TtvJob job;                   // launch configuration (pointers filled at run time)
+  int out_buf;                  // intermediate id, or -1 for the FP64 M buffer
+  int out_mode;                 // if out_buf == -1: the mode whose M this is
+  std::vector<int> kept;
+};
+
+enum OpKind { OP_L1 = 0, OP_TTV = 1, OP_SOLVE = 2 };
+struct Op {
+  OpKind kind;
+  int idx;   // into l1 / ttv vectors, or the mode for SOLVE
+};
+
+struct BufDesc {
+  size_t off = 0, bytes = 0;
+};
+
+}  // namespace
+
+struct ppals_plan {
+  int N = 0, R = 0;
+  int64_t dims[PPALS_MAX_ORDER] = {0};
+  int tdt = DT_F64, l1dt = DT_F64, bulk = DT_F64;
+  int second_order = 1;
+  int64_t max_s = 0, sum_s = 0;
+
+  std::vector<L1Step> l1;
+  std::vector<TtvStep> ttv;
+  std::vector<BufDesc> bufs;       // intermediates (bulk dtype)
+  std::vector<Op> dt_ops;          // ALS sweep
+  std::vector<Op> pp_ops;          // operator build (L1 + TTV to leaves)
+  std::vector<int> mp_ttv;         // per mode: TTV step producing M_p^(n) (out to mp buffer)
+  int leaf_buf[PPALS_MAX_ORDER][PPALS_MAX_ORDER];
+  // per mode PP correction batch configuration
+  TtvBatch ppb[PPALS_MAX_ORDER];
+  int pp_slots[PPALS_MAX_ORDER];
+
+  // workspace offsets
+  size_t off_B = 0, sz_B = 0;          // level-1 operand
+  size_t off_l1part = 0, sz_l1part = 0;
+  size_t off_F = 0, sz_F = 0;          // FP64 Khatri-Rao block for multi-mode TTV
+  size_t off_tpart = 0, sz_tpart = 0;  // FP64 TTV partial slots
+  size_t off_M = 0;                    // FP64 max_s x R
+  size_t off_Mp = 0, off_Ap = 0, off_dA = 0;  // FP64 sum_s x R each
+  size_t off_U = 0;                    // N R^2
+  size_t off_gamma = 0, off_L = 0, off_W = 0;
+  size_t off_rowpart = 0;              // max_s x 4
+  size_t off_scal = 0;                 // 64 doubles
+  size_t off_status = 0;               // ints
+  size_t off_norm = 0;                 // 4096 doubles
+  size_t off_ppart = 0, sz_ppart = 0;  // PP partial slots
+  size_t ws_bytes = 0;
+  std::vector<size_t> mode_off;        // element offsets of mode n in sum_s x R arrays
+
+  // state
+  bool ops_built = false;
+  int sweeps_since_build = 0;
+
+  std::string describe;
+};
+
+namespace {
+
+int esize(int dt) { return dt == DT_F64 ? 8 : (dt == DT_F32 ? 4 : 2); }
+
+int64_t prod_dims(const ppals_plan* p, const std::vector<int>& modes, int a, int b) {
+  int64_t r = 1;
+  for (int i = a; i < b; ++i) r *= p->dims[modes[i]];
+  return r;
+}
+
+void ttv_config(TtvJob& J, int64_t P, int64_t X, int64_t Q, int R) {
+  memset(&J, 0, sizeof(J));
+  J.P = P;
+  J.X = X;
+  J.Q = Q;
+  const int64_t QR = Q * R;
+  if (QR >= 256) {
+    J.Jb = 256;
+    J.G = 1;
+    J.jblocks = (int)((QR + 255) / 256);
+  } else {
+    J.Jb = (int)QR;
+    J.G = (int)(256 / QR);
+    J.jblocks = 1;
+  }
+  const int64_t base = P * J.jblocks;
+  const int64_t target = 2048;
+  int64_t xs = (target + base - 1) / base;
+  const int64_t maxs = std::max<int64_t>(1, X / (8 * (int64_t)J.G));
+  xs = std::max<int64_t>(1, std::min(xs, maxs));
+  J.xsplit = (int)xs;
+  J.blocks = base * xs;
+  J.out_split_stride = P * QR;
+}
+
+Level1Geom l1_config(const ppals_plan* p, int lo, int hi) {
+  Level1Geom g;
+  memset(&g, 0, sizeof(g));
+  int64_t P = 1, K = 1, Q = 1;
+  for (int i = 0; i < lo; ++i) P *= p->dims[i];
+  for (int i = lo; i < hi; ++i) K *= p->dims[i];
+  for (int i = hi; i < p->N; ++i) Q *= p->dims[i];
+  g.M = P * Q;
+  g.K = K;
+  g.Q = Q;
+  g.R = p->R;
+  const int nbt = (p->R + 15) / 16;
+  g.nslices = (nbt + 3) / 4;
+  g.NB = (nbt + g.nslices - 1) / g.nslices;
+  const int KC = p->l1dt == DT_BF16 ? 64 : 32;
+  g.Kpad = (K + KC - 1) / KC * KC;
+  g.kc_mode = (Q == 1) ? 1 : 0;
+  int BM;
+  if (p->l1dt == DT_F64) BM = 128;
+  else if (p->l1dt == DT_F32) BM = 256;
+  else BM = g.kc_mode ? 256 : 128;
+  const int64_t mtiles = (g.M + BM - 1) / BM;
+  const int64_t nchunks = g.Kpad / KC;
+  int64_t ks = (512 + mtiles * g.nslices - 1) / (mtiles * g.nslices);
+  ks = std::max<int64_t>(1, std::min(ks, nchunks / 4));
+  const int64_t cps = (nchunks + ks - 1) / ks;
+  g.kchunk = cps * KC;
+  g.ksplit = (int)((g.K + g.kchunk - 1) / g.kchunk);
+  return g;
+}
+
+int new_buf(ppals_plan* p, size_t bytes) {
+  BufDesc b;
+  b.bytes = bytes;
+  p->bufs.push_back(b);
+  return (int)p->bufs.size() - 1;
+}
+
+int add_l1(ppals_plan* p, int lo, int hi, int out_buf) {
+  L1Step s;
+  s.lo = lo;
+  s.hi = hi;
+  s.geom = l1_config(p, lo, hi);
+  s.out_buf = out_buf;
+  for (int i = 0; i < p->N; ++i)
+    if (i < lo || i >= hi) s.kept.push_back(i);
+  p->l1.push_back(s);
+  return (int)p->l1.size() - 1;
+}
+
+int add_ttv(ppals_plan* p, int src_buf, const std::vector<int>& src_modes, int bpos, int blen,
+            int out_buf, int out_mode) {
+  TtvStep t;
+  t.src_buf = src_buf;
+  t.src_modes = src_modes;
+  t.bpos = bpos;
+  t.blen = blen;
+  t.P = prod_dims(p, src_modes, 0, bpos);
+  t.X = prod_dims(p, src_modes, bpos, bpos + blen);
+  t.Q = prod_dims(p, src_modes, bpos + blen, (int)src_modes.size());
+  ttv_config(t.job, t.P, t.X, t.Q, p->R);
+  t.out_buf = out_buf;
+  t.out_mode = out_mode;
+  for (int i = 0; i < (int)src_modes.size(); ++i)
+    if (i < bpos || i >= bpos + blen) t.kept.push_back(src_modes[i]);
+  p->ttv.push_back(t);
+  return (int)p->ttv.size() - 1;
+}
+
+size_t node_bytes(const ppals_plan* p, const std::vector<int>& modes) {
+  int64_t n = p->R;
+  for (int m : modes) n *= p->dims[m];
+  return (size_t)n * esize(p->bulk);
+}
+
+// Recursive part of the ALS dimension tree: `buf` holds M^(modes) (|modes| >= 2).
+void dt_recurse(ppals_plan* p, int buf, const std::vector<int>& modes, std::vector<int>& depth_buf,
+                int depth) {
+  const int k = (int)modes.size();
+  const int m = (k + 1) / 2;
+  std::vector<int> left(modes.begin(), modes.begin() + m), right(modes.begin() + m, modes.end());
+  for (int side = 0; side < 2; ++side) {
+    const std::vector<int>& keep = side == 0 ? left : right;
+    // left child contracts the trailing block, right child the leading block
+    const int bpos = side == 0 ? m : 0;
+    const int blen = side == 0 ? k - m : m;
+    if (keep.size() == 1) {
+      const int t = add_ttv(p, buf, modes, bpos, blen, -1, keep[0]);
+      p->dt_ops.push_back({OP_TTV, t});
+      p->dt_ops.push_back({OP_SOLVE, keep[0]});
+    } else {
+      if ((int)depth_buf.size() <= depth) depth_buf.push_back(new_buf(p, 0));
+      const int ob = depth_buf[depth];
+      p->bufs[ob].bytes = std::max(p->bufs[ob].bytes, node_bytes(p, keep));
+      const int t = add_ttv(p, buf, modes, bpos, blen, ob, -1);
+      p->dt_ops.push_back({OP_TTV, t});
+      dt_recurse(p, ob, keep, depth_buf, depth + 1);
+    }
+  }
+}
+
+void build_dt(ppals_plan* p) {
+  const int N = p->N;
+  std::vector<int> depth_buf;
+  depth_buf.push_back(new_buf(p, 0));
+  const int b0 = depth_buf[0];
+  auto root_child = [&](int lo, int hi) {
+    std::vector<int> keep;
+    for (int i = 0; i < N; ++i)
+      if (i < lo || i >= hi) keep.push_back(i);
+    p->bufs[b0].bytes = std::max(p->bufs[b0].bytes, node_bytes(p, keep));
+    const int s = add_l1(p, lo, hi, b0);
+    p->dt_ops.push_back({OP_L1, s});
+    dt_recurse(p, b0, keep, depth_buf, 1);
+  };
+  if (N == 3) {
+    root_child(2, 3);   // M^(1,2) = X x_3 A^(3)  -> M^(1), M^(2)
+    root_child(0, 1);   // M^(2,3) = X x_1 A^(1)  -> (M^(2) unused) M^(3)
+  } else {
+    const int h = (N + 1) / 2;
+    root_child(h, N);
+    root_child(0, h);
+  }
+}
+
+// For N == 3 the second root child {2,3} would produce M^(2) a second time; keep
+// only the first SOLVE of each mode and, by backward liveness, the contractions
+// that feed a kept op.
+void prune_dt(ppals_plan* p) {
+  const int nops = (int)p->dt_ops.size();
+  std::vector<int> first_solve(p->N, -1);
+  for (int i = 0; i < nops; ++i)
+    if (p->dt_ops[i].kind == OP_SOLVE && first_solve[p->dt_ops[i].idx] < 0)
+      first_solve[p->dt_ops[i].idx] = i;
+  std::vector<bool> keep(nops, false);
+  std::vector<int> readers(p->bufs.size(), 0);  // kept readers of a buffer's current value
+  bool need_M = false;
+  for (int i = nops - 1; i >= 0; --i) {
+    const Op& o = p->dt_ops[i];
+    if (o.kind == OP_SOLVE) {
+      keep[i] = first_solve[o.idx] == i;
+      if (keep[i]) need_M = true;
+    } else if (o.kind == OP_TTV) {
+      const TtvStep& t = p->ttv[o.idx];
+      if (t.out_buf < 0) {
+        keep[i] = need_M;
+        need_M = false;
+      } else {
+        keep[i] = readers[t.out_buf] > 0;
+        readers[t.out_buf] = 0;
+      }
+      if (keep[i]) readers[t.src_buf]++;
+    } else {
+      const L1Step& l = p->l1[o.idx];
+      keep[i] = readers[l.out_buf] > 0;
+      readers[l.out_buf] = 0;
+    }
+  }
+  std::vector<Op> out;
+  for (int i = 0; i < nops; ++i)
+    if (keep[i]) out.push_back(p->dt_ops[i]);
+  p->dt_ops.swap(out);
+}
+
+void build_pp(ppals_plan* p) {
+  const int N = p->N;
+  // node store: mode list -> buffer id
+  std::vector<std::pair<std::vector<int>, int>> nodes;
+  auto find = [&](const std::vector<int>& m) {
+    for (auto& e : nodes)
+      if (e.first == m) return e.second;
+    return -1;
+  };
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) p->leaf_buf[i][j] = -1;
+  // level 2 (paper numbering, modes 1-based in the text; 0-based here)
+  for (int l = 2; l <= N - 1; ++l) {
+    std::vector<int> tail;
+    for (int m = l + 2; m <= N; ++m) tail.push_back(m - 1);
+    for (int i = 1; i <= l + 1; ++i)
+      for (int j = i + 1; j <= l + 1; ++j) {
+        int w = (j <= l) ? l + 1 : std::max(i == l - 1 ? -1 : l - 1, i == l ? -1 : l);
+        std::vector<int> child = {i - 1, j - 1};
+        child.insert(child.end(), tail.begin(), tail.end());
+        std::vector<int> parent = child;
+        parent.push_back(w - 1);
+        std::sort(parent.begin(), parent.end());
+        const int ob = new_buf(p, node_bytes(p, child));
+        if (l == 2) {
+          const int s = add_l1(p, w - 1, w, ob);
+          p->pp_ops.push_back({OP_L1, s});
+        } else {
+          const int pb = find(parent);
+          const int pos = (int)(std::find(parent.begin(), parent.end(), w - 1) - parent.begin());
+          const int t = add_ttv(p, pb, parent, pos, 1, ob, -1);
+          p->pp_ops.push_back({OP_TTV, t});
+        }
+        nodes.push_back({child, ob});
+        if (l == N - 1) p->leaf_buf[i - 1][j - 1] = ob;
+      }
+  }
+  // M_p^(n) from a leaf (M_p^(1) from M_p^(1,2) contracting mode 2; others from M_p^(1,n))
+  p->mp_ttv.assign(N, -1);
+  for (int n = 0; n < N; ++n) {
+    if (n == 0) {
+      p->mp_ttv[n] = add_ttv(p, p->leaf_buf[0][1], {0, 1}, 1, 1, -2, 0);
+    } else {
+      p->mp_ttv[n] = add_ttv(p, p->leaf_buf[0][n], {0, n}, 0, 1, -2, n);
+    }
+  }
+  // per-mode correction batches
+  for (int n = 0; n < N; ++n) {
+    TtvBatch& b = p->ppb[n];
+    memset(&b, 0, sizeof(b));
+    b.R = p->R;
+    int nj = 0, slots = 0;
+    for (int i = 0; i < N; ++i) {
+      if (i == n) continue;
+      TtvJob& J = b.job[nj++];
+      if (i < n) ttv_config(J, 1, p->dims[i], p->dims[n], p->R);   // op (i,n): contract leading
+      else ttv_config(J, p->dims[n], p->dims[i], 1, p->R);         // op (n,i): contract trailing
+      J.out_split_stride = p->dims[n] * (int64_t)p->R;
+      slots += J.xsplit;
+    }
+    b.njobs = nj;
+    p->pp_slots[n] = slots;
+  }
+}
+
+void layout(ppals_plan* p) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align256(std::max<size_t>(bytes, 1));
+    return o;
+  };
+  const int R = p->R;
+  // level-1 operand and split partials
+  size_t szB = 0, szP = 0;
+  for (auto& s : p->l1) {
+    const Level1Geom& g = s.geom;
+    szB = std::max(szB, (size_t)g.nslices * g.Kpad * 16 * g.NB * esize(p->l1dt));
+    if (g.ksplit > 1) szP = std::max(szP, (size_t)g.ksplit * g.M * R * esize(p->bulk));
+  }
+  // TTV partials and KRP blocks
+  size_t szF = 0, szT = 0;
+  for (auto& t : p->ttv) {
+    if (t.blen > 1) szF = std::max(szF, (size_t)t.X * R * 8);
+    szT = std::max(szT, (size_t)t.job.xsplit * t.P * t.Q * R * 8);
+  }
+  size_t szPP = 0;
+  for (int n = 0; n < p->N; ++n) szPP = std::max(szPP, (size_t)p->pp_slots[n] * p->dims[n] * R * 8);
+  p->off_B = take(szB); p->sz_B = szB;
+  p->off_l1part = take(szP); p->sz_l1part = szP;
+  p->off_F = take(szF); p->sz_F = szF;
+  p->off_tpart = take(szT); p->sz_tpart = szT;
+  p->off_ppart = take(szPP); p->sz_ppart = szPP;
+  p->off_M = take((size_t)p->max_s * R * 8);
+  p->off_Mp = take((size_t)p->sum_s * R * 8);
+  p->off_Ap = take((size_t)p->sum_s * R * 8);
+  p->off_dA = take((size_t)p->sum_s * R * 8);
+  p->off_U = take((size_t)p->N * R * R * 8);
+  p->off_gamma = take((size_t)R * R * 8);
+  p->off_L = take((size_t)R * R * 8);
+  p->off_W = take((size_t)R * R * 8);
+  p->off_rowpart = take((size_t)p->max_s * 4 * 8);
+  p->off_scal = take(64 * 8);
+  p->off_status = take(64 * 4);
+  p->off_norm = take(4096 * 8);
+  for (auto& b : p->bufs) b.off = take(b.bytes);
+  p->ws_bytes = off;
+}
+
+std::string json_ops(const ppals_plan* p, const std::vector<Op>& ops, double* flops_l1,
+                     double* flops_ttv) {
+  std::string s = "[";
+  char tmp[512];
+  bool first = true;
+  *flops_l1 = 0;
+  *flops_ttv = 0;
+  for (const Op& o : ops) {
+    if (!first) s += ",";
+    first = false;
+    if (o.kind == OP_L1) {
+      const L1Step& st = p->l1[o.idx];
+      const double f = 2.0 * (double)st.geom.M * (double)st.geom.K * p->R;
+      *flops_l1 += f;
+      std::string kept;
+      for (size_t i = 0; i < st.kept.size(); ++i) kept += (i ? "," : "") + std::to_string(st.kept[i]);
+      snprintf(tmp, sizeof(tmp),
+               "{\"op\":\"level1\",\"contract\":[%d,%d],\"kept\":[%s],\"M\":%lld,\"K\":%lld,"
+               "\"Q\":%lld,\"ksplit\":%d,\"kc_mode\":%d,\"flops\":%.0f}",
+               st.lo, st.hi, kept.c_str(), (long long)st.geom.M, (long long)st.geom.K,
+               (long long)st.geom.Q, st.geom.ksplit, st.geom.kc_mode, f);
+    } else if (o.kind == OP_TTV) {
+      const TtvStep& t = p->ttv[o.idx];
+      const double f = 2.0 * (double)t.P * t.X * t.Q * p->R;
+      *flops_ttv += f;
+      std::string kept, src;
+      for (size_t i = 0; i < t.kept.size(); ++i) kept += (i ? "," : "") + std::to_string(t.kept[i]);
+      for (size_t i = 0; i < t.src_modes.size(); ++i) src += (i ? "," : "") + std::to_string(t.src_modes[i]);
+      snprintf(tmp, sizeof(tmp),
+               "{\"op\":\"ttv\",\"src\":[%s],\"contract_pos\":[%d,%d],\"kept\":[%s],\"P\":%lld,"
+               "\"X\":%lld,\"Q\":%lld,\"xsplit\":%d,\"out_mode\":%d,\"flops\":%.0f}",
+               src.c_str(), t.bpos, t.blen, kept.c_str(), (long long)t.P, (long long)t.X,
+               (long long)t.Q, t.job.xsplit, t.out_mode, f);
+    } else {
+      snprintf(tmp, sizeof(tmp), "{\"op\":\"solve\",\"mode\":%d}", o.idx);
+    }
+    s += tmp;
+  }
+  s += "]";
+  return s;
+}
+
+void make_describe(ppals_plan* p) {
+  double a1, a2, b1, b2;
+  std::string dt = json_ops(p, p->dt_ops, &a1, &a2);
+  std::string pp = json_ops(p, p->pp_ops, &b1, &b2);
+  double mpf = 0;
+  for (int n = 0; n < p->N; ++n) {
+    const TtvStep& t = p->ttv[p->mp_ttv[n]];
+    mpf += 2.0 * (double)t.P * t.X * t.Q * p->R;
+  }
+  double approx = 0;
+  for (int n = 0; n < p->N; ++n)
+    for (int i = 0; i < p->N; ++i)
+      if (i != n) approx += 2.0 * (double)p->dims[i] * p->dims[n] * p->R;
+  char tmp[1024];
+  snprintf(tmp, sizeof(tmp),
+           "\"dt_level1_flops\":%.0f,\"dt_ttv_flops\":%.0f,\"pp_build_level1_flops\":%.0f,"
+           "\"pp_build_tree_ttv_flops\":%.0f,\"pp_build_mp_flops\":%.0f,"
+           "\"pp_approx_first_order_flops\":%.0f,\"workspace_bytes\":%zu,\"order\":%d,\"rank\":%d",
+           a1, a2, b1, b2, mpf, approx, p->ws_bytes, p->N, p->R);
+  p->describe = std::string("{") + tmp + ",\"dt_ops\":" + dt + ",\"pp_build_ops\":" + pp + "}";
+}
+
+// ---------------------------------------------------------------------------
+// Run-time helpers
+// ---------------------------------------------------------------------------
+struct Ctx {
+  ppals_plan* p;
+  char* ws;
+  hipStream_t s;
+  template <typename T>
+  T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+  double* M() const { return at<double>(p->off_M); }
+  double* Mp(int n) const { return at<double>(p->off_Mp) + p->mode_off[n]; }
+  double* Ap(int n) const { return at<double>(p->off_Ap) + p->mode_off[n]; }
+  double* dA(int n) const { return at<double>(p->off_dA) + p->mode_off[n]; }
+  double* U() const { return at<double>(p->off_U); }
+  void* buf(int b) const { return ws + p->bufs[b].off; }
+};
+
+ppals_status run_l1(const Ctx& c, const L1Step& st, const void* X, const void* Xb,
+                    double* const* A, void* out) {
+  ppals_plan* p = c.p;
+  KrpDesc krp;
+  memset(&krp, 0, sizeof(krp));
+  krp.nf = st.hi - st.lo;
+  krp.R = p->R;
+  for (int f = 0; f < krp.nf; ++f) {
+    krp.A[f] = A[st.lo + f];
+    krp.dim[f] = p->dims[st.lo + f];
+  }
+  void* B = c.ws + p->off_B;
+  HIPCHK(launch_prep_operand(krp, st.geom, p->l1dt, B, c.s));
+  const void* xin = p->l1dt == DT_BF16 ? Xb : X;
+  HIPCHK(launch_level1(xin, p->l1dt, B, st.geom, out, c.ws + p->off_l1part, c.s));
+  return PPALS_OK;
+}
+
+// Run a TTV step; out_fp64 (if non-null) receives the FP64 result (M buffers),
+// otherwise the step's intermediate buffer gets the bulk-dtype result.
+ppals_status run_ttv(const Ctx& c, const TtvStep& t, double* const* A, double* out_fp64) {
+  ppals_plan* p = c.p;
+  const double* F;
+  if (t.blen == 1) {
+    F = A[t.src_modes[t.bpos]];
+  } else {
+    KrpDesc krp;
+    memset(&krp, 0, sizeof(krp));
+    krp.nf = t.blen;
+    krp.R = p->R;
+    for (int f = 0; f < t.blen; ++f) {
+      krp.A[f] = A[t.src_modes[t.bpos + f]];
+      krp.dim[f] = p->dims[t.src_modes[t.bpos + f]];
+    }
+    double* Fb = c.at<double>(p->off_F);
+    HIPCHK(launch_krp_f64(krp, t.X, Fb, c.s));
+    F = Fb;
+  }
+  TtvBatch b;
+  memset(&b, 0, sizeof(b));
+  b.R = p->R;
+  b.njobs = 1;
+  b.job[0] = t.job;
+  b.job[0].T = c.buf(t.src_buf);
+  b.job[0].t_is_f32 = p->bulk == DT_F32;
+  b.job[0].F = F;
+  double* part = c.at<double>(p->off_tpart);
+  b.job[0].out = part;
+  HIPCHK(launch_ttv(b, c.s));
+  const int64_t count = t.P * t.Q * p->R;
+  if (out_fp64) {
+    HIPCHK(launch_combine(out_fp64, count, p->R, nullptr, part, t.job.xsplit, count, nullptr,
+                          nullptr, c.s));
+  } else {
+    HIPCHK(launch_reduce_splits_to(c.buf(t.out_buf), p->bulk == DT_F32, part, 0, t.job.xsplit,
+                                   count, c.s));
+  }
+  return PPALS_OK;
+}
+
+ppals_status mode_begin(const Ctx& c, double* S, double normX2, ppals_sweep_record* rec, int n,
+                        int prev, int pp, int write_fit, int kind) {
+  ppals_plan* p = c.p;
+  ModeArgs a;
+  memset(&a, 0, sizeof(a));
+  a.N = p->N;
+  a.R = p->R;
+  a.n = n;
+  a.prev = prev;
+  a.pp = pp;
+  a.second_order = p->second_order;
+  a.write_fit = write_fit;
+  a.sweep_kind = kind;
+  a.prev_rows = prev >= 0 ? p->dims[prev] : 0;
+  a.normX2 = normX2;
+  a.S = S;
+  a.U = c.U();
+  a.gamma = c.at<double>(p->off_gamma);
+  a.L = c.at<double>(p->off_L);
+  a.gamma_save = a.gamma;
+  a.W = c.at<double>(p->off_W);
+  a.rowpart = c.at<double>(p->off_rowpart);
+  a.scal = c.at<double>(p->off_scal);
+  a.rec = rec;
+  a.status = c.at<int>(p->off_status);
+  HIPCHK(launch_mode_begin(a, c.s));
+  return PPALS_OK;
+}
+
+ppals_status solve_mode(const Ctx& c, double* const* A, double* S, int n, bool pp) {
+  ppals_plan* p = c.p;
+  SolveArgs a;
+  memset(&a, 0, sizeof(a));
+  a.R = p->R;
+  a.rows = p->dims[n];
+  a.M = c.M();
+  a.L = c.at<double>(p->off_L);
+  a.gamma = c.at<double>(p->off_gamma);
+  a.A = A[n];
+  a.Aref = pp ? c.Ap(n) : nullptr;
+  a.dA = pp ? c.dA(n) : nullptr;
+  a.rowpart = c.at<double>(p->off_rowpart);
+  a.status = c.at<int>(p->off_status) + n;
+  HIPCHK(launch_solve_rows(a, c.s));
+  HIPCHK(launch_gram(A[n], pp ? c.dA(n) : nullptr, p->dims[n], p->R, S + (size_t)n * p->R * p->R,
+                     pp ? c.U() + (size_t)n * p->R * p->R : nullptr, c.s));
+  return PPALS_OK;
+}
+
+ppals_status check_common(const ppals_plan* p, const void* X, const void* Xb, double* const* A,
+                          const void* ws) {
+  if (!p) return fail(PPALS_E_ARG, "plan is NULL");
+  if (!X) return fail(PPALS_E_ARG, "X is NULL");
+  if (p->l1dt == DT_BF16 && !Xb) return fail(PPALS_E_ARG, "X_bf16 is NULL in the BF16 tier");
+  if (!A) return fail(PPALS_E_ARG, "A is NULL");
+  for (int n = 0; n < p->N; ++n)
+    if (!A[n]) return fail(PPALS_E_ARG, "A[" + std::to_string(n) + "] is NULL");
+  if (!ws) return fail(PPALS_E_WORKSPACE, "workspace is NULL");
+  return PPALS_OK;
+}
+
+ppals_status do_als_sweep(ppals_plan* p, const void* X, const void* Xb, double* const* A,
+                          double* S, double normX2, void* ws, ppals_sweep_record* rec,
+                          hipStream_t s) {
+  Ctx c{p, (char*)ws, s};
+  int prev = -1;
+  for (const Op& o : p->dt_ops) {
+    ppals_status st = PPALS_OK;
+    if (o.kind == OP_L1) {
+      const L1Step& l = p->l1[o.idx];
+      st = run_l1(c, l, X, Xb, A, c.buf(l.out_buf));
+    } else if (o.kind == OP_TTV) {
+      const TtvStep& t = p->ttv[o.idx];
+      st = run_ttv(c, t, A, t.out_buf < 0 ? c.M() : nullptr);
+    } else {
+      const int n = o.idx;
+      st = mode_begin(c, S, normX2, rec, n, prev, 0, 0, PPALS_SWEEP_ALS);
+      if (st == PPALS_OK) st = solve_mode(c, A, S, n, false);
+      prev = n;
+    }
+    if (st != PPALS_OK) return st;
+  }
+  return mode_begin(c, S, normX2, rec, -1, prev, 0, 1, PPALS_SWEEP_ALS);
+}
+
+ppals_status do_pp_build(ppals_plan* p, const void* X, const void* Xb, double* const* A,
+                         void* ws, hipStream_t s) {
+  Ctx c{p, (char*)ws, s};
+  for (const Op& o : p->pp_ops) {
+    ppals_status st;
+    if (o.kind == OP_L1) {
+      const L1Step& l = p->l1[o.idx];
+      st = run_l1(c, l, X, Xb, A, c.buf(l.out_buf));
+    } else {
+      st = run_ttv(c, p->ttv[o.idx], A, nullptr);
+    }
+    if (st != PPALS_OK) return st;
+  }
+  for (int n = 0; n < p->N; ++n) {
+    ppals_status st = run_ttv(c, p->ttv[p->mp_ttv[n]], A, c.Mp(n));
+    if (st != PPALS_OK) return st;
+  }
+  for (int n = 0; n < p->N; ++n) {
+    const size_t bytes = (size_t)p->dims[n] * p->R * sizeof(double);
+    HIPCHK(launch_copy(c.Ap(n), A[n], (int64_t)(bytes / sizeof(double)), s));
+    HIPCHK(launch_fill(c.dA(n), 0.0, (int64_t)(bytes / sizeof(double)), s));
+  }
+  HIPCHK(launch_fill(c.U(), 0.0, (int64_t)p->N * p->R * p->R, s));
+  p->ops_built = true;
+  p->sweeps_since_build = 0;
+  return PPALS_OK;
+}
+
+ppals_status pp_correct(const Ctx& c, double* const* A, int n, double* out) {
+  ppals_plan* p = c.p;
+  TtvBatch b = p->ppb[n];
+  double* part = c.at<double>(p->off_ppart);
+  int64_t slot_off = 0;
+  int nj = 0;
+  for (int i = 0; i < p->N; ++i) {
+    if (i == n) continue;
+    TtvJob& J = b.job[nj++];
+    const int lo = std::min(i, n), hi = std::max(i, n);
+    J.T = c.buf(p->leaf_buf[lo][hi]);
+    J.t_is_f32 = p->bulk == DT_F32;
+    J.F = c.dA(i);
+    J.out = part + slot_off;
+    slot_off += (int64_t)J.xsplit * J.out_split_stride;
+  }
+  HIPCHK(launch_ttv(b, c.s));
+  const int64_t count = p->dims[n] * (int64_t)p->R;
+  HIPCHK(launch_combine(out, count, p->R, c.Mp(n), part, p->pp_slots[n], count,
+                        p->second_order ? A[n] : nullptr,
+                        p->second_order ? c.at<double>(p->off_W) : nullptr, c.s));
+  return PPALS_OK;
+}
+
+ppals_status do_pp_sweep(ppals_plan* p, double* const* A, double* S, double normX2, void* ws,
+                         ppals_sweep_record* rec, hipStream_t s) {
+  Ctx c{p, (char*)ws, s};
+  const int kind = p->sweeps_since_build == 0 ? PPALS_SWEEP_PP_INIT : PPALS_SWEEP_PP_APPROX;
+  int prev = -1;
+  for (int n = 0; n < p->N; ++n) {
+    ppals_status st = mode_begin(c, S, normX2, rec, n, prev, 1, 0, kind);
+    if (st == PPALS_OK) st = pp_correct(c, A, n, c.M());
+    if (st == PPALS_OK) st = solve_mode(c, A, S, n, true);
+    if (st != PPALS_OK) return st;
+    prev = n;
+  }
+  ppals_status st = mode_begin(c, S, normX2, rec, -1, prev, 1, 1, kind);
+  if (st == PPALS_OK) p->sweeps_since_build++;
+  return st;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+ppals_status ppals_plan_create(const ppals_desc* d, ppals_plan** out) {
+  if (!d || !out) return fail(PPALS_E_ARG, "desc or out is NULL");
+  *out = nullptr;
+  if (d->order < 3 || d->order > PPALS_MAX_ORDER)
+    return fail(PPALS_E_UNSUPPORTED, "order must be in [3, 8]");
+  if (d->rank < 1 || d->rank > PPALS_MAX_RANK)
+    return fail(PPALS_E_UNSUPPORTED, "rank must be in [1, 128]");
+  for (int i = 0; i < d->order; ++i)
+    if (d->dims[i] < 1) return fail(PPALS_E_ARG, "dims must be >= 1");
+  const bool tier_ok = (d->tensor_dtype == PPALS_FP64 && d->level1_dtype == PPALS_FP64) ||
+                       (d->tensor_dtype == PPALS_FP32 &&
+                        (d->level1_dtype == PPALS_FP32 || d->level1_dtype == PPALS_BF16));
+  if (!tier_ok) return fail(PPALS_E_UNSUPPORTED, "unsupported (tensor_dtype, level1_dtype) pair");
+  ppals_plan* p = new ppals_plan();
+  p->N = d->order;
+  p->R = d->rank;
+  for (int i = 0; i < p->N; ++i) p->dims[i] = d->dims[i];
+  p->tdt = d->tensor_dtype;
+  p->l1dt = d->level1_dtype;
+  p->bulk = d->tensor_dtype == PPALS_FP64 ? DT_F64 : DT_F32;
+  p->second_order = d->use_second_order ? 1 : 0;
+  p->mode_off.resize(p->N);
+  for (int i = 0; i < p->N; ++i) {
+    p->mode_off[i] = (size_t)p->sum_s * p->R;
+    p->sum_s += p->dims[i];
+    p->max_s = std::max(p->max_s, p->dims[i]);
+  }
+  build_dt(p);
+  prune_dt(p);
+  build_pp(p);
+  layout(p);
+  make_describe(p);
+  *out = p;
+  return PPALS_OK;
+}
+
+void ppals_plan_destroy(ppals_plan* p) { delete p; }
+
+size_t ppals_workspace_bytes(const ppals_plan* p) { return p ? p->ws_bytes : 0; }
+
+ppals_status ppals_plan_describe(const ppals_plan* p, char* buf, size_t len) {
+  if (!p || !buf) return fail(PPALS_E_ARG, "plan or buf is NULL");
+  if (len < p->describe.size() + 1) return fail(PPALS_E_ARG, "buffer too small");
+  memcpy(buf, p->describe.c_str(), p->describe.size() + 1);
+  return PPALS_OK;
+}
+
+ppals_status cp_als_sweep(ppals_plan* p, const void* X, const void* Xb, double* const* A,
+                          double* S, double normX2, void* ws, ppals_sweep_record* rec,
+                          hipStream_t s) {
+  ppals_status st = check_common(p, X, Xb, A, ws);
+  if (st != PPALS_OK) return st;
+  if (!S || !rec) return fail(PPALS_E_ARG, "S or rec is NULL");
+  if (!(normX2 > 0.0)) return fail(PPALS_E_ARG, "normX2 must be > 0");
+  return do_als_sweep(p, X, Xb, A, S, normX2, ws, rec, s);
+}
+
+ppals_status pp_build_operators(ppals_plan* p, const void* X, const void* Xb, double* const* A,
+                                void* ws, hipStream_t s) {
+  ppals_status st = check_common(p, X, Xb, A, ws);
+  if (st != PPALS_OK) return st;
+  return do_pp_build(p, X, Xb, A, ws, s);
+}
+
+ppals_status pp_sweep(ppals_plan* p, double* const* A, double* S, double normX2, void* ws,
+                      ppals_sweep_record* rec, hipStream_t s) {
+  if (!p || !A || !S || !rec) return fail(PPALS_E_ARG, "NULL argument");
+  if (!ws) return fail(PPALS_E_WORKSPACE, "workspace is NULL");
+  for (int n = 0; n < p->N; ++n)
+    if (!A[n]) return fail(PPALS_E_ARG, "A[n] is NULL");
+  if (!p->ops_built) return fail(PPALS_E_STATE, "pp_sweep before pp_build_operators");
+  if (!(normX2 > 0.0)) return fail(PPALS_E_ARG, "normX2 must be > 0");
+  return do_pp_sweep(p, A, S, normX2, ws, rec, s);
+}
+
+size_t ppals_gram_solve_workspace_bytes(int32_t R, int64_t rows) {
+  if (R < 1 || rows < 1) return 0;
+  return align256((size_t)R * R * 8) + align256((size_t)rows * 4 * 8) + 256;
+}
+
+ppals_status gram_solve(int32_t R, int64_t rows, const double* Gamma, const void* M,
+                        int32_t m_dtype, double* A_inout, double* grad_norm_out,
+                        int32_t* chol_status_out, void* ws, hipStream_t s) {
+  if (R < 1 || R > PPALS_MAX_RANK) return fail(PPALS_E_UNSUPPORTED, "rank must be in [1, 128]");
+  if (rows < 1) return fail(PPALS_E_ARG, "rows must be >= 1");
+  if (!Gamma || !M || !A_inout || !grad_norm_out || !chol_status_out)
+    return fail(PPALS_E_ARG, "NULL argument");
+  if (m_dtype != PPALS_FP64 && m_dtype != PPALS_FP32)
+    return fail(PPALS_E_UNSUPPORTED, "m_dtype must be FP64 or FP32");
+  if (!ws) return fail(PPALS_E_WORKSPACE, "workspace is NULL");
+  char* w = (char*)ws;
+  double* L = (double*)w;
+  double* rowpart = (double*)(w + align256((size_t)R * R * 8));
+  int* status = (int*)(w + align256((size_t)R * R * 8) + align256((size_t)rows * 4 * 8));
+  HIPCHK(launch_chol_standalone(Gamma, R, L, status, s));
+  SolveArgs a;
+  memset(&a, 0, sizeof(a));
+  a.R = R;
+  a.rows = rows;
+  if (m_dtype == PPALS_FP64) a.M = (const double*)M;
+  else a.M32 = (const float*)M;
+  a.L = L;
+  a.gamma = Gamma;
+  a.A = A_inout;
+  a.rowpart = rowpart;
+  a.status = status;
+  HIPCHK(launch_solve_rows(a, s));
+  HIPCHK(launch_finish_gram_solve(rowpart, rows, grad_norm_out, chol_status_out, status, s));
+  return PPALS_OK;
+}
+
+size_t ppals_norm2_workspace_bytes(void) { return 1024 * sizeof(double); }
+
+ppals_status ppals_tensor_norm2(const void* X, int32_t dtype, int64_t count, double* out,
+                                void* ws, hipStream_t s) {
+  if (!X || !out) return fail(PPALS_E_ARG, "NULL argument");
+  if (!ws) return fail(PPALS_E_WORKSPACE, "workspace is NULL");
+  if (dtype != PPALS_FP64 && dtype != PPALS_FP32) return fail(PPALS_E_UNSUPPORTED, "dtype");
+  if (count < 1) return fail(PPALS_E_ARG, "count must be >= 1");
+  HIPCHK(launch_norm2(X, dtype == PPALS_FP64 ? DT_F64 : DT_F32, count, (double*)ws, 1024, out, s));
+  return PPALS_OK;
+}
+
+ppals_status ppals_cast_bf16(const float* in, uint16_t* out, int64_t count, hipStream_t s) {
+  if (!in || !out) return fail(PPALS_E_ARG, "NULL argument");
+  if (count < 0) return fail(PPALS_E_ARG, "count must be >= 0");
+  if (count == 0) return PPALS_OK;
+  HIPCHK(launch_cast_bf16(in, out, count, s));
+  return PPALS_OK;
+}
+
+ppals_status ppals_level1(ppals_plan* p, const void* X, const void* Xb, double* const* A,
+                          uint32_t mask, void* out, void* ws, hipStream_t s) {
+  ppals_status st = check_common(p, X, Xb, A, ws);
+  if (st != PPALS_OK) return st;
+  if (!out) return fail(PPALS_E_ARG, "out is NULL");
+  int lo = -1, hi = -1;
+  for (int i = 0; i < p->N; ++i)
+    if (mask & (1u << i)) {
+      if (lo < 0) lo = i;
+      hi = i + 1;
+    }
+  if (lo < 0 || (mask >> p->N) != 0) return fail(PPALS_E_ARG, "contract_mask empty or out of range");
+  for (int i = lo; i < hi; ++i)
+    if (!(mask & (1u << i))) return fail(PPALS_E_ARG, "contract_mask must be contiguous");
+  if (hi - lo == p->N) return fail(PPALS_E_ARG, "cannot contract every mode");
+  L1Step stp;
+  stp.lo = lo;
+  stp.hi = hi;
+  stp.geom = l1_config(p, lo, hi);
+  // the workspace was sized for the plan's own contractions
+  Level1Geom& g = stp.geom;
+  if ((size_t)g.nslices * g.Kpad * 16 * g.NB * esize(p->l1dt) > p->sz_B)
+    return fail(PPALS_E_UNSUPPORTED, "contraction larger than the plan's operand buffer");
+  if (g.ksplit > 1 && (size_t)g.ksplit * g.M * p->R * esize(p->bulk) > p->sz_l1part) {
+    g.ksplit = 1;
+    g.kchunk = g.Kpad;
+  }
+  Ctx c{p, (char*)ws, s};
+  return run_l1(c, stp, X, Xb, A, out);
+}
+
+ppals_status ppals_mttkrp(ppals_plan* p, const void* X, const void* Xb, double* const* A,
+                          int32_t mode, void* out, void* ws, hipStream_t s) {
+  ppals_status st = check_common(p, X, Xb, A, ws);
+  if (st != PPALS_OK) return st;
+  if (!out) return fail(PPALS_E_ARG, "out is NULL");
+  if (mode < 0 || mode >= p->N) return fail(PPALS_E_ARG, "mode out of range");
+  // Run the ALS tree up to the first time M^(mode) is formed, without solving.
+  Ctx c{p, (char*)ws, s};
+  for (const Op& o : p->dt_ops) {
+    if (o.kind == OP_L1) {
+      const L1Step& l = p->l1[o.idx];
+      st = run_l1(c, l, X, Xb, A, c.buf(l.out_buf));
+    } else if (o.kind == OP_TTV) {
+      const TtvStep& t = p->ttv[o.idx];
+      if (t.out_buf < 0 && t.out_mode != mode) continue;
+      st = run_ttv(c, t, A, t.out_buf < 0 ? (double*)out : nullptr);
+      if (st == PPALS_OK && t.out_buf < 0 && t.out_mode == mode) return PPALS_OK;
+    }
+    if (st != PPALS_OK) return st;
+  }
+  return fail(PPALS_E_STATE, "mode not produced by the dimension tree");
+}
+
+ppals_status ppals_pp_rhs(ppals_plan* p, double* const* A, const double* S, int32_t mode,
+                          double* out, void* ws, hipStream_t s) {
+  if (!p || !A || !S || !out) return fail(PPALS_E_ARG, "NULL argument");
+  if (!ws) return fail(PPALS_E_WORKSPACE, "workspace is NULL");
+  if (mode < 0 || mode >= p->N) return fail(PPALS_E_ARG, "mode out of range");
+  if (!p->ops_built) return fail(PPALS_E_STATE, "operators not built");
+  Ctx c{p, (char*)ws, s};
+  // dA_i = A_i - A_p,i and U_i = A_i^T dA_i for every mode (the gram kernel's S
+  // output goes to the L scratch, which mode_begin overwrites afterwards)
+  for (int i = 0; i < p->N; ++i) {
+    const int64_t cnt = p->dims[i] * (int64_t)p->R;
+    HIPCHK(launch_sub(c.dA(i), A[i], c.Ap(i), cnt, s));
+    HIPCHK(launch_gram(A[i], c.dA(i), p->dims[i], p->R, c.at<double>(p->off_L),
+                       c.U() + (size_t)i * p->R * p->R, s));
+  }
+  ppals_status st = mode_begin(c, (double*)S, 1.0, nullptr, mode, -1, 1, 0, PPALS_SWEEP_PP_APPROX);
+  if (st != PPALS_OK) return st;
+  return pp_correct(c, A, mode, out);
+}
+
+ppals_status ppals_get_operator(ppals_plan* p, const void* ws, int32_t i, int32_t j, void* out,
+                                hipStream_t s) {
+  if (!p || !ws || !out) return fail(PPALS_E_ARG, "NULL argument");
+  if (!(0 <= i && i < j && j < p->N)) return fail(PPALS_E_ARG, "need 0 <= i < j < N");
+  if (!p->ops_built) return fail(PPALS_E_STATE, "operators not built");
+  const BufDesc& b = p->bufs[p->leaf_buf[i][j]];
+  const size_t bytes = (size_t)p->dims[i] * p->dims[j] * p->R * esize(p->bulk);
+  HIPCHK(hipMemcpyAsync(out, (const char*)ws + b.off, bytes, hipMemcpyDeviceToDevice, s));
+  return PPALS_OK;
+}
+
+ppals_status ppals_exact_residual2(ppals_plan* p, const void* X, double* const* A, double* out,
+                                   void* ws, hipStream_t s) {
+  if (!p || !X || !A || !out) return fail(PPALS_E_ARG, "NULL argument");
+  if (!ws) return fail(PPALS_E_WORKSPACE, "workspace is NULL");
+  Ctx c{p, (char*)ws, s};
+  HIPCHK(launch_residual2(X, p->bulk, A, p->dims, p->N, p->R, c.at<double>(p->off_norm), 4096,
+                          out, s));
+  return PPALS_OK;
+}
+
+ppals_status ppals_run(ppals_plan* p, const void* X, const void* Xb, double* const* A, double* S,
+                       double normX2, void* ws, ppals_sweep_record* rec_dev, double eps,
+                       double delta, int32_t max_sweeps, const int32_t* replay,
+                       ppals_sweep_record* host_records, float* sweep_ms, int32_t* n_done,
+                       hipStream_t s) {
+  ppals_status st = check_common(p, X, Xb, A, ws);
+  if (st != PPALS_OK) return st;
+  if (!S || !rec_dev || !host_records || !n_done) return fail(PPALS_E_ARG, "NULL argument");
+  if (max_sweeps < 0) return fail(PPALS_E_ARG, "max_sweeps < 0");
+  if (!(normX2 > 0.0)) return fail(PPALS_E_ARG, "normX2 must be > 0");
+  *n_done = 0;
+  for (int n = 0; n < p->N; ++n)
+    HIPCHK(launch_gram(A[n], nullptr, p->dims[n], p->R, S + (size_t)n * p->R * p->R, nullptr, s));
+  p->ops_built = false;
+  std::vector<double> rel(p->N, 1.0);
+  const double normX = std::sqrt(normX2);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (sweep_ms) {
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+  }
+  int prev_kind = -1;
+  for (int it = 0; it < max_sweeps; ++it) {
+    int kind;
+    if (replay) {
+      kind = replay[it];
+    } else {
+      bool small = eps > 0.0;
+      for (int n = 0; n < p->N; ++n) small = small && rel[n] < eps;
+      kind = small ? (prev_kind == PPALS_SWEEP_ALS || prev_kind < 0 ? PPALS_SWEEP_PP_INIT
+                                                                     : PPALS_SWEEP_PP_APPROX)
+                   : PPALS_SWEEP_ALS;
+    }
+    if (sweep_ms) HIPCHK(hipEventRecord(e0, s));
+    if (kind == PPALS_SWEEP_PP_INIT) {
+      st = do_pp_build(p, X, Xb, A, ws, s);
+      if (st == PPALS_OK) st = do_pp_sweep(p, A, S, normX2, ws, rec_dev, s);
+    } else if (kind == PPALS_SWEEP_PP_APPROX) {
+      if (!p->ops_built) return fail(PPALS_E_STATE, "replay asks for pp_approx before a build");
+      st = do_pp_sweep(p, A, S, normX2, ws, rec_dev, s);
+    } else {
+      st = do_als_sweep(p, X, Xb, A, S, normX2, ws, rec_dev, s);
+    }
+    if (st != PPALS_OK) return st;
+    if (sweep_ms) HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipMemcpyAsync(&host_records[it], rec_dev, sizeof(ppals_sweep_record),
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (sweep_ms) HIPCHK(hipEventElapsedTime(&sweep_ms[it], e0, e1));
+    host_records[it].sweep_kind = kind;
+    for (int n = 0; n < p->N; ++n) rel[n] = host_records[it].rel_change[n];
+    prev_kind = kind;
+    *n_done = it + 1;
+    if (delta > 0.0) {
+      double g = 0;
+      for (int n = 0; n < p->N; ++n) g += host_records[it].grad_norm[n];
+      if (g <= delta * normX) break;
+    }
+  }
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  return PPALS_OK;
+}
+
+}  // extern "C"

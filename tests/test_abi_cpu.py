@@ -1,0 +1,177 @@
+"""Host-side checks of the C ABI (no GPU): the shared library loads and exports
+every entry point declared in include/ppals.h, argument validation returns the
+documented status codes without touching a device, and the host plans follow
+the dimension-tree schedules and cost formulas of Sections 2.5 and 3.2.3."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from oracle import tree
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ppals.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1811_10573_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1811_10573_amd import build
+        build.build()
+    return _lib.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "typedef")))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), n
+    from paper_1811_10573_amd import _lib
+    assert set(names) == set(_lib.SIGNATURES), set(names) ^ set(_lib.SIGNATURES)
+
+
+def _desc(dims, rank, tdt=0, l1=0, so=1):
+    from paper_1811_10573_amd import _lib
+    d = _lib.Desc()
+    d.order = len(dims)
+    d.rank = rank
+    for i, s in enumerate(dims):
+        d.dims[i] = s
+    d.tensor_dtype, d.level1_dtype, d.use_second_order = tdt, l1, so
+    return d
+
+
+def _create(lib, *a, **k):
+    h = ctypes.c_void_p()
+    st = lib.ppals_plan_create(ctypes.byref(_desc(*a, **k)), ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("dims,rank,tdt,l1,want", [
+    ((5, 6), 3, 0, 0, -2),               # order 2
+    ((2,) * 9, 3, 0, 0, -2),             # order 9 (dims beyond 8 are not even representable)
+    ((5, 6, 7), 0, 0, 0, -2),
+    ((5, 6, 7), 129, 0, 0, -2),
+    ((5, 0, 7), 3, 0, 0, -1),
+    ((5, 6, 7), 3, 0, 1, -2),            # FP64 tensor with FP32 first level
+    ((5, 6, 7), 3, 0, 2, -2),            # FP64 tensor with BF16 first level
+    ((5, 6, 7), 3, 1, 0, -2),
+])
+def test_plan_argument_errors(lib, dims, rank, tdt, l1, want):
+    if len(dims) > 8:
+        d = _desc(dims[:8], rank, tdt, l1)
+        d.order = 9
+        h = ctypes.c_void_p()
+        st = lib.ppals_plan_create(ctypes.byref(d), ctypes.byref(h))
+    else:
+        st, h = _create(lib, dims, rank, tdt, l1)
+    assert st == want
+    assert not h.value
+    assert len(lib.ppals_last_error()) > 0
+
+
+def test_null_arguments_fail_before_any_device_work(lib):
+    st, h = _create(lib, (6, 7, 8), 4)
+    assert st == 0
+    try:
+        nul = ctypes.c_void_p()
+        arr = (ctypes.c_void_p * 3)(1, 2, 3)
+        assert lib.cp_als_sweep(h, nul, nul, arr, nul, 1.0, nul, nul, nul) == -1
+        assert lib.cp_als_sweep(h, ctypes.c_void_p(8), nul, arr, ctypes.c_void_p(8), 1.0, nul,
+                                ctypes.c_void_p(8), nul) == -4
+        assert lib.pp_sweep(h, arr, ctypes.c_void_p(8), 1.0, ctypes.c_void_p(8),
+                            ctypes.c_void_p(8), nul) == -5     # no operators built
+        assert lib.pp_build_operators(h, nul, nul, arr, ctypes.c_void_p(8), nul) == -1
+        assert lib.gram_solve(0, 5, nul, nul, 0, nul, nul, nul, nul, nul) == -2
+        assert lib.gram_solve(4, 5, nul, nul, 0, nul, nul, nul, nul, nul) == -1
+        assert lib.ppals_tensor_norm2(nul, 0, 10, nul, nul, nul) == -1
+        assert lib.ppals_cast_bf16(nul, nul, 10, nul) == -1
+        assert lib.ppals_cast_bf16(ctypes.c_void_p(8), ctypes.c_void_p(8), 0, nul) == 0
+        assert lib.ppals_mttkrp(h, ctypes.c_void_p(8), nul, arr, 7, ctypes.c_void_p(8),
+                                ctypes.c_void_p(8), nul) == -1
+        assert lib.ppals_level1(h, ctypes.c_void_p(8), nul, arr, 0b101, ctypes.c_void_p(8),
+                                ctypes.c_void_p(8), nul) == -1  # not contiguous
+        assert lib.ppals_level1(h, ctypes.c_void_p(8), nul, arr, 0b111, ctypes.c_void_p(8),
+                                ctypes.c_void_p(8), nul) == -1  # all modes
+        assert lib.ppals_get_operator(h, ctypes.c_void_p(8), 0, 1, ctypes.c_void_p(8), nul) == -5
+        assert lib.ppals_get_operator(h, ctypes.c_void_p(8), 1, 0, ctypes.c_void_p(8), nul) == -1
+    finally:
+        lib.ppals_plan_destroy(h)
+
+
+def test_bf16_tier_requires_bf16_copy(lib):
+    st, h = _create(lib, (6, 7, 8), 4, 1, 2)
+    assert st == 0
+    try:
+        arr = (ctypes.c_void_p * 3)(1, 2, 3)
+        nul = ctypes.c_void_p()
+        assert lib.pp_build_operators(h, ctypes.c_void_p(8), nul, arr, ctypes.c_void_p(8), nul) == -1
+    finally:
+        lib.ppals_plan_destroy(h)
+
+
+def _describe(lib, dims, rank, tdt=0, l1=0):
+    import json
+    st, h = _create(lib, dims, rank, tdt, l1)
+    assert st == 0
+    buf = ctypes.create_string_buffer(1 << 20)
+    assert lib.ppals_plan_describe(h, buf, len(buf)) == 0
+    small = ctypes.create_string_buffer(8)
+    assert lib.ppals_plan_describe(h, small, len(small)) == -1
+    ws = lib.ppals_workspace_bytes(h)
+    lib.ppals_plan_destroy(h)
+    return json.loads(buf.value.decode()), ws
+
+
+@pytest.mark.parametrize("N,s,R", [(3, 40, 5), (3, 800, 50), (4, 160, 64), (5, 40, 40), (6, 9, 3),
+                                   (8, 3, 2)])
+def test_plan_costs_match_the_paper(lib, N, s, R):
+    d, ws = _describe(lib, (s,) * N, R)
+    assert ws > 0
+    # Section 2.5: all MTTKRPs of one sweep cost 4 s^N R to leading order (two first-level
+    # contractions of 2 s^N R each)
+    assert d["dt_level1_flops"] == 4 * s ** N * R
+    assert d["dt_ttv_flops"] < d["dt_level1_flops"]
+    # Section 3.2.3: operator build 2R sum_{l=2}^{N-1} C(l+1,2) s^(N-l+2)
+    assert d["pp_build_level1_flops"] + d["pp_build_tree_ttv_flops"] == \
+        tree.pp_build_flops_formula(s, N, R)
+    assert d["pp_build_level1_flops"] == 6 * s ** N * R
+    # Table 1, first-order part of the approximated step: N(N-1) operator contractions
+    assert d["pp_approx_first_order_flops"] == 2 * N * (N - 1) * s * s * R
+
+
+@pytest.mark.parametrize("dims", [(7, 5, 9), (4, 6, 5, 3), (3, 4, 2, 5, 3), (2, 3, 2, 2, 3, 2, 2)])
+def test_dt_schedule_solves_every_mode_once_in_order(lib, dims):
+    d, _ = _describe(lib, dims, 3)
+    solves = [o["mode"] for o in d["dt_ops"] if o["op"] == "solve"]
+    assert solves == list(range(len(dims)))
+    # every TTV that feeds a solve keeps exactly that mode
+    ops = d["dt_ops"]
+    for a, b in zip(ops, ops[1:]):
+        if b["op"] == "solve":
+            assert a["op"] == "ttv" and a["kept"] == [b["mode"]]
+
+
+@pytest.mark.parametrize("N", [3, 4, 5, 6])
+def test_pp_build_schedule_matches_oracle_tree(lib, N):
+    d, _ = _describe(lib, (4,) * N, 2)
+    ops = d["pp_build_ops"]
+    nodes = tree.pp_tree(N)
+    assert len(ops) == len(nodes)
+    for o, (l, child, parent, w) in zip(ops, nodes):
+        assert o["kept"] == [m - 1 for m in child]
+        if l == 2:
+            assert o["op"] == "level1" and o["contract"] == [w - 1, w]
+        else:
+            assert o["op"] == "ttv" and o["src"] == [m - 1 for m in parent]
+            assert o["src"][o["contract_pos"][0]] == w - 1

@@ -1,0 +1,188 @@
+"""GPU parity of whole sweeps (Algorithm 1, Algorithm 3) against the float64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import tensorgen
+from oracle import cp as ocp
+from oracle import pp as opp
+
+from gpu_util import U32, U64, assert_within, dev, fp32_round, to_dev
+
+pytestmark = pytest.mark.gpu
+
+pp = pytest.importorskip("paper_1811_10573_amd")
+
+
+class Run:
+    """Device copies of one problem plus the library state."""
+
+    def __init__(self, prob, tier="f64", second_order=True, init=None):
+        self.prob = prob
+        self.tier = tier
+        dims = prob.shape
+        R = prob.rank
+        tdt = "f64" if tier == "f64" else "f32"
+        self.plan = pp.Plan(dims, R, tdt, tier, second_order)
+        self.Xh = prob.X if tier == "f64" else fp32_round(prob.X)
+        self.X = to_dev(self.Xh, self.plan.torch_dtype)
+        self.Xb = None
+        if tier == "bf16":
+            self.Xb = torch.empty(self.X.numel(), dtype=torch.int16, device=dev())
+            pp.cast_bf16(self.X, self.Xb)
+        init = prob.init if init is None else init
+        self.A = [to_dev(a.copy()) for a in init]
+        N = len(dims)
+        self.S = to_dev(np.stack([a.T @ a for a in init]).reshape(-1))
+        self.ws = self.plan.workspace(dev())
+        self.rec = pp.new_record(dev())
+        nrm = torch.zeros(1, dtype=torch.float64, device=dev())
+        pp.tensor_norm2(self.X, nrm)
+        self.normX2 = float(nrm.item())
+        self.N = N
+
+    def factors(self):
+        return [a.cpu().numpy().reshape(s, self.prob.rank) for a, s in zip(self.A, self.prob.shape)]
+
+    def grams(self):
+        R = self.prob.rank
+        return self.S.cpu().numpy().reshape(self.N, R, R)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("dims,R", [((37, 29, 41), 5), ((20, 22, 18, 16), 7), ((6, 7, 5, 6, 4), 4),
+                                    ((50, 3, 60), 2)])
+def test_als_sweep_matches_oracle(dims, R):
+    prob = tensorgen.make_problem(dims, R, seed=3, eta=1e-2)
+    r = Run(prob)
+    A = [a.copy() for a in prob.init]
+    S = [a.T @ a for a in A]
+    for sweep in range(3):
+        pp.cp_als_sweep(r.plan, r.X, None, r.A, r.S, r.normX2, r.ws, r.rec)
+        ref = ocp.als_sweep(prob.X, A, S)
+        got = pp.read_record(r.rec)
+        for n in range(len(dims)):
+            assert rel(r.factors()[n], A[n]) < 1e-9, (sweep, n)
+            assert abs(got["grad_norm"][n] - ref.grad_norm[n]) <= 1e-8 * max(1.0, ref.grad_norm[n])
+            assert abs(got["rel_change"][n] - ref.rel_change[n]) <= 1e-9 * max(1e-3, ref.rel_change[n])
+        assert abs(got["fit_est"] - ref.fit_est) < 1e-11
+        assert got["kind"] == "als"
+        for n in range(len(dims)):
+            np.testing.assert_allclose(r.grams()[n], S[n], rtol=1e-10, atol=1e-10 * np.abs(S[n]).max())
+
+
+@pytest.mark.parametrize("tier", ["f64", "f32"])
+@pytest.mark.parametrize("dims,R", [((13, 11, 12), 3), ((9, 8, 7, 10), 5), ((5, 4, 6, 5, 4), 3)])
+def test_pp_operators_match_definition(tier, dims, R):
+    prob = tensorgen.make_problem(dims, R, seed=4, eta=1e-2)
+    A = [fp32_round(a) for a in prob.init] if tier == "f32" else prob.init
+    r = Run(prob, tier, init=A)
+    pp.pp_build_operators(r.plan, r.X, r.Xb, r.A, r.ws)
+    st = opp.build_operators(r.Xh, A)
+    u = U64 if tier == "f64" else U32
+    total = int(np.prod(dims))
+    for (i, j), op in st.ops.items():
+        out = torch.empty(dims[i] * dims[j] * R, dtype=r.plan.torch_dtype, device=dev())
+        pp.get_operator(r.plan, r.ws, i, j, out)
+        base = ocp.partial_mttkrp(np.abs(r.Xh), [np.abs(a) for a in A], (i, j))
+        K = total // (dims[i] * dims[j])
+        assert_within(out.cpu().numpy().reshape(op.shape), op, (K + 4) * u * base,
+                      f"{tier} operator ({i},{j}) {dims}")
+
+
+@pytest.mark.parametrize("second_order", [True, False])
+@pytest.mark.parametrize("dims,R", [((13, 11, 12), 3), ((9, 8, 7, 10), 5), ((5, 4, 6, 5, 4), 3),
+                                    ((30, 20, 25), 40)])
+def test_pp_rhs_matches_oracle(dims, R, second_order):
+    prob = tensorgen.make_problem(dims, R, seed=5, eta=1e-2)
+    r = Run(prob, "f64", second_order)
+    pp.pp_build_operators(r.plan, r.X, None, r.A, r.ws)
+    st = opp.build_operators(prob.X, prob.init)
+    rng = np.random.default_rng(6)
+    A = [a + 0.03 * rng.standard_normal(a.shape) for a in prob.init]
+    st.dA = [a - b for a, b in zip(A, prob.init)]
+    S = [a.T @ a for a in A]
+    Ad = [to_dev(a) for a in A]
+    Sd = to_dev(np.stack(S).reshape(-1))
+    for n in range(len(dims)):
+        out = torch.empty(dims[n] * R, dtype=torch.float64, device=dev())
+        pp.pp_rhs(r.plan, Ad, Sd, n, out, r.ws)
+        want = opp.pp_rhs(st, A, S, n, second_order)
+        assert rel(out.cpu().numpy().reshape(dims[n], R), want) < 1e-11, n
+
+
+@pytest.mark.parametrize("dims,R", [((23, 19, 21), 4), ((8, 9, 7, 8), 6), ((5, 4, 6, 5, 4), 3)])
+def test_pp_sweeps_match_oracle(dims, R):
+    prob = tensorgen.make_problem(dims, R, seed=7, eta=1e-3)
+    # bring the iterate close to convergence first (plain ALS), identical on both sides
+    A0, _ = ocp.cp_als(prob.X, prob.init, 8)
+    r = Run(prob, "f64", init=A0)
+    pp.pp_build_operators(r.plan, r.X, None, r.A, r.ws)
+    A = [a.copy() for a in A0]
+    S = [a.T @ a for a in A]
+    st = opp.build_operators(prob.X, A)
+    normX2 = float(np.sum(prob.X ** 2))
+    for k in range(4):
+        pp.pp_sweep(r.plan, r.A, r.S, r.normX2, r.ws, r.rec)
+        ref = opp.pp_sweep(st, A, S, normX2, True, "pp_init" if k == 0 else "pp_approx")
+        got = pp.read_record(r.rec)
+        assert got["kind"] == ref.kind
+        for n in range(len(dims)):
+            assert rel(r.factors()[n], A[n]) < 1e-9, (k, n)
+            assert abs(got["rel_change"][n] - ref.rel_change[n]) <= 1e-8 * max(1e-4, ref.rel_change[n])
+        assert abs(got["fit_est"] - ref.fit_est) < 1e-11
+
+
+def test_c1_als_fit_every_sweep():
+    """64^3, planted rank 10 with N(0,1) factors, 1e-3 noise, 20 ALS sweeps from a uniform
+    init: the fit of every sweep matches the oracle to 1e-10 relative."""
+    prob = tensorgen.make_problem((64, 64, 64), 10, seed=0, eta=1e-3)
+    r = Run(prob)
+    recs, ms = pp.run(r.plan, r.X, None, r.A, r.S, r.normX2, r.ws, r.rec, eps=0.0, max_sweeps=20)
+    _, ref = ocp.cp_als(prob.X, prob.init, 20)
+    assert [x["kind"] for x in recs] == ["als"] * 20
+    for i, (g, o) in enumerate(zip(recs, ref)):
+        assert abs(g["fit_est"] - o.fit_est) <= 1e-10 * abs(o.fit_est), (i, g["fit_est"], o.fit_est)
+    assert all(m > 0 for m in ms)
+
+
+@pytest.mark.parametrize("dims,R,eps", [((40, 36, 44), 6, 0.1), ((12, 14, 11, 13), 5, 0.2),
+                                        ((7, 6, 8, 5, 6), 3, 0.2)])
+def test_pp_als_run_replay_matches_oracle(dims, R, eps):
+    prob = tensorgen.make_problem(dims, R, seed=8, eta=1e-3, collinearity=0.5)
+    r = Run(prob)
+    recs, _ = pp.run(r.plan, r.X, None, r.A, r.S, r.normX2, r.ws, r.rec, eps=eps, max_sweeps=40)
+    kinds = [x["kind"] for x in recs]
+    assert "pp_approx" in kinds, kinds
+    A_or, ref = opp.pp_als(prob.X, prob.init, eps=eps, sweeps=40, replay=kinds)
+    for n in range(len(dims)):
+        assert rel(r.factors()[n], A_or[n]) < 1e-8, n
+    assert abs(recs[-1]["fit_est"] - ref[-1].fit_est) <= 1e-10
+    # the free-running oracle takes the same decisions (no threshold ties here)
+    _, free = opp.pp_als(prob.X, prob.init, eps=eps, sweeps=40)
+    assert [x.kind for x in free] == kinds
+
+
+@pytest.mark.parametrize("tier,tol", [("f32", 1e-5), ("bf16", 1e-3)])
+def test_lower_precision_tiers_final_fit(tier, tol):
+    """FP32 tier within 1e-5 and BF16 first level within 1e-3 of the FP64 oracle's fit."""
+    prob = tensorgen.make_problem((48, 40, 44), 6, seed=9, eta=1e-2)
+    r = Run(prob, tier)
+    recs, _ = pp.run(r.plan, r.X, r.Xb, r.A, r.S, r.normX2, r.ws, r.rec, eps=0.1, max_sweeps=30)
+    A_or, _ = opp.pp_als(prob.X, prob.init, eps=0.1, sweeps=30)
+    f_or = ocp.fit_direct(prob.X, A_or)
+    f_gpu = ocp.fit_direct(prob.X, r.factors())
+    assert abs(f_gpu - f_or) <= tol * abs(f_or), (f_gpu, f_or)
+
+
+def test_no_second_order_flag_matches_oracle():
+    prob = tensorgen.make_problem((15, 16, 14), 4, seed=10, eta=1e-3)
+    r = Run(prob, "f64", second_order=False)
+    recs, _ = pp.run(r.plan, r.X, None, r.A, r.S, r.normX2, r.ws, r.rec, eps=0.05, max_sweeps=25)
+    kinds = [x["kind"] for x in recs]
+    A_or, ref = opp.pp_als(prob.X, prob.init, eps=0.05, sweeps=25, second_order=False, replay=kinds)
+    for n in range(3):
+        assert rel(r.factors()[n], A_or[n]) < 1e-8
