@@ -167,9 +167,9 @@ ppals_status ppals_tensor_norm2(const void* X, int32_t dtype, int64_t count, dou
  * bit patterns.  Used to make X_bf16 for the BF16 first-level tier. */
 ppals_status ppals_cast_bf16(const float* in, uint16_t* out, int64_t count, hipStream_t stream);
 
-/* MTTKRP of one mode through the library's contraction kernels, without the
- * solve: out = X_(n) (Khatri-Rao product of the other factors), s_n x R in
- * the plan's bulk dtype (FP64 in the FP64 tier, FP32 otherwise).
+/* MTTKRP of one mode through the library's contraction kernels (the ALS
+ * dimension tree up to that mode, without any solve): out = X_(n) times the
+ * Khatri-Rao product of the other factors (Section 2.3), s_n x R doubles.
  * 0 <= mode < N. */
 ppals_status ppals_mttkrp(ppals_plan* plan, const void* X, const void* X_bf16,
                           double* const* A, int32_t mode, void* out, void* ws,
@@ -215,6 +215,26 @@ ppals_status ppals_run(ppals_plan* plan, const void* X, const void* X_bf16, doub
                        double eps, double delta, int32_t max_sweeps, const int32_t* replay,
                        ppals_sweep_record* host_records, float* sweep_ms, int32_t* n_done,
                        hipStream_t stream);
+
+/* Optional timing of kernel classes with HIP events recorded on the launch
+ * stream around each launch (level-1 GEMM, PP correction TTV, dimension-tree
+ * TTV, PP combine, per-mode FP64 tail, operand preparation, PP-tree TTV,
+ * split reduction).  Statistics accumulate while enabled and are resolved at
+ * the per-sweep synchronisation of ppals_run or by ppals_get_profile (which
+ * waits for the recorded events).  flops and bytes are the algorithmic work
+ * of the timed launches (compulsory HBM traffic: inputs read once, outputs
+ * written once). */
+#define PPALS_PROF_CLASSES 8
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double total_ms;
+  double flops;
+  double bytes;
+} ppals_kernel_stat;
+ppals_status ppals_set_profiling(ppals_plan* plan, int32_t enable);
+ppals_status ppals_get_profile(ppals_plan* plan, ppals_kernel_stat* out, int32_t max_entries,
+                               int32_t* n_out, int32_t reset);
 
 #ifdef __cplusplus
 }

@@ -126,6 +126,27 @@ class Plan:
         return _p(X), None
 
 
+def set_profiling(plan, enable=True):
+    _lib.check(lib().ppals_set_profiling(plan.handle, 1 if enable else 0))
+
+
+def get_profile(plan, reset=False):
+    """Per-kernel-class statistics: {name: {launches, total_ms, avg_ms, flops, bytes}}."""
+    arr = (_lib.KernelStat * _lib.PROF_CLASSES)()
+    n = ctypes.c_int32(0)
+    _lib.check(lib().ppals_get_profile(plan.handle, arr, _lib.PROF_CLASSES, ctypes.byref(n),
+                                       1 if reset else 0))
+    out = {}
+    for i in range(n.value):
+        e = arr[i]
+        out[e.name.decode()] = {
+            "launches": int(e.launches), "total_ms": e.total_ms,
+            "avg_ms": e.total_ms / e.launches if e.launches else 0.0,
+            "flops": e.flops, "bytes": e.bytes,
+        }
+    return out
+
+
 def new_record(device="cuda"):
     return torch.zeros(RECORD_BYTES, dtype=torch.uint8, device=device)
 

@@ -45,6 +45,18 @@ class SweepRecord(ctypes.Structure):
 
 RECORD_BYTES = ctypes.sizeof(SweepRecord)
 
+PROF_CLASSES = 8
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [
+        ("name", ctypes.c_char * 32),
+        ("launches", ctypes.c_int64),
+        ("total_ms", ctypes.c_double),
+        ("flops", ctypes.c_double),
+        ("bytes", ctypes.c_double),
+    ]
+
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
 _i64 = ctypes.c_int64
@@ -76,6 +88,8 @@ SIGNATURES = {
     "ppals_run": (_i32, [_vp, _vp, _vp, _ptrs, _vp, _dbl, _vp, _vp, _dbl, _dbl, _i32,
                          ctypes.POINTER(_i32), ctypes.POINTER(SweepRecord),
                          ctypes.POINTER(ctypes.c_float), ctypes.POINTER(_i32), _vp]),
+    "ppals_set_profiling": (_i32, [_vp, _i32]),
+    "ppals_get_profile": (_i32, [_vp, ctypes.POINTER(KernelStat), _i32, ctypes.POINTER(_i32), _i32]),
 }
 
 _LIB = None

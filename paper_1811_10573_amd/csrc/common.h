@@ -73,7 +73,7 @@ namespace ppk {
 hipError_t launch_prep_operand(const KrpDesc& krp, const Level1Geom& g, int dt, void* out,
                                hipStream_t s);
 hipError_t launch_level1(const void* X, int dt, const void* B, const Level1Geom& g, void* C,
-                         void* partial, hipStream_t s);
+                         void* partial, hipStream_t s, hipEvent_t after_gemm = nullptr);
 hipError_t launch_krp_f64(const KrpDesc& krp, int64_t K, double* out, hipStream_t s);
 hipError_t launch_ttv(const TtvBatch& b, hipStream_t s);
 hipError_t launch_combine(double* out, int64_t count, int R, const double* base,

@@ -570,7 +570,7 @@ static bool vec_ok(int dt, const Level1Geom& g) {
 }
 
 hipError_t launch_level1(const void* X, int dt, const void* B, const Level1Geom& g, void* C,
-                         void* partial, hipStream_t s) {
+                         void* partial, hipStream_t s, hipEvent_t after_gemm) {
   const bool split = g.ksplit > 1;
   void* dst = split ? partial : C;
   const int64_t stride = split ? g.M * (int64_t)g.R : 0;
@@ -586,7 +586,12 @@ hipError_t launch_level1(const void* X, int dt, const void* B, const Level1Geom&
     else { if (vec) launch_bf16_nb<2, false, true>(X, B, g, dst, stride, s); else launch_bf16_nb<2, false, false>(X, B, g, dst, stride, s); }
   }
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || !split) return e;
+  if (e != hipSuccess) return e;
+  if (after_gemm) {
+    e = hipEventRecord(after_gemm, s);
+    if (e != hipSuccess) return e;
+  }
+  if (!split) return hipSuccess;
   const int64_t count = g.M * (int64_t)g.R;
   if (dt == DT_F64)
     hipLaunchKernelGGL((k_reduce_splits<double, double>), dim3(grid_for(count)), dim3(256), 0, s,

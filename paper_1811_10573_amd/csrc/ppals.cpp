@@ -117,6 +117,13 @@ struct ppals_plan {
   bool ops_built = false;
   int sweeps_since_build = 0;
 
+  // optional per-kernel-class timing with HIP events on the launch stream
+  bool prof = false;
+  struct Pending { int cls; hipEvent_t a, b; double flops, bytes; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  ppals_kernel_stat stats[PPALS_PROF_CLASSES];
+
   std::string describe;
 };
 
@@ -509,6 +516,66 @@ struct Ctx {
   void* buf(int b) const { return ws + p->bufs[b].off; }
 };
 
+const char* const kProfNames[PPALS_PROF_CLASSES] = {
+    "level1_gemm", "pp_correct_ttv", "dt_ttv", "pp_combine", "mode_tail", "prep_operand",
+    "pp_build_ttv", "split_reduce"};
+
+hipEvent_t prof_event(ppals_plan* p) {
+  if (!p->pool.empty()) {
+    hipEvent_t e = p->pool.back();
+    p->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one launch (or a short group of launches) of a kernel class.
+struct Prof {
+  ppals_plan* p;
+  int cls;
+  hipStream_t s;
+  double flops, bytes;
+  hipEvent_t a = nullptr;
+  Prof(ppals_plan* p_, int cls_, hipStream_t s_, double f = 0, double b = 0)
+      : p(p_), cls(cls_), s(s_), flops(f), bytes(b) {
+    if (p->prof) {
+      a = prof_event(p);
+      if (a && hipEventRecord(a, s) != hipSuccess) a = nullptr;
+    }
+  }
+  hipEvent_t end_event() {
+    if (!p->prof || !a) return nullptr;
+    hipEvent_t b = prof_event(p);
+    if (!b) return nullptr;
+    p->pending.push_back({cls, a, b, flops, bytes});
+    a = nullptr;
+    return b;
+  }
+  void end() {
+    hipEvent_t b = end_event();
+    if (b && hipEventRecord(b, s) != hipSuccess) p->pending.pop_back();
+  }
+};
+
+// Fold finished event pairs into the statistics (the stream must have been synchronised).
+void prof_resolve(ppals_plan* p) {
+  for (auto& e : p->pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(e.b) == hipSuccess && hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+      ppals_kernel_stat& st = p->stats[e.cls];
+      st.launches += 1;
+      st.total_ms += ms;
+      st.flops += e.flops;
+      st.bytes += e.bytes;
+    }
+    p->pool.push_back(e.a);
+    p->pool.push_back(e.b);
+  }
+  p->pending.clear();
+}
+
 ppals_status run_l1(const Ctx& c, const L1Step& st, const void* X, const void* Xb,
                     double* const* A, void* out) {
   ppals_plan* p = c.p;
@@ -521,15 +588,25 @@ ppals_status run_l1(const Ctx& c, const L1Step& st, const void* X, const void* X
     krp.dim[f] = p->dims[st.lo + f];
   }
   void* B = c.ws + p->off_B;
-  HIPCHK(launch_prep_operand(krp, st.geom, p->l1dt, B, c.s));
+  {
+    Prof pr(p, 5, c.s);
+    HIPCHK(launch_prep_operand(krp, st.geom, p->l1dt, B, c.s));
+    pr.end();
+  }
   const void* xin = p->l1dt == DT_BF16 ? Xb : X;
-  HIPCHK(launch_level1(xin, p->l1dt, B, st.geom, out, c.ws + p->off_l1part, c.s));
+  const Level1Geom& g = st.geom;
+  const double flops = 2.0 * (double)g.M * (double)g.K * p->R;
+  const double bytes = (double)g.M * g.K * esize(p->l1dt) + (double)g.K * p->R * esize(p->l1dt) +
+                       (double)g.M * p->R * esize(p->bulk) * g.ksplit;
+  Prof pr(p, 0, c.s, flops, bytes);
+  HIPCHK(launch_level1(xin, p->l1dt, B, st.geom, out, c.ws + p->off_l1part, c.s, pr.end_event()));
   return PPALS_OK;
 }
 
 // Run a TTV step; out_fp64 (if non-null) receives the FP64 result (M buffers),
 // otherwise the step's intermediate buffer gets the bulk-dtype result.
-ppals_status run_ttv(const Ctx& c, const TtvStep& t, double* const* A, double* out_fp64) {
+ppals_status run_ttv(const Ctx& c, const TtvStep& t, double* const* A, double* out_fp64,
+                     int cls = 2) {
   ppals_plan* p = c.p;
   const double* F;
   if (t.blen == 1) {
@@ -557,8 +634,14 @@ ppals_status run_ttv(const Ctx& c, const TtvStep& t, double* const* A, double* o
   b.job[0].F = F;
   double* part = c.at<double>(p->off_tpart);
   b.job[0].out = part;
-  HIPCHK(launch_ttv(b, c.s));
   const int64_t count = t.P * t.Q * p->R;
+  {
+    const double tb = (double)t.P * t.X * t.Q * p->R * esize(p->bulk);
+    Prof pr(p, cls, c.s, 2.0 * (double)t.P * t.X * t.Q * p->R,
+            tb + (double)count * 8 * t.job.xsplit + (double)t.X * p->R * 8);
+    HIPCHK(launch_ttv(b, c.s));
+    pr.end();
+  }
   if (out_fp64) {
     HIPCHK(launch_combine(out_fp64, count, p->R, nullptr, part, t.job.xsplit, count, nullptr,
                           nullptr, c.s));
@@ -645,8 +728,10 @@ ppals_status do_als_sweep(ppals_plan* p, const void* X, const void* Xb, double* 
       st = run_ttv(c, t, A, t.out_buf < 0 ? c.M() : nullptr);
     } else {
       const int n = o.idx;
+      Prof pr(p, 4, s);
       st = mode_begin(c, S, normX2, rec, n, prev, 0, 0, PPALS_SWEEP_ALS);
       if (st == PPALS_OK) st = solve_mode(c, A, S, n, false);
+      pr.end();
       prev = n;
     }
     if (st != PPALS_OK) return st;
@@ -663,12 +748,12 @@ ppals_status do_pp_build(ppals_plan* p, const void* X, const void* Xb, double* c
       const L1Step& l = p->l1[o.idx];
       st = run_l1(c, l, X, Xb, A, c.buf(l.out_buf));
     } else {
-      st = run_ttv(c, p->ttv[o.idx], A, nullptr);
+      st = run_ttv(c, p->ttv[o.idx], A, nullptr, 6);
     }
     if (st != PPALS_OK) return st;
   }
   for (int n = 0; n < p->N; ++n) {
-    ppals_status st = run_ttv(c, p->ttv[p->mp_ttv[n]], A, c.Mp(n));
+    ppals_status st = run_ttv(c, p->ttv[p->mp_ttv[n]], A, c.Mp(n), 6);
     if (st != PPALS_OK) return st;
   }
   for (int n = 0; n < p->N; ++n) {
@@ -698,11 +783,27 @@ ppals_status pp_correct(const Ctx& c, double* const* A, int n, double* out) {
     J.out = part + slot_off;
     slot_off += (int64_t)J.xsplit * J.out_split_stride;
   }
-  HIPCHK(launch_ttv(b, c.s));
   const int64_t count = p->dims[n] * (int64_t)p->R;
-  HIPCHK(launch_combine(out, count, p->R, c.Mp(n), part, p->pp_slots[n], count,
-                        p->second_order ? A[n] : nullptr,
-                        p->second_order ? c.at<double>(p->off_W) : nullptr, c.s));
+  {
+    double fl = 0, by = 0;
+    for (int i = 0; i < p->N; ++i) {
+      if (i == n) continue;
+      const double e = (double)p->dims[i] * p->dims[n] * p->R;
+      fl += 2.0 * e;
+      by += e * esize(p->bulk) + (double)p->dims[i] * p->R * 8;
+    }
+    by += (double)p->pp_slots[n] * count * 8;
+    Prof pr(p, 1, c.s, fl, by);
+    HIPCHK(launch_ttv(b, c.s));
+    pr.end();
+  }
+  {
+    Prof pr(p, 3, c.s, 0, (double)(p->pp_slots[n] + 3) * count * 8);
+    HIPCHK(launch_combine(out, count, p->R, c.Mp(n), part, p->pp_slots[n], count,
+                          p->second_order ? A[n] : nullptr,
+                          p->second_order ? c.at<double>(p->off_W) : nullptr, c.s));
+    pr.end();
+  }
   return PPALS_OK;
 }
 
@@ -712,9 +813,18 @@ ppals_status do_pp_sweep(ppals_plan* p, double* const* A, double* S, double norm
   const int kind = p->sweeps_since_build == 0 ? PPALS_SWEEP_PP_INIT : PPALS_SWEEP_PP_APPROX;
   int prev = -1;
   for (int n = 0; n < p->N; ++n) {
-    ppals_status st = mode_begin(c, S, normX2, rec, n, prev, 1, 0, kind);
+    ppals_status st;
+    {
+      Prof pr(p, 4, s);
+      st = mode_begin(c, S, normX2, rec, n, prev, 1, 0, kind);
+      pr.end();
+    }
     if (st == PPALS_OK) st = pp_correct(c, A, n, c.M());
-    if (st == PPALS_OK) st = solve_mode(c, A, S, n, true);
+    if (st == PPALS_OK) {
+      Prof pr(p, 4, s);
+      st = solve_mode(c, A, S, n, true);
+      pr.end();
+    }
     if (st != PPALS_OK) return st;
     prev = n;
   }
@@ -766,7 +876,35 @@ ppals_status ppals_plan_create(const ppals_desc* d, ppals_plan** out) {
   return PPALS_OK;
 }
 
-void ppals_plan_destroy(ppals_plan* p) { delete p; }
+void ppals_plan_destroy(ppals_plan* p) {
+  if (!p) return;
+  for (auto& e : p->pending) {
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  for (auto e : p->pool) (void)hipEventDestroy(e);
+  delete p;
+}
+
+ppals_status ppals_set_profiling(ppals_plan* p, int32_t enable) {
+  if (!p) return fail(PPALS_E_ARG, "plan is NULL");
+  p->prof = enable != 0;
+  return PPALS_OK;
+}
+
+ppals_status ppals_get_profile(ppals_plan* p, ppals_kernel_stat* out, int32_t max_entries,
+                               int32_t* n_out, int32_t reset) {
+  if (!p || !out || !n_out) return fail(PPALS_E_ARG, "NULL argument");
+  prof_resolve(p);
+  const int n = std::min<int>(max_entries, PPALS_PROF_CLASSES);
+  for (int i = 0; i < n; ++i) {
+    out[i] = p->stats[i];
+    snprintf(out[i].name, sizeof(out[i].name), "%s", kProfNames[i]);
+  }
+  *n_out = n;
+  if (reset) memset(p->stats, 0, sizeof(p->stats));
+  return PPALS_OK;
+}
 
 size_t ppals_workspace_bytes(const ppals_plan* p) { return p ? p->ws_bytes : 0; }
 
@@ -1005,6 +1143,7 @@ ppals_status ppals_run(ppals_plan* p, const void* X, const void* Xb, double* con
                           hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (sweep_ms) HIPCHK(hipEventElapsedTime(&sweep_ms[it], e0, e1));
+    if (p->prof) prof_resolve(p);
     host_records[it].sweep_kind = kind;
     for (int n = 0; n < p->N; ++n) rel[n] = host_records[it].rel_change[n];
     prev_kind = kind;
@@ -1015,8 +1154,8 @@ ppals_status ppals_run(ppals_plan* p, const void* X, const void* Xb, double* con
       if (g <= delta * normX) break;
     }
   }
-  if (e0) hipEventDestroy(e0);
-  if (e1) hipEventDestroy(e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
   return PPALS_OK;
 }
 
