@@ -108,6 +108,49 @@ struct ModeArgs {
 };
 hipError_t launch_mode_begin(const ModeArgs& a, hipStream_t s);
 
+// Fast tail (rank <= 64): head kernel on an auxiliary stream, fused solve.
+struct HeadArgs {
+  int N, R;
+  int n;              // mode to prepare
+  int pp, second_order;
+  double* S;          // N x R x R
+  double* U;          // N x R x R
+  double* gamma;
+  double* L;
+  double* W;
+  int* status;
+  int* counter;       // per-mode completion counters of the fused solve
+};
+struct FusedSolveArgs {
+  int R;
+  int mode;
+  int64_t rows;
+  const double* base;      // M_p^(n) or NULL
+  const double* part;      // partial slots (FP64)
+  int nslots;
+  int64_t slot_stride;
+  const double* W;         // second-order matrix or NULL
+  const double* L;
+  const double* gamma;
+  double* A;
+  const double* Aref;      // NULL -> old A
+  double* dA;              // NULL -> not stored
+  double* Spart;
+  double* Upart;           // NULL -> no U
+  double* blockpart;
+  const int* status;
+  int* counter;
+  double* S_out;           // S^(n)
+  double* U_out;           // U^(n) (if Upart)
+  void* rec;
+  int write_fit;
+  int sweep_kind;
+  double normX2;
+};
+hipError_t launch_head(const HeadArgs& h, hipStream_t s);
+hipError_t launch_solve_fused(const FusedSolveArgs& a, hipStream_t s);
+int solve_fused_blocks(int64_t rows);
+
 struct SolveArgs {
   int R;
   int64_t rows;

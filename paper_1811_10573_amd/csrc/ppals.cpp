@@ -110,6 +110,11 @@ struct ppals_plan {
   size_t off_status = 0;               // ints
   size_t off_norm = 0;                 // 4096 doubles
   size_t off_ppart = 0, sz_ppart = 0;  // PP partial slots
+  size_t off_Spart = 0, off_Upart = 0, off_blockpart = 0;  // fused-solve partials
+  size_t off_counter = 0;              // per-mode completion counters
+  bool fast = false;                   // rank <= 64: fused head/solve tail
+  hipStream_t aux = nullptr;           // stream for the head kernel (default priority)
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   size_t ws_bytes = 0;
   std::vector<size_t> mode_off;        // element offsets of mode n in sum_s x R arrays
 
@@ -431,6 +436,13 @@ void layout(ppals_plan* p) {
   p->off_scal = take(64 * 8);
   p->off_status = take(64 * 4);
   p->off_norm = take(4096 * 8);
+  {
+    const int64_t nb = solve_fused_blocks(p->max_s);
+    p->off_Spart = take((size_t)nb * R * R * 8);
+    p->off_Upart = take((size_t)nb * R * R * 8);
+    p->off_blockpart = take((size_t)nb * 4 * 8);
+    p->off_counter = take(64 * sizeof(int));
+  }
   for (auto& b : p->bufs) b.off = take(b.bytes);
   p->ws_bytes = off;
 }
@@ -606,7 +618,7 @@ ppals_status run_l1(const Ctx& c, const L1Step& st, const void* X, const void* X
 // Run a TTV step; out_fp64 (if non-null) receives the FP64 result (M buffers),
 // otherwise the step's intermediate buffer gets the bulk-dtype result.
 ppals_status run_ttv(const Ctx& c, const TtvStep& t, double* const* A, double* out_fp64,
-                     int cls = 2) {
+                     int cls = 2, bool keep_partials = false) {
   ppals_plan* p = c.p;
   const double* F;
   if (t.blen == 1) {
@@ -642,6 +654,7 @@ ppals_status run_ttv(const Ctx& c, const TtvStep& t, double* const* A, double* o
     HIPCHK(launch_ttv(b, c.s));
     pr.end();
   }
+  if (keep_partials) return PPALS_OK;
   if (out_fp64) {
     HIPCHK(launch_combine(out_fp64, count, p->R, nullptr, part, t.job.xsplit, count, nullptr,
                           nullptr, c.s));
@@ -713,9 +726,118 @@ ppals_status check_common(const ppals_plan* p, const void* X, const void* Xb, do
   return PPALS_OK;
 }
 
+HeadArgs head_args(const Ctx& c, double* S, int n, int pp) {
+  ppals_plan* p = c.p;
+  HeadArgs h;
+  memset(&h, 0, sizeof(h));
+  h.N = p->N;
+  h.R = p->R;
+  h.n = n;
+  h.pp = pp;
+  h.second_order = p->second_order;
+  h.S = S;
+  h.U = c.U();
+  h.gamma = c.at<double>(p->off_gamma);
+  h.L = c.at<double>(p->off_L);
+  h.W = c.at<double>(p->off_W);
+  h.status = c.at<int>(p->off_status);
+  h.counter = c.at<int>(p->off_counter);
+  return h;
+}
+
+// Fast path: the head of mode n runs on the auxiliary stream, forked from the main
+// stream after the previous solve and joined before the solve of mode n.
+ppals_status head_fork(const Ctx& c, const HeadArgs& h) {
+  ppals_plan* p = c.p;
+  if (!p->aux) {
+    HIPCHK(hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
+  }
+  HIPCHK(hipEventRecord(p->ev_fork, c.s));
+  HIPCHK(hipStreamWaitEvent(p->aux, p->ev_fork, 0));
+  HIPCHK(launch_head(h, p->aux));
+  HIPCHK(hipEventRecord(p->ev_join, p->aux));
+  return PPALS_OK;
+}
+ppals_status head_join(const Ctx& c) {
+  HIPCHK(hipStreamWaitEvent(c.s, c.p->ev_join, 0));
+  return PPALS_OK;
+}
+
+ppals_status solve_fused(const Ctx& c, double* const* A, double* S, double normX2,
+                         ppals_sweep_record* rec, int n, const double* base, const double* part,
+                         int nslots, bool pp, int kind) {
+  ppals_plan* p = c.p;
+  FusedSolveArgs a;
+  memset(&a, 0, sizeof(a));
+  a.R = p->R;
+  a.mode = n;
+  a.rows = p->dims[n];
+  a.base = base;
+  a.part = part;
+  a.nslots = nslots;
+  a.slot_stride = p->dims[n] * (int64_t)p->R;
+  a.W = (pp && p->second_order) ? c.at<double>(p->off_W) : nullptr;
+  a.L = c.at<double>(p->off_L);
+  a.gamma = c.at<double>(p->off_gamma);
+  a.A = A[n];
+  a.Aref = pp ? c.Ap(n) : nullptr;
+  a.dA = pp ? c.dA(n) : nullptr;
+  a.Spart = c.at<double>(p->off_Spart);
+  a.Upart = pp ? c.at<double>(p->off_Upart) : nullptr;
+  a.blockpart = c.at<double>(p->off_blockpart);
+  a.status = c.at<int>(p->off_status) + n;
+  a.counter = c.at<int>(p->off_counter) + n;
+  a.S_out = S + (size_t)n * p->R * p->R;
+  a.U_out = c.U() + (size_t)n * p->R * p->R;
+  a.rec = rec;
+  a.write_fit = n == p->N - 1;
+  a.sweep_kind = kind;
+  a.normX2 = normX2;
+  Prof pr(p, 4, c.s);
+  HIPCHK(launch_solve_fused(a, c.s));
+  pr.end();
+  return PPALS_OK;
+}
+
 ppals_status do_als_sweep(ppals_plan* p, const void* X, const void* Xb, double* const* A,
                           double* S, double normX2, void* ws, ppals_sweep_record* rec,
                           hipStream_t s) {
+  if (p->fast) {
+    Ctx c{p, (char*)ws, s};
+    int prev = -1, nslots = 0;
+    bool forked = false;
+    for (const Op& o : p->dt_ops) {
+      ppals_status st = PPALS_OK;
+      if (o.kind != OP_SOLVE && !forked) {
+        st = head_fork(c, head_args(c, S, prev + 1, 0));
+        forked = true;
+      }
+      if (st != PPALS_OK) return st;
+      if (o.kind == OP_L1) {
+        const L1Step& l = p->l1[o.idx];
+        st = run_l1(c, l, X, Xb, A, c.buf(l.out_buf));
+      } else if (o.kind == OP_TTV) {
+        const TtvStep& t = p->ttv[o.idx];
+        if (t.out_buf < 0) {
+          st = run_ttv(c, t, A, nullptr, 2, /*keep_partials=*/true);
+          nslots = t.job.xsplit;
+        } else {
+          st = run_ttv(c, t, A, nullptr);
+        }
+      } else {
+        st = head_join(c);
+        if (st == PPALS_OK)
+          st = solve_fused(c, A, S, normX2, rec, o.idx, nullptr, c.at<double>(p->off_tpart),
+                           nslots, false, PPALS_SWEEP_ALS);
+        prev = o.idx;
+        forked = false;
+      }
+      if (st != PPALS_OK) return st;
+    }
+    return PPALS_OK;
+  }
   Ctx c{p, (char*)ws, s};
   int prev = -1;
   for (const Op& o : p->dt_ops) {
@@ -812,6 +934,43 @@ ppals_status do_pp_sweep(ppals_plan* p, double* const* A, double* S, double norm
   Ctx c{p, (char*)ws, s};
   const int kind = p->sweeps_since_build == 0 ? PPALS_SWEEP_PP_INIT : PPALS_SWEEP_PP_APPROX;
   int prev = -1;
+  if (p->fast) {
+    double* part = c.at<double>(p->off_ppart);
+    for (int n = 0; n < p->N; ++n) {
+      TtvBatch b = p->ppb[n];
+      int64_t slot_off = 0;
+      int nj = 0;
+      double fl = 0, by = 0;
+      for (int i = 0; i < p->N; ++i) {
+        if (i == n) continue;
+        TtvJob& J = b.job[nj++];
+        const int lo = std::min(i, n), hi = std::max(i, n);
+        J.T = c.buf(p->leaf_buf[lo][hi]);
+        J.t_is_f32 = p->bulk == DT_F32;
+        J.F = c.dA(i);
+        J.out = part + slot_off;
+        slot_off += (int64_t)J.xsplit * J.out_split_stride;
+        const double e = (double)p->dims[i] * p->dims[n] * p->R;
+        fl += 2.0 * e;
+        by += e * esize(p->bulk) + (double)p->dims[i] * p->R * 8;
+      }
+      by += (double)p->pp_slots[n] * p->dims[n] * p->R * 8;
+      ppals_status st = head_fork(c, head_args(c, S, n, 1));
+      if (st != PPALS_OK) return st;
+      {
+        Prof pr(p, 1, s, fl, by);
+        HIPCHK(launch_ttv(b, s));
+        pr.end();
+      }
+      st = head_join(c);
+      if (st == PPALS_OK)
+        st = solve_fused(c, A, S, normX2, rec, n, c.Mp(n), part, p->pp_slots[n], true, kind);
+      if (st != PPALS_OK) return st;
+      prev = n;
+    }
+    p->sweeps_since_build++;
+    return PPALS_OK;
+  }
   for (int n = 0; n < p->N; ++n) {
     ppals_status st;
     {
@@ -861,6 +1020,7 @@ ppals_status ppals_plan_create(const ppals_desc* d, ppals_plan** out) {
   p->l1dt = d->level1_dtype;
   p->bulk = d->tensor_dtype == PPALS_FP64 ? DT_F64 : DT_F32;
   p->second_order = d->use_second_order ? 1 : 0;
+  p->fast = p->R <= 64;
   p->mode_off.resize(p->N);
   for (int i = 0; i < p->N; ++i) {
     p->mode_off[i] = (size_t)p->sum_s * p->R;
@@ -883,6 +1043,9 @@ void ppals_plan_destroy(ppals_plan* p) {
     (void)hipEventDestroy(e.b);
   }
   for (auto e : p->pool) (void)hipEventDestroy(e);
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+  if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+  if (p->aux) (void)hipStreamDestroy(p->aux);
   delete p;
 }
 
