@@ -119,11 +119,22 @@ struct HeadArgs {
   double* L;
   double* W;
   int* status;
-  int* counter;       // per-mode completion counters of the fused solve
+};
+struct GramArgs {
+  int R, mode, nblk;
+  int64_t rows;
+  const double* A;
+  const double* dA;        // NULL -> S only
+  double* S_out;
+  double* U_out;
+  const double* blockpart; // solve partials (nblk x 5)
+  const int* status;
+  void* rec;
+  int write_fit, sweep_kind;
+  double normX2;
 };
 struct FusedSolveArgs {
   int R;
-  int mode;
   int64_t rows;
   const double* base;      // M_p^(n) or NULL
   const double* part;      // partial slots (FP64)
@@ -135,21 +146,14 @@ struct FusedSolveArgs {
   double* A;
   const double* Aref;      // NULL -> old A
   double* dA;              // NULL -> not stored
-  double* Spart;
-  double* Upart;           // NULL -> no U
-  double* blockpart;
+  double* blockpart;       // nblk x 5 partial sums
   const int* status;
-  int* counter;
-  double* S_out;           // S^(n)
-  double* U_out;           // U^(n) (if Upart)
-  void* rec;
   int write_fit;
-  int sweep_kind;
-  double normX2;
 };
 hipError_t launch_head(const HeadArgs& h, hipStream_t s);
 hipError_t launch_solve_fused(const FusedSolveArgs& a, hipStream_t s);
 int solve_fused_blocks(int64_t rows);
+hipError_t launch_gram_tiles(const GramArgs& a, hipStream_t s);
 
 struct SolveArgs {
   int R;

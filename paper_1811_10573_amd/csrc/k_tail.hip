@@ -8,12 +8,13 @@
 //     and factorises Gamma^(n) = L L^T (left-looking, one wave, LDS resident), retrying
 //     once with Gamma + delta I, delta = R 2^-52 max(diag Gamma), if a pivot is not
 //     positive;
-//  2. a fused solve: M~ = base + sum of the contraction's partial slots + A^(n) W^(n)
-//     (PP), the forward and backward triangular solves, G = (A_old - A_new) Gamma, dA,
-//     per-block partial Grams S = A^T A, U = A^T dA and norms.  Each wave carries ROWS
-//     rows at once so their dependency chains interleave.  The last block to finish
-//     (completion counter) reduces the partials into S^(n), U^(n), the sweep record and,
-//     after the last mode, the fit.
+//  2. a fused solve with small blocks spread over the chip: M~ = base + sum of the
+//     contraction's partial slots + A^(n) W^(n) (PP), the forward and backward
+//     triangular solves, G = (A_old - A_new) Gamma, dA and per-block norm partials;
+//  3. the Grams S^(n) = A^T A and U^(n) = A^T dA on the matrix cores (one block per
+//     16 x 16 tile), whose first block also writes the sweep record and the fit.
+//     On the auxiliary stream it precedes the next mode's head; after the last mode it
+//     runs on the main stream.
 #include "common.h"
 #include "../../include/ppals.h"
 
@@ -83,21 +84,27 @@ __device__ int chol_lds_wave(double* Lm, int R, int LS, int* fail) {
   return 1;
 }
 
-// Head of mode n (one workgroup): Gamma^(n), W^(n) (PP), Cholesky with one diagonal-shift
-// retry; zeroes the completion counter of the solve that follows.
-__global__ __launch_bounds__(256) void k_head(HeadArgs h) {
+// Head of mode n (one workgroup): Gamma^(n), W^(n) (PP) and the Cholesky factor with one
+// diagonal-shift retry.
+__global__ __launch_bounds__(1024) void k_head(HeadArgs h) {
   extern __shared__ double Lm[];  // R x (R+1)
-  __shared__ double red[4];
+  __shared__ double red[32];
   __shared__ int fail;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, nthr = blockDim.x;
   const int R = h.R, RR = R * R, N = h.N, LS = R + 1;
   const int n = h.n;
-  if (tid == 0) h.counter[n] = 0;
   double dmax = 0.0;
-  for (int e = tid; e < RR; e += blockDim.x) {
+  for (int e = tid; e < RR; e += nthr) {
+    double sv[PP_MAXN], uv[PP_MAXN];
+#pragma unroll
+    for (int i = 0; i < PP_MAXN; ++i) {
+      sv[i] = (i < N) ? h.S[(int64_t)i * RR + e] : 1.0;
+      uv[i] = (h.pp && h.second_order && i < N) ? h.U[(int64_t)i * RR + e] : 0.0;
+    }
     double v = 1.0;
-    for (int i = 0; i < N; ++i)
-      if (i != n) v *= h.S[(int64_t)i * RR + e];
+#pragma unroll
+    for (int i = 0; i < PP_MAXN; ++i)
+      if (i < N && i != n) v *= sv[i];
     h.gamma[e] = v;
     const int r = e / R, c = e - r * R;
     Lm[r * LS + c] = v;
@@ -108,9 +115,9 @@ __global__ __launch_bounds__(256) void k_head(HeadArgs h) {
         if (i == n) continue;
         for (int j = i + 1; j < N; ++j) {
           if (j == n) continue;
-          double t = h.U[(int64_t)i * RR + e] * h.U[(int64_t)j * RR + e];
+          double t = uv[i] * uv[j];
           for (int k = 0; k < N; ++k)
-            if (k != i && k != j && k != n) t *= h.S[(int64_t)k * RR + e];
+            if (k != i && k != j && k != n) t *= sv[k];
           w += t;
         }
       }
@@ -118,21 +125,21 @@ __global__ __launch_bounds__(256) void k_head(HeadArgs h) {
     }
   }
   for (int off = 32; off > 0; off >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, off));
-  if ((tid & 63) == 0) red[tid >> 6] = dmax;
+  if ((tid & 63) == 0) red[16 + (tid >> 6)] = dmax;
   __syncthreads();
   int st = 0;
   if (!chol_lds_wave(Lm, R, LS, &fail)) {
     double mx = 0.0;
-    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) mx = fmax(mx, red[i]);
+    for (int i = 0; i < nthr / 64; ++i) mx = fmax(mx, red[16 + i]);
     const double delta = (double)R * 0x1p-52 * mx;
-    for (int e = tid; e < RR; e += blockDim.x) {
+    for (int e = tid; e < RR; e += nthr) {
       const int r = e / R, c = e - r * R;
       Lm[r * LS + c] = h.gamma[e] + (r == c ? delta : 0.0);
     }
     __syncthreads();
     st = chol_lds_wave(Lm, R, LS, &fail) ? 1 : 2;
   }
-  for (int e = tid; e < RR; e += blockDim.x) {
+  for (int e = tid; e < RR; e += nthr) {
     const int r = e / R, c = e - r * R;
     h.L[e] = (c <= r) ? Lm[r * LS + c] : 0.0;
   }
@@ -140,57 +147,80 @@ __global__ __launch_bounds__(256) void k_head(HeadArgs h) {
 }
 
 // ---------------------------------------------------------------------------
-// Fused right-hand-side assembly + solve + Grams.  Block: 16 waves x ROWS rows; the last
-// block to finish reduces the per-block partials into S^(n), U^(n) and the record.
+// Fused right-hand-side assembly + solve + per-block partial Grams and norms.
+// Block: SOLVE_WAVES waves x SOLVE_ROWS rows.
 // ---------------------------------------------------------------------------
-constexpr int SOLVE_ROWS = 4;
-constexpr int SOLVE_WAVES = 16;
-constexpr int SOLVE_BR = SOLVE_ROWS * SOLVE_WAVES;
+constexpr int SOLVE_ROWS = 2;
+constexpr int SOLVE_WAVES = 4;
+constexpr int SOLVE_BR = SOLVE_ROWS * SOLVE_WAVES;  // rows per block
+constexpr int SOLVE_STAGE = 16;                     // staged L/Gamma/W entries per thread
+constexpr int NPART = 5;                            // per-block norm partials
 
-__global__ __launch_bounds__(1024) void k_solve_fused(FusedSolveArgs a) {
+// Fused right-hand-side assembly + solve.  Per row: M~ = base + sum of the contraction's
+// partial slots + A_old W (PP second-order term); forward and backward substitution with
+// L (lane k owns column k); g = (A_old - A_new) Gamma; dA = A_new - ref.  Per block it
+// writes NPART partial sums: ||g||^2, ||dA||^2, ||A_new||^2, <M~, A_new> and, for the
+// fit, sum of A_new Gamma A_new^T (the squared norm of the CP model, row by row).
+__global__ __launch_bounds__(SOLVE_WAVES * 64) void k_solve_fused(FusedSolveArgs a) {
   constexpr int ROWS = SOLVE_ROWS;
   constexpr int BR = SOLVE_BR;
   extern __shared__ double sm[];
   const int R = a.R, LS = R + 1, RR = R * R;
   double* Ls = sm;                          // R x (R+1)
-  double* Ws = Ls + (size_t)R * LS;         // R x R (second-order term)
+  double* Gs = Ls + (size_t)R * LS;         // R x R
+  double* Ws = Gs + (size_t)R * R;          // R x R (second-order term)
   double* invd = Ws + (size_t)R * R;        // R
-  double* An = invd + R;                    // BR x R new rows
-  double* Dn = An + (size_t)BR * R;         // BR x R dA rows
-  __shared__ double red[SOLVE_WAVES][4];
-  __shared__ int is_last;
+  __shared__ double red[SOLVE_WAVES][NPART];
 
-  const int tid = threadIdx.x;
-  for (int e = tid; e < RR; e += blockDim.x) {
-    const int i = e / R, k = e - i * R;
-    Ls[i * LS + k] = a.L[e];
-    if (a.W) Ws[e] = a.W[e];
-  }
-  __syncthreads();
-  for (int e = tid; e < R; e += blockDim.x) invd[e] = 1.0 / Ls[e * LS + e];
-  __syncthreads();
-
-  const int st = *a.status;
+  const int tid = threadIdx.x, nthr = blockDim.x;
   const int w = tid >> 6, l = tid & 63;
   const bool lv = l < R;
   const int64_t row0 = (int64_t)blockIdx.x * BR + (int64_t)w * ROWS;
-  double m[ROWS], ao[ROWS], x[ROWS];
+  double m[ROWS], ao[ROWS], rf[ROWS], x[ROWS];
   bool rv[ROWS];
 #pragma unroll
   for (int q = 0; q < ROWS; ++q) {
     rv[q] = (row0 + q) < a.rows;
     const int64_t off = (row0 + q) * R + l;
-    m[q] = (rv[q] && lv && a.base) ? a.base[off] : 0.0;
-    ao[q] = (rv[q] && lv) ? a.A[off] : 0.0;
+    const bool ok = rv[q] && lv;
+    m[q] = (ok && a.base) ? a.base[off] : 0.0;
+    ao[q] = ok ? a.A[off] : 0.0;
+    rf[q] = (ok && a.Aref) ? a.Aref[off] : 0.0;
   }
-  // partial slots of the contraction (independent loads, several in flight)
-#pragma unroll 4
+  // stage L, Gamma, W through registers (loads issued together)
+  for (int e0 = 0; e0 < RR; e0 += SOLVE_STAGE * nthr) {
+    double stL[SOLVE_STAGE], stG[SOLVE_STAGE], stW[SOLVE_STAGE];
+#pragma unroll
+    for (int t = 0; t < SOLVE_STAGE; ++t) {
+      const int e = e0 + tid + t * nthr;
+      const bool ok = e < RR;
+      stL[t] = ok ? a.L[e] : 0.0;
+      stG[t] = ok ? a.gamma[e] : 0.0;
+      stW[t] = (ok && a.W) ? a.W[e] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < SOLVE_STAGE; ++t) {
+      const int e = e0 + tid + t * nthr;
+      if (e < RR) {
+        const int i = e / R, k = e - i * R;
+        Ls[i * LS + k] = stL[t];
+        Gs[e] = stG[t];
+        Ws[e] = stW[t];
+      }
+    }
+  }
+#pragma unroll 8
   for (int sl = 0; sl < a.nslots; ++sl) {
     const double* ps = a.part + (int64_t)sl * a.slot_stride;
 #pragma unroll
     for (int q = 0; q < ROWS; ++q)
       if (rv[q] && lv) m[q] += ps[(row0 + q) * R + l];
   }
+  __syncthreads();
+  for (int e = tid; e < R; e += nthr) invd[e] = 1.0 / Ls[e * LS + e];
+  __syncthreads();
+
+  const int st = *a.status;
   if (a.W) {
     for (int j = 0; j < R; ++j) {
       const double wj = lv ? Ws[j * R + l] : 0.0;
@@ -226,128 +256,131 @@ __global__ __launch_bounds__(1024) void k_solve_fused(FusedSolveArgs a) {
 #pragma unroll
     for (int q = 0; q < ROWS; ++q) x[q] = ao[q];
   }
-  double g[ROWS];
+  double g[ROWS], hq[ROWS];
 #pragma unroll
-  for (int q = 0; q < ROWS; ++q) g[q] = 0.0;
-  for (int j = 0; j < R; ++j) {          // g = (a_old - a_new) Gamma
-    const double gjk = lv ? a.gamma[j * R + l] : 0.0;
+  for (int q = 0; q < ROWS; ++q) g[q] = hq[q] = 0.0;
+  for (int j = 0; j < R; ++j) {          // g = (a_old - a_new) Gamma; h = a_new Gamma (fit)
+    const double gjk = lv ? Gs[j * R + l] : 0.0;
 #pragma unroll
-    for (int q = 0; q < ROWS; ++q) g[q] = fma(bcast(ao[q] - x[q], j), gjk, g[q]);
+    for (int q = 0; q < ROWS; ++q) {
+      g[q] = fma(bcast(ao[q] - x[q], j), gjk, g[q]);
+      if (a.write_fit) hq[q] = fma(bcast(x[q], j), gjk, hq[q]);
+    }
   }
-  double sg = 0, sd = 0, sa = 0, smm = 0;
+  double v[NPART] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int q = 0; q < ROWS; ++q) {
     const int64_t off = (row0 + q) * R + l;
-    const int lr = w * ROWS + q;
-    double d = 0.0;
     if (rv[q] && lv) {
-      const double ref = a.Aref ? a.Aref[off] : ao[q];
-      d = x[q] - ref;
+      const double ref = a.Aref ? rf[q] : ao[q];
+      const double d = x[q] - ref;
       a.A[off] = x[q];
       if (a.dA) a.dA[off] = d;
-      sg = fma(g[q], g[q], sg);
-      sd = fma(d, d, sd);
-      sa = fma(x[q], x[q], sa);
-      smm = fma(mo[q], x[q], smm);
-    }
-    if (lv) {
-      An[lr * R + l] = rv[q] ? x[q] : 0.0;
-      Dn[lr * R + l] = rv[q] ? d : 0.0;
+      v[0] = fma(g[q], g[q], v[0]);
+      v[1] = fma(d, d, v[1]);
+      v[2] = fma(x[q], x[q], v[2]);
+      v[3] = fma(mo[q], x[q], v[3]);
+      v[4] = fma(x[q], hq[q], v[4]);
     }
   }
-  sg = wsum(sg);
-  sd = wsum(sd);
-  sa = wsum(sa);
-  smm = wsum(smm);
+#pragma unroll
+  for (int c = 0; c < NPART; ++c) v[c] = wsum(v[c]);
   if (l == 0) {
-    red[w][0] = sg;
-    red[w][1] = sd;
-    red[w][2] = sa;
-    red[w][3] = smm;
+#pragma unroll
+    for (int c = 0; c < NPART; ++c) red[w][c] = v[c];
   }
   __syncthreads();
-  const int64_t blk = blockIdx.x;
-  if (tid < 4) {
+  if (tid < NPART) {
     double s = 0.0;
     for (int q = 0; q < SOLVE_WAVES; ++q) s += red[q][tid];
-    a.blockpart[blk * 4 + tid] = s;
+    a.blockpart[(int64_t)blockIdx.x * NPART + tid] = s;
   }
-  const int nrows = (int)min((int64_t)BR, a.rows - blk * BR);
-  for (int e = tid; e < RR; e += blockDim.x) {
-    const int r = e / R, c = e - (e / R) * R;
-    double s = 0.0, u = 0.0;
-    for (int t = 0; t < nrows; ++t) {
-      const double ar = An[t * R + r];
-      s = fma(ar, An[t * R + c], s);
-      if (a.Upart) u = fma(ar, Dn[t * R + c], u);
+}
+
+// Grams of the updated factor on the matrix cores: S = A^T A and, in PP sweeps,
+// U = A^T dA.  One block per 16 x 16 output tile (grid.y selects S or U); the rows are
+// staged through LDS in chunks of GCH and split over the block's waves (f64 16x16x4;
+// lane l: A operand A[k][r0 + l%16], B operand B[k][c0 + l%16] with k = 4s + l/16;
+// accumulator register v holds tile row 4v + l/16, column l%16).  Block (0, 0) also
+// reduces the solve's per-block partials into the sweep record (and the fit).
+constexpr int GCH = 192;
+constexpr int GWAVES = 16;
+
+__global__ __launch_bounds__(GWAVES * 64) void k_gram_tiles(GramArgs a) {
+  __shared__ double sh[2 * GCH * 16];  // two row panels; reused for the wave reduction
+  double(*ta)[16] = (double(*)[16])sh;
+  double(*tb)[16] = (double(*)[16])(sh + GCH * 16);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int w = tid >> 6, l = tid & 63;
+  const int R = a.R;
+  const int NBR = (R + 15) / 16;
+  const int r0 = (blockIdx.x / NBR) * 16, c0 = (blockIdx.x % NBR) * 16;
+  const double* B = blockIdx.y ? a.dA : a.A;
+  double* out = blockIdx.y ? a.U_out : a.S_out;
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t y0 = 0; y0 < a.rows; y0 += GCH) {
+    constexpr int PER = GCH * 16 / (GWAVES * 64);
+    double va[PER], vb[PER];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int e = tid + t * nthr;
+      const int rr = e >> 4, cc = e & 15;
+      const int64_t y = y0 + rr;
+      va[t] = (y < a.rows && r0 + cc < R) ? a.A[y * R + r0 + cc] : 0.0;
+      vb[t] = (y < a.rows && c0 + cc < R) ? B[y * R + c0 + cc] : 0.0;
     }
-    a.Spart[blk * RR + e] = s;
-    if (a.Upart) a.Upart[blk * RR + e] = u;
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int e = tid + t * nthr;
+      ta[e >> 4][e & 15] = va[t];
+      tb[e >> 4][e & 15] = vb[t];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k0 = 4 * w; k0 < GCH; k0 += 4 * GWAVES) {
+      const int k = k0 + (l >> 4);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ta[k][l & 15], tb[k][l & 15], acc, 0, 0, 0);
+    }
   }
-  // completion count: the last block reduces every block's partials
-  __threadfence();
   __syncthreads();
-  if (tid == 0) is_last = (atomicAdd(a.counter, 1) == (int)gridDim.x - 1);
+  double* racc = sh;  // GWAVES x 4 x 64
+#pragma unroll
+  for (int v = 0; v < 4; ++v) racc[(w * 4 + v) * 64 + l] = acc[v];
   __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  const int nb = gridDim.x;
-  for (int e = tid; e < RR; e += blockDim.x) {
-    double s0 = 0.0, s1 = 0.0, u0 = 0.0, u1 = 0.0;
-    int b = 0;
-    for (; b + 1 < nb; b += 2) {
-      s0 += a.Spart[(int64_t)b * RR + e];
-      s1 += a.Spart[(int64_t)(b + 1) * RR + e];
-      if (a.Upart) {
-        u0 += a.Upart[(int64_t)b * RR + e];
-        u1 += a.Upart[(int64_t)(b + 1) * RR + e];
+  if (w == 0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      double s = 0.0;
+      for (int q = 0; q < GWAVES; ++q) s += racc[(q * 4 + v) * 64 + l];
+      const int r = r0 + 4 * v + (l >> 4), c = c0 + (l & 15);
+      if (r < R && c < R) out[r * R + c] = s;
+    }
+  }
+  if (blockIdx.x != 0 || blockIdx.y != 0) return;
+  // record for this mode from the solve's per-block partials
+  __shared__ double sums[NPART];
+  if (w == 0) {
+    double v[NPART] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int b = l; b < a.nblk; b += 64)
+#pragma unroll
+      for (int c = 0; c < NPART; ++c) v[c] += a.blockpart[(int64_t)b * NPART + c];
+#pragma unroll
+    for (int c = 0; c < NPART; ++c) v[c] = wsum(v[c]);
+    if (l == 0) {
+#pragma unroll
+      for (int c = 0; c < NPART; ++c) sums[c] = v[c];
+      ppals_sweep_record* rec = (ppals_sweep_record*)a.rec;
+      const double g2 = sums[0], d2 = sums[1], a2 = sums[2];
+      rec->grad_norm[a.mode] = sqrt(g2);
+      rec->rel_change[a.mode] = a2 > 0.0 ? sqrt(d2) / sqrt(a2) : (d2 > 0.0 ? INFINITY : 0.0);
+      rec->chol_status[a.mode] = *a.status;
+      if (a.write_fit) {
+        const double r2 = a.normX2 - 2.0 * sums[3] + sums[4];
+        rec->fit_est = 1.0 - sqrt(r2 > 0.0 ? r2 : 0.0) / sqrt(a.normX2);
+        rec->sweep_kind = a.sweep_kind;
       }
     }
-    if (b < nb) {
-      s0 += a.Spart[(int64_t)b * RR + e];
-      if (a.Upart) u0 += a.Upart[(int64_t)b * RR + e];
-    }
-    a.S_out[e] = s0 + s1;
-    if (a.Upart) a.U_out[e] = u0 + u1;
-  }
-  if (w == 0) {
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int b = l; b < nb; b += 64)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) v[c] += a.blockpart[(int64_t)b * 4 + c];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) v[c] = wsum(v[c]);
-    if (l == 0) {
-      red[0][0] = v[0];
-      red[0][1] = v[1];
-      red[0][2] = v[2];
-      red[0][3] = v[3];
-    }
-  }
-  __threadfence_block();
-  __syncthreads();
-  ppals_sweep_record* rec = (ppals_sweep_record*)a.rec;
-  if (a.write_fit) {
-    double s = 0.0;
-    for (int e = tid; e < RR; e += blockDim.x) s += a.gamma[e] * a.S_out[e];
-    s = wsum(s);
-    __shared__ double fr[SOLVE_WAVES];
-    if (l == 0) fr[w] = s;
-    __syncthreads();
-    if (tid == 0) {
-      double f = 0.0;
-      for (int q = 0; q < SOLVE_WAVES; ++q) f += fr[q];
-      const double r2 = a.normX2 - 2.0 * red[0][3] + f;
-      rec->fit_est = 1.0 - sqrt(r2 > 0.0 ? r2 : 0.0) / sqrt(a.normX2);
-      rec->sweep_kind = a.sweep_kind;
-    }
-  }
-  if (tid == 0) {
-    const double g2 = red[0][0], d2 = red[0][1], a2 = red[0][2];
-    rec->grad_norm[a.mode] = sqrt(g2);
-    rec->rel_change[a.mode] = a2 > 0.0 ? sqrt(d2) / sqrt(a2) : (d2 > 0.0 ? INFINITY : 0.0);
-    rec->chol_status[a.mode] = st;
-    *a.counter = 0;
   }
 }
 
@@ -361,19 +394,25 @@ static hipError_t allow_lds(K kernel, size_t bytes) {
 
 hipError_t launch_head(const HeadArgs& h, hipStream_t s) {
   const size_t lds = (size_t)h.R * (h.R + 1) * sizeof(double);
-  hipLaunchKernelGGL(k_head, dim3(1), dim3(256), lds, s, h);
+  hipLaunchKernelGGL(k_head, dim3(1), dim3(1024), lds, s, h);
   return hipGetLastError();
 }
 
 int solve_fused_blocks(int64_t rows) { return (int)((rows + SOLVE_BR - 1) / SOLVE_BR); }
 
+hipError_t launch_gram_tiles(const GramArgs& a, hipStream_t s) {
+  const int NBR = (a.R + 15) / 16;
+  hipLaunchKernelGGL(k_gram_tiles, dim3(NBR * NBR, a.dA ? 2 : 1), dim3(GWAVES * 64), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_solve_fused(const FusedSolveArgs& a, hipStream_t s) {
   const int R = a.R;
-  const size_t lds = ((size_t)R * (R + 1) + (size_t)R * R + R + 2 * (size_t)SOLVE_BR * R) *
-                     sizeof(double);
+  const size_t lds = ((size_t)R * (R + 1) + 2 * (size_t)R * R + R) * sizeof(double);
   hipError_t e = allow_lds(k_solve_fused, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_solve_fused, dim3(solve_fused_blocks(a.rows)), dim3(1024), lds, s, a);
+  hipLaunchKernelGGL(k_solve_fused, dim3(solve_fused_blocks(a.rows)), dim3(SOLVE_WAVES * 64), lds,
+                     s, a);
   return hipGetLastError();
 }
 

@@ -110,10 +110,10 @@ struct ppals_plan {
   size_t off_status = 0;               // ints
   size_t off_norm = 0;                 // 4096 doubles
   size_t off_ppart = 0, sz_ppart = 0;  // PP partial slots
-  size_t off_Spart = 0, off_Upart = 0, off_blockpart = 0;  // fused-solve partials
-  size_t off_counter = 0;              // per-mode completion counters
+  size_t off_blockpart = 0;  // fused-solve per-block partial sums
   bool fast = false;                   // rank <= 64: fused head/solve tail
   hipStream_t aux = nullptr;           // stream for the head kernel (default priority)
+  ppals_sweep_record* pinned_rec = nullptr;  // pinned host staging of the sweep record
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   size_t ws_bytes = 0;
   std::vector<size_t> mode_off;        // element offsets of mode n in sum_s x R arrays
@@ -438,10 +438,7 @@ void layout(ppals_plan* p) {
   p->off_norm = take(4096 * 8);
   {
     const int64_t nb = solve_fused_blocks(p->max_s);
-    p->off_Spart = take((size_t)nb * R * R * 8);
-    p->off_Upart = take((size_t)nb * R * R * 8);
-    p->off_blockpart = take((size_t)nb * 4 * 8);
-    p->off_counter = take(64 * sizeof(int));
+    p->off_blockpart = take((size_t)nb * 5 * 8);
   }
   for (auto& b : p->bufs) b.off = take(b.bytes);
   p->ws_bytes = off;
@@ -741,13 +738,37 @@ HeadArgs head_args(const Ctx& c, double* S, int n, int pp) {
   h.L = c.at<double>(p->off_L);
   h.W = c.at<double>(p->off_W);
   h.status = c.at<int>(p->off_status);
-  h.counter = c.at<int>(p->off_counter);
   return h;
 }
 
-// Fast path: the head of mode n runs on the auxiliary stream, forked from the main
-// stream after the previous solve and joined before the solve of mode n.
-ppals_status head_fork(const Ctx& c, const HeadArgs& h) {
+// Grams of the freshly solved factor n into S^(n) (and U^(n) in PP sweeps) plus the
+// sweep record of mode n (and the fit after the last mode).
+GramArgs gram_args(const Ctx& c, double* const* A, double* S, int n, int pp, double normX2,
+                   ppals_sweep_record* rec, int write_fit, int kind) {
+  ppals_plan* p = c.p;
+  GramArgs g;
+  memset(&g, 0, sizeof(g));
+  g.R = p->R;
+  g.mode = n;
+  g.rows = p->dims[n];
+  g.nblk = solve_fused_blocks(p->dims[n]);
+  g.A = A[n];
+  g.dA = pp ? c.dA(n) : nullptr;
+  g.S_out = S + (size_t)n * p->R * p->R;
+  g.U_out = c.U() + (size_t)n * p->R * p->R;
+  g.blockpart = c.at<double>(p->off_blockpart);
+  g.status = c.at<int>(p->off_status) + n;
+  g.rec = rec;
+  g.write_fit = write_fit;
+  g.sweep_kind = kind;
+  g.normX2 = normX2;
+  return g;
+}
+
+// Fast path: the Grams of the previous mode and the head of the next mode run on the
+// auxiliary stream, forked from the main stream after the previous solve and joined
+// before the next solve, so they overlap the next mode's contractions.
+ppals_status tail_fork(const Ctx& c, const GramArgs* g, const HeadArgs* h) {
   ppals_plan* p = c.p;
   if (!p->aux) {
     HIPCHK(hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking));
@@ -756,23 +777,22 @@ ppals_status head_fork(const Ctx& c, const HeadArgs& h) {
   }
   HIPCHK(hipEventRecord(p->ev_fork, c.s));
   HIPCHK(hipStreamWaitEvent(p->aux, p->ev_fork, 0));
-  HIPCHK(launch_head(h, p->aux));
+  if (g) HIPCHK(launch_gram_tiles(*g, p->aux));
+  if (h) HIPCHK(launch_head(*h, p->aux));
   HIPCHK(hipEventRecord(p->ev_join, p->aux));
   return PPALS_OK;
 }
-ppals_status head_join(const Ctx& c) {
+ppals_status tail_join(const Ctx& c) {
   HIPCHK(hipStreamWaitEvent(c.s, c.p->ev_join, 0));
   return PPALS_OK;
 }
 
-ppals_status solve_fused(const Ctx& c, double* const* A, double* S, double normX2,
-                         ppals_sweep_record* rec, int n, const double* base, const double* part,
-                         int nslots, bool pp, int kind) {
+ppals_status solve_fused(const Ctx& c, double* const* A, int n, const double* base,
+                         const double* part, int nslots, bool pp, int write_fit) {
   ppals_plan* p = c.p;
   FusedSolveArgs a;
   memset(&a, 0, sizeof(a));
   a.R = p->R;
-  a.mode = n;
   a.rows = p->dims[n];
   a.base = base;
   a.part = part;
@@ -784,19 +804,21 @@ ppals_status solve_fused(const Ctx& c, double* const* A, double* S, double normX
   a.A = A[n];
   a.Aref = pp ? c.Ap(n) : nullptr;
   a.dA = pp ? c.dA(n) : nullptr;
-  a.Spart = c.at<double>(p->off_Spart);
-  a.Upart = pp ? c.at<double>(p->off_Upart) : nullptr;
   a.blockpart = c.at<double>(p->off_blockpart);
   a.status = c.at<int>(p->off_status) + n;
-  a.counter = c.at<int>(p->off_counter) + n;
-  a.S_out = S + (size_t)n * p->R * p->R;
-  a.U_out = c.U() + (size_t)n * p->R * p->R;
-  a.rec = rec;
-  a.write_fit = n == p->N - 1;
-  a.sweep_kind = kind;
-  a.normX2 = normX2;
+  a.write_fit = write_fit;
   Prof pr(p, 4, c.s);
   HIPCHK(launch_solve_fused(a, c.s));
+  pr.end();
+  return PPALS_OK;
+}
+
+// End of a sweep: Grams and record of the last mode plus the fit (main stream).
+ppals_status finish_sweep_fast(const Ctx& c, double* const* A, double* S, double normX2,
+                               ppals_sweep_record* rec, int prev, int pp, int kind) {
+  GramArgs g = gram_args(c, A, S, prev, pp, normX2, rec, 1, kind);
+  Prof pr(c.p, 4, c.s);
+  HIPCHK(launch_gram_tiles(g, c.s));
   pr.end();
   return PPALS_OK;
 }
@@ -811,7 +833,13 @@ ppals_status do_als_sweep(ppals_plan* p, const void* X, const void* Xb, double* 
     for (const Op& o : p->dt_ops) {
       ppals_status st = PPALS_OK;
       if (o.kind != OP_SOLVE && !forked) {
-        st = head_fork(c, head_args(c, S, prev + 1, 0));
+        const HeadArgs h = head_args(c, S, prev + 1, 0);
+        if (prev >= 0) {
+          const GramArgs g = gram_args(c, A, S, prev, 0, normX2, rec, 0, PPALS_SWEEP_ALS);
+          st = tail_fork(c, &g, &h);
+        } else {
+          st = tail_fork(c, nullptr, &h);
+        }
         forked = true;
       }
       if (st != PPALS_OK) return st;
@@ -827,16 +855,16 @@ ppals_status do_als_sweep(ppals_plan* p, const void* X, const void* Xb, double* 
           st = run_ttv(c, t, A, nullptr);
         }
       } else {
-        st = head_join(c);
+        st = tail_join(c);
         if (st == PPALS_OK)
-          st = solve_fused(c, A, S, normX2, rec, o.idx, nullptr, c.at<double>(p->off_tpart),
-                           nslots, false, PPALS_SWEEP_ALS);
+          st = solve_fused(c, A, o.idx, nullptr, c.at<double>(p->off_tpart), nslots, false,
+                           o.idx == p->N - 1);
         prev = o.idx;
         forked = false;
       }
       if (st != PPALS_OK) return st;
     }
-    return PPALS_OK;
+    return finish_sweep_fast(c, A, S, normX2, rec, prev, 0, PPALS_SWEEP_ALS);
   }
   Ctx c{p, (char*)ws, s};
   int prev = -1;
@@ -955,21 +983,29 @@ ppals_status do_pp_sweep(ppals_plan* p, double* const* A, double* S, double norm
         by += e * esize(p->bulk) + (double)p->dims[i] * p->R * 8;
       }
       by += (double)p->pp_slots[n] * p->dims[n] * p->R * 8;
-      ppals_status st = head_fork(c, head_args(c, S, n, 1));
+      const HeadArgs h = head_args(c, S, n, 1);
+      ppals_status st;
+      if (prev >= 0) {
+        const GramArgs g = gram_args(c, A, S, prev, 1, normX2, rec, 0, kind);
+        st = tail_fork(c, &g, &h);
+      } else {
+        st = tail_fork(c, nullptr, &h);
+      }
       if (st != PPALS_OK) return st;
       {
         Prof pr(p, 1, s, fl, by);
         HIPCHK(launch_ttv(b, s));
         pr.end();
       }
-      st = head_join(c);
+      st = tail_join(c);
       if (st == PPALS_OK)
-        st = solve_fused(c, A, S, normX2, rec, n, c.Mp(n), part, p->pp_slots[n], true, kind);
+        st = solve_fused(c, A, n, c.Mp(n), part, p->pp_slots[n], true, n == p->N - 1);
       if (st != PPALS_OK) return st;
       prev = n;
     }
-    p->sweeps_since_build++;
-    return PPALS_OK;
+    ppals_status st = finish_sweep_fast(c, A, S, normX2, rec, prev, 1, kind);
+    if (st == PPALS_OK) p->sweeps_since_build++;
+    return st;
   }
   for (int n = 0; n < p->N; ++n) {
     ppals_status st;
@@ -1046,6 +1082,7 @@ void ppals_plan_destroy(ppals_plan* p) {
   if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
   if (p->ev_join) (void)hipEventDestroy(p->ev_join);
   if (p->aux) (void)hipStreamDestroy(p->aux);
+  if (p->pinned_rec) (void)hipHostFree(p->pinned_rec);
   delete p;
 }
 
@@ -1302,9 +1339,12 @@ ppals_status ppals_run(ppals_plan* p, const void* X, const void* Xb, double* con
     }
     if (st != PPALS_OK) return st;
     if (sweep_ms) HIPCHK(hipEventRecord(e1, s));
-    HIPCHK(hipMemcpyAsync(&host_records[it], rec_dev, sizeof(ppals_sweep_record),
-                          hipMemcpyDeviceToHost, s));
+    if (!p->pinned_rec)
+      HIPCHK(hipHostMalloc((void**)&p->pinned_rec, sizeof(ppals_sweep_record), hipHostMallocDefault));
+    HIPCHK(hipMemcpyAsync(p->pinned_rec, rec_dev, sizeof(ppals_sweep_record), hipMemcpyDeviceToHost,
+                          s));
     HIPCHK(hipStreamSynchronize(s));
+    host_records[it] = *p->pinned_rec;
     if (sweep_ms) HIPCHK(hipEventElapsedTime(&sweep_ms[it], e0, e1));
     if (p->prof) prof_resolve(p);
     host_records[it].sweep_kind = kind;
