@@ -99,6 +99,46 @@ def cpu_baseline(X, init, rank, eps, gpu_kinds, budget_s):
     }
 
 
+COPY_BYTES = 1 << 30
+
+
+def copy_calibration(torch, dev):
+    """A plain device-to-device copy of COPY_BYTES, five times: under a counter profiler
+    its FETCH_SIZE / WRITE_SIZE per dispatch give the scale from counter units to bytes."""
+    x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": COPY_BYTES, "dispatches": 5}), flush=True)
+
+
+def measured_traffic(kernel, tier, shape, rank):
+    """HBM bytes per launch from the committed counter summary of this kernel and
+    workload, or None when there is none or the kernel source changed since."""
+    import re
+    fn = os.path.join(ROOT, "profiles", f"{kernel}_{tier}_{'x'.join(map(str, shape))}_r{rank}_counters.md")
+    if not os.path.exists(fn):
+        return None
+    txt = open(fn).read()
+    m = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    h = re.search(r"source_sha256:\s*([0-9a-f]{64})", txt)
+    if not m or not h:
+        return None
+    if h.group(1) != kernel_source_hash():
+        return None
+    return float(m.group(1))
+
+
+def kernel_source_hash():
+    import hashlib
+    d = os.path.join(ROOT, "paper_1811_10573_amd", "csrc")
+    hsh = hashlib.sha256()
+    for f in ("common.h", "k_level1.hip"):
+        hsh.update(open(os.path.join(d, f), "rb").read())
+    return hsh.hexdigest()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +154,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dt", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (for scaling HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -128,6 +170,9 @@ def main():
     import tensorgen
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        copy_calibration(torch, dev)
+        return
     s, R = args.size, args.rank
     shape = (s, s, s)
     log(f"generating {shape} rank-{R} planted tensor (collinearity {args.collinearity}, seed {args.seed})")
@@ -216,14 +261,17 @@ def main():
         log(f"DT-ALS: {out_dt['sweeps_per_s']:.1f} sweeps/s, fit {fit_dt:.8f}; "
             f"PP fit {fit_pp:.8f}; equal-fit target {target:.8f}: PP {t_pp} ms vs DT {t_dt} ms")
 
-    # roofline of the dominant kernel class of the timed region
-    dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
+    # roofline of the dominant kernel class of the timed region (among the classes
+    # with algorithmic work)
+    dom = max(((k, v) for k, v in prof.items() if v["flops"] > 0 or v["bytes"] > 0),
+              key=lambda kv: kv[1]["total_ms"])
     name, st = dom
     if name == "level1_gemm":
         peak = PEAK[{"f64": "f64_TFs", "f32": "f32_TFs", "bf16": "bf16_TFs"}[args.tier]]
         achieved = st["flops"] / (st["total_ms"] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None, "kernel": name,
+                "frac": achieved / peak,
+                "traffic": measured_traffic(name, args.tier, shape, R), "kernel": name,
                 "launches": st["launches"], "avg_ms": st["avg_ms"],
                 "work_per_launch": st["flops"] / max(1, st["launches"])}
     else:

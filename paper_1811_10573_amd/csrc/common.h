@@ -58,6 +58,10 @@ struct TtvJob {
 };
 
 #define PP_MAX_JOBS 8
+// Threads per multi-TTV workgroup: 12 waves, so at most two workgroups (six waves per
+// SIMD) fit on a compute unit and the small per-mode kernels of the other stream find
+// free wave slots and registers while a contraction streams.
+constexpr int TTV_THREADS = 768;
 struct TtvBatch {
   TtvJob job[PP_MAX_JOBS];
   int njobs;

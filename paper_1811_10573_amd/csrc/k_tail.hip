@@ -5,9 +5,9 @@
 //     concurrently with the mode's contractions (TTV or first-level GEMM) on the main
 //     stream: it forms Gamma^(n) = Hadamard_{i != n} S^(i) and, in PP sweeps,
 //     W^(n) = sum over unordered pairs {i,j} (i,j != n) of U^(i)*U^(j)*Hadamard_{k != i,j,n} S^(k),
-//     and factorises Gamma^(n) = L L^T (left-looking, one wave, LDS resident), retrying
-//     once with Gamma + delta I, delta = R 2^-52 max(diag Gamma), if a pivot is not
-//     positive;
+//     and factorises Gamma^(n) = L L^T (left-looking, one wave, LDS resident, no
+//     workgroup barriers), retrying once with Gamma + delta I,
+//     delta = R 2^-52 max(diag Gamma), if a pivot is not positive;
 //  2. a fused solve with small blocks spread over the chip: M~ = base + sum of the
 //     contraction's partial slots + A^(n) W^(n) (PP), the forward and backward
 //     triangular solves, G = (A_old - A_new) Gamma, dA and per-block norm partials;
@@ -32,114 +32,146 @@ __device__ __forceinline__ double wsum(double v) {
   return v;
 }
 
-__device__ double bsum(double v, double* red) {
-  v = wsum(v);
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  __syncthreads();
-  if (l == 0) red[w] = v;
-  __syncthreads();
-  double s = 0.0;
-  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
-  return s;
-}
+// Cholesky factorisation of the R x R matrix held in LDS (row stride LS), run by one
+// wave with no workgroup barriers (the wave's LDS accesses complete in order); lane i
+// owns row i.  Columns are taken in blocks of CHB (left-looking between blocks):
+//  A. for the block's columns c = j0..j0+CHB-1, lanes i >= j0 form
+//     t_ic = a_ic - sum_{k<j0} l_ik l_ck from the finished columns in LDS (the l_ck
+//     are LDS broadcasts, the products independent, so this part is throughput-bound);
+//  B. inside the block, column by column in registers: s_i = t_ic - sum_{j0<=k<c} l_ik l_ck
+//     (l_ck read from lane c), l_cc = sqrt(s_c), l_ic = s_i * (1 / l_cc);
+//  then the block's columns are written back to LDS.  Returns false at the first pivot
+//  that is not positive (or not finite).
+constexpr int CHB = 8;
 
-// Left-looking Cholesky of the R x R matrix held in LDS (row stride LS) by wave 0 of
-// the block; every thread of the block must call it (one barrier per column).
-// Column j: lanes i >= j form s_i = a_ij - sum_{k<j} l_ik l_jk, then l_jj = sqrt(s_j)
-// and l_ij = s_i / l_jj.  Returns 1 on success.
-__device__ int chol_lds_wave(double* Lm, int R, int LS, int* fail) {
-  const int tid = threadIdx.x;
-  if (tid == 0) *fail = 0;
-  __syncthreads();
-  for (int j = 0; j < R; ++j) {
-    if (tid < 64) {
-      const int i = tid;
-      double s = 0.0;
-      if (i >= j && i < R) {
-        const double* li = Lm + i * LS;
-        const double* lj = Lm + j * LS;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        int k = 0;
-        for (; k + 3 < j; k += 4) {
-          s0 = fma(li[k], lj[k], s0);
-          s1 = fma(li[k + 1], lj[k + 1], s1);
-          s2 = fma(li[k + 2], lj[k + 2], s2);
-          s3 = fma(li[k + 3], lj[k + 3], s3);
+__device__ bool chol_wave(double* Lm, int R, int LS) {
+  const int l = threadIdx.x & 63;
+  const bool own = l < R;
+  for (int j0 = 0; j0 < R; j0 += CHB) {
+    __builtin_amdgcn_wave_barrier();
+    double t[CHB];
+#pragma unroll
+    for (int c = 0; c < CHB; ++c) t[c] = (own && l >= j0 && j0 + c < R) ? Lm[l * LS + j0 + c] : 0.0;
+    if (own && l >= j0) {
+      const double* li = Lm + l * LS;
+      double u[CHB];
+#pragma unroll
+      for (int c = 0; c < CHB; ++c) u[c] = 0.0;
+      for (int k = 0; k < j0; ++k) {
+        const double lik = li[k];
+#pragma unroll
+        for (int c = 0; c < CHB; ++c) {
+          const int rc = min(j0 + c, R - 1);  // rows past R are never used
+          u[c] = fma(lik, Lm[rc * LS + k], u[c]);
         }
-        for (; k < j; ++k) s0 = fma(li[k], lj[k], s0);
-        s = li[j] - ((s0 + s1) + (s2 + s3));
       }
-      const double sj = bcast(s, j);
-      if (!(sj > 0.0) || !isfinite(sj)) {
-        if (tid == 0) *fail = 1;
-      } else {
+#pragma unroll
+      for (int c = 0; c < CHB; ++c) t[c] -= u[c];
+    }
+    double lb[CHB];
+#pragma unroll
+    for (int c = 0; c < CHB; ++c) {
+      lb[c] = 0.0;
+      const int col = j0 + c;
+      if (col < R) {
+        double s = t[c];
+#pragma unroll
+        for (int q = 0; q < c; ++q) s = fma(-lb[q], bcast(lb[q], col), s);
+        const double sj = bcast(s, col);
+        if (!(sj > 0.0) || !isfinite(sj)) return false;
         const double d = sqrt(sj);
-        if (i == j) Lm[j * LS + j] = d;
-        else if (i > j && i < R) Lm[i * LS + j] = s / d;
+        const double inv = 1.0 / d;
+        lb[c] = (l == col) ? d : s * inv;
       }
     }
-    __syncthreads();
-    if (*fail) return 0;
+    if (own && l >= j0) {
+#pragma unroll
+      for (int c = 0; c < CHB; ++c)
+        if (j0 + c < R && j0 + c <= l) Lm[l * LS + j0 + c] = lb[c];
+    }
   }
-  return 1;
+  __builtin_amdgcn_wave_barrier();
+  return true;
 }
 
-// Head of mode n (one workgroup): Gamma^(n), W^(n) (PP) and the Cholesky factor with one
-// diagonal-shift retry.
-__global__ __launch_bounds__(1024) void k_head(HeadArgs h) {
+// Gamma^(n)[e] = prod_{i != n} S^(i)[e]
+__device__ __forceinline__ double gamma_entry(const double* S, int N, int n, int64_t RR, int e) {
+  double sv[PP_MAXN];
+#pragma unroll
+  for (int i = 0; i < PP_MAXN; ++i) sv[i] = (i < N && i != n) ? S[i * RR + e] : 1.0;
+  double v = 1.0;
+#pragma unroll
+  for (int i = 0; i < PP_MAXN; ++i) v *= sv[i];
+  return v;
+}
+
+constexpr int HEAD_THREADS = 256;
+
+// Head of mode n (one workgroup of four waves): Gamma^(n), W^(n) (PP) and, in wave 0,
+// the Cholesky factor with one diagonal-shift retry.  Small enough to be co-resident
+// with the contraction kernels that run meanwhile on the other stream.
+__global__ __launch_bounds__(HEAD_THREADS) void k_head(HeadArgs h) {
   extern __shared__ double Lm[];  // R x (R+1)
-  __shared__ double red[32];
-  __shared__ int fail;
+  __shared__ double red[HEAD_THREADS / 64];
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int R = h.R, RR = R * R, N = h.N, LS = R + 1;
   const int n = h.n;
   double dmax = 0.0;
-  for (int e = tid; e < RR; e += nthr) {
-    double sv[PP_MAXN], uv[PP_MAXN];
+  const bool wterm = h.pp && h.second_order;
+  constexpr int EB = 2;  // entries per thread whose loads are issued together
+  for (int e0 = tid; e0 < RR; e0 += EB * nthr) {
+    double sv[EB][PP_MAXN], uv[EB][PP_MAXN];
 #pragma unroll
-    for (int i = 0; i < PP_MAXN; ++i) {
-      sv[i] = (i < N) ? h.S[(int64_t)i * RR + e] : 1.0;
-      uv[i] = (h.pp && h.second_order && i < N) ? h.U[(int64_t)i * RR + e] : 0.0;
+    for (int b = 0; b < EB; ++b) {
+      const int e = e0 + b * nthr;
+#pragma unroll
+      for (int i = 0; i < PP_MAXN; ++i) {
+        sv[b][i] = (i < N && e < RR) ? h.S[(int64_t)i * RR + e] : 1.0;
+        uv[b][i] = (wterm && i < N && e < RR) ? h.U[(int64_t)i * RR + e] : 0.0;
+      }
     }
-    double v = 1.0;
 #pragma unroll
-    for (int i = 0; i < PP_MAXN; ++i)
-      if (i < N && i != n) v *= sv[i];
-    h.gamma[e] = v;
-    const int r = e / R, c = e - r * R;
-    Lm[r * LS + c] = v;
-    if (r == c) dmax = fmax(dmax, v);
-    if (h.pp && h.second_order) {
-      double w = 0.0;
-      for (int i = 0; i < N; ++i) {
-        if (i == n) continue;
-        for (int j = i + 1; j < N; ++j) {
-          if (j == n) continue;
-          double t = uv[i] * uv[j];
-          for (int k = 0; k < N; ++k)
-            if (k != i && k != j && k != n) t *= sv[k];
-          w += t;
+    for (int b = 0; b < EB; ++b) {
+      const int e = e0 + b * nthr;
+      if (e >= RR) break;
+      // Running sums over the modes k != n: P0 = prod s_k (= Gamma), P1 = sum_i u_i
+      // prod_{k != i} s_k, P2 = sum_{i<j} u_i u_j prod_{k != i,j} s_k (= W).
+      double P0 = 1.0, P1 = 0.0, P2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < PP_MAXN; ++k) {
+        if (k < N && k != n) {
+          P2 = fma(P2, sv[b][k], P1 * uv[b][k]);
+          P1 = fma(P1, sv[b][k], P0 * uv[b][k]);
+          P0 *= sv[b][k];
         }
       }
-      h.W[e] = w;
+      const double v = P0;
+      h.gamma[e] = v;
+      const int r = e / R, c = e - r * R;
+      Lm[r * LS + c] = v;
+      if (r == c) dmax = fmax(dmax, v);
+      if (wterm) {
+        const double w = P2;
+        h.W[e] = w;
+      }
     }
   }
   for (int off = 32; off > 0; off >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, off));
-  if ((tid & 63) == 0) red[16 + (tid >> 6)] = dmax;
+  if ((tid & 63) == 0) red[tid >> 6] = dmax;
   __syncthreads();
+  if (tid >= 64) return;  // the factorisation is wave 0's alone (no barriers follow)
   int st = 0;
-  if (!chol_lds_wave(Lm, R, LS, &fail)) {
+  if (!chol_wave(Lm, R, LS)) {
     double mx = 0.0;
-    for (int i = 0; i < nthr / 64; ++i) mx = fmax(mx, red[16 + i]);
+    for (int i = 0; i < nthr / 64; ++i) mx = fmax(mx, red[i]);
     const double delta = (double)R * 0x1p-52 * mx;
-    for (int e = tid; e < RR; e += nthr) {
+    for (int e = tid; e < RR; e += 64) {
       const int r = e / R, c = e - r * R;
-      Lm[r * LS + c] = h.gamma[e] + (r == c ? delta : 0.0);
+      Lm[r * LS + c] = gamma_entry(h.S, N, n, RR, e) + (r == c ? delta : 0.0);
     }
-    __syncthreads();
-    st = chol_lds_wave(Lm, R, LS, &fail) ? 1 : 2;
+    st = chol_wave(Lm, R, LS) ? 1 : 2;
   }
-  for (int e = tid; e < RR; e += nthr) {
+  for (int e = tid; e < RR; e += 64) {
     const int r = e / R, c = e - r * R;
     h.L[e] = (c <= r) ? Lm[r * LS + c] : 0.0;
   }
@@ -298,53 +330,40 @@ __global__ __launch_bounds__(SOLVE_WAVES * 64) void k_solve_fused(FusedSolveArgs
 }
 
 // Grams of the updated factor on the matrix cores: S = A^T A and, in PP sweeps,
-// U = A^T dA.  One block per 16 x 16 output tile (grid.y selects S or U); the rows are
-// staged through LDS in chunks of GCH and split over the block's waves (f64 16x16x4;
-// lane l: A operand A[k][r0 + l%16], B operand B[k][c0 + l%16] with k = 4s + l/16;
-// accumulator register v holds tile row 4v + l/16, column l%16).  Block (0, 0) also
-// reduces the solve's per-block partials into the sweep record (and the fit).
-constexpr int GCH = 192;
-constexpr int GWAVES = 16;
+// U = A^T dA.  One workgroup of GRAM_WAVES waves per 16 x 16 output tile (grid.y selects
+// S or U); each wave takes GRAM_UNROLL groups of 4 rows at a time, its MFMA operands
+// loaded straight from memory (f64 16x16x4: lane l supplies A[y0 + l/16][r0 + l%16] and
+// B[y0 + l/16][c0 + l%16]; accumulator register v holds tile row 4v + l/16, column
+// l%16).  Block (0, 0) also reduces the solve's per-block partials into the sweep
+// record (and the fit).
+constexpr int GRAM_WAVES = 4;
+constexpr int GRAM_UNROLL = 8;
 
-__global__ __launch_bounds__(GWAVES * 64) void k_gram_tiles(GramArgs a) {
-  __shared__ double sh[2 * GCH * 16];  // two row panels; reused for the wave reduction
-  double(*ta)[16] = (double(*)[16])sh;
-  double(*tb)[16] = (double(*)[16])(sh + GCH * 16);
-  const int tid = threadIdx.x, nthr = blockDim.x;
+__global__ __launch_bounds__(GRAM_WAVES * 64) void k_gram_tiles(GramArgs a) {
+  __shared__ double racc[GRAM_WAVES * 4 * 64];
+  const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63;
   const int R = a.R;
   const int NBR = (R + 15) / 16;
   const int r0 = (blockIdx.x / NBR) * 16, c0 = (blockIdx.x % NBR) * 16;
   const double* B = blockIdx.y ? a.dA : a.A;
   double* out = blockIdx.y ? a.U_out : a.S_out;
+  const int ky = l >> 4, cc = l & 15;
+  const bool oka = r0 + cc < R, okb = c0 + cc < R;
   d4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t y0 = 0; y0 < a.rows; y0 += GCH) {
-    constexpr int PER = GCH * 16 / (GWAVES * 64);
-    double va[PER], vb[PER];
+  for (int64_t y0 = (int64_t)w * 4 * GRAM_UNROLL; y0 < a.rows;
+       y0 += (int64_t)4 * GRAM_UNROLL * GRAM_WAVES) {
+    double xa[GRAM_UNROLL], xb[GRAM_UNROLL];
 #pragma unroll
-    for (int t = 0; t < PER; ++t) {
-      const int e = tid + t * nthr;
-      const int rr = e >> 4, cc = e & 15;
-      const int64_t y = y0 + rr;
-      va[t] = (y < a.rows && r0 + cc < R) ? a.A[y * R + r0 + cc] : 0.0;
-      vb[t] = (y < a.rows && c0 + cc < R) ? B[y * R + c0 + cc] : 0.0;
+    for (int u = 0; u < GRAM_UNROLL; ++u) {
+      const int64_t y = y0 + 4 * u + ky;
+      xa[u] = (y < a.rows && oka) ? a.A[y * R + r0 + cc] : 0.0;
+      xb[u] = (y < a.rows && okb) ? B[y * R + c0 + cc] : 0.0;
     }
-    __syncthreads();
 #pragma unroll
-    for (int t = 0; t < PER; ++t) {
-      const int e = tid + t * nthr;
-      ta[e >> 4][e & 15] = va[t];
-      tb[e >> 4][e & 15] = vb[t];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k0 = 4 * w; k0 < GCH; k0 += 4 * GWAVES) {
-      const int k = k0 + (l >> 4);
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ta[k][l & 15], tb[k][l & 15], acc, 0, 0, 0);
-    }
+    for (int u = 0; u < GRAM_UNROLL; ++u)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u], xb[u], acc, 0, 0, 0);
   }
-  __syncthreads();
-  double* racc = sh;  // GWAVES x 4 x 64
 #pragma unroll
   for (int v = 0; v < 4; ++v) racc[(w * 4 + v) * 64 + l] = acc[v];
   __syncthreads();
@@ -352,7 +371,7 @@ __global__ __launch_bounds__(GWAVES * 64) void k_gram_tiles(GramArgs a) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       double s = 0.0;
-      for (int q = 0; q < GWAVES; ++q) s += racc[(q * 4 + v) * 64 + l];
+      for (int q = 0; q < GRAM_WAVES; ++q) s += racc[(q * 4 + v) * 64 + l];
       const int r = r0 + 4 * v + (l >> 4), c = c0 + (l & 15);
       if (r < R && c < R) out[r * R + c] = s;
     }
@@ -394,7 +413,7 @@ static hipError_t allow_lds(K kernel, size_t bytes) {
 
 hipError_t launch_head(const HeadArgs& h, hipStream_t s) {
   const size_t lds = (size_t)h.R * (h.R + 1) * sizeof(double);
-  hipLaunchKernelGGL(k_head, dim3(1), dim3(1024), lds, s, h);
+  hipLaunchKernelGGL(k_head, dim3(1), dim3(HEAD_THREADS), lds, s, h);
   return hipGetLastError();
 }
 
@@ -402,7 +421,7 @@ int solve_fused_blocks(int64_t rows) { return (int)((rows + SOLVE_BR - 1) / SOLV
 
 hipError_t launch_gram_tiles(const GramArgs& a, hipStream_t s) {
   const int NBR = (a.R + 15) / 16;
-  hipLaunchKernelGGL(k_gram_tiles, dim3(NBR * NBR, a.dA ? 2 : 1), dim3(GWAVES * 64), 0, s, a);
+  hipLaunchKernelGGL(k_gram_tiles, dim3(NBR * NBR, a.dA ? 2 : 1), dim3(GRAM_WAVES * 64), 0, s, a);
   return hipGetLastError();
 }
 

@@ -8,8 +8,8 @@
 // T is an intermediate with the rank index fastest (FP64 or FP32), F an X x R
 // FP64 matrix (a factor, a Khatri-Rao block or dA), out FP64 partial slots.
 // These kernels are HBM-bound: each workgroup streams a contiguous slab of T with
-// 256 threads; when Q*R < 256 the threads are split into G groups that read G
-// consecutive x-rows at once and are reduced through LDS.  Accumulation is FP64.
+// TTV_THREADS threads; when Q*R < TTV_THREADS the threads are split into G groups that
+// read G consecutive x-rows at once and are reduced through LDS.  Accumulation is FP64.
 #include "common.h"
 
 namespace ppk {
@@ -35,8 +35,8 @@ __device__ __forceinline__ double ttv_body(const T* __restrict__ src, const doub
   return (a0 + a1) + (a2 + a3);
 }
 
-__global__ __launch_bounds__(256) void k_ttv(TtvBatch b) {
-  __shared__ double red[256];
+__global__ __launch_bounds__(TTV_THREADS) __attribute__((amdgpu_num_vgpr(64))) void k_ttv(TtvBatch b) {
+  __shared__ double red[TTV_THREADS];
   int64_t bid = blockIdx.x;
   int jid = 0;
   while (jid < b.njobs - 1 && bid >= b.job[jid].blocks) {
@@ -159,7 +159,7 @@ hipError_t launch_ttv(const TtvBatch& b, hipStream_t s) {
   int64_t total = 0;
   for (int i = 0; i < b.njobs; ++i) total += b.job[i].blocks;
   if (total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ttv, dim3((unsigned)total), dim3(256), 0, s, b);
+  hipLaunchKernelGGL(k_ttv, dim3((unsigned)total), dim3(TTV_THREADS), 0, s, b);
   return hipGetLastError();
 }
 

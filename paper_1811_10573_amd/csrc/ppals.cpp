@@ -148,17 +148,17 @@ void ttv_config(TtvJob& J, int64_t P, int64_t X, int64_t Q, int R) {
   J.X = X;
   J.Q = Q;
   const int64_t QR = Q * R;
-  if (QR >= 256) {
-    J.Jb = 256;
+  if (QR >= TTV_THREADS) {
+    J.Jb = TTV_THREADS;
     J.G = 1;
-    J.jblocks = (int)((QR + 255) / 256);
+    J.jblocks = (int)((QR + TTV_THREADS - 1) / TTV_THREADS);
   } else {
     J.Jb = (int)QR;
-    J.G = (int)(256 / QR);
+    J.G = (int)(TTV_THREADS / QR);
     J.jblocks = 1;
   }
   const int64_t base = P * J.jblocks;
-  const int64_t target = 2048;
+  const int64_t target = 512;
   int64_t xs = (target + base - 1) / base;
   const int64_t maxs = std::max<int64_t>(1, X / (8 * (int64_t)J.G));
   xs = std::max<int64_t>(1, std::min(xs, maxs));
