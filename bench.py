@@ -65,17 +65,17 @@ def cpu_baseline(X, init, rank, eps, gpu_kinds, budget_s):
     normX2 = float(np.sum(X * X))
     t_als, t_init, t_appr = [], [], []
     start = time.perf_counter()
-    for _ in range(3):
+    for _ in range(8):
         t0 = time.perf_counter()
         ocp.als_sweep(X, A, S, normX2)
         t_als.append(time.perf_counter() - t0)
-        if time.perf_counter() - start > budget_s / 3:
+        if time.perf_counter() - start > budget_s * 0.4:
             break
     t0 = time.perf_counter()
     st = opp.build_operators(X, A)
     opp.pp_sweep(st, A, S, normX2, True, "pp_init")
     t_init.append(time.perf_counter() - t0)
-    for _ in range(3):
+    for _ in range(40):
         t0 = time.perf_counter()
         opp.pp_sweep(st, A, S, normX2, True, "pp_approx")
         t_appr.append(time.perf_counter() - t0)
@@ -134,8 +134,7 @@ def kernel_source_hash():
     import hashlib
     d = os.path.join(ROOT, "paper_1811_10573_amd", "csrc")
     hsh = hashlib.sha256()
-    for f in ("common.h", "k_level1.hip"):
-        hsh.update(open(os.path.join(d, f), "rb").read())
+    hsh.update(open(os.path.join(d, "k_level1.hip"), "rb").read())
     return hsh.hexdigest()
 
 
