@@ -22,4 +22,4 @@ Contents (each function cites the passage of the paper it follows):
 * ``oracle.mlp``     -- float64 two-layer MLP forward/backward/Adam used to
                         check the learned PP controller.
 """
-from . import bf16, cp, linalg, pp, tree  # noqa: F401
+from . import bf16, cp, linalg, mlp, pp, tree  # noqa: F401
