@@ -89,7 +89,16 @@ typedef struct {
  *                  (ALS) or since the operator build (PP), Algorithm 3;
  *   chol_status[n] 0: clean Cholesky; 1: factorised Gamma + delta I with
  *                  delta = R 2^-52 max(diag Gamma); 2: failed after the shift
- *                  (A^(n) left unchanged). */
+ *                  (A^(n) left unchanged).
+ * The ctrl_* fields are written by ppals_run when a learned controller is
+ * attached (ppals_set_controller); otherwise ppals_run sets them to
+ * ctrl_pred = NaN, ctrl_true_err = -1, ctrl_leave = -1, ctrl_fallback = 0:
+ *   ctrl_pred      the network's prediction of log10 of the PP right-hand-side
+ *                  error after this PP sweep;
+ *   ctrl_true_err  the measured error max_n ||M~^(n) - M^(n)||_F / ||M^(n)||_F
+ *                  when this sweep was a periodic check, else -1;
+ *   ctrl_leave     1 if the prediction asked to leave the PP phase;
+ *   ctrl_fallback  1 once a check disabled the controller for the run. */
 typedef struct {
   double fit_est;
   double grad_norm[PPALS_MAX_ORDER];
@@ -97,6 +106,10 @@ typedef struct {
   int32_t chol_status[PPALS_MAX_ORDER];
   int32_t sweep_kind;
   int32_t pad;
+  double ctrl_pred;
+  double ctrl_true_err;
+  int32_t ctrl_leave;
+  int32_t ctrl_fallback;
 } ppals_sweep_record;
 
 typedef struct ppals_plan ppals_plan;
@@ -145,7 +158,8 @@ ppals_status pp_build_operators(ppals_plan* plan, const void* X, const void* X_b
 ppals_status pp_sweep(ppals_plan* plan, double* const* A, double* S, double normX2,
                       void* ws, ppals_sweep_record* rec, hipStream_t stream);
 
-/* Standalone normal-equation solve (Algorithm 1, update and gradient lines):
+/* Standalone normal-equation solve (Algorithm 1, the factor update and its
+ * gradient):
  * A_new Gamma = M for `rows` right-hand-side rows, Gamma = L L^T (Cholesky,
  * with the diagonal-shift retry), then grad_norm = ||(A_old - A_new) Gamma||_F
  * and A_inout := A_new.  Gamma: R x R doubles; M: rows x R in m_dtype (FP64
@@ -215,6 +229,72 @@ ppals_status ppals_run(ppals_plan* plan, const void* X, const void* X_bf16, doub
                        double eps, double delta, int32_t max_sweeps, const int32_t* replay,
                        ppals_sweep_record* host_records, float* sweep_ms, int32_t* n_done,
                        hipStream_t stream);
+
+/* ---- Learned PP controller ------------------------------------------------
+ * Algorithm 3 leaves the PP phase when some ||dA^(i)|| / ||A^(i)|| reaches eps;
+ * other switching schemes are named as future work (Section 6).  The library
+ * provides a small network that predicts log10 of the PP right-hand-side error
+ * e = max_n ||M~^(n) - M^(n)||_F / ||M^(n)||_F from the state of the iteration,
+ * its training kernels, and a driver mode that leaves PP when the prediction
+ * reaches log10(tau).
+ *
+ * Network: d = order + 2 inputs, `hidden` tanh units, one linear output, FP32:
+ *   h = tanh(W1 x + b1), y = W2 . h + b2.
+ * Parameters: a device array of P = hidden*d + 2*hidden + 1 floats laid out as
+ * [W1 (hidden x d, row-major), b1 (hidden), W2 (hidden), b2].
+ * Inputs x for a PP iterate: log10(rel_change_i + 1e-12) for each mode,
+ * log1p(sweep index), -log10(1 - fit_est + 1e-16) (sweep index = 0-based index
+ * of the sweep just finished).  Limits: 1 <= d <= 16, 1 <= hidden <= 1024. */
+
+/* Forward pass for B samples: X is B x d (row-major, device), y (B floats,
+ * device) receives the outputs; hcache (B x hidden floats, device, may be
+ * NULL) receives the hidden activations for ppals_mlp_backward. */
+ppals_status ppals_mlp_forward(const float* params, int32_t d, int32_t hidden, const float* X,
+                               int64_t B, float* y, float* hcache, hipStream_t stream);
+
+/* Gradient of L = (1/B) sum_b (y_b - t_b)^2 with respect to the parameters
+ * (same layout as params) from the forward pass's y and hcache; t: B targets.
+ * loss (one float, device, may be NULL) receives L.  Reductions run in a fixed
+ * order (deterministic). */
+ppals_status ppals_mlp_backward(const float* params, int32_t d, int32_t hidden, const float* X,
+                                const float* hcache, const float* y, const float* t, int64_t B,
+                                float* grad, float* loss, hipStream_t stream);
+
+/* One Adam step (Kingma & Ba, 2015) on P parameters, in place: with the step
+ * count `step` >= 1, m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps).
+ * m and v (P floats each) start at zero. */
+ppals_status ppals_mlp_adam(float* params, const float* grad, float* m, float* v, int64_t P,
+                            int32_t step, float lr, float beta1, float beta2, float eps,
+                            hipStream_t stream);
+
+/* Measured PP right-hand-side error at the current iterate (the controller's
+ * label): e = max_n ||M~^(n) - M^(n)||_F / ||M^(n)||_F, where M~^(n) is the
+ * general PP update (Section 3.2.1) from the operators of the last
+ * pp_build_operators and the current factors, and M^(n) the exact MTTKRP of
+ * the current factors (dimension tree, no solves).  err: one device double.
+ * Returns PPALS_E_STATE if no operators were built with this plan. */
+ppals_status ppals_pp_rhs_error(ppals_plan* plan, const void* X, const void* X_bf16,
+                                double* const* A, const double* S, void* ws, double* err,
+                                hipStream_t stream);
+
+typedef struct {
+  const float* params;      /* device parameters, d = order + 2 inputs        */
+  int32_t hidden;           /* hidden units (1..1024)                          */
+  int32_t check_period;     /* every check_period-th PP sweep of a run the true
+                               error is measured (0: never)                   */
+  double log10_tau;         /* leave PP when the prediction >= log10_tau       */
+  double rho_cap;           /* also leave PP when some rel_change >= rho_cap    */
+  double fallback_factor;   /* a measured error > fallback_factor * tau turns the
+                               controller off for the rest of the run (the fixed
+                               threshold rule of Algorithm 3 then decides)     */
+} ppals_controller;
+
+/* Attach (ctl != NULL, copied) or detach (NULL) a learned controller for
+ * ppals_run.  Entering the PP phase always follows the threshold rule; with a
+ * controller attached, staying in it follows the network (and rho_cap) until a
+ * periodic check falls back.  The parameters must stay valid while attached. */
+ppals_status ppals_set_controller(ppals_plan* plan, const ppals_controller* ctl);
 
 /* Optional timing of kernel classes with HIP events recorded on the launch
  * stream around each launch (level-1 GEMM, PP correction TTV, dimension-tree

@@ -165,6 +165,10 @@ def record_dict(r, order=None):
         "rel_change": list(r.rel_change)[:n],
         "chol_status": list(r.chol_status)[:n],
         "kind": KIND_NAMES.get(r.sweep_kind, str(r.sweep_kind)),
+        "ctrl_pred": r.ctrl_pred,
+        "ctrl_true_err": r.ctrl_true_err,
+        "ctrl_leave": r.ctrl_leave,
+        "ctrl_fallback": r.ctrl_fallback,
     }
 
 
@@ -300,3 +304,69 @@ def run(plan, X, X_bf16, A, S, normX2, ws, rec, eps, max_sweeps, delta=0.0, repl
                                ms, ctypes.byref(done), _stream(stream)))
     out = [record_dict(recs[i], plan.order) for i in range(done.value)]
     return out, ([float(ms[i]) for i in range(done.value)] if timing else None)
+
+
+# ---- learned PP controller --------------------------------------------------
+
+def mlp_n_params(d, hidden):
+    return hidden * d + 2 * hidden + 1
+
+
+def mlp_forward(params, d, hidden, X, y, hcache=None, stream=None):
+    B = X.shape[0]
+    _dev(params, "params", torch.float32, mlp_n_params(d, hidden))
+    _dev(X, "X", torch.float32, B * d)
+    _dev(y, "y", torch.float32, B)
+    if hcache is not None:
+        _dev(hcache, "hcache", torch.float32, B * hidden)
+    _lib.check(lib().ppals_mlp_forward(_p(params), int(d), int(hidden), _p(X), int(B), _p(y),
+                                       _p(hcache), _stream(stream)))
+
+
+def mlp_backward(params, d, hidden, X, hcache, y, t, grad, loss=None, stream=None):
+    B = X.shape[0]
+    _dev(params, "params", torch.float32, mlp_n_params(d, hidden))
+    _dev(X, "X", torch.float32, B * d)
+    _dev(hcache, "hcache", torch.float32, B * hidden)
+    _dev(y, "y", torch.float32, B)
+    _dev(t, "t", torch.float32, B)
+    _dev(grad, "grad", torch.float32, mlp_n_params(d, hidden))
+    if loss is not None:
+        _dev(loss, "loss", torch.float32, 1)
+    _lib.check(lib().ppals_mlp_backward(_p(params), int(d), int(hidden), _p(X), _p(hcache), _p(y),
+                                        _p(t), int(B), _p(grad), _p(loss), _stream(stream)))
+
+
+def mlp_adam(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    P = params.numel()
+    for name, t in (("params", params), ("grad", grad), ("m", m), ("v", v)):
+        _dev(t, name, torch.float32, P)
+    _lib.check(lib().ppals_mlp_adam(_p(params), _p(grad), _p(m), _p(v), int(P), int(step),
+                                    float(lr), float(beta1), float(beta2), float(eps),
+                                    _stream(stream)))
+
+
+def pp_rhs_error(plan, X, X_bf16, A, S, ws, err, stream=None):
+    """Device double err := max_n ||M~^(n) - M^(n)|| / ||M^(n)|| at the current factors."""
+    x, xb = plan._x(X, X_bf16)
+    _dev(S, "S", torch.float64, plan.order * plan.rank * plan.rank)
+    _dev(ws, "ws", min_bytes=plan.workspace_bytes)
+    _dev(err, "err", torch.float64)
+    _lib.check(lib().ppals_pp_rhs_error(plan.handle, x, xb, _factor_array(plan, A), _p(S), _p(ws),
+                                        _p(err), _stream(stream)))
+
+
+def set_controller(plan, params=None, hidden=64, log10_tau=-2.0, rho_cap=0.3, check_period=0,
+                   fallback_factor=10.0):
+    """Attach a learned controller to the plan's native driver (params=None detaches).
+    The parameter tensor must stay alive while attached."""
+    if params is None:
+        _lib.check(lib().ppals_set_controller(plan.handle, None))
+        plan._ctl_params = None
+        return
+    _dev(params, "params", torch.float32, mlp_n_params(plan.order + 2, hidden))
+    c = _lib.Controller(params=params.data_ptr(), hidden=int(hidden), check_period=int(check_period),
+                        log10_tau=float(log10_tau), rho_cap=float(rho_cap),
+                        fallback_factor=float(fallback_factor))
+    _lib.check(lib().ppals_set_controller(plan.handle, ctypes.byref(c)))
+    plan._ctl_params = params

@@ -40,10 +40,25 @@ class SweepRecord(ctypes.Structure):
         ("chol_status", ctypes.c_int32 * MAX_ORDER),
         ("sweep_kind", ctypes.c_int32),
         ("pad", ctypes.c_int32),
+        ("ctrl_pred", ctypes.c_double),
+        ("ctrl_true_err", ctypes.c_double),
+        ("ctrl_leave", ctypes.c_int32),
+        ("ctrl_fallback", ctypes.c_int32),
     ]
 
 
 RECORD_BYTES = ctypes.sizeof(SweepRecord)
+
+
+class Controller(ctypes.Structure):
+    _fields_ = [
+        ("params", ctypes.c_void_p),
+        ("hidden", ctypes.c_int32),
+        ("check_period", ctypes.c_int32),
+        ("log10_tau", ctypes.c_double),
+        ("rho_cap", ctypes.c_double),
+        ("fallback_factor", ctypes.c_double),
+    ]
 
 PROF_CLASSES = 8
 
@@ -88,6 +103,12 @@ SIGNATURES = {
     "ppals_run": (_i32, [_vp, _vp, _vp, _ptrs, _vp, _dbl, _vp, _vp, _dbl, _dbl, _i32,
                          ctypes.POINTER(_i32), ctypes.POINTER(SweepRecord),
                          ctypes.POINTER(ctypes.c_float), ctypes.POINTER(_i32), _vp]),
+    "ppals_mlp_forward": (_i32, [_vp, _i32, _i32, _vp, _i64, _vp, _vp, _vp]),
+    "ppals_mlp_backward": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp]),
+    "ppals_mlp_adam": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, ctypes.c_float, ctypes.c_float,
+                              ctypes.c_float, ctypes.c_float, _vp]),
+    "ppals_pp_rhs_error": (_i32, [_vp, _vp, _vp, _ptrs, _vp, _vp, _vp, _vp]),
+    "ppals_set_controller": (_i32, [_vp, ctypes.POINTER(Controller)]),
     "ppals_set_profiling": (_i32, [_vp, _i32]),
     "ppals_get_profile": (_i32, [_vp, ctypes.POINTER(KernelStat), _i32, ctypes.POINTER(_i32), _i32]),
 }

@@ -159,6 +159,22 @@ hipError_t launch_solve_fused(const FusedSolveArgs& a, hipStream_t s);
 int solve_fused_blocks(int64_t rows);
 hipError_t launch_gram_tiles(const GramArgs& a, hipStream_t s);
 
+// learned PP controller (k_mlp.hip)
+constexpr int MLP_MAX_IN = 16;
+constexpr int MLP_MAX_HIDDEN = 1024;
+hipError_t launch_mlp_forward(const float* p, int d, int H, const float* X, int64_t B, float* y,
+                              float* hcache, hipStream_t s);
+hipError_t launch_mlp_backward(const float* p, int d, int H, const float* X, const float* hcache,
+                               const float* y, const float* t, int64_t B, float* g, float* loss,
+                               hipStream_t s);
+hipError_t launch_mlp_adam(float* p, const float* g, float* m, float* v, int64_t P, float lr,
+                           float beta1, float beta2, float eps, float c1, float c2, hipStream_t s);
+hipError_t launch_mlp_decide(const float* p, int H, int N, void* rec, int sweep, double log10_tau,
+                             hipStream_t s);
+hipError_t launch_rhs_err(const double* Mt, const double* M, int64_t count, double* out,
+                          hipStream_t s);
+hipError_t launch_rhs_err_max(const double* sums, int N, double* err, hipStream_t s);
+
 struct SolveArgs {
   int R;
   int64_t rows;

@@ -111,6 +111,7 @@ struct ppals_plan {
   size_t off_norm = 0;                 // 4096 doubles
   size_t off_ppart = 0, sz_ppart = 0;  // PP partial slots
   size_t off_blockpart = 0;  // fused-solve per-block partial sums
+  size_t off_Mx = 0, off_Mt = 0, off_errsum = 0;  // right-hand-side error measurement
   bool fast = false;                   // rank <= 64: fused head/solve tail
   hipStream_t aux = nullptr;           // stream for the head kernel (default priority)
   ppals_sweep_record* pinned_rec = nullptr;  // pinned host staging of the sweep record
@@ -121,6 +122,10 @@ struct ppals_plan {
   // state
   bool ops_built = false;
   int sweeps_since_build = 0;
+
+  // learned controller for leaving the PP phase (ppals_set_controller)
+  bool ctl_set = false;
+  ppals_controller ctl{};
 
   // optional per-kernel-class timing with HIP events on the launch stream
   bool prof = false;
@@ -440,6 +445,9 @@ void layout(ppals_plan* p) {
     const int64_t nb = solve_fused_blocks(p->max_s);
     p->off_blockpart = take((size_t)nb * 5 * 8);
   }
+  p->off_Mx = take((size_t)p->sum_s * R * 8);
+  p->off_Mt = take((size_t)p->max_s * R * 8);
+  p->off_errsum = take((size_t)2 * PPALS_MAX_ORDER * 8);
   for (auto& b : p->bufs) b.off = take(b.bytes);
   p->ws_bytes = off;
 }
@@ -1033,6 +1041,43 @@ ppals_status do_pp_sweep(ppals_plan* p, double* const* A, double* S, double norm
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
+// Right-hand-side error of the PP update at the current factors (the learned
+// controller's label): the exact MTTKRP of every mode through the ALS dimension tree
+// without solves, the general PP update of every mode from the operators, and
+// err = max_n ||M~^(n) - M^(n)||_F / ||M^(n)||_F.
+ppals_status rhs_error(ppals_plan* p, const void* X, const void* Xb, double* const* A,
+                       const double* S, void* ws, double* err, hipStream_t s) {
+  Ctx c{p, (char*)ws, s};
+  double* Mx = c.at<double>(p->off_Mx);
+  for (const Op& o : p->dt_ops) {
+    ppals_status st = PPALS_OK;
+    if (o.kind == OP_L1) {
+      const L1Step& l = p->l1[o.idx];
+      st = run_l1(c, l, X, Xb, A, c.buf(l.out_buf));
+    } else if (o.kind == OP_TTV) {
+      const TtvStep& t = p->ttv[o.idx];
+      st = run_ttv(c, t, A, t.out_buf < 0 ? Mx + p->mode_off[t.out_mode] : nullptr);
+    }
+    if (st != PPALS_OK) return st;
+  }
+  for (int i = 0; i < p->N; ++i) {
+    const int64_t cnt = p->dims[i] * (int64_t)p->R;
+    HIPCHK(launch_sub(c.dA(i), A[i], c.Ap(i), cnt, s));
+    HIPCHK(launch_gram(A[i], c.dA(i), p->dims[i], p->R, c.at<double>(p->off_L),
+                       c.U() + (size_t)i * p->R * p->R, s));
+  }
+  double* Mt = c.at<double>(p->off_Mt);
+  double* sums = c.at<double>(p->off_errsum);
+  for (int n = 0; n < p->N; ++n) {
+    ppals_status st = mode_begin(c, (double*)S, 1.0, nullptr, n, -1, 1, 0, PPALS_SWEEP_PP_APPROX);
+    if (st == PPALS_OK) st = pp_correct(c, A, n, Mt);
+    if (st != PPALS_OK) return st;
+    HIPCHK(launch_rhs_err(Mt, Mx + p->mode_off[n], p->dims[n] * (int64_t)p->R, sums + 2 * n, s));
+  }
+  HIPCHK(launch_rhs_err_max(sums, p->N, err, s));
+  return PPALS_OK;
+}
+
 extern "C" {
 
 ppals_status ppals_plan_create(const ppals_desc* d, ppals_plan** out) {
@@ -1084,6 +1129,69 @@ void ppals_plan_destroy(ppals_plan* p) {
   if (p->aux) (void)hipStreamDestroy(p->aux);
   if (p->pinned_rec) (void)hipHostFree(p->pinned_rec);
   delete p;
+}
+
+ppals_status ppals_mlp_forward(const float* params, int32_t d, int32_t hidden, const float* X,
+                               int64_t B, float* y, float* hcache, hipStream_t s) {
+  if (!params || !X || !y) return fail(PPALS_E_ARG, "NULL argument");
+  if (d < 1 || d > MLP_MAX_IN) return fail(PPALS_E_UNSUPPORTED, "need 1 <= d <= 16");
+  if (hidden < 1 || hidden > MLP_MAX_HIDDEN) return fail(PPALS_E_UNSUPPORTED, "need 1 <= hidden <= 1024");
+  if (B < 0) return fail(PPALS_E_ARG, "B < 0");
+  HIPCHK(launch_mlp_forward(params, d, hidden, X, B, y, hcache, s));
+  return PPALS_OK;
+}
+
+ppals_status ppals_mlp_backward(const float* params, int32_t d, int32_t hidden, const float* X,
+                                const float* hcache, const float* y, const float* t, int64_t B,
+                                float* grad, float* loss, hipStream_t s) {
+  if (!params || !X || !hcache || !y || !t || !grad) return fail(PPALS_E_ARG, "NULL argument");
+  if (d < 1 || d > MLP_MAX_IN) return fail(PPALS_E_UNSUPPORTED, "need 1 <= d <= 16");
+  if (hidden < 1 || hidden > MLP_MAX_HIDDEN) return fail(PPALS_E_UNSUPPORTED, "need 1 <= hidden <= 1024");
+  if (B < 1) return fail(PPALS_E_ARG, "B < 1");
+  HIPCHK(launch_mlp_backward(params, d, hidden, X, hcache, y, t, B, grad, loss, s));
+  return PPALS_OK;
+}
+
+ppals_status ppals_mlp_adam(float* params, const float* grad, float* m, float* v, int64_t P,
+                            int32_t step, float lr, float beta1, float beta2, float eps,
+                            hipStream_t s) {
+  if (!params || !grad || !m || !v) return fail(PPALS_E_ARG, "NULL argument");
+  if (P < 0) return fail(PPALS_E_ARG, "P < 0");
+  if (step < 1) return fail(PPALS_E_ARG, "step must be >= 1");
+  if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f))
+    return fail(PPALS_E_ARG, "betas must lie in [0, 1)");
+  if (P == 0) return PPALS_OK;
+  const float c1 = (float)(1.0 - std::pow((double)beta1, (double)step));
+  const float c2 = (float)(1.0 - std::pow((double)beta2, (double)step));
+  HIPCHK(launch_mlp_adam(params, grad, m, v, P, lr, beta1, beta2, eps, c1, c2, s));
+  return PPALS_OK;
+}
+
+ppals_status ppals_pp_rhs_error(ppals_plan* p, const void* X, const void* Xb, double* const* A,
+                                const double* S, void* ws, double* err, hipStream_t s) {
+  ppals_status st = check_common(p, X, Xb, A, ws);
+  if (st != PPALS_OK) return st;
+  if (!S || !err) return fail(PPALS_E_ARG, "NULL argument");
+  if (!p->ops_built) return fail(PPALS_E_STATE, "operators not built");
+  return rhs_error(p, X, Xb, A, S, ws, err, s);
+}
+
+ppals_status ppals_set_controller(ppals_plan* p, const ppals_controller* ctl) {
+  if (!p) return fail(PPALS_E_ARG, "plan is NULL");
+  if (!ctl) {
+    p->ctl_set = false;
+    return PPALS_OK;
+  }
+  if (!ctl->params) return fail(PPALS_E_ARG, "controller params are NULL");
+  if (ctl->hidden < 1 || ctl->hidden > MLP_MAX_HIDDEN)
+    return fail(PPALS_E_UNSUPPORTED, "need 1 <= hidden <= 1024");
+  if (p->N + 2 > MLP_MAX_IN) return fail(PPALS_E_UNSUPPORTED, "order + 2 exceeds 16 inputs");
+  if (ctl->check_period < 0) return fail(PPALS_E_ARG, "check_period < 0");
+  if (!(ctl->rho_cap > 0.0)) return fail(PPALS_E_ARG, "rho_cap must be > 0");
+  if (!(ctl->fallback_factor > 0.0)) return fail(PPALS_E_ARG, "fallback_factor must be > 0");
+  p->ctl = *ctl;
+  p->ctl_set = true;
+  return PPALS_OK;
 }
 
 ppals_status ppals_set_profiling(ppals_plan* p, int32_t enable) {
@@ -1316,10 +1424,22 @@ ppals_status ppals_run(ppals_plan* p, const void* X, const void* Xb, double* con
     HIPCHK(hipEventCreate(&e1));
   }
   int prev_kind = -1;
+  // learned controller: decides whether to stay in the PP phase until a periodic
+  // check of the true right-hand-side error falls back to the threshold rule
+  bool ctl_on = p->ctl_set;
+  bool leave_pp = false;
+  int pp_count = 0;
+  bool fell_back = false;
+  const double tau = std::pow(10.0, p->ctl.log10_tau);
   for (int it = 0; it < max_sweeps; ++it) {
     int kind;
+    const bool in_pp = prev_kind == PPALS_SWEEP_PP_INIT || prev_kind == PPALS_SWEEP_PP_APPROX;
     if (replay) {
       kind = replay[it];
+    } else if (in_pp && ctl_on) {
+      bool stay = !leave_pp;
+      for (int n = 0; n < p->N; ++n) stay = stay && rel[n] < p->ctl.rho_cap;
+      kind = stay ? PPALS_SWEEP_PP_APPROX : PPALS_SWEEP_ALS;
     } else {
       bool small = eps > 0.0;
       for (int n = 0; n < p->N; ++n) small = small && rel[n] < eps;
@@ -1338,6 +1458,18 @@ ppals_status ppals_run(ppals_plan* p, const void* X, const void* Xb, double* con
       st = do_als_sweep(p, X, Xb, A, S, normX2, ws, rec_dev, s);
     }
     if (st != PPALS_OK) return st;
+    const bool pp_kind = kind != PPALS_SWEEP_ALS;
+    bool checked = false;
+    if (ctl_on && pp_kind) {
+      HIPCHK(launch_mlp_decide(p->ctl.params, p->ctl.hidden, p->N, rec_dev, it, p->ctl.log10_tau, s));
+      ++pp_count;
+      if (p->ctl.check_period > 0 && pp_count % p->ctl.check_period == 0) {
+        st = rhs_error(p, X, Xb, A, S, ws, &rec_dev->ctrl_true_err, s);
+        if (st != PPALS_OK) return st;
+        checked = true;
+      }
+    }
+    // the sweep's time includes the controller's inference and checks
     if (sweep_ms) HIPCHK(hipEventRecord(e1, s));
     if (!p->pinned_rec)
       HIPCHK(hipHostMalloc((void**)&p->pinned_rec, sizeof(ppals_sweep_record), hipHostMallocDefault));
@@ -1345,15 +1477,27 @@ ppals_status ppals_run(ppals_plan* p, const void* X, const void* Xb, double* con
                           s));
     HIPCHK(hipStreamSynchronize(s));
     host_records[it] = *p->pinned_rec;
+    ppals_sweep_record& hr = host_records[it];
     if (sweep_ms) HIPCHK(hipEventElapsedTime(&sweep_ms[it], e0, e1));
     if (p->prof) prof_resolve(p);
-    host_records[it].sweep_kind = kind;
-    for (int n = 0; n < p->N; ++n) rel[n] = host_records[it].rel_change[n];
+    hr.sweep_kind = kind;
+    if (!(ctl_on && pp_kind)) {
+      hr.ctrl_pred = std::nan("");
+      hr.ctrl_leave = -1;
+    }
+    if (!checked) hr.ctrl_true_err = -1.0;
+    if (checked && hr.ctrl_true_err > p->ctl.fallback_factor * tau) {
+      ctl_on = false;
+      fell_back = true;
+    }
+    hr.ctrl_fallback = fell_back ? 1 : 0;
+    leave_pp = ctl_on && pp_kind && hr.ctrl_leave == 1;
+    for (int n = 0; n < p->N; ++n) rel[n] = hr.rel_change[n];
     prev_kind = kind;
     *n_done = it + 1;
     if (delta > 0.0) {
       double g = 0;
-      for (int n = 0; n < p->N; ++n) g += host_records[it].grad_norm[n];
+      for (int n = 0; n < p->N; ++n) g += hr.grad_norm[n];
       if (g <= delta * normX) break;
     }
   }

@@ -33,6 +33,8 @@ __all__ = [
     "add_noise",
     "init_factors",
     "make_problem",
+    "DeviceProblem",
+    "make_problem_device",
 ]
 
 
@@ -134,3 +136,43 @@ def make_problem(shape, rank, seed, planted_rank=None, eta=1e-3, dist="normal",
     del T
     init = init_factors(shape, rank, g_init)
     return Problem(X=X, planted=planted, init=init, rank=rank, eta=eta, seed=seed)
+
+
+@dataclasses.dataclass
+class DeviceProblem:
+    X: object                # torch tensor on the device (float32 or float64), row-major
+    planted: list            # planted factors (numpy)
+    init: list               # initial factors for ALS (numpy)
+    rank: int
+    eta: float
+    seed: int
+    shape: tuple
+
+
+def make_problem_device(shape, rank, seed, eta=1e-3, dist="normal", collinearity=None,
+                        dtype="f32", device="cuda"):
+    """Same recipe as make_problem with the dense tensor assembled on the GPU (for
+    workloads too many or too large to generate on the host).  Planted factors and
+    the initial guess come from the same numpy streams as make_problem; the noise
+    E is drawn by torch's device generator seeded from the noise stream, so the
+    tensor is reproducible for a given seed but differs from make_problem's."""
+    import torch
+    g_fac, g_noise, g_init = streams(seed)
+    planted = planted_factors(shape, rank, g_fac, dist=dist, collinearity=collinearity)
+    init = init_factors(shape, rank, g_init)
+    dev = torch.device(device)
+    F = [torch.from_numpy(a).to(dev) for a in planted]
+    rest = F[1]
+    for m in F[2:]:
+        rest = (rest[:, None, :] * m[None, :, :]).reshape(-1, m.shape[1])
+    T = torch.matmul(F[0], rest.t().contiguous()).reshape(tuple(shape))
+    del rest
+    if eta > 0.0:
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(int(g_noise.integers(0, 2**62)))
+        E = torch.randn(tuple(shape), generator=gen, dtype=torch.float64, device=dev)
+        T.add_(E, alpha=float(eta * torch.linalg.vector_norm(T) / torch.linalg.vector_norm(E)))
+        del E
+    X = T.to(torch.float32) if dtype == "f32" else T
+    return DeviceProblem(X=X.contiguous(), planted=planted, init=init, rank=rank, eta=eta,
+                         seed=seed, shape=tuple(shape))

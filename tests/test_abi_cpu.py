@@ -175,3 +175,40 @@ def test_pp_build_schedule_matches_oracle_tree(lib, N):
         else:
             assert o["op"] == "ttv" and o["src"] == [m - 1 for m in parent]
             assert o["src"][o["contract_pos"][0]] == w - 1
+
+
+def test_controller_entry_points_validate_arguments(lib):
+    from paper_1811_10573_amd import _lib
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    E_ARG, E_UNS, E_STATE = _lib.PPALS_E_ARG, _lib.PPALS_E_UNSUPPORTED, _lib.PPALS_E_STATE
+    assert lib.ppals_mlp_forward(None, 5, 64, fake, 4, fake, None, None) == E_ARG
+    assert lib.ppals_mlp_forward(fake, 0, 64, fake, 4, fake, None, None) == E_UNS
+    assert lib.ppals_mlp_forward(fake, 17, 64, fake, 4, fake, None, None) == E_UNS
+    assert lib.ppals_mlp_forward(fake, 5, 1025, fake, 4, fake, None, None) == E_UNS
+    assert lib.ppals_mlp_forward(fake, 5, 64, fake, -1, fake, None, None) == E_ARG
+    assert lib.ppals_mlp_backward(fake, 5, 64, fake, None, fake, fake, 4, fake, None, None) == E_ARG
+    assert lib.ppals_mlp_backward(fake, 5, 64, fake, fake, fake, fake, 0, fake, None, None) == E_ARG
+    assert lib.ppals_mlp_adam(fake, fake, fake, fake, 10, 0, 1e-3, 0.9, 0.999, 1e-8, None) == E_ARG
+    assert lib.ppals_mlp_adam(fake, fake, fake, fake, 10, 1, 1e-3, 1.0, 0.999, 1e-8, None) == E_ARG
+    assert lib.ppals_mlp_adam(fake, None, fake, fake, 10, 1, 1e-3, 0.9, 0.999, 1e-8, None) == E_ARG
+    st, h = _create(lib, [6, 5, 7], 3)
+    assert st == 0
+    try:
+        ptrs = (ctypes.c_void_p * 3)(0x1000, 0x2000, 0x3000)
+        # no operators built yet
+        assert lib.ppals_pp_rhs_error(h, fake, None, ptrs, fake, fake, fake, None) == E_STATE
+        assert lib.ppals_pp_rhs_error(h, fake, None, ptrs, None, fake, fake, None) == E_ARG
+        c = _lib.Controller(params=0x1000, hidden=64, check_period=5, log10_tau=-2.0, rho_cap=0.3,
+                            fallback_factor=10.0)
+        assert lib.ppals_set_controller(h, ctypes.byref(c)) == 0
+        assert lib.ppals_set_controller(h, None) == 0
+        bad = [dict(params=None), dict(hidden=0), dict(hidden=2048), dict(check_period=-1),
+               dict(rho_cap=0.0), dict(fallback_factor=0.0)]
+        for b in bad:
+            kw = dict(params=0x1000, hidden=64, check_period=5, log10_tau=-2.0, rho_cap=0.3,
+                      fallback_factor=10.0)
+            kw.update(b)
+            c = _lib.Controller(**kw)
+            assert lib.ppals_set_controller(h, ctypes.byref(c)) != 0, b
+    finally:
+        lib.ppals_plan_destroy(h)
