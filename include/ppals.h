@@ -296,6 +296,77 @@ typedef struct {
  * periodic check falls back.  The parameters must stay valid while attached. */
 ppals_status ppals_set_controller(ppals_plan* plan, const ppals_controller* ctl);
 
+/* ---- Batched execution ------------------------------------------------------
+ * Many independent order-3 decompositions of uneven size and rank advanced
+ * together: every problem runs PP-CP-ALS (Algorithm 3 with the threshold rule,
+ * dimension-tree ALS sweeps of Section 2.5, PP sweeps of Section 3.2.1) with its
+ * own state machine on the device, so one batched sweep is a fixed sequence of
+ * grouped kernels that a HIP graph can capture once and replay.  Tensors are
+ * FP32, factors FP64; Grams, Cholesky solves, norms and fits FP64.  A problem
+ * stops when |fit - previous fit| < tol or after max_sweeps sweeps.
+ * Limits: 1 <= dims <= 256, 1 <= rank <= 64. */
+typedef struct ppals_batch ppals_batch;
+typedef struct {
+  int32_t dims[3];
+  int32_t rank;
+} ppals_batch_problem;
+
+typedef struct {
+  int32_t sweeps;            /* sweeps run                                        */
+  int32_t converged_sweep;   /* sweep count at convergence, -1 if not converged    */
+  int32_t n_als, n_pp_init, n_pp_approx;
+  int32_t done;
+  int32_t chol_status[3];    /* of the last sweep, as in ppals_sweep_record         */
+  int32_t pad;
+  double fit;                /* fit estimate after the last sweep (identity form)   */
+  double normX2;
+  double rel_change[3];
+  double time_to_converge_ms;/* device clock, first batched sweep to convergence
+                                (-1 if not converged)                              */
+} ppals_batch_result;
+
+/* Host only: copies the problem list and lays out the workspace.  Every problem
+ * gets its own regions for the three pairwise operators, M_p, A_p, dA, Grams,
+ * right-hand side and sweep-kind log. */
+ppals_status ppals_batch_create(const ppals_batch_problem* problems, int32_t count,
+                                int32_t max_sweeps, ppals_batch** out);
+void ppals_batch_destroy(ppals_batch* batch);
+size_t ppals_batch_workspace_bytes(const ppals_batch* batch);
+
+/* Binds the caller's tensors X[p] (device, FP32, row-major) and factors
+ * A[3p + n] (device, FP64, dims[n] x rank, updated in place) and the workspace,
+ * sets eps (PP threshold), tol and the second-order switch, and initialises every
+ * problem (||X||^2, Grams, state).  Synchronises the stream. */
+ppals_status ppals_batch_bind(ppals_batch* batch, const float* const* X, double* const* A,
+                              void* ws, double eps, double tol, int32_t second_order,
+                              hipStream_t stream);
+
+/* Measures the first-level contraction kernel's tile variants (64 or 128 output
+ * rows) on the bound problems of every (rank, size) bucket and keeps the faster
+ * one per bucket (ppals_batch_describe reports the table).  Call after bind,
+ * before the run; it overwrites operator scratch only. */
+ppals_status ppals_batch_autotune(ppals_batch* batch, void* ws, int32_t reps, hipStream_t stream);
+
+/* Enqueues one batched sweep (no host synchronisation; graph-capturable). */
+ppals_status ppals_batch_sweep(ppals_batch* batch, void* ws, hipStream_t stream);
+
+/* Enqueues `sweeps` batched sweeps; with use_graph the sweep is captured once in
+ * a HIP graph (kept until the binding or tuning changes) and replayed. */
+ppals_status ppals_batch_run(ppals_batch* batch, void* ws, int32_t sweeps, int32_t use_graph,
+                             hipStream_t stream);
+
+/* Per-problem results (host array of count entries); synchronises the stream. */
+ppals_status ppals_batch_results(ppals_batch* batch, const void* ws, ppals_batch_result* out,
+                                 hipStream_t stream);
+
+/* Sweep kinds (PPALS_SWEEP_* + 1; 0 = none) of every problem, count x max_sweeps
+ * bytes into a host buffer; synchronises the stream. */
+ppals_status ppals_batch_kind_log(ppals_batch* batch, const void* ws, uint8_t* out,
+                                  hipStream_t stream);
+
+/* JSON text: sizes, workspace bytes and the autotuner's per-bucket table. */
+ppals_status ppals_batch_describe(const ppals_batch* batch, char* buf, size_t len);
+
 /* Optional timing of kernel classes with HIP events recorded on the launch
  * stream around each launch (level-1 GEMM, PP correction TTV, dimension-tree
  * TTV, PP combine, per-mode FP64 tail, operand preparation, PP-tree TTV,

@@ -370,3 +370,86 @@ def set_controller(plan, params=None, hidden=64, log10_tau=-2.0, rho_cap=0.3, ch
                         fallback_factor=float(fallback_factor))
     _lib.check(lib().ppals_set_controller(plan.handle, ctypes.byref(c)))
     plan._ctl_params = params
+
+
+# ---- batched execution ------------------------------------------------------
+
+class Batch:
+    """Many independent order-3 problems (FP32 tensors, FP64 factors) advanced by the
+    library's grouped kernels with per-problem device state machines."""
+
+    def __init__(self, problems, max_sweeps):
+        arr = (_lib.BatchProblem * len(problems))()
+        for i, (dims, rank) in enumerate(problems):
+            if len(dims) != 3:
+                raise ValueError("batched problems are order 3")
+            arr[i].dims[:] = [int(d) for d in dims]
+            arr[i].rank = int(rank)
+        h = ctypes.c_void_p()
+        _lib.check(lib().ppals_batch_create(arr, len(problems), int(max_sweeps), ctypes.byref(h)))
+        self._h = h
+        self.problems = [(tuple(int(d) for d in dims), int(rank)) for dims, rank in problems]
+        self.count = len(problems)
+        self.max_sweeps = int(max_sweeps)
+        self._bound = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().ppals_batch_destroy(h)
+            self._h = None
+
+    @property
+    def workspace_bytes(self):
+        return int(lib().ppals_batch_workspace_bytes(self._h))
+
+    def workspace(self, device="cuda"):
+        return torch.empty(max(1, self.workspace_bytes), dtype=torch.uint8, device=device)
+
+    def bind(self, X, A, ws, eps, tol, second_order=True, stream=None):
+        if len(X) != self.count or len(A) != self.count:
+            raise ValueError("need one tensor and three factors per problem")
+        for p, ((dims, R), x, fs) in enumerate(zip(self.problems, X, A)):
+            _dev(x, f"X[{p}]", torch.float32, dims[0] * dims[1] * dims[2])
+            for n in range(3):
+                _dev(fs[n], f"A[{p}][{n}]", torch.float64, dims[n] * R)
+        _dev(ws, "ws", min_bytes=self.workspace_bytes)
+        xs = (ctypes.c_void_p * self.count)(*[x.data_ptr() for x in X])
+        As = (ctypes.c_void_p * (3 * self.count))(*[f.data_ptr() for fs in A for f in fs])
+        _lib.check(lib().ppals_batch_bind(self._h, xs, As, _p(ws), float(eps), float(tol),
+                                          1 if second_order else 0, _stream(stream)))
+        self._bound = (X, A, ws)
+
+    def autotune(self, ws, reps=3, stream=None):
+        _lib.check(lib().ppals_batch_autotune(self._h, _p(ws), int(reps), _stream(stream)))
+
+    def sweep(self, ws, stream=None):
+        _lib.check(lib().ppals_batch_sweep(self._h, _p(ws), _stream(stream)))
+
+    def run(self, ws, sweeps, use_graph=True, stream=None):
+        _lib.check(lib().ppals_batch_run(self._h, _p(ws), int(sweeps), 1 if use_graph else 0,
+                                         _stream(stream)))
+
+    def results(self, ws, stream=None):
+        out = (_lib.BatchResult * self.count)()
+        _lib.check(lib().ppals_batch_results(self._h, _p(ws), out, _stream(stream)))
+        return [{
+            "sweeps": r.sweeps, "converged_sweep": r.converged_sweep, "n_als": r.n_als,
+            "n_pp_init": r.n_pp_init, "n_pp_approx": r.n_pp_approx, "done": r.done,
+            "chol_status": list(r.chol_status), "fit": r.fit, "normX2": r.normX2,
+            "rel_change": list(r.rel_change), "time_to_converge_ms": r.time_to_converge_ms,
+        } for r in out]
+
+    def kind_log(self, ws, stream=None):
+        import numpy as np
+        buf = (ctypes.c_uint8 * (self.count * self.max_sweeps))()
+        _lib.check(lib().ppals_batch_kind_log(self._h, _p(ws), buf, _stream(stream)))
+        return np.frombuffer(bytes(buf), dtype=np.uint8).reshape(self.count, self.max_sweeps)
+
+    def describe(self):
+        buf = ctypes.create_string_buffer(1 << 16)
+        _lib.check(lib().ppals_batch_describe(self._h, buf, len(buf)))
+        return json.loads(buf.value.decode())
+
+
+BATCH_KIND_NAMES = {1: "als", 2: "pp_init", 3: "pp_approx"}

@@ -50,6 +50,27 @@ class SweepRecord(ctypes.Structure):
 RECORD_BYTES = ctypes.sizeof(SweepRecord)
 
 
+class BatchProblem(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32 * 3), ("rank", ctypes.c_int32)]
+
+
+class BatchResult(ctypes.Structure):
+    _fields_ = [
+        ("sweeps", ctypes.c_int32),
+        ("converged_sweep", ctypes.c_int32),
+        ("n_als", ctypes.c_int32),
+        ("n_pp_init", ctypes.c_int32),
+        ("n_pp_approx", ctypes.c_int32),
+        ("done", ctypes.c_int32),
+        ("chol_status", ctypes.c_int32 * 3),
+        ("pad", ctypes.c_int32),
+        ("fit", ctypes.c_double),
+        ("normX2", ctypes.c_double),
+        ("rel_change", ctypes.c_double * 3),
+        ("time_to_converge_ms", ctypes.c_double),
+    ]
+
+
 class Controller(ctypes.Structure):
     _fields_ = [
         ("params", ctypes.c_void_p),
@@ -109,6 +130,16 @@ SIGNATURES = {
                               ctypes.c_float, ctypes.c_float, _vp]),
     "ppals_pp_rhs_error": (_i32, [_vp, _vp, _vp, _ptrs, _vp, _vp, _vp, _vp]),
     "ppals_set_controller": (_i32, [_vp, ctypes.POINTER(Controller)]),
+    "ppals_batch_create": (_i32, [ctypes.POINTER(BatchProblem), _i32, _i32, ctypes.POINTER(_vp)]),
+    "ppals_batch_destroy": (None, [_vp]),
+    "ppals_batch_workspace_bytes": (_sz, [_vp]),
+    "ppals_batch_bind": (_i32, [_vp, _ptrs, _ptrs, _vp, _dbl, _dbl, _i32, _vp]),
+    "ppals_batch_autotune": (_i32, [_vp, _vp, _i32, _vp]),
+    "ppals_batch_sweep": (_i32, [_vp, _vp, _vp]),
+    "ppals_batch_run": (_i32, [_vp, _vp, _i32, _i32, _vp]),
+    "ppals_batch_results": (_i32, [_vp, _vp, ctypes.POINTER(BatchResult), _vp]),
+    "ppals_batch_kind_log": (_i32, [_vp, _vp, ctypes.POINTER(ctypes.c_uint8), _vp]),
+    "ppals_batch_describe": (_i32, [_vp, ctypes.c_char_p, _sz]),
     "ppals_set_profiling": (_i32, [_vp, _i32]),
     "ppals_get_profile": (_i32, [_vp, ctypes.POINTER(KernelStat), _i32, ctypes.POINTER(_i32), _i32]),
 }

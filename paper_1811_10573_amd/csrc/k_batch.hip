@@ -1,0 +1,557 @@
+// Batched PP-CP-ALS kernels for many independent order-3 problems of uneven size
+// and rank (s_n <= 256, R <= 64), FP32 tensors, FP64 factors and small dense work.
+//
+// One batched sweep is a fixed sequence of grouped launches.  Each problem carries a
+// device-side state machine (BState): at the start of a sweep it picks ALS,
+// PP initialisation or PP-approximated for itself with the threshold rule of
+// Algorithm 3, or nothing once it has converged, and every grouped kernel skips the
+// problems whose current kind it does not serve.  No launch depends on a host
+// decision, so a sweep can be captured once in a HIP graph and replayed.
+//
+// Per sweep, for every problem (N = 3, Section 2.5 dimension tree, Section 3.2.1 PP):
+//   ALS:        I01 = X x_2 A^(2); M^(0) = I01 x_1 A^(1); M^(1) = I01 x_0 A^(0);
+//               I12 = X x_0 A^(0); M^(2) = I12 x_1 A^(1)  (with the updated factors)
+//   PP build:   M^(0,1) = X x_2 A, M^(0,2) = X x_1 A, M^(1,2) = X x_0 A and M_p^(n)
+//   PP sweep:   M~^(n) = M_p^(n) + sum_{i != n} M^(i,n) x_i dA^(i) + A^(n) W^(n),
+//               W^(n) = U^(i) * U^(j) for the two other modes i, j
+// followed by the FP64 solve A^(n) = M Gamma^-1 (Cholesky), Grams and norms.
+#include "batch.h"
+#include "common.h"
+#include "tail_dev.h"
+
+namespace ppk {
+
+// ---------------------------------------------------------------------------
+// State machine
+// ---------------------------------------------------------------------------
+__global__ void k_b_begin(BState* st, BProb* pr, const BConf* conf, int count) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= count) return;
+  BState& S = st[p];
+  if (S.sweep == 0 && !S.done) S.t_start = wall_clock64();
+  if (S.done) {
+    S.kind = BK_NONE;
+    return;
+  }
+  if (S.sweep >= conf->max_sweeps) {
+    S.done = 1;
+    S.kind = BK_NONE;
+    return;
+  }
+  bool small = conf->eps > 0.0;
+  for (int n = 0; n < 3; ++n) small = small && S.rel[n] < conf->eps;
+  int kind = BK_ALS;
+  if (small) kind = (S.prev_kind == BK_PP_INIT || S.prev_kind == BK_PP_APPROX) ? BK_PP_APPROX
+                                                                              : BK_PP_INIT;
+  S.kind = kind;
+  pr[p].klog[S.sweep] = (uint8_t)kind;
+}
+
+// PP initialisation of the problems that start a PP phase: A_p := A, dA := 0, U := 0.
+__global__ __launch_bounds__(256) void k_b_prep(const BProb* pr, const BState* st, int count) {
+  const int p = blockIdx.x;
+  if (p >= count || st[p].kind != BK_PP_INIT) return;
+  const BProb& P = pr[p];
+  const int R = P.R;
+  for (int n = 0; n < 3; ++n) {
+    const int64_t cnt = (int64_t)P.s[n] * R;
+    for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) {
+      P.Ap[n][e] = P.A[n][e];
+      P.dA[n][e] = 0.0;
+    }
+  }
+  for (int e = threadIdx.x; e < 3 * R * R; e += blockDim.x) P.U[e] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Grouped first-level contraction: out[m][r] = sum_k X(m, k) A^(c)[k][r], FP32 on the
+// matrix cores (f32 16x16x4: lane l supplies A[m0 + l%16][k + l/16] and
+// B[k + l/16][c0 + l%16]; accumulator register v holds row 4 (l/16) + v, column l%16).
+// With P = prod s_{<c}, Q = prod s_{>c}: X(m, k) = X[p K Q + k Q + q], m = p Q + q.
+// TM output rows per tile, 4 waves of TM/4 rows each, R padded to 16-column tiles.
+// ---------------------------------------------------------------------------
+constexpr int BKC = 16;  // k per LDS chunk
+
+template <int TM>
+__global__ __launch_bounds__(256) void k_b_gemm(const BProb* pr, const BState* st,
+                                                const BTile* tiles, int ntiles, int cmode,
+                                                int out_op, int kind_mask) {
+  constexpr int RS = TM / 64;  // 16-row subtiles per wave
+  __shared__ float xs[BKC][TM + 4];
+  __shared__ float as[BKC][BATCH_MAX_R + 4];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const BTile tile = tiles[t];
+    const int p = tile.prob;
+    if (!(kind_mask & (1 << st[p].kind))) continue;
+    const BProb& P = pr[p];
+    const int R = P.R;
+    const int64_t K = P.s[cmode];
+    int64_t Pd = 1, Q = 1;
+    for (int i = 0; i < cmode; ++i) Pd *= P.s[i];
+    for (int i = cmode + 1; i < 3; ++i) Q *= P.s[i];
+    const int64_t M = Pd * Q;
+    const int m0 = tile.m0;
+    const float* X = P.X;
+    const double* A = P.A[cmode];
+    float* out = P.op[out_op];
+    const int NCT = (R + 15) >> 4;
+    f4 acc[RS][4];
+#pragma unroll
+    for (int i = 0; i < RS; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t k0 = 0; k0 < K; k0 += BKC) {
+      __syncthreads();
+      // stage X(m0.., k0..) as xs[k][m] with coalesced reads along the contiguous index
+      for (int idx = tid; idx < BKC * TM; idx += 256) {
+        int mm, kk;
+        if (Q == 1) {
+          kk = idx % BKC;
+          mm = idx / BKC;
+        } else {
+          mm = idx % TM;
+          kk = idx / TM;
+        }
+        const int64_t m = m0 + mm, k = k0 + kk;
+        float v = 0.f;
+        if (m < M && k < K) {
+          const int64_t pp = m / Q, q = m - pp * Q;
+          v = X[(pp * K + k) * Q + q];
+        }
+        xs[kk][mm] = v;
+      }
+      for (int idx = tid; idx < BKC * BATCH_MAX_R; idx += 256) {
+        const int kk = idx / BATCH_MAX_R, r = idx % BATCH_MAX_R;
+        const int64_t k = k0 + kk;
+        as[kk][r] = (k < K && r < R) ? (float)A[k * R + r] : 0.f;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < BKC; kk += 4) {
+        const int kr = kk + (l >> 4);
+        float a[RS];
+#pragma unroll
+        for (int i = 0; i < RS; ++i) a[i] = xs[kr][w * (TM / 4) + i * 16 + (l & 15)];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (j < NCT) {
+            const float b = as[kr][j * 16 + (l & 15)];
+#pragma unroll
+            for (int i = 0; i < RS; ++i)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b, acc[i][j], 0, 0, 0);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < RS; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (j >= NCT) continue;
+        const int c = j * 16 + (l & 15);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t m = m0 + w * (TM / 4) + i * 16 + 4 * (l >> 4) + v;
+          if (m < M && c < R) out[m * R + c] = acc[i][j][v];
+        }
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Grouped multi-TTV: out[y][r] = base[y][r] + sum_jobs sum_x T[p][x][q][r] F[x][r],
+// y = p Q + q.  One thread per output element, FP64 accumulation.
+// ---------------------------------------------------------------------------
+struct BJob {
+  const float* T;
+  const double* F;
+  int P, X, Q;
+};
+
+__device__ __forceinline__ double b_ttv_job(const BJob& J, int R, int y, int r) {
+  const int p = y / J.Q, q = y - p * J.Q;
+  const int64_t QR = (int64_t)J.Q * R;
+  const float* t = J.T + (int64_t)p * J.X * QR + (int64_t)q * R + r;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int x = 0;
+  for (; x + 3 < J.X; x += 4) {
+    a0 = fma((double)t[(int64_t)x * QR], J.F[(int64_t)x * R + r], a0);
+    a1 = fma((double)t[(int64_t)(x + 1) * QR], J.F[(int64_t)(x + 1) * R + r], a1);
+    a2 = fma((double)t[(int64_t)(x + 2) * QR], J.F[(int64_t)(x + 2) * R + r], a2);
+    a3 = fma((double)t[(int64_t)(x + 3) * QR], J.F[(int64_t)(x + 3) * R + r], a3);
+  }
+  for (; x < J.X; ++x) a0 = fma((double)t[(int64_t)x * QR], J.F[(int64_t)x * R + r], a0);
+  return (a0 + a1) + (a2 + a3);
+}
+
+__global__ __launch_bounds__(256) void k_b_ttv(const BProb* pr, const BState* st, const BTile* tiles,
+                                               int ntiles, int n, int build_mp) {
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const BTile tile = tiles[t];
+    const int p = tile.prob;
+    const int kind = st[p].kind;
+    if (build_mp ? kind != BK_PP_INIT : kind == BK_NONE) continue;
+    const BProb& P = pr[p];
+    const int R = P.R;
+    const int s0 = P.s[0], s1 = P.s[1], s2 = P.s[2];
+    const int e = tile.m0 + threadIdx.x;
+    if (e >= P.s[n] * R) continue;
+    const int y = e / R, r = e - (e / R) * R;
+    BJob J[2];
+    int nj = 0;
+    const double* base = nullptr;
+    double* out = P.M;
+    if (build_mp || kind == BK_ALS) {
+      const double* const* F = P.A;
+      if (build_mp) out = P.Mp[n];
+      if (n == 0) J[nj++] = BJob{P.op[0], F[1], s0, s1, 1};
+      else if (n == 1) J[nj++] = BJob{P.op[0], F[0], 1, s0, s1};
+      else if (build_mp) J[nj++] = BJob{P.op[1], F[0], 1, s0, s2};
+      else J[nj++] = BJob{P.op[2], F[1], 1, s1, s2};
+    } else {
+      base = P.Mp[n];
+      if (n == 0) {
+        J[nj++] = BJob{P.op[0], P.dA[1], s0, s1, 1};
+        J[nj++] = BJob{P.op[1], P.dA[2], s0, s2, 1};
+      } else if (n == 1) {
+        J[nj++] = BJob{P.op[0], P.dA[0], 1, s0, s1};
+        J[nj++] = BJob{P.op[2], P.dA[2], s1, s2, 1};
+      } else {
+        J[nj++] = BJob{P.op[1], P.dA[0], 1, s0, s2};
+        J[nj++] = BJob{P.op[2], P.dA[1], 1, s1, s2};
+      }
+    }
+    double v = base ? base[e] : 0.0;
+    for (int j = 0; j < nj; ++j) v += b_ttv_job(J[j], R, y, r);
+    out[e] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-problem solve of mode n (one workgroup per problem): Gamma = S^(i) * S^(j),
+// W = U^(i) * U^(j) (PP), Cholesky with one diagonal-shift retry, the rows of
+// A^(n) = M Gamma^-1 (plus A^(n) W in the PP right-hand side), dA, norms, and the
+// Grams S^(n) = A^T A and U^(n) = A^T dA on the matrix cores, 64 rows at a time.
+// ---------------------------------------------------------------------------
+constexpr int BSOLVE_CH = 64;
+
+__global__ __launch_bounds__(256) void k_b_solve(const BProb* pr, BState* st, const BConf* conf,
+                                                 int n) {
+  extern __shared__ double sm[];
+  __shared__ double red[4][4];
+  const int p = blockIdx.x;
+  const int kind = st[p].kind;
+  if (kind == BK_NONE) return;
+  const BProb& P = pr[p];
+  const int R = P.R, LS = R + 1, RR = R * R;
+  const int rows = P.s[n];
+  const bool pp = kind != BK_ALS;
+  const bool wterm = pp && conf->second_order;
+  const int i1 = n == 0 ? 1 : 0, i2 = n == 2 ? 1 : 2;  // the two other modes
+  double* Lm = sm;                         // R x (R+1)
+  double* Ws = Lm + R * LS;                // R x R
+  double* invd = Ws + RR;                  // R
+  double* ca = invd + R;                   // BSOLVE_CH x R: new rows
+  double* cd = ca + BSOLVE_CH * R;         // BSOLVE_CH x R: dA rows
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const bool lv = l < R;
+  const double* S = P.S;
+  const double* U = P.U;
+  double dmax = 0.0;
+  for (int e = tid; e < RR; e += 256) {
+    const double g = S[i1 * RR + e] * S[i2 * RR + e];
+    const int r = e / R, c = e - r * R;
+    Lm[r * LS + c] = g;
+    if (r == c) dmax = fmax(dmax, g);
+    Ws[e] = wterm ? U[i1 * RR + e] * U[i2 * RR + e] : 0.0;
+  }
+  for (int off = 32; off > 0; off >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, off));
+  if (l == 0) red[w][0] = dmax;
+  __syncthreads();
+  __shared__ int status;
+  if (w == 0) {
+    int stv = 0;
+    if (!chol_wave(Lm, R, LS)) {
+      const double mx = fmax(fmax(red[0][0], red[1][0]), fmax(red[2][0], red[3][0]));
+      const double delta = (double)R * 0x1p-52 * mx;
+      for (int e = l; e < RR; e += 64) {
+        const int r = e / R, c = e - r * R;
+        Lm[r * LS + c] = S[i1 * RR + e] * S[i2 * RR + e] + (r == c ? delta : 0.0);
+      }
+      stv = chol_wave(Lm, R, LS) ? 1 : 2;
+    }
+    if (l == 0) status = stv;
+    if (l < R) invd[l] = 1.0 / Lm[l * LS + l];
+  }
+  __syncthreads();
+  const int stv = status;
+  // Gram tiles owned by this wave: tile index tt = w + 4 * slot over NBR^2 S tiles then
+  // NBR^2 U tiles
+  const int NBR = (R + 15) >> 4;
+  const int ntile = NBR * NBR * (pp ? 2 : 1);
+  d4 gacc[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) gacc[q] = d4{0.0, 0.0, 0.0, 0.0};
+  double nd = 0.0, na = 0.0, nm = 0.0;
+  double* An = P.A[n];
+  const double* M = P.M;
+  const double* Apn = P.Ap[n];
+  double* dAn = P.dA[n];
+  for (int c0 = 0; c0 < rows; c0 += BSOLVE_CH) {
+    // each wave solves 16 rows of the chunk, two at a time
+    for (int rr = 0; rr < BSOLVE_CH / 4; rr += 2) {
+      double m[2], ao[2], x[2], mo[2];
+      bool rv[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int y = c0 + w * (BSOLVE_CH / 4) + rr + q;
+        rv[q] = y < rows;
+        const bool ok = rv[q] && lv;
+        m[q] = ok ? M[(int64_t)y * R + l] : 0.0;
+        ao[q] = ok ? An[(int64_t)y * R + l] : 0.0;
+      }
+      if (wterm) {
+        for (int j = 0; j < R; ++j) {
+          const double wj = lv ? Ws[j * R + l] : 0.0;
+#pragma unroll
+          for (int q = 0; q < 2; ++q) m[q] = fma(bcast(ao[q], j), wj, m[q]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q) mo[q] = m[q];
+      if (stv != 2) {
+        for (int j = 0; j < R; ++j) {
+          const double lkj = (lv && l > j) ? Lm[l * LS + j] : 0.0;
+          const double ij = invd[j];
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const double zj = bcast(m[q], j) * ij;
+            m[q] = (l == j) ? zj : m[q] - lkj * zj;
+          }
+        }
+        for (int j = R - 1; j >= 0; --j) {
+          const double ljk = (lv && l < j) ? Lm[j * LS + l] : 0.0;
+          const double ij = invd[j];
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const double xj = bcast(m[q], j) * ij;
+            m[q] = (l == j) ? xj : m[q] - ljk * xj;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) x[q] = lv ? m[q] : 0.0;
+      } else {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) x[q] = ao[q];
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int y = c0 + w * (BSOLVE_CH / 4) + rr + q;
+        const int yl = y - c0;
+        double d = 0.0;
+        if (rv[q] && lv) {
+          d = pp ? x[q] - Apn[(int64_t)y * R + l] : x[q] - ao[q];
+          An[(int64_t)y * R + l] = x[q];
+          if (pp) dAn[(int64_t)y * R + l] = d;
+          nd = fma(d, d, nd);
+          na = fma(x[q], x[q], na);
+          nm = fma(mo[q], x[q], nm);
+        }
+        if (lv) {
+          ca[yl * R + l] = (rv[q] ? x[q] : 0.0);
+          cd[yl * R + l] = (rv[q] ? d : 0.0);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int tt = w + 4 * q;
+      if (tt < ntile) {
+        const bool isU = tt >= NBR * NBR;
+        const int tl = isU ? tt - NBR * NBR : tt;
+        const int r0 = (tl / NBR) * 16, cc0 = (tl % NBR) * 16;
+        const double* Bm = isU ? cd : ca;
+        const int ra = r0 + (l & 15), cb = cc0 + (l & 15);
+        for (int kk = 0; kk < BSOLVE_CH; kk += 4) {
+          const int k = kk + (l >> 4);
+          const double a = ra < R ? ca[k * R + ra] : 0.0;
+          const double b = cb < R ? Bm[k * R + cb] : 0.0;
+          gacc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, gacc[q], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int tt = w + 4 * q;
+    if (tt < ntile) {
+      const bool isU = tt >= NBR * NBR;
+      const int tl = isU ? tt - NBR * NBR : tt;
+      const int r0 = (tl / NBR) * 16, cc0 = (tl % NBR) * 16;
+      double* out = (isU ? P.U : P.S) + (size_t)n * RR;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = r0 + 4 * v + (l >> 4), c = cc0 + (l & 15);
+        if (r < R && c < R) out[r * R + c] = gacc[q][v];
+      }
+    }
+  }
+  nd = wsum(nd);
+  na = wsum(na);
+  nm = wsum(nm);
+  if (l == 0) {
+    red[w][1] = nd;
+    red[w][2] = na;
+    red[w][3] = nm;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    BState& B = st[p];
+    B.sums[n][0] = ((red[0][1] + red[1][1]) + red[2][1]) + red[3][1];
+    B.sums[n][1] = ((red[0][2] + red[1][2]) + red[2][2]) + red[3][2];
+    B.sums[n][2] = ((red[0][3] + red[1][3]) + red[2][3]) + red[3][3];
+    B.chol[n] = stv;
+  }
+  if (n == 2) {
+    // sum of Gamma^(2) * S^(2) with the new Gram (written above by this workgroup)
+    double g = 0.0;
+    for (int e = tid; e < RR; e += 256) g = fma(S[e] * S[RR + e], S[2 * RR + e], g);
+    g = wsum(g);
+    __syncthreads();
+    if (l == 0) red[w][0] = g;
+    __syncthreads();
+    if (tid == 0) st[p].gs = ((red[0][0] + red[1][0]) + red[2][0]) + red[3][0];
+  }
+}
+
+// End of a sweep: relative changes, fit, convergence.
+__global__ void k_b_end(BState* st, const BConf* conf, int count) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= count) return;
+  BState& S = st[p];
+  if (S.kind == BK_NONE) return;
+  for (int n = 0; n < 3; ++n) {
+    const double d2 = S.sums[n][0], a2 = S.sums[n][1];
+    S.rel[n] = a2 > 0.0 ? sqrt(d2) / sqrt(a2) : (d2 > 0.0 ? INFINITY : 0.0);
+  }
+  const double r2 = S.normX2 - 2.0 * S.sums[2][2] + S.gs;
+  S.fit = 1.0 - sqrt(r2 > 0.0 ? r2 : 0.0) / sqrt(S.normX2);
+  if (S.kind == BK_ALS) S.n_als++;
+  else if (S.kind == BK_PP_INIT) S.n_init++;
+  else S.n_approx++;
+  const bool conv = S.sweep >= 1 && fabs(S.fit - S.fit_prev) < conf->tol;
+  S.fit_prev = S.fit;
+  S.prev_kind = S.kind;
+  S.sweep++;
+  if (conv) {
+    S.done = 1;
+    S.conv_sweep = S.sweep;
+    S.t_conv = wall_clock64();
+  }
+}
+
+// Initialisation: ||X||^2, the Grams of the initial factors, a fresh state and an empty
+// sweep-kind log.
+__global__ __launch_bounds__(256) void k_b_norm(const BProb* pr, BState* st, const BConf* conf,
+                                                int count) {
+  __shared__ double red[4];
+  const int p = blockIdx.x;
+  if (p >= count) return;
+  const BProb& P = pr[p];
+  for (int k = threadIdx.x; k < conf->max_sweeps; k += 256) P.klog[k] = 0;
+  const int64_t total = (int64_t)P.s[0] * P.s[1] * P.s[2];
+  double a = 0.0;
+  for (int64_t e = threadIdx.x; e < total; e += 256) {
+    const double v = P.X[e];
+    a = fma(v, v, a);
+  }
+  a = wsum(a);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) red[w] = a;
+  const int R = P.R;
+  for (int n = 0; n < 3; ++n)
+    for (int e = threadIdx.x; e < R * R; e += 256) {
+      const int r = e / R, c = e - r * R;
+      double g = 0.0;
+      for (int y = 0; y < P.s[n]; ++y) g = fma(P.A[n][y * R + r], P.A[n][y * R + c], g);
+      P.S[n * R * R + e] = g;
+    }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    BState& S = st[p];
+    S.normX2 = ((red[0] + red[1]) + red[2]) + red[3];
+    S.kind = BK_NONE;
+    S.prev_kind = BK_NONE;
+    S.sweep = 0;
+    S.done = 0;
+    S.conv_sweep = -1;
+    S.n_als = S.n_init = S.n_approx = 0;
+    S.fit = S.fit_prev = 0.0;
+    for (int n = 0; n < 3; ++n) {
+      S.rel[n] = 1.0;
+      S.chol[n] = 0;
+    }
+    S.gs = 0.0;
+    S.t_start = 0;
+    S.t_conv = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+int batch_gemm_rows(int variant) { return variant == 0 ? 64 : 128; }
+
+static int grid_for(int ntiles) { return ntiles < 2048 ? (ntiles > 0 ? ntiles : 1) : 2048; }
+
+hipError_t launch_b_begin(BState* st, BProb* pr, const BConf* conf, int count, hipStream_t s) {
+  hipLaunchKernelGGL(k_b_begin, dim3((count + 255) / 256), dim3(256), 0, s, st, pr, conf, count);
+  return hipGetLastError();
+}
+hipError_t launch_b_prep(const BProb* pr, const BState* st, int count, hipStream_t s) {
+  hipLaunchKernelGGL(k_b_prep, dim3(count), dim3(256), 0, s, pr, st, count);
+  return hipGetLastError();
+}
+hipError_t launch_b_gemm(int variant, const BProb* pr, const BState* st, const BTile* tiles,
+                         int ntiles, int cmode, int out_op, int kind_mask, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (variant == 0)
+    hipLaunchKernelGGL(k_b_gemm<64>, dim3(grid_for(ntiles)), dim3(256), 0, s, pr, st, tiles, ntiles,
+                       cmode, out_op, kind_mask);
+  else
+    hipLaunchKernelGGL(k_b_gemm<128>, dim3(grid_for(ntiles)), dim3(256), 0, s, pr, st, tiles,
+                       ntiles, cmode, out_op, kind_mask);
+  return hipGetLastError();
+}
+hipError_t launch_b_ttv(const BProb* pr, const BState* st, const BTile* tiles, int ntiles, int mode,
+                        int build_mp, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_b_ttv, dim3(grid_for(ntiles)), dim3(256), 0, s, pr, st, tiles, ntiles, mode,
+                     build_mp);
+  return hipGetLastError();
+}
+static size_t b_solve_lds(int maxR) {
+  return ((size_t)maxR * (maxR + 1) + (size_t)maxR * maxR + maxR + 2 * (size_t)BSOLVE_CH * maxR) *
+         sizeof(double);
+}
+// The solve's LDS request above 64 KB is enabled once, outside any graph capture.
+hipError_t batch_prepare() {
+  return hipFuncSetAttribute((const void*)k_b_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)b_solve_lds(BATCH_MAX_R));
+}
+hipError_t launch_b_solve(const BProb* pr, BState* st, const BConf* conf, int count, int mode,
+                          int maxR, hipStream_t s) {
+  hipLaunchKernelGGL(k_b_solve, dim3(count), dim3(256), b_solve_lds(maxR), s, pr, st, conf, mode);
+  return hipGetLastError();
+}
+hipError_t launch_b_end(BState* st, const BConf* conf, int count, hipStream_t s) {
+  hipLaunchKernelGGL(k_b_end, dim3((count + 255) / 256), dim3(256), 0, s, st, conf, count);
+  return hipGetLastError();
+}
+hipError_t launch_b_norm(const BProb* pr, BState* st, const BConf* conf, int count, hipStream_t s) {
+  hipLaunchKernelGGL(k_b_norm, dim3(count), dim3(256), 0, s, pr, st, conf, count);
+  return hipGetLastError();
+}
+
+}  // namespace ppk

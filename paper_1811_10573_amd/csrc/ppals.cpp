@@ -35,6 +35,10 @@ static ppals_status fail(ppals_status st, const std::string& msg) {
   g_err = msg;
   return st;
 }
+namespace ppk {
+// error reporting for the other host translation units (the batched engine)
+ppals_status set_error(ppals_status st, const std::string& msg) { return fail(st, msg); }
+}  // namespace ppk
 #define HIPCHK(expr)                                                                   \
   do {                                                                                 \
     hipError_t e_ = (expr);                                                            \

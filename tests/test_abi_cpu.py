@@ -212,3 +212,40 @@ def test_controller_entry_points_validate_arguments(lib):
             assert lib.ppals_set_controller(h, ctypes.byref(c)) != 0, b
     finally:
         lib.ppals_plan_destroy(h)
+
+
+def test_batch_create_validates_and_describes(lib):
+    import json
+    from paper_1811_10573_amd import _lib
+    h = ctypes.c_void_p()
+    arr = (_lib.BatchProblem * 2)()
+    arr[0].dims[:] = [10, 20, 30]
+    arr[0].rank = 5
+    arr[1].dims[:] = [40, 8, 9]
+    arr[1].rank = 64
+    assert lib.ppals_batch_create(arr, 0, 10, ctypes.byref(h)) == _lib.PPALS_E_ARG
+    assert lib.ppals_batch_create(arr, 2, 0, ctypes.byref(h)) == _lib.PPALS_E_ARG
+    assert lib.ppals_batch_create(None, 2, 10, ctypes.byref(h)) == _lib.PPALS_E_ARG
+    arr[1].rank = 65
+    assert lib.ppals_batch_create(arr, 2, 10, ctypes.byref(h)) == _lib.PPALS_E_UNSUPPORTED
+    arr[1].rank = 64
+    arr[1].dims[1] = 257
+    assert lib.ppals_batch_create(arr, 2, 10, ctypes.byref(h)) == _lib.PPALS_E_UNSUPPORTED
+    arr[1].dims[1] = 8
+    assert lib.ppals_batch_create(arr, 2, 10, ctypes.byref(h)) == 0
+    try:
+        ws = lib.ppals_batch_workspace_bytes(h)
+        # at least the three FP32 operators of every problem
+        assert ws >= 4 * (10 * 20 + 10 * 30 + 20 * 30) * 5 + 4 * (40 * 8 + 40 * 9 + 8 * 9) * 64
+        buf = ctypes.create_string_buffer(4096)
+        assert lib.ppals_batch_describe(h, buf, 4096) == 0
+        info = json.loads(buf.value.decode())
+        assert info["count"] == 2 and info["max_rank"] == 64 and info["max_dim"] == 40
+        assert not info["tuned"]
+        # nothing bound yet: the device entry points refuse before touching a device
+        fake = ctypes.c_void_p(0x1000)
+        assert lib.ppals_batch_sweep(h, fake, None) == _lib.PPALS_E_STATE
+        assert lib.ppals_batch_run(h, fake, 1, 1, None) == _lib.PPALS_E_STATE
+        assert lib.ppals_batch_autotune(h, fake, 1, None) == _lib.PPALS_E_STATE
+    finally:
+        lib.ppals_batch_destroy(h)

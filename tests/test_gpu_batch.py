@@ -1,0 +1,162 @@
+"""GPU parity of the batched engine: every problem of a batch against the float64
+oracle replaying that problem's sweep-kind log, against the single-problem GPU path,
+graph replays against eager sweeps, tile variants against each other, and the
+convergence bookkeeping."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1811_10573_amd as pp
+import tensorgen
+from gpu_util import dev, fp32_round, to_dev
+from oracle import cp as ocp
+from oracle import pp as opp
+
+pytestmark = pytest.mark.gpu
+
+
+def _problems(count, seed, smin=5, smax=20, rmin=2, rmax=6):
+    rng = np.random.default_rng(seed)
+    out = []
+    for p in range(count):
+        dims = tuple(int(d) for d in rng.integers(smin, smax + 1, 3))
+        R = int(rng.integers(rmin, rmax + 1))
+        out.append((dims, R, 1000 * seed + p))
+    return out
+
+
+class BatchRun:
+    def __init__(self, specs, max_sweeps, eps, tol, collinearity=None):
+        self.specs = specs
+        self.probs = [tensorgen.make_problem(d, R, seed=s, eta=1e-3, collinearity=collinearity)
+                      for d, R, s in specs]
+        self.b = pp.Batch([(d, R) for d, R, _ in specs], max_sweeps)
+        self.ws = self.b.workspace(dev())
+        self.X = [to_dev(fp32_round(q.X).reshape(-1), torch.float32) for q in self.probs]
+        self.A = [[to_dev(a.copy()) for a in q.init] for q in self.probs]
+        self.eps, self.tol = eps, tol
+        self.b.bind(self.X, self.A, self.ws, eps, tol)
+
+    def reset(self):
+        for fs, q in zip(self.A, self.probs):
+            for f, a in zip(fs, q.init):
+                f.copy_(torch.from_numpy(a).to(f.device))
+        self.b.bind(self.X, self.A, self.ws, self.eps, self.tol)
+
+    def factors(self, p):
+        d, R, _ = self.specs[p]
+        return [f.cpu().numpy().reshape(d[n], R) for n, f in enumerate(self.A[p])]
+
+
+def _kinds(log_row):
+    return [pp.BATCH_KIND_NAMES[int(k)] for k in log_row if k]
+
+
+def test_batch_matches_oracle_replay():
+    specs = _problems(7, seed=1)
+    r = BatchRun(specs, max_sweeps=14, eps=0.3, tol=0.0, collinearity=0.5)
+    r.b.run(r.ws, 14, use_graph=False)
+    res = r.b.results(r.ws)
+    log = r.b.kind_log(r.ws)
+    saw_pp = False
+    for p, (q, (d, R, _)) in enumerate(zip(r.probs, specs)):
+        kinds = _kinds(log[p])
+        assert len(kinds) == 14 and res[p]["sweeps"] == 14
+        saw_pp |= "pp_approx" in kinds
+        Xh = fp32_round(q.X)
+        A_or, recs = opp.pp_als(Xh, q.init, eps=0.3, sweeps=14, replay=kinds)
+        got = r.factors(p)
+        for n in range(3):
+            err = np.linalg.norm(got[n] - A_or[n]) / np.linalg.norm(A_or[n])
+            assert err < 1e-4, (p, n, err)
+        assert abs(res[p]["fit"] - recs[-1].fit_est) < 1e-5, p
+        # the decisions follow the threshold rule on the oracle's relative changes,
+        # except where a change sits within rounding of eps
+        for k in range(1, len(kinds)):
+            rel = recs[k - 1].rel_change
+            if min(abs(x - 0.3) for x in rel) < 1e-4:
+                continue
+            small = all(x < 0.3 for x in rel)
+            if not small:
+                assert kinds[k] == "als", (p, k)
+            else:
+                assert kinds[k] == ("pp_approx" if kinds[k - 1] != "als" else "pp_init"), (p, k)
+    assert saw_pp
+
+
+def test_graph_replays_equal_eager_sweeps():
+    specs = _problems(9, seed=2)
+    r = BatchRun(specs, max_sweeps=10, eps=0.3, tol=0.0, collinearity=0.5)
+    eager = []
+    for k in range(4):
+        r.b.sweep(r.ws)
+        torch.cuda.synchronize()
+        eager.append([np.concatenate([f.cpu().numpy() for f in fs]) for fs in r.A])
+    r.reset()
+    for k in range(4):
+        r.b.run(r.ws, 1, use_graph=True)
+        torch.cuda.synchronize()
+        # eager host work between the replays
+        _ = torch.ones(1000, device=dev()).sum().item()
+        got = [np.concatenate([f.cpu().numpy() for f in fs]) for fs in r.A]
+        for p in range(len(specs)):
+            assert np.array_equal(got[p], eager[k][p]), (k, p)
+
+
+def test_autotuned_tiles_give_identical_results():
+    specs = _problems(6, seed=3, smin=30, smax=90, rmin=3, rmax=40)
+    r = BatchRun(specs, max_sweeps=6, eps=0.3, tol=0.0)
+    r.b.run(r.ws, 6, use_graph=True)
+    before = [np.concatenate([f.cpu().numpy() for f in fs]) for fs in r.A]
+    r.reset()
+    r.b.autotune(r.ws, reps=2)
+    info = r.b.describe()
+    assert info["tuned"] and info["buckets"]
+    assert all(bk["tile_rows"] in (64, 128) for bk in info["buckets"])
+    r.b.run(r.ws, 6, use_graph=True)
+    after = [np.concatenate([f.cpu().numpy() for f in fs]) for fs in r.A]
+    for p in range(len(specs)):
+        assert np.array_equal(before[p], after[p]), p
+
+
+def test_batch_matches_single_problem_path():
+    specs = _problems(4, seed=4, smin=12, smax=30, rmin=3, rmax=8)
+    r = BatchRun(specs, max_sweeps=10, eps=0.3, tol=0.0, collinearity=0.5)
+    r.b.run(r.ws, 10)
+    res = r.b.results(r.ws)
+    log = r.b.kind_log(r.ws)
+    for p, (q, (d, R, _)) in enumerate(zip(r.probs, specs)):
+        plan = pp.Plan(d, R, "f32", "f32", True)
+        X = to_dev(fp32_round(q.X), torch.float32)
+        A = [to_dev(a.copy()) for a in q.init]
+        S = torch.zeros(3 * R * R, dtype=torch.float64, device=dev())
+        ws = plan.workspace(dev())
+        rec = pp.new_record(dev())
+        nrm = torch.zeros(1, dtype=torch.float64, device=dev())
+        pp.tensor_norm2(X, nrm)
+        assert abs(float(nrm.item()) - res[p]["normX2"]) <= 1e-12 * res[p]["normX2"]
+        recs, _ = pp.run(plan, X, None, A, S, float(nrm.item()), ws, rec, eps=0.3, max_sweeps=10,
+                         replay=_kinds(log[p]))
+        got = r.factors(p)
+        for n in range(3):
+            single = A[n].cpu().numpy().reshape(d[n], R)
+            assert np.linalg.norm(got[n] - single) <= 1e-4 * np.linalg.norm(single), (p, n)
+        assert abs(recs[-1]["fit_est"] - res[p]["fit"]) < 1e-5
+
+
+def test_convergence_bookkeeping():
+    specs = _problems(12, seed=5, smin=10, smax=40, rmin=2, rmax=6)
+    r = BatchRun(specs, max_sweeps=200, eps=0.1, tol=1e-5)
+    r.b.run(r.ws, 200)
+    res = r.b.results(r.ws)
+    log = r.b.kind_log(r.ws)
+    for p, x in enumerate(res):
+        kinds = _kinds(log[p])
+        assert x["sweeps"] == len(kinds)
+        assert x["n_als"] + x["n_pp_init"] + x["n_pp_approx"] == x["sweeps"]
+        if x["converged_sweep"] > 0:
+            assert x["done"] == 1 and x["converged_sweep"] == x["sweeps"]
+            assert x["time_to_converge_ms"] > 0.0
+        else:
+            assert x["sweeps"] == 200
+    assert sum(x["converged_sweep"] > 0 for x in res) >= 10
