@@ -113,6 +113,130 @@ def copy_calibration(torch, dev):
     print(json.dumps({"copy_calibration_bytes": COPY_BYTES, "dispatches": 5}), flush=True)
 
 
+def batch_specs(count, seed=0):
+    """Sizes and ranks of the batched workload: s_n ~ U{32..192} per mode, R ~ U{4..48},
+    from SeedSequence(seed).spawn(count); the tensor of problem p uses seed p."""
+    out = []
+    for p, ss in enumerate(np.random.SeedSequence(seed).spawn(count)):
+        rng = np.random.default_rng(ss)
+        dims = tuple(int(d) for d in rng.integers(32, 193, 3))
+        out.append((dims, int(rng.integers(4, 49)), p))
+    return out
+
+
+def batch_cpu_baseline(specs, eps, sweeps, tol, budget_s):
+    """The float64 oracle on a bounded sample of the batched workload: whole
+    decompositions of the first problems (same recipe, host generator) until the
+    budget is spent; sweeps per second over the sample."""
+    import threadpoolctl
+    import tensorgen
+    from oracle import pp as opp
+    threads = max((p.get("num_threads", 1) for p in threadpoolctl.threadpool_info()), default=1)
+    done = 0
+    t_all = 0.0
+    used = 0
+    start = time.perf_counter()
+    for dims, R, seed in specs:
+        prob = tensorgen.make_problem(dims, R, seed=seed, eta=1e-3)
+        Xh = prob.X.astype(np.float32).astype(np.float64)
+        t0 = time.perf_counter()
+        _, recs = opp.pp_als(Xh, prob.init, eps=eps, sweeps=sweeps)
+        fits = [r.fit_est for r in recs]
+        n = len(recs)
+        for k in range(1, len(fits)):
+            if abs(fits[k] - fits[k - 1]) < tol:
+                n = k + 1
+                break
+        t_all += (time.perf_counter() - t0) * n / len(recs)
+        done += n
+        used += 1
+        if time.perf_counter() - start > budget_s:
+            break
+    return {"value": done / t_all if t_all > 0 else None, "unit": "sweeps/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"float64 oracle, the first {used} problems of the batch run to convergence "
+                      f"(|dfit| < {tol}) or {sweeps} sweeps: {done} sweeps in {t_all:.1f} s",
+            "host_cpus": len(os.sched_getaffinity(0))}
+
+
+def batch_bench(args, torch, dev):
+    import paper_1811_10573_amd as pp
+    import tensorgen
+    count, sweeps, eps, tol = args.batch_count, 100, 0.1, 1e-5
+    specs = batch_specs(count)
+    log(f"generating {count} problems (s ~ U{{32..192}}, R ~ U{{4..48}})")
+    X, A = [], []
+    for dims, R, seed in specs:
+        prob = tensorgen.make_problem_device(dims, R, seed, eta=1e-3, dtype="f32", device=dev)
+        X.append(prob.X.reshape(-1))
+        A.append([torch.from_numpy(a.copy()).to(dev) for a in prob.init])
+    init = [[a.clone() for a in fs] for fs in A]
+    b = pp.Batch([(d, R) for d, R, _ in specs], sweeps)
+    ws = b.workspace(dev)
+    log(f"workspace {b.workspace_bytes / 2**30:.2f} GiB, tensors "
+        f"{sum(x.numel() for x in X) * 4 / 2**30:.2f} GiB")
+
+    def reset():
+        for fs, f0 in zip(A, init):
+            for a, a0 in zip(fs, f0):
+                a.copy_(a0)
+        b.bind(X, A, ws, eps, tol)
+
+    reset()
+    b.autotune(ws, reps=3)
+    tune = b.describe()
+    for w in range(args.warmup):
+        reset()
+        b.run(ws, sweeps, use_graph=True)
+        torch.cuda.synchronize()
+    reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(ws, sweeps, use_graph=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    res = b.results(ws)
+    total = sum(r["sweeps"] for r in res)
+    conv = [r["time_to_converge_ms"] for r in res if r["converged_sweep"] > 0]
+    value = total / elapsed
+    log(f"{total} problem-sweeps in {elapsed * 1e3:.1f} ms -> {value:.0f} sweeps/s; "
+        f"{len(conv)}/{count} converged")
+    # roofline of the grouped first-level contraction from the autotuner's timings
+    # (contiguous-mode and leading-mode contractions of every problem, chosen variant);
+    # most problems have R < 40, where the contraction is bound by HBM (AI = R/2 flop/B)
+    nbytes = sum(2 * (4.0 * d[0] * d[1] * d[2] + 4.0 * R * (d[0] * d[1] + d[1] * d[2]) / 2)
+                 for d, R, _ in specs)
+    flops = sum(2.0 * R * (d[0] * d[1] * d[2]) * 2 for d, R, _ in specs)
+    ms = sum(bk[f"ms_{bk['tile_rows']}"] for bk in tune["buckets"])
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
+            "frac": achieved / PEAK["hbm_GBs"], "traffic": None, "kernel": "k_b_gemm",
+            "avg_ms": ms / 2, "work_per_launch": nbytes / 2,
+            "TFLOP_s": flops / (ms * 1e-3) / 1e12}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the float64 oracle on the host (bounded sample)")
+        cpu = batch_cpu_baseline(specs, eps, sweeps, tol, args.cpu_seconds)
+    kinds = {"als": sum(r["n_als"] for r in res), "pp_init": sum(r["n_pp_init"] for r in res),
+             "pp_approx": sum(r["n_pp_approx"] for r in res)}
+    line = {
+        "metric": "aggregate ALS sweeps/sec over a batch of independent PP-CP-ALS decompositions",
+        "value": value, "unit": "sweeps/s", "n_gpus": 1, "steps": 1, "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded planted CP + noise)",
+        "config": {"workload": f"{count} order-3 FP32 problems, s_n ~ U{{32..192}}, R ~ U{{4..48}}, "
+                               f"N(0,1) planted factors, 1e-3 noise, eps={eps}, {sweeps} sweeps max, "
+                               f"stop at |dfit| < {tol}, one HIP graph per batched sweep",
+                   "count": count},
+        "roofline": roof, "cpu_baseline": cpu,
+        "batch": {"converged": len(conv),
+                  "time_to_converge_ms_p50": float(np.percentile(conv, 50)) if conv else None,
+                  "time_to_converge_ms_p99": float(np.percentile(conv, 99)) if conv else None,
+                  "sweep_kinds": kinds, "autotune": tune},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def measured_traffic(kernel, tier, shape, rank):
     """HBM bytes per launch from the committed counter summary of this kernel and
     workload, or None when there is none or the kernel source changed since."""
@@ -153,6 +277,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dt", action="store_true")
+    ap.add_argument("--workload", default="pp", choices=["pp", "batch"],
+                    help="pp: the 800^3 decomposition (default); batch: 512 independent problems")
+    ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for scaling HBM counters)")
     args = ap.parse_args()
@@ -171,6 +298,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.copy_calibration:
         copy_calibration(torch, dev)
+        return
+    if args.workload == "batch":
+        batch_bench(args, torch, dev)
         return
     s, R = args.size, args.rank
     shape = (s, s, s)
