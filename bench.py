@@ -272,7 +272,14 @@ def main():
     ap.add_argument("--rank", type=int, default=50)
     ap.add_argument("--sweeps", type=int, default=200)
     ap.add_argument("--eps", type=float, default=0.1)
-    ap.add_argument("--collinearity", type=float, default=0.9)
+    ap.add_argument("--collinearity", type=float, default=0.9,
+                    help="column collinearity of the planted factors (< 0: i.i.d. N(0,1) factors)")
+    ap.add_argument("--order", type=int, default=3)
+    ap.add_argument("--eta", type=float, default=1e-3, help="relative noise level")
+    ap.add_argument("--device-gen", action="store_true",
+                    help="assemble the tensor on the GPU (tensorgen.make_problem_device)")
+    ap.add_argument("--compare-f64", action="store_true",
+                    help="replay the run's sweep kinds with the FP64 tier and report the difference")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -303,25 +310,37 @@ def main():
         batch_bench(args, torch, dev)
         return
     s, R = args.size, args.rank
-    shape = (s, s, s)
-    log(f"generating {shape} rank-{R} planted tensor (collinearity {args.collinearity}, seed {args.seed})")
+    shape = (s,) * args.order
+    coll = args.collinearity if args.collinearity >= 0 else None
+    log(f"generating {shape} rank-{R} planted tensor (collinearity {coll}, noise {args.eta}, "
+        f"seed {args.seed})")
     t0 = time.perf_counter()
-    prob = tensorgen.make_problem(shape, R, seed=args.seed, eta=1e-3, collinearity=args.collinearity)
+    if args.device_gen:
+        prob = tensorgen.make_problem_device(shape, R, args.seed, eta=args.eta, collinearity=coll,
+                                             dtype="f64", device=dev)
+        X64 = prob.X.reshape(-1)
+    else:
+        prob = tensorgen.make_problem(shape, R, seed=args.seed, eta=args.eta, collinearity=coll)
+        X64 = None
     log(f"generated in {time.perf_counter() - t0:.1f} s")
 
     tdt = "f64" if args.tier == "f64" else "f32"
     plan = pp.Plan(shape, R, tdt, args.tier, True)
-    if tdt == "f64":
+    if args.device_gen:
+        X = X64 if tdt == "f64" else X64.to(torch.float32)
+    elif tdt == "f64":
         X = torch.from_numpy(prob.X).to(dev)
     else:
         X = torch.from_numpy(prob.X.astype(np.float32)).to(dev)
+    if tdt == "f32" and X64 is not None and not args.compare_f64:
+        X64 = None
     Xb = None
     if args.tier == "bf16":
         Xb = torch.empty(X.numel(), dtype=torch.int16, device=dev)
         pp.cast_bf16(X, Xb)
     A0 = [torch.from_numpy(a).to(dev) for a in prob.init]
     A = [a.clone() for a in A0]
-    S = torch.zeros(3 * R * R, dtype=torch.float64, device=dev)
+    S = torch.zeros(len(shape) * R * R, dtype=torch.float64, device=dev)
     ws = plan.workspace(dev)
     rec = pp.new_record(dev)
     nrm = torch.zeros(1, dtype=torch.float64, device=dev)
@@ -368,6 +387,7 @@ def main():
     res2 = torch.zeros(1, dtype=torch.float64, device=dev)
     pp.exact_residual2(plan, X, A, res2, ws)
     fit_pp = 1.0 - float(np.sqrt(res2.item() / normX2))
+    A_pp = [a.clone() for a in A] if args.compare_f64 else None
 
     out_dt = None
     speedup = None
@@ -420,10 +440,35 @@ def main():
             e["GB_s"] = v["bytes"] / (v["total_ms"] * 1e-3) / 1e9
         kernels[k] = e
 
+    vs64 = None
+    if args.compare_f64 and args.tier != "f64":
+        # the same decisions with the FP64 tier on the FP64 tensor
+        if X64 is None:
+            X64 = torch.from_numpy(prob.X).to(dev).reshape(-1)
+        plan64 = pp.Plan(shape, R, "f64", "f64", True)
+        ws64 = plan64.workspace(dev)
+        A64 = [a.clone() for a in A0]
+        S64 = torch.zeros_like(S)
+        n64 = torch.zeros(1, dtype=torch.float64, device=dev)
+        pp.tensor_norm2(X64, n64)
+        recs64, _ = pp.run(plan64, X64, None, A64, S64, float(n64.item()), ws64, rec, eps=args.eps,
+                           max_sweeps=len(recs), replay=kinds)
+        pp.exact_residual2(plan64, X64, A64, res2, ws64)
+        fit64 = 1.0 - float(np.sqrt(res2.item() / float(n64.item())))
+        # this tier's final factors (the last timed step) on the FP64 tensor
+        pp.exact_residual2(plan64, X64, A_pp, res2, ws64)
+        fit_tier_on64 = 1.0 - float(np.sqrt(res2.item() / float(n64.item())))
+        fdiff = max(float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+                    for a, b in zip(A_pp, A64))
+        vs64 = {"fit_f64_replay": fit64, "fit_this_tier_on_f64_tensor": fit_tier_on64,
+                "fit_abs_diff": abs(fit_tier_on64 - fit64), "factor_rel_diff_max": fdiff}
+        log(f"vs FP64 replay: fit {fit_tier_on64:.10f} vs {fit64:.10f}, factor rel diff {fdiff:.2e}")
+        del ws64, X64
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the float64 oracle on the host (bounded sample)")
-        cpu = cpu_baseline(prob.X, prob.init, R, args.eps, kinds, args.cpu_seconds)
+        Xh = prob.X if not args.device_gen else prob.X.cpu().numpy()
+        cpu = cpu_baseline(Xh, prob.init, R, args.eps, kinds, args.cpu_seconds)
         log(f"oracle: {cpu['value']:.4f} sweeps/s projected for the same sweep mix")
 
     line = {
@@ -440,17 +485,21 @@ def main():
         "dtype": {"f64": "f64", "f32": "f32", "bf16": "bf16-in/f32-acc"}[args.tier],
         "data": "synthetic (seeded planted CP + Gaussian noise, tensorgen)",
         "config": {
-            "workload": (f"PP-CP-ALS, order-3 {s}x{s}x{s} {tdt.upper()} tensor, planted rank-{R} CP "
-                         f"with collinearity {args.collinearity}, 1e-3 noise, decomposition rank {R}, "
-                         f"eps={args.eps}, {args.sweeps} sweeps per step"),
+            "workload": (f"PP-CP-ALS, order-{len(shape)} {'x'.join(map(str, shape))} {tdt.upper()} "
+                         f"tensor, planted rank-{R} CP with "
+                         f"{'collinearity ' + str(coll) if coll is not None else 'N(0,1) factors'}, "
+                         f"{args.eta:g} noise, decomposition rank {R}, eps={args.eps}, "
+                         f"{args.sweeps} sweeps per step"),
             "shape": list(shape), "rank": R, "eps": args.eps, "sweeps_per_step": args.sweeps,
             "tier": args.tier, "seed": args.seed,
+            "generator": "device" if args.device_gen else "host",
         },
         "roofline": roof,
         "cpu_baseline": cpu,
         "pp": {"final_fit_exact": fit_pp, "final_fit_est": recs[-1]["fit_est"], "per_kind": per_kind},
         "dt_als": out_dt,
         "pp_vs_dt_time_to_equal_fit": speedup,
+        "vs_f64": vs64,
         "kernels": kernels,
     }
     print(json.dumps(line), flush=True)

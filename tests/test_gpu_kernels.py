@@ -117,6 +117,17 @@ def test_level1_blocks(tier, dims, R, blocks):
         assert_within(out.cpu().numpy(), want, (K + 1) * u * base, f"{tier} level1 {blk} {dims}")
 
 
+@pytest.mark.parametrize("tier", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("dims,R,blocks", [
+    ((8, 700, 8), 50, [[1]]),                         # long contraction, few rows: split over k
+    ((24, 40, 40, 24), 64, [[2, 3], [0, 1], [1, 2]]),  # combined two-mode contractions
+    ((20, 30, 30, 20), 48, [[2, 3], [0, 1]]),
+])
+def test_level1_split_k(tier, dims, R, blocks):
+    """Contractions long enough for the k range to be split over workgroups."""
+    test_level1_blocks(tier, dims, R, blocks)
+
+
 @pytest.mark.parametrize("tier", ["f64", "f32"])
 @pytest.mark.parametrize("dims,R", [((33, 27, 45), 9), ((10, 12, 9, 11), 16), ((5, 6, 4, 5, 6), 5),
                                     ((64, 64, 64), 10), ((3, 2, 3, 2, 2, 3), 4)])
