@@ -131,6 +131,16 @@ struct ppals_plan {
   bool ctl_set = false;
   ppals_controller ctl{};
 
+  // PP-approximated sweep captured once in a HIP graph by ppals_run (rank <= 64 path)
+  hipStream_t cap_stream = nullptr;  // capture stream (default priority)
+  hipGraph_t pp_graph = nullptr;
+  hipGraphExec_t pp_exec = nullptr;
+  const void* g_ws = nullptr;
+  const void* g_rec = nullptr;
+  const double* g_S = nullptr;
+  const double* g_A[PPALS_MAX_ORDER] = {nullptr};
+  double g_normX2 = 0.0;
+
   // optional per-kernel-class timing with HIP events on the launch stream
   bool prof = false;
   struct Pending { int cls; hipEvent_t a, b; double flops, bytes; };
@@ -1045,6 +1055,46 @@ ppals_status do_pp_sweep(ppals_plan* p, double* const* A, double* S, double norm
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
+// A PP-approximated sweep of the rank <= 64 path is a fixed sequence of launches on the
+// caller's and the auxiliary stream.  ppals_run captures it once (on a capture stream of
+// its own, since the caller's may be the null stream) and replays the graph; the graph
+// holds kernels and stream dependencies only.  It is rebuilt whenever the workspace,
+// factor, Gram or record pointers or ||X||^2 change.
+ppals_status pp_sweep_graphed(ppals_plan* p, double* const* A, double* S, double normX2, void* ws,
+                              ppals_sweep_record* rec, hipStream_t s) {
+  bool same = p->pp_exec && p->g_ws == ws && p->g_rec == rec && p->g_S == S &&
+              p->g_normX2 == normX2;
+  for (int n = 0; same && n < p->N; ++n) same = p->g_A[n] == A[n];
+  if (!same) {
+    if (p->pp_exec) (void)hipGraphExecDestroy(p->pp_exec);
+    if (p->pp_graph) (void)hipGraphDestroy(p->pp_graph);
+    p->pp_exec = nullptr;
+    p->pp_graph = nullptr;
+    if (!p->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    const int before = p->sweeps_since_build;
+    ppals_status st = do_pp_sweep(p, A, S, normX2, ws, rec, p->cap_stream);
+    p->sweeps_since_build = before;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+    if (st != PPALS_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return fail(PPALS_E_HIP, std::string("capture: ") + hipGetErrorString(e));
+    p->pp_graph = g;
+    HIPCHK(hipGraphInstantiate(&p->pp_exec, g, nullptr, nullptr, 0));
+    p->g_ws = ws;
+    p->g_rec = rec;
+    p->g_S = S;
+    p->g_normX2 = normX2;
+    for (int n = 0; n < p->N; ++n) p->g_A[n] = A[n];
+  }
+  HIPCHK(hipGraphLaunch(p->pp_exec, s));
+  p->sweeps_since_build++;
+  return PPALS_OK;
+}
+
 // Right-hand-side error of the PP update at the current factors (the learned
 // controller's label): the exact MTTKRP of every mode through the ALS dimension tree
 // without solves, the general PP update of every mode from the operators, and
@@ -1132,6 +1182,9 @@ void ppals_plan_destroy(ppals_plan* p) {
   if (p->ev_join) (void)hipEventDestroy(p->ev_join);
   if (p->aux) (void)hipStreamDestroy(p->aux);
   if (p->pinned_rec) (void)hipHostFree(p->pinned_rec);
+  if (p->pp_exec) (void)hipGraphExecDestroy(p->pp_exec);
+  if (p->pp_graph) (void)hipGraphDestroy(p->pp_graph);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   delete p;
 }
 
@@ -1457,7 +1510,11 @@ ppals_status ppals_run(ppals_plan* p, const void* X, const void* Xb, double* con
       if (st == PPALS_OK) st = do_pp_sweep(p, A, S, normX2, ws, rec_dev, s);
     } else if (kind == PPALS_SWEEP_PP_APPROX) {
       if (!p->ops_built) return fail(PPALS_E_STATE, "replay asks for pp_approx before a build");
-      st = do_pp_sweep(p, A, S, normX2, ws, rec_dev, s);
+      // graph replay unless per-kernel profiling is on (its events are host-side state)
+      if (p->fast && !p->prof && p->sweeps_since_build > 0)
+        st = pp_sweep_graphed(p, A, S, normX2, ws, rec_dev, s);
+      else
+        st = do_pp_sweep(p, A, S, normX2, ws, rec_dev, s);
     } else {
       st = do_als_sweep(p, X, Xb, A, S, normX2, ws, rec_dev, s);
     }

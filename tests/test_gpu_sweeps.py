@@ -253,3 +253,20 @@ def test_forced_pp_sweeps_high_rank(dims, R):
     # the fit estimate inherits the factors' sensitivity to rounding
     for g, o in zip(recs, ref):
         assert abs(g["fit_est"] - o.fit_est) <= max(1e-6, 1e3 * sens), (g["fit_est"], o.fit_est, sens)
+
+
+def test_graph_replayed_pp_sweeps_equal_eager_sweeps():
+    """The driver replays PP-approximated sweeps from a captured HIP graph; with
+    per-kernel profiling on it launches them one by one.  Both give identical bits."""
+    prob = tensorgen.make_problem((40, 36, 44), 6, seed=8, eta=1e-3, collinearity=0.5)
+    out = []
+    for profiling in (True, False):
+        r = Run(prob)
+        pp.set_profiling(r.plan, profiling)
+        recs, _ = pp.run(r.plan, r.X, None, r.A, r.S, r.normX2, r.ws, r.rec, eps=0.1, max_sweeps=40)
+        pp.set_profiling(r.plan, False)
+        out.append(([x["kind"] for x in recs], [x["fit_est"] for x in recs], r.factors()))
+    assert out[0][0] == out[1][0] and out[0][0].count("pp_approx") >= 3
+    assert out[0][1] == out[1][1]
+    for a, b in zip(out[0][2], out[1][2]):
+        assert np.array_equal(a, b)
