@@ -69,16 +69,20 @@ __global__ __launch_bounds__(256) void k_b_prep(const BProb* pr, const BState* s
 // B[k + l/16][c0 + l%16]; accumulator register v holds row 4 (l/16) + v, column l%16).
 // With P = prod s_{<c}, Q = prod s_{>c}: X(m, k) = X[p K Q + k Q + q], m = p Q + q.
 // TM output rows per tile, 4 waves of TM/4 rows each, R padded to 16-column tiles.
+// Chunks of BKC k-values pass through double-buffered LDS; the next chunk's X and
+// factor entries are loaded into registers while the current chunk is multiplied.
 // ---------------------------------------------------------------------------
-constexpr int BKC = 16;  // k per LDS chunk
+constexpr int BKC = 32;  // k per LDS chunk
 
 template <int TM>
 __global__ __launch_bounds__(256) void k_b_gemm(const BProb* pr, const BState* st,
                                                 const BTile* tiles, int ntiles, int cmode,
                                                 int out_op, int kind_mask) {
-  constexpr int RS = TM / 64;  // 16-row subtiles per wave
-  __shared__ float xs[BKC][TM + 4];
-  __shared__ float as[BKC][BATCH_MAX_R + 4];
+  constexpr int RS = TM / 64;                       // 16-row subtiles per wave
+  constexpr int XPER = BKC * TM / 256;              // X elements staged per thread
+  constexpr int APER = BKC * BATCH_MAX_R / 256;     // factor elements staged per thread
+  __shared__ float xs[2][BKC][TM + 4];
+  __shared__ float as[2][BKC][BATCH_MAX_R + 4];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const BTile tile = tiles[t];
@@ -96,53 +100,86 @@ __global__ __launch_bounds__(256) void k_b_gemm(const BProb* pr, const BState* s
     const double* A = P.A[cmode];
     float* out = P.op[out_op];
     const int NCT = (R + 15) >> 4;
+    float xr[XPER], ar[APER];
+    // Element j of the chunk staged by this thread.  Q == 1 (rows k-contiguous): row
+    // m0 + tid/BKC + (256/BKC) j, k = k0 + tid%BKC; otherwise (rows contiguous for a
+    // fixed k): row m0 + tid%TM, k = k0 + tid/TM + (256/TM) j.  The row's (p, q) split
+    // is formed once per tile.
+    const bool kcm = Q == 1;
+    const int mm0 = kcm ? tid / BKC : tid % TM;
+    const int kk0 = kcm ? tid % BKC : tid / TM;
+    constexpr int MSTEP = 256 / BKC, KSTEP_Q = 256 / TM;
+    // 32-bit element offsets (a problem holds at most 256^3 elements)
+    int xbase = 0;
+    bool rowv = true;
+    if (!kcm) {
+      const int m = m0 + mm0;
+      rowv = m < (int)M;
+      const int pp = rowv ? m / (int)Q : 0, q = rowv ? m - pp * (int)Q : 0;
+      xbase = pp * (int)K * (int)Q + q;
+    }
+    const int Ki = (int)K, Qi = (int)Q, Mi = (int)M;
+    const int ar_r = tid % BATCH_MAX_R, ar_k = tid / BATCH_MAX_R;
+    auto load_chunk = [&](int k0) {
+#pragma unroll
+      for (int j = 0; j < XPER; ++j) {
+        float v = 0.f;
+        if (kcm) {
+          const int m = m0 + mm0 + MSTEP * j, k = k0 + kk0;
+          if (m < Mi && k < Ki) v = X[m * Ki + k];
+        } else {
+          const int k = k0 + kk0 + KSTEP_Q * j;
+          if (rowv && k < Ki) v = X[xbase + k * Qi];
+        }
+        xr[j] = v;
+      }
+#pragma unroll
+      for (int j = 0; j < APER; ++j) {
+        const int k = k0 + ar_k + (256 / BATCH_MAX_R) * j;
+        ar[j] = (k < Ki && ar_r < R) ? (float)A[k * R + ar_r] : 0.f;
+      }
+    };
+    auto store_chunk = [&](int buf) {
+#pragma unroll
+      for (int j = 0; j < XPER; ++j) {
+        if (kcm) xs[buf][kk0][mm0 + MSTEP * j] = xr[j];
+        else xs[buf][kk0 + KSTEP_Q * j][mm0] = xr[j];
+      }
+#pragma unroll
+      for (int j = 0; j < APER; ++j) as[buf][ar_k + (256 / BATCH_MAX_R) * j][ar_r] = ar[j];
+    };
     f4 acc[RS][4];
 #pragma unroll
     for (int i = 0; i < RS; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-    for (int64_t k0 = 0; k0 < K; k0 += BKC) {
-      __syncthreads();
-      // stage X(m0.., k0..) as xs[k][m] with coalesced reads along the contiguous index
-      for (int idx = tid; idx < BKC * TM; idx += 256) {
-        int mm, kk;
-        if (Q == 1) {
-          kk = idx % BKC;
-          mm = idx / BKC;
-        } else {
-          mm = idx % TM;
-          kk = idx / TM;
-        }
-        const int64_t m = m0 + mm, k = k0 + kk;
-        float v = 0.f;
-        if (m < M && k < K) {
-          const int64_t pp = m / Q, q = m - pp * Q;
-          v = X[(pp * K + k) * Q + q];
-        }
-        xs[kk][mm] = v;
-      }
-      for (int idx = tid; idx < BKC * BATCH_MAX_R; idx += 256) {
-        const int kk = idx / BATCH_MAX_R, r = idx % BATCH_MAX_R;
-        const int64_t k = k0 + kk;
-        as[kk][r] = (k < K && r < R) ? (float)A[k * R + r] : 0.f;
-      }
-      __syncthreads();
+    __syncthreads();  // the previous tile's last chunk is no longer read
+    load_chunk(0);
+    store_chunk(0);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = 0; k0 < Ki; k0 += BKC) {
+      const bool more = k0 + BKC < Ki;
+      if (more) load_chunk(k0 + BKC);
 #pragma unroll
       for (int kk = 0; kk < BKC; kk += 4) {
         const int kr = kk + (l >> 4);
         float a[RS];
 #pragma unroll
-        for (int i = 0; i < RS; ++i) a[i] = xs[kr][w * (TM / 4) + i * 16 + (l & 15)];
+        for (int i = 0; i < RS; ++i) a[i] = xs[buf][kr][w * (TM / 4) + i * 16 + (l & 15)];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           if (j < NCT) {
-            const float b = as[kr][j * 16 + (l & 15)];
+            const float b = as[buf][kr][j * 16 + (l & 15)];
 #pragma unroll
             for (int i = 0; i < RS; ++i)
               acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b, acc[i][j], 0, 0, 0);
           }
         }
       }
+      if (more) store_chunk(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
     }
 #pragma unroll
     for (int i = 0; i < RS; ++i)
