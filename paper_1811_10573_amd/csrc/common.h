@@ -66,6 +66,7 @@ struct TtvBatch {
   TtvJob job[PP_MAX_JOBS];
   int njobs;
   int R;
+  const int* gate;     // if set and *gate == 0 the launch does nothing
 };
 
 }  // namespace ppk
@@ -123,6 +124,7 @@ struct HeadArgs {
   double* L;
   double* W;
   int* status;
+  const int* gate;    // if set and *gate == 0 the launch does nothing
 };
 struct GramArgs {
   int R, mode, nblk;
@@ -136,6 +138,7 @@ struct GramArgs {
   void* rec;
   int write_fit, sweep_kind;
   double normX2;
+  const int* gate;         // if set and *gate == 0 the launch does nothing
 };
 struct FusedSolveArgs {
   int R;
@@ -153,11 +156,14 @@ struct FusedSolveArgs {
   double* blockpart;       // nblk x 5 partial sums
   const int* status;
   int write_fit;
+  const int* gate;         // if set and *gate == 0 the launch does nothing
 };
 hipError_t launch_head(const HeadArgs& h, hipStream_t s);
 hipError_t launch_solve_fused(const FusedSolveArgs& a, hipStream_t s);
 int solve_fused_blocks(int64_t rows);
 hipError_t launch_gram_tiles(const GramArgs& a, hipStream_t s);
+hipError_t launch_set_int(int* p, int v, hipStream_t s);
+hipError_t launch_pp_gate(void* rec, int N, double eps, int* gate, hipStream_t s);
 
 // learned PP controller (k_mlp.hip)
 constexpr int MLP_MAX_IN = 16;

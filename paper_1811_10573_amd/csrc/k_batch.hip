@@ -74,7 +74,7 @@ __global__ __launch_bounds__(256) void k_b_prep(const BProb* pr, const BState* s
 // ---------------------------------------------------------------------------
 constexpr int BKC = 32;  // k per LDS chunk
 
-template <int TM>
+template <int TM, bool KCM>
 __global__ __launch_bounds__(256) void k_b_gemm(const BProb* pr, const BState* st,
                                                 const BTile* tiles, int ntiles, int cmode,
                                                 int out_op, int kind_mask) {
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(256) void k_b_gemm(const BProb* pr, const BState* s
     // m0 + tid/BKC + (256/BKC) j, k = k0 + tid%BKC; otherwise (rows contiguous for a
     // fixed k): row m0 + tid%TM, k = k0 + tid/TM + (256/TM) j.  The row's (p, q) split
     // is formed once per tile.
-    const bool kcm = Q == 1;
+    constexpr bool kcm = KCM;  // Q == 1 exactly when the last mode is contracted
     const int mm0 = kcm ? tid / BKC : tid % TM;
     const int kk0 = kcm ? tid % BKC : tid / TM;
     constexpr int MSTEP = 256 / BKC, KSTEP_Q = 256 / TM;
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(256) void k_b_gemm(const BProb* pr, const BState* s
     for (int k0 = 0; k0 < Ki; k0 += BKC) {
       const bool more = k0 + BKC < Ki;
       if (more) load_chunk(k0 + BKC);
-#pragma unroll
+#pragma unroll 2
       for (int kk = 0; kk < BKC; kk += 4) {
         const int kr = kk + (l >> 4);
         float a[RS];
@@ -553,12 +553,15 @@ hipError_t launch_b_prep(const BProb* pr, const BState* st, int count, hipStream
 hipError_t launch_b_gemm(int variant, const BProb* pr, const BState* st, const BTile* tiles,
                          int ntiles, int cmode, int out_op, int kind_mask, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  if (variant == 0)
-    hipLaunchKernelGGL(k_b_gemm<64>, dim3(grid_for(ntiles)), dim3(256), 0, s, pr, st, tiles, ntiles,
-                       cmode, out_op, kind_mask);
-  else
-    hipLaunchKernelGGL(k_b_gemm<128>, dim3(grid_for(ntiles)), dim3(256), 0, s, pr, st, tiles,
-                       ntiles, cmode, out_op, kind_mask);
+  const dim3 grid(grid_for(ntiles)), block(256);
+  const bool kcm = cmode == 2;
+  if (variant == 0) {
+    if (kcm) hipLaunchKernelGGL((k_b_gemm<64, true>), grid, block, 0, s, pr, st, tiles, ntiles, cmode, out_op, kind_mask);
+    else hipLaunchKernelGGL((k_b_gemm<64, false>), grid, block, 0, s, pr, st, tiles, ntiles, cmode, out_op, kind_mask);
+  } else {
+    if (kcm) hipLaunchKernelGGL((k_b_gemm<128, true>), grid, block, 0, s, pr, st, tiles, ntiles, cmode, out_op, kind_mask);
+    else hipLaunchKernelGGL((k_b_gemm<128, false>), grid, block, 0, s, pr, st, tiles, ntiles, cmode, out_op, kind_mask);
+  }
   return hipGetLastError();
 }
 hipError_t launch_b_ttv(const BProb* pr, const BState* st, const BTile* tiles, int ntiles, int mode,

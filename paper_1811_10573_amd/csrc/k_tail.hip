@@ -40,6 +40,7 @@ constexpr int HEAD_THREADS = 256;
 __global__ __launch_bounds__(HEAD_THREADS) void k_head(HeadArgs h) {
   extern __shared__ double Lm[];  // R x (R+1)
   __shared__ double red[HEAD_THREADS / 64];
+  if (h.gate && *h.gate == 0) return;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int R = h.R, RR = R * R, N = h.N, LS = R + 1;
   const int n = h.n;
@@ -124,6 +125,7 @@ __global__ __launch_bounds__(SOLVE_WAVES * 64) void k_solve_fused(FusedSolveArgs
   constexpr int ROWS = SOLVE_ROWS;
   constexpr int BR = SOLVE_BR;
   extern __shared__ double sm[];
+  if (a.gate && *a.gate == 0) return;
   const int R = a.R, LS = R + 1, RR = R * R;
   double* Ls = sm;                          // R x (R+1)
   double* Gs = Ls + (size_t)R * LS;         // R x R
@@ -268,6 +270,7 @@ constexpr int GRAM_UNROLL = 8;
 
 __global__ __launch_bounds__(GRAM_WAVES * 64) void k_gram_tiles(GramArgs a) {
   __shared__ double racc[GRAM_WAVES * 4 * 64];
+  if (a.gate && *a.gate == 0) return;
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63;
   const int R = a.R;
@@ -345,6 +348,31 @@ hipError_t launch_head(const HeadArgs& h, hipStream_t s) {
 }
 
 int solve_fused_blocks(int64_t rows) { return (int)((rows + SOLVE_BR - 1) / SOLVE_BR); }
+
+__global__ void k_set_int(int* p, int v) {
+  if (threadIdx.x == 0) *p = v;
+}
+
+// Gate of a PP-approximated sweep enqueued ahead of the host's decision (Algorithm 3's
+// test on the device): it stays open while every relative change of the sweep before
+// is below eps, closes otherwise and stays closed.  The sweep kind of the record tells
+// the host which of the enqueued sweeps ran (-1: skipped).
+__global__ void k_pp_gate(ppals_sweep_record* rec, int N, double eps, int* gate) {
+  if (threadIdx.x != 0) return;
+  bool open = *gate != 0;
+  for (int n = 0; n < N; ++n) open = open && rec->rel_change[n] < eps;
+  *gate = open ? 1 : 0;
+  rec->sweep_kind = open ? PPALS_SWEEP_PP_APPROX : -1;
+}
+
+hipError_t launch_set_int(int* p, int v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, p, v);
+  return hipGetLastError();
+}
+hipError_t launch_pp_gate(void* rec, int N, double eps, int* gate, hipStream_t s) {
+  hipLaunchKernelGGL(k_pp_gate, dim3(1), dim3(64), 0, s, (ppals_sweep_record*)rec, N, eps, gate);
+  return hipGetLastError();
+}
 
 hipError_t launch_gram_tiles(const GramArgs& a, hipStream_t s) {
   const int NBR = (a.R + 15) / 16;

@@ -37,6 +37,7 @@ __device__ __forceinline__ double ttv_body(const T* __restrict__ src, const doub
 
 __global__ __launch_bounds__(TTV_THREADS) __attribute__((amdgpu_num_vgpr(64))) void k_ttv(TtvBatch b) {
   __shared__ double red[TTV_THREADS];
+  if (b.gate && *b.gate == 0) return;
   int64_t bid = blockIdx.x;
   int jid = 0;
   while (jid < b.njobs - 1 && bid >= b.job[jid].blocks) {

@@ -116,6 +116,8 @@ struct ppals_plan {
   size_t off_ppart = 0, sz_ppart = 0;  // PP partial slots
   size_t off_blockpart = 0;  // fused-solve per-block partial sums
   size_t off_Mx = 0, off_Mt = 0, off_errsum = 0;  // right-hand-side error measurement
+  size_t off_gate = 0;                              // gate of PP sweeps enqueued ahead
+  const int* cur_gate = nullptr;  // set while the gated PP sweep is being captured
   bool fast = false;                   // rank <= 64: fused head/solve tail
   hipStream_t aux = nullptr;           // stream for the head kernel (default priority)
   ppals_sweep_record* pinned_rec = nullptr;  // pinned host staging of the sweep record
@@ -140,6 +142,10 @@ struct ppals_plan {
   const double* g_S = nullptr;
   const double* g_A[PPALS_MAX_ORDER] = {nullptr};
   double g_normX2 = 0.0;
+  // PP-approximated sweeps enqueued ahead of the host's decision by ppals_run
+  static constexpr int kLookahead = 8;
+  ppals_sweep_record* la_rec = nullptr;  // pinned host records, kLookahead slots
+  hipEvent_t la_e0[kLookahead] = {nullptr}, la_e1[kLookahead] = {nullptr};
 
   // optional per-kernel-class timing with HIP events on the launch stream
   bool prof = false;
@@ -462,6 +468,7 @@ void layout(ppals_plan* p) {
   p->off_Mx = take((size_t)p->sum_s * R * 8);
   p->off_Mt = take((size_t)p->max_s * R * 8);
   p->off_errsum = take((size_t)2 * PPALS_MAX_ORDER * 8);
+  p->off_gate = take(64);
   for (auto& b : p->bufs) b.off = take(b.bytes);
   p->ws_bytes = off;
 }
@@ -760,6 +767,7 @@ HeadArgs head_args(const Ctx& c, double* S, int n, int pp) {
   h.L = c.at<double>(p->off_L);
   h.W = c.at<double>(p->off_W);
   h.status = c.at<int>(p->off_status);
+  h.gate = p->cur_gate;
   return h;
 }
 
@@ -784,6 +792,7 @@ GramArgs gram_args(const Ctx& c, double* const* A, double* S, int n, int pp, dou
   g.write_fit = write_fit;
   g.sweep_kind = kind;
   g.normX2 = normX2;
+  g.gate = p->cur_gate;
   return g;
 }
 
@@ -829,6 +838,7 @@ ppals_status solve_fused(const Ctx& c, double* const* A, int n, const double* ba
   a.blockpart = c.at<double>(p->off_blockpart);
   a.status = c.at<int>(p->off_status) + n;
   a.write_fit = write_fit;
+  a.gate = p->cur_gate;
   Prof pr(p, 4, c.s);
   HIPCHK(launch_solve_fused(a, c.s));
   pr.end();
@@ -988,6 +998,7 @@ ppals_status do_pp_sweep(ppals_plan* p, double* const* A, double* S, double norm
     double* part = c.at<double>(p->off_ppart);
     for (int n = 0; n < p->N; ++n) {
       TtvBatch b = p->ppb[n];
+      b.gate = p->cur_gate;
       int64_t slot_off = 0;
       int nj = 0;
       double fl = 0, by = 0;
@@ -1059,9 +1070,13 @@ ppals_status do_pp_sweep(ppals_plan* p, double* const* A, double* S, double norm
 // caller's and the auxiliary stream.  ppals_run captures it once (on a capture stream of
 // its own, since the caller's may be the null stream) and replays the graph; the graph
 // holds kernels and stream dependencies only.  It is rebuilt whenever the workspace,
-// factor, Gram or record pointers or ||X||^2 change.
+// factor, Gram or record pointers or ||X||^2 change.  Every kernel of the captured sweep
+// reads a device gate and does nothing when it is closed, so that sweeps can be enqueued
+// ahead of the host's decision with the threshold test taken on the device.
+// open_gate: the host has decided this sweep (the gate is set open before the replay);
+// otherwise the caller has enqueued the device-side gate test before it.
 ppals_status pp_sweep_graphed(ppals_plan* p, double* const* A, double* S, double normX2, void* ws,
-                              ppals_sweep_record* rec, hipStream_t s) {
+                              ppals_sweep_record* rec, hipStream_t s, bool open_gate = true) {
   bool same = p->pp_exec && p->g_ws == ws && p->g_rec == rec && p->g_S == S &&
               p->g_normX2 == normX2;
   for (int n = 0; same && n < p->N; ++n) same = p->g_A[n] == A[n];
@@ -1073,7 +1088,9 @@ ppals_status pp_sweep_graphed(ppals_plan* p, double* const* A, double* S, double
     if (!p->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
     HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
     const int before = p->sweeps_since_build;
+    p->cur_gate = (const int*)((char*)ws + p->off_gate);
     ppals_status st = do_pp_sweep(p, A, S, normX2, ws, rec, p->cap_stream);
+    p->cur_gate = nullptr;
     p->sweeps_since_build = before;
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
@@ -1090,8 +1107,9 @@ ppals_status pp_sweep_graphed(ppals_plan* p, double* const* A, double* S, double
     p->g_normX2 = normX2;
     for (int n = 0; n < p->N; ++n) p->g_A[n] = A[n];
   }
+  if (open_gate) HIPCHK(launch_set_int((int*)((char*)ws + p->off_gate), 1, s));
   HIPCHK(hipGraphLaunch(p->pp_exec, s));
-  p->sweeps_since_build++;
+  if (open_gate) p->sweeps_since_build++;
   return PPALS_OK;
 }
 
@@ -1185,6 +1203,11 @@ void ppals_plan_destroy(ppals_plan* p) {
   if (p->pp_exec) (void)hipGraphExecDestroy(p->pp_exec);
   if (p->pp_graph) (void)hipGraphDestroy(p->pp_graph);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->la_rec) (void)hipHostFree(p->la_rec);
+  for (int k = 0; k < ppals_plan::kLookahead; ++k) {
+    if (p->la_e0[k]) (void)hipEventDestroy(p->la_e0[k]);
+    if (p->la_e1[k]) (void)hipEventDestroy(p->la_e1[k]);
+  }
   delete p;
 }
 
@@ -1503,6 +1526,65 @@ ppals_status ppals_run(ppals_plan* p, const void* X, const void* Xb, double* con
       kind = small ? (prev_kind == PPALS_SWEEP_ALS || prev_kind < 0 ? PPALS_SWEEP_PP_INIT
                                                                      : PPALS_SWEEP_PP_APPROX)
                    : PPALS_SWEEP_ALS;
+    }
+    // Inside a PP phase, with no controller, replay, gradient stop or profiling, up to
+    // kLookahead PP-approximated sweeps are enqueued at once; a device gate before each
+    // takes the threshold test of Algorithm 3 on the previous sweep's record, and the
+    // sweeps after the first failed test do nothing.  One synchronisation serves them all.
+    if (kind == PPALS_SWEEP_PP_APPROX && !replay && !ctl_on && !(delta > 0.0) && p->fast &&
+        !p->prof && p->ops_built && p->sweeps_since_build > 0) {
+      // how many sweeps to enqueue: the sweeps left before the largest relative change
+      // reaches eps, extrapolated linearly from the last two sweeps of this PP phase
+      int L = 2;
+      if (it >= 1 && host_records[it - 1].sweep_kind != PPALS_SWEEP_ALS) {
+        double r1 = 0.0, r0 = 0.0;
+        for (int n = 0; n < p->N; ++n) {
+          r1 = std::max(r1, rel[n]);
+          if (it >= 2) r0 = std::max(r0, host_records[it - 2].rel_change[n]);
+        }
+        if (it >= 2 && host_records[it - 2].sweep_kind == PPALS_SWEEP_PP_APPROX && r1 > r0)
+          L = 1 + (int)std::floor((eps - r1) / (r1 - r0));
+      }
+      L = std::max(1, std::min(L, std::min(ppals_plan::kLookahead, max_sweeps - it)));
+      if (!p->la_rec)
+        HIPCHK(hipHostMalloc((void**)&p->la_rec, sizeof(ppals_sweep_record) * ppals_plan::kLookahead,
+                             hipHostMallocDefault));
+      for (int k = 0; k < L && sweep_ms; ++k) {
+        if (!p->la_e0[k]) HIPCHK(hipEventCreate(&p->la_e0[k]));
+        if (!p->la_e1[k]) HIPCHK(hipEventCreate(&p->la_e1[k]));
+      }
+      int* gate = (int*)((char*)ws + p->off_gate);
+      HIPCHK(launch_set_int(gate, 1, s));
+      for (int k = 0; k < L; ++k) {
+        if (sweep_ms) HIPCHK(hipEventRecord(p->la_e0[k], s));
+        HIPCHK(launch_pp_gate(rec_dev, p->N, eps, gate, s));
+        st = pp_sweep_graphed(p, A, S, normX2, ws, rec_dev, s, /*open_gate=*/false);
+        if (st != PPALS_OK) return st;
+        if (sweep_ms) HIPCHK(hipEventRecord(p->la_e1[k], s));
+        HIPCHK(hipMemcpyAsync(p->la_rec + k, rec_dev, sizeof(ppals_sweep_record),
+                              hipMemcpyDeviceToHost, s));
+      }
+      HIPCHK(hipStreamSynchronize(s));
+      int ran = 0;
+      while (ran < L && p->la_rec[ran].sweep_kind == PPALS_SWEEP_PP_APPROX) ++ran;
+      if (ran == 0) return fail(PPALS_E_STATE, "device gate closed a sweep the host opened");
+      for (int k = 0; k < ran; ++k) {
+        ppals_sweep_record& hr = host_records[it];
+        hr = p->la_rec[k];
+        if (sweep_ms) HIPCHK(hipEventElapsedTime(&sweep_ms[it], p->la_e0[k], p->la_e1[k]));
+        hr.sweep_kind = PPALS_SWEEP_PP_APPROX;
+        hr.ctrl_pred = std::nan("");
+        hr.ctrl_leave = -1;
+        hr.ctrl_true_err = -1.0;
+        hr.ctrl_fallback = fell_back ? 1 : 0;
+        for (int n = 0; n < p->N; ++n) rel[n] = hr.rel_change[n];
+        p->sweeps_since_build++;
+        prev_kind = PPALS_SWEEP_PP_APPROX;
+        ++it;
+        *n_done = it;
+      }
+      --it;  // the loop increments
+      continue;
     }
     if (sweep_ms) HIPCHK(hipEventRecord(e0, s));
     if (kind == PPALS_SWEEP_PP_INIT) {
