@@ -50,7 +50,7 @@ typedef enum {
   PPALS_E_ARG = -1,          /* invalid argument (null pointer, bad size)        */
   PPALS_E_UNSUPPORTED = -2,  /* valid but not supported (order, rank, dtype mix)  */
   PPALS_E_HIP = -3,          /* a HIP runtime call or launch failed               */
-  PPALS_E_WORKSPACE = -4,    /* workspace pointer null while bytes are needed      */
+  PPALS_E_WORKSPACE = -4,    /* workspace pointer null or not 256-byte aligned     */
   PPALS_E_STATE = -5         /* pp_sweep before pp_build_operators                 */
 } ppals_status;
 
@@ -123,7 +123,9 @@ ppals_status ppals_plan_create(const ppals_desc* desc, ppals_plan** out);
 void ppals_plan_destroy(ppals_plan* plan);
 
 /* Bytes of device workspace the plan needs (intermediates of the dimension
- * trees, the C(N,2) pairwise perturbation operators, staging and scratch). */
+ * trees, the C(N,2) pairwise perturbation operators, staging and scratch).
+ * Every workspace argument of this library must be 256-byte aligned (device
+ * allocations are); a NULL or misaligned one fails with PPALS_E_WORKSPACE. */
 size_t ppals_workspace_bytes(const ppals_plan* plan);
 
 /* Host only: writes a JSON description of the schedules (contractions of the

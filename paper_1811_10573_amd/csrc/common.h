@@ -53,9 +53,20 @@ struct TtvJob {
   int jblocks;
   int G;               // x-groups per workgroup
   int Jb;              // j-width per group (j = q*R + r)
-  int64_t blocks;      // P * jblocks * xsplit
+  int64_t blocks;      // workgroups of this job
   int t_is_f32;
+  int kind;            // TTV_SCALAR, TTV_SLAB or TTV_ROWS (vector kernel, 256 threads)
+  int lanes;           // TTV_SLAB: active lanes per wave (VEC * lanes is a multiple of R)
+  int xs;              // TTV_ROWS: x-rows per split
+  int f_vec;           // TTV_SLAB: F is 16-byte aligned (vector weight loads)
 };
+// Job kinds.  TTV_SCALAR: the general kernel (any P, X, Q).  TTV_SLAB (Q == 1): each
+// (p, x-split) is a contiguous slab whose flat index is also F's, streamed with 16-byte
+// loads by lanes whose rank indices stay fixed.  TTV_ROWS (Q*R a multiple of the vector
+// width): each x-row of Q*R elements is streamed with 16-byte loads, F's rows of the
+// split staged in LDS.
+enum { TTV_SCALAR = 0, TTV_SLAB = 1, TTV_ROWS = 2 };
+constexpr int TTV_VTHREADS = 256;
 
 #define PP_MAX_JOBS 8
 // Threads per multi-TTV workgroup: 12 waves, so at most two workgroups (six waves per

@@ -5,12 +5,13 @@
 //     concurrently with the mode's contractions (TTV or first-level GEMM) on the main
 //     stream: it forms Gamma^(n) = Hadamard_{i != n} S^(i) and, in PP sweeps,
 //     W^(n) = sum over unordered pairs {i,j} (i,j != n) of U^(i)*U^(j)*Hadamard_{k != i,j,n} S^(k),
-//     and factorises Gamma^(n) = L L^T (left-looking, one wave, LDS resident, no
-//     workgroup barriers), retrying once with Gamma + delta I,
-//     delta = R 2^-52 max(diag Gamma), if a pivot is not positive;
+//     and factorises Gamma^(n) = L L^T (one wave, LDS resident, panels of 16 columns
+//     updated on the matrix cores, no workgroup barriers), retrying once with
+//     Gamma + delta I, delta = R 2^-52 max(diag Gamma), if a pivot is not positive;
 //  2. a fused solve with small blocks spread over the chip: M~ = base + sum of the
-//     contraction's partial slots + A^(n) W^(n) (PP), the forward and backward
-//     triangular solves, G = (A_old - A_new) Gamma, dA and per-block norm partials;
+//     contraction's partial slots + A^(n) W^(n) (PP), the two triangular solves (as
+//     unit-triangular substitutions and diagonal scalings), G = (A_old - A_new) Gamma,
+//     dA and per-block norm partials;
 //  3. the Grams S^(n) = A^T A and U^(n) = A^T dA on the matrix cores (one block per
 //     16 x 16 tile), whose first block also writes the sweep record and the fit.
 //     On the auxiliary stream it precedes the next mode's head; after the last mode it
@@ -36,51 +37,60 @@ constexpr int HEAD_THREADS = 256;
 
 // Head of mode n (one workgroup of four waves): Gamma^(n), W^(n) (PP) and, in wave 0,
 // the Cholesky factor with one diagonal-shift retry.  Small enough to be co-resident
-// with the contraction kernels that run meanwhile on the other stream.
+// with the contraction kernels that run meanwhile on the other stream.  NM is the
+// tensor order: each thread takes EB entries at a time and issues the loads of every
+// mode's S (and U) for them together.
+template <int NM>
 __global__ __launch_bounds__(HEAD_THREADS) void k_head(HeadArgs h) {
-  extern __shared__ double Lm[];  // R x (R+1)
+  __shared__ double Lm[64 * CH64_LS];  // Gamma, zero-padded to 64 x 64
   __shared__ double red[HEAD_THREADS / 64];
   if (h.gate && *h.gate == 0) return;
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int R = h.R, RR = R * R, N = h.N, LS = R + 1;
+  const int tid = threadIdx.x;
+  const int R = h.R, RR = R * R;
   const int n = h.n;
-  double dmax = 0.0;
   const bool wterm = h.pp && h.second_order;
-  constexpr int EB = 2;  // entries per thread whose loads are issued together
-  for (int e0 = tid; e0 < RR; e0 += EB * nthr) {
-    double sv[EB][PP_MAXN], uv[EB][PP_MAXN];
+  for (int e = tid; e < 64 * CH64_LS; e += HEAD_THREADS) {
+    const int r = e / CH64_LS, c = e - r * CH64_LS;
+    if (r >= R || c >= R) Lm[e] = 0.0;
+  }
+  constexpr int EB = 16 / NM > 0 ? 16 / NM : 1;
+  double dmax = 0.0;
+  for (int e0 = tid; e0 < RR; e0 += EB * HEAD_THREADS) {
+    double sv[EB][NM], uv[EB][NM];
 #pragma unroll
     for (int b = 0; b < EB; ++b) {
-      const int e = e0 + b * nthr;
+      const int e = e0 + b * HEAD_THREADS;
+      const int ec = e < RR ? e : 0;
 #pragma unroll
-      for (int i = 0; i < PP_MAXN; ++i) {
-        sv[b][i] = (i < N && e < RR) ? h.S[(int64_t)i * RR + e] : 1.0;
-        uv[b][i] = (wterm && i < N && e < RR) ? h.U[(int64_t)i * RR + e] : 0.0;
+      for (int k = 0; k < NM; ++k) sv[b][k] = h.S[(int64_t)k * RR + ec];
+      if (wterm) {
+#pragma unroll
+        for (int k = 0; k < NM; ++k) uv[b][k] = h.U[(int64_t)k * RR + ec];
+      } else {
+#pragma unroll
+        for (int k = 0; k < NM; ++k) uv[b][k] = 0.0;
       }
     }
 #pragma unroll
     for (int b = 0; b < EB; ++b) {
-      const int e = e0 + b * nthr;
-      if (e >= RR) break;
-      // Running sums over the modes k != n: P0 = prod s_k (= Gamma), P1 = sum_i u_i
-      // prod_{k != i} s_k, P2 = sum_{i<j} u_i u_j prod_{k != i,j} s_k (= W).
-      double P0 = 1.0, P1 = 0.0, P2 = 0.0;
+      const int e = e0 + b * HEAD_THREADS;
+      if (e < RR) {
+        // Running sums over the modes k != n: P0 = prod s_k (= Gamma), P1 = sum_i u_i
+        // prod_{k != i} s_k, P2 = sum_{i<j} u_i u_j prod_{k != i,j} s_k (= W).
+        double P0 = 1.0, P1 = 0.0, P2 = 0.0;
 #pragma unroll
-      for (int k = 0; k < PP_MAXN; ++k) {
-        if (k < N && k != n) {
-          P2 = fma(P2, sv[b][k], P1 * uv[b][k]);
-          P1 = fma(P1, sv[b][k], P0 * uv[b][k]);
-          P0 *= sv[b][k];
+        for (int k = 0; k < NM; ++k) {
+          const double sk = k == n ? 1.0 : sv[b][k];
+          const double uk = k == n ? 0.0 : uv[b][k];
+          P2 = fma(P2, sk, P1 * uk);
+          P1 = fma(P1, sk, P0 * uk);
+          P0 *= sk;
         }
-      }
-      const double v = P0;
-      h.gamma[e] = v;
-      const int r = e / R, c = e - r * R;
-      Lm[r * LS + c] = v;
-      if (r == c) dmax = fmax(dmax, v);
-      if (wterm) {
-        const double w = P2;
-        h.W[e] = w;
+        h.gamma[e] = P0;
+        const int r = e / R, c = e - r * R;
+        Lm[r * CH64_LS + c] = P0;
+        if (r == c) dmax = fmax(dmax, P0);
+        if (wterm) h.W[e] = P2;
       }
     }
   }
@@ -89,19 +99,24 @@ __global__ __launch_bounds__(HEAD_THREADS) void k_head(HeadArgs h) {
   __syncthreads();
   if (tid >= 64) return;  // the factorisation is wave 0's alone (no barriers follow)
   int st = 0;
-  if (!chol_wave(Lm, R, LS)) {
-    double mx = 0.0;
-    for (int i = 0; i < nthr / 64; ++i) mx = fmax(mx, red[i]);
-    const double delta = (double)R * 0x1p-52 * mx;
-    for (int e = tid; e < RR; e += 64) {
-      const int r = e / R, c = e - r * R;
-      Lm[r * LS + c] = gamma_entry(h.S, N, n, RR, e) + (r == c ? delta : 0.0);
+  for (int attempt = 0;; ++attempt) {
+    if (chol_wave64(Lm, R)) break;
+    if (attempt == 1) {
+      st = 2;
+      break;
     }
-    st = chol_wave(Lm, R, LS) ? 1 : 2;
+    double mx = 0.0;
+    for (int i = 0; i < HEAD_THREADS / 64; ++i) mx = fmax(mx, red[i]);
+    const double delta = (double)R * 0x1p-52 * mx;
+    for (int e = tid; e < 64 * CH64_LS; e += 64) {
+      const int r = e / CH64_LS, c = e - r * CH64_LS;
+      Lm[e] = (r < R && c < R) ? gamma_entry(h.S, h.N, n, RR, r * R + c) + (r == c ? delta : 0.0) : 0.0;
+    }
+    st = 1;
   }
   for (int e = tid; e < RR; e += 64) {
     const int r = e / R, c = e - r * R;
-    h.L[e] = (c <= r) ? Lm[r * LS + c] : 0.0;
+    h.L[e] = (c <= r) ? Lm[r * CH64_LS + c] : 0.0;
   }
   if (tid == 0) h.status[n] = st;
 }
@@ -117,25 +132,33 @@ constexpr int SOLVE_STAGE = 16;                     // staged L/Gamma/W entries 
 constexpr int NPART = 5;                            // per-block norm partials
 
 // Fused right-hand-side assembly + solve.  Per row: M~ = base + sum of the contraction's
-// partial slots + A_old W (PP second-order term); forward and backward substitution with
-// L (lane k owns column k); g = (A_old - A_new) Gamma; dA = A_new - ref.  Per block it
-// writes NPART partial sums: ||g||^2, ||dA||^2, ||A_new||^2, <M~, A_new> and, for the
-// fit, sum of A_new Gamma A_new^T (the squared norm of the CP model, row by row).
+// partial slots + A_old W (PP second-order term); then Gamma x = M~ through L L^T with
+// the factor split as L = (L D^-1) D (D = diag L): a unit lower substitution, a scaling
+// by D^-1, a unit upper substitution with D^-1 L and a last scaling by D^-1.  The unit
+// factors are formed once per block in LDS, row j holding the entries that step j of
+// each substitution subtracts, so a step is one lane broadcast and one FMA and the
+// LDS reads of eight steps are issued together.  Then g = (A_old - A_new) Gamma and
+// dA = A_new - ref.  Per block it writes NPART partial sums: ||g||^2, ||dA||^2,
+// ||A_new||^2, <M~, A_new> and, for the fit, sum of A_new Gamma A_new^T (the squared
+// norm of the CP model, row by row).
 __global__ __launch_bounds__(SOLVE_WAVES * 64) void k_solve_fused(FusedSolveArgs a) {
   constexpr int ROWS = SOLVE_ROWS;
   constexpr int BR = SOLVE_BR;
+  constexpr int UB = 8;  // substitution steps whose LDS operands are read together
   extern __shared__ double sm[];
   if (a.gate && *a.gate == 0) return;
-  const int R = a.R, LS = R + 1, RR = R * R;
-  double* Ls = sm;                          // R x (R+1)
-  double* Gs = Ls + (size_t)R * LS;         // R x R
-  double* Ws = Gs + (size_t)R * R;          // R x R (second-order term)
-  double* invd = Ws + (size_t)R * R;        // R
+  const int R = a.R, RR = R * R;
+  double* LF = sm;              // LF[j][k] = L[k][j] / L[j][j] for k > j, else 0
+  double* LB = LF + RR;         // LB[j][k] = L[j][k] / L[j][j] for k < j, else 0
+  double* Gs = LB + RR;         // Gamma
+  double* Ws = Gs + RR;         // second-order term
+  double* invd = Ws + RR;       // 1 / L[j][j]
   __shared__ double red[SOLVE_WAVES][NPART];
 
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int w = tid >> 6, l = tid & 63;
   const bool lv = l < R;
+  const int lc = lv ? l : 0;
   const int64_t row0 = (int64_t)blockIdx.x * BR + (int64_t)w * ROWS;
   double m[ROWS], ao[ROWS], rf[ROWS], x[ROWS];
   bool rv[ROWS];
@@ -148,7 +171,8 @@ __global__ __launch_bounds__(SOLVE_WAVES * 64) void k_solve_fused(FusedSolveArgs
     ao[q] = ok ? a.A[off] : 0.0;
     rf[q] = (ok && a.Aref) ? a.Aref[off] : 0.0;
   }
-  // stage L, Gamma, W through registers (loads issued together)
+  if (tid < R) invd[tid] = 1.0 / a.L[tid * R + tid];
+  // stage L (raw, into LB), Gamma and W
   for (int e0 = 0; e0 < RR; e0 += SOLVE_STAGE * nthr) {
     double stL[SOLVE_STAGE], stG[SOLVE_STAGE], stW[SOLVE_STAGE];
 #pragma unroll
@@ -163,8 +187,7 @@ __global__ __launch_bounds__(SOLVE_WAVES * 64) void k_solve_fused(FusedSolveArgs
     for (int t = 0; t < SOLVE_STAGE; ++t) {
       const int e = e0 + tid + t * nthr;
       if (e < RR) {
-        const int i = e / R, k = e - i * R;
-        Ls[i * LS + k] = stL[t];
+        LB[e] = stL[t];
         Gs[e] = stG[t];
         Ws[e] = stW[t];
       }
@@ -178,41 +201,63 @@ __global__ __launch_bounds__(SOLVE_WAVES * 64) void k_solve_fused(FusedSolveArgs
       if (rv[q] && lv) m[q] += ps[(row0 + q) * R + l];
   }
   __syncthreads();
-  for (int e = tid; e < R; e += nthr) invd[e] = 1.0 / Ls[e * LS + e];
+  // unit factors: each thread rescales the entries it staged (no other thread reads them yet)
+  for (int e = tid; e < RR; e += nthr) {
+    const int i = e / R, k = e - i * R;
+    const double v = LB[e];
+    LF[k * R + i] = i > k ? v * invd[k] : 0.0;
+    LB[e] = k < i ? v * invd[i] : 0.0;
+  }
   __syncthreads();
 
   const int st = *a.status;
   if (a.W) {
-    for (int j = 0; j < R; ++j) {
-      const double wj = lv ? Ws[j * R + l] : 0.0;
+    for (int j0 = 0; j0 < R; j0 += UB) {
+      double wv[UB];
 #pragma unroll
-      for (int q = 0; q < ROWS; ++q) m[q] = fma(bcast(ao[q], j), wj, m[q]);
+      for (int u = 0; u < UB; ++u) wv[u] = (j0 + u < R && lv) ? Ws[(j0 + u) * R + lc] : 0.0;
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        if (j0 + u < R) {
+#pragma unroll
+          for (int q = 0; q < ROWS; ++q) m[q] = fma(bcast(ao[q], j0 + u), wv[u], m[q]);
+        }
+      }
     }
   }
   double mo[ROWS];
 #pragma unroll
   for (int q = 0; q < ROWS; ++q) mo[q] = m[q];
   if (st != 2) {
-    for (int j = 0; j < R; ++j) {       // forward: L z = m
-      const double lkj = (lv && l > j) ? Ls[l * LS + j] : 0.0;
-      const double ij = invd[j];
+    const double dl = lv ? invd[lc] : 0.0;
+    for (int j0 = 0; j0 < R; j0 += UB) {            // (L D^-1) y = M~
+      double lf[UB];
 #pragma unroll
-      for (int q = 0; q < ROWS; ++q) {
-        const double zj = bcast(m[q], j) * ij;
-        m[q] = (l == j) ? zj : m[q] - lkj * zj;
-      }
-    }
-    for (int j = R - 1; j >= 0; --j) {  // backward: L^T x = z
-      const double ljk = (lv && l < j) ? Ls[j * LS + l] : 0.0;
-      const double ij = invd[j];
+      for (int u = 0; u < UB; ++u) lf[u] = (j0 + u < R && lv) ? LF[(j0 + u) * R + lc] : 0.0;
 #pragma unroll
-      for (int q = 0; q < ROWS; ++q) {
-        const double xj = bcast(m[q], j) * ij;
-        m[q] = (l == j) ? xj : m[q] - ljk * xj;
+      for (int u = 0; u < UB; ++u) {
+        if (j0 + u < R) {
+#pragma unroll
+          for (int q = 0; q < ROWS; ++q) m[q] = fma(-lf[u], bcast(m[q], j0 + u), m[q]);
+        }
       }
     }
 #pragma unroll
-    for (int q = 0; q < ROWS; ++q) x[q] = lv ? m[q] : 0.0;
+    for (int q = 0; q < ROWS; ++q) m[q] *= dl;
+    for (int j1 = R - 1; j1 >= 0; j1 -= UB) {       // (D^-1 L)^T v = D^-1 y, descending
+      double lb[UB];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) lb[u] = (j1 - u >= 0 && lv) ? LB[(j1 - u) * R + lc] : 0.0;
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        if (j1 - u >= 0) {
+#pragma unroll
+          for (int q = 0; q < ROWS; ++q) m[q] = fma(-lb[u], bcast(m[q], j1 - u), m[q]);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < ROWS; ++q) x[q] = m[q] * dl;
   } else {
 #pragma unroll
     for (int q = 0; q < ROWS; ++q) x[q] = ao[q];
@@ -220,12 +265,22 @@ __global__ __launch_bounds__(SOLVE_WAVES * 64) void k_solve_fused(FusedSolveArgs
   double g[ROWS], hq[ROWS];
 #pragma unroll
   for (int q = 0; q < ROWS; ++q) g[q] = hq[q] = 0.0;
-  for (int j = 0; j < R; ++j) {          // g = (a_old - a_new) Gamma; h = a_new Gamma (fit)
-    const double gjk = lv ? Gs[j * R + l] : 0.0;
+  double dx[ROWS];
 #pragma unroll
-    for (int q = 0; q < ROWS; ++q) {
-      g[q] = fma(bcast(ao[q] - x[q], j), gjk, g[q]);
-      if (a.write_fit) hq[q] = fma(bcast(x[q], j), gjk, hq[q]);
+  for (int q = 0; q < ROWS; ++q) dx[q] = ao[q] - x[q];
+  for (int j0 = 0; j0 < R; j0 += UB) {   // g = (a_old - a_new) Gamma; h = a_new Gamma (fit)
+    double gv[UB];
+#pragma unroll
+    for (int u = 0; u < UB; ++u) gv[u] = (j0 + u < R && lv) ? Gs[(j0 + u) * R + lc] : 0.0;
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      if (j0 + u < R) {
+#pragma unroll
+        for (int q = 0; q < ROWS; ++q) {
+          g[q] = fma(bcast(dx[q], j0 + u), gv[u], g[q]);
+          if (a.write_fit) hq[q] = fma(bcast(x[q], j0 + u), gv[u], hq[q]);
+        }
+      }
     }
   }
   double v[NPART] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -342,8 +397,16 @@ static hipError_t allow_lds(K kernel, size_t bytes) {
 }
 
 hipError_t launch_head(const HeadArgs& h, hipStream_t s) {
-  const size_t lds = (size_t)h.R * (h.R + 1) * sizeof(double);
-  hipLaunchKernelGGL(k_head, dim3(1), dim3(HEAD_THREADS), lds, s, h);
+  if (h.R > 64 || h.N < 2 || h.N > PP_MAXN) return hipErrorInvalidValue;
+  switch (h.N) {
+    case 2: hipLaunchKernelGGL(k_head<2>, dim3(1), dim3(HEAD_THREADS), 0, s, h); break;
+    case 3: hipLaunchKernelGGL(k_head<3>, dim3(1), dim3(HEAD_THREADS), 0, s, h); break;
+    case 4: hipLaunchKernelGGL(k_head<4>, dim3(1), dim3(HEAD_THREADS), 0, s, h); break;
+    case 5: hipLaunchKernelGGL(k_head<5>, dim3(1), dim3(HEAD_THREADS), 0, s, h); break;
+    case 6: hipLaunchKernelGGL(k_head<6>, dim3(1), dim3(HEAD_THREADS), 0, s, h); break;
+    case 7: hipLaunchKernelGGL(k_head<7>, dim3(1), dim3(HEAD_THREADS), 0, s, h); break;
+    default: hipLaunchKernelGGL(k_head<8>, dim3(1), dim3(HEAD_THREADS), 0, s, h); break;
+  }
   return hipGetLastError();
 }
 
@@ -382,7 +445,7 @@ hipError_t launch_gram_tiles(const GramArgs& a, hipStream_t s) {
 
 hipError_t launch_solve_fused(const FusedSolveArgs& a, hipStream_t s) {
   const int R = a.R;
-  const size_t lds = ((size_t)R * (R + 1) + 2 * (size_t)R * R + R) * sizeof(double);
+  const size_t lds = (4 * (size_t)R * R + R) * sizeof(double);
   hipError_t e = allow_lds(k_solve_fused, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_solve_fused, dim3(solve_fused_blocks(a.rows)), dim3(SOLVE_WAVES * 64), lds,

@@ -11,6 +11,7 @@
 // TTV_THREADS threads; when Q*R < TTV_THREADS the threads are split into G groups that
 // read G consecutive x-rows at once and are reduced through LDS.  Accumulation is FP64.
 #include "common.h"
+#include <algorithm>
 
 namespace ppk {
 
@@ -81,6 +82,173 @@ __global__ __launch_bounds__(TTV_THREADS) __attribute__((amdgpu_num_vgpr(64))) v
     }
   }
   if (gi == 0 && j < QR) J.out[(int64_t)split * J.out_split_stride + p * QR + j] = acc;
+}
+
+// Vector multi-TTV (TTV_VTHREADS threads, jobs of kinds TTV_SLAB and TTV_ROWS).  Each
+// lane streams 16-byte vectors of T (VEC = 4 FP32 or 2 FP64 elements) and accumulates
+// in FP64.
+template <typename T> struct TtvVecT;
+template <> struct TtvVecT<float> {
+  static constexpr int VEC = 4;
+  typedef float4 V;
+  __device__ static __forceinline__ void get(const V& v, double (&o)[4]) {
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+  }
+};
+template <> struct TtvVecT<double> {
+  static constexpr int VEC = 2;
+  typedef double2 V;
+  __device__ static __forceinline__ void get(const V& v, double (&o)[2]) {
+    o[0] = v.x; o[1] = v.y;
+  }
+};
+constexpr int TTV_U = 4;                         // vectors in flight per lane
+constexpr int TTV_W = TTV_VTHREADS / 64;         // waves per workgroup
+
+// TTV_SLAB: workgroup (p, split); wave w takes iterations w, w + TTV_W, ... of its split,
+// each covering S = VEC * lanes consecutive elements (a whole number of rank rows), so
+// lane l always holds ranks (VEC l + c) mod R.  Partial sums meet in LDS.
+template <typename T>
+__device__ __forceinline__ void ttv_slab(const TtvJob& J, int R, int64_t bid, double* red) {
+  using TV = TtvVecT<T>;
+  constexpr int VEC = TV::VEC;
+  const int64_t p = bid / J.xsplit;
+  const int split = (int)(bid - p * J.xsplit);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int L = J.lanes;
+  const int64_t n = J.X * R;
+  const int S = VEC * L;
+  const int64_t niter = n / S;
+  const int64_t per = (niter + J.xsplit - 1) / J.xsplit;
+  const int64_t it0 = (int64_t)split * per, it1 = min(niter, it0 + per);
+  const T* src = (const T*)J.T + p * n;
+  const double* F = J.F;
+  double acc[VEC];
+#pragma unroll
+  for (int c = 0; c < VEC; ++c) acc[c] = 0.0;
+  if (lane < L) {
+    int64_t it = it0 + w;
+    for (; it + (TTV_U - 1) * TTV_W < it1; it += TTV_U * TTV_W) {
+      typename TV::V tv[TTV_U];
+      double fv[TTV_U][VEC];
+#pragma unroll
+      for (int u = 0; u < TTV_U; ++u) {
+        const int64_t e = (it + u * TTV_W) * S + VEC * lane;
+        tv[u] = *reinterpret_cast<const typename TV::V*>(src + e);
+        if (J.f_vec) {
+#pragma unroll
+          for (int c = 0; c < VEC; c += 2) {
+            const double2 f2 = *reinterpret_cast<const double2*>(F + e + c);
+            fv[u][c] = f2.x;
+            fv[u][c + 1] = f2.y;
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < VEC; ++c) fv[u][c] = F[e + c];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < TTV_U; ++u) {
+        double t[VEC];
+        TV::get(tv[u], t);
+#pragma unroll
+        for (int c = 0; c < VEC; ++c) acc[c] = fma(t[c], fv[u][c], acc[c]);
+      }
+    }
+    for (; it < it1; it += TTV_W) {
+      const int64_t e = it * S + VEC * lane;
+      double t[VEC];
+      TV::get(*reinterpret_cast<const typename TV::V*>(src + e), t);
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) acc[c] = fma(t[c], F[e + c], acc[c]);
+    }
+    if (w == 0 && split == J.xsplit - 1) {  // the elements after the last whole iteration
+      const int64_t e = niter * S + VEC * lane;
+#pragma unroll
+      for (int c = 0; c < VEC; ++c)
+        if (e + c < n) acc[c] = fma((double)src[e + c], F[e + c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < VEC; ++c) red[w * 256 + VEC * lane + c] = acc[c];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < R) {
+    double sum = 0.0;
+    for (int ww = 0; ww < TTV_W; ++ww)
+      for (int k = threadIdx.x; k < S; k += R) sum += red[ww * 256 + k];
+    J.out[(int64_t)split * J.out_split_stride + p * R + threadIdx.x] = sum;
+  }
+}
+
+// TTV_ROWS: workgroup (jb, p, split) covers VEC * TTV_VTHREADS consecutive j of the rows
+// x in [x0, x1); F's rows x0..x1-1 are staged in LDS first.
+template <typename T>
+__device__ __forceinline__ void ttv_rows(const TtvJob& J, int R, int64_t bid, double* fl) {
+  using TV = TtvVecT<T>;
+  constexpr int VEC = TV::VEC;
+  const int64_t QR = J.Q * R;
+  const int64_t jb = bid % J.jblocks;
+  const int64_t rest = bid / J.jblocks;
+  const int64_t p = rest % J.P;
+  const int split = (int)(rest / J.P);
+  const int64_t x0 = (int64_t)split * J.xs;
+  const int64_t x1 = min(J.X, x0 + J.xs);
+  const int nf = (int)((x1 - x0) * R);
+  for (int i = threadIdx.x; i < nf; i += TTV_VTHREADS) fl[i] = J.F[x0 * R + i];
+  __syncthreads();
+  const int64_t j = (jb * TTV_VTHREADS + threadIdx.x) * VEC;
+  if (j >= QR) return;
+  int rc[VEC];
+#pragma unroll
+  for (int c = 0; c < VEC; ++c) rc[c] = (int)((j + c) % R);
+  const T* src = (const T*)J.T + p * J.X * QR + j;
+  double acc[VEC];
+#pragma unroll
+  for (int c = 0; c < VEC; ++c) acc[c] = 0.0;
+  int64_t x = x0;
+  for (; x + TTV_U - 1 < x1; x += TTV_U) {
+    typename TV::V tv[TTV_U];
+#pragma unroll
+    for (int u = 0; u < TTV_U; ++u) tv[u] = *reinterpret_cast<const typename TV::V*>(src + (x + u) * QR);
+#pragma unroll
+    for (int u = 0; u < TTV_U; ++u) {
+      double t[VEC];
+      TV::get(tv[u], t);
+      const double* fr = fl + (x + u - x0) * R;
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) acc[c] = fma(t[c], fr[rc[c]], acc[c]);
+    }
+  }
+  for (; x < x1; ++x) {
+    double t[VEC];
+    TV::get(*reinterpret_cast<const typename TV::V*>(src + x * QR), t);
+    const double* fr = fl + (x - x0) * R;
+#pragma unroll
+    for (int c = 0; c < VEC; ++c) acc[c] = fma(t[c], fr[rc[c]], acc[c]);
+  }
+  double* o = J.out + (int64_t)split * J.out_split_stride + p * QR + j;
+#pragma unroll
+  for (int c = 0; c < VEC; ++c) o[c] = acc[c];
+}
+
+__global__ __launch_bounds__(TTV_VTHREADS) void k_ttv_vec(TtvBatch b) {
+  __shared__ double red[TTV_W * 256];
+  extern __shared__ double fl[];
+  if (b.gate && *b.gate == 0) return;
+  int64_t bid = blockIdx.x;
+  int jid = 0;
+  while (jid < b.njobs - 1 && bid >= b.job[jid].blocks) {
+    bid -= b.job[jid].blocks;
+    ++jid;
+  }
+  const TtvJob& J = b.job[jid];
+  if (J.kind == TTV_SLAB) {
+    if (J.t_is_f32) ttv_slab<float>(J, b.R, bid, red);
+    else ttv_slab<double>(J, b.R, bid, red);
+  } else {
+    if (J.t_is_f32) ttv_rows<float>(J, b.R, bid, fl);
+    else ttv_rows<double>(J, b.R, bid, fl);
+  }
 }
 
 // out[idx] = (base ? base[idx] : 0) + sum_slots partial[slot][idx]
@@ -156,12 +324,42 @@ hipError_t launch_fill(double* out, double v, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Jobs of the scalar kind go to k_ttv, the others to k_ttv_vec (one launch each).
 hipError_t launch_ttv(const TtvBatch& b, hipStream_t s) {
-  int64_t total = 0;
-  for (int i = 0; i < b.njobs; ++i) total += b.job[i].blocks;
-  if (total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ttv, dim3((unsigned)total), dim3(TTV_THREADS), 0, s, b);
-  return hipGetLastError();
+  TtvBatch sb = b, vb = b;
+  sb.njobs = vb.njobs = 0;
+  int64_t stotal = 0, vtotal = 0;
+  size_t lds = 0;
+  for (int i = 0; i < b.njobs; ++i) {
+    const TtvJob& J = b.job[i];
+    if (J.blocks <= 0) continue;
+    if (J.kind == TTV_SCALAR) {
+      sb.job[sb.njobs++] = J;
+      stotal += J.blocks;
+    } else {
+      if ((uintptr_t)J.T % 16 != 0) return hipErrorInvalidValue;  // vector loads of T
+      TtvJob& V = vb.job[vb.njobs++];
+      V = J;
+      V.f_vec = (uintptr_t)J.F % 16 == 0;
+      vtotal += J.blocks;
+      if (J.kind == TTV_ROWS) lds = std::max(lds, (size_t)J.xs * b.R * sizeof(double));
+    }
+  }
+  if (stotal > 0) {
+    hipLaunchKernelGGL(k_ttv, dim3((unsigned)stotal), dim3(TTV_THREADS), 0, s, sb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (vtotal > 0) {
+    if (lds > 65536) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ttv_vec),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_ttv_vec, dim3((unsigned)vtotal), dim3(TTV_VTHREADS), lds, s, vb);
+    return hipGetLastError();
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_combine(double* out, int64_t count, int R, const double* base,

@@ -22,6 +22,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -167,12 +168,43 @@ int64_t prod_dims(const ppals_plan* p, const std::vector<int>& modes, int a, int
   return r;
 }
 
-void ttv_config(TtvJob& J, int64_t P, int64_t X, int64_t Q, int R) {
+// Work decomposition of one multi-TTV job (T is P x X x Q x R with elements of es bytes).
+// The vector kinds stream 16-byte vectors; the scalar kind covers every other shape.
+void ttv_config(TtvJob& J, int64_t P, int64_t X, int64_t Q, int R, int es) {
   memset(&J, 0, sizeof(J));
   J.P = P;
   J.X = X;
   J.Q = Q;
   const int64_t QR = Q * R;
+  const int VEC = 16 / es;
+  const int g = R / std::gcd(R, VEC);  // lanes per whole number of rank rows
+  if (Q == 1 && (X * R) % VEC == 0 && g <= 64) {
+    J.kind = TTV_SLAB;
+    J.lanes = (64 / g) * g;
+    const int64_t niter = X * R / ((int64_t)VEC * J.lanes);
+    const int64_t cap = std::max<int64_t>(1, niter / 32);
+    J.xsplit = (int)std::max<int64_t>(1, std::min<int64_t>((1600 + P - 1) / P, cap));
+    J.jblocks = 1;
+    J.blocks = P * J.xsplit;
+    J.out_split_stride = P * QR;
+    return;
+  }
+  if (QR % VEC == 0 && QR >= (int64_t)VEC * 64) {
+    J.kind = TTV_ROWS;
+    J.jblocks = (int)((QR + (int64_t)VEC * TTV_VTHREADS - 1) / ((int64_t)VEC * TTV_VTHREADS));
+    const int64_t base = P * J.jblocks;
+    int64_t xsplit = (640 + base - 1) / base;
+    xsplit = std::max<int64_t>(1, std::min<int64_t>(xsplit, X / 8));
+    int64_t xs = (X + xsplit - 1) / xsplit;
+    xs = std::min<int64_t>(xs, 8192 / R);  // F rows staged in at most 64 KB of LDS
+    xs = std::max<int64_t>(xs, 1);
+    J.xs = (int)xs;
+    J.xsplit = (int)((X + xs - 1) / xs);
+    J.blocks = base * J.xsplit;
+    J.out_split_stride = P * QR;
+    return;
+  }
+  J.kind = TTV_SCALAR;
   if (QR >= TTV_THREADS) {
     J.Jb = TTV_THREADS;
     J.G = 1;
@@ -252,7 +284,7 @@ int add_ttv(ppals_plan* p, int src_buf, const std::vector<int>& src_modes, int b
   t.P = prod_dims(p, src_modes, 0, bpos);
   t.X = prod_dims(p, src_modes, bpos, bpos + blen);
   t.Q = prod_dims(p, src_modes, bpos + blen, (int)src_modes.size());
-  ttv_config(t.job, t.P, t.X, t.Q, p->R);
+  ttv_config(t.job, t.P, t.X, t.Q, p->R, esize(p->bulk));
   t.out_buf = out_buf;
   t.out_mode = out_mode;
   for (int i = 0; i < (int)src_modes.size(); ++i)
@@ -411,8 +443,8 @@ void build_pp(ppals_plan* p) {
     for (int i = 0; i < N; ++i) {
       if (i == n) continue;
       TtvJob& J = b.job[nj++];
-      if (i < n) ttv_config(J, 1, p->dims[i], p->dims[n], p->R);   // op (i,n): contract leading
-      else ttv_config(J, p->dims[n], p->dims[i], 1, p->R);         // op (n,i): contract trailing
+      if (i < n) ttv_config(J, 1, p->dims[i], p->dims[n], p->R, esize(p->bulk));  // op (i,n): contract leading
+      else ttv_config(J, p->dims[n], p->dims[i], 1, p->R, esize(p->bulk));        // op (n,i): contract trailing
       J.out_split_stride = p->dims[n] * (int64_t)p->R;
       slots += J.xsplit;
     }
@@ -749,6 +781,7 @@ ppals_status check_common(const ppals_plan* p, const void* X, const void* Xb, do
   for (int n = 0; n < p->N; ++n)
     if (!A[n]) return fail(PPALS_E_ARG, "A[" + std::to_string(n) + "] is NULL");
   if (!ws) return fail(PPALS_E_WORKSPACE, "workspace is NULL");
+  if ((uintptr_t)ws % 256 != 0) return fail(PPALS_E_WORKSPACE, "workspace is not 256-byte aligned");
   return PPALS_OK;
 }
 
@@ -1324,6 +1357,7 @@ ppals_status pp_sweep(ppals_plan* p, double* const* A, double* S, double normX2,
                       ppals_sweep_record* rec, hipStream_t s) {
   if (!p || !A || !S || !rec) return fail(PPALS_E_ARG, "NULL argument");
   if (!ws) return fail(PPALS_E_WORKSPACE, "workspace is NULL");
+  if ((uintptr_t)ws % 256 != 0) return fail(PPALS_E_WORKSPACE, "workspace is not 256-byte aligned");
   for (int n = 0; n < p->N; ++n)
     if (!A[n]) return fail(PPALS_E_ARG, "A[n] is NULL");
   if (!p->ops_built) return fail(PPALS_E_STATE, "pp_sweep before pp_build_operators");
@@ -1346,6 +1380,7 @@ ppals_status gram_solve(int32_t R, int64_t rows, const double* Gamma, const void
   if (m_dtype != PPALS_FP64 && m_dtype != PPALS_FP32)
     return fail(PPALS_E_UNSUPPORTED, "m_dtype must be FP64 or FP32");
   if (!ws) return fail(PPALS_E_WORKSPACE, "workspace is NULL");
+  if ((uintptr_t)ws % 256 != 0) return fail(PPALS_E_WORKSPACE, "workspace is not 256-byte aligned");
   char* w = (char*)ws;
   double* L = (double*)w;
   double* rowpart = (double*)(w + align256((size_t)R * R * 8));
@@ -1373,6 +1408,7 @@ ppals_status ppals_tensor_norm2(const void* X, int32_t dtype, int64_t count, dou
                                 void* ws, hipStream_t s) {
   if (!X || !out) return fail(PPALS_E_ARG, "NULL argument");
   if (!ws) return fail(PPALS_E_WORKSPACE, "workspace is NULL");
+  if ((uintptr_t)ws % 256 != 0) return fail(PPALS_E_WORKSPACE, "workspace is not 256-byte aligned");
   if (dtype != PPALS_FP64 && dtype != PPALS_FP32) return fail(PPALS_E_UNSUPPORTED, "dtype");
   if (count < 1) return fail(PPALS_E_ARG, "count must be >= 1");
   HIPCHK(launch_norm2(X, dtype == PPALS_FP64 ? DT_F64 : DT_F32, count, (double*)ws, 1024, out, s));
@@ -1445,6 +1481,7 @@ ppals_status ppals_pp_rhs(ppals_plan* p, double* const* A, const double* S, int3
                           double* out, void* ws, hipStream_t s) {
   if (!p || !A || !S || !out) return fail(PPALS_E_ARG, "NULL argument");
   if (!ws) return fail(PPALS_E_WORKSPACE, "workspace is NULL");
+  if ((uintptr_t)ws % 256 != 0) return fail(PPALS_E_WORKSPACE, "workspace is not 256-byte aligned");
   if (mode < 0 || mode >= p->N) return fail(PPALS_E_ARG, "mode out of range");
   if (!p->ops_built) return fail(PPALS_E_STATE, "operators not built");
   Ctx c{p, (char*)ws, s};
@@ -1476,6 +1513,7 @@ ppals_status ppals_exact_residual2(ppals_plan* p, const void* X, double* const* 
                                    void* ws, hipStream_t s) {
   if (!p || !X || !A || !out) return fail(PPALS_E_ARG, "NULL argument");
   if (!ws) return fail(PPALS_E_WORKSPACE, "workspace is NULL");
+  if ((uintptr_t)ws % 256 != 0) return fail(PPALS_E_WORKSPACE, "workspace is not 256-byte aligned");
   Ctx c{p, (char*)ws, s};
   HIPCHK(launch_residual2(X, p->bulk, A, p->dims, p->N, p->R, c.at<double>(p->off_norm), 4096,
                           out, s));

@@ -90,6 +90,8 @@ def test_null_arguments_fail_before_any_device_work(lib):
         assert lib.cp_als_sweep(h, ctypes.c_void_p(8), nul, arr, ctypes.c_void_p(8), 1.0, nul,
                                 ctypes.c_void_p(8), nul) == -4
         assert lib.pp_sweep(h, arr, ctypes.c_void_p(8), 1.0, ctypes.c_void_p(8),
+                            ctypes.c_void_p(8), nul) == -4     # workspace not 256-byte aligned
+        assert lib.pp_sweep(h, arr, ctypes.c_void_p(8), 1.0, ctypes.c_void_p(4096),
                             ctypes.c_void_p(8), nul) == -5     # no operators built
         assert lib.pp_build_operators(h, nul, nul, arr, ctypes.c_void_p(8), nul) == -1
         assert lib.gram_solve(0, 5, nul, nul, 0, nul, nul, nul, nul, nul) == -2
@@ -97,14 +99,15 @@ def test_null_arguments_fail_before_any_device_work(lib):
         assert lib.ppals_tensor_norm2(nul, 0, 10, nul, nul, nul) == -1
         assert lib.ppals_cast_bf16(nul, nul, 10, nul) == -1
         assert lib.ppals_cast_bf16(ctypes.c_void_p(8), ctypes.c_void_p(8), 0, nul) == 0
+        ws = ctypes.c_void_p(4096)
         assert lib.ppals_mttkrp(h, ctypes.c_void_p(8), nul, arr, 7, ctypes.c_void_p(8),
-                                ctypes.c_void_p(8), nul) == -1
+                                ws, nul) == -1
         assert lib.ppals_level1(h, ctypes.c_void_p(8), nul, arr, 0b101, ctypes.c_void_p(8),
-                                ctypes.c_void_p(8), nul) == -1  # not contiguous
+                                ws, nul) == -1  # not contiguous
         assert lib.ppals_level1(h, ctypes.c_void_p(8), nul, arr, 0b111, ctypes.c_void_p(8),
-                                ctypes.c_void_p(8), nul) == -1  # all modes
-        assert lib.ppals_get_operator(h, ctypes.c_void_p(8), 0, 1, ctypes.c_void_p(8), nul) == -5
-        assert lib.ppals_get_operator(h, ctypes.c_void_p(8), 1, 0, ctypes.c_void_p(8), nul) == -1
+                                ws, nul) == -1  # all modes
+        assert lib.ppals_get_operator(h, ws, 0, 1, ctypes.c_void_p(8), nul) == -5
+        assert lib.ppals_get_operator(h, ws, 1, 0, ctypes.c_void_p(8), nul) == -1
     finally:
         lib.ppals_plan_destroy(h)
 
