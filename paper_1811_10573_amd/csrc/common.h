@@ -134,6 +134,7 @@ struct HeadArgs {
   double* gamma;
   double* L;
   double* W;
+  double* pack;       // solve operands: L D^-1 (transposed), D^-1 L, 1 / diag L
   int* status;
   const int* gate;    // if set and *gate == 0 the launch does nothing
 };
@@ -159,7 +160,7 @@ struct FusedSolveArgs {
   int nslots;
   int64_t slot_stride;
   const double* W;         // second-order matrix or NULL
-  const double* L;
+  const double* pack;      // written by the head: L D^-1 (transposed), D^-1 L, 1 / diag L
   const double* gamma;
   double* A;
   const double* Aref;      // NULL -> old A

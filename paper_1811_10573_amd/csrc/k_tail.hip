@@ -35,14 +35,17 @@ __device__ __forceinline__ double gamma_entry(const double* S, int N, int n, int
 
 constexpr int HEAD_THREADS = 256;
 
-// Head of mode n (one workgroup of four waves): Gamma^(n), W^(n) (PP) and, in wave 0,
-// the Cholesky factor with one diagonal-shift retry.  Small enough to be co-resident
-// with the contraction kernels that run meanwhile on the other stream.  NM is the
-// tensor order: each thread takes EB entries at a time and issues the loads of every
-// mode's S (and U) for them together.
+// Head of mode n (one workgroup of four waves): Gamma^(n), W^(n) (PP), the Cholesky
+// factor (wave 0, one diagonal-shift retry) and the solve operands.  Small enough to be
+// co-resident with the contraction kernels that run meanwhile on the other stream.  NM
+// is the tensor order; thread t takes row t / 4 and columns t % 4 + 4 j, a batch of CB
+// columns at a time with the loads of every other mode's S (and U) issued together.
 template <int NM>
 __global__ __launch_bounds__(HEAD_THREADS) void k_head(HeadArgs h) {
-  __shared__ double Lm[64 * CH64_LS];  // Gamma, zero-padded to 64 x 64
+  constexpr int NO = NM - 1;                 // modes other than n
+  constexpr int CB = 16 / NO > 1 ? 16 / NO : 2;
+  __shared__ double Lm[64 * CH64_LS];        // Gamma, zero-padded to 64 x 64
+  __shared__ double cb[128];
   __shared__ double red[HEAD_THREADS / 64];
   if (h.gate && *h.gate == 0) return;
   const int tid = threadIdx.x;
@@ -53,251 +56,236 @@ __global__ __launch_bounds__(HEAD_THREADS) void k_head(HeadArgs h) {
     const int r = e / CH64_LS, c = e - r * CH64_LS;
     if (r >= R || c >= R) Lm[e] = 0.0;
   }
-  constexpr int EB = 16 / NM > 0 ? 16 / NM : 1;
+  const int row = tid >> 2, c0 = tid & 3;
   double dmax = 0.0;
-  for (int e0 = tid; e0 < RR; e0 += EB * HEAD_THREADS) {
-    double sv[EB][NM], uv[EB][NM];
+  if (row < R) {
+    for (int j0 = 0; c0 + 4 * j0 < R; j0 += CB) {
+      double sv[CB][NO], uv[CB][NO];
 #pragma unroll
-    for (int b = 0; b < EB; ++b) {
-      const int e = e0 + b * HEAD_THREADS;
-      const int ec = e < RR ? e : 0;
+      for (int j = 0; j < CB; ++j) {
+        const int c = c0 + 4 * (j0 + j);
+        const int e = row * R + (c < R ? c : 0);
 #pragma unroll
-      for (int k = 0; k < NM; ++k) sv[b][k] = h.S[(int64_t)k * RR + ec];
-      if (wterm) {
-#pragma unroll
-        for (int k = 0; k < NM; ++k) uv[b][k] = h.U[(int64_t)k * RR + ec];
-      } else {
-#pragma unroll
-        for (int k = 0; k < NM; ++k) uv[b][k] = 0.0;
-      }
-    }
-#pragma unroll
-    for (int b = 0; b < EB; ++b) {
-      const int e = e0 + b * HEAD_THREADS;
-      if (e < RR) {
-        // Running sums over the modes k != n: P0 = prod s_k (= Gamma), P1 = sum_i u_i
-        // prod_{k != i} s_k, P2 = sum_{i<j} u_i u_j prod_{k != i,j} s_k (= W).
-        double P0 = 1.0, P1 = 0.0, P2 = 0.0;
-#pragma unroll
-        for (int k = 0; k < NM; ++k) {
-          const double sk = k == n ? 1.0 : sv[b][k];
-          const double uk = k == n ? 0.0 : uv[b][k];
-          P2 = fma(P2, sk, P1 * uk);
-          P1 = fma(P1, sk, P0 * uk);
-          P0 *= sk;
+        for (int k = 0; k < NO; ++k) {
+          const int mk = k + (k >= n ? 1 : 0);
+          sv[j][k] = h.S[(int64_t)mk * RR + e];
+          uv[j][k] = wterm ? h.U[(int64_t)mk * RR + e] : 0.0;
         }
-        h.gamma[e] = P0;
-        const int r = e / R, c = e - r * R;
-        Lm[r * CH64_LS + c] = P0;
-        if (r == c) dmax = fmax(dmax, P0);
-        if (wterm) h.W[e] = P2;
+      }
+#pragma unroll
+      for (int j = 0; j < CB; ++j) {
+        const int c = c0 + 4 * (j0 + j);
+        if (c < R) {
+          // Running sums over the modes k != n: P0 = prod s_k (= Gamma), P1 = sum_i u_i
+          // prod_{k != i} s_k, P2 = sum_{i<j} u_i u_j prod_{k != i,j} s_k (= W).
+          double P0 = 1.0, P1 = 0.0, P2 = 0.0;
+#pragma unroll
+          for (int k = 0; k < NO; ++k) {
+            P2 = fma(P2, sv[j][k], P1 * uv[j][k]);
+            P1 = fma(P1, sv[j][k], P0 * uv[j][k]);
+            P0 *= sv[j][k];
+          }
+          const int e = row * R + c;
+          h.gamma[e] = P0;
+          Lm[row * CH64_LS + c] = P0;
+          if (row == c) dmax = fmax(dmax, P0);
+          if (wterm) h.W[e] = P2;
+        }
       }
     }
   }
   for (int off = 32; off > 0; off >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, off));
   if ((tid & 63) == 0) red[tid >> 6] = dmax;
   __syncthreads();
-  if (tid >= 64) return;  // the factorisation is wave 0's alone (no barriers follow)
-  int st = 0;
-  for (int attempt = 0;; ++attempt) {
-    if (chol_wave64(Lm, R)) break;
-    if (attempt == 1) {
-      st = 2;
-      break;
+  if (tid < 64) {  // the factorisation is wave 0's alone; the other waves wait below
+    int st = 0;
+    for (int attempt = 0;; ++attempt) {
+      if (chol_wave64(Lm, cb, R)) break;
+      if (attempt == 1) {
+        st = 2;
+        break;
+      }
+      double mx = 0.0;
+      for (int i = 0; i < HEAD_THREADS / 64; ++i) mx = fmax(mx, red[i]);
+      const double delta = (double)R * 0x1p-52 * mx;
+      for (int e = tid; e < 64 * CH64_LS; e += 64) {
+        const int r = e / CH64_LS, c = e - r * CH64_LS;
+        Lm[e] = (r < R && c < R) ? gamma_entry(h.S, h.N, n, RR, r * R + c) + (r == c ? delta : 0.0) : 0.0;
+      }
+      st = 1;
     }
-    double mx = 0.0;
-    for (int i = 0; i < HEAD_THREADS / 64; ++i) mx = fmax(mx, red[i]);
-    const double delta = (double)R * 0x1p-52 * mx;
-    for (int e = tid; e < 64 * CH64_LS; e += 64) {
-      const int r = e / CH64_LS, c = e - r * CH64_LS;
-      Lm[e] = (r < R && c < R) ? gamma_entry(h.S, h.N, n, RR, r * R + c) + (r == c ? delta : 0.0) : 0.0;
+    if (tid < R) cb[tid] = 1.0 / Lm[tid * CH64_LS + tid];
+    if (tid == 0) h.status[n] = st;
+  }
+  __syncthreads();
+  // L, and the solve operands: LF[k][i] = L[i][k] / L[k][k] (i > k), LB[i][k] = L[i][k] / L[i][i]
+  // (k < i), zero elsewhere, then 1 / L[i][i]
+  double* LF = h.pack;
+  double* LB = LF + RR;
+  if (row < R) {
+    const double di = cb[row];
+    for (int c = c0; c < R; c += 4) {
+      const double v = c <= row ? Lm[row * CH64_LS + c] : 0.0;
+      h.L[row * R + c] = v;
+      LF[c * R + row] = row > c ? v * cb[c] : 0.0;
+      LB[row * R + c] = c < row ? v * di : 0.0;
     }
-    st = 1;
+    if (c0 == 0) LB[RR + row] = di;
   }
-  for (int e = tid; e < RR; e += 64) {
-    const int r = e / R, c = e - r * R;
-    h.L[e] = (c <= r) ? Lm[r * CH64_LS + c] : 0.0;
-  }
-  if (tid == 0) h.status[n] = st;
 }
 
 // ---------------------------------------------------------------------------
-// Fused right-hand-side assembly + solve + per-block partial Grams and norms.
-// Block: SOLVE_WAVES waves x SOLVE_ROWS rows.
+// Fused right-hand-side assembly + solve + per-block norm partials.
+// Block: SOLVE_WAVES waves, one row each.
 // ---------------------------------------------------------------------------
-constexpr int SOLVE_ROWS = 2;
-constexpr int SOLVE_WAVES = 4;
-constexpr int SOLVE_BR = SOLVE_ROWS * SOLVE_WAVES;  // rows per block
-constexpr int SOLVE_STAGE = 16;                     // staged L/Gamma/W entries per thread
+constexpr int SOLVE_WAVES = 8;
+constexpr int SOLVE_BR = SOLVE_WAVES;               // rows per block
 constexpr int NPART = 5;                            // per-block norm partials
 
 // Fused right-hand-side assembly + solve.  Per row: M~ = base + sum of the contraction's
 // partial slots + A_old W (PP second-order term); then Gamma x = M~ through L L^T with
 // the factor split as L = (L D^-1) D (D = diag L): a unit lower substitution, a scaling
-// by D^-1, a unit upper substitution with D^-1 L and a last scaling by D^-1.  The unit
-// factors are formed once per block in LDS, row j holding the entries that step j of
-// each substitution subtracts, so a step is one lane broadcast and one FMA and the
-// LDS reads of eight steps are issued together.  Then g = (A_old - A_new) Gamma and
-// dA = A_new - ref.  Per block it writes NPART partial sums: ||g||^2, ||dA||^2,
-// ||A_new||^2, <M~, A_new> and, for the fit, sum of A_new Gamma A_new^T (the squared
-// norm of the CP model, row by row).
+// by D^-1, a unit upper substitution with D^-1 L and a last scaling by D^-1 (the head
+// forms the unit factors).  Each substitution step is one lane broadcast and one FMA.
+// Products with a full R x R matrix (A_old W, the gradient and the fit term) read the
+// row vector back from LDS as broadcasts, eight entries per batch.  Then
+// g = (A_old - A_new) Gamma and dA = A_new - ref.  Per block it writes NPART partial
+// sums: ||g||^2, ||dA||^2, ||A_new||^2, <M~, A_new> and, for the fit, sum of
+// A_new Gamma A_new^T (the squared norm of the CP model, row by row).
 __global__ __launch_bounds__(SOLVE_WAVES * 64) void k_solve_fused(FusedSolveArgs a) {
-  constexpr int ROWS = SOLVE_ROWS;
-  constexpr int BR = SOLVE_BR;
-  constexpr int UB = 8;  // substitution steps whose LDS operands are read together
+  constexpr int UB = 8;  // steps whose LDS operands are read together
   extern __shared__ double sm[];
   if (a.gate && *a.gate == 0) return;
   const int R = a.R, RR = R * R;
-  double* LF = sm;              // LF[j][k] = L[k][j] / L[j][j] for k > j, else 0
-  double* LB = LF + RR;         // LB[j][k] = L[j][k] / L[j][j] for k < j, else 0
-  double* Gs = LB + RR;         // Gamma
-  double* Ws = Gs + RR;         // second-order term
-  double* invd = Ws + RR;       // 1 / L[j][j]
+  const int npk = 2 * RR + R;
+  double* LF = sm;               // LF[j][k] = L[k][j] / L[j][j] for k > j, else 0
+  double* LB = LF + RR;          // LB[j][k] = L[j][k] / L[j][j] for k < j, else 0
+  double* invd = LB + RR;        // 1 / L[j][j]
+  double* Gs = LF + npk;         // Gamma
+  double* Ws = Gs + RR;          // second-order term
+  double* vb = Ws + RR;          // per-wave broadcast vectors, SOLVE_WAVES x 3 x 64
   __shared__ double red[SOLVE_WAVES][NPART];
 
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int w = tid >> 6, l = tid & 63;
   const bool lv = l < R;
   const int lc = lv ? l : 0;
-  const int64_t row0 = (int64_t)blockIdx.x * BR + (int64_t)w * ROWS;
-  double m[ROWS], ao[ROWS], rf[ROWS], x[ROWS];
-  bool rv[ROWS];
+  const int64_t row = (int64_t)blockIdx.x * SOLVE_BR + w;
+  const bool rv = row < a.rows;
+  const bool ok = rv && lv;
+  const int64_t off = row * R + l;
+  // loads are unconditional (clamped row and column), masked afterwards
+  const int64_t offc = (rv ? row : a.rows - 1) * R + lc;
+  double m = a.base ? a.base[offc] : 0.0;
+  double ao = a.A[offc];
+  double rf = a.Aref ? a.Aref[offc] : 0.0;
+  {
+    double ps[8];
+    int sl = 0;
+    for (; sl + 8 <= a.nslots; sl += 8) {
 #pragma unroll
-  for (int q = 0; q < ROWS; ++q) {
-    rv[q] = (row0 + q) < a.rows;
-    const int64_t off = (row0 + q) * R + l;
-    const bool ok = rv[q] && lv;
-    m[q] = (ok && a.base) ? a.base[off] : 0.0;
-    ao[q] = ok ? a.A[off] : 0.0;
-    rf[q] = (ok && a.Aref) ? a.Aref[off] : 0.0;
-  }
-  if (tid < R) invd[tid] = 1.0 / a.L[tid * R + tid];
-  // stage L (raw, into LB), Gamma and W
-  for (int e0 = 0; e0 < RR; e0 += SOLVE_STAGE * nthr) {
-    double stL[SOLVE_STAGE], stG[SOLVE_STAGE], stW[SOLVE_STAGE];
+      for (int u = 0; u < 8; ++u) ps[u] = a.part[(int64_t)(sl + u) * a.slot_stride + offc];
 #pragma unroll
-    for (int t = 0; t < SOLVE_STAGE; ++t) {
-      const int e = e0 + tid + t * nthr;
-      const bool ok = e < RR;
-      stL[t] = ok ? a.L[e] : 0.0;
-      stG[t] = ok ? a.gamma[e] : 0.0;
-      stW[t] = (ok && a.W) ? a.W[e] : 0.0;
+      for (int u = 0; u < 8; ++u) m += ps[u];
     }
+    for (; sl < a.nslots; ++sl) m += a.part[(int64_t)sl * a.slot_stride + offc];
+  }
+  m = ok ? m : 0.0;
+  ao = ok ? ao : 0.0;
+  rf = ok ? rf : 0.0;
+  // stage the head's unit factors and 1 / diag L, Gamma and W
+  {
+    constexpr int ST = 8;
+    auto copy = [&](double* dst, const double* src, int cnt) {
+      for (int e0 = tid; e0 < cnt; e0 += ST * nthr) {
+        double v[ST];
 #pragma unroll
-    for (int t = 0; t < SOLVE_STAGE; ++t) {
-      const int e = e0 + tid + t * nthr;
-      if (e < RR) {
-        LB[e] = stL[t];
-        Gs[e] = stG[t];
-        Ws[e] = stW[t];
+        for (int u = 0; u < ST; ++u) v[u] = src[min(e0 + u * nthr, cnt - 1)];
+#pragma unroll
+        for (int u = 0; u < ST; ++u)
+          if (e0 + u * nthr < cnt) dst[e0 + u * nthr] = v[u];
       }
-    }
-  }
-#pragma unroll 8
-  for (int sl = 0; sl < a.nslots; ++sl) {
-    const double* ps = a.part + (int64_t)sl * a.slot_stride;
-#pragma unroll
-    for (int q = 0; q < ROWS; ++q)
-      if (rv[q] && lv) m[q] += ps[(row0 + q) * R + l];
-  }
-  __syncthreads();
-  // unit factors: each thread rescales the entries it staged (no other thread reads them yet)
-  for (int e = tid; e < RR; e += nthr) {
-    const int i = e / R, k = e - i * R;
-    const double v = LB[e];
-    LF[k * R + i] = i > k ? v * invd[k] : 0.0;
-    LB[e] = k < i ? v * invd[i] : 0.0;
+    };
+    copy(LF, a.pack, npk);
+    copy(Gs, a.gamma, RR);
+    if (a.W) copy(Ws, a.W, RR);
   }
   __syncthreads();
 
+  double* bv = vb + w * 3 * 64;
   const int st = *a.status;
-  if (a.W) {
+  if (a.W) {  // M~ += A_old W
+    bv[l] = ao;
+    __builtin_amdgcn_wave_barrier();
     for (int j0 = 0; j0 < R; j0 += UB) {
-      double wv[UB];
-#pragma unroll
-      for (int u = 0; u < UB; ++u) wv[u] = (j0 + u < R && lv) ? Ws[(j0 + u) * R + lc] : 0.0;
+      double wv[UB], av[UB];
 #pragma unroll
       for (int u = 0; u < UB; ++u) {
-        if (j0 + u < R) {
-#pragma unroll
-          for (int q = 0; q < ROWS; ++q) m[q] = fma(bcast(ao[q], j0 + u), wv[u], m[q]);
-        }
+        const int j = min(j0 + u, R - 1);
+        wv[u] = Ws[j * R + lc];
+        av[u] = j0 + u < R ? bv[j] : 0.0;
       }
+#pragma unroll
+      for (int u = 0; u < UB; ++u) m = fma(av[u], wv[u], m);
     }
   }
-  double mo[ROWS];
-#pragma unroll
-  for (int q = 0; q < ROWS; ++q) mo[q] = m[q];
+  const double mo = m;
+  double x;
   if (st != 2) {
     const double dl = lv ? invd[lc] : 0.0;
     for (int j0 = 0; j0 < R; j0 += UB) {            // (L D^-1) y = M~
       double lf[UB];
 #pragma unroll
-      for (int u = 0; u < UB; ++u) lf[u] = (j0 + u < R && lv) ? LF[(j0 + u) * R + lc] : 0.0;
+      for (int u = 0; u < UB; ++u) lf[u] = LF[min(j0 + u, R - 1) * R + lc];
 #pragma unroll
-      for (int u = 0; u < UB; ++u) {
-        if (j0 + u < R) {
-#pragma unroll
-          for (int q = 0; q < ROWS; ++q) m[q] = fma(-lf[u], bcast(m[q], j0 + u), m[q]);
-        }
-      }
+      for (int u = 0; u < UB; ++u)
+        if (j0 + u < R) m = fma(-lf[u], bcast(m, j0 + u), m);
     }
-#pragma unroll
-    for (int q = 0; q < ROWS; ++q) m[q] *= dl;
+    m *= dl;
     for (int j1 = R - 1; j1 >= 0; j1 -= UB) {       // (D^-1 L)^T v = D^-1 y, descending
       double lb[UB];
 #pragma unroll
-      for (int u = 0; u < UB; ++u) lb[u] = (j1 - u >= 0 && lv) ? LB[(j1 - u) * R + lc] : 0.0;
+      for (int u = 0; u < UB; ++u) lb[u] = LB[max(j1 - u, 0) * R + lc];
 #pragma unroll
-      for (int u = 0; u < UB; ++u) {
-        if (j1 - u >= 0) {
-#pragma unroll
-          for (int q = 0; q < ROWS; ++q) m[q] = fma(-lb[u], bcast(m[q], j1 - u), m[q]);
-        }
-      }
+      for (int u = 0; u < UB; ++u)
+        if (j1 - u >= 0) m = fma(-lb[u], bcast(m, j1 - u), m);
     }
-#pragma unroll
-    for (int q = 0; q < ROWS; ++q) x[q] = m[q] * dl;
+    x = m * dl;
   } else {
-#pragma unroll
-    for (int q = 0; q < ROWS; ++q) x[q] = ao[q];
+    x = ao;
   }
-  double g[ROWS], hq[ROWS];
-#pragma unroll
-  for (int q = 0; q < ROWS; ++q) g[q] = hq[q] = 0.0;
-  double dx[ROWS];
-#pragma unroll
-  for (int q = 0; q < ROWS; ++q) dx[q] = ao[q] - x[q];
-  for (int j0 = 0; j0 < R; j0 += UB) {   // g = (a_old - a_new) Gamma; h = a_new Gamma (fit)
-    double gv[UB];
-#pragma unroll
-    for (int u = 0; u < UB; ++u) gv[u] = (j0 + u < R && lv) ? Gs[(j0 + u) * R + lc] : 0.0;
+  // g = (a_old - a_new) Gamma; h = a_new Gamma (fit)
+  double g = 0.0, hq = 0.0;
+  bv[64 + l] = lv ? ao - x : 0.0;
+  bv[128 + l] = lv ? x : 0.0;
+  __builtin_amdgcn_wave_barrier();
+  for (int j0 = 0; j0 < R; j0 += UB) {
+    double gv[UB], dv[UB], xv[UB];
 #pragma unroll
     for (int u = 0; u < UB; ++u) {
-      if (j0 + u < R) {
+      const int j = min(j0 + u, R - 1);
+      const bool in = j0 + u < R;
+      gv[u] = Gs[j * R + lc];
+      dv[u] = in ? bv[64 + j] : 0.0;
+      xv[u] = in ? bv[128 + j] : 0.0;
+    }
 #pragma unroll
-        for (int q = 0; q < ROWS; ++q) {
-          g[q] = fma(bcast(dx[q], j0 + u), gv[u], g[q]);
-          if (a.write_fit) hq[q] = fma(bcast(x[q], j0 + u), gv[u], hq[q]);
-        }
-      }
+    for (int u = 0; u < UB; ++u) {
+      g = fma(dv[u], gv[u], g);
+      hq = fma(xv[u], gv[u], hq);
     }
   }
   double v[NPART] = {0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int q = 0; q < ROWS; ++q) {
-    const int64_t off = (row0 + q) * R + l;
-    if (rv[q] && lv) {
-      const double ref = a.Aref ? rf[q] : ao[q];
-      const double d = x[q] - ref;
-      a.A[off] = x[q];
-      if (a.dA) a.dA[off] = d;
-      v[0] = fma(g[q], g[q], v[0]);
-      v[1] = fma(d, d, v[1]);
-      v[2] = fma(x[q], x[q], v[2]);
-      v[3] = fma(mo[q], x[q], v[3]);
-      v[4] = fma(x[q], hq[q], v[4]);
-    }
+  if (ok) {
+    const double ref = a.Aref ? rf : ao;
+    const double d = x - ref;
+    a.A[off] = x;
+    if (a.dA) a.dA[off] = d;
+    v[0] = g * g;
+    v[1] = d * d;
+    v[2] = x * x;
+    v[3] = mo * x;
+    v[4] = a.write_fit ? x * hq : 0.0;
   }
 #pragma unroll
   for (int c = 0; c < NPART; ++c) v[c] = wsum(v[c]);
@@ -314,54 +302,77 @@ __global__ __launch_bounds__(SOLVE_WAVES * 64) void k_solve_fused(FusedSolveArgs
 }
 
 // Grams of the updated factor on the matrix cores: S = A^T A and, in PP sweeps,
-// U = A^T dA.  One workgroup of GRAM_WAVES waves per 16 x 16 output tile (grid.y selects
-// S or U); each wave takes GRAM_UNROLL groups of 4 rows at a time, its MFMA operands
-// loaded straight from memory (f64 16x16x4: lane l supplies A[y0 + l/16][r0 + l%16] and
-// B[y0 + l/16][c0 + l%16]; accumulator register v holds tile row 4v + l/16, column
-// l%16).  Block (0, 0) also reduces the solve's per-block partials into the sweep
-// record (and the fit).
-constexpr int GRAM_WAVES = 4;
-constexpr int GRAM_UNROLL = 8;
+// U = A^T dA.  One workgroup of GRAM_WAVES waves per 16 x 16 output tile, computing the
+// tile of S and of U from one read of A's tile columns; each wave takes GRAM_U groups of
+// 4 rows at a time and loads the next groups before the current matrix-core steps
+// (f64 16x16x4: lane l supplies A[y0 + l/16][r0 + l%16] and B[y0 + l/16][c0 + l%16];
+// accumulator register v holds tile row 4v + l/16, column l%16).  Block 0 also reduces
+// the solve's per-block partials into the sweep record (and the fit).
+constexpr int GRAM_WAVES = 8;
+constexpr int GRAM_U = 4;
 
 __global__ __launch_bounds__(GRAM_WAVES * 64) void k_gram_tiles(GramArgs a) {
-  __shared__ double racc[GRAM_WAVES * 4 * 64];
+  __shared__ double racc[GRAM_WAVES * 2 * 4 * 64];
   if (a.gate && *a.gate == 0) return;
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63;
   const int R = a.R;
   const int NBR = (R + 15) / 16;
   const int r0 = (blockIdx.x / NBR) * 16, c0 = (blockIdx.x % NBR) * 16;
-  const double* B = blockIdx.y ? a.dA : a.A;
-  double* out = blockIdx.y ? a.U_out : a.S_out;
+  const bool has_u = a.dA != nullptr;
   const int ky = l >> 4, cc = l & 15;
   const bool oka = r0 + cc < R, okb = c0 + cc < R;
-  d4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t y0 = (int64_t)w * 4 * GRAM_UNROLL; y0 < a.rows;
-       y0 += (int64_t)4 * GRAM_UNROLL * GRAM_WAVES) {
-    double xa[GRAM_UNROLL], xb[GRAM_UNROLL];
+  const int64_t rows = a.rows;
+  d4 accS = {0.0, 0.0, 0.0, 0.0}, accU = {0.0, 0.0, 0.0, 0.0};
+  double xa[GRAM_U], xb[GRAM_U], xd[GRAM_U];
+  auto load = [&](int64_t y0, double (&va)[GRAM_U], double (&vb)[GRAM_U], double (&vd)[GRAM_U]) {
 #pragma unroll
-    for (int u = 0; u < GRAM_UNROLL; ++u) {
+    for (int u = 0; u < GRAM_U; ++u) {
       const int64_t y = y0 + 4 * u + ky;
-      xa[u] = (y < a.rows && oka) ? a.A[y * R + r0 + cc] : 0.0;
-      xb[u] = (y < a.rows && okb) ? B[y * R + c0 + cc] : 0.0;
+      const bool in = y < rows;
+      va[u] = (in && oka) ? a.A[y * R + r0 + cc] : 0.0;
+      vb[u] = (in && okb) ? a.A[y * R + c0 + cc] : 0.0;
+      vd[u] = (in && okb && has_u) ? a.dA[y * R + c0 + cc] : 0.0;
     }
+  };
+  const int64_t step = (int64_t)4 * GRAM_U * GRAM_WAVES;
+  int64_t y0 = (int64_t)w * 4 * GRAM_U;
+  load(y0, xa, xb, xd);
+  for (; y0 < rows; y0 += step) {
+    double na[GRAM_U], nb[GRAM_U], nd[GRAM_U];
+    const bool more = y0 + step < rows;
+    if (more) load(y0 + step, na, nb, nd);
 #pragma unroll
-    for (int u = 0; u < GRAM_UNROLL; ++u)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u], xb[u], acc, 0, 0, 0);
+    for (int u = 0; u < GRAM_U; ++u) {
+      accS = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u], xb[u], accS, 0, 0, 0);
+      if (has_u) accU = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u], xd[u], accU, 0, 0, 0);
+    }
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < GRAM_U; ++u) {
+        xa[u] = na[u];
+        xb[u] = nb[u];
+        xd[u] = nd[u];
+      }
+    }
   }
 #pragma unroll
-  for (int v = 0; v < 4; ++v) racc[(w * 4 + v) * 64 + l] = acc[v];
+  for (int v = 0; v < 4; ++v) {
+    racc[((w * 2 + 0) * 4 + v) * 64 + l] = accS[v];
+    racc[((w * 2 + 1) * 4 + v) * 64 + l] = accU[v];
+  }
   __syncthreads();
-  if (w == 0) {
+  if (w < 2 && (w == 0 || has_u)) {
+    double* out = w ? a.U_out : a.S_out;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      double s = 0.0;
-      for (int q = 0; q < GRAM_WAVES; ++q) s += racc[(q * 4 + v) * 64 + l];
+      double sum = 0.0;
+      for (int q = 0; q < GRAM_WAVES; ++q) sum += racc[((q * 2 + w) * 4 + v) * 64 + l];
       const int r = r0 + 4 * v + (l >> 4), c = c0 + (l & 15);
-      if (r < R && c < R) out[r * R + c] = s;
+      if (r < R && c < R) out[r * R + c] = sum;
     }
   }
-  if (blockIdx.x != 0 || blockIdx.y != 0) return;
+  if (blockIdx.x != 0) return;
   // record for this mode from the solve's per-block partials
   __shared__ double sums[NPART];
   if (w == 0) {
@@ -439,13 +450,13 @@ hipError_t launch_pp_gate(void* rec, int N, double eps, int* gate, hipStream_t s
 
 hipError_t launch_gram_tiles(const GramArgs& a, hipStream_t s) {
   const int NBR = (a.R + 15) / 16;
-  hipLaunchKernelGGL(k_gram_tiles, dim3(NBR * NBR, a.dA ? 2 : 1), dim3(GRAM_WAVES * 64), 0, s, a);
+  hipLaunchKernelGGL(k_gram_tiles, dim3(NBR * NBR), dim3(GRAM_WAVES * 64), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_solve_fused(const FusedSolveArgs& a, hipStream_t s) {
   const int R = a.R;
-  const size_t lds = (4 * (size_t)R * R + R) * sizeof(double);
+  const size_t lds = (4 * (size_t)R * R + R + (size_t)SOLVE_WAVES * 3 * 64) * sizeof(double);
   hipError_t e = allow_lds(k_solve_fused, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_solve_fused, dim3(solve_fused_blocks(a.rows)), dim3(SOLVE_WAVES * 64), lds,

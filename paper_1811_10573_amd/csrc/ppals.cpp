@@ -109,7 +109,7 @@ struct ppals_plan {
   size_t off_M = 0;                    // FP64 max_s x R
   size_t off_Mp = 0, off_Ap = 0, off_dA = 0;  // FP64 sum_s x R each
   size_t off_U = 0;                    // N R^2
-  size_t off_gamma = 0, off_L = 0, off_W = 0;
+  size_t off_gamma = 0, off_L = 0, off_W = 0, off_pack = 0;
   size_t off_rowpart = 0;              // max_s x 4
   size_t off_scal = 0;                 // 64 doubles
   size_t off_status = 0;               // ints
@@ -488,6 +488,7 @@ void layout(ppals_plan* p) {
   p->off_U = take((size_t)p->N * R * R * 8);
   p->off_gamma = take((size_t)R * R * 8);
   p->off_L = take((size_t)R * R * 8);
+  p->off_pack = take((2 * (size_t)R * R + R) * 8);
   p->off_W = take((size_t)R * R * 8);
   p->off_rowpart = take((size_t)p->max_s * 4 * 8);
   p->off_scal = take(64 * 8);
@@ -799,6 +800,7 @@ HeadArgs head_args(const Ctx& c, double* S, int n, int pp) {
   h.gamma = c.at<double>(p->off_gamma);
   h.L = c.at<double>(p->off_L);
   h.W = c.at<double>(p->off_W);
+  h.pack = c.at<double>(p->off_pack);
   h.status = c.at<int>(p->off_status);
   h.gate = p->cur_gate;
   return h;
@@ -863,7 +865,7 @@ ppals_status solve_fused(const Ctx& c, double* const* A, int n, const double* ba
   a.nslots = nslots;
   a.slot_stride = p->dims[n] * (int64_t)p->R;
   a.W = (pp && p->second_order) ? c.at<double>(p->off_W) : nullptr;
-  a.L = c.at<double>(p->off_L);
+  a.pack = c.at<double>(p->off_pack);
   a.gamma = c.at<double>(p->off_gamma);
   a.A = A[n];
   a.Aref = pp ? c.Ap(n) : nullptr;

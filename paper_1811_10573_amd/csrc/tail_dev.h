@@ -91,7 +91,8 @@ __device__ inline bool chol_wave(double* Lm, int R, int LS) {
 //  B. the panel in registers, right-looking, lane i holding row i: pivot s = t_cc
 //     (broadcast from lane c), r = 1/sqrt(s) from the hardware estimate refined by two
 //     Newton steps, l_cc = s r, l_ic = t_ic r, then the panel's later columns are
-//     updated with the new column.
+//     updated with the new column (the next one through a lane broadcast, the others
+//     through the LDS buffer cb of 2 x 64 entries, alternating between its halves).
 // Returns false at the first pivot that is not positive (or not finite).
 constexpr int CH64_LS = 65;
 
@@ -106,7 +107,7 @@ __device__ __forceinline__ double rsqrt_refined(double s) {
   return y;
 }
 
-__device__ __forceinline__ bool chol_wave64(double* Lm, int R) {
+__device__ __forceinline__ bool chol_wave64(double* Lm, double* cb, int R) {
   constexpr int LS = CH64_LS;
   const int l = threadIdx.x & 63;
   const int i16 = l & 15, k4 = l >> 4;
@@ -138,19 +139,30 @@ __device__ __forceinline__ bool chol_wave64(double* Lm, int R) {
     double t[16];
 #pragma unroll
     for (int c = 0; c < 16; ++c) t[c] = Lm[l * LS + j0 + c];
+    // One basic block per panel (no branches), so the scheduler can overlap a column's
+    // LDS round trip with the next column's pivot chain.  Columns past R see a unit
+    // pivot on zero padding and leave the rows below R unchanged.
+    bool bad = false;
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
       const int col = j0 + c;
-      if (col < R) {
-        const double s = bcast(t[c], col);
-        if (!(s > 0.0) || !isfinite(s)) return false;
-        const double r = rsqrt_refined(s);
-        const double lc = (l == col) ? s * r : t[c] * r;
-        t[c] = lc;
+      const bool live = col < R;
+      double s = bcast(t[c], col);
+      const bool good = s > 0.0 && s < INFINITY;
+      bad = bad || (live && !good);
+      s = (live && good) ? s : 1.0;
+      const double r = rsqrt_refined(s);
+      const double lc = (l == col) ? s * r : t[c] * r;
+      t[c] = lc;
+      if (c + 1 < 16) t[c + 1] = fma(-lc, bcast(lc, col + 1), t[c + 1]);
+      if (c + 2 < 16) {
+        double* cbc = cb + 64 * (c & 1);
+        cbc[l] = lc;
 #pragma unroll
-        for (int c2 = c + 1; c2 < 16; ++c2) t[c2] = fma(-lc, bcast(lc, j0 + c2), t[c2]);
+        for (int c2 = c + 2; c2 < 16; ++c2) t[c2] = fma(-lc, cbc[j0 + c2], t[c2]);
       }
     }
+    if (bad) return false;
 #pragma unroll
     for (int c = 0; c < 16; ++c)
       if (j0 + c <= l) Lm[l * LS + j0 + c] = t[c];
