@@ -175,7 +175,9 @@ hipError_t launch_solve_fused(const FusedSolveArgs& a, hipStream_t s);
 int solve_fused_blocks(int64_t rows);
 hipError_t launch_gram_tiles(const GramArgs& a, hipStream_t s);
 hipError_t launch_set_int(int* p, int v, hipStream_t s);
-hipError_t launch_pp_gate(void* rec, int N, double eps, int* gate, hipStream_t s);
+hipError_t launch_pp_gate_ring(void* rec, int N, double eps, int* gate, void* ring, int* ctr,
+                               hipStream_t s);
+hipError_t launch_rec_store(const void* rec, void* ring, const int* ctr, hipStream_t s);
 
 // learned PP controller (k_mlp.hip)
 constexpr int MLP_MAX_IN = 16;

@@ -48,6 +48,7 @@ __global__ __launch_bounds__(HEAD_THREADS) void k_head(HeadArgs h) {
   __shared__ double cb[128];
   __shared__ double red[HEAD_THREADS / 64];
   if (h.gate && *h.gate == 0) return;
+  __builtin_amdgcn_s_setprio(3);  // latency-bound: first in line for issue beside streaming kernels
   const int tid = threadIdx.x;
   const int R = h.R, RR = R * R;
   const int n = h.n;
@@ -138,7 +139,7 @@ __global__ __launch_bounds__(HEAD_THREADS) void k_head(HeadArgs h) {
 // Fused right-hand-side assembly + solve + per-block norm partials.
 // Block: SOLVE_WAVES waves, one row each.
 // ---------------------------------------------------------------------------
-constexpr int SOLVE_WAVES = 8;
+constexpr int SOLVE_WAVES = 4;
 constexpr int SOLVE_BR = SOLVE_WAVES;               // rows per block
 constexpr int NPART = 5;                            // per-block norm partials
 
@@ -156,6 +157,7 @@ __global__ __launch_bounds__(SOLVE_WAVES * 64) void k_solve_fused(FusedSolveArgs
   constexpr int UB = 8;  // steps whose LDS operands are read together
   extern __shared__ double sm[];
   if (a.gate && *a.gate == 0) return;
+  __builtin_amdgcn_s_setprio(3);
   const int R = a.R, RR = R * R;
   const int npk = 2 * RR + R;
   double* LF = sm;               // LF[j][k] = L[k][j] / L[j][j] for k > j, else 0
@@ -314,6 +316,7 @@ constexpr int GRAM_U = 4;
 __global__ __launch_bounds__(GRAM_WAVES * 64) void k_gram_tiles(GramArgs a) {
   __shared__ double racc[GRAM_WAVES * 2 * 4 * 64];
   if (a.gate && *a.gate == 0) return;
+  __builtin_amdgcn_s_setprio(3);
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63;
   const int R = a.R;
@@ -428,23 +431,51 @@ __global__ void k_set_int(int* p, int v) {
 }
 
 // Gate of a PP-approximated sweep enqueued ahead of the host's decision (Algorithm 3's
-// test on the device): it stays open while every relative change of the sweep before
-// is below eps, closes otherwise and stays closed.  The sweep kind of the record tells
-// the host which of the enqueued sweeps ran (-1: skipped).
-__global__ void k_pp_gate(ppals_sweep_record* rec, int N, double eps, int* gate) {
+// test on the device), the first node of the graph such sweeps replay: the gate stays open
+// while every relative change of the sweep before is below eps, closes otherwise and stays
+// closed; the sweep kind of the record tells the host which of the enqueued sweeps ran
+// (-1: skipped).  It first files the record of the sweep before (or of the host's last
+// sweep, for the first replay) in ring[*ctr] and advances *ctr, so that the host reads all
+// the records of the enqueued sweeps with one copy.
+__global__ void k_pp_gate_ring(ppals_sweep_record* rec, int N, double eps, int* gate,
+                               ppals_sweep_record* ring, int* ctr) {
+  constexpr int W = (int)(sizeof(ppals_sweep_record) / sizeof(int));
+  const int k = *ctr;
+  const int* src = (const int*)rec;
+  int* dst = (int*)(ring + k);
+  for (int i = threadIdx.x; i < W; i += blockDim.x) dst[i] = src[i];
+  __syncthreads();
   if (threadIdx.x != 0) return;
   bool open = *gate != 0;
   for (int n = 0; n < N; ++n) open = open && rec->rel_change[n] < eps;
   *gate = open ? 1 : 0;
   rec->sweep_kind = open ? PPALS_SWEEP_PP_APPROX : -1;
+  *ctr = k + 1;
+}
+
+// Files the record of the last enqueued sweep in ring[*ctr].
+__global__ void k_rec_store(const ppals_sweep_record* rec, ppals_sweep_record* ring, const int* ctr) {
+  constexpr int W = (int)(sizeof(ppals_sweep_record) / sizeof(int));
+  const int k = *ctr;
+  const int* src = (const int*)rec;
+  int* dst = (int*)(ring + k);
+  for (int i = threadIdx.x; i < W; i += blockDim.x) dst[i] = src[i];
+}
+
+hipError_t launch_pp_gate_ring(void* rec, int N, double eps, int* gate, void* ring, int* ctr,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_pp_gate_ring, dim3(1), dim3(64), 0, s, (ppals_sweep_record*)rec, N, eps, gate,
+                     (ppals_sweep_record*)ring, ctr);
+  return hipGetLastError();
+}
+hipError_t launch_rec_store(const void* rec, void* ring, const int* ctr, hipStream_t s) {
+  hipLaunchKernelGGL(k_rec_store, dim3(1), dim3(64), 0, s, (const ppals_sweep_record*)rec,
+                     (ppals_sweep_record*)ring, ctr);
+  return hipGetLastError();
 }
 
 hipError_t launch_set_int(int* p, int v, hipStream_t s) {
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, p, v);
-  return hipGetLastError();
-}
-hipError_t launch_pp_gate(void* rec, int N, double eps, int* gate, hipStream_t s) {
-  hipLaunchKernelGGL(k_pp_gate, dim3(1), dim3(64), 0, s, (ppals_sweep_record*)rec, N, eps, gate);
   return hipGetLastError();
 }
 

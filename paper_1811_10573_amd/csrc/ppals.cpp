@@ -117,7 +117,9 @@ struct ppals_plan {
   size_t off_ppart = 0, sz_ppart = 0;  // PP partial slots
   size_t off_blockpart = 0;  // fused-solve per-block partial sums
   size_t off_Mx = 0, off_Mt = 0, off_errsum = 0;  // right-hand-side error measurement
-  size_t off_gate = 0;                              // gate of PP sweeps enqueued ahead
+  size_t off_gate = 0;                              // gate of PP sweeps enqueued ahead (int),
+                                                    // then the ring position (int, +16 bytes)
+  size_t off_ring = 0;                              // records of sweeps enqueued ahead
   const int* cur_gate = nullptr;  // set while the gated PP sweep is being captured
   bool fast = false;                   // rank <= 64: fused head/solve tail
   hipStream_t aux = nullptr;           // stream for the head kernel (default priority)
@@ -138,6 +140,14 @@ struct ppals_plan {
   hipStream_t cap_stream = nullptr;  // capture stream (default priority)
   hipGraph_t pp_graph = nullptr;
   hipGraphExec_t pp_exec = nullptr;
+  // the same sweep behind the device-side threshold test, for sweeps enqueued ahead
+  hipGraph_t la_graph = nullptr;
+  hipGraphExec_t la_exec = nullptr;
+  void* la_ws = nullptr;
+  const void* la_recp = nullptr;
+  const double* la_S = nullptr;
+  const double* la_A[PPALS_MAX_ORDER] = {nullptr};
+  double la_normX2 = 0.0, la_eps = 0.0;
   const void* g_ws = nullptr;
   const void* g_rec = nullptr;
   const double* g_S = nullptr;
@@ -502,6 +512,7 @@ void layout(ppals_plan* p) {
   p->off_Mt = take((size_t)p->max_s * R * 8);
   p->off_errsum = take((size_t)2 * PPALS_MAX_ORDER * 8);
   p->off_gate = take(64);
+  p->off_ring = take(sizeof(ppals_sweep_record) * (ppals_plan::kLookahead + 1));
   for (auto& b : p->bufs) b.off = take(b.bytes);
   p->ws_bytes = off;
 }
@@ -1106,12 +1117,10 @@ ppals_status do_pp_sweep(ppals_plan* p, double* const* A, double* S, double norm
 // its own, since the caller's may be the null stream) and replays the graph; the graph
 // holds kernels and stream dependencies only.  It is rebuilt whenever the workspace,
 // factor, Gram or record pointers or ||X||^2 change.  Every kernel of the captured sweep
-// reads a device gate and does nothing when it is closed, so that sweeps can be enqueued
-// ahead of the host's decision with the threshold test taken on the device.
-// open_gate: the host has decided this sweep (the gate is set open before the replay);
-// otherwise the caller has enqueued the device-side gate test before it.
+// reads a device gate and does nothing when it is closed (the host opens it before this
+// replay); la_sweep_graphed replays the same sweep behind the device-side test.
 ppals_status pp_sweep_graphed(ppals_plan* p, double* const* A, double* S, double normX2, void* ws,
-                              ppals_sweep_record* rec, hipStream_t s, bool open_gate = true) {
+                              ppals_sweep_record* rec, hipStream_t s) {
   bool same = p->pp_exec && p->g_ws == ws && p->g_rec == rec && p->g_S == S &&
               p->g_normX2 == normX2;
   for (int n = 0; same && n < p->N; ++n) same = p->g_A[n] == A[n];
@@ -1142,9 +1151,57 @@ ppals_status pp_sweep_graphed(ppals_plan* p, double* const* A, double* S, double
     p->g_normX2 = normX2;
     for (int n = 0; n < p->N; ++n) p->g_A[n] = A[n];
   }
-  if (open_gate) HIPCHK(launch_set_int((int*)((char*)ws + p->off_gate), 1, s));
+  HIPCHK(launch_set_int((int*)((char*)ws + p->off_gate), 1, s));
   HIPCHK(hipGraphLaunch(p->pp_exec, s));
-  if (open_gate) p->sweeps_since_build++;
+  p->sweeps_since_build++;
+  return PPALS_OK;
+}
+
+// PP-approximated sweep enqueued ahead of the host's decision, replayed from a graph whose
+// first node takes the threshold test of Algorithm 3 on the device (k_pp_gate_ring, which
+// also files the record before it in the ring); rebuilt when a pointer, ||X||^2 or eps
+// changes.
+ppals_status la_sweep_graphed(ppals_plan* p, double* const* A, double* S, double normX2, void* ws,
+                              ppals_sweep_record* rec, double eps, hipStream_t s) {
+  bool same = p->la_exec && p->la_ws == ws && p->la_recp == rec && p->la_S == S &&
+              p->la_normX2 == normX2 && p->la_eps == eps;
+  for (int n = 0; same && n < p->N; ++n) same = p->la_A[n] == A[n];
+  if (!same) {
+    if (p->la_exec) (void)hipGraphExecDestroy(p->la_exec);
+    if (p->la_graph) (void)hipGraphDestroy(p->la_graph);
+    p->la_exec = nullptr;
+    p->la_graph = nullptr;
+    if (!p->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    int* gate = (int*)((char*)ws + p->off_gate);
+    ppals_status st = PPALS_OK;
+    const hipError_t le = launch_pp_gate_ring(rec, p->N, eps, gate, (char*)ws + p->off_ring,
+                                              gate + 4, p->cap_stream);
+    const int before = p->sweeps_since_build;
+    if (le == hipSuccess) {
+      p->cur_gate = gate;
+      st = do_pp_sweep(p, A, S, normX2, ws, rec, p->cap_stream);
+      p->cur_gate = nullptr;
+    }
+    p->sweeps_since_build = before;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+    if (le != hipSuccess || st != PPALS_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      if (le != hipSuccess) return fail(PPALS_E_HIP, std::string("capture: ") + hipGetErrorString(le));
+      return st;
+    }
+    if (e != hipSuccess) return fail(PPALS_E_HIP, std::string("capture: ") + hipGetErrorString(e));
+    p->la_graph = g;
+    HIPCHK(hipGraphInstantiate(&p->la_exec, g, nullptr, nullptr, 0));
+    p->la_ws = ws;
+    p->la_recp = rec;
+    p->la_S = S;
+    p->la_normX2 = normX2;
+    p->la_eps = eps;
+    for (int n = 0; n < p->N; ++n) p->la_A[n] = A[n];
+  }
+  HIPCHK(hipGraphLaunch(p->la_exec, s));
   return PPALS_OK;
 }
 
@@ -1237,6 +1294,8 @@ void ppals_plan_destroy(ppals_plan* p) {
   if (p->pinned_rec) (void)hipHostFree(p->pinned_rec);
   if (p->pp_exec) (void)hipGraphExecDestroy(p->pp_exec);
   if (p->pp_graph) (void)hipGraphDestroy(p->pp_graph);
+  if (p->la_exec) (void)hipGraphExecDestroy(p->la_exec);
+  if (p->la_graph) (void)hipGraphDestroy(p->la_graph);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   if (p->la_rec) (void)hipHostFree(p->la_rec);
   for (int k = 0; k < ppals_plan::kLookahead; ++k) {
@@ -1594,16 +1653,19 @@ ppals_status ppals_run(ppals_plan* p, const void* X, const void* Xb, double* con
         if (!p->la_e1[k]) HIPCHK(hipEventCreate(&p->la_e1[k]));
       }
       int* gate = (int*)((char*)ws + p->off_gate);
+      ppals_sweep_record* ring = (ppals_sweep_record*)((char*)ws + p->off_ring);
       HIPCHK(launch_set_int(gate, 1, s));
+      HIPCHK(launch_set_int(gate + 4, 0, s));
       for (int k = 0; k < L; ++k) {
         if (sweep_ms) HIPCHK(hipEventRecord(p->la_e0[k], s));
-        HIPCHK(launch_pp_gate(rec_dev, p->N, eps, gate, s));
-        st = pp_sweep_graphed(p, A, S, normX2, ws, rec_dev, s, /*open_gate=*/false);
+        st = la_sweep_graphed(p, A, S, normX2, ws, rec_dev, eps, s);
         if (st != PPALS_OK) return st;
         if (sweep_ms) HIPCHK(hipEventRecord(p->la_e1[k], s));
-        HIPCHK(hipMemcpyAsync(p->la_rec + k, rec_dev, sizeof(ppals_sweep_record),
-                              hipMemcpyDeviceToHost, s));
       }
+      // ring[0] holds the record before the first enqueued sweep, ring[k + 1] that of sweep k
+      HIPCHK(launch_rec_store(rec_dev, ring, gate + 4, s));
+      HIPCHK(hipMemcpyAsync(p->la_rec, ring + 1, sizeof(ppals_sweep_record) * L,
+                            hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       int ran = 0;
       while (ran < L && p->la_rec[ran].sweep_kind == PPALS_SWEEP_PP_APPROX) ++ran;

@@ -140,26 +140,26 @@ __device__ __forceinline__ bool chol_wave64(double* Lm, double* cb, int R) {
 #pragma unroll
     for (int c = 0; c < 16; ++c) t[c] = Lm[l * LS + j0 + c];
     // One basic block per panel (no branches), so the scheduler can overlap a column's
-    // LDS round trip with the next column's pivot chain.  Columns past R see a unit
-    // pivot on zero padding and leave the rows below R unchanged.
+    // LDS round trip with the next columns' pivot chains: the next two entries of the
+    // new column reach the rows that need them through lane broadcasts, the others
+    // through LDS.  The pivot test is off the chain; a column past R (only in the last
+    // panel) meets zero padding and leaves rows below R unchanged.
     bool bad = false;
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
       const int col = j0 + c;
-      const bool live = col < R;
-      double s = bcast(t[c], col);
-      const bool good = s > 0.0 && s < INFINITY;
-      bad = bad || (live && !good);
-      s = (live && good) ? s : 1.0;
+      const double s = bcast(t[c], col);
+      bad = bad || (col < R && !(s > 0.0 && s < INFINITY));
       const double r = rsqrt_refined(s);
       const double lc = (l == col) ? s * r : t[c] * r;
       t[c] = lc;
       if (c + 1 < 16) t[c + 1] = fma(-lc, bcast(lc, col + 1), t[c + 1]);
-      if (c + 2 < 16) {
+      if (c + 2 < 16) t[c + 2] = fma(-lc, bcast(lc, col + 2), t[c + 2]);
+      if (c + 3 < 16) {
         double* cbc = cb + 64 * (c & 1);
         cbc[l] = lc;
 #pragma unroll
-        for (int c2 = c + 2; c2 < 16; ++c2) t[c2] = fma(-lc, cbc[j0 + c2], t[c2]);
+        for (int c2 = c + 3; c2 < 16; ++c2) t[c2] = fma(-lc, cbc[j0 + c2], t[c2]);
       }
     }
     if (bad) return false;
