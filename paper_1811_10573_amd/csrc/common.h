@@ -67,6 +67,7 @@ struct TtvJob {
 // split staged in LDS.
 enum { TTV_SCALAR = 0, TTV_SLAB = 1, TTV_ROWS = 2 };
 constexpr int TTV_VTHREADS = 256;
+constexpr int TTV_SLAB_PB = 2;  // slabs per TTV_SLAB workgroup (they share the weight loads)
 
 #define PP_MAX_JOBS 8
 // Threads per multi-TTV workgroup: 12 waves, so at most two workgroups (six waves per
@@ -129,6 +130,7 @@ struct HeadArgs {
   int N, R;
   int n;              // mode to prepare
   int pp, second_order;
+  int gamma_ready;    // Gamma^(n) (and W^(n)) already formed by the Gram kernel of mode n-1
   double* S;          // N x R x R
   double* U;          // N x R x R
   double* gamma;
@@ -151,6 +153,12 @@ struct GramArgs {
   int write_fit, sweep_kind;
   double normX2;
   const int* gate;         // if set and *gate == 0 the launch does nothing
+  // optional: Gamma^(next) and W^(next) of the following mode, tile by tile (gamma_out NULL: off)
+  int N, next, wterm;
+  const double* S_all;     // N x R x R (the slot of this mode is being written)
+  const double* U_all;
+  double* gamma_out;
+  double* W_out;
 };
 struct FusedSolveArgs {
   int R;

@@ -18,6 +18,7 @@
 //     runs on the main stream.
 #include "common.h"
 #include "tail_dev.h"
+#include <algorithm>
 #include "../../include/ppals.h"
 
 namespace ppk {
@@ -59,7 +60,24 @@ __global__ __launch_bounds__(HEAD_THREADS) void k_head(HeadArgs h) {
   }
   const int row = tid >> 2, c0 = tid & 3;
   double dmax = 0.0;
-  if (row < R) {
+  if (h.gamma_ready) {
+    if (row < R) {
+      double gv[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int c = c0 + 4 * j;
+        gv[j] = h.gamma[row * R + (c < R ? c : 0)];
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int c = c0 + 4 * j;
+        if (c < R) {
+          Lm[row * CH64_LS + c] = gv[j];
+          if (row == c) dmax = fmax(dmax, gv[j]);
+        }
+      }
+    }
+  } else if (row < R) {
     for (int j0 = 0; c0 + 4 * j0 < R; j0 += CB) {
       double sv[CB][NO], uv[CB][NO];
 #pragma unroll
@@ -119,7 +137,7 @@ __global__ __launch_bounds__(HEAD_THREADS) void k_head(HeadArgs h) {
     if (tid == 0) h.status[n] = st;
   }
   __syncthreads();
-  // L, and the solve operands: LF[k][i] = L[i][k] / L[k][k] (i > k), LB[i][k] = L[i][k] / L[i][i]
+  // the solve operands: LF[k][i] = L[i][k] / L[k][k] (i > k), LB[i][k] = L[i][k] / L[i][i]
   // (k < i), zero elsewhere, then 1 / L[i][i]
   double* LF = h.pack;
   double* LB = LF + RR;
@@ -127,7 +145,6 @@ __global__ __launch_bounds__(HEAD_THREADS) void k_head(HeadArgs h) {
     const double di = cb[row];
     for (int c = c0; c < R; c += 4) {
       const double v = c <= row ? Lm[row * CH64_LS + c] : 0.0;
-      h.L[row * R + c] = v;
       LF[c * R + row] = row > c ? v * cb[c] : 0.0;
       LB[row * R + c] = c < row ? v * di : 0.0;
     }
@@ -182,15 +199,17 @@ __global__ __launch_bounds__(SOLVE_WAVES * 64) void k_solve_fused(FusedSolveArgs
   double ao = a.A[offc];
   double rf = a.Aref ? a.Aref[offc] : 0.0;
   {
-    double ps[8];
-    int sl = 0;
-    for (; sl + 8 <= a.nslots; sl += 8) {
+    // slot loads issued SLOTB at a time (clamped to the last slot, masked), summed in order
+    constexpr int SLOTB = 32;
+    for (int sl = 0; sl < a.nslots; sl += SLOTB) {
+      double ps[SLOTB];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) ps[u] = a.part[(int64_t)(sl + u) * a.slot_stride + offc];
+      for (int u = 0; u < SLOTB; ++u)
+        ps[u] = a.part[(int64_t)min(sl + u, a.nslots - 1) * a.slot_stride + offc];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) m += ps[u];
+      for (int u = 0; u < SLOTB; ++u)
+        if (sl + u < a.nslots) m += ps[u];
     }
-    for (; sl < a.nslots; ++sl) m += a.part[(int64_t)sl * a.slot_stride + offc];
   }
   m = ok ? m : 0.0;
   ao = ok ? ao : 0.0;
@@ -308,21 +327,29 @@ __global__ __launch_bounds__(SOLVE_WAVES * 64) void k_solve_fused(FusedSolveArgs
 // tile of S and of U from one read of A's tile columns; each wave takes GRAM_U groups of
 // 4 rows at a time and loads the next groups before the current matrix-core steps
 // (f64 16x16x4: lane l supplies A[y0 + l/16][r0 + l%16] and B[y0 + l/16][c0 + l%16];
-// accumulator register v holds tile row 4v + l/16, column l%16).  Block 0 also reduces
-// the solve's per-block partials into the sweep record (and the fit).
-constexpr int GRAM_WAVES = 8;
+// accumulator register v holds tile row 4v + l/16, column l%16).  When asked, each
+// workgroup also forms its tile of Gamma^(next) and W^(next) for the following mode's
+// head, with the other modes' S and U tiles loaded at the start.  Block 0 also reduces the
+// solve's per-block partials into the sweep record (and the fit).
+constexpr int GRAM_WAVES = 16;
 constexpr int GRAM_U = 4;
 
 __global__ __launch_bounds__(GRAM_WAVES * 64) void k_gram_tiles(GramArgs a) {
-  __shared__ double racc[GRAM_WAVES * 2 * 4 * 64];
+  __shared__ double racc[(GRAM_WAVES / 2) * 2 * 4 * 64];
+  __shared__ double tileS[256], tileU[256];
+  extern __shared__ double tileO[];  // the other modes' S and U tiles, (N - 2) x 2 x 256
   if (a.gate && *a.gate == 0) return;
   __builtin_amdgcn_s_setprio(3);
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63;
-  const int R = a.R;
+  const int R = a.R, RR = R * R;
   const int NBR = (R + 15) / 16;
   const int r0 = (blockIdx.x / NBR) * 16, c0 = (blockIdx.x % NBR) * 16;
   const bool has_u = a.dA != nullptr;
+  // this thread's tile entry for Gamma^(next): the other modes' S and U, loaded up front
+  const bool want_g = a.gamma_out != nullptr;
+  const int te_r = r0 + ((tid & 255) >> 4), te_c = c0 + (tid & 15);
+  const bool te_ok = want_g && te_r < R && te_c < R;
   const int ky = l >> 4, cc = l & 15;
   const bool oka = r0 + cc < R, okb = c0 + cc < R;
   const int64_t rows = a.rows;
@@ -341,6 +368,25 @@ __global__ __launch_bounds__(GRAM_WAVES * 64) void k_gram_tiles(GramArgs a) {
   const int64_t step = (int64_t)4 * GRAM_U * GRAM_WAVES;
   int64_t y0 = (int64_t)w * 4 * GRAM_U;
   load(y0, xa, xb, xd);
+  if (want_g) {
+    // the other modes' tiles, in the same round trip as the first operands: thread t takes
+    // entry t % 256 of mode k = t / 256 + 4 j (S and U)
+    // (other mode o = the o-th mode that is neither this one nor the next)
+    const int e = te_ok ? te_r * R + te_c : 0;
+#pragma unroll
+    for (int j = 0; j < (PP_MAXN - 2 + 3) / 4; ++j) {
+      const int o = (tid >> 8) + 4 * j;
+      int k = -1;
+      for (int q = 0, cnt = 0; q < a.N; ++q)
+        if (q != a.mode && q != a.next && cnt++ == o) k = q;
+      if (k >= 0) {
+        const double sv = a.S_all[(int64_t)k * RR + e];
+        const double uv = a.wterm ? a.U_all[(int64_t)k * RR + e] : 0.0;
+        tileO[(o * 2 + 0) * 256 + (tid & 255)] = sv;
+        tileO[(o * 2 + 1) * 256 + (tid & 255)] = uv;
+      }
+    }
+  }
   for (; y0 < rows; y0 += step) {
     double na[GRAM_U], nb[GRAM_U], nd[GRAM_U];
     const bool more = y0 + step < rows;
@@ -359,20 +405,62 @@ __global__ __launch_bounds__(GRAM_WAVES * 64) void k_gram_tiles(GramArgs a) {
       }
     }
   }
+  // two-stage reduction over the waves: the upper half adds into the lower half
+  constexpr int HW = GRAM_WAVES / 2;
+  if (w >= HW) {
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    racc[((w * 2 + 0) * 4 + v) * 64 + l] = accS[v];
-    racc[((w * 2 + 1) * 4 + v) * 64 + l] = accU[v];
+    for (int v = 0; v < 4; ++v) {
+      racc[(((w - HW) * 2 + 0) * 4 + v) * 64 + l] = accS[v];
+      racc[(((w - HW) * 2 + 1) * 4 + v) * 64 + l] = accU[v];
+    }
+  }
+  __syncthreads();
+  if (w < HW) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      racc[((w * 2 + 0) * 4 + v) * 64 + l] += accS[v];
+      racc[((w * 2 + 1) * 4 + v) * 64 + l] += accU[v];
+    }
   }
   __syncthreads();
   if (w < 2 && (w == 0 || has_u)) {
     double* out = w ? a.U_out : a.S_out;
+    double* tile = w ? tileU : tileS;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       double sum = 0.0;
-      for (int q = 0; q < GRAM_WAVES; ++q) sum += racc[((q * 2 + w) * 4 + v) * 64 + l];
-      const int r = r0 + 4 * v + (l >> 4), c = c0 + (l & 15);
+      for (int q = 0; q < HW; ++q) sum += racc[((q * 2 + w) * 4 + v) * 64 + l];
+      const int tr = 4 * v + (l >> 4), tc = l & 15;
+      const int r = r0 + tr, c = c0 + tc;
       if (r < R && c < R) out[r * R + c] = sum;
+      tile[tr * 16 + tc] = sum;
+    }
+  }
+  if (want_g) {
+    __syncthreads();
+    if (te_ok && tid < 256) {
+      // Running sums over the modes k != next (order of k as in the head): P0 = Gamma,
+      // P2 = W (second-order term)
+      double P0 = 1.0, P1 = 0.0, P2 = 0.0;
+      int o = 0;
+      for (int k = 0; k < a.N; ++k) {
+        if (k == a.next) continue;
+        double sk, uk;
+        if (k == a.mode) {
+          sk = tileS[tid];
+          uk = has_u ? tileU[tid] : 0.0;
+        } else {
+          sk = tileO[(o * 2 + 0) * 256 + tid];
+          uk = tileO[(o * 2 + 1) * 256 + tid];
+          ++o;
+        }
+        P2 = fma(P2, sk, P1 * uk);
+        P1 = fma(P1, sk, P0 * uk);
+        P0 *= sk;
+      }
+      const int e = te_r * R + te_c;
+      a.gamma_out[e] = P0;
+      if (a.wterm) a.W_out[e] = P2;
     }
   }
   if (blockIdx.x != 0) return;
@@ -481,7 +569,8 @@ hipError_t launch_set_int(int* p, int v, hipStream_t s) {
 
 hipError_t launch_gram_tiles(const GramArgs& a, hipStream_t s) {
   const int NBR = (a.R + 15) / 16;
-  hipLaunchKernelGGL(k_gram_tiles, dim3(NBR * NBR), dim3(GRAM_WAVES * 64), 0, s, a);
+  const size_t lds = a.gamma_out ? (size_t)std::max(1, a.N - 2) * 2 * 256 * sizeof(double) : 0;
+  hipLaunchKernelGGL(k_gram_tiles, dim3(NBR * NBR), dim3(GRAM_WAVES * 64), lds, s, a);
   return hipGetLastError();
 }
 

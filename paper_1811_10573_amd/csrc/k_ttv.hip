@@ -105,15 +105,18 @@ template <> struct TtvVecT<double> {
 constexpr int TTV_U = 4;                         // vectors in flight per lane
 constexpr int TTV_W = TTV_VTHREADS / 64;         // waves per workgroup
 
-// TTV_SLAB: workgroup (p, split); wave w takes iterations w, w + TTV_W, ... of its split,
-// each covering S = VEC * lanes consecutive elements (a whole number of rank rows), so
-// lane l always holds ranks (VEC l + c) mod R.  Partial sums meet in LDS.
+// TTV_SLAB: workgroup (pair of slabs p, p + 1; split); wave w takes iterations w, w + TTV_W,
+// ... of its split, each covering S = VEC * lanes consecutive elements (a whole number of
+// rank rows), so lane l always holds ranks (VEC l + c) mod R.  The weights share the
+// slabs' flat index and are loaded once for both slabs.  Partial sums meet in LDS.
 template <typename T>
 __device__ __forceinline__ void ttv_slab(const TtvJob& J, int R, int64_t bid, double* red) {
   using TV = TtvVecT<T>;
   constexpr int VEC = TV::VEC;
-  const int64_t p = bid / J.xsplit;
-  const int split = (int)(bid - p * J.xsplit);
+  constexpr int PB = TTV_SLAB_PB;
+  constexpr int U = TTV_U / PB;
+  const int64_t pg = bid / J.xsplit;
+  const int split = (int)(bid - pg * J.xsplit);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int L = J.lanes;
   const int64_t n = J.X * R;
@@ -121,20 +124,25 @@ __device__ __forceinline__ void ttv_slab(const TtvJob& J, int R, int64_t bid, do
   const int64_t niter = n / S;
   const int64_t per = (niter + J.xsplit - 1) / J.xsplit;
   const int64_t it0 = (int64_t)split * per, it1 = min(niter, it0 + per);
-  const T* src = (const T*)J.T + p * n;
-  const double* F = J.F;
-  double acc[VEC];
+  const T* src[PB];
 #pragma unroll
-  for (int c = 0; c < VEC; ++c) acc[c] = 0.0;
+  for (int b = 0; b < PB; ++b) src[b] = (const T*)J.T + min(pg * PB + b, J.P - 1) * n;
+  const double* F = J.F;
+  double acc[PB][VEC];
+#pragma unroll
+  for (int b = 0; b < PB; ++b)
+#pragma unroll
+    for (int c = 0; c < VEC; ++c) acc[b][c] = 0.0;
   if (lane < L) {
     int64_t it = it0 + w;
-    for (; it + (TTV_U - 1) * TTV_W < it1; it += TTV_U * TTV_W) {
-      typename TV::V tv[TTV_U];
-      double fv[TTV_U][VEC];
+    for (; it + (U - 1) * TTV_W < it1; it += U * TTV_W) {
+      typename TV::V tv[U][PB];
+      double fv[U][VEC];
 #pragma unroll
-      for (int u = 0; u < TTV_U; ++u) {
+      for (int u = 0; u < U; ++u) {
         const int64_t e = (it + u * TTV_W) * S + VEC * lane;
-        tv[u] = *reinterpret_cast<const typename TV::V*>(src + e);
+#pragma unroll
+        for (int b = 0; b < PB; ++b) tv[u][b] = *reinterpret_cast<const typename TV::V*>(src[b] + e);
         if (J.f_vec) {
 #pragma unroll
           for (int c = 0; c < VEC; c += 2) {
@@ -148,35 +156,48 @@ __device__ __forceinline__ void ttv_slab(const TtvJob& J, int R, int64_t bid, do
         }
       }
 #pragma unroll
-      for (int u = 0; u < TTV_U; ++u) {
-        double t[VEC];
-        TV::get(tv[u], t);
+      for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int c = 0; c < VEC; ++c) acc[c] = fma(t[c], fv[u][c], acc[c]);
-      }
+        for (int b = 0; b < PB; ++b) {
+          double t[VEC];
+          TV::get(tv[u][b], t);
+#pragma unroll
+          for (int c = 0; c < VEC; ++c) acc[b][c] = fma(t[c], fv[u][c], acc[b][c]);
+        }
     }
     for (; it < it1; it += TTV_W) {
       const int64_t e = it * S + VEC * lane;
-      double t[VEC];
-      TV::get(*reinterpret_cast<const typename TV::V*>(src + e), t);
 #pragma unroll
-      for (int c = 0; c < VEC; ++c) acc[c] = fma(t[c], F[e + c], acc[c]);
+      for (int b = 0; b < PB; ++b) {
+        double t[VEC];
+        TV::get(*reinterpret_cast<const typename TV::V*>(src[b] + e), t);
+#pragma unroll
+        for (int c = 0; c < VEC; ++c) acc[b][c] = fma(t[c], F[e + c], acc[b][c]);
+      }
     }
     if (w == 0 && split == J.xsplit - 1) {  // the elements after the last whole iteration
       const int64_t e = niter * S + VEC * lane;
 #pragma unroll
-      for (int c = 0; c < VEC; ++c)
-        if (e + c < n) acc[c] = fma((double)src[e + c], F[e + c], acc[c]);
+      for (int b = 0; b < PB; ++b)
+#pragma unroll
+        for (int c = 0; c < VEC; ++c)
+          if (e + c < n) acc[b][c] = fma((double)src[b][e + c], F[e + c], acc[b][c]);
     }
 #pragma unroll
-    for (int c = 0; c < VEC; ++c) red[w * 256 + VEC * lane + c] = acc[c];
+    for (int b = 0; b < PB; ++b)
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) red[(w * PB + b) * 256 + VEC * lane + c] = acc[b][c];
   }
   __syncthreads();
-  if ((int)threadIdx.x < R) {
-    double sum = 0.0;
-    for (int ww = 0; ww < TTV_W; ++ww)
-      for (int k = threadIdx.x; k < S; k += R) sum += red[ww * 256 + k];
-    J.out[(int64_t)split * J.out_split_stride + p * R + threadIdx.x] = sum;
+  for (int t = threadIdx.x; t < PB * R; t += TTV_VTHREADS) {
+    const int b = t / R, r = t - b * R;
+    const int64_t p = pg * PB + b;
+    if (p < J.P) {
+      double sum = 0.0;
+      for (int ww = 0; ww < TTV_W; ++ww)
+        for (int k = r; k < S; k += R) sum += red[(ww * PB + b) * 256 + k];
+      J.out[(int64_t)split * J.out_split_stride + p * R + r] = sum;
+    }
   }
 }
 
@@ -232,7 +253,7 @@ __device__ __forceinline__ void ttv_rows(const TtvJob& J, int R, int64_t bid, do
 }
 
 __global__ __launch_bounds__(TTV_VTHREADS) void k_ttv_vec(TtvBatch b) {
-  __shared__ double red[TTV_W * 256];
+  __shared__ double red[TTV_W * TTV_SLAB_PB * 256];
   extern __shared__ double fl[];
   if (b.gate && *b.gate == 0) return;
   int64_t bid = blockIdx.x;

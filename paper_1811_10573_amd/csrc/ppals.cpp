@@ -180,7 +180,13 @@ int64_t prod_dims(const ppals_plan* p, const std::vector<int>& modes, int a, int
 
 // Work decomposition of one multi-TTV job (T is P x X x Q x R with elements of es bytes).
 // The vector kinds stream 16-byte vectors; the scalar kind covers every other shape.
-void ttv_config(TtvJob& J, int64_t P, int64_t X, int64_t Q, int R, int es) {
+// Workgroups of the slab kind wanted per multi-TTV launch (the row kind, whose workgroups
+// stream more, takes 2/5 as many).  Measured on 800^3, R = 50: more, smaller workgroups
+// of the slab kind shorten the tail of a launch; one round of large workgroups is slower.
+constexpr int64_t kTtvRound = 3200;
+
+// target: workgroups wanted for this job (slab kind; 2/5 of it for the row kind).
+void ttv_config(TtvJob& J, int64_t P, int64_t X, int64_t Q, int R, int es, int64_t target) {
   memset(&J, 0, sizeof(J));
   J.P = P;
   J.X = X;
@@ -193,9 +199,10 @@ void ttv_config(TtvJob& J, int64_t P, int64_t X, int64_t Q, int R, int es) {
     J.lanes = (64 / g) * g;
     const int64_t niter = X * R / ((int64_t)VEC * J.lanes);
     const int64_t cap = std::max<int64_t>(1, niter / 32);
-    J.xsplit = (int)std::max<int64_t>(1, std::min<int64_t>((1600 + P - 1) / P, cap));
+    const int64_t groups = (P + TTV_SLAB_PB - 1) / TTV_SLAB_PB;
+    J.xsplit = (int)std::max<int64_t>(1, std::min<int64_t>((target + groups - 1) / groups, cap));
     J.jblocks = 1;
-    J.blocks = P * J.xsplit;
+    J.blocks = groups * J.xsplit;
     J.out_split_stride = P * QR;
     return;
   }
@@ -203,7 +210,7 @@ void ttv_config(TtvJob& J, int64_t P, int64_t X, int64_t Q, int R, int es) {
     J.kind = TTV_ROWS;
     J.jblocks = (int)((QR + (int64_t)VEC * TTV_VTHREADS - 1) / ((int64_t)VEC * TTV_VTHREADS));
     const int64_t base = P * J.jblocks;
-    int64_t xsplit = (640 + base - 1) / base;
+    int64_t xsplit = (target * 2 / 5 + base - 1) / base;
     xsplit = std::max<int64_t>(1, std::min<int64_t>(xsplit, X / 8));
     int64_t xs = (X + xsplit - 1) / xsplit;
     xs = std::min<int64_t>(xs, 8192 / R);  // F rows staged in at most 64 KB of LDS
@@ -225,8 +232,8 @@ void ttv_config(TtvJob& J, int64_t P, int64_t X, int64_t Q, int R, int es) {
     J.jblocks = 1;
   }
   const int64_t base = P * J.jblocks;
-  const int64_t target = 512;
-  int64_t xs = (target + base - 1) / base;
+  const int64_t starget = 512;  // 768-thread workgroups of the scalar kernel
+  int64_t xs = (starget + base - 1) / base;
   const int64_t maxs = std::max<int64_t>(1, X / (8 * (int64_t)J.G));
   xs = std::max<int64_t>(1, std::min(xs, maxs));
   J.xsplit = (int)xs;
@@ -294,7 +301,7 @@ int add_ttv(ppals_plan* p, int src_buf, const std::vector<int>& src_modes, int b
   t.P = prod_dims(p, src_modes, 0, bpos);
   t.X = prod_dims(p, src_modes, bpos, bpos + blen);
   t.Q = prod_dims(p, src_modes, bpos + blen, (int)src_modes.size());
-  ttv_config(t.job, t.P, t.X, t.Q, p->R, esize(p->bulk));
+  ttv_config(t.job, t.P, t.X, t.Q, p->R, esize(p->bulk), kTtvRound / 2);
   t.out_buf = out_buf;
   t.out_mode = out_mode;
   for (int i = 0; i < (int)src_modes.size(); ++i)
@@ -453,8 +460,9 @@ void build_pp(ppals_plan* p) {
     for (int i = 0; i < N; ++i) {
       if (i == n) continue;
       TtvJob& J = b.job[nj++];
-      if (i < n) ttv_config(J, 1, p->dims[i], p->dims[n], p->R, esize(p->bulk));  // op (i,n): contract leading
-      else ttv_config(J, p->dims[n], p->dims[i], 1, p->R, esize(p->bulk));        // op (n,i): contract trailing
+      const int64_t tg = kTtvRound / (N - 1);
+      if (i < n) ttv_config(J, 1, p->dims[i], p->dims[n], p->R, esize(p->bulk), tg);  // op (i,n): contract leading
+      else ttv_config(J, p->dims[n], p->dims[i], 1, p->R, esize(p->bulk), tg);        // op (n,i): contract trailing
       J.out_split_stride = p->dims[n] * (int64_t)p->R;
       slots += J.xsplit;
     }
@@ -854,8 +862,25 @@ ppals_status tail_fork(const Ctx& c, const GramArgs* g, const HeadArgs* h) {
   }
   HIPCHK(hipEventRecord(p->ev_fork, c.s));
   HIPCHK(hipStreamWaitEvent(p->aux, p->ev_fork, 0));
-  if (g) HIPCHK(launch_gram_tiles(*g, p->aux));
-  if (h) HIPCHK(launch_head(*h, p->aux));
+  if (g && h) {
+    // the Gram kernel also forms Gamma^(n) and W^(n) of the next mode tile by tile, so the
+    // head starts from them
+    GramArgs g2 = *g;
+    HeadArgs h2 = *h;
+    g2.N = h->N;
+    g2.next = h->n;
+    g2.wterm = h->pp && h->second_order;
+    g2.S_all = h->S;
+    g2.U_all = h->U;
+    g2.gamma_out = h->gamma;
+    g2.W_out = h->W;
+    h2.gamma_ready = 1;
+    HIPCHK(launch_gram_tiles(g2, p->aux));
+    HIPCHK(launch_head(h2, p->aux));
+  } else {
+    if (g) HIPCHK(launch_gram_tiles(*g, p->aux));
+    if (h) HIPCHK(launch_head(*h, p->aux));
+  }
   HIPCHK(hipEventRecord(p->ev_join, p->aux));
   return PPALS_OK;
 }
