@@ -237,28 +237,32 @@ def batch_bench(args, torch, dev):
     print(json.dumps(line), flush=True)
 
 
+# source file of each kernel class whose HBM traffic has a committed counter summary
+TRAFFIC_SOURCE = {"level1_gemm": "k_level1.hip", "pp_correct_ttv": "k_ttv.hip"}
+
+
 def measured_traffic(kernel, tier, shape, rank):
     """HBM bytes per launch from the committed counter summary of this kernel and
     workload, or None when there is none or the kernel source changed since."""
     import re
     fn = os.path.join(ROOT, "profiles", f"{kernel}_{tier}_{'x'.join(map(str, shape))}_r{rank}_counters.md")
-    if not os.path.exists(fn):
+    if kernel not in TRAFFIC_SOURCE or not os.path.exists(fn):
         return None
     txt = open(fn).read()
     m = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
     h = re.search(r"source_sha256:\s*([0-9a-f]{64})", txt)
     if not m or not h:
         return None
-    if h.group(1) != kernel_source_hash():
+    if h.group(1) != kernel_source_hash(TRAFFIC_SOURCE[kernel]):
         return None
     return float(m.group(1))
 
 
-def kernel_source_hash():
+def kernel_source_hash(src="k_level1.hip"):
     import hashlib
     d = os.path.join(ROOT, "paper_1811_10573_amd", "csrc")
     hsh = hashlib.sha256()
-    hsh.update(open(os.path.join(d, "k_level1.hip"), "rb").read())
+    hsh.update(open(os.path.join(d, src), "rb").read())
     return hsh.hexdigest()
 
 
@@ -441,6 +445,17 @@ def main():
                 "frac": achieved / PEAK["hbm_GBs"], "traffic": None, "kernel": name,
                 "launches": st["launches"], "avg_ms": st["avg_ms"],
                 "work_per_launch": st["bytes"] / max(1, st["launches"])}
+    # the PP-correction contractions (HBM-bound) against the HBM peak
+    roof_ttv = None
+    st_t = prof.get("pp_correct_ttv")
+    if st_t and st_t["launches"] > 0 and st_t["bytes"] > 0:
+        ach = st_t["bytes"] / (st_t["total_ms"] * 1e-3) / 1e9
+        roof_ttv = {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
+                    "frac": ach / PEAK["hbm_GBs"],
+                    "traffic": measured_traffic("pp_correct_ttv", args.tier, shape, R),
+                    "kernel": "pp_correct_ttv", "launches": st_t["launches"],
+                    "avg_ms": st_t["avg_ms"],
+                    "work_per_launch": st_t["bytes"] / max(1, st_t["launches"])}
     kernels = {}
     for k, v in prof.items():
         if v["launches"] == 0:
@@ -507,6 +522,7 @@ def main():
             "generator": "device" if args.device_gen else "host",
         },
         "roofline": roof,
+        "roofline_pp_ttv": roof_ttv,
         "cpu_baseline": cpu,
         "pp": {"final_fit_exact": fit_pp, "final_fit_est": recs[-1]["fit_est"], "per_kind": per_kind},
         "dt_als": out_dt,

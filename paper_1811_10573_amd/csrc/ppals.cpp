@@ -140,6 +140,14 @@ struct ppals_plan {
   hipStream_t cap_stream = nullptr;  // capture stream (default priority)
   hipGraph_t pp_graph = nullptr;
   hipGraphExec_t pp_exec = nullptr;
+  // ALS sweeps and PP-initialisation sweeps (operator build + first PP sweep), replayed
+  struct SweepGraph {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t e = nullptr;
+    const void *ws = nullptr, *rec = nullptr, *S = nullptr, *X = nullptr, *Xb = nullptr;
+    const double* A[PPALS_MAX_ORDER] = {nullptr};
+    double normX2 = 0.0;
+  } als_g, init_g;
   // the same sweep behind the device-side threshold test, for sweeps enqueued ahead
   hipGraph_t la_graph = nullptr;
   hipGraphExec_t la_exec = nullptr;
@@ -1182,6 +1190,50 @@ ppals_status pp_sweep_graphed(ppals_plan* p, double* const* A, double* S, double
   return PPALS_OK;
 }
 
+// A host-decided ALS or PP-initialisation sweep replayed from a graph captured on the
+// first call (the sequence of launches is fixed by the plan); rebuilt when a pointer or
+// ||X||^2 changes.  body enqueues the sweep on the stream it is given; host-side plan state
+// it changes is restored after the capture (the caller applies it after each replay).
+template <typename Body>
+ppals_status sweep_graphed(ppals_plan* p, ppals_plan::SweepGraph& G, const void* X, const void* Xb,
+                           double* const* A, double* S, double normX2, void* ws,
+                           ppals_sweep_record* rec, hipStream_t s, Body body) {
+  bool same = G.e && G.ws == ws && G.rec == rec && G.S == S && G.X == X && G.Xb == Xb &&
+              G.normX2 == normX2;
+  for (int n = 0; same && n < p->N; ++n) same = G.A[n] == A[n];
+  if (!same) {
+    if (G.e) (void)hipGraphExecDestroy(G.e);
+    if (G.g) (void)hipGraphDestroy(G.g);
+    G.e = nullptr;
+    G.g = nullptr;
+    if (!p->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    const bool built = p->ops_built;
+    const int since = p->sweeps_since_build;
+    HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    ppals_status st = body(p->cap_stream);
+    p->ops_built = built;
+    p->sweeps_since_build = since;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+    if (st != PPALS_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return fail(PPALS_E_HIP, std::string("capture: ") + hipGetErrorString(e));
+    G.g = g;
+    HIPCHK(hipGraphInstantiate(&G.e, g, nullptr, nullptr, 0));
+    G.ws = ws;
+    G.rec = rec;
+    G.S = S;
+    G.X = X;
+    G.Xb = Xb;
+    G.normX2 = normX2;
+    for (int n = 0; n < p->N; ++n) G.A[n] = A[n];
+  }
+  HIPCHK(hipGraphLaunch(G.e, s));
+  return PPALS_OK;
+}
+
 // PP-approximated sweep enqueued ahead of the host's decision, replayed from a graph whose
 // first node takes the threshold test of Algorithm 3 on the device (k_pp_gate_ring, which
 // also files the record before it in the ring); rebuilt when a pointer, ||X||^2 or eps
@@ -1321,6 +1373,10 @@ void ppals_plan_destroy(ppals_plan* p) {
   if (p->pp_graph) (void)hipGraphDestroy(p->pp_graph);
   if (p->la_exec) (void)hipGraphExecDestroy(p->la_exec);
   if (p->la_graph) (void)hipGraphDestroy(p->la_graph);
+  for (auto* G : {&p->als_g, &p->init_g}) {
+    if (G->e) (void)hipGraphExecDestroy(G->e);
+    if (G->g) (void)hipGraphDestroy(G->g);
+  }
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   if (p->la_rec) (void)hipHostFree(p->la_rec);
   for (int k = 0; k < ppals_plan::kLookahead; ++k) {
@@ -1714,9 +1770,22 @@ ppals_status ppals_run(ppals_plan* p, const void* X, const void* Xb, double* con
       continue;
     }
     if (sweep_ms) HIPCHK(hipEventRecord(e0, s));
+    const bool graph_ok = p->fast && !p->prof;
     if (kind == PPALS_SWEEP_PP_INIT) {
-      st = do_pp_build(p, X, Xb, A, ws, s);
-      if (st == PPALS_OK) st = do_pp_sweep(p, A, S, normX2, ws, rec_dev, s);
+      if (graph_ok) {
+        st = sweep_graphed(p, p->init_g, X, Xb, A, S, normX2, ws, rec_dev, s, [&](hipStream_t cs) {
+          ppals_status r = do_pp_build(p, X, Xb, A, ws, cs);
+          if (r == PPALS_OK) r = do_pp_sweep(p, A, S, normX2, ws, rec_dev, cs);
+          return r;
+        });
+        if (st == PPALS_OK) {
+          p->ops_built = true;
+          p->sweeps_since_build = 1;
+        }
+      } else {
+        st = do_pp_build(p, X, Xb, A, ws, s);
+        if (st == PPALS_OK) st = do_pp_sweep(p, A, S, normX2, ws, rec_dev, s);
+      }
     } else if (kind == PPALS_SWEEP_PP_APPROX) {
       if (!p->ops_built) return fail(PPALS_E_STATE, "replay asks for pp_approx before a build");
       // graph replay unless per-kernel profiling is on (its events are host-side state)
@@ -1724,6 +1793,10 @@ ppals_status ppals_run(ppals_plan* p, const void* X, const void* Xb, double* con
         st = pp_sweep_graphed(p, A, S, normX2, ws, rec_dev, s);
       else
         st = do_pp_sweep(p, A, S, normX2, ws, rec_dev, s);
+    } else if (graph_ok) {
+      st = sweep_graphed(p, p->als_g, X, Xb, A, S, normX2, ws, rec_dev, s, [&](hipStream_t cs) {
+        return do_als_sweep(p, X, Xb, A, S, normX2, ws, rec_dev, cs);
+      });
     } else {
       st = do_als_sweep(p, X, Xb, A, S, normX2, ws, rec_dev, s);
     }
