@@ -266,164 +266,217 @@ __global__ __launch_bounds__(256) void k_b_ttv(const BProb* pr, const BState* st
 }
 
 // ---------------------------------------------------------------------------
-// Per-problem solve of mode n (one workgroup per problem): Gamma = S^(i) * S^(j),
-// W = U^(i) * U^(j) (PP), Cholesky with one diagonal-shift retry, the rows of
-// A^(n) = M Gamma^-1 (plus A^(n) W in the PP right-hand side), dA, norms, and the
-// Grams S^(n) = A^T A and U^(n) = A^T dA on the matrix cores, 64 rows at a time.
+// Per-problem solve of mode n (one workgroup of BSOLVE_WAVES waves per problem):
+// Gamma = S^(i) * S^(j), W = U^(i) * U^(j) (PP), the one-wave Cholesky of the rank <= 64
+// tail (matrix-core panel updates) with one diagonal-shift retry, the unit-triangular
+// factors L D^-1 and D^-1 L, the rows of A^(n) = M Gamma^-1 (plus A^(n) W in the PP
+// right-hand side; BSOLVE_RPW rows per wave at a time, their substitution chains
+// interleaved), dA, norms, and the Grams S^(n) = A^T A and U^(n) = A^T dA on the matrix
+// cores, BSOLVE_CH rows at a time.
 // ---------------------------------------------------------------------------
-constexpr int BSOLVE_CH = 64;
+constexpr int BSOLVE_WAVES = 8;
+constexpr int BSOLVE_CH = 32;
+constexpr int BSOLVE_RPW = BSOLVE_CH / BSOLVE_WAVES;  // rows per wave per chunk
+constexpr int BSOLVE_TPW = 4;                         // Gram tiles per wave (<= 32 tiles)
 
-__global__ __launch_bounds__(256) void k_b_solve(const BProb* pr, BState* st, const BConf* conf,
-                                                 int n) {
+__global__ __launch_bounds__(BSOLVE_WAVES * 64) void k_b_solve(const BProb* pr, BState* st,
+                                                               const BConf* conf, int n) {
+  constexpr int UB = 8;  // steps whose LDS operands are read together
   extern __shared__ double sm[];
-  __shared__ double red[4][4];
+  __shared__ double red[BSOLVE_WAVES][4];
+  __shared__ double cb[128];
+  __shared__ int status;
   const int p = blockIdx.x;
   const int kind = st[p].kind;
   if (kind == BK_NONE) return;
   const BProb& P = pr[p];
-  const int R = P.R, LS = R + 1, RR = R * R;
+  const int R = P.R, RR = R * R;
   const int rows = P.s[n];
   const bool pp = kind != BK_ALS;
   const bool wterm = pp && conf->second_order;
   const int i1 = n == 0 ? 1 : 0, i2 = n == 2 ? 1 : 2;  // the two other modes
-  double* Lm = sm;                         // R x (R+1)
-  double* Ws = Lm + R * LS;                // R x R
-  double* invd = Ws + RR;                  // R
-  double* ca = invd + R;                   // BSOLVE_CH x R: new rows
-  double* cd = ca + BSOLVE_CH * R;         // BSOLVE_CH x R: dA rows
-  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  double* Lm = sm;                          // 64 x 65: Gamma, then L, then D^-1 L
+  double* LF = Lm + 64 * CH64_LS;           // R x R: LF[j][k] = L[k][j] / L[j][j] (k > j)
+  double* Ws = LF + RR;                     // R x R
+  double* invd = Ws + RR;                   // 64
+  double* ca = invd + 64;                   // BSOLVE_CH x R: new rows
+  double* cd = ca + BSOLVE_CH * R;          // BSOLVE_CH x R: dA rows
+  double* bv = cd + BSOLVE_CH * R;          // BSOLVE_WAVES x BSOLVE_RPW x 64 broadcast rows
+  const int tid = threadIdx.x, nthr = blockDim.x, w = tid >> 6, l = tid & 63;
   const bool lv = l < R;
+  const int lc = lv ? l : 0;
   const double* S = P.S;
   const double* U = P.U;
   double dmax = 0.0;
-  for (int e = tid; e < RR; e += 256) {
-    const double g = S[i1 * RR + e] * S[i2 * RR + e];
-    const int r = e / R, c = e - r * R;
-    Lm[r * LS + c] = g;
-    if (r == c) dmax = fmax(dmax, g);
-    Ws[e] = wterm ? U[i1 * RR + e] * U[i2 * RR + e] : 0.0;
+  for (int e = tid; e < 64 * CH64_LS; e += nthr) {
+    const int r = e / CH64_LS, c = e - r * CH64_LS;
+    double g = 0.0;
+    if (r < R && c < R) {
+      g = S[i1 * RR + r * R + c] * S[i2 * RR + r * R + c];
+      if (r == c) dmax = fmax(dmax, g);
+    }
+    Lm[e] = g;
   }
+  for (int e = tid; e < RR; e += nthr) Ws[e] = wterm ? U[i1 * RR + e] * U[i2 * RR + e] : 0.0;
   for (int off = 32; off > 0; off >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, off));
   if (l == 0) red[w][0] = dmax;
   __syncthreads();
-  __shared__ int status;
   if (w == 0) {
     int stv = 0;
-    if (!chol_wave(Lm, R, LS)) {
-      const double mx = fmax(fmax(red[0][0], red[1][0]), fmax(red[2][0], red[3][0]));
-      const double delta = (double)R * 0x1p-52 * mx;
-      for (int e = l; e < RR; e += 64) {
-        const int r = e / R, c = e - r * R;
-        Lm[r * LS + c] = S[i1 * RR + e] * S[i2 * RR + e] + (r == c ? delta : 0.0);
+    for (int attempt = 0;; ++attempt) {
+      if (chol_wave64(Lm, cb, R)) break;
+      if (attempt == 1) {
+        stv = 2;
+        break;
       }
-      stv = chol_wave(Lm, R, LS) ? 1 : 2;
+      double mx = 0.0;
+      for (int q = 0; q < BSOLVE_WAVES; ++q) mx = fmax(mx, red[q][0]);
+      const double delta = (double)R * 0x1p-52 * mx;
+      for (int e = l; e < 64 * CH64_LS; e += 64) {
+        const int r = e / CH64_LS, c = e - r * CH64_LS;
+        Lm[e] = (r < R && c < R) ? S[i1 * RR + r * R + c] * S[i2 * RR + r * R + c] + (r == c ? delta : 0.0)
+                                 : 0.0;
+      }
+      stv = 1;
     }
     if (l == 0) status = stv;
-    if (l < R) invd[l] = 1.0 / Lm[l * LS + l];
+    if (l < R) invd[l] = 1.0 / Lm[l * CH64_LS + l];
   }
   __syncthreads();
   const int stv = status;
-  // Gram tiles owned by this wave: tile index tt = w + 4 * slot over NBR^2 S tiles then
+  // unit factors: LF from L, then D^-1 L in place (strictly lower, zero elsewhere)
+  for (int e = tid; e < RR; e += nthr) {
+    const int i = e / R, k = e - i * R;
+    LF[k * R + i] = i > k ? Lm[i * CH64_LS + k] * invd[k] : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < RR; e += nthr) {
+    const int i = e / R, k = e - i * R;
+    Lm[i * CH64_LS + k] = k < i ? Lm[i * CH64_LS + k] * invd[i] : 0.0;
+  }
+  __syncthreads();
+  // Gram tiles owned by this wave: tt = w + BSOLVE_WAVES * t over NBR^2 S tiles then
   // NBR^2 U tiles
   const int NBR = (R + 15) >> 4;
   const int ntile = NBR * NBR * (pp ? 2 : 1);
-  d4 gacc[8];
+  d4 gacc[BSOLVE_TPW];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) gacc[q] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int t = 0; t < BSOLVE_TPW; ++t) gacc[t] = d4{0.0, 0.0, 0.0, 0.0};
   double nd = 0.0, na = 0.0, nm = 0.0;
   double* An = P.A[n];
   const double* M = P.M;
   const double* Apn = P.Ap[n];
   double* dAn = P.dA[n];
+  double* bw = bv + w * BSOLVE_RPW * 64;
+  const double dl = lv ? invd[lc] : 0.0;
   for (int c0 = 0; c0 < rows; c0 += BSOLVE_CH) {
-    // each wave solves 16 rows of the chunk, two at a time
-    for (int rr = 0; rr < BSOLVE_CH / 4; rr += 2) {
-      double m[2], ao[2], x[2], mo[2];
-      bool rv[2];
+    double m[BSOLVE_RPW], ao[BSOLVE_RPW], x[BSOLVE_RPW];
+    bool rv[BSOLVE_RPW];
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int y = c0 + w * (BSOLVE_CH / 4) + rr + q;
-        rv[q] = y < rows;
-        const bool ok = rv[q] && lv;
-        m[q] = ok ? M[(int64_t)y * R + l] : 0.0;
-        ao[q] = ok ? An[(int64_t)y * R + l] : 0.0;
-      }
-      if (wterm) {
-        for (int j = 0; j < R; ++j) {
-          const double wj = lv ? Ws[j * R + l] : 0.0;
+    for (int q = 0; q < BSOLVE_RPW; ++q) {
+      const int y = c0 + w * BSOLVE_RPW + q;
+      rv[q] = y < rows;
+      const int64_t off = (int64_t)(rv[q] ? y : rows - 1) * R + lc;
+      const bool ok = rv[q] && lv;
+      const double mv = M[off], av = An[off];
+      m[q] = ok ? mv : 0.0;
+      ao[q] = ok ? av : 0.0;
+    }
+    if (wterm) {  // M~ += A_old W, A_old rows read back as broadcasts
 #pragma unroll
-          for (int q = 0; q < 2; ++q) m[q] = fma(bcast(ao[q], j), wj, m[q]);
+      for (int q = 0; q < BSOLVE_RPW; ++q) bw[q * 64 + l] = ao[q];
+      __builtin_amdgcn_wave_barrier();
+      for (int j0 = 0; j0 < R; j0 += UB) {
+        double wv[UB], av[BSOLVE_RPW][UB];
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+          const int j = min(j0 + u, R - 1);
+          wv[u] = Ws[j * R + lc];
+#pragma unroll
+          for (int q = 0; q < BSOLVE_RPW; ++q) av[q][u] = j0 + u < R ? bw[q * 64 + j] : 0.0;
         }
+#pragma unroll
+        for (int u = 0; u < UB; ++u)
+#pragma unroll
+          for (int q = 0; q < BSOLVE_RPW; ++q) m[q] = fma(av[q][u], wv[u], m[q]);
       }
+      __builtin_amdgcn_wave_barrier();
+    }
+    double mo[BSOLVE_RPW];
 #pragma unroll
-      for (int q = 0; q < 2; ++q) mo[q] = m[q];
-      if (stv != 2) {
-        for (int j = 0; j < R; ++j) {
-          const double lkj = (lv && l > j) ? Lm[l * LS + j] : 0.0;
-          const double ij = invd[j];
+    for (int q = 0; q < BSOLVE_RPW; ++q) mo[q] = m[q];
+    if (stv != 2) {
+      for (int j0 = 0; j0 < R; j0 += UB) {            // (L D^-1) y = M~
+        double lf[UB];
 #pragma unroll
-          for (int q = 0; q < 2; ++q) {
-            const double zj = bcast(m[q], j) * ij;
-            m[q] = (l == j) ? zj : m[q] - lkj * zj;
+        for (int u = 0; u < UB; ++u) lf[u] = LF[min(j0 + u, R - 1) * R + lc];
+#pragma unroll
+        for (int u = 0; u < UB; ++u)
+          if (j0 + u < R) {
+#pragma unroll
+            for (int q = 0; q < BSOLVE_RPW; ++q) m[q] = fma(-lf[u], bcast(m[q], j0 + u), m[q]);
           }
-        }
-        for (int j = R - 1; j >= 0; --j) {
-          const double ljk = (lv && l < j) ? Lm[j * LS + l] : 0.0;
-          const double ij = invd[j];
-#pragma unroll
-          for (int q = 0; q < 2; ++q) {
-            const double xj = bcast(m[q], j) * ij;
-            m[q] = (l == j) ? xj : m[q] - ljk * xj;
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < 2; ++q) x[q] = lv ? m[q] : 0.0;
-      } else {
-#pragma unroll
-        for (int q = 0; q < 2; ++q) x[q] = ao[q];
       }
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int y = c0 + w * (BSOLVE_CH / 4) + rr + q;
-        const int yl = y - c0;
-        double d = 0.0;
-        if (rv[q] && lv) {
-          d = pp ? x[q] - Apn[(int64_t)y * R + l] : x[q] - ao[q];
-          An[(int64_t)y * R + l] = x[q];
-          if (pp) dAn[(int64_t)y * R + l] = d;
-          nd = fma(d, d, nd);
-          na = fma(x[q], x[q], na);
-          nm = fma(mo[q], x[q], nm);
-        }
-        if (lv) {
-          ca[yl * R + l] = (rv[q] ? x[q] : 0.0);
-          cd[yl * R + l] = (rv[q] ? d : 0.0);
-        }
+      for (int q = 0; q < BSOLVE_RPW; ++q) m[q] *= dl;
+      for (int j1 = R - 1; j1 >= 0; j1 -= UB) {       // (D^-1 L)^T v = D^-1 y, descending
+        double lb[UB];
+#pragma unroll
+        for (int u = 0; u < UB; ++u) lb[u] = Lm[max(j1 - u, 0) * CH64_LS + lc];
+#pragma unroll
+        for (int u = 0; u < UB; ++u)
+          if (j1 - u >= 0) {
+#pragma unroll
+            for (int q = 0; q < BSOLVE_RPW; ++q) m[q] = fma(-lb[u], bcast(m[q], j1 - u), m[q]);
+          }
+      }
+#pragma unroll
+      for (int q = 0; q < BSOLVE_RPW; ++q) x[q] = lv ? m[q] * dl : 0.0;
+    } else {
+#pragma unroll
+      for (int q = 0; q < BSOLVE_RPW; ++q) x[q] = ao[q];
+    }
+#pragma unroll
+    for (int q = 0; q < BSOLVE_RPW; ++q) {
+      const int y = c0 + w * BSOLVE_RPW + q;
+      const int yl = y - c0;
+      double d = 0.0;
+      if (rv[q] && lv) {
+        d = pp ? x[q] - Apn[(int64_t)y * R + l] : x[q] - ao[q];
+        An[(int64_t)y * R + l] = x[q];
+        if (pp) dAn[(int64_t)y * R + l] = d;
+        nd = fma(d, d, nd);
+        na = fma(x[q], x[q], na);
+        nm = fma(mo[q], x[q], nm);
+      }
+      if (lv) {
+        ca[yl * R + l] = (rv[q] ? x[q] : 0.0);
+        cd[yl * R + l] = (rv[q] ? d : 0.0);
       }
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int tt = w + 4 * q;
+    for (int t = 0; t < BSOLVE_TPW; ++t) {
+      const int tt = w + BSOLVE_WAVES * t;
       if (tt < ntile) {
         const bool isU = tt >= NBR * NBR;
         const int tl = isU ? tt - NBR * NBR : tt;
         const int r0 = (tl / NBR) * 16, cc0 = (tl % NBR) * 16;
         const double* Bm = isU ? cd : ca;
-        const int ra = r0 + (l & 15), cb = cc0 + (l & 15);
+        const int ra = r0 + (l & 15), cbx = cc0 + (l & 15);
         for (int kk = 0; kk < BSOLVE_CH; kk += 4) {
           const int k = kk + (l >> 4);
           const double a = ra < R ? ca[k * R + ra] : 0.0;
-          const double b = cb < R ? Bm[k * R + cb] : 0.0;
-          gacc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, gacc[q], 0, 0, 0);
+          const double b = cbx < R ? Bm[k * R + cbx] : 0.0;
+          gacc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, gacc[t], 0, 0, 0);
         }
       }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int tt = w + 4 * q;
+  for (int t = 0; t < BSOLVE_TPW; ++t) {
+    const int tt = w + BSOLVE_WAVES * t;
     if (tt < ntile) {
       const bool isU = tt >= NBR * NBR;
       const int tl = isU ? tt - NBR * NBR : tt;
@@ -432,7 +485,7 @@ __global__ __launch_bounds__(256) void k_b_solve(const BProb* pr, BState* st, co
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = r0 + 4 * v + (l >> 4), c = cc0 + (l & 15);
-        if (r < R && c < R) out[r * R + c] = gacc[q][v];
+        if (r < R && c < R) out[r * R + c] = gacc[t][v];
       }
     }
   }
@@ -447,20 +500,30 @@ __global__ __launch_bounds__(256) void k_b_solve(const BProb* pr, BState* st, co
   __syncthreads();
   if (tid == 0) {
     BState& B = st[p];
-    B.sums[n][0] = ((red[0][1] + red[1][1]) + red[2][1]) + red[3][1];
-    B.sums[n][1] = ((red[0][2] + red[1][2]) + red[2][2]) + red[3][2];
-    B.sums[n][2] = ((red[0][3] + red[1][3]) + red[2][3]) + red[3][3];
+    double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int q = 0; q < BSOLVE_WAVES; ++q) {
+      s1 += red[q][1];
+      s2 += red[q][2];
+      s3 += red[q][3];
+    }
+    B.sums[n][0] = s1;
+    B.sums[n][1] = s2;
+    B.sums[n][2] = s3;
     B.chol[n] = stv;
   }
   if (n == 2) {
     // sum of Gamma^(2) * S^(2) with the new Gram (written above by this workgroup)
-    double g = 0.0;
-    for (int e = tid; e < RR; e += 256) g = fma(S[e] * S[RR + e], S[2 * RR + e], g);
-    g = wsum(g);
     __syncthreads();
+    double g = 0.0;
+    for (int e = tid; e < RR; e += nthr) g = fma(S[e] * S[RR + e], S[2 * RR + e], g);
+    g = wsum(g);
     if (l == 0) red[w][0] = g;
     __syncthreads();
-    if (tid == 0) st[p].gs = ((red[0][0] + red[1][0]) + red[2][0]) + red[3][0];
+    if (tid == 0) {
+      double gs = 0.0;
+      for (int q = 0; q < BSOLVE_WAVES; ++q) gs += red[q][0];
+      st[p].gs = gs;
+    }
   }
 }
 
@@ -572,7 +635,8 @@ hipError_t launch_b_ttv(const BProb* pr, const BState* st, const BTile* tiles, i
   return hipGetLastError();
 }
 static size_t b_solve_lds(int maxR) {
-  return ((size_t)maxR * (maxR + 1) + (size_t)maxR * maxR + maxR + 2 * (size_t)BSOLVE_CH * maxR) *
+  return ((size_t)64 * CH64_LS + 2 * (size_t)maxR * maxR + 64 + 2 * (size_t)BSOLVE_CH * maxR +
+          (size_t)BSOLVE_WAVES * BSOLVE_RPW * 64) *
          sizeof(double);
 }
 // The solve's LDS request above 64 KB is enabled once, outside any graph capture.
@@ -582,7 +646,8 @@ hipError_t batch_prepare() {
 }
 hipError_t launch_b_solve(const BProb* pr, BState* st, const BConf* conf, int count, int mode,
                           int maxR, hipStream_t s) {
-  hipLaunchKernelGGL(k_b_solve, dim3(count), dim3(256), b_solve_lds(maxR), s, pr, st, conf, mode);
+  hipLaunchKernelGGL(k_b_solve, dim3(count), dim3(BSOLVE_WAVES * 64), b_solve_lds(maxR), s, pr, st,
+                     conf, mode);
   return hipGetLastError();
 }
 hipError_t launch_b_end(BState* st, const BConf* conf, int count, hipStream_t s) {
