@@ -47,7 +47,8 @@ struct ppals_batch {
   int max_sweeps = 0;
   int maxR = 0, max_s = 0;
   std::vector<ppals_batch_problem> probs;
-  std::vector<size_t> off_op[3], off_Mp[3], off_Ap[3], off_dA[3], off_S, off_U, off_M, off_klog;
+  std::vector<size_t> off_op[3], off_Mp[3], off_Ap[3], off_dA[3], off_Af[3], off_S, off_U, off_M,
+      off_klog;
   size_t off_prob = 0, off_state = 0, off_conf = 0, off_tiles = 0, tiles_bytes = 0;
   size_t ws_bytes = 0;
   std::vector<int> variant;                 // GEMM tile variant per problem
@@ -74,14 +75,13 @@ void build_tiles(ppals_batch* b) {
   for (int c = 0; c < 3; ++c)
     for (int v = 0; v < BATCH_GEMM_VARIANTS; ++v) {
       b->g_off[c][v] = (int)b->tiles.size();
-      const int TM = batch_gemm_rows(v);
       for (int p = 0; p < b->count; ++p) {
         if (b->variant[p] != v) continue;
         const auto& q = b->probs[p];
         int64_t M = 1;
         for (int i = 0; i < 3; ++i)
           if (i != c) M *= q.dims[i];
-        for (int64_t m0 = 0; m0 < M; m0 += TM) b->tiles.push_back(BTile{p, (int)m0});
+        for (int64_t m0 = 0; m0 < M; m0 += BATCH_RUN_ROWS) b->tiles.push_back(BTile{p, (int)m0});
       }
       b->g_cnt[c][v] = (int)b->tiles.size() - b->g_off[c][v];
     }
@@ -96,14 +96,15 @@ void build_tiles(ppals_batch* b) {
 }
 
 size_t max_tiles_bytes(const ppals_batch* b) {
-  // every problem in the smaller-tile variant gives the longest list
+  // one GEMM work item per BATCH_RUN_ROWS rows of each contraction, one TTV tile per
+  // 256 output elements
   size_t n = 0;
   for (const auto& q : b->probs) {
     for (int c = 0; c < 3; ++c) {
       int64_t M = 1;
       for (int i = 0; i < 3; ++i)
         if (i != c) M *= q.dims[i];
-      n += (size_t)((M + 63) / 64);
+      n += (size_t)((M + BATCH_RUN_ROWS - 1) / BATCH_RUN_ROWS);
     }
     for (int i = 0; i < 3; ++i) n += (size_t)(((int64_t)q.dims[i] * q.rank + 255) / 256);
   }
@@ -140,6 +141,7 @@ ppals_status enqueue_sweep(ppals_batch* b, char* ws, hipStream_t s) {
   for (int n = 0; n < 3; ++n) {
     BHIPCHK(launch_b_ttv(pr, st, tl + b->t_off[n], b->t_cnt[n], n, 0, s));
     BHIPCHK(launch_b_solve(pr, st, cf, C, n, b->maxR, s));
+    if (n != 1) BHIPCHK(launch_b_f32(pr, st, C, n == 0 ? 1 : 6, s));  // FP32 factor copies
     if (n == 0 && (r = gemm(0, 2, BMASK_ALS)) != PPALS_OK) return r;  // X x_0 A^(0), updated
   }
   BHIPCHK(launch_b_end(st, cf, C, s));
@@ -203,6 +205,7 @@ ppals_status ppals_batch_create(const ppals_batch_problem* probs, int32_t count,
       b->off_Mp[n].push_back(take((size_t)q.dims[n] * R * 8));
       b->off_Ap[n].push_back(take((size_t)q.dims[n] * R * 8));
       b->off_dA[n].push_back(take((size_t)q.dims[n] * R * 8));
+      b->off_Af[n].push_back(take((size_t)((q.dims[n] + 31) / 32 * 32) * BATCH_MAX_R * 4));
     }
     b->off_S.push_back(take(3 * R * R * 8));
     b->off_U.push_back(take(3 * R * R * 8));
@@ -259,6 +262,7 @@ ppals_status ppals_batch_bind(ppals_batch* b, const float* const* X, double* con
       P.Mp[n] = (double*)(w + b->off_Mp[n][p]);
       P.Ap[n] = (double*)(w + b->off_Ap[n][p]);
       P.dA[n] = (double*)(w + b->off_dA[n][p]);
+      P.Af[n] = (float*)(w + b->off_Af[n][p]);
     }
     P.S = (double*)(w + b->off_S[p]);
     P.U = (double*)(w + b->off_U[p]);

@@ -17,6 +17,7 @@ constexpr int BMASK_PP = BMASK_INIT | BMASK_APPROX;
 constexpr int BATCH_MAX_R = 64;
 constexpr int BATCH_MAX_S = 256;
 constexpr int BATCH_GEMM_VARIANTS = 2;  // rows per GEMM tile: 64 or 128
+constexpr int BATCH_RUN_ROWS = 1024;   // rows of one problem per GEMM work item (a run of tiles)
 
 // Static description of one problem (device pointers into the caller's buffers and
 // the batch workspace).
@@ -25,6 +26,8 @@ struct BProb {
   int R;
   const float* X;   // s0 x s1 x s2, row-major
   double* A[3];     // factors, s_n x R
+  float* Af[3];     // the factors transposed in FP32 for the contraction kernel:
+                    // BATCH_MAX_R columns of ceil(s_n / 32) * 32 entries, zero beyond R x s_n
   double* S;        // 3 x R x R Grams
   double* U;        // 3 x R x R, A^(n)T dA^(n)
   float* op[3];     // op[0] = M^(0,1) (s0 x s1 x R), op[1] = M^(0,2) (s0 x s2 x R),
@@ -58,13 +61,15 @@ struct BConf {
   int second_order;
 };
 
-// Work item of the grouped contraction kernels: one tile of output rows.
+// Work item of the grouped kernels: the problem and the first output row (contraction:
+// BATCH_RUN_ROWS rows from m0; multi-TTV: 256 output elements from m0).
 struct BTile {
   int prob;
   int m0;
 };
 
 hipError_t launch_b_begin(BState* st, BProb* pr, const BConf* conf, int count, hipStream_t s);
+hipError_t launch_b_f32(const BProb* pr, const BState* st, int count, int mode_mask, hipStream_t s);
 hipError_t launch_b_prep(const BProb* pr, const BState* st, int count, hipStream_t s);
 hipError_t launch_b_gemm(int variant, const BProb* pr, const BState* st, const BTile* tiles,
                          int ntiles, int cmode, int out_op, int kind_mask, hipStream_t s);

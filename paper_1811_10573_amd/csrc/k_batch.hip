@@ -65,134 +65,190 @@ __global__ __launch_bounds__(256) void k_b_prep(const BProb* pr, const BState* s
 
 // ---------------------------------------------------------------------------
 // Grouped first-level contraction: out[m][r] = sum_k X(m, k) A^(c)[k][r], FP32 on the
-// matrix cores (f32 16x16x4: lane l supplies A[m0 + l%16][k + l/16] and
-// B[k + l/16][c0 + l%16]; accumulator register v holds row 4 (l/16) + v, column l%16).
+// matrix cores (f32 16x16x4: lane l supplies A[m0 + l%16][k_g] and B[k_g][c0 + l%16] for
+// the k-index g = l/16 of the step; accumulator register v holds row 4 (l/16) + v, column
+// l%16).  The order in which k enters the sum is free as long as both operands follow
+// it: step s of a 16-deep k block gives group g the k-value 4 g + s, so each lane reads
+// four consecutive k of its row (and of its factor column) with one 16-byte LDS read and
+// feeds them to four steps.
 // With P = prod s_{<c}, Q = prod s_{>c}: X(m, k) = X[p K Q + k Q + q], m = p Q + q.
 // TM output rows per tile, 4 waves of TM/4 rows each, R padded to 16-column tiles.
-// Chunks of BKC k-values pass through double-buffered LDS; the next chunk's X and
-// factor entries are loaded into registers while the current chunk is multiplied.
+// A work item is a run of consecutive tiles of one problem (BATCH_RUN_ROWS rows), walked
+// as one sequence of (tile, k-chunk) steps: the next step's X and factor entries are
+// loaded into registers while the current step is multiplied, also across tile
+// boundaries, so the problem's descriptors and the first chunk's load latency are paid
+// once per run.  Chunks of BKC k-values pass through double-buffered LDS, X as [m][k]
+// and the factor as [c][k], from the factor's transposed FP32 copy (64 columns of
+// BKC-padded length, zero-filled), which a chunk reads with two unconditional 16-byte
+// loads per thread.
 // ---------------------------------------------------------------------------
 constexpr int BKC = 32;  // k per LDS chunk
+
+// LDS position (in floats) of the k-quad kq of row r in a chunk of 32-float rows.  Rows
+// are not padded; the quad index is XOR-ed with (r / 2) mod 8, so the 16 rows of one
+// 16-byte read (one per lane of a 16-lane group) and the rows of a 16-lane store land on
+// distinct banks.
+__device__ __forceinline__ int swz_q(int r, int kq) { return r * BKC + 4 * (kq ^ ((r >> 1) & 7)); }
 
 template <int TM, bool KCM>
 __global__ __launch_bounds__(256) void k_b_gemm(const BProb* pr, const BState* st,
                                                 const BTile* tiles, int ntiles, int cmode,
                                                 int out_op, int kind_mask) {
-  constexpr int RS = TM / 64;                       // 16-row subtiles per wave
-  constexpr int XPER = BKC * TM / 256;              // X elements staged per thread
-  constexpr int APER = BKC * BATCH_MAX_R / 256;     // factor elements staged per thread
-  __shared__ float xs[2][BKC][TM + 4];
-  __shared__ float as[2][BKC][BATCH_MAX_R + 4];
-  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  static_assert(BATCH_RUN_ROWS % TM == 0, "a run holds whole tiles");
+  static_assert(BKC == 32 && BATCH_MAX_R == 64, "layout assumes 32-deep chunks of 64 columns");
+  constexpr int RS = TM / 64;                        // 16-row subtiles per wave
+  constexpr int XQ = BKC * TM / 4 / 256;             // X k-quads staged per thread
+  constexpr int AV4 = BKC * BATCH_MAX_R / 4 / 256;   // factor 16-byte vectors per thread
+  __shared__ __attribute__((aligned(16))) float xs[2][TM * BKC];
+  __shared__ __attribute__((aligned(16))) float as[2][BATCH_MAX_R * BKC];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const BTile tile = tiles[t];
     const int p = tile.prob;
     if (!(kind_mask & (1 << st[p].kind))) continue;
     const BProb& P = pr[p];
     const int R = P.R;
-    const int64_t K = P.s[cmode];
-    int64_t Pd = 1, Q = 1;
+    int Pd = 1, Qi = 1;
     for (int i = 0; i < cmode; ++i) Pd *= P.s[i];
-    for (int i = cmode + 1; i < 3; ++i) Q *= P.s[i];
-    const int64_t M = Pd * Q;
-    const int m0 = tile.m0;
+    for (int i = cmode + 1; i < 3; ++i) Qi *= P.s[i];
+    // 32-bit element offsets (a problem holds at most 256^3 elements)
+    const int Ki = P.s[cmode], Mi = Pd * Qi;
+    const int Kpad = (Ki + BKC - 1) / BKC * BKC;
+    const int mend = min(Mi, tile.m0 + BATCH_RUN_ROWS);
     const float* X = P.X;
-    const double* A = P.A[cmode];
+    const float* Af = P.Af[cmode];
     float* out = P.op[out_op];
     const int NCT = (R + 15) >> 4;
-    float xr[XPER], ar[APER];
-    // Element j of the chunk staged by this thread.  Q == 1 (rows k-contiguous): row
-    // m0 + tid/BKC + (256/BKC) j, k = k0 + tid%BKC; otherwise (rows contiguous for a
-    // fixed k): row m0 + tid%TM, k = k0 + tid/TM + (256/TM) j.  The row's (p, q) split
-    // is formed once per tile.
+    // X staging.
+    //   Q == 1 (rows k-contiguous): quad u of this thread is row m0 + tid/8 + 32 u,
+    //   k-quad tid%8; 8 lanes read one row's 32 consecutive k with 16-byte loads (4-byte
+    //   aligned addresses suffice).  A quad that crosses the row's end is read element by
+    //   element.
+    //   otherwise (rows contiguous for a fixed k): this thread reads row m0 + tid%TM at
+    //   the k of quads tid/TM + (256/TM) u, consecutive lanes reading consecutive rows.
     constexpr bool kcm = KCM;  // Q == 1 exactly when the last mode is contracted
-    const int mm0 = kcm ? tid / BKC : tid % TM;
-    const int kk0 = kcm ? tid % BKC : tid / TM;
-    constexpr int MSTEP = 256 / BKC, KSTEP_Q = 256 / TM;
-    // 32-bit element offsets (a problem holds at most 256^3 elements)
+    constexpr int QSTEP = 256 / TM;
+    float4 xr[XQ], ar[AV4];
+    auto xm = [&](int u) { return kcm ? tid / 8 + 32 * u : tid % TM; };
+    auto xq = [&](int u) { return kcm ? tid % 8 : tid / TM + QSTEP * u; };
     int xbase = 0;
     bool rowv = true;
-    if (!kcm) {
-      const int m = m0 + mm0;
-      rowv = m < (int)M;
-      const int pp = rowv ? m / (int)Q : 0, q = rowv ? m - pp * (int)Q : 0;
-      xbase = pp * (int)K * (int)Q + q;
-    }
-    const int Ki = (int)K, Qi = (int)Q, Mi = (int)M;
-    const int ar_r = tid % BATCH_MAX_R, ar_k = tid / BATCH_MAX_R;
-    auto load_chunk = [&](int k0) {
+    auto set_rows = [&](int m0) {
+      if (!kcm) {
+        const int m = m0 + tid % TM;
+        rowv = m < Mi;
+        const int pp = rowv ? m / Qi : 0, q = rowv ? m - pp * Qi : 0;
+        xbase = pp * Ki * Qi + q;
+      }
+    };
+    auto load_chunk = [&](int m0, int k0) {
 #pragma unroll
-      for (int j = 0; j < XPER; ++j) {
-        float v = 0.f;
+      for (int u = 0; u < XQ; ++u) {
+        const int kb = k0 + 4 * xq(u);
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         if (kcm) {
-          const int m = m0 + mm0 + MSTEP * j, k = k0 + kk0;
-          if (m < Mi && k < Ki) v = X[m * Ki + k];
-        } else {
-          const int k = k0 + kk0 + KSTEP_Q * j;
-          if (rowv && k < Ki) v = X[xbase + k * Qi];
+          const int m = m0 + xm(u);
+          if (m < Mi) {
+            const float* src = X + m * Ki + kb;
+            if (kb + 3 < Ki) {
+              __builtin_memcpy(&v, src, 16);
+            } else {
+              if (kb < Ki) v.x = src[0];
+              if (kb + 1 < Ki) v.y = src[1];
+              if (kb + 2 < Ki) v.z = src[2];
+            }
+          }
+        } else if (rowv) {
+          const float* src = X + xbase + kb * Qi;
+          if (kb < Ki) v.x = src[0];
+          if (kb + 1 < Ki) v.y = src[Qi];
+          if (kb + 2 < Ki) v.z = src[2 * Qi];
+          if (kb + 3 < Ki) v.w = src[3 * Qi];
         }
-        xr[j] = v;
+        xr[u] = v;
       }
 #pragma unroll
-      for (int j = 0; j < APER; ++j) {
-        const int k = k0 + ar_k + (256 / BATCH_MAX_R) * j;
-        ar[j] = (k < Ki && ar_r < R) ? (float)A[k * R + ar_r] : 0.f;
+      for (int j = 0; j < AV4; ++j) {
+        const int vi = tid + 256 * j, c = vi / 8, q = vi % 8;
+        ar[j] = *reinterpret_cast<const float4*>(Af + c * Kpad + k0 + 4 * q);
       }
     };
     auto store_chunk = [&](int buf) {
 #pragma unroll
-      for (int j = 0; j < XPER; ++j) {
-        if (kcm) xs[buf][kk0][mm0 + MSTEP * j] = xr[j];
-        else xs[buf][kk0 + KSTEP_Q * j][mm0] = xr[j];
-      }
+      for (int u = 0; u < XQ; ++u) *reinterpret_cast<float4*>(&xs[buf][swz_q(xm(u), xq(u))]) = xr[u];
 #pragma unroll
-      for (int j = 0; j < APER; ++j) as[buf][ar_k + (256 / BATCH_MAX_R) * j][ar_r] = ar[j];
+      for (int j = 0; j < AV4; ++j) {
+        const int vi = tid + 256 * j, c = vi / 8, q = vi % 8;
+        *reinterpret_cast<float4*>(&as[buf][swz_q(c, q)]) = ar[j];
+      }
     };
     f4 acc[RS][4];
 #pragma unroll
     for (int i = 0; i < RS; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-    __syncthreads();  // the previous tile's last chunk is no longer read
-    load_chunk(0);
+    // step being multiplied (cm0, ck0) and step being loaded (lm0, lk0)
+    int cm0 = tile.m0, ck0 = 0, lm0 = tile.m0, lk0 = 0;
+    auto advance = [&]() {
+      lk0 += BKC;
+      if (lk0 >= Ki) {
+        lk0 = 0;
+        lm0 += TM;
+        set_rows(lm0);
+      }
+    };
+    __syncthreads();  // the previous run's last chunk is no longer read
+    set_rows(lm0);
+    load_chunk(lm0, lk0);
     store_chunk(0);
     __syncthreads();
+    advance();
     int buf = 0;
-    for (int k0 = 0; k0 < Ki; k0 += BKC) {
-      const bool more = k0 + BKC < Ki;
-      if (more) load_chunk(k0 + BKC);
-#pragma unroll 2
-      for (int kk = 0; kk < BKC; kk += 4) {
-        const int kr = kk + (l >> 4);
-        float a[RS];
+    for (;;) {
+      const bool more = lm0 < mend;
+      if (more) load_chunk(lm0, lk0);
 #pragma unroll
-        for (int i = 0; i < RS; ++i) a[i] = xs[buf][kr][w * (TM / 4) + i * 16 + (l & 15)];
+      for (int kb = 0; kb < BKC / 16; ++kb) {  // 16-deep k blocks: quad 4 kb + g per lane
+        f4 a[RS], b[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          if (j < NCT) {
-            const float b = as[buf][kr][j * 16 + (l & 15)];
+        for (int i = 0; i < RS; ++i)
+          a[i] = *reinterpret_cast<const f4*>(&xs[buf][swz_q(w * (TM / 4) + i * 16 + (l & 15), 4 * kb + g)]);
 #pragma unroll
-            for (int i = 0; i < RS; ++i)
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b, acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 4; ++j)
+          if (j < NCT) b[j] = *reinterpret_cast<const f4*>(&as[buf][swz_q(j * 16 + (l & 15), 4 * kb + g)]);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (j < NCT) {
+#pragma unroll
+              for (int i = 0; i < RS; ++i)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
+            }
+      }
+      if (ck0 + BKC >= Ki) {  // last chunk of the tile at cm0: write it out, restart
+#pragma unroll
+        for (int i = 0; i < RS; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (j >= NCT) continue;
+            const int c = j * 16 + (l & 15);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int m = cm0 + w * (TM / 4) + i * 16 + 4 * g + v;
+              if (m < Mi && c < R) out[(int64_t)m * R + c] = acc[i][j][v];
+            }
+            acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
           }
-        }
       }
       if (more) store_chunk(buf ^ 1);
       __syncthreads();
       buf ^= 1;
+      if (!more) break;
+      cm0 = lm0;
+      ck0 = lk0;
+      advance();
     }
-#pragma unroll
-    for (int i = 0; i < RS; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (j >= NCT) continue;
-        const int c = j * 16 + (l & 15);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int64_t m = m0 + w * (TM / 4) + i * 16 + 4 * (l >> 4) + v;
-          if (m < M && c < R) out[m * R + c] = acc[i][j][v];
-        }
-      }
   }
 }
 
@@ -553,8 +609,25 @@ __global__ void k_b_end(BState* st, const BConf* conf, int count) {
   }
 }
 
-// Initialisation: ||X||^2, the Grams of the initial factors, a fresh state and an empty
-// sweep-kind log.
+// FP32 copies of the factors of the modes in mode_mask, for the problems that swept.
+__global__ __launch_bounds__(256) void k_b_f32(const BProb* pr, const BState* st, int count,
+                                               int mode_mask) {
+  const int p = blockIdx.x;
+  if (p >= count || st[p].kind == BK_NONE) return;
+  const BProb& P = pr[p];
+  const int R = P.R;
+  for (int n = 0; n < 3; ++n) {
+    if (!(mode_mask & (1 << n))) continue;
+    const int sn = P.s[n], Kpad = (sn + BKC - 1) / BKC * BKC;
+    for (int e = threadIdx.x; e < R * sn; e += 256) {  // columns >= R and rows >= s_n stay 0
+      const int c = e / sn, y = e - c * sn;
+      P.Af[n][c * Kpad + y] = (float)P.A[n][y * R + c];
+    }
+  }
+}
+
+// Initialisation: ||X||^2, the Grams of the initial factors, their FP32 copies, a fresh
+// state and an empty sweep-kind log.
 __global__ __launch_bounds__(256) void k_b_norm(const BProb* pr, BState* st, const BConf* conf,
                                                 int count) {
   __shared__ double red[4];
@@ -579,6 +652,13 @@ __global__ __launch_bounds__(256) void k_b_norm(const BProb* pr, BState* st, con
       for (int y = 0; y < P.s[n]; ++y) g = fma(P.A[n][y * R + r], P.A[n][y * R + c], g);
       P.S[n * R * R + e] = g;
     }
+  for (int n = 0; n < 3; ++n) {
+    const int Kpad = (P.s[n] + BKC - 1) / BKC * BKC;
+    for (int e = threadIdx.x; e < Kpad * BATCH_MAX_R; e += 256) {
+      const int c = e / Kpad, y = e - c * Kpad;
+      P.Af[n][e] = (y < P.s[n] && c < R) ? (float)P.A[n][y * R + c] : 0.f;
+    }
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     BState& S = st[p];
@@ -607,6 +687,10 @@ static int grid_for(int ntiles) { return ntiles < 2048 ? (ntiles > 0 ? ntiles : 
 
 hipError_t launch_b_begin(BState* st, BProb* pr, const BConf* conf, int count, hipStream_t s) {
   hipLaunchKernelGGL(k_b_begin, dim3((count + 255) / 256), dim3(256), 0, s, st, pr, conf, count);
+  return hipGetLastError();
+}
+hipError_t launch_b_f32(const BProb* pr, const BState* st, int count, int mode_mask, hipStream_t s) {
+  hipLaunchKernelGGL(k_b_f32, dim3(count), dim3(256), 0, s, pr, st, count, mode_mask);
   return hipGetLastError();
 }
 hipError_t launch_b_prep(const BProb* pr, const BState* st, int count, hipStream_t s) {
