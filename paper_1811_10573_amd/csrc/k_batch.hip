@@ -21,6 +21,15 @@
 
 namespace ppk {
 
+// The per-problem pointers live in BProb records in device memory, so the compiler cannot
+// tell their address space and would access them with flat instructions, whose completion
+// is counted together with LDS operations (every wait for an LDS read would then also wait
+// for all outstanding global loads).  They all point to global memory: gl() says so.
+#define GLB __attribute__((address_space(1)))
+template <typename T> __device__ __forceinline__ GLB T* gl(T* p) { return (GLB T*)p; }
+template <typename T> __device__ __forceinline__ const GLB T* gl(const T* p) { return (const GLB T*)p; }
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));  // 4-byte aligned 16-byte vector
+
 // ---------------------------------------------------------------------------
 // State machine
 // ---------------------------------------------------------------------------
@@ -44,7 +53,7 @@ __global__ void k_b_begin(BState* st, BProb* pr, const BConf* conf, int count) {
   if (small) kind = (S.prev_kind == BK_PP_INIT || S.prev_kind == BK_PP_APPROX) ? BK_PP_APPROX
                                                                               : BK_PP_INIT;
   S.kind = kind;
-  pr[p].klog[S.sweep] = (uint8_t)kind;
+  gl(pr[p].klog)[S.sweep] = (uint8_t)kind;
 }
 
 // PP initialisation of the problems that start a PP phase: A_p := A, dA := 0, U := 0.
@@ -56,11 +65,11 @@ __global__ __launch_bounds__(256) void k_b_prep(const BProb* pr, const BState* s
   for (int n = 0; n < 3; ++n) {
     const int64_t cnt = (int64_t)P.s[n] * R;
     for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) {
-      P.Ap[n][e] = P.A[n][e];
-      P.dA[n][e] = 0.0;
+      gl(P.Ap[n])[e] = gl(P.A[n])[e];
+      gl(P.dA[n])[e] = 0.0;
     }
   }
-  for (int e = threadIdx.x; e < 3 * R * R; e += blockDim.x) P.U[e] = 0.0;
+  for (int e = threadIdx.x; e < 3 * R * R; e += blockDim.x) gl(P.U)[e] = 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -83,6 +92,7 @@ __global__ __launch_bounds__(256) void k_b_prep(const BProb* pr, const BState* s
 // loads per thread.
 // ---------------------------------------------------------------------------
 constexpr int BKC = 32;  // k per LDS chunk
+template <int V> struct IC { static constexpr int value = V; };  // compile-time index
 
 // LDS position (in floats) of the k-quad kq of row r in a chunk of 32-float rows.  Rows
 // are not padded; the quad index is XOR-ed with (r / 2) mod 8, so the 16 rows of one
@@ -115,9 +125,9 @@ __global__ __launch_bounds__(256) void k_b_gemm(const BProb* pr, const BState* s
     const int Ki = P.s[cmode], Mi = Pd * Qi;
     const int Kpad = (Ki + BKC - 1) / BKC * BKC;
     const int mend = min(Mi, tile.m0 + BATCH_RUN_ROWS);
-    const float* X = P.X;
-    const float* Af = P.Af[cmode];
-    float* out = P.op[out_op];
+    const GLB float* X = gl(P.X);
+    const GLB float* Af = gl(P.Af[cmode]);
+    GLB float* out = gl(P.op[out_op]);
     const int NCT = (R + 15) >> 4;
     // X staging.
     //   Q == 1 (rows k-contiguous): quad u of this thread is row m0 + tid/8 + 32 u,
@@ -128,7 +138,7 @@ __global__ __launch_bounds__(256) void k_b_gemm(const BProb* pr, const BState* s
     //   the k of quads tid/TM + (256/TM) u, consecutive lanes reading consecutive rows.
     constexpr bool kcm = KCM;  // Q == 1 exactly when the last mode is contracted
     constexpr int QSTEP = 256 / TM;
-    float4 xr[XQ], ar[AV4];
+    f4 xr[2][XQ], ar[2][AV4];  // two register sets: steps i + 1 and i + 2
     auto xm = [&](int u) { return kcm ? tid / 8 + 32 * u : tid % TM; };
     auto xq = [&](int u) { return kcm ? tid % 8 : tid / TM + QSTEP * u; };
     int xbase = 0;
@@ -141,17 +151,19 @@ __global__ __launch_bounds__(256) void k_b_gemm(const BProb* pr, const BState* s
         xbase = pp * Ki * Qi + q;
       }
     };
-    auto load_chunk = [&](int m0, int k0) {
+    auto load_chunk = [&](auto set, int m0, int k0) {
+      constexpr int S = decltype(set)::value;
 #pragma unroll
       for (int u = 0; u < XQ; ++u) {
         const int kb = k0 + 4 * xq(u);
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        f4 v = f4{0.f, 0.f, 0.f, 0.f};
         if (kcm) {
           const int m = m0 + xm(u);
           if (m < Mi) {
-            const float* src = X + m * Ki + kb;
+            const GLB float* src = X + m * Ki + kb;
             if (kb + 3 < Ki) {
-              __builtin_memcpy(&v, src, 16);
+              const f4u w4 = *reinterpret_cast<const GLB f4u*>(src);
+              v = f4{w4.x, w4.y, w4.z, w4.w};
             } else {
               if (kb < Ki) v.x = src[0];
               if (kb + 1 < Ki) v.y = src[1];
@@ -159,27 +171,28 @@ __global__ __launch_bounds__(256) void k_b_gemm(const BProb* pr, const BState* s
             }
           }
         } else if (rowv) {
-          const float* src = X + xbase + kb * Qi;
+          const GLB float* src = X + xbase + kb * Qi;
           if (kb < Ki) v.x = src[0];
           if (kb + 1 < Ki) v.y = src[Qi];
           if (kb + 2 < Ki) v.z = src[2 * Qi];
           if (kb + 3 < Ki) v.w = src[3 * Qi];
         }
-        xr[u] = v;
+        xr[S][u] = v;
       }
 #pragma unroll
       for (int j = 0; j < AV4; ++j) {
         const int vi = tid + 256 * j, c = vi / 8, q = vi % 8;
-        ar[j] = *reinterpret_cast<const float4*>(Af + c * Kpad + k0 + 4 * q);
+        ar[S][j] = *reinterpret_cast<const GLB f4*>(Af + c * Kpad + k0 + 4 * q);
       }
     };
-    auto store_chunk = [&](int buf) {
+    auto store_chunk = [&](auto set, int buf) {
+      constexpr int S = decltype(set)::value;
 #pragma unroll
-      for (int u = 0; u < XQ; ++u) *reinterpret_cast<float4*>(&xs[buf][swz_q(xm(u), xq(u))]) = xr[u];
+      for (int u = 0; u < XQ; ++u) *reinterpret_cast<f4*>(&xs[buf][swz_q(xm(u), xq(u))]) = xr[S][u];
 #pragma unroll
       for (int j = 0; j < AV4; ++j) {
         const int vi = tid + 256 * j, c = vi / 8, q = vi % 8;
-        *reinterpret_cast<float4*>(&as[buf][swz_q(c, q)]) = ar[j];
+        *reinterpret_cast<f4*>(&as[buf][swz_q(c, q)]) = ar[S][j];
       }
     };
     f4 acc[RS][4];
@@ -187,8 +200,10 @@ __global__ __launch_bounds__(256) void k_b_gemm(const BProb* pr, const BState* s
     for (int i = 0; i < RS; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-    // step being multiplied (cm0, ck0) and step being loaded (lm0, lk0)
-    int cm0 = tile.m0, ck0 = 0, lm0 = tile.m0, lk0 = 0;
+    // Step being multiplied (cm0, ck0, in LDS buffer buf), the next step (nm0, nk0, in a
+    // register set while nv) and the step being loaded (lm0, lk0).
+    int cm0 = tile.m0, ck0 = 0, nm0 = 0, nk0 = 0, lm0 = tile.m0, lk0 = 0;
+    bool nv = false;
     auto advance = [&]() {
       lk0 += BKC;
       if (lk0 >= Ki) {
@@ -199,14 +214,24 @@ __global__ __launch_bounds__(256) void k_b_gemm(const BProb* pr, const BState* s
     };
     __syncthreads();  // the previous run's last chunk is no longer read
     set_rows(lm0);
-    load_chunk(lm0, lk0);
-    store_chunk(0);
-    __syncthreads();
+    load_chunk(IC<0>{}, lm0, lk0);
     advance();
+    if (lm0 < mend) {
+      nv = true;
+      nm0 = lm0;
+      nk0 = lk0;
+      load_chunk(IC<1>{}, lm0, lk0);
+      advance();
+    }
+    store_chunk(IC<0>{}, 0);
+    __syncthreads();
     int buf = 0;
-    for (;;) {
-      const bool more = lm0 < mend;
-      if (more) load_chunk(lm0, lk0);
+    // One step with the next step's data in register set N; loads the step after it into
+    // the other set.  Returns false after the run's last step.
+    auto step = [&](auto nset) -> bool {
+      constexpr int N = decltype(nset)::value;
+      const bool ld = nv && lm0 < mend;
+      if (ld) load_chunk(IC<1 - N>{}, lm0, lk0);
 #pragma unroll
       for (int kb = 0; kb < BKC / 16; ++kb) {  // 16-deep k blocks: quad 4 kb + g per lane
         f4 a[RS], b[4];
@@ -241,13 +266,22 @@ __global__ __launch_bounds__(256) void k_b_gemm(const BProb* pr, const BState* s
             acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
           }
       }
-      if (more) store_chunk(buf ^ 1);
+      if (nv) store_chunk(IC<N>{}, buf ^ 1);
       __syncthreads();
+      if (!nv) return false;
       buf ^= 1;
-      if (!more) break;
-      cm0 = lm0;
-      ck0 = lk0;
-      advance();
+      cm0 = nm0;
+      ck0 = nk0;
+      if (ld) {
+        nm0 = lm0;
+        nk0 = lk0;
+        advance();
+      } else {
+        nv = false;
+      }
+      return true;
+    };
+    while (step(IC<1>{}) && step(IC<0>{})) {
     }
   }
 }
@@ -265,16 +299,17 @@ struct BJob {
 __device__ __forceinline__ double b_ttv_job(const BJob& J, int R, int y, int r) {
   const int p = y / J.Q, q = y - p * J.Q;
   const int64_t QR = (int64_t)J.Q * R;
-  const float* t = J.T + (int64_t)p * J.X * QR + (int64_t)q * R + r;
+  const GLB float* t = gl(J.T) + (int64_t)p * J.X * QR + (int64_t)q * R + r;
+  const GLB double* F = gl(J.F);
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   int x = 0;
   for (; x + 3 < J.X; x += 4) {
-    a0 = fma((double)t[(int64_t)x * QR], J.F[(int64_t)x * R + r], a0);
-    a1 = fma((double)t[(int64_t)(x + 1) * QR], J.F[(int64_t)(x + 1) * R + r], a1);
-    a2 = fma((double)t[(int64_t)(x + 2) * QR], J.F[(int64_t)(x + 2) * R + r], a2);
-    a3 = fma((double)t[(int64_t)(x + 3) * QR], J.F[(int64_t)(x + 3) * R + r], a3);
+    a0 = fma((double)t[(int64_t)x * QR], F[(int64_t)x * R + r], a0);
+    a1 = fma((double)t[(int64_t)(x + 1) * QR], F[(int64_t)(x + 1) * R + r], a1);
+    a2 = fma((double)t[(int64_t)(x + 2) * QR], F[(int64_t)(x + 2) * R + r], a2);
+    a3 = fma((double)t[(int64_t)(x + 3) * QR], F[(int64_t)(x + 3) * R + r], a3);
   }
-  for (; x < J.X; ++x) a0 = fma((double)t[(int64_t)x * QR], J.F[(int64_t)x * R + r], a0);
+  for (; x < J.X; ++x) a0 = fma((double)t[(int64_t)x * QR], F[(int64_t)x * R + r], a0);
   return (a0 + a1) + (a2 + a3);
 }
 
@@ -315,9 +350,9 @@ __global__ __launch_bounds__(256) void k_b_ttv(const BProb* pr, const BState* st
         J[nj++] = BJob{P.op[2], P.dA[1], 1, s1, s2};
       }
     }
-    double v = base ? base[e] : 0.0;
+    double v = base ? gl(base)[e] : 0.0;
     for (int j = 0; j < nj; ++j) v += b_ttv_job(J[j], R, y, r);
-    out[e] = v;
+    gl(out)[e] = v;
   }
 }
 
@@ -361,8 +396,8 @@ __global__ __launch_bounds__(BSOLVE_WAVES * 64) void k_b_solve(const BProb* pr, 
   const int tid = threadIdx.x, nthr = blockDim.x, w = tid >> 6, l = tid & 63;
   const bool lv = l < R;
   const int lc = lv ? l : 0;
-  const double* S = P.S;
-  const double* U = P.U;
+  const GLB double* S = gl(P.S);
+  const GLB double* U = gl(P.U);
   double dmax = 0.0;
   for (int e = tid; e < 64 * CH64_LS; e += nthr) {
     const int r = e / CH64_LS, c = e - r * CH64_LS;
@@ -419,10 +454,10 @@ __global__ __launch_bounds__(BSOLVE_WAVES * 64) void k_b_solve(const BProb* pr, 
 #pragma unroll
   for (int t = 0; t < BSOLVE_TPW; ++t) gacc[t] = d4{0.0, 0.0, 0.0, 0.0};
   double nd = 0.0, na = 0.0, nm = 0.0;
-  double* An = P.A[n];
-  const double* M = P.M;
-  const double* Apn = P.Ap[n];
-  double* dAn = P.dA[n];
+  GLB double* An = gl(P.A[n]);
+  const GLB double* M = gl(P.M);
+  const GLB double* Apn = gl(P.Ap[n]);
+  GLB double* dAn = gl(P.dA[n]);
   double* bw = bv + w * BSOLVE_RPW * 64;
   const double dl = lv ? invd[lc] : 0.0;
   for (int c0 = 0; c0 < rows; c0 += BSOLVE_CH) {
@@ -537,7 +572,7 @@ __global__ __launch_bounds__(BSOLVE_WAVES * 64) void k_b_solve(const BProb* pr, 
       const bool isU = tt >= NBR * NBR;
       const int tl = isU ? tt - NBR * NBR : tt;
       const int r0 = (tl / NBR) * 16, cc0 = (tl % NBR) * 16;
-      double* out = (isU ? P.U : P.S) + (size_t)n * RR;
+      GLB double* out = gl(isU ? P.U : P.S) + (size_t)n * RR;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = r0 + 4 * v + (l >> 4), c = cc0 + (l & 15);
@@ -621,7 +656,7 @@ __global__ __launch_bounds__(256) void k_b_f32(const BProb* pr, const BState* st
     const int sn = P.s[n], Kpad = (sn + BKC - 1) / BKC * BKC;
     for (int e = threadIdx.x; e < R * sn; e += 256) {  // columns >= R and rows >= s_n stay 0
       const int c = e / sn, y = e - c * sn;
-      P.Af[n][c * Kpad + y] = (float)P.A[n][y * R + c];
+      gl(P.Af[n])[c * Kpad + y] = (float)gl(P.A[n])[y * R + c];
     }
   }
 }
@@ -634,11 +669,11 @@ __global__ __launch_bounds__(256) void k_b_norm(const BProb* pr, BState* st, con
   const int p = blockIdx.x;
   if (p >= count) return;
   const BProb& P = pr[p];
-  for (int k = threadIdx.x; k < conf->max_sweeps; k += 256) P.klog[k] = 0;
+  for (int k = threadIdx.x; k < conf->max_sweeps; k += 256) gl(P.klog)[k] = 0;
   const int64_t total = (int64_t)P.s[0] * P.s[1] * P.s[2];
   double a = 0.0;
   for (int64_t e = threadIdx.x; e < total; e += 256) {
-    const double v = P.X[e];
+    const double v = gl(P.X)[e];
     a = fma(v, v, a);
   }
   a = wsum(a);
@@ -649,14 +684,15 @@ __global__ __launch_bounds__(256) void k_b_norm(const BProb* pr, BState* st, con
     for (int e = threadIdx.x; e < R * R; e += 256) {
       const int r = e / R, c = e - r * R;
       double g = 0.0;
-      for (int y = 0; y < P.s[n]; ++y) g = fma(P.A[n][y * R + r], P.A[n][y * R + c], g);
-      P.S[n * R * R + e] = g;
+      const GLB double* An = gl(P.A[n]);
+      for (int y = 0; y < P.s[n]; ++y) g = fma(An[y * R + r], An[y * R + c], g);
+      gl(P.S)[n * R * R + e] = g;
     }
   for (int n = 0; n < 3; ++n) {
     const int Kpad = (P.s[n] + BKC - 1) / BKC * BKC;
     for (int e = threadIdx.x; e < Kpad * BATCH_MAX_R; e += 256) {
       const int c = e / Kpad, y = e - c * Kpad;
-      P.Af[n][e] = (y < P.s[n] && c < R) ? (float)P.A[n][y * R + c] : 0.f;
+      gl(P.Af[n])[e] = (y < P.s[n] && c < R) ? (float)gl(P.A[n])[y * R + c] : 0.f;
     }
   }
   __syncthreads();
