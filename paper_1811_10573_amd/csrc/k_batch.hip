@@ -288,33 +288,23 @@ __global__ __launch_bounds__(256) void k_b_gemm(const BProb* pr, const BState* s
 
 // ---------------------------------------------------------------------------
 // Grouped multi-TTV: out[y][r] = base[y][r] + sum_jobs sum_x T[p][x][q][r] F[x][r],
-// y = p Q + q.  One thread per output element, FP64 accumulation.
+// y = p Q + q, FP64 accumulation, one output element per thread.  A workgroup's 256
+// elements belong to one problem and share F: it passes through LDS BTTV_XC rows at a
+// time (double-buffered, one barrier per chunk), so each F entry is read from global
+// memory once per workgroup instead of once per output row.  The chunk's T values are
+// requested before the chunk's F rows are stored, so both loads overlap.
 // ---------------------------------------------------------------------------
+constexpr int BTTV_XC = 32;  // x per chunk
+
 struct BJob {
   const float* T;
   const double* F;
   int P, X, Q;
 };
 
-__device__ __forceinline__ double b_ttv_job(const BJob& J, int R, int y, int r) {
-  const int p = y / J.Q, q = y - p * J.Q;
-  const int64_t QR = (int64_t)J.Q * R;
-  const GLB float* t = gl(J.T) + (int64_t)p * J.X * QR + (int64_t)q * R + r;
-  const GLB double* F = gl(J.F);
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  int x = 0;
-  for (; x + 3 < J.X; x += 4) {
-    a0 = fma((double)t[(int64_t)x * QR], F[(int64_t)x * R + r], a0);
-    a1 = fma((double)t[(int64_t)(x + 1) * QR], F[(int64_t)(x + 1) * R + r], a1);
-    a2 = fma((double)t[(int64_t)(x + 2) * QR], F[(int64_t)(x + 2) * R + r], a2);
-    a3 = fma((double)t[(int64_t)(x + 3) * QR], F[(int64_t)(x + 3) * R + r], a3);
-  }
-  for (; x < J.X; ++x) a0 = fma((double)t[(int64_t)x * QR], F[(int64_t)x * R + r], a0);
-  return (a0 + a1) + (a2 + a3);
-}
-
 __global__ __launch_bounds__(256) void k_b_ttv(const BProb* pr, const BState* st, const BTile* tiles,
                                                int ntiles, int n, int build_mp) {
+  __shared__ double fsh[2 * BTTV_XC * BATCH_MAX_R];
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const BTile tile = tiles[t];
     const int p = tile.prob;
@@ -323,9 +313,11 @@ __global__ __launch_bounds__(256) void k_b_ttv(const BProb* pr, const BState* st
     const BProb& P = pr[p];
     const int R = P.R;
     const int s0 = P.s[0], s1 = P.s[1], s2 = P.s[2];
+    const int ne = P.s[n] * R;
     const int e = tile.m0 + threadIdx.x;
-    if (e >= P.s[n] * R) continue;
-    const int y = e / R, r = e - (e / R) * R;
+    const bool act = e < ne;
+    const int ec = act ? e : ne - 1;
+    const int y = ec / R, r = ec - y * R;
     BJob J[2];
     int nj = 0;
     const double* base = nullptr;
@@ -350,9 +342,42 @@ __global__ __launch_bounds__(256) void k_b_ttv(const BProb* pr, const BState* st
         J[nj++] = BJob{P.op[2], P.dA[1], 1, s1, s2};
       }
     }
-    double v = base ? gl(base)[e] : 0.0;
-    for (int j = 0; j < nj; ++j) v += b_ttv_job(J[j], R, y, r);
-    gl(out)[e] = v;
+    double acc0 = 0.0, acc1 = 0.0;
+    int buf = 0;
+    __syncthreads();  // the previous tile's last chunk is no longer read
+    for (int j = 0; j < nj; ++j) {
+      const int X = J[j].X, QR = J[j].Q * R;
+      const int pp = y / J[j].Q, q = y - pp * J[j].Q;
+      const GLB float* T = gl(J[j].T) + ((int64_t)pp * X * QR + (int64_t)q * R + r);
+      const GLB double* F = gl(J[j].F);
+      for (int x0 = 0; x0 < X; x0 += BTTV_XC) {
+        const int xn = min(BTTV_XC, X - x0), cnt = xn * R;
+        double* fl = fsh + buf * (BTTV_XC * BATCH_MAX_R);
+        double fr[BTTV_XC * BATCH_MAX_R / 256];
+#pragma unroll
+        for (int i = 0; i < BTTV_XC * BATCH_MAX_R / 256; ++i) {
+          const int idx = (int)threadIdx.x + 256 * i;
+          fr[i] = F[(int64_t)x0 * R + min(idx, cnt - 1)];
+        }
+        float tv[BTTV_XC];
+#pragma unroll
+        for (int xx = 0; xx < BTTV_XC; ++xx) tv[xx] = T[(int64_t)(x0 + min(xx, xn - 1)) * QR];
+#pragma unroll
+        for (int i = 0; i < BTTV_XC * BATCH_MAX_R / 256; ++i) {
+          const int idx = (int)threadIdx.x + 256 * i;
+          if (idx < cnt) fl[idx] = fr[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int xx = 0; xx < BTTV_XC; xx += 2) {
+          const double f0 = fl[min(xx, xn - 1) * R + r], f1 = fl[min(xx + 1, xn - 1) * R + r];
+          acc0 = fma(xx < xn ? (double)tv[xx] : 0.0, f0, acc0);
+          acc1 = fma(xx + 1 < xn ? (double)tv[xx + 1] : 0.0, f1, acc1);
+        }
+        buf ^= 1;
+      }
+    }
+    if (act) gl(out)[e] = (base ? gl(base)[e] : 0.0) + (acc0 + acc1);
   }
 }
 
@@ -750,8 +775,8 @@ hipError_t launch_b_gemm(int variant, const BProb* pr, const BState* st, const B
 hipError_t launch_b_ttv(const BProb* pr, const BState* st, const BTile* tiles, int ntiles, int mode,
                         int build_mp, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_b_ttv, dim3(grid_for(ntiles)), dim3(256), 0, s, pr, st, tiles, ntiles, mode,
-                     build_mp);
+  hipLaunchKernelGGL(k_b_ttv, dim3(ntiles < 16384 ? ntiles : 16384), dim3(256), 0, s, pr, st, tiles,
+                     ntiles, mode, build_mp);
   return hipGetLastError();
 }
 static size_t b_solve_lds(int maxR) {
