@@ -145,6 +145,9 @@ struct BStage {
 //   !KCM, VEC: rows contiguous for fixed k; one 16-byte load gives VW = MB rows.
 //   !KCM, !VEC: scalar loads.
 // ---------------------------------------------------------------------------
+// Zeros read in place of X entries outside the tensor (64 bytes covers the widest read).
+__device__ __attribute__((aligned(16))) double l1_zero[8];
+
 template <int DT, int MB, int NB, bool KCM, bool VEC>
 __global__ __launch_bounds__(256) void k_level1_reg(const typename L1T<DT>::T* __restrict__ X,
                                                     const typename L1T<DT>::T* __restrict__ B,
@@ -209,6 +212,11 @@ __global__ __launch_bounds__(256) void k_level1_reg(const typename L1T<DT>::T* _
   // X registers for one chunk: xr[b][t] = A-operand of m-block b at step t.
   T xc[MB][NSTEP], xn[MB][NSTEP];
 
+  // Loads are unconditional: an invalid row or k reads zeros from l1_zero instead.  A
+  // guarded load becomes a branch, around which the number of outstanding loads is not
+  // known, and a zero select right after the load makes it wait there; either way the
+  // wait for the current chunk would also wait for the next chunk's prefetch.
+  const T* zero = reinterpret_cast<const T*>(l1_zero);
   auto load_x = [&](T (&xr)[MB][NSTEP], int64_t kbase) {
     if (KCM) {
 #pragma unroll
@@ -218,10 +226,10 @@ __global__ __launch_bounds__(256) void k_level1_reg(const typename L1T<DT>::T* _
           const bool ok = rowok[b] && (k0 < kb1);
           using VT = typename Vec16<T>::type;
           constexpr int VN = Vec16<T>::n;
-          const VT* src = reinterpret_cast<const VT*>(X + base[b] + k0);
+          const VT* src = reinterpret_cast<const VT*>(ok ? X + base[b] + k0 : zero);
 #pragma unroll
           for (int v = 0; v < 8 / VN; ++v) {
-            const VT val = ok ? src[v] : VT{};
+            const VT val = src[v];
 #pragma unroll
             for (int e = 0; e < VN; ++e) xr[b][v * VN + e] = val[e];
           }
@@ -229,7 +237,7 @@ __global__ __launch_bounds__(256) void k_level1_reg(const typename L1T<DT>::T* _
 #pragma unroll
           for (int t = 0; t < NSTEP; ++t) {
             const int64_t k = k0 + t;
-            xr[b][t] = (rowok[b] && k < kb1) ? X[base[b] + k] : (T)0;
+            xr[b][t] = *((rowok[b] && k < kb1) ? X + base[b] + k : zero);
           }
         }
       }
@@ -237,9 +245,8 @@ __global__ __launch_bounds__(256) void k_level1_reg(const typename L1T<DT>::T* _
 #pragma unroll
       for (int t = 0; t < NSTEP; ++t) {
         const int64_t k = kbase + 4 * t + kk;
-        const bool ok = rowok[0] && (k < kb1);
         using VT = typename Vec16<T>::type;
-        const VT val = ok ? *reinterpret_cast<const VT*>(X + base[0] + k * gQ) : VT{};
+        const VT val = *reinterpret_cast<const VT*>((rowok[0] && k < kb1) ? X + base[0] + k * gQ : zero);
 #pragma unroll
         for (int b = 0; b < MB; ++b) xr[b][t] = val[b];
       }
@@ -248,8 +255,7 @@ __global__ __launch_bounds__(256) void k_level1_reg(const typename L1T<DT>::T* _
       for (int t = 0; t < NSTEP; ++t) {
         const int64_t k = kbase + 4 * t + kk;
 #pragma unroll
-        for (int b = 0; b < MB; ++b)
-          xr[b][t] = (rowok[b] && k < kb1) ? X[base[b] + k * gQ] : (T)0;
+        for (int b = 0; b < MB; ++b) xr[b][t] = *((rowok[b] && k < kb1) ? X + base[b] + k * gQ : zero);
       }
     }
   };
@@ -260,20 +266,27 @@ __global__ __launch_bounds__(256) void k_level1_reg(const typename L1T<DT>::T* _
 #pragma unroll
     for (int c = 0; c < NB; ++c) acc[b][c] = V{0, 0, 0, 0};
 
-  // Prologue: chunk 0 of B into LDS buffer 0, X chunk 0 into registers.
+  // Prologue: chunk 0 of B into LDS buffer 0, X chunk 0 into the prefetch registers.
+  // Each chunk first takes the prefetched X (xc = xn: the only wait for global loads
+  // before the matrix cores start) and then issues the next chunk's B and X loads, B
+  // first, so that storing B into LDS after the MFMAs waits for B alone.
   const int64_t chunk0 = kb0 / KC;
   BStage<NVEC> st;
   st.load(Bslice + chunk0 * NVEC);
   st.store(reinterpret_cast<uint4*>(ldsB[0]));
-  load_x(xc, kb0);
+  load_x(xn, kb0);
   __syncthreads();
 
   for (int ch = 0; ch < nch; ++ch) {
     const int buf = ch & 1;
     const bool more = ch + 1 < nch;
+#pragma unroll
+    for (int b = 0; b < MB; ++b)
+#pragma unroll
+      for (int t = 0; t < NSTEP; ++t) xc[b][t] = xn[b][t];
     if (more) {
-      load_x(xn, kb0 + (int64_t)(ch + 1) * KC);
       st.load(Bslice + (chunk0 + ch + 1) * NVEC);
+      load_x(xn, kb0 + (int64_t)(ch + 1) * KC);
     }
     const T* lb = ldsB[buf];
 #pragma unroll
@@ -288,12 +301,6 @@ __global__ __launch_bounds__(256) void k_level1_reg(const typename L1T<DT>::T* _
     }
     if (more) st.store(reinterpret_cast<uint4*>(ldsB[buf ^ 1]));
     __syncthreads();
-    if (more) {
-#pragma unroll
-      for (int b = 0; b < MB; ++b)
-#pragma unroll
-        for (int t = 0; t < NSTEP; ++t) xc[b][t] = xn[b][t];
-    }
   }
 
   // Store: accumulator register r of lane l holds row acc_row(l, r), column l % 16.
