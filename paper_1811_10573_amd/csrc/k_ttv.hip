@@ -102,7 +102,7 @@ template <> struct TtvVecT<double> {
     o[0] = v.x; o[1] = v.y;
   }
 };
-constexpr int TTV_U = 4;                         // vectors in flight per lane
+constexpr int TTV_U = 8;                         // vectors in flight per lane
 constexpr int TTV_W = TTV_VTHREADS / 64;         // waves per workgroup
 
 // TTV_SLAB: workgroup (pair of slabs p, p + 1; split); wave w takes iterations w, w + TTV_W,
