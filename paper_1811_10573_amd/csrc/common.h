@@ -182,6 +182,11 @@ hipError_t launch_head(const HeadArgs& h, hipStream_t s);
 hipError_t launch_solve_fused(const FusedSolveArgs& a, hipStream_t s);
 int solve_fused_blocks(int64_t rows);
 hipError_t launch_gram_tiles(const GramArgs& a, hipStream_t s);
+// The contraction jobs of a PP mode, the Grams of the previous mode (g may be NULL) and
+// the head of this mode in one launch; ctr is a device int that is zero between launches.
+bool ttv_tail_fusable(const TtvBatch& b);
+hipError_t launch_ttv_tail(const TtvBatch& b, const GramArgs* g, const HeadArgs& h, int* ctr,
+                           hipStream_t s);
 hipError_t launch_set_int(int* p, int v, hipStream_t s);
 hipError_t launch_pp_gate_ring(void* rec, int N, double eps, int* gate, void* ring, int* ctr,
                                hipStream_t s);

@@ -18,138 +18,17 @@
 //     runs on the main stream.
 #include "common.h"
 #include "tail_dev.h"
+#include "tail_bodies.h"
 #include <algorithm>
 #include "../../include/ppals.h"
 
 namespace ppk {
 
-// Gamma^(n)[e] = prod_{i != n} S^(i)[e]
-__device__ __forceinline__ double gamma_entry(const double* S, int N, int n, int64_t RR, int e) {
-  double sv[PP_MAXN];
-#pragma unroll
-  for (int i = 0; i < PP_MAXN; ++i) sv[i] = (i < N && i != n) ? S[i * RR + e] : 1.0;
-  double v = 1.0;
-#pragma unroll
-  for (int i = 0; i < PP_MAXN; ++i) v *= sv[i];
-  return v;
-}
-
-constexpr int HEAD_THREADS = 256;
-
-// Head of mode n (one workgroup of four waves): Gamma^(n), W^(n) (PP), the Cholesky
-// factor (wave 0, one diagonal-shift retry) and the solve operands.  Small enough to be
-// co-resident with the contraction kernels that run meanwhile on the other stream.  NM
-// is the tensor order; thread t takes row t / 4 and columns t % 4 + 4 j, a batch of CB
-// columns at a time with the loads of every other mode's S (and U) issued together.
 template <int NM>
 __global__ __launch_bounds__(HEAD_THREADS) void k_head(HeadArgs h) {
-  constexpr int NO = NM - 1;                 // modes other than n
-  constexpr int CB = 16 / NO > 1 ? 16 / NO : 2;
-  __shared__ double Lm[64 * CH64_LS];        // Gamma, zero-padded to 64 x 64
-  __shared__ double cb[128];
-  __shared__ double red[HEAD_THREADS / 64];
+  __shared__ double lds[HEAD_LDS];
   if (h.gate && *h.gate == 0) return;
-  __builtin_amdgcn_s_setprio(3);  // latency-bound: first in line for issue beside streaming kernels
-  const int tid = threadIdx.x;
-  const int R = h.R, RR = R * R;
-  const int n = h.n;
-  const bool wterm = h.pp && h.second_order;
-  for (int e = tid; e < 64 * CH64_LS; e += HEAD_THREADS) {
-    const int r = e / CH64_LS, c = e - r * CH64_LS;
-    if (r >= R || c >= R) Lm[e] = 0.0;
-  }
-  const int row = tid >> 2, c0 = tid & 3;
-  double dmax = 0.0;
-  if (h.gamma_ready) {
-    if (row < R) {
-      double gv[16];
-#pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const int c = c0 + 4 * j;
-        gv[j] = h.gamma[row * R + (c < R ? c : 0)];
-      }
-#pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const int c = c0 + 4 * j;
-        if (c < R) {
-          Lm[row * CH64_LS + c] = gv[j];
-          if (row == c) dmax = fmax(dmax, gv[j]);
-        }
-      }
-    }
-  } else if (row < R) {
-    for (int j0 = 0; c0 + 4 * j0 < R; j0 += CB) {
-      double sv[CB][NO], uv[CB][NO];
-#pragma unroll
-      for (int j = 0; j < CB; ++j) {
-        const int c = c0 + 4 * (j0 + j);
-        const int e = row * R + (c < R ? c : 0);
-#pragma unroll
-        for (int k = 0; k < NO; ++k) {
-          const int mk = k + (k >= n ? 1 : 0);
-          sv[j][k] = h.S[(int64_t)mk * RR + e];
-          uv[j][k] = wterm ? h.U[(int64_t)mk * RR + e] : 0.0;
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < CB; ++j) {
-        const int c = c0 + 4 * (j0 + j);
-        if (c < R) {
-          // Running sums over the modes k != n: P0 = prod s_k (= Gamma), P1 = sum_i u_i
-          // prod_{k != i} s_k, P2 = sum_{i<j} u_i u_j prod_{k != i,j} s_k (= W).
-          double P0 = 1.0, P1 = 0.0, P2 = 0.0;
-#pragma unroll
-          for (int k = 0; k < NO; ++k) {
-            P2 = fma(P2, sv[j][k], P1 * uv[j][k]);
-            P1 = fma(P1, sv[j][k], P0 * uv[j][k]);
-            P0 *= sv[j][k];
-          }
-          const int e = row * R + c;
-          h.gamma[e] = P0;
-          Lm[row * CH64_LS + c] = P0;
-          if (row == c) dmax = fmax(dmax, P0);
-          if (wterm) h.W[e] = P2;
-        }
-      }
-    }
-  }
-  for (int off = 32; off > 0; off >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, off));
-  if ((tid & 63) == 0) red[tid >> 6] = dmax;
-  __syncthreads();
-  if (tid < 64) {  // the factorisation is wave 0's alone; the other waves wait below
-    int st = 0;
-    for (int attempt = 0;; ++attempt) {
-      if (chol_wave64(Lm, cb, R)) break;
-      if (attempt == 1) {
-        st = 2;
-        break;
-      }
-      double mx = 0.0;
-      for (int i = 0; i < HEAD_THREADS / 64; ++i) mx = fmax(mx, red[i]);
-      const double delta = (double)R * 0x1p-52 * mx;
-      for (int e = tid; e < 64 * CH64_LS; e += 64) {
-        const int r = e / CH64_LS, c = e - r * CH64_LS;
-        Lm[e] = (r < R && c < R) ? gamma_entry(h.S, h.N, n, RR, r * R + c) + (r == c ? delta : 0.0) : 0.0;
-      }
-      st = 1;
-    }
-    if (tid < R) cb[tid] = 1.0 / Lm[tid * CH64_LS + tid];
-    if (tid == 0) h.status[n] = st;
-  }
-  __syncthreads();
-  // the solve operands: LF[k][i] = L[i][k] / L[k][k] (i > k), LB[i][k] = L[i][k] / L[i][i]
-  // (k < i), zero elsewhere, then 1 / L[i][i]
-  double* LF = h.pack;
-  double* LB = LF + RR;
-  if (row < R) {
-    const double di = cb[row];
-    for (int c = c0; c < R; c += 4) {
-      const double v = c <= row ? Lm[row * CH64_LS + c] : 0.0;
-      LF[c * R + row] = row > c ? v * cb[c] : 0.0;
-      LB[row * R + c] = c < row ? v * di : 0.0;
-    }
-    if (c0 == 0) LB[RR + row] = di;
-  }
+  head_body<NM>(h, lds, lds + 64 * CH64_LS, lds + 64 * CH64_LS + 128);
 }
 
 // ---------------------------------------------------------------------------
@@ -158,7 +37,6 @@ __global__ __launch_bounds__(HEAD_THREADS) void k_head(HeadArgs h) {
 // ---------------------------------------------------------------------------
 constexpr int SOLVE_WAVES = 4;
 constexpr int SOLVE_BR = SOLVE_WAVES;               // rows per block
-constexpr int NPART = 5;                            // per-block norm partials
 
 // Fused right-hand-side assembly + solve.  Per row: M~ = base + sum of the contraction's
 // partial slots + A_old W (PP second-order term); then Gamma x = M~ through L L^T with
@@ -322,172 +200,14 @@ __global__ __launch_bounds__(SOLVE_WAVES * 64) void k_solve_fused(FusedSolveArgs
   }
 }
 
-// Grams of the updated factor on the matrix cores: S = A^T A and, in PP sweeps,
-// U = A^T dA.  One workgroup of GRAM_WAVES waves per 16 x 16 output tile, computing the
-// tile of S and of U from one read of A's tile columns; each wave takes GRAM_U groups of
-// 4 rows at a time and loads the next groups before the current matrix-core steps
-// (f64 16x16x4: lane l supplies A[y0 + l/16][r0 + l%16] and B[y0 + l/16][c0 + l%16];
-// accumulator register v holds tile row 4v + l/16, column l%16).  When asked, each
-// workgroup also forms its tile of Gamma^(next) and W^(next) for the following mode's
-// head, with the other modes' S and U tiles loaded at the start.  Block 0 also reduces the
-// solve's per-block partials into the sweep record (and the fit).
 constexpr int GRAM_WAVES = 16;
-constexpr int GRAM_U = 4;
 
 __global__ __launch_bounds__(GRAM_WAVES * 64) void k_gram_tiles(GramArgs a) {
-  __shared__ double racc[(GRAM_WAVES / 2) * 2 * 4 * 64];
-  __shared__ double tileS[256], tileU[256];
+  __shared__ double racc[GRAM_RACC(GRAM_WAVES)];
+  __shared__ double tiles[512];
   extern __shared__ double tileO[];  // the other modes' S and U tiles, (N - 2) x 2 x 256
   if (a.gate && *a.gate == 0) return;
-  __builtin_amdgcn_s_setprio(3);
-  const int tid = threadIdx.x;
-  const int w = tid >> 6, l = tid & 63;
-  const int R = a.R, RR = R * R;
-  const int NBR = (R + 15) / 16;
-  const int r0 = (blockIdx.x / NBR) * 16, c0 = (blockIdx.x % NBR) * 16;
-  const bool has_u = a.dA != nullptr;
-  // this thread's tile entry for Gamma^(next): the other modes' S and U, loaded up front
-  const bool want_g = a.gamma_out != nullptr;
-  const int te_r = r0 + ((tid & 255) >> 4), te_c = c0 + (tid & 15);
-  const bool te_ok = want_g && te_r < R && te_c < R;
-  const int ky = l >> 4, cc = l & 15;
-  const bool oka = r0 + cc < R, okb = c0 + cc < R;
-  const int64_t rows = a.rows;
-  d4 accS = {0.0, 0.0, 0.0, 0.0}, accU = {0.0, 0.0, 0.0, 0.0};
-  double xa[GRAM_U], xb[GRAM_U], xd[GRAM_U];
-  auto load = [&](int64_t y0, double (&va)[GRAM_U], double (&vb)[GRAM_U], double (&vd)[GRAM_U]) {
-#pragma unroll
-    for (int u = 0; u < GRAM_U; ++u) {
-      const int64_t y = y0 + 4 * u + ky;
-      const bool in = y < rows;
-      va[u] = (in && oka) ? a.A[y * R + r0 + cc] : 0.0;
-      vb[u] = (in && okb) ? a.A[y * R + c0 + cc] : 0.0;
-      vd[u] = (in && okb && has_u) ? a.dA[y * R + c0 + cc] : 0.0;
-    }
-  };
-  const int64_t step = (int64_t)4 * GRAM_U * GRAM_WAVES;
-  int64_t y0 = (int64_t)w * 4 * GRAM_U;
-  load(y0, xa, xb, xd);
-  if (want_g) {
-    // the other modes' tiles, in the same round trip as the first operands: thread t takes
-    // entry t % 256 of mode k = t / 256 + 4 j (S and U)
-    // (other mode o = the o-th mode that is neither this one nor the next)
-    const int e = te_ok ? te_r * R + te_c : 0;
-#pragma unroll
-    for (int j = 0; j < (PP_MAXN - 2 + 3) / 4; ++j) {
-      const int o = (tid >> 8) + 4 * j;
-      int k = -1;
-      for (int q = 0, cnt = 0; q < a.N; ++q)
-        if (q != a.mode && q != a.next && cnt++ == o) k = q;
-      if (k >= 0) {
-        const double sv = a.S_all[(int64_t)k * RR + e];
-        const double uv = a.wterm ? a.U_all[(int64_t)k * RR + e] : 0.0;
-        tileO[(o * 2 + 0) * 256 + (tid & 255)] = sv;
-        tileO[(o * 2 + 1) * 256 + (tid & 255)] = uv;
-      }
-    }
-  }
-  for (; y0 < rows; y0 += step) {
-    double na[GRAM_U], nb[GRAM_U], nd[GRAM_U];
-    const bool more = y0 + step < rows;
-    if (more) load(y0 + step, na, nb, nd);
-#pragma unroll
-    for (int u = 0; u < GRAM_U; ++u) {
-      accS = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u], xb[u], accS, 0, 0, 0);
-      if (has_u) accU = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u], xd[u], accU, 0, 0, 0);
-    }
-    if (more) {
-#pragma unroll
-      for (int u = 0; u < GRAM_U; ++u) {
-        xa[u] = na[u];
-        xb[u] = nb[u];
-        xd[u] = nd[u];
-      }
-    }
-  }
-  // two-stage reduction over the waves: the upper half adds into the lower half
-  constexpr int HW = GRAM_WAVES / 2;
-  if (w >= HW) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      racc[(((w - HW) * 2 + 0) * 4 + v) * 64 + l] = accS[v];
-      racc[(((w - HW) * 2 + 1) * 4 + v) * 64 + l] = accU[v];
-    }
-  }
-  __syncthreads();
-  if (w < HW) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      racc[((w * 2 + 0) * 4 + v) * 64 + l] += accS[v];
-      racc[((w * 2 + 1) * 4 + v) * 64 + l] += accU[v];
-    }
-  }
-  __syncthreads();
-  if (w < 2 && (w == 0 || has_u)) {
-    double* out = w ? a.U_out : a.S_out;
-    double* tile = w ? tileU : tileS;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      double sum = 0.0;
-      for (int q = 0; q < HW; ++q) sum += racc[((q * 2 + w) * 4 + v) * 64 + l];
-      const int tr = 4 * v + (l >> 4), tc = l & 15;
-      const int r = r0 + tr, c = c0 + tc;
-      if (r < R && c < R) out[r * R + c] = sum;
-      tile[tr * 16 + tc] = sum;
-    }
-  }
-  if (want_g) {
-    __syncthreads();
-    if (te_ok && tid < 256) {
-      // Running sums over the modes k != next (order of k as in the head): P0 = Gamma,
-      // P2 = W (second-order term)
-      double P0 = 1.0, P1 = 0.0, P2 = 0.0;
-      int o = 0;
-      for (int k = 0; k < a.N; ++k) {
-        if (k == a.next) continue;
-        double sk, uk;
-        if (k == a.mode) {
-          sk = tileS[tid];
-          uk = has_u ? tileU[tid] : 0.0;
-        } else {
-          sk = tileO[(o * 2 + 0) * 256 + tid];
-          uk = tileO[(o * 2 + 1) * 256 + tid];
-          ++o;
-        }
-        P2 = fma(P2, sk, P1 * uk);
-        P1 = fma(P1, sk, P0 * uk);
-        P0 *= sk;
-      }
-      const int e = te_r * R + te_c;
-      a.gamma_out[e] = P0;
-      if (a.wterm) a.W_out[e] = P2;
-    }
-  }
-  if (blockIdx.x != 0) return;
-  // record for this mode from the solve's per-block partials
-  __shared__ double sums[NPART];
-  if (w == 0) {
-    double v[NPART] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int b = l; b < a.nblk; b += 64)
-#pragma unroll
-      for (int c = 0; c < NPART; ++c) v[c] += a.blockpart[(int64_t)b * NPART + c];
-#pragma unroll
-    for (int c = 0; c < NPART; ++c) v[c] = wsum(v[c]);
-    if (l == 0) {
-#pragma unroll
-      for (int c = 0; c < NPART; ++c) sums[c] = v[c];
-      ppals_sweep_record* rec = (ppals_sweep_record*)a.rec;
-      const double g2 = sums[0], d2 = sums[1], a2 = sums[2];
-      rec->grad_norm[a.mode] = sqrt(g2);
-      rec->rel_change[a.mode] = a2 > 0.0 ? sqrt(d2) / sqrt(a2) : (d2 > 0.0 ? INFINITY : 0.0);
-      rec->chol_status[a.mode] = *a.status;
-      if (a.write_fit) {
-        const double r2 = a.normX2 - 2.0 * sums[3] + sums[4];
-        rec->fit_est = 1.0 - sqrt(r2 > 0.0 ? r2 : 0.0) / sqrt(a.normX2);
-        rec->sweep_kind = a.sweep_kind;
-      }
-    }
-  }
+  gram_body<GRAM_WAVES>(a, blockIdx.x, racc, tiles, tiles + 256, tileO);
 }
 
 // ---------------------------------------------------------------------------

@@ -11,6 +11,7 @@
 // TTV_THREADS threads; when Q*R < TTV_THREADS the threads are split into G groups that
 // read G consecutive x-rows at once and are reduced through LDS.  Accumulation is FP64.
 #include "common.h"
+#include "tail_bodies.h"
 #include <algorithm>
 
 namespace ppk {
@@ -272,6 +273,57 @@ __global__ __launch_bounds__(TTV_VTHREADS) void k_ttv_vec(TtvBatch b) {
   }
 }
 
+// One launch per mode of a PP sweep for the mode's contractions, the Grams of the previous
+// mode and the head of this mode, so that the solve after it depends on one kernel on one
+// stream (a dependency between streams costs several microseconds each way).  Workgroups
+// 0 .. ngram-1 take the Gram tiles (four waves each; they are dispatched first); the last
+// of them to finish, told by a device-scope counter that it resets, then runs the head
+// from the Gamma and W tiles the others left in global memory.  With ngram == 0 (first
+// mode of a sweep) workgroup 0 runs the head alone.  The other workgroups run the
+// contraction jobs exactly as k_ttv_vec does.  All roles share one dynamic LDS block.
+constexpr int TAIL_GRAM_WAVES = TTV_VTHREADS / 64;
+
+template <int NM>
+__global__ __launch_bounds__(TTV_VTHREADS) void k_ttv_tail(TtvBatch b, GramArgs g, HeadArgs h,
+                                                           int ngram, int* ctr) {
+  extern __shared__ double dyn[];
+  __shared__ int last;
+  if (b.gate && *b.gate == 0) return;
+  const int nrole = ngram > 0 ? ngram : 1;
+  if ((int)blockIdx.x < nrole) {
+    if (ngram > 0) {
+      double* racc = dyn;
+      double* tiles = racc + GRAM_RACC(TAIL_GRAM_WAVES);
+      gram_body<TAIL_GRAM_WAVES>(g, blockIdx.x, racc, tiles, tiles + 256, tiles + 512);
+      __threadfence();  // this tile's Gamma, W, S and U (and the record) before the count
+      __syncthreads();
+      if (threadIdx.x == 0) last = atomicAdd(ctr, 1) == ngram - 1;
+      __syncthreads();
+      if (!last) return;
+      __threadfence();  // the other tiles' writes are visible after the count
+      if (threadIdx.x == 0) *ctr = 0;
+    }
+    head_body<NM>(h, dyn, dyn + 64 * CH64_LS, dyn + 64 * CH64_LS + 128);
+    return;
+  }
+  int64_t bid = (int64_t)blockIdx.x - nrole;
+  int jid = 0;
+  while (jid < b.njobs - 1 && bid >= b.job[jid].blocks) {
+    bid -= b.job[jid].blocks;
+    ++jid;
+  }
+  const TtvJob& J = b.job[jid];
+  double* red = dyn;
+  double* fl = dyn + TTV_W * TTV_SLAB_PB * 256;
+  if (J.kind == TTV_SLAB) {
+    if (J.t_is_f32) ttv_slab<float>(J, b.R, bid, red);
+    else ttv_slab<double>(J, b.R, bid, red);
+  } else {
+    if (J.t_is_f32) ttv_rows<float>(J, b.R, bid, fl);
+    else ttv_rows<double>(J, b.R, bid, fl);
+  }
+}
+
 // out[idx] = (base ? base[idx] : 0) + sum_slots partial[slot][idx]
 //            + (W ? sum_l A[y][l] W[l][r] : 0),   idx = y*R + r
 __global__ __launch_bounds__(256) void k_combine(double* __restrict__ out, int64_t count, int R,
@@ -381,6 +433,59 @@ hipError_t launch_ttv(const TtvBatch& b, hipStream_t s) {
     return hipGetLastError();
   }
   return hipSuccess;
+}
+
+bool ttv_tail_fusable(const TtvBatch& b) {
+  if (b.R > 64) return false;
+  for (int i = 0; i < b.njobs; ++i) {
+    const TtvJob& J = b.job[i];
+    if (J.blocks <= 0) continue;
+    if (J.kind == TTV_SCALAR || (uintptr_t)J.T % 16 != 0) return false;
+  }
+  return true;
+}
+
+hipError_t launch_ttv_tail(const TtvBatch& b, const GramArgs* g, const HeadArgs& h, int* ctr,
+                           hipStream_t s) {
+  if (!ttv_tail_fusable(b) || h.R != b.R || h.N < 2 || h.N > PP_MAXN) return hipErrorInvalidValue;
+  TtvBatch vb = b;
+  vb.njobs = 0;
+  int64_t vtotal = 0;
+  size_t ttv_lds = (size_t)TTV_W * TTV_SLAB_PB * 256;
+  size_t fl = 0;
+  for (int i = 0; i < b.njobs; ++i) {
+    const TtvJob& J = b.job[i];
+    if (J.blocks <= 0) continue;
+    TtvJob& V = vb.job[vb.njobs++];
+    V = J;
+    V.f_vec = (uintptr_t)J.F % 16 == 0;
+    vtotal += J.blocks;
+    if (J.kind == TTV_ROWS) fl = std::max(fl, (size_t)J.xs * b.R);
+  }
+  const int NBR = (b.R + 15) / 16;
+  const int ngram = g ? NBR * NBR : 0;
+  const size_t gram_lds = (size_t)GRAM_RACC(TAIL_GRAM_WAVES) + 512 +
+                          (g && g->gamma_out ? (size_t)std::max(1, g->N - 2) * 512 : 0);
+  const size_t lds = std::max({ttv_lds + fl, gram_lds, (size_t)HEAD_LDS}) * sizeof(double);
+  GramArgs ga{};
+  if (g) ga = *g;
+  const dim3 grid((unsigned)((ngram > 0 ? ngram : 1) + vtotal)), block(TTV_VTHREADS);
+#define PPK_TAIL_CASE(NMV)                                                                        \
+  case NMV: {                                                                                     \
+    if (lds > 65536) {                                                                            \
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ttv_tail<NMV>),          \
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);   \
+      if (e != hipSuccess) return e;                                                              \
+    }                                                                                             \
+    hipLaunchKernelGGL(k_ttv_tail<NMV>, grid, block, lds, s, vb, ga, h, ngram, ctr);              \
+    break;                                                                                        \
+  }
+  switch (h.N) {
+    PPK_TAIL_CASE(2) PPK_TAIL_CASE(3) PPK_TAIL_CASE(4) PPK_TAIL_CASE(5)
+    PPK_TAIL_CASE(6) PPK_TAIL_CASE(7) PPK_TAIL_CASE(8)
+  }
+#undef PPK_TAIL_CASE
+  return hipGetLastError();
 }
 
 hipError_t launch_combine(double* out, int64_t count, int R, const double* base,

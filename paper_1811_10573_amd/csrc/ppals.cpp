@@ -119,6 +119,7 @@ struct ppals_plan {
   size_t off_Mx = 0, off_Mt = 0, off_errsum = 0;  // right-hand-side error measurement
   size_t off_gate = 0;                              // gate of PP sweeps enqueued ahead (int),
                                                     // then the ring position (int, +16 bytes)
+                                                    // and the fused tail's counter (int, +32)
   size_t off_ring = 0;                              // records of sweeps enqueued ahead
   const int* cur_gate = nullptr;  // set while the gated PP sweep is being captured
   bool fast = false;                   // rank <= 64: fused head/solve tail
@@ -1075,6 +1076,8 @@ ppals_status do_pp_sweep(ppals_plan* p, double* const* A, double* S, double norm
   int prev = -1;
   if (p->fast) {
     double* part = c.at<double>(p->off_ppart);
+    int* tail_ctr = c.at<int>(p->off_gate) + 8;
+    HIPCHK(launch_set_int(tail_ctr, 0, s));
     for (int n = 0; n < p->N; ++n) {
       TtvBatch b = p->ppb[n];
       b.gate = p->cur_gate;
@@ -1097,6 +1100,33 @@ ppals_status do_pp_sweep(ppals_plan* p, double* const* A, double* S, double norm
       by += (double)p->pp_slots[n] * p->dims[n] * p->R * 8;
       const HeadArgs h = head_args(c, S, n, 1);
       ppals_status st;
+      if (ttv_tail_fusable(b)) {
+        // contractions, the previous mode's Grams and this mode's head in one launch
+        HeadArgs h2 = h;
+        GramArgs g2;
+        const GramArgs* gp = nullptr;
+        if (prev >= 0) {
+          g2 = gram_args(c, A, S, prev, 1, normX2, rec, 0, kind);
+          g2.N = h.N;
+          g2.next = h.n;
+          g2.wterm = h.pp && h.second_order;
+          g2.S_all = h.S;
+          g2.U_all = h.U;
+          g2.gamma_out = h.gamma;
+          g2.W_out = h.W;
+          h2.gamma_ready = 1;
+          gp = &g2;
+        }
+        {
+          Prof pr(p, 1, s, fl, by);
+          HIPCHK(launch_ttv_tail(b, gp, h2, tail_ctr, s));
+          pr.end();
+        }
+        st = solve_fused(c, A, n, c.Mp(n), part, p->pp_slots[n], true, n == p->N - 1);
+        if (st != PPALS_OK) return st;
+        prev = n;
+        continue;
+      }
       if (prev >= 0) {
         const GramArgs g = gram_args(c, A, S, prev, 1, normX2, rec, 0, kind);
         st = tail_fork(c, &g, &h);
