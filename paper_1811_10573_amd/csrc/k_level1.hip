@@ -104,6 +104,11 @@ __global__ void k_prep_operand(KrpDesc krp, Level1Geom g, typename L1T<DT>::T* _
 __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+// 16 independent 4x4x1 outer products (block l/4: rows from lanes 4(l/4)..+3 of a, columns
+// from the same lanes of b; register v of lane l holds row v, column l%4 of its block)
+__device__ __forceinline__ f4 mfma_tail(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
+}
 __device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
@@ -148,7 +153,7 @@ struct BStage {
 // Zeros read in place of X entries outside the tensor (64 bytes covers the widest read).
 __device__ __attribute__((aligned(16))) double l1_zero[8];
 
-template <int DT, int MB, int NB, bool KCM, bool VEC>
+template <int DT, int MB, int NB, bool KCM, bool VEC, bool TAIL = false>
 __global__ __launch_bounds__(256) void k_level1_reg(const typename L1T<DT>::T* __restrict__ X,
                                                     const typename L1T<DT>::T* __restrict__ B,
                                                     Level1Geom g,
@@ -260,6 +265,15 @@ __global__ __launch_bounds__(256) void k_level1_reg(const typename L1T<DT>::T* _
     }
   };
 
+  // TAIL (FP32, at most four useful columns in the last 16-column block): the last block
+  // runs on the 4x4x1 matrix-core shape (16 blocks of 4 x 4 outer products, the same
+  // MACs per cycle) with the X register of the 16x16x4 steps as its B operand: lane l
+  // holds X[row(l%16)][k(l/16)], so block l/4 multiplies rows 4((l/4)%4) + 0..3 of the
+  // 16-row block by the four tail columns at the k of group l/16.  The four k groups are
+  // summed across lanes at the end.  This cuts the matrix-core time of the last block by
+  // a factor of four.
+  constexpr int NBF = TAIL ? NB - 1 : NB;  // blocks on the 16x16x4 shape
+  static_assert(!TAIL || DT == DT_F32, "tail path is FP32 only");
   V acc[MB][NB];
 #pragma unroll
   for (int b = 0; b < MB; ++b)
@@ -293,11 +307,15 @@ __global__ __launch_bounds__(256) void k_level1_reg(const typename L1T<DT>::T* _
     for (int t = 0; t < NSTEP; ++t) {
       T bop[NB];
 #pragma unroll
-      for (int c = 0; c < NB; ++c) bop[c] = lb[(t * NB + c) * 64 + l];
+      for (int c = 0; c < NBF; ++c) bop[c] = lb[(t * NB + c) * 64 + l];
+      // tail: lane l takes column 16 (NB - 1) + l%4 of its own k group
+      if constexpr (TAIL) bop[NB - 1] = lb[(t * NB + NB - 1) * 64 + (l & 48) + (l & 3)];
 #pragma unroll
-      for (int b = 0; b < MB; ++b)
+      for (int b = 0; b < MB; ++b) {
 #pragma unroll
-        for (int c = 0; c < NB; ++c) acc[b][c] = mfma(xc[b][t], bop[c], acc[b][c]);
+        for (int c = 0; c < NBF; ++c) acc[b][c] = mfma(xc[b][t], bop[c], acc[b][c]);
+        if constexpr (TAIL) acc[b][NB - 1] = mfma_tail(bop[NB - 1], xc[b][t], acc[b][NB - 1]);
+      }
     }
     if (more) st.store(reinterpret_cast<uint4*>(ldsB[buf ^ 1]));
     __syncthreads();
@@ -305,10 +323,25 @@ __global__ __launch_bounds__(256) void k_level1_reg(const typename L1T<DT>::T* _
 
   // Store: accumulator register r of lane l holds row acc_row(l, r), column l % 16.
   typename TR::Acc* Cz = C + (int64_t)z * c_split_stride;
+  if constexpr (TAIL) {
+    // tail block: register v of lane l holds column 16 (NB - 1) + v of row l%16 (in the
+    // row order of the 16x16x4 operand), partial over k group l/16
+#pragma unroll
+    for (int b = 0; b < MB; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        float sv = acc[b][NB - 1][v];
+        sv += __shfl_xor(sv, 16);
+        sv += __shfl_xor(sv, 32);
+        const int col = slice * 16 * NB + 16 * (NB - 1) + v;
+        const int64_t gr = (!KCM && VEC) ? (g0w + (int64_t)TR::VW * i + b) : (g0w + 16 * b + i);
+        if (l < 16 && col < gR && gr < gM) Cz[gr * gR + col] = sv;
+      }
+  }
 #pragma unroll
   for (int b = 0; b < MB; ++b)
 #pragma unroll
-    for (int c = 0; c < NB; ++c) {
+    for (int c = 0; c < NBF; ++c) {
       const int col = slice * 16 * NB + 16 * c + i;
       if (col >= gR) continue;
 #pragma unroll
@@ -544,6 +577,17 @@ static void launch_reg_nb(const void* X, const void* B, const Level1Geom& g, voi
   using Acc = typename TR::Acc;
   constexpr int BM = 4 * 16 * MB;
   dim3 grid((unsigned)((g.M + BM - 1) / BM), g.nslices, g.ksplit), block(256);
+  // FP32 with one column slice whose last 16-column block holds 1..4 useful columns
+  if constexpr (DT == DT_F32) {
+    const int rem = g.R - 16 * (g.NB - 1);
+    if (g.nslices == 1 && g.NB >= 2 && rem >= 1 && rem <= 4) {
+      switch (g.NB) {
+        case 2: hipLaunchKernelGGL((k_level1_reg<DT, MB, 2, KCM, VEC, true>), grid, block, 0, s, (const T*)X, (const T*)B, g, (Acc*)C, stride); return;
+        case 3: hipLaunchKernelGGL((k_level1_reg<DT, MB, 3, KCM, VEC, true>), grid, block, 0, s, (const T*)X, (const T*)B, g, (Acc*)C, stride); return;
+        default: hipLaunchKernelGGL((k_level1_reg<DT, MB, 4, KCM, VEC, true>), grid, block, 0, s, (const T*)X, (const T*)B, g, (Acc*)C, stride); return;
+      }
+    }
+  }
   switch (g.NB) {
     case 1: hipLaunchKernelGGL((k_level1_reg<DT, MB, 1, KCM, VEC>), grid, block, 0, s, (const T*)X, (const T*)B, g, (Acc*)C, stride); break;
     case 2: hipLaunchKernelGGL((k_level1_reg<DT, MB, 2, KCM, VEC>), grid, block, 0, s, (const T*)X, (const T*)B, g, (Acc*)C, stride); break;

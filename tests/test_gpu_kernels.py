@@ -53,6 +53,9 @@ def test_tensor_norm2(dt, n):
 L1_CASES = [
     ((37, 29, 41), 5), ((64, 48, 80), 50), ((130, 33, 67), 17), ((19, 23, 9), 1),
     ((40, 36, 44), 64), ((24, 18, 20), 65), ((21, 13, 17), 128), ((1, 7, 5), 3),
+    # FP32 with 1..4 columns in the last 16-column block (the 4x4x1 tail path), three
+    # blocks: odd extents (scalar loads) and 16-byte-aligned extents (vector loads)
+    ((29, 31, 27), 35), ((32, 40, 48), 34),
 ]
 
 
