@@ -294,16 +294,19 @@ __global__ __launch_bounds__(TTV_VTHREADS) void k_ttv_tail(TtvBatch b, GramArgs 
     if (ngram > 0) {
       double* racc = dyn;
       double* tiles = racc + GRAM_RACC(TAIL_GRAM_WAVES);
-      gram_body<TAIL_GRAM_WAVES>(g, blockIdx.x, racc, tiles, tiles + 256, tiles + 512);
-      __threadfence();  // this tile's Gamma, W, S and U (and the record) before the count
+      gram_body<TAIL_GRAM_WAVES, true>(g, blockIdx.x, racc, tiles, tiles + 256, tiles + 512);
+      // The head needs only the Gamma tiles, written through with device-scope atomic
+      // stores: waiting for this workgroup's stores to complete orders them before the
+      // count, with no release fence (which would write back every dirty line of this
+      // XCD's L2, while the contraction workgroups keep filling it).
+      __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
       if (threadIdx.x == 0) last = atomicAdd(ctr, 1) == ngram - 1;
       __syncthreads();
       if (!last) return;
-      __threadfence();  // the other tiles' writes are visible after the count
       if (threadIdx.x == 0) *ctr = 0;
     }
-    head_body<NM>(h, dyn, dyn + 64 * CH64_LS, dyn + 64 * CH64_LS + 128);
+    head_body<NM, true>(h, dyn, dyn + 64 * CH64_LS, dyn + 64 * CH64_LS + 128);
     return;
   }
   int64_t bid = (int64_t)blockIdx.x - nrole;

@@ -34,7 +34,16 @@ constexpr int HEAD_THREADS = 256;
 // (HEAD_THREADS / 64 doubles).
 constexpr int HEAD_LDS = 64 * CH64_LS + 128 + HEAD_THREADS / 64;  // doubles
 
-template <int NM>
+// COH: Gamma was left by workgroups of the same launch (other XCDs' caches); it is read
+// with device-scope atomic loads, which bypass the non-coherent L2.
+__device__ __forceinline__ double coh_load(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void coh_store(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int NM, bool COH = false>
 __device__ __forceinline__ void head_body(const HeadArgs& h, double* Lm, double* cb, double* red) {
   constexpr int NO = NM - 1;                 // modes other than n
   constexpr int CB = 16 / NO > 1 ? 16 / NO : 2;
@@ -55,7 +64,8 @@ __device__ __forceinline__ void head_body(const HeadArgs& h, double* Lm, double*
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         const int c = c0 + 4 * j;
-        gv[j] = h.gamma[row * R + (c < R ? c : 0)];
+        const double* gp = h.gamma + row * R + (c < R ? c : 0);
+        gv[j] = COH ? coh_load(gp) : *gp;
       }
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
@@ -118,7 +128,12 @@ __device__ __forceinline__ void head_body(const HeadArgs& h, double* Lm, double*
       const double delta = (double)R * 0x1p-52 * mx;
       for (int e = tid; e < 64 * CH64_LS; e += 64) {
         const int r = e / CH64_LS, c = e - r * CH64_LS;
-        Lm[e] = (r < R && c < R) ? gamma_entry(h.S, h.N, n, RR, r * R + c) + (r == c ? delta : 0.0) : 0.0;
+        double g = 0.0;
+        if (r < R && c < R) {
+          if (!h.gamma_ready) g = gamma_entry(h.S, h.N, n, RR, r * R + c);
+          else g = COH ? coh_load(h.gamma + r * R + c) : h.gamma[r * R + c];
+        }
+        Lm[e] = g + (r < R && r == c ? delta : 0.0);
       }
       st = 1;
     }
@@ -156,7 +171,9 @@ __device__ __forceinline__ void head_body(const HeadArgs& h, double* Lm, double*
 constexpr int GRAM_U = 4;
 constexpr int GRAM_RACC(int gw) { return (gw / 2) * 2 * 4 * 64; }
 
-template <int GW>
+// COH: the Gamma tile is stored with device-scope atomic stores (written through to the
+// coherent level), for a head in another workgroup of the same launch.
+template <int GW, bool COH = false>
 __device__ __forceinline__ void gram_body(const GramArgs& a, int tile, double* racc, double* tileS,
                                           double* tileU, double* tileO) {
   __builtin_amdgcn_s_setprio(3);
@@ -277,7 +294,8 @@ __device__ __forceinline__ void gram_body(const GramArgs& a, int tile, double* r
         P0 *= sk;
       }
       const int e = te_r * R + te_c;
-      a.gamma_out[e] = P0;
+      if (COH) coh_store(a.gamma_out + e, P0);
+      else a.gamma_out[e] = P0;
       if (a.wterm) a.W_out[e] = P2;
     }
   }
