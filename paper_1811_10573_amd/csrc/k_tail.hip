@@ -71,44 +71,54 @@ __global__ __launch_bounds__(SOLVE_WAVES * 64) void k_solve_fused(FusedSolveArgs
   const bool rv = row < a.rows;
   const bool ok = rv && lv;
   const int64_t off = row * R + l;
-  // loads are unconditional (clamped row and column), masked afterwards
+  // All of the block's global loads are unconditional (clamped row, column and index;
+  // absent operands read A instead and are masked) and issued before the first wait: the
+  // row's M_p, A and A_ref, the first SLOTB partial slots and the first SB staged
+  // operand entries per thread.  Guarded loads and stores would become branches, each
+  // closed by a wait, and the prologue would take one memory round trip per batch.
   const int64_t offc = (rv ? row : a.rows - 1) * R + lc;
-  double m = a.base ? a.base[offc] : 0.0;
+  constexpr int SLOTB = 32, SB = 48;
+  const double* basep = a.base ? a.base : a.A;
+  const double* refp = a.Aref ? a.Aref : a.A;
+  double m = basep[offc];
   double ao = a.A[offc];
-  double rf = a.Aref ? a.Aref[offc] : 0.0;
-  {
-    // slot loads issued SLOTB at a time (clamped to the last slot, masked), summed in order
-    constexpr int SLOTB = 32;
-    for (int sl = 0; sl < a.nslots; sl += SLOTB) {
-      double ps[SLOTB];
+  double rf = refp[offc];
+  double ps[SLOTB];
 #pragma unroll
-      for (int u = 0; u < SLOTB; ++u)
-        ps[u] = a.part[(int64_t)min(sl + u, a.nslots - 1) * a.slot_stride + offc];
+  for (int u = 0; u < SLOTB; ++u)
+    ps[u] = a.nslots > 0 ? a.part[(int64_t)min(u, a.nslots - 1) * a.slot_stride + offc] : 0.0;
+  // staged operands, one flat range in LDS: the head's unit factors and 1 / diag L
+  // (npk), Gamma (RR) and W (RR)
+  const int tot = npk + RR + (a.W ? RR : 0);
+  const double* Wsrc = a.W ? a.W : a.gamma;
+  auto stage_src = [&](int e) {
+    return e < npk ? a.pack + e : (e < npk + RR ? a.gamma + (e - npk) : Wsrc + (e - npk - RR));
+  };
+  double sv[SB];
 #pragma unroll
-      for (int u = 0; u < SLOTB; ++u)
-        if (sl + u < a.nslots) m += ps[u];
-    }
+  for (int u = 0; u < SB; ++u) sv[u] = *stage_src(min(tid + u * nthr, tot - 1));
+  m = a.base ? m : 0.0;
+#pragma unroll
+  for (int u = 0; u < SLOTB; ++u) m += u < a.nslots ? ps[u] : 0.0;
+  for (int sl = SLOTB; sl < a.nslots; sl += SLOTB) {  // more than SLOTB slots
+#pragma unroll
+    for (int u = 0; u < SLOTB; ++u)
+      ps[u] = a.part[(int64_t)min(sl + u, a.nslots - 1) * a.slot_stride + offc];
+#pragma unroll
+    for (int u = 0; u < SLOTB; ++u) m += sl + u < a.nslots ? ps[u] : 0.0;
+  }
+  // out-of-range entries rewrite the last one with its own value
+#pragma unroll
+  for (int u = 0; u < SB; ++u) LF[min(tid + u * nthr, tot - 1)] = sv[u];
+  for (int e0 = SB * nthr; e0 < tot; e0 += SB * nthr) {  // larger ranks
+#pragma unroll
+    for (int u = 0; u < SB; ++u) sv[u] = *stage_src(min(e0 + tid + u * nthr, tot - 1));
+#pragma unroll
+    for (int u = 0; u < SB; ++u) LF[min(e0 + tid + u * nthr, tot - 1)] = sv[u];
   }
   m = ok ? m : 0.0;
   ao = ok ? ao : 0.0;
   rf = ok ? rf : 0.0;
-  // stage the head's unit factors and 1 / diag L, Gamma and W
-  {
-    constexpr int ST = 8;
-    auto copy = [&](double* dst, const double* src, int cnt) {
-      for (int e0 = tid; e0 < cnt; e0 += ST * nthr) {
-        double v[ST];
-#pragma unroll
-        for (int u = 0; u < ST; ++u) v[u] = src[min(e0 + u * nthr, cnt - 1)];
-#pragma unroll
-        for (int u = 0; u < ST; ++u)
-          if (e0 + u * nthr < cnt) dst[e0 + u * nthr] = v[u];
-      }
-    };
-    copy(LF, a.pack, npk);
-    copy(Gs, a.gamma, RR);
-    if (a.W) copy(Ws, a.W, RR);
-  }
   __syncthreads();
 
   double* bv = vb + w * 3 * 64;
