@@ -238,7 +238,8 @@ def batch_bench(args, torch, dev):
 
 
 # source file of each kernel class whose HBM traffic has a committed counter summary
-TRAFFIC_SOURCE = {"level1_gemm": "k_level1.hip", "pp_correct_ttv": "k_ttv.hip"}
+# sources whose SHA-256 (of their concatenation, in this order) the counter summary names
+TRAFFIC_SOURCE = {"level1_gemm": ["k_level1.hip"], "pp_correct_ttv": ["k_ttv.hip", "tail_bodies.h"]}
 
 
 def measured_traffic(kernel, tier, shape, rank):
@@ -258,11 +259,12 @@ def measured_traffic(kernel, tier, shape, rank):
     return float(m.group(1))
 
 
-def kernel_source_hash(src="k_level1.hip"):
+def kernel_source_hash(srcs=("k_level1.hip",)):
     import hashlib
     d = os.path.join(ROOT, "paper_1811_10573_amd", "csrc")
     hsh = hashlib.sha256()
-    hsh.update(open(os.path.join(d, src), "rb").read())
+    for src in ([srcs] if isinstance(srcs, str) else srcs):
+        hsh.update(open(os.path.join(d, src), "rb").read())
     return hsh.hexdigest()
 
 

@@ -36,6 +36,16 @@ static ppals_status fail(ppals_status st, const std::string& msg) {
   g_err = msg;
   return st;
 }
+
+// Waits for the stream by polling it: the driver's wait may put the thread to sleep, and
+// the wake-up after each of the run loop's host decisions then costs up to hundreds of
+// microseconds, depending on the host.
+static hipError_t sync_spin(hipStream_t s) {
+  for (;;) {
+    const hipError_t e = hipStreamQuery(s);
+    if (e != hipErrorNotReady) return e;
+  }
+}
 namespace ppk {
 // error reporting for the other host translation units (the batched engine)
 ppals_status set_error(ppals_status st, const std::string& msg) { return fail(st, msg); }
@@ -1777,7 +1787,7 @@ ppals_status ppals_run(ppals_plan* p, const void* X, const void* Xb, double* con
       HIPCHK(launch_rec_store(rec_dev, ring, gate + 4, s));
       HIPCHK(hipMemcpyAsync(p->la_rec, ring + 1, sizeof(ppals_sweep_record) * L,
                             hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
+      HIPCHK(sync_spin(s));
       int ran = 0;
       while (ran < L && p->la_rec[ran].sweep_kind == PPALS_SWEEP_PP_APPROX) ++ran;
       if (ran == 0) return fail(PPALS_E_STATE, "device gate closed a sweep the host opened");
@@ -1848,7 +1858,7 @@ ppals_status ppals_run(ppals_plan* p, const void* X, const void* Xb, double* con
       HIPCHK(hipHostMalloc((void**)&p->pinned_rec, sizeof(ppals_sweep_record), hipHostMallocDefault));
     HIPCHK(hipMemcpyAsync(p->pinned_rec, rec_dev, sizeof(ppals_sweep_record), hipMemcpyDeviceToHost,
                           s));
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(sync_spin(s));
     host_records[it] = *p->pinned_rec;
     ppals_sweep_record& hr = host_records[it];
     if (sweep_ms) HIPCHK(hipEventElapsedTime(&sweep_ms[it], e0, e1));
