@@ -423,17 +423,39 @@ __global__ __launch_bounds__(BSOLVE_WAVES * 64) void k_b_solve(const BProb* pr, 
   const int lc = lv ? l : 0;
   const GLB double* S = gl(P.S);
   const GLB double* U = gl(P.U);
-  double dmax = 0.0;
-  for (int e = tid; e < 64 * CH64_LS; e += nthr) {
-    const int r = e / CH64_LS, c = e - r * CH64_LS;
-    double g = 0.0;
-    if (r < R && c < R) {
-      g = S[i1 * RR + r * R + c] * S[i2 * RR + r * R + c];
-      if (r == c) dmax = fmax(dmax, g);
-    }
-    Lm[e] = g;
+  // Gamma = S^(i1) * S^(i2) into the zero-padded 64 x 65 array and W = U^(i1) * U^(i2): all
+  // loads unconditional (clamped) and issued before the first wait
+  constexpr int NT = BSOLVE_WAVES * 64;
+  constexpr int GE = (64 * CH64_LS + NT - 1) / NT, WE = (64 * 64 + NT - 1) / NT;
+  double g1[GE], g2[GE], u1[WE], u2[WE];
+#pragma unroll
+  for (int j = 0; j < GE; ++j) {
+    const int e = tid + j * NT, r = e / CH64_LS, c = e - r * CH64_LS;
+    const int idx = (e < 64 * CH64_LS && r < R && c < R) ? r * R + c : 0;
+    g1[j] = S[i1 * RR + idx];
+    g2[j] = S[i2 * RR + idx];
   }
-  for (int e = tid; e < RR; e += nthr) Ws[e] = wterm ? U[i1 * RR + e] * U[i2 * RR + e] : 0.0;
+#pragma unroll
+  for (int j = 0; j < WE; ++j) {
+    const int e = tid + j * NT, idx = e < RR ? e : 0;
+    u1[j] = U[i1 * RR + idx];
+    u2[j] = U[i2 * RR + idx];
+  }
+  double dmax = 0.0;
+#pragma unroll
+  for (int j = 0; j < GE; ++j) {
+    const int e = tid + j * NT, r = e / CH64_LS, c = e - r * CH64_LS;
+    if (e < 64 * CH64_LS) {
+      const double g = (r < R && c < R) ? g1[j] * g2[j] : 0.0;
+      if (r == c && r < R) dmax = fmax(dmax, g);
+      Lm[e] = g;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < WE; ++j) {
+    const int e = tid + j * NT;
+    if (e < RR) Ws[e] = wterm ? u1[j] * u2[j] : 0.0;
+  }
   for (int off = 32; off > 0; off >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, off));
   if (l == 0) red[w][0] = dmax;
   __syncthreads();
@@ -486,17 +508,21 @@ __global__ __launch_bounds__(BSOLVE_WAVES * 64) void k_b_solve(const BProb* pr, 
   double* bw = bv + w * BSOLVE_RPW * 64;
   const double dl = lv ? invd[lc] : 0.0;
   for (int c0 = 0; c0 < rows; c0 += BSOLVE_CH) {
-    double m[BSOLVE_RPW], ao[BSOLVE_RPW], x[BSOLVE_RPW];
+    double m[BSOLVE_RPW], ao[BSOLVE_RPW], x[BSOLVE_RPW], ap[BSOLVE_RPW];
     bool rv[BSOLVE_RPW];
+    // the chunk's row operands in one round trip (unconditional, clamped, masked): M~,
+    // A_old and, in PP sweeps, A_p
+    const GLB double* Aref = pp ? Apn : An;
 #pragma unroll
     for (int q = 0; q < BSOLVE_RPW; ++q) {
       const int y = c0 + w * BSOLVE_RPW + q;
       rv[q] = y < rows;
       const int64_t off = (int64_t)(rv[q] ? y : rows - 1) * R + lc;
       const bool ok = rv[q] && lv;
-      const double mv = M[off], av = An[off];
+      const double mv = M[off], av = An[off], pv = Aref[off];
       m[q] = ok ? mv : 0.0;
       ao[q] = ok ? av : 0.0;
+      ap[q] = pv;
     }
     if (wterm) {  // M~ += A_old W, A_old rows read back as broadcasts
 #pragma unroll
@@ -558,7 +584,7 @@ __global__ __launch_bounds__(BSOLVE_WAVES * 64) void k_b_solve(const BProb* pr, 
       const int yl = y - c0;
       double d = 0.0;
       if (rv[q] && lv) {
-        d = pp ? x[q] - Apn[(int64_t)y * R + l] : x[q] - ao[q];
+        d = x[q] - ap[q];  // A_p in PP sweeps, A_old otherwise
         An[(int64_t)y * R + l] = x[q];
         if (pp) dAn[(int64_t)y * R + l] = d;
         nd = fma(d, d, nd);
@@ -590,6 +616,10 @@ __global__ __launch_bounds__(BSOLVE_WAVES * 64) void k_b_solve(const BProb* pr, 
     }
     __syncthreads();
   }
+  // both output pointers read together, outside the branches (a record field read under
+  // a branch costs a round trip each)
+  GLB double* const Sout = gl(P.S) + (size_t)n * RR;
+  GLB double* const Uout = gl(P.U) + (size_t)n * RR;
 #pragma unroll
   for (int t = 0; t < BSOLVE_TPW; ++t) {
     const int tt = w + BSOLVE_WAVES * t;
@@ -597,7 +627,7 @@ __global__ __launch_bounds__(BSOLVE_WAVES * 64) void k_b_solve(const BProb* pr, 
       const bool isU = tt >= NBR * NBR;
       const int tl = isU ? tt - NBR * NBR : tt;
       const int r0 = (tl / NBR) * 16, cc0 = (tl % NBR) * 16;
-      GLB double* out = gl(isU ? P.U : P.S) + (size_t)n * RR;
+      GLB double* out = isU ? Uout : Sout;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = r0 + 4 * v + (l >> 4), c = cc0 + (l & 15);
