@@ -46,6 +46,12 @@ static hipError_t sync_spin(hipStream_t s) {
     if (e != hipErrorNotReady) return e;
   }
 }
+
+// The k-th mode (k = 0 .. N-2) of mode n's PP-correction jobs, in the order their
+// operators are read: the operator shared with the previous mode first, the one shared
+// with the next mode last, so that consecutive modes read the operator they share back to
+// back and the memory-side cache can serve the second read.
+static inline int pp_job_mode(int N, int n, int k) { return ((n - 1 - k) % N + N) % N; }
 namespace ppk {
 // error reporting for the other host translation units (the batched engine)
 ppals_status set_error(ppals_status st, const std::string& msg) { return fail(st, msg); }
@@ -476,8 +482,8 @@ void build_pp(ppals_plan* p) {
     memset(&b, 0, sizeof(b));
     b.R = p->R;
     int nj = 0, slots = 0;
-    for (int i = 0; i < N; ++i) {
-      if (i == n) continue;
+    for (int k = 0; k < N - 1; ++k) {
+      const int i = pp_job_mode(N, n, k);
       TtvJob& J = b.job[nj++];
       const int64_t tg = kTtvRound / (N - 1);
       if (i < n) ttv_config(J, 1, p->dims[i], p->dims[n], p->R, esize(p->bulk), tg);  // op (i,n): contract leading
@@ -1045,8 +1051,8 @@ ppals_status pp_correct(const Ctx& c, double* const* A, int n, double* out) {
   double* part = c.at<double>(p->off_ppart);
   int64_t slot_off = 0;
   int nj = 0;
-  for (int i = 0; i < p->N; ++i) {
-    if (i == n) continue;
+  for (int k = 0; k < p->N - 1; ++k) {
+    const int i = pp_job_mode(p->N, n, k);
     TtvJob& J = b.job[nj++];
     const int lo = std::min(i, n), hi = std::max(i, n);
     J.T = c.buf(p->leaf_buf[lo][hi]);
@@ -1094,8 +1100,8 @@ ppals_status do_pp_sweep(ppals_plan* p, double* const* A, double* S, double norm
       int64_t slot_off = 0;
       int nj = 0;
       double fl = 0, by = 0;
-      for (int i = 0; i < p->N; ++i) {
-        if (i == n) continue;
+      for (int k = 0; k < p->N - 1; ++k) {
+        const int i = pp_job_mode(p->N, n, k);
         TtvJob& J = b.job[nj++];
         const int lo = std::min(i, n), hi = std::max(i, n);
         J.T = c.buf(p->leaf_buf[lo][hi]);
