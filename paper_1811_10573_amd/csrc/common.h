@@ -98,6 +98,7 @@ hipError_t launch_combine(double* out, int64_t count, int R, const double* base,
                           const double* A, const double* W, hipStream_t s);
 hipError_t launch_sub(double* out, const double* a, const double* b, int64_t n, hipStream_t s);
 hipError_t launch_copy(double* out, const double* a, int64_t n, hipStream_t s);
+hipError_t launch_copy_bytes(void* out, const void* in, size_t bytes, hipStream_t s);
 hipError_t launch_fill(double* out, double v, int64_t n, hipStream_t s);
 hipError_t launch_reduce_splits_to(void* out, int out_f32, const void* partial, int part_f32,
                                    int nsplit, int64_t count, hipStream_t s);

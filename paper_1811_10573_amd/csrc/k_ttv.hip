@@ -395,6 +395,34 @@ hipError_t launch_copy(double* out, const double* a, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_sub, dim3(ew_blocks(n)), dim3(256), 0, s, out, a, (const double*)nullptr, n);
   return hipGetLastError();
 }
+// Byte-range copy: 16-byte vectors, four in flight per thread, then the last bytes one
+// at a time (both pointers 16-byte aligned).
+__global__ void k_copy16(uint4* __restrict__ out, const uint4* __restrict__ in, int64_t nv,
+                         unsigned char* __restrict__ ob, const unsigned char* __restrict__ ib,
+                         int64_t tail) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < nv; i += 4 * stride) {
+    const uint4 a = in[i], b = in[i + stride], c = in[i + 2 * stride], d = in[i + 3 * stride];
+    out[i] = a;
+    out[i + stride] = b;
+    out[i + 2 * stride] = c;
+    out[i + 3 * stride] = d;
+  }
+  for (; i < nv; i += stride) out[i] = in[i];
+  if (blockIdx.x == 0)
+    for (int64_t t = threadIdx.x; t < tail; t += blockDim.x) ob[t] = ib[t];
+}
+hipError_t launch_copy_bytes(void* out, const void* in, size_t bytes, hipStream_t s) {
+  if ((((uintptr_t)out) | ((uintptr_t)in)) & 15) return hipErrorInvalidValue;
+  const int64_t nv = (int64_t)(bytes / 16), tail = (int64_t)(bytes % 16);
+  int64_t blocks = (nv / 4 + 255) / 256;
+  blocks = blocks < 1 ? 1 : (blocks > 8192 ? 8192 : blocks);
+  hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, s, (uint4*)out,
+                     (const uint4*)in, nv, (unsigned char*)out + nv * 16,
+                     (const unsigned char*)in + nv * 16, tail);
+  return hipGetLastError();
+}
 hipError_t launch_fill(double* out, double v, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_fill, dim3(ew_blocks(n)), dim3(256), 0, s, out, v, n);
   return hipGetLastError();

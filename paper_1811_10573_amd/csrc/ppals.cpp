@@ -113,6 +113,10 @@ struct ppals_plan {
   std::vector<Op> pp_ops;          // operator build (L1 + TTV to leaves)
   std::vector<int> mp_ttv;         // per mode: TTV step producing M_p^(n) (out to mp buffer)
   int leaf_buf[PPALS_MAX_ORDER][PPALS_MAX_ORDER];
+  // A first-level step of the operator build whose tensor the ALS sweep's tree also
+  // contracts, with factors that are final by then: a build right after an ALS sweep copies
+  // it from the tree's buffer (reuse_src) instead of contracting X again.  -1: none.
+  int reuse_l1 = -1, reuse_src = -1;
   // per mode PP correction batch configuration
   TtvBatch ppb[PPALS_MAX_ORDER];
   int pp_slots[PPALS_MAX_ORDER];
@@ -164,7 +168,7 @@ struct ppals_plan {
     const void *ws = nullptr, *rec = nullptr, *S = nullptr, *X = nullptr, *Xb = nullptr;
     const double* A[PPALS_MAX_ORDER] = {nullptr};
     double normX2 = 0.0;
-  } als_g, init_g;
+  } als_g, init_g, init_rg;  // init_rg: the build that copies the reused step
   // the same sweep behind the device-side threshold test, for sweeps enqueued ahead
   hipGraph_t la_graph = nullptr;
   hipGraphExec_t la_exec = nullptr;
@@ -550,6 +554,42 @@ void layout(ppals_plan* p) {
   p->ws_bytes = off;
 }
 
+// A first-level step of the ALS sweep whose contracted modes are all solved before it in
+// the sweep, and whose buffer nothing later in the sweep writes, holds at the end of the
+// sweep the same tensor as the build step with the same contracted modes (the factors it
+// used are the ones a build right after the sweep takes as A_p).  For order 3 this is
+// X x_1 A^(1) = M_p^(2,3) (modes 1-based).
+void find_reuse(ppals_plan* p) {
+  const int nops = (int)p->dt_ops.size();
+  for (int k = nops - 1; k >= 0 && p->reuse_l1 < 0; --k) {
+    const Op& o = p->dt_ops[k];
+    if (o.kind != OP_L1) continue;
+    const L1Step& d = p->l1[o.idx];
+    bool ok = true;
+    for (int m = d.lo; m < d.hi && ok; ++m) {
+      bool solved = false;
+      for (int q = 0; q < k; ++q)
+        solved = solved || (p->dt_ops[q].kind == OP_SOLVE && p->dt_ops[q].idx == m);
+      ok = solved;
+    }
+    for (int q = k + 1; q < nops && ok; ++q) {
+      const Op& w = p->dt_ops[q];
+      if (w.kind == OP_L1 && p->l1[w.idx].out_buf == d.out_buf) ok = false;
+      if (w.kind == OP_TTV && p->ttv[w.idx].out_buf == d.out_buf) ok = false;
+    }
+    if (!ok) continue;
+    for (const Op& q : p->pp_ops) {
+      if (q.kind != OP_L1) continue;
+      const L1Step& b = p->l1[q.idx];
+      if (b.lo == d.lo && b.hi == d.hi && b.kept == d.kept) {
+        p->reuse_l1 = q.idx;
+        p->reuse_src = d.out_buf;
+        break;
+      }
+    }
+  }
+}
+
 std::string json_ops(const ppals_plan* p, const std::vector<Op>& ops, double* flops_l1,
                      double* flops_ttv) {
   std::string s = "[";
@@ -611,7 +651,11 @@ void make_describe(ppals_plan* p) {
            "\"pp_build_tree_ttv_flops\":%.0f,\"pp_build_mp_flops\":%.0f,"
            "\"pp_approx_first_order_flops\":%.0f,\"workspace_bytes\":%zu,\"order\":%d,\"rank\":%d",
            a1, a2, b1, b2, mpf, approx, p->ws_bytes, p->N, p->R);
-  p->describe = std::string("{") + tmp + ",\"dt_ops\":" + dt + ",\"pp_build_ops\":" + pp + "}";
+  std::string reuse = "null";
+  if (p->reuse_l1 >= 0)
+    reuse = "[" + std::to_string(p->l1[p->reuse_l1].lo) + "," + std::to_string(p->l1[p->reuse_l1].hi) + "]";
+  p->describe = std::string("{") + tmp + ",\"dt_ops\":" + dt + ",\"pp_build_ops\":" + pp +
+                ",\"pp_build_reused_after_als\":" + reuse + "}";
 }
 
 // ---------------------------------------------------------------------------
@@ -1017,14 +1061,19 @@ ppals_status do_als_sweep(ppals_plan* p, const void* X, const void* Xb, double* 
   return mode_begin(c, S, normX2, rec, -1, prev, 0, 1, PPALS_SWEEP_ALS);
 }
 
+// reuse: the ALS sweep just before left the tensor of build step reuse_l1 in its buffer
+// (same factors), so that step is a copy.
 ppals_status do_pp_build(ppals_plan* p, const void* X, const void* Xb, double* const* A,
-                         void* ws, hipStream_t s) {
+                         void* ws, hipStream_t s, bool reuse = false) {
   Ctx c{p, (char*)ws, s};
   for (const Op& o : p->pp_ops) {
-    ppals_status st;
+    ppals_status st = PPALS_OK;
     if (o.kind == OP_L1) {
       const L1Step& l = p->l1[o.idx];
-      st = run_l1(c, l, X, Xb, A, c.buf(l.out_buf));
+      if (reuse && o.idx == p->reuse_l1)
+        HIPCHK(launch_copy_bytes(c.buf(l.out_buf), c.buf(p->reuse_src), node_bytes(p, l.kept), s));
+      else
+        st = run_l1(c, l, X, Xb, A, c.buf(l.out_buf));
     } else {
       st = run_ttv(c, p->ttv[o.idx], A, nullptr, 6);
     }
@@ -1398,6 +1447,7 @@ ppals_status ppals_plan_create(const ppals_desc* d, ppals_plan** out) {
   build_dt(p);
   prune_dt(p);
   build_pp(p);
+  find_reuse(p);
   layout(p);
   make_describe(p);
   *out = p;
@@ -1419,7 +1469,7 @@ void ppals_plan_destroy(ppals_plan* p) {
   if (p->pp_graph) (void)hipGraphDestroy(p->pp_graph);
   if (p->la_exec) (void)hipGraphExecDestroy(p->la_exec);
   if (p->la_graph) (void)hipGraphDestroy(p->la_graph);
-  for (auto* G : {&p->als_g, &p->init_g}) {
+  for (auto* G : {&p->als_g, &p->init_g, &p->init_rg}) {
     if (G->e) (void)hipGraphExecDestroy(G->e);
     if (G->g) (void)hipGraphDestroy(G->g);
   }
@@ -1818,9 +1868,12 @@ ppals_status ppals_run(ppals_plan* p, const void* X, const void* Xb, double* con
     if (sweep_ms) HIPCHK(hipEventRecord(e0, s));
     const bool graph_ok = p->fast && !p->prof;
     if (kind == PPALS_SWEEP_PP_INIT) {
+      // right after an ALS sweep of this run, its tree's buffer holds one build tensor
+      const bool reuse = prev_kind == PPALS_SWEEP_ALS && p->reuse_l1 >= 0;
       if (graph_ok) {
-        st = sweep_graphed(p, p->init_g, X, Xb, A, S, normX2, ws, rec_dev, s, [&](hipStream_t cs) {
-          ppals_status r = do_pp_build(p, X, Xb, A, ws, cs);
+        st = sweep_graphed(p, reuse ? p->init_rg : p->init_g, X, Xb, A, S, normX2, ws, rec_dev, s,
+                           [&](hipStream_t cs) {
+          ppals_status r = do_pp_build(p, X, Xb, A, ws, cs, reuse);
           if (r == PPALS_OK) r = do_pp_sweep(p, A, S, normX2, ws, rec_dev, cs);
           return r;
         });
@@ -1829,7 +1882,7 @@ ppals_status ppals_run(ppals_plan* p, const void* X, const void* Xb, double* con
           p->sweeps_since_build = 1;
         }
       } else {
-        st = do_pp_build(p, X, Xb, A, ws, s);
+        st = do_pp_build(p, X, Xb, A, ws, s, reuse);
         if (st == PPALS_OK) st = do_pp_sweep(p, A, S, normX2, ws, rec_dev, s);
       }
     } else if (kind == PPALS_SWEEP_PP_APPROX) {

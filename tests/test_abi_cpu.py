@@ -180,6 +180,26 @@ def test_pp_build_schedule_matches_oracle_tree(lib, N):
             assert o["src"][o["contract_pos"][0]] == w - 1
 
 
+@pytest.mark.parametrize("N", [3, 4, 5])
+def test_pp_build_reuse_after_als(lib, N):
+    # an ALS sweep of order 3 ends with X contracted with the final first factor, the build's
+    # first-level step that keeps modes 2 and 3 (1-based); the trees of higher orders
+    # contract two or more modes at their first level, which no build step does
+    d, _ = _describe(lib, (5,) * N, 3)
+    reused = d["pp_build_reused_after_als"]
+    if N == 3:
+        assert reused == [0, 1]
+        dt_l1 = [o for o in d["dt_ops"] if o["op"] == "level1"]
+        last = dt_l1[-1]
+        assert last["contract"] == reused and last["kept"] == [1, 2]
+        k = d["dt_ops"].index(last)
+        assert {"op": "solve", "mode": 0} in d["dt_ops"][:k]
+        assert any(o["op"] == "level1" and o["contract"] == reused and o["kept"] == [1, 2]
+                   for o in d["pp_build_ops"])
+    else:
+        assert reused is None
+
+
 def test_controller_entry_points_validate_arguments(lib):
     from paper_1811_10573_amd import _lib
     fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first

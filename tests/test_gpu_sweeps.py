@@ -255,6 +255,36 @@ def test_forced_pp_sweeps_high_rank(dims, R):
         assert abs(g["fit_est"] - o.fit_est) <= max(1e-6, 1e3 * sens), (g["fit_est"], o.fit_est, sens)
 
 
+@pytest.mark.parametrize("tier", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("profiling", [False, True])
+def test_pp_init_after_als_reuses_tree_tensor(tier, profiling):
+    """A PP initialisation right after an ALS sweep copies the tensor the sweep's tree left
+    in its buffer (X contracted with the final first factor) instead of contracting X
+    again.  Every operator then equals, bit for bit, the one a full build from the same
+    factors gives (graph replay and eager launches)."""
+    prob = tensorgen.make_problem((40, 36, 44), 6, seed=21, eta=1e-3)
+    ra = Run(prob, tier)
+    assert ra.plan.describe()["pp_build_reused_after_als"] == [0, 1]
+    pp.run(ra.plan, ra.X, ra.Xb, ra.A, ra.S, ra.normX2, ra.ws, ra.rec, eps=0.1, max_sweeps=2,
+           replay=["als", "als"])
+    rb = Run(prob, tier)
+    pp.set_profiling(rb.plan, profiling)
+    recs, _ = pp.run(rb.plan, rb.X, rb.Xb, rb.A, rb.S, rb.normX2, rb.ws, rb.rec, eps=0.1,
+                     max_sweeps=3, replay=["als", "als", "pp_init"])
+    pp.set_profiling(rb.plan, False)
+    assert [x["kind"] for x in recs] == ["als", "als", "pp_init"]
+    # full build from the factors after the same two ALS sweeps
+    pp.pp_build_operators(ra.plan, ra.X, ra.Xb, ra.A, ra.ws)
+    dims = prob.shape
+    for i in range(3):
+        for j in range(i + 1, 3):
+            oa = torch.empty(dims[i] * dims[j] * prob.rank, dtype=ra.plan.torch_dtype, device=dev())
+            ob = torch.empty_like(oa)
+            pp.get_operator(ra.plan, ra.ws, i, j, oa)
+            pp.get_operator(rb.plan, rb.ws, i, j, ob)
+            assert torch.equal(oa, ob), (tier, i, j)
+
+
 def test_graph_replayed_pp_sweeps_equal_eager_sweeps():
     """The driver replays PP-approximated sweeps from a captured HIP graph; with
     per-kernel profiling on it launches them one by one.  Both give identical bits."""
