@@ -9,8 +9,10 @@ side, operators, exact residual and the native decomposition driver).
 """
 from __future__ import annotations
 
+import collections.abc
 import ctypes
 import json
+import operator
 
 import torch
 
@@ -161,9 +163,9 @@ def record_dict(r, order=None):
     n = _lib.MAX_ORDER if order is None else order
     return {
         "fit_est": r.fit_est,
-        "grad_norm": list(r.grad_norm)[:n],
-        "rel_change": list(r.rel_change)[:n],
-        "chol_status": list(r.chol_status)[:n],
+        "grad_norm": r.grad_norm[:n],
+        "rel_change": r.rel_change[:n],
+        "chol_status": r.chol_status[:n],
         "kind": KIND_NAMES.get(r.sweep_kind, str(r.sweep_kind)),
         "ctrl_pred": r.ctrl_pred,
         "ctrl_true_err": r.ctrl_true_err,
@@ -279,11 +281,32 @@ def exact_residual2(plan, X, A, out, ws, stream=None):
                                            _stream(stream)))
 
 
+class Records(collections.abc.Sequence):
+    """The sweep records of a run, each turned into a dict (record_dict) when read."""
+
+    def __init__(self, raw, count, order):
+        self._raw, self._n, self._order = raw, count, order
+
+    def __len__(self):
+        return self._n
+
+    def __getitem__(self, i):
+        if isinstance(i, slice):
+            return [self[k] for k in range(*i.indices(self._n))]
+        i = operator.index(i)
+        if i < 0:
+            i += self._n
+        if not 0 <= i < self._n:
+            raise IndexError(i)
+        return record_dict(self._raw[i], self._order)
+
+
 def run(plan, X, X_bf16, A, S, normX2, ws, rec, eps, max_sweeps, delta=0.0, replay=None,
         timing=True, stream=None):
     """Native decomposition driver (Algorithm 3 control; eps <= 0 gives plain ALS).
 
-    Returns (records, sweep_ms): one dict per sweep and the device time of each.
+    Returns (records, sweep_ms): a sequence of one dict per sweep (Records) and the device
+    time of each.
     """
     x, xb = plan._x(X, X_bf16)
     _dev(S, "S", torch.float64, plan.order * plan.rank * plan.rank)
@@ -302,8 +325,7 @@ def run(plan, X, X_bf16, A, S, normX2, ws, rec, eps, max_sweeps, delta=0.0, repl
     _lib.check(lib().ppals_run(plan.handle, x, xb, _factor_array(plan, A), _p(S), float(normX2),
                                _p(ws), _p(rec), float(eps), float(delta), n, rp, recs,
                                ms, ctypes.byref(done), _stream(stream)))
-    out = [record_dict(recs[i], plan.order) for i in range(done.value)]
-    return out, ([float(ms[i]) for i in range(done.value)] if timing else None)
+    return Records(recs, done.value, plan.order), (ms[:done.value] if timing else None)
 
 
 # ---- learned PP controller --------------------------------------------------

@@ -189,6 +189,7 @@ bool ttv_tail_fusable(const TtvBatch& b);
 hipError_t launch_ttv_tail(const TtvBatch& b, const GramArgs* g, const HeadArgs& h, int* ctr,
                            hipStream_t s);
 hipError_t launch_set_int(int* p, int v, hipStream_t s);
+hipError_t launch_set_int2(int* p, int v, int* q, int w, hipStream_t s);
 hipError_t launch_pp_gate_ring(void* rec, int N, double eps, int* gate, void* ring, int* ctr,
                                hipStream_t s);
 hipError_t launch_rec_store(const void* rec, void* ring, const int* ctr, hipStream_t s);

@@ -247,6 +247,12 @@ int solve_fused_blocks(int64_t rows) { return (int)((rows + SOLVE_BR - 1) / SOLV
 __global__ void k_set_int(int* p, int v) {
   if (threadIdx.x == 0) *p = v;
 }
+__global__ void k_set_int2(int* p, int v, int* q, int w) {
+  if (threadIdx.x == 0) {
+    *p = v;
+    *q = w;
+  }
+}
 
 // Gate of a PP-approximated sweep enqueued ahead of the host's decision (Algorithm 3's
 // test on the device), the first node of the graph such sweeps replay: the gate stays open
@@ -294,6 +300,10 @@ hipError_t launch_rec_store(const void* rec, void* ring, const int* ctr, hipStre
 
 hipError_t launch_set_int(int* p, int v, hipStream_t s) {
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, p, v);
+  return hipGetLastError();
+}
+hipError_t launch_set_int2(int* p, int v, int* q, int w, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_int2, dim3(1), dim3(64), 0, s, p, v, q, w);
   return hipGetLastError();
 }
 

@@ -304,7 +304,9 @@ __global__ __launch_bounds__(TTV_VTHREADS) void k_ttv_tail(TtvBatch b, GramArgs 
       if (threadIdx.x == 0) last = atomicAdd(ctr, 1) == ngram - 1;
       __syncthreads();
       if (!last) return;
-      if (threadIdx.x == 0) *ctr = 0;
+      // every workgroup has counted: reset for the next launch (zeroed once per build),
+      // at the same device scope as the counts
+      if (threadIdx.x == 0) __hip_atomic_store(ctr, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     head_body<NM, true>(h, dyn, dyn + 64 * CH64_LS, dyn + 64 * CH64_LS + 128);
     return;

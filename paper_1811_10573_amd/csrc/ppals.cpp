@@ -1089,6 +1089,8 @@ ppals_status do_pp_build(ppals_plan* p, const void* X, const void* Xb, double* c
     HIPCHK(launch_fill(c.dA(n), 0.0, (int64_t)(bytes / sizeof(double)), s));
   }
   HIPCHK(launch_fill(c.U(), 0.0, (int64_t)p->N * p->R * p->R, s));
+  // counter of the fused PP-correction launches, which each leave it at zero again
+  HIPCHK(launch_set_int(c.at<int>(p->off_gate) + 8, 0, s));
   p->ops_built = true;
   p->sweeps_since_build = 0;
   return PPALS_OK;
@@ -1141,8 +1143,7 @@ ppals_status do_pp_sweep(ppals_plan* p, double* const* A, double* S, double norm
   int prev = -1;
   if (p->fast) {
     double* part = c.at<double>(p->off_ppart);
-    int* tail_ctr = c.at<int>(p->off_gate) + 8;
-    HIPCHK(launch_set_int(tail_ctr, 0, s));
+    int* tail_ctr = c.at<int>(p->off_gate) + 8;  // zero after every build and fused launch
     for (int n = 0; n < p->N; ++n) {
       TtvBatch b = p->ppb[n];
       b.gate = p->cur_gate;
@@ -1831,8 +1832,7 @@ ppals_status ppals_run(ppals_plan* p, const void* X, const void* Xb, double* con
       }
       int* gate = (int*)((char*)ws + p->off_gate);
       ppals_sweep_record* ring = (ppals_sweep_record*)((char*)ws + p->off_ring);
-      HIPCHK(launch_set_int(gate, 1, s));
-      HIPCHK(launch_set_int(gate + 4, 0, s));
+      HIPCHK(launch_set_int2(gate, 1, gate + 4, 0, s));
       for (int k = 0; k < L; ++k) {
         if (sweep_ms) HIPCHK(hipEventRecord(p->la_e0[k], s));
         st = la_sweep_graphed(p, A, S, normX2, ws, rec_dev, eps, s);
