@@ -127,7 +127,7 @@ __device__ __forceinline__ int acc_row(int l, int r) {
 template <int NVEC>
 struct BStage {
   static constexpr int PER = (NVEC + 255) / 256;
-  uint4 v[PER];
+  uint4 v[PER > 0 ? PER : 1];
   __device__ __forceinline__ void load(const uint4* __restrict__ src) {
 #pragma unroll
     for (int s = 0; s < PER; ++s) {
@@ -154,7 +154,7 @@ struct BStage {
 __device__ __attribute__((aligned(16))) double l1_zero[8];
 
 template <int DT, int MB, int NB, bool KCM, bool VEC, bool TAIL = false>
-__global__ __launch_bounds__(256) void k_level1_reg(const typename L1T<DT>::T* __restrict__ X,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DT == DT_F32 && (KCM || VEC) ? 3 : 1))) void k_level1_reg(const typename L1T<DT>::T* __restrict__ X,
                                                     const typename L1T<DT>::T* __restrict__ B,
                                                     Level1Geom g,
                                                     typename L1T<DT>::Acc* __restrict__ C,
@@ -285,10 +285,32 @@ __global__ __launch_bounds__(256) void k_level1_reg(const typename L1T<DT>::T* _
   // before the matrix cores start) and then issues the next chunk's B and X loads, B
   // first, so that storing B into LDS after the MFMAs waits for B alone.
   const int64_t chunk0 = kb0 / KC;
-  BStage<NVEC> st;
-  st.load(Bslice + chunk0 * NVEC);
-  st.store(reinterpret_cast<uint4*>(ldsB[0]));
+  // FP32: B chunks go from global memory straight into LDS (16 bytes per lane, no
+  // registers), which keeps the kernel within 168 registers per lane, three waves per
+  // SIMD: wave w moves vectors 64 w .. 64 w + 63 of each 256-vector round, which land at
+  // consecutive LDS addresses from a wave-uniform base.  FP64 (two waves per SIMD either
+  // way) stages B through registers, stored to LDS after the chunk's matrix-core work.
+  constexpr bool DMA_B = DT == DT_F32;
+  BStage<DMA_B ? 0 : NVEC> st;
+  auto load_b = [&](int64_t chunk, int bufi) {
+    if constexpr (DMA_B) {
+#pragma unroll
+      for (int r = 0; r < (NVEC + 255) / 256; ++r) {
+        const int v = 256 * r + tid;
+        if (NVEC % 256 == 0 || v < NVEC)
+          __builtin_amdgcn_global_load_lds(
+              (const void*)(Bslice + chunk * NVEC + v),
+              (__attribute__((address_space(3))) void*)(reinterpret_cast<uint4*>(ldsB[bufi]) + 256 * r + 64 * w),
+              16, 0, 0);
+      }
+    } else {
+      st.load(Bslice + chunk * NVEC);
+    }
+  };
+  load_b(chunk0, 0);
+  if constexpr (!DMA_B) st.store(reinterpret_cast<uint4*>(ldsB[0]));
   load_x(xn, kb0);
+  if constexpr (DMA_B) __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
 
   for (int ch = 0; ch < nch; ++ch) {
@@ -299,7 +321,7 @@ __global__ __launch_bounds__(256) void k_level1_reg(const typename L1T<DT>::T* _
 #pragma unroll
       for (int t = 0; t < NSTEP; ++t) xc[b][t] = xn[b][t];
     if (more) {
-      st.load(Bslice + (chunk0 + ch + 1) * NVEC);
+      load_b(chunk0 + ch + 1, buf ^ 1);
       load_x(xn, kb0 + (int64_t)(ch + 1) * KC);
     }
     const T* lb = ldsB[buf];
@@ -317,7 +339,12 @@ __global__ __launch_bounds__(256) void k_level1_reg(const typename L1T<DT>::T* _
         if constexpr (TAIL) acc[b][NB - 1] = mfma_tail(bop[NB - 1], xc[b][t], acc[b][NB - 1]);
       }
     }
-    if (more) st.store(reinterpret_cast<uint4*>(ldsB[buf ^ 1]));
+    if constexpr (DMA_B) {
+      // the next chunk's B (and X) loads are complete before any wave reads that buffer
+      __builtin_amdgcn_s_waitcnt(0);
+    } else {
+      if (more) st.store(reinterpret_cast<uint4*>(ldsB[buf ^ 1]));
+    }
     __syncthreads();
   }
 
