@@ -160,6 +160,13 @@ struct GramArgs {
   const double* U_all;
   double* gamma_out;
   double* W_out;
+  // optional (write_fit set): once the record is complete, file it in ring[*ring_ctr],
+  // advance the position and take Algorithm 3's threshold test for the sweep that follows:
+  // *gate_out = 1 while every relative change is below eps, else 0 (sweep kind -1)
+  void* ring;
+  int* ring_ctr;
+  int* gate_out;
+  double eps;
 };
 struct FusedSolveArgs {
   int R;
@@ -182,7 +189,9 @@ struct FusedSolveArgs {
 hipError_t launch_head(const HeadArgs& h, hipStream_t s);
 hipError_t launch_solve_fused(const FusedSolveArgs& a, hipStream_t s);
 int solve_fused_blocks(int64_t rows);
-hipError_t launch_gram_tiles(const GramArgs& a, hipStream_t s);
+// tail_order: the wave count (and so the summation order) of the fused PP-correction
+// launch's Gram role, so that both give the same bits
+hipError_t launch_gram_tiles(const GramArgs& a, hipStream_t s, bool tail_order = false);
 // The contraction jobs of a PP mode, the Grams of the previous mode (g may be NULL) and
 // the head of this mode in one launch; ctr is a device int that is zero between launches.
 bool ttv_tail_fusable(const TtvBatch& b);

@@ -212,12 +212,13 @@ __global__ __launch_bounds__(SOLVE_WAVES * 64) void k_solve_fused(FusedSolveArgs
 
 constexpr int GRAM_WAVES = 16;
 
-__global__ __launch_bounds__(GRAM_WAVES * 64) void k_gram_tiles(GramArgs a) {
-  __shared__ double racc[GRAM_RACC(GRAM_WAVES)];
+template <int GW>
+__global__ __launch_bounds__(GW * 64) void k_gram_tiles(GramArgs a) {
+  __shared__ double racc[GRAM_RACC(GW)];
   __shared__ double tiles[512];
   extern __shared__ double tileO[];  // the other modes' S and U tiles, (N - 2) x 2 x 256
   if (a.gate && *a.gate == 0) return;
-  gram_body<GRAM_WAVES>(a, blockIdx.x, racc, tiles, tiles + 256, tileO);
+  gram_body<GW>(a, blockIdx.x, racc, tiles, tiles + 256, tileO);
 }
 
 // ---------------------------------------------------------------------------
@@ -307,10 +308,14 @@ hipError_t launch_set_int2(int* p, int v, int* q, int w, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_gram_tiles(const GramArgs& a, hipStream_t s) {
+hipError_t launch_gram_tiles(const GramArgs& a, hipStream_t s, bool tail_order) {
   const int NBR = (a.R + 15) / 16;
   const size_t lds = a.gamma_out ? (size_t)std::max(1, a.N - 2) * 2 * 256 * sizeof(double) : 0;
-  hipLaunchKernelGGL(k_gram_tiles, dim3(NBR * NBR), dim3(GRAM_WAVES * 64), lds, s, a);
+  constexpr int TW = TTV_VTHREADS / 64;  // the Gram role of the fused PP-correction launch
+  if (tail_order)
+    hipLaunchKernelGGL(k_gram_tiles<TW>, dim3(NBR * NBR), dim3(TW * 64), lds, s, a);
+  else
+    hipLaunchKernelGGL(k_gram_tiles<GRAM_WAVES>, dim3(NBR * NBR), dim3(GRAM_WAVES * 64), lds, s, a);
   return hipGetLastError();
 }
 

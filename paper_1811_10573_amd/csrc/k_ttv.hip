@@ -288,8 +288,13 @@ __global__ __launch_bounds__(TTV_VTHREADS) void k_ttv_tail(TtvBatch b, GramArgs 
                                                            int ngram, int* ctr) {
   extern __shared__ double dyn[];
   __shared__ int last;
-  if (b.gate && *b.gate == 0) return;
   const int nrole = ngram > 0 ? ngram : 1;
+  // In a launch whose Gram role takes the threshold test (g.gate_out), Gram workgroup 0
+  // may close the gate while the launch runs; the Gram role skips the check, so that every
+  // Gram workgroup is counted (its work repeats what is already there when the gate was
+  // closed before the launch, and workgroup 0 then leaves the record alone).
+  const bool gram_role = ngram > 0 && (int)blockIdx.x < nrole;
+  if (!(gram_role && g.gate_out) && b.gate && *b.gate == 0) return;
   if ((int)blockIdx.x < nrole) {
     if (ngram > 0) {
       double* racc = dyn;

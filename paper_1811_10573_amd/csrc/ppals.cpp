@@ -142,6 +142,10 @@ struct ppals_plan {
                                                     // and the fused tail's counter (int, +32)
   size_t off_ring = 0;                              // records of sweeps enqueued ahead
   const int* cur_gate = nullptr;  // set while the gated PP sweep is being captured
+  // while a PP sweep enqueued ahead is captured: its threshold test (eps); whether mode 0's
+  // fused launch takes it (and finishes the sweep before), or a gate kernel does
+  bool la_cur = false, la_gate_fused = false;
+  double la_eps_cur = 0.0;
   bool fast = false;                   // rank <= 64: fused head/solve tail
   hipStream_t aux = nullptr;           // stream for the head kernel (default priority)
   ppals_sweep_record* pinned_rec = nullptr;  // pinned host staging of the sweep record
@@ -990,7 +994,9 @@ ppals_status finish_sweep_fast(const Ctx& c, double* const* A, double* S, double
                                ppals_sweep_record* rec, int prev, int pp, int kind) {
   GramArgs g = gram_args(c, A, S, prev, pp, normX2, rec, 1, kind);
   Prof pr(c.p, 4, c.s);
-  HIPCHK(launch_gram_tiles(g, c.s));
+  // PP sweeps: the summation order of the fused launches' Gram role, which computes the
+  // same Grams for sweeps enqueued ahead
+  HIPCHK(launch_gram_tiles(g, c.s, pp != 0));
   pr.end();
   return PPALS_OK;
 }
@@ -1166,13 +1172,35 @@ ppals_status do_pp_sweep(ppals_plan* p, double* const* A, double* S, double norm
       by += (double)p->pp_slots[n] * p->dims[n] * p->R * 8;
       const HeadArgs h = head_args(c, S, n, 1);
       ppals_status st;
-      if (ttv_tail_fusable(b)) {
+      const bool fusable = ttv_tail_fusable(b);
+      // A sweep enqueued ahead starts with the threshold test on the record of the sweep
+      // before.  With the fused launch for mode 0, its Gram role finishes that record (Grams
+      // of the last mode, the fit), files it and takes the test; otherwise a gate kernel
+      // does, and this sweep ends with its own last Grams and record.
+      if (n == 0 && p->la_cur) {
+        p->la_gate_fused = fusable;
+        if (!fusable) {
+          int* gate = (int*)p->cur_gate;
+          HIPCHK(launch_pp_gate_ring(rec, p->N, p->la_eps_cur, gate, c.ws + p->off_ring, gate + 4, s));
+        }
+      }
+      const bool fin_before = n == 0 && p->la_cur && fusable;
+      if (fusable) {
         // contractions, the previous mode's Grams and this mode's head in one launch
         HeadArgs h2 = h;
         GramArgs g2;
         const GramArgs* gp = nullptr;
-        if (prev >= 0) {
-          g2 = gram_args(c, A, S, prev, 1, normX2, rec, 0, kind);
+        if (prev >= 0 || fin_before) {
+          const int gm = fin_before ? p->N - 1 : prev;
+          g2 = gram_args(c, A, S, gm, 1, normX2, rec, fin_before ? 1 : 0,
+                         fin_before ? PPALS_SWEEP_PP_APPROX : kind);
+          if (fin_before) {
+            int* gate = (int*)p->cur_gate;
+            g2.ring = c.ws + p->off_ring;
+            g2.ring_ctr = gate + 4;
+            g2.gate_out = gate;
+            g2.eps = p->la_eps_cur;
+          }
           g2.N = h.N;
           g2.next = h.n;
           g2.wterm = h.pp && h.second_order;
@@ -1211,7 +1239,10 @@ ppals_status do_pp_sweep(ppals_plan* p, double* const* A, double* S, double norm
       if (st != PPALS_OK) return st;
       prev = n;
     }
-    ppals_status st = finish_sweep_fast(c, A, S, normX2, rec, prev, 1, kind);
+    // a sweep enqueued ahead whose first launch took the test leaves its last Grams and
+    // record to the next sweep's first launch (or to the kernel after the last one)
+    ppals_status st = PPALS_OK;
+    if (!(p->la_cur && p->la_gate_fused)) st = finish_sweep_fast(c, A, S, normX2, rec, prev, 1, kind);
     if (st == PPALS_OK) p->sweeps_since_build++;
     return st;
   }
@@ -1330,10 +1361,10 @@ ppals_status sweep_graphed(ppals_plan* p, ppals_plan::SweepGraph& G, const void*
   return PPALS_OK;
 }
 
-// PP-approximated sweep enqueued ahead of the host's decision, replayed from a graph whose
-// first node takes the threshold test of Algorithm 3 on the device (k_pp_gate_ring, which
-// also files the record before it in the ring); rebuilt when a pointer, ||X||^2 or eps
-// changes.
+// PP-approximated sweep enqueued ahead of the host's decision, replayed from a graph that
+// starts with the threshold test of Algorithm 3 on the device (taken by mode 0's fused
+// launch, or by k_pp_gate_ring before it), which also files the record before it in the
+// ring; rebuilt when a pointer, ||X||^2 or eps changes.
 ppals_status la_sweep_graphed(ppals_plan* p, double* const* A, double* S, double normX2, void* ws,
                               ppals_sweep_record* rec, double eps, hipStream_t s) {
   bool same = p->la_exec && p->la_ws == ws && p->la_recp == rec && p->la_S == S &&
@@ -1347,21 +1378,18 @@ ppals_status la_sweep_graphed(ppals_plan* p, double* const* A, double* S, double
     if (!p->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
     HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
     int* gate = (int*)((char*)ws + p->off_gate);
-    ppals_status st = PPALS_OK;
-    const hipError_t le = launch_pp_gate_ring(rec, p->N, eps, gate, (char*)ws + p->off_ring,
-                                              gate + 4, p->cap_stream);
     const int before = p->sweeps_since_build;
-    if (le == hipSuccess) {
-      p->cur_gate = gate;
-      st = do_pp_sweep(p, A, S, normX2, ws, rec, p->cap_stream);
-      p->cur_gate = nullptr;
-    }
+    p->cur_gate = gate;
+    p->la_cur = true;
+    p->la_eps_cur = eps;
+    const ppals_status st = do_pp_sweep(p, A, S, normX2, ws, rec, p->cap_stream);
+    p->la_cur = false;
+    p->cur_gate = nullptr;
     p->sweeps_since_build = before;
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
-    if (le != hipSuccess || st != PPALS_OK) {
+    if (st != PPALS_OK) {
       if (g) (void)hipGraphDestroy(g);
-      if (le != hipSuccess) return fail(PPALS_E_HIP, std::string("capture: ") + hipGetErrorString(le));
       return st;
     }
     if (e != hipSuccess) return fail(PPALS_E_HIP, std::string("capture: ") + hipGetErrorString(e));
@@ -1838,6 +1866,13 @@ ppals_status ppals_run(ppals_plan* p, const void* X, const void* Xb, double* con
         st = la_sweep_graphed(p, A, S, normX2, ws, rec_dev, eps, s);
         if (st != PPALS_OK) return st;
         if (sweep_ms) HIPCHK(hipEventRecord(p->la_e1[k], s));
+      }
+      if (p->la_gate_fused) {
+        // the last enqueued sweep's Grams of its last mode, fit and record (if it ran)
+        Ctx c{p, (char*)ws, s};
+        GramArgs g = gram_args(c, A, S, p->N - 1, 1, normX2, rec_dev, 1, PPALS_SWEEP_PP_APPROX);
+        g.gate = gate;
+        HIPCHK(launch_gram_tiles(g, s, true));
       }
       // ring[0] holds the record before the first enqueued sweep, ring[k + 1] that of sweep k
       HIPCHK(launch_rec_store(rec_dev, ring, gate + 4, s));

@@ -300,6 +300,9 @@ __device__ __forceinline__ void gram_body(const GramArgs& a, int tile, double* r
     }
   }
   if (tile != 0) return;
+  // a launch that takes the threshold test with the gate already closed (only this
+  // workgroup writes it) leaves the record as it is
+  if (a.gate_out && *a.gate_out == 0) return;
   // record for this mode from the solve's per-block partials
   __shared__ double sums[NPART];
   if (w == 0) {
@@ -321,6 +324,17 @@ __device__ __forceinline__ void gram_body(const GramArgs& a, int tile, double* r
         const double r2 = a.normX2 - 2.0 * sums[3] + sums[4];
         rec->fit_est = 1.0 - sqrt(r2 > 0.0 ? r2 : 0.0) / sqrt(a.normX2);
         rec->sweep_kind = a.sweep_kind;
+        if (a.ring) {
+          // the sweep's record is complete: file it, then decide whether the next sweep runs
+          ppals_sweep_record* ring = (ppals_sweep_record*)a.ring;
+          const int k = *a.ring_ctr;
+          ring[k] = *rec;
+          *a.ring_ctr = k + 1;
+          bool open = true;
+          for (int q = 0; q < a.N; ++q) open = open && rec->rel_change[q] < a.eps;
+          *a.gate_out = open ? 1 : 0;
+          rec->sweep_kind = open ? PPALS_SWEEP_PP_APPROX : -1;
+        }
       }
     }
   }
