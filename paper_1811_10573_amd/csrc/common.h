@@ -167,6 +167,12 @@ struct GramArgs {
   int* ring_ctr;
   int* gate_out;
   double eps;
+  // optional: row ranges per tile (<= 1: one), with, in the fused PP-correction launch,
+  // their partial tiles (tiles x nsplit x 512 doubles) and per-tile counters (zero between
+  // launches)
+  int nsplit;
+  double* gpart;
+  int* gctr;
 };
 struct FusedSolveArgs {
   int R;

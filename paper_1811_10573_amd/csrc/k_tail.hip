@@ -218,7 +218,7 @@ __global__ __launch_bounds__(GW * 64) void k_gram_tiles(GramArgs a) {
   __shared__ double tiles[512];
   extern __shared__ double tileO[];  // the other modes' S and U tiles, (N - 2) x 2 x 256
   if (a.gate && *a.gate == 0) return;
-  gram_body<GW>(a, blockIdx.x, racc, tiles, tiles + 256, tileO);
+  gram_body<GW>(a, blockIdx.x, 0, racc, tiles, tiles + 256, tileO);
 }
 
 // ---------------------------------------------------------------------------

@@ -276,7 +276,8 @@ __global__ __launch_bounds__(TTV_VTHREADS) void k_ttv_vec(TtvBatch b) {
 // One launch per mode of a PP sweep for the mode's contractions, the Grams of the previous
 // mode and the head of this mode, so that the solve after it depends on one kernel on one
 // stream (a dependency between streams costs several microseconds each way).  Workgroups
-// 0 .. ngram-1 take the Gram tiles (four waves each; they are dispatched first); the last
+// 0 .. ngram-1 take the Gram tiles, nsplit row ranges of each (four waves each; they are
+// dispatched first, and the last range of a tile to finish adds the partial tiles); the last
 // of them to finish, told by a device-scope counter that it resets, then runs the head
 // from the Gamma and W tiles the others left in global memory.  With ngram == 0 (first
 // mode of a sweep) workgroup 0 runs the head alone.  The other workgroups run the
@@ -299,7 +300,9 @@ __global__ __launch_bounds__(TTV_VTHREADS) void k_ttv_tail(TtvBatch b, GramArgs 
     if (ngram > 0) {
       double* racc = dyn;
       double* tiles = racc + GRAM_RACC(TAIL_GRAM_WAVES);
-      gram_body<TAIL_GRAM_WAVES, true>(g, blockIdx.x, racc, tiles, tiles + 256, tiles + 512);
+      const int nsplit = g.nsplit > 1 ? g.nsplit : 1;
+      gram_body<TAIL_GRAM_WAVES, true>(g, blockIdx.x / nsplit, blockIdx.x % nsplit, racc, tiles,
+                                       tiles + 256, tiles + 512);
       // The head needs only the Gamma tiles, written through with device-scope atomic
       // stores: waiting for this workgroup's stores to complete orders them before the
       // count, with no release fence (which would write back every dirty line of this
@@ -501,7 +504,8 @@ hipError_t launch_ttv_tail(const TtvBatch& b, const GramArgs* g, const HeadArgs&
     if (J.kind == TTV_ROWS) fl = std::max(fl, (size_t)J.xs * b.R);
   }
   const int NBR = (b.R + 15) / 16;
-  const int ngram = g ? NBR * NBR : 0;
+  const int ngram = g ? NBR * NBR * (g->nsplit > 1 ? g->nsplit : 1) : 0;
+  if (g && g->nsplit > 1 && (!g->gpart || !g->gctr)) return hipErrorInvalidValue;
   const size_t gram_lds = (size_t)GRAM_RACC(TAIL_GRAM_WAVES) + 512 +
                           (g && g->gamma_out ? (size_t)std::max(1, g->N - 2) * 512 : 0);
   const size_t lds = std::max({ttv_lds + fl, gram_lds, (size_t)HEAD_LDS}) * sizeof(double);

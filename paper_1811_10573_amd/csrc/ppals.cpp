@@ -141,6 +141,7 @@ struct ppals_plan {
                                                     // then the ring position (int, +16 bytes)
                                                     // and the fused tail's counter (int, +32)
   size_t off_ring = 0;                              // records of sweeps enqueued ahead
+  size_t off_gpart = 0, off_gctr = 0;  // Gram tiles' row-range partials and counters
   const int* cur_gate = nullptr;  // set while the gated PP sweep is being captured
   // while a PP sweep enqueued ahead is captured: its threshold test (eps); whether mode 0's
   // fused launch takes it (and finishes the sweep before), or a gate kernel does
@@ -217,6 +218,7 @@ int64_t prod_dims(const ppals_plan* p, const std::vector<int>& modes, int a, int
 // stream more, takes 2/5 as many).  Measured on 800^3, R = 50: more, smaller workgroups
 // of the slab kind shorten the tail of a launch; one round of large workgroups is slower.
 constexpr int64_t kTtvRound = 3200;
+constexpr int kGramSplitMax = 4;  // row ranges per Gram tile in PP sweeps
 
 // target: workgroups wanted for this job (slab kind; 2/5 of it for the row kind).
 void ttv_config(TtvJob& J, int64_t P, int64_t X, int64_t Q, int R, int es, int64_t target) {
@@ -554,6 +556,11 @@ void layout(ppals_plan* p) {
   p->off_errsum = take((size_t)2 * PPALS_MAX_ORDER * 8);
   p->off_gate = take(64);
   p->off_ring = take(sizeof(ppals_sweep_record) * (ppals_plan::kLookahead + 1));
+  {
+    const int nbr = (R + 15) / 16;
+    p->off_gpart = take((size_t)nbr * nbr * kGramSplitMax * 512 * sizeof(double));
+    p->off_gctr = take((size_t)nbr * nbr * sizeof(int));
+  }
   for (auto& b : p->bufs) b.off = take(b.bytes);
   p->ws_bytes = off;
 }
@@ -900,6 +907,15 @@ HeadArgs head_args(const Ctx& c, double* S, int n, int pp) {
 
 // Grams of the freshly solved factor n into S^(n) (and U^(n) in PP sweeps) plus the
 // sweep record of mode n (and the fit after the last mode).
+// PP sweeps' Grams (rank <= 64): the rows of each tile in up to kGramSplitMax ranges of at
+// least 192 rows, so that the fused launch's Gram role, which runs beside the
+// contraction's memory traffic, takes fewer dependent load rounds per workgroup.
+void gram_split(const Ctx& c, GramArgs& g) {
+  g.nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(kGramSplitMax, g.rows / 192));
+  g.gpart = c.at<double>(c.p->off_gpart);
+  g.gctr = c.at<int>(c.p->off_gctr);
+}
+
 GramArgs gram_args(const Ctx& c, double* const* A, double* S, int n, int pp, double normX2,
                    ppals_sweep_record* rec, int write_fit, int kind) {
   ppals_plan* p = c.p;
@@ -993,6 +1009,7 @@ ppals_status solve_fused(const Ctx& c, double* const* A, int n, const double* ba
 ppals_status finish_sweep_fast(const Ctx& c, double* const* A, double* S, double normX2,
                                ppals_sweep_record* rec, int prev, int pp, int kind) {
   GramArgs g = gram_args(c, A, S, prev, pp, normX2, rec, 1, kind);
+  if (pp) gram_split(c, g);
   Prof pr(c.p, 4, c.s);
   // PP sweeps: the summation order of the fused launches' Gram role, which computes the
   // same Grams for sweeps enqueued ahead
@@ -1095,8 +1112,12 @@ ppals_status do_pp_build(ppals_plan* p, const void* X, const void* Xb, double* c
     HIPCHK(launch_fill(c.dA(n), 0.0, (int64_t)(bytes / sizeof(double)), s));
   }
   HIPCHK(launch_fill(c.U(), 0.0, (int64_t)p->N * p->R * p->R, s));
-  // counter of the fused PP-correction launches, which each leave it at zero again
+  // counters of the fused PP-correction launches, which each leave them at zero again
   HIPCHK(launch_set_int(c.at<int>(p->off_gate) + 8, 0, s));
+  {
+    const int nbr = (p->R + 15) / 16;
+    HIPCHK(launch_fill(c.at<double>(p->off_gctr), 0.0, (nbr * nbr + 1) / 2, s));
+  }
   p->ops_built = true;
   p->sweeps_since_build = 0;
   return PPALS_OK;
@@ -1208,6 +1229,7 @@ ppals_status do_pp_sweep(ppals_plan* p, double* const* A, double* S, double norm
           g2.U_all = h.U;
           g2.gamma_out = h.gamma;
           g2.W_out = h.W;
+          gram_split(c, g2);
           h2.gamma_ready = 1;
           gp = &g2;
         }
@@ -1871,6 +1893,7 @@ ppals_status ppals_run(ppals_plan* p, const void* X, const void* Xb, double* con
         // the last enqueued sweep's Grams of its last mode, fit and record (if it ran)
         Ctx c{p, (char*)ws, s};
         GramArgs g = gram_args(c, A, S, p->N - 1, 1, normX2, rec_dev, 1, PPALS_SWEEP_PP_APPROX);
+        gram_split(c, g);
         g.gate = gate;
         HIPCHK(launch_gram_tiles(g, s, true));
       }

@@ -173,9 +173,16 @@ constexpr int GRAM_RACC(int gw) { return (gw / 2) * 2 * 4 * 64; }
 
 // COH: the Gamma tile is stored with device-scope atomic stores (written through to the
 // coherent level), for a head in another workgroup of the same launch.
+//
+// Row splits (a.nsplit > 1): the rows are cut into nsplit ranges and the tile is the sum of
+// the ranges' partial tiles, added in range order.  With COH each range is its own
+// workgroup (`split`): it writes its partial tile through to a.gpart, counts itself on the
+// tile's counter a.gctr[tile], and the last of them adds the partials and goes on (the
+// others return).  Without COH one workgroup computes the ranges one after another; both
+// give the same bits.
 template <int GW, bool COH = false>
-__device__ __forceinline__ void gram_body(const GramArgs& a, int tile, double* racc, double* tileS,
-                                          double* tileU, double* tileO) {
+__device__ __forceinline__ void gram_body(const GramArgs& a, int tile, int split, double* racc,
+                                          double* tileS, double* tileU, double* tileO) {
   __builtin_amdgcn_s_setprio(3);
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63;
@@ -190,25 +197,9 @@ __device__ __forceinline__ void gram_body(const GramArgs& a, int tile, double* r
   const int ky = l >> 4, cc = l & 15;
   const bool oka = r0 + cc < R, okb = c0 + cc < R;
   const int64_t rows = a.rows;
-  d4 accS = {0.0, 0.0, 0.0, 0.0}, accU = {0.0, 0.0, 0.0, 0.0};
-  double xa[GRAM_U], xb[GRAM_U], xd[GRAM_U];
-  auto load = [&](int64_t y0, double (&va)[GRAM_U], double (&vb)[GRAM_U], double (&vd)[GRAM_U]) {
-#pragma unroll
-    for (int u = 0; u < GRAM_U; ++u) {
-      const int64_t y = y0 + 4 * u + ky;
-      const bool in = y < rows;
-      va[u] = (in && oka) ? a.A[y * R + r0 + cc] : 0.0;
-      vb[u] = (in && okb) ? a.A[y * R + c0 + cc] : 0.0;
-      vd[u] = (in && okb && has_u) ? a.dA[y * R + c0 + cc] : 0.0;
-    }
-  };
-  const int64_t step = (int64_t)4 * GRAM_U * GW;
-  int64_t y0 = (int64_t)w * 4 * GRAM_U;
-  load(y0, xa, xb, xd);
   if (want_g) {
-    // the other modes' tiles, in the same round trip as the first operands: thread t takes
-    // entry t % 256 of the other modes o = t / 256, t / 256 + GW / 4, ... (S and U)
-    // (other mode o = the o-th mode that is neither this one nor the next)
+    // thread t takes entry t % 256 of the other modes o = t / 256, t / 256 + GW / 4, ...
+    // (S and U; other mode o = the o-th mode that is neither this one nor the next)
     const int e = te_ok ? te_r * R + te_c : 0;
     for (int o = tid >> 8; o < a.N - 2; o += GW * 64 / 256) {
       int k = -1;
@@ -222,53 +213,115 @@ __device__ __forceinline__ void gram_body(const GramArgs& a, int tile, double* r
       }
     }
   }
-  for (; y0 < rows; y0 += step) {
-    double na[GRAM_U], nb[GRAM_U], nd[GRAM_U];
-    const bool more = y0 + step < rows;
-    if (more) load(y0 + step, na, nb, nd);
-#pragma unroll
-    for (int u = 0; u < GRAM_U; ++u) {
-      accS = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u], xb[u], accS, 0, 0, 0);
-      if (has_u) accU = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u], xd[u], accU, 0, 0, 0);
-    }
-    if (more) {
+  // The tile of S (waves 0) and U (wave 1) over rows [ys, ye): sum[v] = tile row 4v + l/16,
+  // column l%16.
+  constexpr int HW = GW / 2;
+  auto tile_sum = [&](int64_t ys, int64_t ye, double (&sum)[4]) {
+    d4 accS = {0.0, 0.0, 0.0, 0.0}, accU = {0.0, 0.0, 0.0, 0.0};
+    double xa[GRAM_U], xb[GRAM_U], xd[GRAM_U];
+    auto load = [&](int64_t y0, double (&va)[GRAM_U], double (&vb)[GRAM_U], double (&vd)[GRAM_U]) {
 #pragma unroll
       for (int u = 0; u < GRAM_U; ++u) {
-        xa[u] = na[u];
-        xb[u] = nb[u];
-        xd[u] = nd[u];
+        const int64_t y = y0 + 4 * u + ky;
+        const bool in = y < ye;
+        va[u] = (in && oka) ? a.A[y * R + r0 + cc] : 0.0;
+        vb[u] = (in && okb) ? a.A[y * R + c0 + cc] : 0.0;
+        vd[u] = (in && okb && has_u) ? a.dA[y * R + c0 + cc] : 0.0;
+      }
+    };
+    const int64_t step = (int64_t)4 * GRAM_U * GW;
+    int64_t y0 = ys + (int64_t)w * 4 * GRAM_U;
+    load(y0, xa, xb, xd);
+    for (; y0 < ye; y0 += step) {
+      double na[GRAM_U], nb[GRAM_U], nd[GRAM_U];
+      const bool more = y0 + step < ye;
+      if (more) load(y0 + step, na, nb, nd);
+#pragma unroll
+      for (int u = 0; u < GRAM_U; ++u) {
+        accS = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u], xb[u], accS, 0, 0, 0);
+        if (has_u) accU = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u], xd[u], accU, 0, 0, 0);
+      }
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < GRAM_U; ++u) {
+          xa[u] = na[u];
+          xb[u] = nb[u];
+          xd[u] = nd[u];
+        }
       }
     }
-  }
-  // two-stage reduction over the waves: the upper half adds into the lower half
-  constexpr int HW = GW / 2;
-  if (w >= HW) {
+    // two-stage reduction over the waves: the upper half adds into the lower half
+    if (w >= HW) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      racc[(((w - HW) * 2 + 0) * 4 + v) * 64 + l] = accS[v];
-      racc[(((w - HW) * 2 + 1) * 4 + v) * 64 + l] = accU[v];
+      for (int v = 0; v < 4; ++v) {
+        racc[(((w - HW) * 2 + 0) * 4 + v) * 64 + l] = accS[v];
+        racc[(((w - HW) * 2 + 1) * 4 + v) * 64 + l] = accU[v];
+      }
+    }
+    __syncthreads();
+    if (w < HW) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        racc[((w * 2 + 0) * 4 + v) * 64 + l] += accS[v];
+        racc[((w * 2 + 1) * 4 + v) * 64 + l] += accU[v];
+      }
+    }
+    __syncthreads();
+    if (w < 2) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double t = 0.0;
+        for (int q = 0; q < HW; ++q) t += racc[((q * 2 + w) * 4 + v) * 64 + l];
+        sum[v] = t;
+      }
+    }
+    __syncthreads();  // racc is free again
+  };
+  const int nsplit = a.nsplit > 1 ? a.nsplit : 1;
+  const int64_t per = (rows + nsplit - 1) / nsplit;
+  double tot[4] = {0.0, 0.0, 0.0, 0.0};
+  if (COH && nsplit > 1) {
+    __shared__ int last_split;
+    const int64_t ys = (int64_t)split * per;
+    tile_sum(ys, ys + per < rows ? ys + per : rows, tot);
+    double* gp = a.gpart + (int64_t)tile * nsplit * 512;
+    const int pe = w * 256 + (4 * 0 + ky) * 16 + cc;  // entry of register v = 0
+    if (w < 2) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) coh_store(gp + split * 512 + pe + 64 * v, tot[v]);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0) last_split = atomicAdd(a.gctr + tile, 1) == nsplit - 1;
+    __syncthreads();
+    if (!last_split) return;
+    if (tid == 0) __hip_atomic_store(a.gctr + tile, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (w < 2) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double t = coh_load(gp + pe + 64 * v);
+        for (int q = 1; q < nsplit; ++q) t += coh_load(gp + q * 512 + pe + 64 * v);
+        tot[v] = t;
+      }
+    }
+  } else {
+    for (int q = 0; q < nsplit; ++q) {
+      double part[4];
+      const int64_t ys = (int64_t)q * per;
+      tile_sum(ys, ys + per < rows ? ys + per : rows, part);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) tot[v] = q == 0 ? part[v] : tot[v] + part[v];
     }
   }
-  __syncthreads();
-  if (w < HW) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      racc[((w * 2 + 0) * 4 + v) * 64 + l] += accS[v];
-      racc[((w * 2 + 1) * 4 + v) * 64 + l] += accU[v];
-    }
-  }
-  __syncthreads();
   if (w < 2 && (w == 0 || has_u)) {
     double* out = w ? a.U_out : a.S_out;
-    double* tile = w ? tileU : tileS;
+    double* tl = w ? tileU : tileS;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      double sum = 0.0;
-      for (int q = 0; q < HW; ++q) sum += racc[((q * 2 + w) * 4 + v) * 64 + l];
-      const int tr = 4 * v + (l >> 4), tc = l & 15;
+      const int tr = 4 * v + ky, tc = cc;
       const int r = r0 + tr, c = c0 + tc;
-      if (r < R && c < R) out[r * R + c] = sum;
-      tile[tr * 16 + tc] = sum;
+      if (r < R && c < R) out[r * R + c] = tot[v];
+      tl[tr * 16 + tc] = tot[v];
     }
   }
   if (want_g) {
