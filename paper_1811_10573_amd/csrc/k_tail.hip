@@ -221,6 +221,18 @@ __global__ __launch_bounds__(GW * 64) void k_gram_tiles(GramArgs a) {
   gram_body<GW>(a, blockIdx.x, 0, racc, tiles, tiles + 256, tileO);
 }
 
+// The Gram tiles in row ranges, one workgroup per (tile, range), with the fused
+// PP-correction launch's Gram role itself (same bits).
+template <int GW>
+__global__ __launch_bounds__(GW * 64) void k_gram_split(GramArgs a) {
+  __shared__ double racc[GRAM_RACC(GW)];
+  __shared__ double tiles[512];
+  extern __shared__ double tileO[];
+  if (a.gate && *a.gate == 0) return;
+  gram_body<GW, true>(a, blockIdx.x / a.nsplit, blockIdx.x % a.nsplit, racc, tiles, tiles + 256,
+                      tileO);
+}
+
 // ---------------------------------------------------------------------------
 template <typename K>
 static hipError_t allow_lds(K kernel, size_t bytes) {
@@ -312,7 +324,10 @@ hipError_t launch_gram_tiles(const GramArgs& a, hipStream_t s, bool tail_order) 
   const int NBR = (a.R + 15) / 16;
   const size_t lds = a.gamma_out ? (size_t)std::max(1, a.N - 2) * 2 * 256 * sizeof(double) : 0;
   constexpr int TW = TTV_VTHREADS / 64;  // the Gram role of the fused PP-correction launch
-  if (tail_order)
+  if (tail_order && a.nsplit > 1) {
+    if (!a.gpart || !a.gctr) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gram_split<TW>, dim3(NBR * NBR * a.nsplit), dim3(TW * 64), lds, s, a);
+  } else if (tail_order)
     hipLaunchKernelGGL(k_gram_tiles<TW>, dim3(NBR * NBR), dim3(TW * 64), lds, s, a);
   else
     hipLaunchKernelGGL(k_gram_tiles<GRAM_WAVES>, dim3(NBR * NBR), dim3(GRAM_WAVES * 64), lds, s, a);
