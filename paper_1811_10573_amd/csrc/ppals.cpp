@@ -1175,10 +1175,14 @@ ppals_status do_pp_sweep(ppals_plan* p, double* const* A, double* S, double norm
       TtvBatch b = p->ppb[n];
       b.gate = p->cur_gate;
       int64_t slot_off = 0;
-      int nj = 0;
+      int nj = 0, nslots = 0;
       double fl = 0, by = 0;
       for (int k = 0; k < p->N - 1; ++k) {
         const int i = pp_job_mode(p->N, n, k);
+        // Right after a build dA^(i) is exactly zero until mode i's solve in this sweep, so
+        // the contraction with it adds exact zeros: the first sweep skips it (same bits).
+        if (kind == PPALS_SWEEP_PP_INIT && i > n) continue;
+        b.job[nj] = p->ppb[n].job[k];
         TtvJob& J = b.job[nj++];
         const int lo = std::min(i, n), hi = std::max(i, n);
         J.T = c.buf(p->leaf_buf[lo][hi]);
@@ -1186,11 +1190,13 @@ ppals_status do_pp_sweep(ppals_plan* p, double* const* A, double* S, double norm
         J.F = c.dA(i);
         J.out = part + slot_off;
         slot_off += (int64_t)J.xsplit * J.out_split_stride;
+        nslots += J.xsplit;
         const double e = (double)p->dims[i] * p->dims[n] * p->R;
         fl += 2.0 * e;
         by += e * esize(p->bulk) + (double)p->dims[i] * p->R * 8;
       }
-      by += (double)p->pp_slots[n] * p->dims[n] * p->R * 8;
+      b.njobs = nj;
+      by += (double)nslots * p->dims[n] * p->R * 8;
       const HeadArgs h = head_args(c, S, n, 1);
       ppals_status st;
       const bool fusable = ttv_tail_fusable(b);
@@ -1238,7 +1244,7 @@ ppals_status do_pp_sweep(ppals_plan* p, double* const* A, double* S, double norm
           HIPCHK(launch_ttv_tail(b, gp, h2, tail_ctr, s));
           pr.end();
         }
-        st = solve_fused(c, A, n, c.Mp(n), part, p->pp_slots[n], true, n == p->N - 1);
+        st = solve_fused(c, A, n, c.Mp(n), part, nslots, true, n == p->N - 1);
         if (st != PPALS_OK) return st;
         prev = n;
         continue;
@@ -1257,7 +1263,7 @@ ppals_status do_pp_sweep(ppals_plan* p, double* const* A, double* S, double norm
       }
       st = tail_join(c);
       if (st == PPALS_OK)
-        st = solve_fused(c, A, n, c.Mp(n), part, p->pp_slots[n], true, n == p->N - 1);
+        st = solve_fused(c, A, n, c.Mp(n), part, nslots, true, n == p->N - 1);
       if (st != PPALS_OK) return st;
       prev = n;
     }
