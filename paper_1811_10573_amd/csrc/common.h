@@ -99,6 +99,21 @@ hipError_t launch_combine(double* out, int64_t count, int R, const double* base,
 hipError_t launch_sub(double* out, const double* a, const double* b, int64_t n, hipStream_t s);
 hipError_t launch_copy(double* out, const double* a, int64_t n, hipStream_t s);
 hipError_t launch_copy_bytes(void* out, const void* in, size_t bytes, hipStream_t s);
+// End of an operator build in one launch: A_p^(n) := A^(n) for every mode (Ap holds the
+// modes back to back, mode n from off[n]), dA := 0 and U := 0, and the counters zeroed.
+struct BuildReset {
+  const double* A[PP_MAXN];
+  double* Ap;
+  int64_t off[PP_MAXN + 1];
+  int N;
+  double* dA;
+  int64_t ndA;
+  double* U;
+  int64_t nU;
+  int* ints[2];
+  int nints[2];
+};
+hipError_t launch_build_reset(const BuildReset& r, hipStream_t s);
 hipError_t launch_fill(double* out, double v, int64_t n, hipStream_t s);
 hipError_t launch_reduce_splits_to(void* out, int out_f32, const void* partial, int part_f32,
                                    int nsplit, int64_t count, hipStream_t s);

@@ -534,4 +534,29 @@ hipError_t launch_chol_standalone(const double* gamma, int R, double* L, int* st
   return hipGetLastError();
 }
 
+// End of an operator build in one launch (BuildReset).
+__global__ void k_build_reset(BuildReset r) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = t0; i < r.off[r.N]; i += stride) {
+    int n = 0;
+    while (n + 1 < r.N && i >= r.off[n + 1]) ++n;
+    r.Ap[i] = r.A[n][i - r.off[n]];
+  }
+  for (int64_t i = t0; i < r.ndA; i += stride) r.dA[i] = 0.0;
+  for (int64_t i = t0; i < r.nU; i += stride) r.U[i] = 0.0;
+  for (int q = 0; q < 2; ++q)
+    for (int64_t i = t0; i < r.nints[q]; i += stride) r.ints[q][i] = 0;
+}
+hipError_t launch_build_reset(const BuildReset& r, hipStream_t s) {
+  if (r.N < 1 || r.N > PP_MAXN) return hipErrorInvalidValue;
+  int64_t n = r.off[r.N];
+  if (r.ndA > n) n = r.ndA;
+  if (r.nU > n) n = r.nU;
+  int64_t blocks = (n + 255) / 256;
+  blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
+  hipLaunchKernelGGL(k_build_reset, dim3((unsigned)blocks), dim3(256), 0, s, r);
+  return hipGetLastError();
+}
+
 }  // namespace ppk

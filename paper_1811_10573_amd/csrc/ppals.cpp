@@ -1106,17 +1106,29 @@ ppals_status do_pp_build(ppals_plan* p, const void* X, const void* Xb, double* c
     ppals_status st = run_ttv(c, p->ttv[p->mp_ttv[n]], A, c.Mp(n), 6);
     if (st != PPALS_OK) return st;
   }
-  for (int n = 0; n < p->N; ++n) {
-    const size_t bytes = (size_t)p->dims[n] * p->R * sizeof(double);
-    HIPCHK(launch_copy(c.Ap(n), A[n], (int64_t)(bytes / sizeof(double)), s));
-    HIPCHK(launch_fill(c.dA(n), 0.0, (int64_t)(bytes / sizeof(double)), s));
-  }
-  HIPCHK(launch_fill(c.U(), 0.0, (int64_t)p->N * p->R * p->R, s));
-  // counters of the fused PP-correction launches, which each leave them at zero again
-  HIPCHK(launch_set_int(c.at<int>(p->off_gate) + 8, 0, s));
   {
+    // A_p := A, dA := 0, U := 0 and the counters of the fused PP-correction launches (which
+    // each leave them at zero again), in one launch
+    BuildReset r{};
+    r.N = p->N;
+    int64_t o = 0;
+    for (int n = 0; n < p->N; ++n) {
+      r.A[n] = A[n];
+      r.off[n] = o;
+      o += (int64_t)p->dims[n] * p->R;
+    }
+    r.off[p->N] = o;
+    r.Ap = c.Ap(0);
+    r.dA = c.dA(0);
+    r.ndA = o;
+    r.U = c.U();
+    r.nU = (int64_t)p->N * p->R * p->R;
     const int nbr = (p->R + 15) / 16;
-    HIPCHK(launch_fill(c.at<double>(p->off_gctr), 0.0, (nbr * nbr + 1) / 2, s));
+    r.ints[0] = c.at<int>(p->off_gate) + 8;
+    r.nints[0] = 1;
+    r.ints[1] = c.at<int>(p->off_gctr);
+    r.nints[1] = nbr * nbr;
+    HIPCHK(launch_build_reset(r, s));
   }
   p->ops_built = true;
   p->sweeps_since_build = 0;
