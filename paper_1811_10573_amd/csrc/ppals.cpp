@@ -157,6 +157,9 @@ struct ppals_plan {
   // state
   bool ops_built = false;
   int sweeps_since_build = 0;
+  // dA^(n) = 0 for every mode since the last build (set by the build, cleared by the first
+  // sweep after it and by every other writer of dA)
+  bool dA_zero = false;
 
   // learned controller for leaving the PP phase (ppals_set_controller)
   bool ctl_set = false;
@@ -219,6 +222,11 @@ int64_t prod_dims(const ppals_plan* p, const std::vector<int>& modes, int a, int
 // of the slab kind shorten the tail of a launch; one round of large workgroups is slower.
 constexpr int64_t kTtvRound = 3200;
 constexpr int kGramSplitMax = 4;  // row ranges per Gram tile in PP sweeps
+// Row ranges of a PP sweep's Gram tiles for a factor of `rows` rows: ranges of at least 192
+// rows, at most kGramSplitMax.
+int gram_ranges(int64_t rows) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(kGramSplitMax, rows / 192));
+}
 
 // target: workgroups wanted for this job (slab kind; 2/5 of it for the row kind).
 void ttv_config(TtvJob& J, int64_t P, int64_t X, int64_t Q, int R, int es, int64_t target) {
@@ -665,8 +673,14 @@ void make_describe(ppals_plan* p) {
   std::string reuse = "null";
   if (p->reuse_l1 >= 0)
     reuse = "[" + std::to_string(p->l1[p->reuse_l1].lo) + "," + std::to_string(p->l1[p->reuse_l1].hi) + "]";
+  // row ranges of the PP sweeps' Gram tiles per mode (rank <= 64 path only)
+  std::string ranges = "[";
+  for (int n = 0; n < p->N; ++n)
+    ranges += (n ? "," : "") + std::to_string(p->fast ? gram_ranges(p->dims[n]) : 0);
+  ranges += "]";
   p->describe = std::string("{") + tmp + ",\"dt_ops\":" + dt + ",\"pp_build_ops\":" + pp +
-                ",\"pp_build_reused_after_als\":" + reuse + "}";
+                ",\"pp_build_reused_after_als\":" + reuse + ",\"fused_tail\":" +
+                (p->fast ? "true" : "false") + ",\"pp_gram_ranges\":" + ranges + "}";
 }
 
 // ---------------------------------------------------------------------------
@@ -911,7 +925,7 @@ HeadArgs head_args(const Ctx& c, double* S, int n, int pp) {
 // least 192 rows, so that the fused launch's Gram role, which runs beside the
 // contraction's memory traffic, takes fewer dependent load rounds per workgroup.
 void gram_split(const Ctx& c, GramArgs& g) {
-  g.nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(kGramSplitMax, g.rows / 192));
+  g.nsplit = gram_ranges(g.rows);
   g.gpart = c.at<double>(c.p->off_gpart);
   g.gctr = c.at<int>(c.p->off_gctr);
 }
@@ -1132,6 +1146,7 @@ ppals_status do_pp_build(ppals_plan* p, const void* X, const void* Xb, double* c
   }
   p->ops_built = true;
   p->sweeps_since_build = 0;
+  p->dA_zero = true;
   return PPALS_OK;
 }
 
@@ -1179,6 +1194,8 @@ ppals_status do_pp_sweep(ppals_plan* p, double* const* A, double* S, double norm
                          ppals_sweep_record* rec, hipStream_t s) {
   Ctx c{p, (char*)ws, s};
   const int kind = p->sweeps_since_build == 0 ? PPALS_SWEEP_PP_INIT : PPALS_SWEEP_PP_APPROX;
+  const bool dA_zero = p->dA_zero;
+  p->dA_zero = false;
   int prev = -1;
   if (p->fast) {
     double* part = c.at<double>(p->off_ppart);
@@ -1193,7 +1210,7 @@ ppals_status do_pp_sweep(ppals_plan* p, double* const* A, double* S, double norm
         const int i = pp_job_mode(p->N, n, k);
         // Right after a build dA^(i) is exactly zero until mode i's solve in this sweep, so
         // the contraction with it adds exact zeros: the first sweep skips it (same bits).
-        if (kind == PPALS_SWEEP_PP_INIT && i > n) continue;
+        if (dA_zero && i > n) continue;
         b.job[nj] = p->ppb[n].job[k];
         TtvJob& J = b.job[nj++];
         const int lo = std::min(i, n), hi = std::max(i, n);
@@ -1465,6 +1482,7 @@ ppals_status rhs_error(ppals_plan* p, const void* X, const void* Xb, double* con
     }
     if (st != PPALS_OK) return st;
   }
+  p->dA_zero = false;  // dA is rewritten from the current factors
   for (int i = 0; i < p->N; ++i) {
     const int64_t cnt = p->dims[i] * (int64_t)p->R;
     HIPCHK(launch_sub(c.dA(i), A[i], c.Ap(i), cnt, s));
@@ -1794,6 +1812,7 @@ ppals_status ppals_pp_rhs(ppals_plan* p, double* const* A, const double* S, int3
   Ctx c{p, (char*)ws, s};
   // dA_i = A_i - A_p,i and U_i = A_i^T dA_i for every mode (the gram kernel's S
   // output goes to the L scratch, which mode_begin overwrites afterwards)
+  p->dA_zero = false;  // dA is rewritten from the current factors
   for (int i = 0; i < p->N; ++i) {
     const int64_t cnt = p->dims[i] * (int64_t)p->R;
     HIPCHK(launch_sub(c.dA(i), A[i], c.Ap(i), cnt, s));
@@ -1888,7 +1907,8 @@ ppals_status ppals_run(ppals_plan* p, const void* X, const void* Xb, double* con
           if (it >= 2) r0 = std::max(r0, host_records[it - 2].rel_change[n]);
         }
         if (it >= 2 && host_records[it - 2].sweep_kind == PPALS_SWEEP_PP_APPROX && r1 > r0)
-          L = 1 + (int)std::floor((eps - r1) / (r1 - r0));
+          L = 1 + (int)std::min<double>(ppals_plan::kLookahead,
+                                        std::max(0.0, std::floor((eps - r1) / (r1 - r0))));
       }
       L = std::max(1, std::min(L, std::min(ppals_plan::kLookahead, max_sweeps - it)));
       if (!p->la_rec)

@@ -79,3 +79,73 @@ def level1_reference(X, A, contract, tier):
     val = ocp.partial_mttkrp(Xr, Ar, keep)
     base = ocp.partial_mttkrp(np.abs(Xr), [np.abs(a) for a in Ar], keep)
     return val, base
+
+
+def oracle_fit(X, A):
+    """Fit 1 - ||X - [[A]]||_F / ||X||_F of the factors A against X, evaluated by the
+    oracle's identity with the exact right-hand side of the last mode (no dense model)."""
+    N = X.ndim
+    A = [np.asarray(a, dtype=np.float64) for a in A]
+    S = [a.T @ a for a in A]
+    M = ocp.mttkrp(X, A, N - 1)
+    return ocp.fit_identity(float(np.sum(X * X)), M, A[N - 1], ocp.hadamard_except(S, N - 1), S[N - 1])
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def oracle_sensitivity(fn, A0, rel_pert=1e-15, seed=0):
+    """How far the oracle's own trajectory moves when its start is perturbed at the
+    level of rounding: the bound a faithful re-implementation can be held to.
+    fn maps a list of start factors to a list of end factors."""
+    rng = np.random.default_rng(seed)
+    base = fn([a.copy() for a in A0])
+    pert = fn([a * (1 + rel_pert * rng.standard_normal(a.shape)) for a in A0])
+    return max(rel(x, y) for x, y in zip(pert, base))
+
+
+class Run:
+    """Device copies of one problem plus the library state (plan, workspace, record)."""
+
+    def __init__(self, prob, tier="f64", second_order=True, init=None, X=None):
+        import paper_1811_10573_amd as pp
+        self.pp = pp
+        self.prob = prob
+        self.tier = tier
+        dims = prob.shape
+        R = prob.rank
+        tdt = "f64" if tier == "f64" else "f32"
+        self.plan = pp.Plan(dims, R, tdt, tier, second_order)
+        X = prob.X if X is None else X
+        self.Xh = X if tier == "f64" else fp32_round(X)
+        self.X = to_dev(self.Xh, self.plan.torch_dtype)
+        self.Xb = None
+        if tier == "bf16":
+            self.Xb = torch.empty(self.X.numel(), dtype=torch.int16, device=dev())
+            pp.cast_bf16(self.X, self.Xb)
+        init = prob.init if init is None else init
+        self.A = [to_dev(a.copy()) for a in init]
+        self.N = len(dims)
+        self.S = to_dev(np.stack([a.T @ a for a in init]).reshape(-1))
+        self.ws = self.plan.workspace(dev())
+        self.rec = pp.new_record(dev())
+        nrm = torch.zeros(1, dtype=torch.float64, device=dev())
+        pp.tensor_norm2(self.X, nrm)
+        self.normX2 = float(nrm.item())
+
+    def factors(self):
+        return [a.cpu().numpy().reshape(s, self.prob.rank) for a, s in zip(self.A, self.prob.shape)]
+
+    def grams(self):
+        R = self.prob.rank
+        return self.S.cpu().numpy().reshape(self.N, R, R)
+
+    def run(self, eps, max_sweeps, replay=None, profiling=False):
+        self.pp.set_profiling(self.plan, profiling)
+        try:
+            recs, ms = self.pp.run(self.plan, self.X, self.Xb, self.A, self.S, self.normX2, self.ws,
+                                   self.rec, eps=eps, max_sweeps=max_sweeps, replay=replay)
+        finally:
+            self.pp.set_profiling(self.plan, False)
+        return list(recs), ms
