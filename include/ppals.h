@@ -173,6 +173,23 @@ ppals_status gram_solve(int32_t R, int64_t rows, const double* Gamma, const void
                         int32_t m_dtype, double* A_inout, double* grad_norm_out,
                         int32_t* chol_status_out, void* ws, hipStream_t stream);
 
+/* gram_solve without a workspace argument, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and errors as gram_solve; the scratch (L, the
+ * per-row partial sums and the status word) is a fixed array inside the library, one
+ * copy per GPU, held until the process ends: PPALS_MAX_RANK^2 doubles plus 4 doubles
+ * per row for up to PPALS_GRAM_SOLVE_NOALLOC_MAX_ROWS rows (about 2.1 MiB).
+ *   rows > PPALS_GRAM_SOLVE_NOALLOC_MAX_ROWS  -> PPALS_E_UNSUPPORTED (nothing enqueued).
+ * The call allocates nothing (no hipMalloc, hipFree or allocating library routine); the
+ * first call on a device looks the array's address up once (hipGetSymbolAddress).
+ * Every call on one GPU shares that GPU's array and leaves its last contents there
+ * (no entry of it needs to start at zero): calls that overlap on one GPU, on different
+ * streams or from different threads, race and must be serialised by the caller. */
+#define PPALS_GRAM_SOLVE_NOALLOC_MAX_ROWS 65536
+ppals_status gram_solve_noalloc(int32_t R, int64_t rows, const double* Gamma, const void* M,
+                                int32_t m_dtype, double* A_inout, double* grad_norm_out,
+                                int32_t* chol_status_out, hipStream_t stream);
+
 /* ||X||_F^2 accumulated in FP64 into *out (device double).  dtype FP64/FP32.
  * ws must hold ppals_norm2_workspace_bytes() bytes. */
 size_t ppals_norm2_workspace_bytes(void);

@@ -216,6 +216,24 @@ def gram_solve(R, rows, Gamma, M, A, grad_out, status_out, ws, stream=None):
                                 _p(status_out), _p(ws), _stream(stream)))
 
 
+GRAM_SOLVE_NOALLOC_MAX_ROWS = 65536
+
+
+def gram_solve_noalloc(R, rows, Gamma, M, A, grad_out, status_out, stream=None):
+    """gram_solve with the library's fixed scratch array instead of a workspace (no
+    device allocation; calls on one GPU must not overlap)."""
+    _dev(Gamma, "Gamma", torch.float64, R * R)
+    if M.dtype not in (torch.float64, torch.float32):
+        raise ValueError("M must be float64 or float32")
+    _dev(M, "M", None, rows * R)
+    _dev(A, "A", torch.float64, rows * R)
+    _dev(grad_out, "grad_out", torch.float64)
+    _dev(status_out, "status_out", torch.int32)
+    mdt = PPALS_FP64 if M.dtype == torch.float64 else PPALS_FP32
+    _lib.check(lib().gram_solve_noalloc(int(R), int(rows), _p(Gamma), _p(M), mdt, _p(A),
+                                        _p(grad_out), _p(status_out), _stream(stream)))
+
+
 def tensor_norm2(X, out, ws=None, stream=None):
     if X.dtype not in (torch.float64, torch.float32):
         raise ValueError("X must be float64 or float32")

@@ -113,6 +113,7 @@ SIGNATURES = {
     "pp_sweep": (_i32, [_vp, _ptrs, _vp, _dbl, _vp, _vp, _vp]),
     "ppals_gram_solve_workspace_bytes": (_sz, [_i32, _i64]),
     "gram_solve": (_i32, [_i32, _i64, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "gram_solve_noalloc": (_i32, [_i32, _i64, _vp, _vp, _i32, _vp, _vp, _vp, _vp]),
     "ppals_norm2_workspace_bytes": (_sz, []),
     "ppals_tensor_norm2": (_i32, [_vp, _i32, _i64, _vp, _vp, _vp]),
     "ppals_cast_bf16": (_i32, [_vp, _vp, _i64, _vp]),

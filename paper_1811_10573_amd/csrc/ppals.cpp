@@ -22,6 +22,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -1501,6 +1502,80 @@ ppals_status rhs_error(ppals_plan* p, const void* X, const void* Xb, double* con
   return PPALS_OK;
 }
 
+namespace {
+
+// The solve behind gram_solve and gram_solve_noalloc.  w is the scratch: L (R x R), the
+// per-row partial sums (rows x 4) and the status word, at the offsets of
+// ppals_gram_solve_workspace_bytes.  Every entry of it that a kernel reads is written
+// earlier in the same call, so nothing in it has to start at zero.
+ppals_status gram_solve_impl(int32_t R, int64_t rows, const double* Gamma, const void* M,
+                             int32_t m_dtype, double* A_inout, double* grad_norm_out,
+                             int32_t* chol_status_out, char* w, hipStream_t s) {
+  double* L = (double*)w;
+  double* rowpart = (double*)(w + align256((size_t)R * R * 8));
+  int* status = (int*)(w + align256((size_t)R * R * 8) + align256((size_t)rows * 4 * 8));
+  HIPCHK(launch_chol_standalone(Gamma, R, L, status, s));
+  SolveArgs a;
+  memset(&a, 0, sizeof(a));
+  a.R = R;
+  a.rows = rows;
+  if (m_dtype == PPALS_FP64) a.M = (const double*)M;
+  else a.M32 = (const float*)M;
+  a.L = L;
+  a.gamma = Gamma;
+  a.A = A_inout;
+  a.rowpart = rowpart;
+  a.status = status;
+  HIPCHK(launch_solve_rows(a, s));
+  HIPCHK(launch_finish_gram_solve(rowpart, rows, grad_norm_out, chol_status_out, status, s));
+  return PPALS_OK;
+}
+
+ppals_status gram_solve_check(int32_t R, int64_t rows, const double* Gamma, const void* M,
+                              int32_t m_dtype, double* A_inout, double* grad_norm_out,
+                              int32_t* chol_status_out) {
+  if (R < 1 || R > PPALS_MAX_RANK) return fail(PPALS_E_UNSUPPORTED, "rank must be in [1, 128]");
+  if (rows < 1) return fail(PPALS_E_ARG, "rows must be >= 1");
+  if (!Gamma || !M || !A_inout || !grad_norm_out || !chol_status_out)
+    return fail(PPALS_E_ARG, "NULL argument");
+  if (m_dtype != PPALS_FP64 && m_dtype != PPALS_FP32)
+    return fail(PPALS_E_UNSUPPORTED, "m_dtype must be FP64 or FP32");
+  return PPALS_OK;
+}
+
+// Scratch of gram_solve_noalloc: a fixed device array of the library, laid out like the
+// workspace of gram_solve at the largest supported size.  Each GPU holds its own copy until
+// the process ends; host code reaches it only through the address hipGetSymbolAddress
+// returns on that GPU (the array's name is a host-side stand-in, not a device address).
+constexpr int64_t kNoAllocMaxRows = PPALS_GRAM_SOLVE_NOALLOC_MAX_ROWS;
+constexpr size_t kNoAllocBytes = (size_t)PPALS_MAX_RANK * PPALS_MAX_RANK * 8 +
+                                 (size_t)kNoAllocMaxRows * 4 * 8 + 256;
+static_assert((size_t)PPALS_MAX_RANK * PPALS_MAX_RANK * 8 % 256 == 0, "L block must stay aligned");
+static_assert((size_t)kNoAllocMaxRows * 4 * 8 % 256 == 0, "row block must stay aligned");
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+ppals_status scratch_address(char** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(PPALS_E_UNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(PPALS_E_HIP, "hipGetSymbolAddress returned NULL for the scratch array");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = (char*)g_scratch_ptr[dev];
+  return PPALS_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 ppals_status ppals_plan_create(const ppals_desc* d, ppals_plan** out) {
@@ -1698,33 +1773,30 @@ size_t ppals_gram_solve_workspace_bytes(int32_t R, int64_t rows) {
 ppals_status gram_solve(int32_t R, int64_t rows, const double* Gamma, const void* M,
                         int32_t m_dtype, double* A_inout, double* grad_norm_out,
                         int32_t* chol_status_out, void* ws, hipStream_t s) {
-  if (R < 1 || R > PPALS_MAX_RANK) return fail(PPALS_E_UNSUPPORTED, "rank must be in [1, 128]");
-  if (rows < 1) return fail(PPALS_E_ARG, "rows must be >= 1");
-  if (!Gamma || !M || !A_inout || !grad_norm_out || !chol_status_out)
-    return fail(PPALS_E_ARG, "NULL argument");
-  if (m_dtype != PPALS_FP64 && m_dtype != PPALS_FP32)
-    return fail(PPALS_E_UNSUPPORTED, "m_dtype must be FP64 or FP32");
+  ppals_status st = gram_solve_check(R, rows, Gamma, M, m_dtype, A_inout, grad_norm_out,
+                                     chol_status_out);
+  if (st != PPALS_OK) return st;
   if (!ws) return fail(PPALS_E_WORKSPACE, "workspace is NULL");
   if ((uintptr_t)ws % 256 != 0) return fail(PPALS_E_WORKSPACE, "workspace is not 256-byte aligned");
-  char* w = (char*)ws;
-  double* L = (double*)w;
-  double* rowpart = (double*)(w + align256((size_t)R * R * 8));
-  int* status = (int*)(w + align256((size_t)R * R * 8) + align256((size_t)rows * 4 * 8));
-  HIPCHK(launch_chol_standalone(Gamma, R, L, status, s));
-  SolveArgs a;
-  memset(&a, 0, sizeof(a));
-  a.R = R;
-  a.rows = rows;
-  if (m_dtype == PPALS_FP64) a.M = (const double*)M;
-  else a.M32 = (const float*)M;
-  a.L = L;
-  a.gamma = Gamma;
-  a.A = A_inout;
-  a.rowpart = rowpart;
-  a.status = status;
-  HIPCHK(launch_solve_rows(a, s));
-  HIPCHK(launch_finish_gram_solve(rowpart, rows, grad_norm_out, chol_status_out, status, s));
-  return PPALS_OK;
+  return gram_solve_impl(R, rows, Gamma, M, m_dtype, A_inout, grad_norm_out, chol_status_out,
+                         (char*)ws, s);
+}
+
+ppals_status gram_solve_noalloc(int32_t R, int64_t rows, const double* Gamma, const void* M,
+                                int32_t m_dtype, double* A_inout, double* grad_norm_out,
+                                int32_t* chol_status_out, hipStream_t s) {
+  ppals_status st = gram_solve_check(R, rows, Gamma, M, m_dtype, A_inout, grad_norm_out,
+                                     chol_status_out);
+  if (st != PPALS_OK) return st;
+  if (rows > kNoAllocMaxRows)
+    return fail(PPALS_E_UNSUPPORTED, "gram_solve_noalloc: rows = " + std::to_string(rows) +
+                                         " exceeds the fixed scratch limit of " +
+                                         std::to_string(kNoAllocMaxRows) + " rows");
+  char* w = nullptr;
+  st = scratch_address(&w);
+  if (st != PPALS_OK) return st;
+  return gram_solve_impl(R, rows, Gamma, M, m_dtype, A_inout, grad_norm_out, chol_status_out, w,
+                         s);
 }
 
 size_t ppals_norm2_workspace_bytes(void) { return 1024 * sizeof(double); }
