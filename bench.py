@@ -39,6 +39,17 @@ PEAK = {  # MI355X published peaks
 }
 
 
+# The paper's own speedups for this path (context, not targets): Intel Xeon Phi KNL nodes
+# (68 cores, 64 threads for the BLAS and tensor-transpose libraries), precision not stated.
+PAPER_NUMBERS = {
+    "hardware": "Intel Xeon Phi KNL (Stampede2), one node, 64 threads; NumPy/MKL/HPTT",
+    "pp_approx_vs_dt_sweep": {"order3_R_eq_s": 6.3, "orders3to6_R50": 33.0},
+    "pp_init_over_dt_sweep": [1.5, 2.0],
+    "time_to_solution_collinear_synthetic": 2.0,
+    "source": "Section 5.1 (per-sweep comparison and synthetic collinearity experiments)",
+}
+
+
 def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
@@ -97,6 +108,57 @@ def cpu_baseline(X, init, rank, eps, gpu_kinds, budget_s):
         "per_sweep_s": per,
         "host_cpus": len(os.sched_getaffinity(0)),
     }
+
+
+def oracle_replay(X, init, kinds, cap_s):
+    """The float64 oracle replaying the GPU run's sweep-kind sequence on the same tensor
+    (host cores): per-kind sweep times and, when the whole sequence ran within cap_s,
+    the final factors and the oracle's fit of them."""
+    import threadpoolctl
+    from oracle import cp as ocp
+    from oracle import pp as opp
+
+    threads = max((p.get("num_threads", 1) for p in threadpoolctl.threadpool_info()), default=1)
+    A = [a.copy() for a in init]
+    S = [a.T @ a for a in A]
+    normX2 = float(np.sum(X * X))
+    times = {"als": [], "pp_init": [], "pp_approx": []}
+    state = None
+    start = time.perf_counter()
+    done = 0
+    for i, kind in enumerate(kinds):
+        t0 = time.perf_counter()
+        if kind == "als":
+            ocp.als_sweep(X, A, S, normX2)
+        elif kind == "pp_init":
+            state = opp.build_operators(X, A)
+            opp.pp_sweep(state, A, S, normX2, True, "pp_init")
+        else:
+            opp.pp_sweep(state, A, S, normX2, True, "pp_approx")
+        times[kind].append(time.perf_counter() - t0)
+        done = i + 1
+        if done % 25 == 0:
+            log(f"oracle replay: {done}/{len(kinds)} sweeps, {time.perf_counter() - start:.1f} s")
+        if time.perf_counter() - start > cap_s:
+            break
+    out = {"threads": int(threads), "sweeps": done, "seconds": time.perf_counter() - start,
+           "per_sweep_s": {k: (float(np.mean(v)) if v else None) for k, v in times.items()},
+           "complete": done == len(kinds), "A": None, "fit": None}
+    if out["complete"]:
+        out["A"] = A
+        out["fit"] = oracle_fit(X, A)
+    return out
+
+
+def oracle_fit(X, A):
+    """1 - ||X - [[A]]||_F / ||X||_F by the oracle's identity with the exact right-hand
+    side of the last mode."""
+    from oracle import cp as ocp
+    N = X.ndim
+    S = [a.T @ a for a in A]
+    M = ocp.mttkrp(X, A, N - 1)
+    return ocp.fit_identity(float(np.sum(X * X)), M, A[N - 1], ocp.hadamard_except(S, N - 1),
+                            S[N - 1])
 
 
 COPY_BYTES = 1 << 30
@@ -237,6 +299,166 @@ def batch_bench(args, torch, dev):
     print(json.dumps(line), flush=True)
 
 
+def roof_of(stat, bound, peak, traffic=None):
+    """Roofline entry of one kernel class from its HIP-event statistics (algorithmic work
+    per launch over the average launch time)."""
+    if not stat or stat["launches"] == 0:
+        return None
+    if bound == "mfma":
+        ach = stat["flops"] / (stat["total_ms"] * 1e-3) / 1e12
+        unit, work = "TFLOP/s", stat["flops"]
+    else:
+        ach = stat["bytes"] / (stat["total_ms"] * 1e-3) / 1e9
+        unit, work = "GB/s", stat["bytes"]
+    return {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
+            "traffic": traffic, "launches": stat["launches"], "avg_ms": stat["avg_ms"],
+            "work_per_launch": work / stat["launches"]}
+
+
+def f64_leg(pp, torch, dev, prob, shape, R, eps, sweeps, kinds_replay, warmup, steps):
+    """The same decomposition with the FP64 tier on the FP64 tensor: free-running sweeps/s
+    (graph replays, X resident), the per-kernel roofline from one profiled step, and a
+    replay of the FP32 run's sweep kinds whose final factors go to the oracle comparison."""
+    X = torch.from_numpy(prob.X).to(dev).reshape(-1)
+    plan = pp.Plan(shape, R, "f64", "f64", True)
+    ws = plan.workspace(dev)
+    A0 = [torch.from_numpy(a).to(dev) for a in prob.init]
+    A = [a.clone() for a in A0]
+    S = torch.zeros(len(shape) * R * R, dtype=torch.float64, device=dev)
+    rec = pp.new_record(dev)
+    nrm = torch.zeros(1, dtype=torch.float64, device=dev)
+    pp.tensor_norm2(X, nrm)
+    normX2 = float(nrm.item())
+
+    def run(replay=None, timing=False):
+        for a, a0 in zip(A, A0):
+            a.copy_(a0)
+        return pp.run(plan, X, None, A, S, normX2, ws, rec, eps=eps, max_sweeps=sweeps,
+                      replay=replay, timing=timing)
+
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    for _ in range(steps):
+        recs, _ = run()
+        done += len(recs)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    recs, ms = run(timing=True)
+    kinds = [r["kind"] for r in recs]
+    pp.get_profile(plan, reset=True)
+    pp.set_profiling(plan, True)
+    run()
+    torch.cuda.synchronize()
+    pp.set_profiling(plan, False)
+    prof = pp.get_profile(plan, reset=True)
+    res2 = torch.zeros(1, dtype=torch.float64, device=dev)
+    pp.exact_residual2(plan, X, A, res2, ws)
+    fit_free = 1.0 - float(np.sqrt(res2.item() / normX2))
+    run(replay=kinds_replay)
+    torch.cuda.synchronize()
+    A_replay = [a.cpu().numpy().reshape(s, R) for a, s in zip(A, shape)]
+    out = {
+        "sweeps_per_s": done / elapsed, "steps": steps, "ms_per_step": elapsed / steps * 1e3,
+        "sweep_mix": {k: kinds.count(k) for k in ("als", "pp_init", "pp_approx")},
+        "per_kind_ms": {k: (float(np.mean([m for r, m in zip(recs, ms) if r["kind"] == k]))
+                            if k in kinds else None) for k in ("als", "pp_init", "pp_approx")},
+        "final_fit_exact": fit_free,
+        "roofline_level1": roof_of(prof.get("level1_gemm"), "mfma", PEAK["f64_TFs"],
+                                   measured_traffic("level1_gemm", "f64", shape, R)),
+        "roofline_pp_ttv": roof_of(prof.get("pp_correct_ttv"), "hbm", PEAK["hbm_GBs"],
+                                   measured_traffic("pp_correct_ttv", "f64", shape, R)),
+    }
+    log(f"FP64 tier: {out['sweeps_per_s']:.1f} sweeps/s, mix {out['sweep_mix']}, "
+        f"fit {fit_free:.10f}")
+    del ws, X
+    torch.cuda.empty_cache()
+    return out, A_replay
+
+
+def c1_leg(pp, torch, dev, tensorgen, runs=20):
+    """64^3 FP64 tensor, planted rank 10 (N(0,1) factors), 1e-3 noise, rank 10, 20 ALS
+    sweeps from the seeded uniform start: sweeps/s over `runs` whole runs and the
+    per-sweep fit estimates (compared with the oracle in the oracle leg)."""
+    prob = tensorgen.make_problem((64, 64, 64), 10, seed=0, eta=1e-3)
+    plan = pp.Plan(prob.shape, 10, "f64")
+    X = torch.from_numpy(prob.X).to(dev)
+    A0 = [torch.from_numpy(a).to(dev) for a in prob.init]
+    A = [a.clone() for a in A0]
+    S = torch.zeros(3 * 100, dtype=torch.float64, device=dev)
+    ws = plan.workspace(dev)
+    rec = pp.new_record(dev)
+    nrm = torch.zeros(1, dtype=torch.float64, device=dev)
+    pp.tensor_norm2(X, nrm)
+
+    def run():
+        for a, a0 in zip(A, A0):
+            a.copy_(a0)
+        return pp.run(plan, X, None, A, S, float(nrm.item()), ws, rec, eps=0.0, max_sweeps=20,
+                      timing=False)
+
+    recs, _ = run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(runs):
+        recs, _ = run()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    out = {"workload": "64x64x64 FP64, planted rank 10, 1e-3 noise, rank 10, 20 ALS sweeps",
+           "sweeps_per_s": 20 * runs / elapsed, "ms_per_run": elapsed / runs * 1e3,
+           "fits": [r["fit_est"] for r in recs]}
+    log(f"C1: {out['sweeps_per_s']:.0f} sweeps/s ({out['ms_per_run']:.2f} ms per 20-sweep run)")
+    return out, prob
+
+
+def c3_level1_leg(pp, torch, dev, tensorgen, reps=5):
+    """First-level contractions of the order-4 workload (160^4 FP32 tensor, planted rank 64,
+    1e-2 noise, assembled on the device; R = 64): the two two-mode contractions of the ALS
+    dimension tree (K = 160^2), FP32 and BF16-input tiers, timed with HIP events."""
+    shape, R = (160, 160, 160, 160), 64
+    prob = tensorgen.make_problem_device(shape, R, 0, eta=1e-2, dtype="f32", device=dev)
+    X = prob.X.reshape(-1)
+    Xb = torch.empty(X.numel(), dtype=torch.int16, device=dev)
+    pp.cast_bf16(X, Xb)
+    A = [torch.from_numpy(a).to(dev) for a in prob.init]
+    out = {"workload": "160^4 FP32 (BF16 copy for the BF16 tier), R = 64; X contracted with "
+                       "the Khatri-Rao product of modes (3,4) and of modes (1,2)"}
+    for tier in ("f32", "bf16"):
+        plan = pp.Plan(shape, R, "f32", tier, True)
+        ws = plan.workspace(dev)
+        res = {}
+        for name, modes in (("contract_modes_34", (2, 3)), ("contract_modes_12", (0, 1))):
+            o = torch.empty(160 * 160 * R, dtype=torch.float32, device=dev)
+            pp.level1(plan, X, Xb, A, modes, o, ws)
+            torch.cuda.synchronize()
+            pp.get_profile(plan, reset=True)
+            pp.set_profiling(plan, True)
+            for _ in range(reps):
+                pp.level1(plan, X, Xb, A, modes, o, ws)
+            torch.cuda.synchronize()
+            pp.set_profiling(plan, False)
+            prof = pp.get_profile(plan, reset=True)
+            g = prof["level1_gemm"]
+            e = {"avg_ms": g["avg_ms"], "TFLOP_s": g["flops"] / (g["total_ms"] * 1e-3) / 1e12,
+                 "HBM_GB_s": g["bytes"] / (g["total_ms"] * 1e-3) / 1e9}
+            e["mfma_frac"] = e["TFLOP_s"] / PEAK["f32_TFs" if tier == "f32" else "bf16_TFs"]
+            e["hbm_frac"] = e["HBM_GB_s"] / PEAK["hbm_GBs"]
+            sr = prof.get("split_reduce")
+            if sr and sr["launches"]:
+                e["split_reduce_avg_ms"] = sr["avg_ms"]
+            res[name] = e
+            del o
+        out[tier] = res
+        log(f"C3 level 1 {tier}: " + ", ".join(f"{k} {v['avg_ms']:.3f} ms {v['TFLOP_s']:.1f} TF/s"
+                                                 for k, v in res.items()))
+        del ws, plan
+    del X, Xb, prob
+    torch.cuda.empty_cache()
+    return out
+
+
 # source file of each kernel class whose HBM traffic has a committed counter summary
 # sources whose SHA-256 (of their concatenation, in this order) the counter summary names
 TRAFFIC_SOURCE = {"level1_gemm": ["k_level1.hip"], "pp_correct_ttv": ["k_ttv.hip", "tail_bodies.h"]}
@@ -293,6 +515,10 @@ def main():
     ap.add_argument("--workload", default="pp", choices=["pp", "batch"],
                     help="pp: the 800^3 decomposition (default); batch: 512 independent problems")
     ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the FP64 tier, the 64^3 ALS and the 160^4 first-level legs")
+    ap.add_argument("--oracle-cap", type=float, default=300.0,
+                    help="seconds the oracle replay of the run's sweep kinds may take")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for scaling HBM counters)")
     args = ap.parse_args()
@@ -402,6 +628,7 @@ def main():
     pp.exact_residual2(plan, X, A, res2, ws)
     fit_pp = 1.0 - float(np.sqrt(res2.item() / normX2))
     A_pp = [a.clone() for a in A] if args.compare_f64 else None
+    A_final = [a.cpu().numpy().reshape(sz, R) for a, sz in zip(A, shape)]
 
     out_dt = None
     speedup = None
@@ -493,12 +720,70 @@ def main():
                 "fit_abs_diff": abs(fit_tier_on64 - fit64), "factor_rel_diff_max": fdiff}
         log(f"vs FP64 replay: fit {fit_tier_on64:.10f} vs {fit64:.10f}, factor rel diff {fdiff:.2e}")
         del ws64, X64
+    # further legs of the default workload: the FP64 tier on the same decomposition, the
+    # 64^3 ALS configuration and the first-level contractions of the 160^4 configuration
+    extras = (not args.no_extras and args.tier == "f32" and args.order == 3 and s == 800
+              and R == 50 and not args.device_gen)
+    f64 = c1 = c3 = None
+    A_f64_replay = c1prob = None
+    if extras:
+        del ws
+        torch.cuda.empty_cache()
+        f64, A_f64_replay = f64_leg(pp, torch, dev, prob, shape, R, args.eps, args.sweeps, kinds,
+                                    warmup=1, steps=2)
+        c1, c1prob = c1_leg(pp, torch, dev, tensorgen)
+        c3 = c3_level1_leg(pp, torch, dev, tensorgen)
+
     cpu = None
+    vs_oracle = None
     if not args.no_cpu_baseline:
-        log("timing the float64 oracle on the host (bounded sample)")
         Xh = prob.X if not args.device_gen else prob.X.cpu().numpy()
-        cpu = cpu_baseline(Xh, prob.init, R, args.eps, kinds, args.cpu_seconds)
+        if extras:
+            log("float64 oracle replaying the run's sweep kinds on the host")
+            rep = oracle_replay(Xh, prob.init, kinds, args.oracle_cap)
+            per = rep["per_sweep_s"]
+            counts = {k: kinds.count(k) for k in per}
+            total = sum(counts[k] * per[k] for k in per if per[k] is not None)
+            cpu = {"value": len(kinds) / total if total > 0 else None, "unit": "sweeps/s",
+                   "cores": rep["threads"], "kind": "oracle",
+                   "sample": (f"float64 oracle replaying this run's {len(kinds)} sweep kinds on "
+                              f"the same tensor: {rep['sweeps']} sweeps in {rep['seconds']:.1f} s; "
+                              f"per-kind mean times weighted by the mix {counts}"),
+                   "per_sweep_s": per, "host_cpus": len(os.sched_getaffinity(0))}
+            if rep["complete"]:
+                f_or = rep["fit"]
+                f32_fit = oracle_fit(Xh, A_final)
+                f64_fit = oracle_fit(Xh, A_f64_replay)
+
+                def fdiff(G):
+                    return max(float(np.linalg.norm(g - o) / np.linalg.norm(o))
+                               for g, o in zip(G, rep["A"]))
+                vs_oracle = {
+                    "what": "final fit of the GPU factors and of the float64 oracle's, both "
+                            "evaluated by the oracle on the FP64 tensor, with this run's sweep "
+                            "kinds replayed by the oracle and by the FP64 tier",
+                    "oracle_fit": f_or,
+                    "f32_fit": f32_fit, "f32_fit_rel_err": abs(f32_fit - f_or) / abs(f_or),
+                    "f32_factor_rel_diff_max": fdiff(A_final),
+                    "f64_fit": f64_fit, "f64_fit_rel_err": abs(f64_fit - f_or) / abs(f_or),
+                    "f64_factor_rel_diff_max": fdiff(A_f64_replay),
+                }
+                log(f"vs oracle: fit {f_or:.12f}; FP32 rel err {vs_oracle['f32_fit_rel_err']:.2e}, "
+                    f"FP64 rel err {vs_oracle['f64_fit_rel_err']:.2e}")
+            if c1 is not None:
+                from oracle import cp as ocp
+                _, ref = ocp.cp_als(c1prob.X, c1prob.init, 20)
+                c1["fit_rel_err_max_vs_oracle"] = max(abs(g - o.fit_est) / abs(o.fit_est)
+                                                      for g, o in zip(c1["fits"], ref))
+                c1["final_fit"] = c1["fits"][-1]
+            if c1 is not None:
+                del c1["fits"]
+        else:
+            log("timing the float64 oracle on the host (bounded sample)")
+            cpu = cpu_baseline(Xh, prob.init, R, args.eps, kinds, args.cpu_seconds)
         log(f"oracle: {cpu['value']:.4f} sweeps/s projected for the same sweep mix")
+    elif c1 is not None:
+        del c1["fits"]
 
     line = {
         "metric": METRIC,
@@ -529,7 +814,11 @@ def main():
         "pp": {"final_fit_exact": fit_pp, "final_fit_est": recs[-1]["fit_est"], "per_kind": per_kind},
         "dt_als": out_dt,
         "pp_vs_dt_time_to_equal_fit": speedup,
-        "vs_f64": vs64,
+        "vs_f64": vs64 if vs64 is not None else vs_oracle,
+        "f64_tier": f64,
+        "c1_als": c1,
+        "c3_level1": c3,
+        "paper_reference": PAPER_NUMBERS,
         "kernels": kernels,
     }
     print(json.dumps(line), flush=True)
