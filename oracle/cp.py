@@ -149,27 +149,33 @@ class SweepRecord:
     rhs: list = None          # right-hand sides used (kept for tests)
 
 
-def als_update(A, S, n, M):
+def als_update(A, S, n, M, step=1.0):
     """One mode update of Algorithm 1 given its right-hand side M.
 
     Gamma <- Hadamard of the other Grams; A_new <- M Gamma^-1;
     G <- (A - A_new) Gamma; A <- A_new; S <- A^T A.
+
+    ``step`` is the update step size lambda of the variant in Section 5.1:
+    A_new = (1 - lambda) A + lambda M Gamma^-1 (lambda = 1 is Algorithm 1).  Reading:
+    G stays the gradient at the factor before the update, (A - M Gamma^-1) Gamma,
+    whatever lambda is.
     Returns (A_new, Gamma, ||G||_F, chol_status); A and S are updated in place.
     """
     gamma = hadamard_except(S, n)
-    a_new, status = linalg.solve_normal(gamma, M)
-    G = (A[n] - a_new) @ gamma
+    a_sol, status = linalg.solve_normal(gamma, M)
+    G = (A[n] - a_sol) @ gamma
+    a_new = a_sol if step == 1.0 else (1.0 - step) * A[n] + step * a_sol
     A[n] = a_new
     S[n] = gram(a_new)
     return a_new, gamma, float(np.linalg.norm(G)), status
 
 
-def als_sweep(X, A, S, normX2=None, mttkrp_fn=mttkrp):
+def als_sweep(X, A, S, normX2=None, mttkrp_fn=mttkrp, step=1.0):
     """One Gauss-Seidel sweep over n = 1..N (Algorithm 1, loop body).
 
     A and S are updated in place.  rel_change[n] = ||A_new - A_old||_F /
     ||A_new||_F, the per-sweep change that Algorithm 3 tests after a regular
-    ALS sweep.
+    ALS sweep.  ``step``: update step size (see als_update).
     """
     N = X.ndim
     if normX2 is None:
@@ -179,7 +185,7 @@ def als_sweep(X, A, S, normX2=None, mttkrp_fn=mttkrp):
     for n in range(N):
         M = mttkrp_fn(X, A, n)
         old = A[n].copy()
-        a_new, gamma, g, st = als_update(A, S, n, M)
+        a_new, gamma, g, st = als_update(A, S, n, M, step)
         gn.append(g)
         cs.append(st)
         rc.append(float(np.linalg.norm(a_new - old) / np.linalg.norm(a_new)))
@@ -188,12 +194,12 @@ def als_sweep(X, A, S, normX2=None, mttkrp_fn=mttkrp):
     return SweepRecord("als", gn, rc, cs, f, rhs)
 
 
-def cp_als(X, A0, sweeps):
+def cp_als(X, A0, sweeps, step=1.0):
     """Plain CP-ALS for a fixed number of sweeps; returns (A, records)."""
     A = [a.copy() for a in A0]
     S = [gram(a) for a in A]
     normX2 = float(np.sum(X * X))
-    recs = [als_sweep(X, A, S, normX2) for _ in range(sweeps)]
+    recs = [als_sweep(X, A, S, normX2, step=step) for _ in range(sweeps)]
     return A, recs
 
 

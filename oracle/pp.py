@@ -95,16 +95,16 @@ def pp_rhs(state, A, S, n, second_order=True):
     return M
 
 
-def pp_sweep(state, A, S, normX2, second_order=True, kind="pp_approx"):
+def pp_sweep(state, A, S, normX2, second_order=True, kind="pp_approx", step=1.0):
     """One approximated sweep (Algorithm 3, inner loop body).  A, S and
     state.dA are updated in place; rel_change[n] = ||A^(n) - A_p^(n)||_F /
-    ||A^(n)||_F."""
+    ||A^(n)||_F.  ``step``: the update step size of Section 5.1 (cp.als_update)."""
     N = len(A)
     gn, rc, cs, rhs = [], [], [], []
     gamma = M = None
     for n in range(N):
         M = pp_rhs(state, A, S, n, second_order)
-        a_new, gamma, g, st = cp.als_update(A, S, n, M)
+        a_new, gamma, g, st = cp.als_update(A, S, n, M, step)
         state.dA[n] = a_new - state.Ap[n]
         gn.append(g)
         cs.append(st)
@@ -114,7 +114,7 @@ def pp_sweep(state, A, S, normX2, second_order=True, kind="pp_approx"):
     return cp.SweepRecord(kind, gn, rc, cs, f, rhs)
 
 
-def pp_als(X, A0, eps, sweeps, second_order=True, replay=None, delta=None):
+def pp_als(X, A0, eps, sweeps, second_order=True, replay=None, delta=None, step=1.0):
     """PP-CP-ALS control (Algorithm 3) for a budget of ``sweeps`` sweeps.
 
     Initially dA = A, so the first sweep is a regular ALS sweep.  Whenever every
@@ -125,7 +125,8 @@ def pp_als(X, A0, eps, sweeps, second_order=True, replay=None, delta=None):
     ``replay``: a list of sweep kinds ("als", "pp_init", "pp_approx") to follow
     instead of deciding (used to compare trajectories without threshold
     ties).  ``delta``: optional gradient stopping tolerance
-    (sum_i ||G^(i)||_F <= delta ||X||_F stops the run).
+    (sum_i ||G^(i)||_F <= delta ||X||_F stops the run).  ``step``: the update
+    step size lambda of Section 5.1, used by ALS and PP sweeps alike.
 
     Returns (A, records).
     """
@@ -139,14 +140,14 @@ def pp_als(X, A0, eps, sweeps, second_order=True, replay=None, delta=None):
         state = None
         for kind in replay[:sweeps]:
             if kind == "als":
-                recs.append(cp.als_sweep(X, A, S, normX2))
+                recs.append(cp.als_sweep(X, A, S, normX2, step=step))
             elif kind == "pp_init":
                 state = build_operators(X, A)
-                recs.append(pp_sweep(state, A, S, normX2, second_order, "pp_init"))
+                recs.append(pp_sweep(state, A, S, normX2, second_order, "pp_init", step))
             elif kind == "pp_approx":
                 if state is None:
                     raise ValueError("pp_approx before any operator build")
-                recs.append(pp_sweep(state, A, S, normX2, second_order, "pp_approx"))
+                recs.append(pp_sweep(state, A, S, normX2, second_order, "pp_approx", step))
             else:
                 raise ValueError(kind)
         return A, recs
@@ -163,13 +164,13 @@ def pp_als(X, A0, eps, sweeps, second_order=True, replay=None, delta=None):
             state = build_operators(X, A)
             kind = "pp_init"
             while len(recs) < sweeps and small(rel) and not converged():
-                rec = pp_sweep(state, A, S, normX2, second_order, kind)
+                rec = pp_sweep(state, A, S, normX2, second_order, kind, step)
                 recs.append(rec)
                 rel = rec.rel_change
                 kind = "pp_approx"
             if len(recs) >= sweeps or converged():
                 break
-        rec = cp.als_sweep(X, A, S, normX2)
+        rec = cp.als_sweep(X, A, S, normX2, step=step)
         recs.append(rec)
         rel = rec.rel_change
     return A, recs
