@@ -62,7 +62,8 @@ typedef enum { PPALS_SWEEP_ALS = 0, PPALS_SWEEP_PP_INIT = 1, PPALS_SWEEP_PP_APPR
 #define PPALS_MAX_RANK 128
 
 /* Problem description.  Supported: 3 <= order <= 8, 1 <= rank <= 128,
- * dims >= 1.  Precision tiers (tensor_dtype, level1_dtype):
+ * dims >= 1, 0 < step_size <= 1 (0 is read as 1).  Precision tiers (tensor_dtype,
+ * level1_dtype):
  *   (FP64, FP64)  every contraction in FP64;
  *   (FP32, FP32)  contractions in FP32 with FP32 MFMA accumulation;
  *   (FP32, BF16)  first-level contractions take bfloat16 inputs (X_bf16 and
@@ -78,6 +79,11 @@ typedef struct {
   int32_t level1_dtype;
   int32_t use_second_order;
   int32_t reserved;
+  /* Update step size lambda of the step-size variant of ALS (Section 5.1): every factor
+   * update of the ALS and PP sweeps is A_new = (1 - lambda) A + lambda M Gamma^-1; the
+   * record's gradient stays the one at A before the update, (A - M Gamma^-1) Gamma.
+   * 1 (or 0) is Algorithm 1.  gram_solve always takes the full step. */
+  double step_size;
 } ppals_desc;
 
 /* Per-sweep record, written on the device at the end of every sweep call.

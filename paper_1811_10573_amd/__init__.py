@@ -65,7 +65,8 @@ def _factor_array(plan, A):
 class Plan:
     """Host plan: dimension-tree schedules and the workspace layout."""
 
-    def __init__(self, dims, rank, tensor_dtype="f64", level1_dtype=None, second_order=True):
+    def __init__(self, dims, rank, tensor_dtype="f64", level1_dtype=None, second_order=True,
+                 step_size=1.0):
         dims = [int(d) for d in dims]
         if level1_dtype is None:
             level1_dtype = tensor_dtype
@@ -77,6 +78,7 @@ class Plan:
         d.tensor_dtype = _DTYPES[tensor_dtype]
         d.level1_dtype = _DTYPES[level1_dtype]
         d.use_second_order = 1 if second_order else 0
+        d.step_size = float(step_size)
         h = ctypes.c_void_p()
         _lib.check(lib().ppals_plan_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
@@ -86,6 +88,7 @@ class Plan:
         self.tensor_dtype = tensor_dtype
         self.level1_dtype = level1_dtype
         self.second_order = bool(second_order)
+        self.step_size = float(step_size)
         self.torch_dtype = torch.float64 if tensor_dtype == "f64" else torch.float32
 
     @property

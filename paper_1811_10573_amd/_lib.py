@@ -29,6 +29,7 @@ class Desc(ctypes.Structure):
         ("level1_dtype", ctypes.c_int32),
         ("use_second_order", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
+        ("step_size", ctypes.c_double),
     ]
 
 

@@ -206,6 +206,7 @@ struct FusedSolveArgs {
   const int* status;
   int write_fit;
   const int* gate;         // if set and *gate == 0 the launch does nothing
+  double step;             // update step size lambda: A_new = A + lambda (M Gamma^-1 - A)
 };
 hipError_t launch_head(const HeadArgs& h, hipStream_t s);
 hipError_t launch_solve_fused(const FusedSolveArgs& a, hipStream_t s);
@@ -252,6 +253,7 @@ struct SolveArgs {
   double* dA;            // rows x R output of A_new - ref (may be NULL)
   double* rowpart;       // rows x 4: ||g||^2, ||dA||^2, ||a||^2, <m, a>
   const int* status;     // Cholesky status (2 -> leave A unchanged)
+  double step;           // update step size lambda: A_new = A + lambda (M Gamma^-1 - A)
 };
 hipError_t launch_solve_rows(const SolveArgs& a, hipStream_t s);
 // S_out = A^T A; if dA: U_out = A^T dA (R x R each)

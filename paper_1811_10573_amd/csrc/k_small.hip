@@ -222,6 +222,12 @@ __global__ __launch_bounds__(256) void k_solve_rows(SolveArgs a) {
       if (v0) g0 = fma(dj, a.gamma[j * R + k0], g0);
       if (v1) g1 = fma(dj, a.gamma[j * R + k1], g1);
     }
+    // step-size variant (Section 5.1): A_new = A_old + step (A_sol - A_old), after the
+    // gradient at A_old
+    if (a.step != 1.0) {
+      x0 = fma(a.step, x0 - aold0, aold0);
+      x1 = fma(a.step, x1 - aold1, aold1);
+    }
     const double ref0 = a.Aref ? (v0 ? a.Aref[rb + k0] : 0.0) : aold0;
     const double ref1 = a.Aref ? (v1 ? a.Aref[rb + k1] : 0.0) : aold1;
     const double da0 = x0 - ref0, da1 = x1 - ref1;

@@ -163,9 +163,13 @@ __global__ __launch_bounds__(SOLVE_WAVES * 64) void k_solve_fused(FusedSolveArgs
   } else {
     x = ao;
   }
-  // g = (a_old - a_new) Gamma; h = a_new Gamma (fit)
+  // Step-size variant (Section 5.1): A_new = A_old + step (A_sol - A_old).  The gradient
+  // stays the one at A_old, (A_old - A_sol) Gamma.
+  const double xs = x;
+  if (a.step != 1.0) x = fma(a.step, xs - ao, ao);
+  // g = (a_old - a_sol) Gamma; h = a_new Gamma (fit)
   double g = 0.0, hq = 0.0;
-  bv[64 + l] = lv ? ao - x : 0.0;
+  bv[64 + l] = lv ? ao - xs : 0.0;
   bv[128 + l] = lv ? x : 0.0;
   __builtin_amdgcn_wave_barrier();
   for (int j0 = 0; j0 < R; j0 += UB) {

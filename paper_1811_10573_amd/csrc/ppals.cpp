@@ -161,6 +161,8 @@ struct ppals_plan {
   // dA^(n) = 0 for every mode since the last build (set by the build, cleared by the first
   // sweep after it and by every other writer of dA)
   bool dA_zero = false;
+  // update step size lambda of the step-size variant (1: Algorithm 1)
+  double step = 1.0;
 
   // learned controller for leaving the PP phase (ppals_set_controller)
   bool ctl_set = false;
@@ -881,6 +883,7 @@ ppals_status solve_mode(const Ctx& c, double* const* A, double* S, int n, bool p
   a.dA = pp ? c.dA(n) : nullptr;
   a.rowpart = c.at<double>(p->off_rowpart);
   a.status = c.at<int>(p->off_status) + n;
+  a.step = p->step;
   HIPCHK(launch_solve_rows(a, c.s));
   HIPCHK(launch_gram(A[n], pp ? c.dA(n) : nullptr, p->dims[n], p->R, S + (size_t)n * p->R * p->R,
                      pp ? c.U() + (size_t)n * p->R * p->R : nullptr, c.s));
@@ -1014,6 +1017,7 @@ ppals_status solve_fused(const Ctx& c, double* const* A, int n, const double* ba
   a.status = c.at<int>(p->off_status) + n;
   a.write_fit = write_fit;
   a.gate = p->cur_gate;
+  a.step = p->step;
   Prof pr(p, 4, c.s);
   HIPCHK(launch_solve_fused(a, c.s));
   pr.end();
@@ -1526,6 +1530,7 @@ ppals_status gram_solve_impl(int32_t R, int64_t rows, const double* Gamma, const
   a.A = A_inout;
   a.rowpart = rowpart;
   a.status = status;
+  a.step = 1.0;
   HIPCHK(launch_solve_rows(a, s));
   HIPCHK(launch_finish_gram_solve(rowpart, rows, grad_norm_out, chol_status_out, status, s));
   return PPALS_OK;
@@ -1591,7 +1596,10 @@ ppals_status ppals_plan_create(const ppals_desc* d, ppals_plan** out) {
                        (d->tensor_dtype == PPALS_FP32 &&
                         (d->level1_dtype == PPALS_FP32 || d->level1_dtype == PPALS_BF16));
   if (!tier_ok) return fail(PPALS_E_UNSUPPORTED, "unsupported (tensor_dtype, level1_dtype) pair");
+  const double step = d->step_size == 0.0 ? 1.0 : d->step_size;
+  if (!(step > 0.0 && step <= 1.0)) return fail(PPALS_E_ARG, "step_size must be in (0, 1] (or 0 for 1)");
   ppals_plan* p = new ppals_plan();
+  p->step = step;
   p->N = d->order;
   p->R = d->rank;
   for (int i = 0; i < p->N; ++i) p->dims[i] = d->dims[i];

@@ -80,6 +80,20 @@ def test_plan_argument_errors(lib, dims, rank, tdt, l1, want):
     assert len(lib.ppals_last_error()) > 0
 
 
+@pytest.mark.parametrize("step,want", [(0.0, 0), (0.7, 0), (1.0, 0), (1.5, -1), (-0.2, -1),
+                                       (float("nan"), -1)])
+def test_plan_step_size_range(lib, step, want):
+    """The update step size of the step-size variant must lie in (0, 1]; 0 reads as 1."""
+    d = _desc((5, 6, 7), 3, 0, 0)
+    d.step_size = step
+    h = ctypes.c_void_p()
+    st = lib.ppals_plan_create(ctypes.byref(d), ctypes.byref(h))
+    assert st == want
+    if h.value:
+        lib.ppals_plan_destroy(h)
+    assert bool(h.value) == (want == 0)
+
+
 def test_null_arguments_fail_before_any_device_work(lib):
     st, h = _create(lib, (6, 7, 8), 4)
     assert st == 0
