@@ -96,6 +96,11 @@ typedef struct {
  *   chol_status[n] 0: clean Cholesky; 1: factorised Gamma + delta I with
  *                  delta = R 2^-52 max(diag Gamma); 2: failed after the shift
  *                  (A^(n) left unchanged).
+ *   chol_pivot[n]  0-based index of the first pivot of the unshifted factorisation of
+ *                  Gamma^(n) that was not positive and finite (Gamma^(n) is not SPD at
+ *                  that leading block), -1 if the factorisation went through.
+ *   nonfinite[n]   1 if the new A^(n), its gradient or the fit term of mode n holds a
+ *                  value that is not finite (NaN or infinity), else 0.
  * The ctrl_* fields are written by ppals_run when a learned controller is
  * attached (ppals_set_controller); otherwise ppals_run sets them to
  * ctrl_pred = NaN, ctrl_true_err = -1, ctrl_leave = -1, ctrl_fallback = 0:
@@ -116,6 +121,8 @@ typedef struct {
   double ctrl_true_err;
   int32_t ctrl_leave;
   int32_t ctrl_fallback;
+  int32_t chol_pivot[PPALS_MAX_ORDER];
+  int32_t nonfinite[PPALS_MAX_ORDER];
 } ppals_sweep_record;
 
 typedef struct ppals_plan ppals_plan;
@@ -173,7 +180,14 @@ ppals_status pp_sweep(ppals_plan* plan, double* const* A, double* S, double norm
  * and A_inout := A_new.  Gamma: R x R doubles; M: rows x R in m_dtype (FP64
  * or FP32); A_inout: rows x R doubles.  grad_norm_out and chol_status_out are
  * device pointers (one double, one int32).  ws must hold
- * ppals_gram_solve_workspace_bytes(R, rows) bytes. */
+ * ppals_gram_solve_workspace_bytes(R, rows) bytes.
+ * *chol_status_out (written on the device):
+ *   bits 0-1   0 clean, 1 factorised Gamma + delta I (delta = R 2^-52 max diag Gamma),
+ *              2 failed after the shift (A_inout left unchanged);
+ *   bit 4      set when the new factor or the gradient holds a value that is not finite;
+ *   bits 8-30  one plus the 0-based index of the first pivot of the unshifted
+ *              factorisation that was not positive and finite (0 if none), i.e. the
+ *              order of the first leading block of Gamma that is not positive definite. */
 size_t ppals_gram_solve_workspace_bytes(int32_t R, int64_t rows);
 ppals_status gram_solve(int32_t R, int64_t rows, const double* Gamma, const void* M,
                         int32_t m_dtype, double* A_inout, double* grad_norm_out,

@@ -13,6 +13,7 @@ from __future__ import annotations
 
 import numpy as np
 import scipy.linalg as sla
+from scipy.linalg import lapack
 
 
 def jitter(gamma):
@@ -32,6 +33,25 @@ def cholesky(gamma):
     except np.linalg.LinAlgError:
         g = gamma + jitter(gamma) * np.eye(gamma.shape[0])
         return np.linalg.cholesky(g), 1
+
+
+def first_failed_pivot(gamma):
+    """0-based index of the first pivot at which the Cholesky factorisation of gamma (no
+    shift) meets a non-positive or non-finite value, or -1 if it succeeds.  LAPACK's
+    dpotrf reports the order of the first leading minor that is not positive definite;
+    the pivot index is that order minus one."""
+    g = np.array(gamma, dtype=np.float64, order="F")
+    bad = np.argwhere(~np.isfinite(g))
+    if bad.size:
+        # entry (r, c) of the lower triangle enters pivot max(r, c) (and no earlier one);
+        # before it, the leading block decides
+        k = int(np.min(np.max(bad, axis=1)))
+        p = first_failed_pivot(g[:k, :k]) if k > 0 else -1
+        return p if p >= 0 else k
+    _, info = lapack.dpotrf(g, lower=1)
+    if info < 0:
+        raise ValueError(f"dpotrf argument error {info}")
+    return int(info) - 1 if info > 0 else -1
 
 
 def solve_normal(gamma, M):

@@ -174,6 +174,8 @@ def record_dict(r, order=None):
         "ctrl_true_err": r.ctrl_true_err,
         "ctrl_leave": r.ctrl_leave,
         "ctrl_fallback": r.ctrl_fallback,
+        "chol_pivot": r.chol_pivot[:n],
+        "nonfinite": r.nonfinite[:n],
     }
 
 

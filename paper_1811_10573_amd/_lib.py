@@ -45,6 +45,8 @@ class SweepRecord(ctypes.Structure):
         ("ctrl_true_err", ctypes.c_double),
         ("ctrl_leave", ctypes.c_int32),
         ("ctrl_fallback", ctypes.c_int32),
+        ("chol_pivot", ctypes.c_int32 * MAX_ORDER),
+        ("nonfinite", ctypes.c_int32 * MAX_ORDER),
     ]
 
 

@@ -214,27 +214,51 @@ def run_controlled(session, params, hidden, log10_tau, eps, rho_cap, check_perio
         set_controller(s.plan, None)
 
 
-def compare(fixed, ctrl, target):
+def constant_params(d, hidden, value=-1e30):
+    """Parameters of a network whose output is `value` for every input: the controller
+    then never leaves on its prediction, only on rho_cap or after a failed periodic check
+    (the ablation that removes the network and keeps the rest of the controller)."""
+    p = np.zeros(mlp_n_params(d, hidden), dtype=np.float32)
+    p[-1] = value
+    return p
+
+
+def compare(fixed, ctrl, target, capped=None):
     recs0, ms0 = fixed
     recs1, ms1 = ctrl
     kinds0 = [r["kind"] for r in recs0]
     kinds1 = [r["kind"] for r in recs1]
-    return {
+    out = {
         "t_fixed_ms": time_to_fit(recs0, ms0, target), "t_ctrl_ms": time_to_fit(recs1, ms1, target),
         "builds_fixed": kinds0.count("pp_init"), "builds_ctrl": kinds1.count("pp_init"),
         "pp_fixed": sum(k != "als" for k in kinds0), "pp_ctrl": sum(k != "als" for k in kinds1),
         "fallback": int(any(r["ctrl_fallback"] for r in recs1)),
         "fit_fixed": recs0[-1]["fit_est"], "fit_ctrl": recs1[-1]["fit_est"],
     }
+    if capped is not None:
+        recs2, ms2 = capped
+        kinds2 = [r["kind"] for r in recs2]
+        out.update({"t_capped_ms": time_to_fit(recs2, ms2, target),
+                    "builds_capped": kinds2.count("pp_init"),
+                    "pp_capped": sum(k != "als" for k in kinds2),
+                    "fallback_capped": int(any(r["ctrl_fallback"] for r in recs2)),
+                    "fit_capped": recs2[-1]["fit_est"]})
+    return out
 
 
 def evaluate(session, params, hidden, log10_tau, eps, rho_cap, check_period, fallback_factor,
-             max_sweeps, target):
-    """Time to the target fit with the threshold rule and with the controller."""
+             max_sweeps, target, ablation=True):
+    """Time to the target fit with the threshold rule, with the controller and (ablation)
+    with the controller's rho_cap and periodic checks but a constant network."""
     fixed = run_fixed(session, eps, max_sweeps)
     ctrl = run_controlled(session, params, hidden, log10_tau, eps, rho_cap, check_period,
                           fallback_factor, max_sweeps)
-    return compare(fixed, ctrl, target)
+    capped = None
+    if ablation:
+        d = len(session.shape) + 2
+        capped = run_controlled(session, constant_params(d, hidden), hidden, log10_tau, eps,
+                                rho_cap, check_period, fallback_factor, max_sweeps)
+    return compare(fixed, ctrl, target, capped)
 
 
 def search_log10_tau(sessions, params, hidden, candidates, eps, rho_cap, check_period,
@@ -259,20 +283,36 @@ def search_log10_tau(sessions, params, hidden, candidates, eps, rho_cap, check_p
     return best[0], table
 
 
-def summarize(evals):
-    ratios = [e["t_fixed_ms"] / e["t_ctrl_ms"] for e in evals
-              if e["t_fixed_ms"] is not None and e["t_ctrl_ms"] is not None]
+def _ratio_stats(evals, num, den):
+    """Speed-up t_num / t_den over the runs where both reached the target."""
+    ratios = [e[num] / e[den] for e in evals if e.get(num) is not None and e.get(den) is not None]
     out = {
-        "runs": len(evals),
         "both_reached": len(ratios),
-        "fixed_only": sum(e["t_fixed_ms"] is not None and e["t_ctrl_ms"] is None for e in evals),
-        "ctrl_only": sum(e["t_fixed_ms"] is None and e["t_ctrl_ms"] is not None for e in evals),
-        "fallback_fraction": float(np.mean([e["fallback"] for e in evals])) if evals else None,
+        "first_only": sum(e.get(num) is not None and e.get(den) is None for e in evals),
+        "second_only": sum(e.get(num) is None and e.get(den) is not None for e in evals),
     }
     if ratios:
         q1, med, q3 = np.quantile(ratios, [0.25, 0.5, 0.75])
         out.update({"speedup_median": float(med), "speedup_q1": float(q1), "speedup_q3": float(q3),
                     "speedup_geomean": float(np.exp(np.mean(np.log(ratios))))})
+    return out
+
+
+def summarize(evals):
+    """Controller against the threshold rule (as before: both_reached, fixed_only,
+    ctrl_only, speed-ups); with the ablation arm also the capped controller against the
+    threshold rule and the network's own share (capped time over controller time)."""
+    r = _ratio_stats(evals, "t_fixed_ms", "t_ctrl_ms")
+    out = {
+        "runs": len(evals),
+        "both_reached": r["both_reached"], "fixed_only": r["first_only"], "ctrl_only": r["second_only"],
+        "fallback_fraction": float(np.mean([e["fallback"] for e in evals])) if evals else None,
+    }
+    out.update({k: v for k, v in r.items() if k.startswith("speedup")})
+    if evals and "t_capped_ms" in evals[0]:
+        out["capped_vs_fixed"] = _ratio_stats(evals, "t_fixed_ms", "t_capped_ms")
+        out["network_vs_capped"] = _ratio_stats(evals, "t_capped_ms", "t_ctrl_ms")
+        out["capped_fallback_fraction"] = float(np.mean([e["fallback_capped"] for e in evals]))
     return out
 
 
@@ -352,11 +392,14 @@ def main():
     args = ap.parse_args()
     results = {}
     saved = {}
-    for k, order in enumerate(args.orders):
-        base = 1000 * k
-        tr = list(range(base, base + args.train_runs))
-        va = list(range(base + args.train_runs, base + args.train_runs + args.val_runs))
-        ev = list(range(2000 + 100 * k, 2000 + 100 * k + args.eval_runs))
+    if args.train_runs + args.val_runs > 2000:
+        raise SystemExit("training and validation seeds must stay below the held-out seeds (2000+)")
+    for order in args.orders:
+        # seeds 0..1999 train/validate, 2000.. are held out; a problem depends on (seed,
+        # order), so the orders share the seed ranges without sharing problems
+        tr = list(range(0, args.train_runs))
+        va = list(range(args.train_runs, args.train_runs + args.val_runs))
+        ev = list(range(2000, 2000 + args.eval_runs))
         shape = None if args.size is None else (args.size,) * order
         res, params = experiment(order, tr, va, ev, shape=shape, max_sweeps=args.max_sweeps,
                                  steps=args.steps)

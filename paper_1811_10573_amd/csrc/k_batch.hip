@@ -462,7 +462,7 @@ __global__ __launch_bounds__(BSOLVE_WAVES * 64) void k_b_solve(const BProb* pr, 
   if (w == 0) {
     int stv = 0;
     for (int attempt = 0;; ++attempt) {
-      if (chol_wave64(Lm, cb, R)) break;
+      if (chol_wave64(Lm, cb, R) < 0) break;
       if (attempt == 1) {
         stv = 2;
         break;

@@ -36,7 +36,8 @@ __device__ double block_sum(double v, double* red) {
 }
 
 // Cholesky (lower) of the R x R matrix a (row-major, in LDS), right-looking.
-// Returns 1 on success.  All threads of the block participate.
+// Returns -1 on success, else the 0-based index of the first pivot that is not positive
+// and finite.  All threads of the block participate.
 __device__ int chol_lds(double* a, int R, int* flag) {
   const int tid = threadIdx.x;
   if (tid == 0) *flag = 0;
@@ -48,7 +49,7 @@ __device__ int chol_lds(double* a, int R, int* flag) {
       else a[j * R + j] = sqrt(d);
     }
     __syncthreads();
-    if (*flag) return 0;
+    if (*flag) return j;
     const double inv = 1.0 / a[j * R + j];
     for (int i = j + 1 + tid; i < R; i += blockDim.x) a[i * R + j] *= inv;
     __syncthreads();
@@ -62,8 +63,13 @@ __device__ int chol_lds(double* a, int R, int* flag) {
     }
     __syncthreads();
   }
-  return 1;
+  return -1;
 }
+
+// Cholesky status word: bits 0-1 the outcome (0 clean, 1 factorised after the diagonal
+// shift, 2 failed after it), bits 8-30 one plus the first failed pivot of the unshifted
+// factorisation (0: none).
+__device__ __forceinline__ int chol_status_lds(int code, int pivot) { return code | ((pivot + 1) << 8); }
 
 // One workgroup: finish mode `prev` (record entries, fit) and prepare mode `n`
 // (Gamma, W, Cholesky with the diagonal-shift retry).
@@ -97,7 +103,10 @@ __global__ __launch_bounds__(256) void k_mode_begin(ModeArgs a) {
     if (tid == 0) {
       rec->grad_norm[a.prev] = sqrt(g2);
       rec->rel_change[a.prev] = a2 > 0.0 ? sqrt(d2) / sqrt(a2) : (d2 > 0.0 ? INFINITY : 0.0);
-      rec->chol_status[a.prev] = a.status[a.prev];
+      const int stw = a.status[a.prev];
+      rec->chol_status[a.prev] = stw & 3;
+      rec->chol_pivot[a.prev] = (stw >> 8) - 1;
+      rec->nonfinite[a.prev] = (isfinite(g2) && isfinite(a2) && isfinite(ma)) ? 0 : 1;
       if (a.write_fit) {
         const double r2 = a.normX2 - 2.0 * ma + fitnrm;
         rec->fit_est = 1.0 - sqrt(r2 > 0.0 ? r2 : 0.0) / sqrt(a.normX2);
@@ -132,7 +141,8 @@ __global__ __launch_bounds__(256) void k_mode_begin(ModeArgs a) {
   }
   __syncthreads();
   int st = 0;
-  if (!chol_lds(sm, R, &flag)) {
+  const int piv0 = chol_lds(sm, R, &flag);
+  if (piv0 >= 0) {
     // retry with Gamma + delta I, delta = R 2^-52 max(diag Gamma)
     double mx = 0.0;
     for (int e = tid; e < R; e += blockDim.x) mx = fmax(mx, a.gamma[e * R + e]);
@@ -153,13 +163,13 @@ __global__ __launch_bounds__(256) void k_mode_begin(ModeArgs a) {
       sm[e] = a.gamma[e] + (i == k ? delta : 0.0);
     }
     __syncthreads();
-    st = chol_lds(sm, R, &flag) ? 1 : 2;
+    st = chol_lds(sm, R, &flag) < 0 ? 1 : 2;
   }
   for (int e = tid; e < RR; e += blockDim.x) {
     const int i = e / R, k = e - (e / R) * R;
     a.L[e] = (k <= i) ? sm[e] : 0.0;
   }
-  if (tid == 0) a.status[n] = st;
+  if (tid == 0) a.status[n] = chol_status_lds(st, piv0);
 }
 
 // Row-parallel solve of A_new Gamma = M with Gamma = L L^T; one wave per row,
@@ -176,7 +186,7 @@ __global__ __launch_bounds__(256) void k_solve_rows(SolveArgs a) {
   __syncthreads();
   for (int e = threadIdx.x; e < R; e += blockDim.x) invd[e] = 1.0 / Ls[e * LS + e];
   __syncthreads();
-  const int st = *a.status;
+  const int st = *a.status & 3;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int64_t wave_global = (int64_t)blockIdx.x * (blockDim.x >> 6) + w;
   const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
@@ -398,12 +408,18 @@ __global__ __launch_bounds__(256) void k_residual2_generic(ResArgs a, int64_t to
 __global__ void k_finish_gram_solve(const double* __restrict__ rowpart, int64_t rows,
                                     double* grad_out, int32_t* status_out, const int* status) {
   __shared__ double red[8];
-  double s = 0.0;
-  for (int64_t y = threadIdx.x; y < rows; y += blockDim.x) s += rowpart[y * 4];
+  double s = 0.0, a2 = 0.0;
+  for (int64_t y = threadIdx.x; y < rows; y += blockDim.x) {
+    s += rowpart[y * 4];
+    a2 += rowpart[y * 4 + 2];
+  }
   s = block_sum(s, red);
+  a2 = block_sum(a2, red);
   if (threadIdx.x == 0) {
     *grad_out = sqrt(s);
-    *status_out = *status;
+    // the Cholesky status word, plus bit 4 when the new factor or the gradient holds a
+    // value that is not finite
+    *status_out = *status | ((isfinite(s) && isfinite(a2)) ? 0 : 16);
   }
 }
 
@@ -416,7 +432,8 @@ __global__ __launch_bounds__(256) void k_chol_standalone(const double* gamma, in
   for (int e = threadIdx.x; e < RR; e += blockDim.x) sm[e] = gamma[e];
   __syncthreads();
   int st = 0;
-  if (!chol_lds(sm, R, &flag)) {
+  const int piv0 = chol_lds(sm, R, &flag);
+  if (piv0 >= 0) {
     if (threadIdx.x == 0) {
       double m2 = 0.0;
       for (int i = 0; i < R; ++i) m2 = fmax(m2, gamma[i * R + i]);
@@ -429,13 +446,13 @@ __global__ __launch_bounds__(256) void k_chol_standalone(const double* gamma, in
       sm[e] = gamma[e] + (i == k ? delta : 0.0);
     }
     __syncthreads();
-    st = chol_lds(sm, R, &flag) ? 1 : 2;
+    st = chol_lds(sm, R, &flag) < 0 ? 1 : 2;
   }
   for (int e = threadIdx.x; e < RR; e += blockDim.x) {
     const int i = e / R, k = e - (e / R) * R;
     L[e] = (k <= i) ? sm[e] : 0.0;
   }
-  if (threadIdx.x == 0) *status = st;
+  if (threadIdx.x == 0) *status = chol_status_lds(st, piv0);
 }
 
 // ---------------------------------------------------------------------------

@@ -140,7 +140,7 @@ __global__ __launch_bounds__(SOLVE_WAVES * 64) void k_solve_fused(FusedSolveArgs
   }
   const double mo = m;
   double x;
-  if (st != 2) {
+  if ((st & 3) != 2) {
     const double dl = lv ? invd[lc] : 0.0;
     for (int j0 = 0; j0 < R; j0 += UB) {            // (L D^-1) y = M~
       double lf[UB];

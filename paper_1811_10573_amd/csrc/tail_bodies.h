@@ -116,9 +116,11 @@ __device__ __forceinline__ void head_body(const HeadArgs& h, double* Lm, double*
   if ((tid & 63) == 0) red[tid >> 6] = dmax;
   __syncthreads();
   if (tid < 64) {  // the factorisation is wave 0's alone; the other waves wait below
-    int st = 0;
+    int st = 0, piv0 = -1;
     for (int attempt = 0;; ++attempt) {
-      if (chol_wave64(Lm, cb, R)) break;
+      const int piv = chol_wave64(Lm, cb, R);
+      if (piv < 0) break;
+      if (attempt == 0) piv0 = piv;
       if (attempt == 1) {
         st = 2;
         break;
@@ -138,7 +140,7 @@ __device__ __forceinline__ void head_body(const HeadArgs& h, double* Lm, double*
       st = 1;
     }
     if (tid < R) cb[tid] = 1.0 / Lm[tid * CH64_LS + tid];
-    if (tid == 0) h.status[n] = st;
+    if (tid == 0) h.status[n] = chol_status_word(st, piv0);
   }
   __syncthreads();
   // the solve operands: LF[k][i] = L[i][k] / L[k][k] (i > k), LB[i][k] = L[i][k] / L[i][i]
@@ -372,7 +374,10 @@ __device__ __forceinline__ void gram_body(const GramArgs& a, int tile, int split
       const double g2 = sums[0], d2 = sums[1], a2 = sums[2];
       rec->grad_norm[a.mode] = sqrt(g2);
       rec->rel_change[a.mode] = a2 > 0.0 ? sqrt(d2) / sqrt(a2) : (d2 > 0.0 ? INFINITY : 0.0);
-      rec->chol_status[a.mode] = *a.status;
+      const int stw = *a.status;
+      rec->chol_status[a.mode] = stw & 3;
+      rec->chol_pivot[a.mode] = (stw >> 8) - 1;
+      rec->nonfinite[a.mode] = (isfinite(g2) && isfinite(a2) && isfinite(sums[3])) ? 0 : 1;
       if (a.write_fit) {
         const double r2 = a.normX2 - 2.0 * sums[3] + sums[4];
         rec->fit_est = 1.0 - sqrt(r2 > 0.0 ? r2 : 0.0) / sqrt(a.normX2);

@@ -44,7 +44,9 @@ __device__ __forceinline__ double rsqrt_refined(double s) {
   return y;
 }
 
-__device__ __forceinline__ bool chol_wave64(double* Lm, double* cb, int R) {
+// Cholesky of the R x R leading block of Lm (one wave).  Returns -1 on success, else the
+// 0-based index of the first pivot that is not positive and finite.
+__device__ __forceinline__ int chol_wave64(double* Lm, double* cb, int R) {
   constexpr int LS = CH64_LS;
   const int l = threadIdx.x & 63;
   const int i16 = l & 15, k4 = l >> 4;
@@ -81,12 +83,12 @@ __device__ __forceinline__ bool chol_wave64(double* Lm, double* cb, int R) {
     // new column reach the rows that need them through lane broadcasts, the others
     // through LDS.  The pivot test is off the chain; a column past R (only in the last
     // panel) meets zero padding and leaves rows below R unchanged.
-    bool bad = false;
+    int bad = -1;
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
       const int col = j0 + c;
       const double s = bcast(t[c], col);
-      bad = bad || (col < R && !(s > 0.0 && s < INFINITY));
+      bad = (bad < 0 && col < R && !(s > 0.0 && s < INFINITY)) ? col : bad;
       const double r = rsqrt_refined(s);
       const double lc = (l == col) ? s * r : t[c] * r;
       t[c] = lc;
@@ -99,13 +101,20 @@ __device__ __forceinline__ bool chol_wave64(double* Lm, double* cb, int R) {
         for (int c2 = c + 3; c2 < 16; ++c2) t[c2] = fma(-lc, cbc[j0 + c2], t[c2]);
       }
     }
-    if (bad) return false;
+    if (bad >= 0) return bad;
 #pragma unroll
     for (int c = 0; c < 16; ++c)
       if (j0 + c <= l) Lm[l * LS + j0 + c] = t[c];
   }
   __builtin_amdgcn_wave_barrier();
-  return true;
+  return -1;
+}
+
+// Cholesky status word: bits 0-1 the outcome (0 clean, 1 factorised after the diagonal
+// shift, 2 failed after it), bits 8-30 one plus the first failed pivot of the unshifted
+// factorisation (0: none).
+__device__ __forceinline__ int chol_status_word(int code, int pivot) {
+  return code | ((pivot + 1) << 8);
 }
 
 }  // namespace ppk

@@ -211,11 +211,20 @@ def test_controller_falls_back_after_a_failed_check():
 def test_learned_controller_end_to_end_small():
     """Labels from the method, training on the device, a threshold from the training
     split and the controller against the threshold rule on held-out seeds (a small
-    version of the order-3 experiment; the full-size run is reported separately)."""
+    version of the order-3 experiment; the full-size run is reported separately).
+
+    What the network itself gains is measured against the ablation that keeps the rest
+    of the controller (leaving at rho_cap = 3 eps, periodic exact checks, fallback) and
+    replaces the network by a constant that never asks to leave.  At full size that
+    share is a loss of 1-2% at both orders (the gain at order 5 comes from rho_cap and
+    the checks): a prediction of the right-hand-side error does not tell when leaving
+    the PP phase pays, because staying costs less than a rebuild until rho_cap.  The
+    test asserts that this absence holds here too: the network's share stays below
+    1.10 (geometric mean over the held-out runs both arms bring to the target)."""
     from paper_1811_10573_amd import controller as ctl
     res, params = ctl.experiment(3, list(range(0, 40)), list(range(40, 50)), list(range(2000, 2008)),
-                                 shape=(60, 60, 60), max_sweeps=80, steps=1500, progress_every=10,
-                                 tau_search_runs=6)
+                                 shape=(60, 60, 60), max_sweeps=150, steps=1500, progress_every=10,
+                                 tau_search_runs=6, target=0.95)
     print({k: v for k, v in res.items() if k != "per_run"})
     assert res["labels"]["train"] >= 100 and res["labels"]["val"] >= 20
     # the network explains most of the label variance on held-out runs
@@ -226,3 +235,9 @@ def test_learned_controller_end_to_end_small():
     # best of the candidates
     assert res["log10_tau"] in [t for t, _ in res["tau_search"]]
     assert max(g for _, g in res["tau_search"]) == dict(res["tau_search"])[res["log10_tau"]]
+    share = ev["network_vs_capped"]
+    assert share["both_reached"] >= 3, ev
+    assert share["speedup_geomean"] < 1.10, share
+    # the ablation arm never leaves on a prediction: it keeps more PP sweeps than the
+    # threshold rule wherever rho stays below rho_cap
+    assert sum(e["pp_capped"] >= e["pp_fixed"] for e in res["per_run"]) >= len(res["per_run"]) // 2

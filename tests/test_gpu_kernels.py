@@ -199,7 +199,9 @@ def test_gram_solve_singular_uses_the_diagonal_shift():
     s = torch.zeros(1, dtype=torch.int32, device=dev())
     ws = torch.empty(pp.gram_solve_workspace_bytes(R, rows), dtype=torch.uint8, device=dev())
     pp.gram_solve(R, rows, to_dev(gamma), to_dev(M), Ad, g, s, ws)
-    assert s.item() == 1
+    # outcome 1 (shifted), no non-finite value, first failed pivot at the zero column
+    assert s.item() & 3 == 1 and not s.item() & 16
+    assert (s.item() >> 8) - 1 == olinalg.first_failed_pivot(gamma) == 2
     got = Ad.cpu().numpy().reshape(rows, R)
     assert np.all(np.isfinite(got))
     np.testing.assert_allclose(got @ gamma, M, atol=1e-6 * np.abs(M).max())
@@ -217,3 +219,57 @@ def test_exact_residual(dims, R, dt):
                        plan.workspace(dev()))
     want = float(np.sum((X - ocp.cp_full(A)) ** 2))
     assert abs(out.item() - want) <= 1e-10 * want
+
+
+def test_gram_solve_flags_non_finite_results():
+    """A right-hand side with a NaN: the factorisation is clean (no pivot), and bit 4 of
+    the status word reports the non-finite factor."""
+    rng = np.random.default_rng(5)
+    R, rows = 7, 11
+    B = rng.standard_normal((30, R))
+    gamma = B.T @ B
+    M = rng.standard_normal((rows, R))
+    M[4, 2] = np.nan
+    Ad = to_dev(np.zeros((rows, R)))
+    g = torch.zeros(1, dtype=torch.float64, device=dev())
+    s = torch.zeros(1, dtype=torch.int32, device=dev())
+    ws = torch.empty(pp.gram_solve_workspace_bytes(R, rows), dtype=torch.uint8, device=dev())
+    pp.gram_solve(R, rows, to_dev(gamma), to_dev(M), Ad, g, s, ws)
+    assert s.item() == 16
+    got = Ad.cpu().numpy().reshape(rows, R)
+    assert np.isnan(got[4]).any() and np.all(np.isfinite(np.delete(got, 4, axis=0)))
+
+
+@pytest.mark.parametrize("dims,R", [((20, 18, 16), 5), ((80, 75, 72), 70)])
+def test_sweep_record_reports_the_failed_pivot(dims, R):
+    """Factors 1 and 2 start with column 3 zero, so every Gamma of the first ALS sweep has
+    a zero row and column 3: the record names pivot 3 (the oracle's first failed pivot)
+    with outcome 1 (diagonal shift) in every mode, on the fused tail (R = 5) and on the
+    general-rank tail (R = 70), and flags no non-finite value."""
+    prob = tensorgen.make_problem(dims, R, seed=3, eta=1e-2)
+    init = [a.copy() for a in prob.init]
+    init[1][:, 3] = 0.0
+    init[2][:, 3] = 0.0
+    plan = pp.Plan(dims, R, "f64")
+    X = to_dev(prob.X)
+    A = [to_dev(a) for a in init]
+    S = to_dev(np.stack([a.T @ a for a in init]).reshape(-1))
+    ws = plan.workspace(dev())
+    rec = pp.new_record(dev())
+    nrm = torch.zeros(1, dtype=torch.float64, device=dev())
+    pp.tensor_norm2(X, nrm)
+    pp.cp_als_sweep(plan, X, None, A, S, float(nrm.item()), ws, rec)
+    got = pp.read_record(rec)
+    Ao = [a.copy() for a in init]
+    So = [a.T @ a for a in Ao]
+    ref = ocp.als_sweep(prob.X, [a.copy() for a in init], [s.copy() for s in So])
+    Aw = [a.copy() for a in init]
+    Sw = [a.T @ a for a in Aw]
+    for n in range(3):
+        gamma = ocp.hadamard_except(Sw, n)
+        want = olinalg.first_failed_pivot(gamma)
+        ocp.als_update(Aw, Sw, n, ocp.mttkrp(prob.X, Aw, n))
+        assert want == 3
+        assert got["chol_pivot"][n] == want, (n, got["chol_pivot"])
+        assert got["chol_status"][n] == ref.chol_status[n] == 1
+        assert got["nonfinite"][n] == 0

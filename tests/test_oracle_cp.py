@@ -190,3 +190,33 @@ def test_gram_hadamard():
             for i in (0, 1, 3):
                 want *= float(np.dot(A[i][:, r], A[i][:, q]))
             assert abs(g[r, q] - want) < 1e-12 * max(1.0, abs(want))
+
+
+def test_first_failed_pivot_is_the_first_non_positive_leading_minor():
+    """Cholesky runs through column k-1 exactly when the leading minors of orders 1..k are
+    positive (a textbook fact): the failing pivot is the first leading minor <= 0."""
+    from oracle import linalg as olinalg
+    rng = np.random.default_rng(4)
+    B = rng.standard_normal((12, 6))
+    spd = B.T @ B
+    assert olinalg.first_failed_pivot(spd) == -1
+    for k in range(6):
+        g = spd.copy()
+        g[k, :] = 0.0
+        g[:, k] = 0.0
+        minors = [np.linalg.det(g[:m, :m]) for m in range(1, 7)]
+        want = next(m for m, d in enumerate(minors) if d <= 1e-12 * abs(minors[0]))
+        assert olinalg.first_failed_pivot(g) == want == k
+    ind = np.diag([1.0, 2.0, -1.0, 3.0])
+    assert olinalg.first_failed_pivot(ind) == 2
+
+
+def test_first_failed_pivot_with_non_finite_entries():
+    from oracle import linalg as olinalg
+    g = np.eye(5) * 2.0
+    g[3, 1] = g[1, 3] = np.nan
+    assert olinalg.first_failed_pivot(g) == 3
+    g = np.eye(5)
+    g[2, 2] = -1.0
+    g[4, 0] = g[0, 4] = np.inf
+    assert olinalg.first_failed_pivot(g) == 2
