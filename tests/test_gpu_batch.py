@@ -160,3 +160,47 @@ def test_convergence_bookkeeping():
         else:
             assert x["sweeps"] == 200
     assert sum(x["converged_sweep"] > 0 for x in res) >= 10
+
+
+def _c5_specs(count):
+    """The first problems of the batched workload: s_n ~ U{32..192} per mode and
+    R ~ U{4..48} from SeedSequence(0).spawn(512), problem p from seed p."""
+    out = []
+    for p, ss in enumerate(np.random.SeedSequence(0).spawn(512)[:count]):
+        rng = np.random.default_rng(ss)
+        dims = tuple(int(d) for d in rng.integers(32, 193, 3))
+        out.append((dims, int(rng.integers(4, 49)), p))
+    return out
+
+
+def test_batch_at_workload_sizes_matches_oracle():
+    """16 problems of the batched workload itself (contractions of up to 36k rows, so
+    many row runs of the grouped GEMM per contraction; ranks up to 48, so up to three
+    column blocks), 100 sweeps of PP-CP-ALS at eps = 0.1 stopping at |dfit| < 1e-5, HIP
+    graph replays.  Each problem's kind log is replayed by the float64 oracle on
+    float64(float32(X)): the final fit estimate within 1e-5 relative (the FP32 bound),
+    the exact fit of the GPU factors within 1e-5 of the oracle's."""
+    specs = _c5_specs(16)
+    assert max(d[0] * d[1] for d, _, _ in specs) > 1024 and max(R for _, R, _ in specs) > 32
+    r = BatchRun(specs, max_sweeps=100, eps=0.1, tol=1e-5)
+    r.b.autotune(r.ws, reps=1)
+    r.reset()
+    r.b.run(r.ws, 100, use_graph=True)
+    res = r.b.results(r.ws)
+    log = r.b.kind_log(r.ws)
+    saw_pp = 0
+    for p, (q, (d, R, _)) in enumerate(zip(r.probs, specs)):
+        kinds = _kinds(log[p])
+        assert res[p]["sweeps"] == len(kinds) >= 2
+        saw_pp += "pp_approx" in kinds
+        Xh = fp32_round(q.X)
+        A_or, recs = opp.pp_als(Xh, q.init, eps=0.1, sweeps=len(kinds), replay=kinds)
+        assert abs(res[p]["fit"] - recs[-1].fit_est) <= 1e-5 * abs(recs[-1].fit_est), (p, d, R)
+        f_gpu = ocp.fit_identity(float(np.sum(Xh * Xh)), ocp.mttkrp(Xh, r.factors(p), 2),
+                                 r.factors(p)[2],
+                                 ocp.hadamard_except([a.T @ a for a in r.factors(p)], 2),
+                                 r.factors(p)[2].T @ r.factors(p)[2])
+        f_or = ocp.fit_identity(float(np.sum(Xh * Xh)), ocp.mttkrp(Xh, A_or, 2), A_or[2],
+                                ocp.hadamard_except([a.T @ a for a in A_or], 2), A_or[2].T @ A_or[2])
+        assert abs(f_gpu - f_or) <= 1e-5 * abs(f_or), (p, d, R, f_gpu, f_or)
+    assert saw_pp >= 4
