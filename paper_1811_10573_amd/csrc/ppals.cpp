@@ -544,6 +544,15 @@ void layout(ppals_plan* p) {
     if (t.blen > 1) szF = std::max(szF, (size_t)t.X * R * 8);
     szT = std::max(szT, (size_t)t.job.xsplit * t.P * t.Q * R * 8);
   }
+  {
+    // the M_p^(n) contractions of a build run in one launch, each with its own slots
+    size_t szMp = 0;
+    for (int n = 0; n < p->N; ++n) {
+      const TtvStep& t = p->ttv[p->mp_ttv[n]];
+      szMp += (size_t)t.job.xsplit * t.P * t.Q * R * 8;
+    }
+    szT = std::max(szT, szMp);
+  }
   size_t szPP = 0;
   for (int n = 0; n < p->N; ++n) szPP = std::max(szPP, (size_t)p->pp_slots[n] * p->dims[n] * R * 8);
   p->off_B = take(szB); p->sz_B = szB;
@@ -1127,9 +1136,44 @@ ppals_status do_pp_build(ppals_plan* p, const void* X, const void* Xb, double* c
     }
     if (st != PPALS_OK) return st;
   }
-  for (int n = 0; n < p->N; ++n) {
-    ppals_status st = run_ttv(c, p->ttv[p->mp_ttv[n]], A, c.Mp(n), 6);
-    if (st != PPALS_OK) return st;
+  {
+    // M_p^(n) for every mode: each contracts a leaf with one build-time factor, so the N
+    // contractions are independent and share one launch (each job with its own partial
+    // slots), followed by one slot reduction per mode.  Same jobs, same bits as N
+    // launches.
+    TtvBatch b;
+    memset(&b, 0, sizeof(b));
+    b.R = p->R;
+    b.njobs = p->N;
+    double* part = c.at<double>(p->off_tpart);
+    int64_t off[PPALS_MAX_ORDER + 1];
+    off[0] = 0;
+    double fl = 0, by = 0;
+    for (int n = 0; n < p->N; ++n) {
+      const TtvStep& t = p->ttv[p->mp_ttv[n]];
+      TtvJob& J = b.job[n];
+      J = t.job;
+      J.T = c.buf(t.src_buf);
+      J.t_is_f32 = p->bulk == DT_F32;
+      J.F = A[t.src_modes[t.bpos]];
+      J.out = part + off[n];
+      const int64_t count = t.P * t.Q * p->R;
+      off[n + 1] = off[n] + count * t.job.xsplit;
+      fl += 2.0 * (double)t.P * t.X * t.Q * p->R;
+      by += (double)t.P * t.X * t.Q * p->R * esize(p->bulk) + (double)count * 8 * t.job.xsplit +
+            (double)t.X * p->R * 8;
+    }
+    {
+      Prof pr(p, 6, s, fl, by);
+      HIPCHK(launch_ttv(b, s));
+      pr.end();
+    }
+    for (int n = 0; n < p->N; ++n) {
+      const TtvStep& t = p->ttv[p->mp_ttv[n]];
+      const int64_t count = t.P * t.Q * p->R;
+      HIPCHK(launch_combine(c.Mp(n), count, p->R, nullptr, part + off[n], t.job.xsplit, count,
+                            nullptr, nullptr, s));
+    }
   }
   {
     // A_p := A, dA := 0, U := 0 and the counters of the fused PP-correction launches (which
