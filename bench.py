@@ -222,6 +222,12 @@ def batch_cpu_baseline(specs, eps, sweeps, tol, budget_s):
 
 
 def batch_bench(args, torch, dev):
+    print(json.dumps(batch_leg(args, torch, dev, cpu=not args.no_cpu_baseline)), flush=True)
+
+
+def batch_leg(args, torch, dev, cpu=True, warmup=None):
+    """The batched workload (512 order-3 problems in one HIP graph per batched sweep):
+    returns its result line."""
     import paper_1811_10573_amd as pp
     import tensorgen
     count, sweeps, eps, tol = args.batch_count, 100, 0.1, 1e-5
@@ -247,7 +253,7 @@ def batch_bench(args, torch, dev):
     reset()
     b.autotune(ws, reps=3)
     tune = b.describe()
-    for w in range(args.warmup):
+    for w in range(args.warmup if warmup is None else warmup):
         reset()
         b.run(ws, sweeps, use_graph=True)
         torch.cuda.synchronize()
@@ -275,10 +281,10 @@ def batch_bench(args, torch, dev):
             "frac": achieved / PEAK["hbm_GBs"], "traffic": None, "kernel": "k_b_gemm",
             "avg_ms": ms / 2, "work_per_launch": nbytes / 2,
             "TFLOP_s": flops / (ms * 1e-3) / 1e12}
-    cpu = None
-    if not args.no_cpu_baseline:
+    cpu_line = None
+    if cpu:
         log("timing the float64 oracle on the host (bounded sample)")
-        cpu = batch_cpu_baseline(specs, eps, sweeps, tol, args.cpu_seconds)
+        cpu_line = batch_cpu_baseline(specs, eps, sweeps, tol, args.cpu_seconds)
     kinds = {"als": sum(r["n_als"] for r in res), "pp_init": sum(r["n_pp_init"] for r in res),
              "pp_approx": sum(r["n_pp_approx"] for r in res)}
     line = {
@@ -290,13 +296,15 @@ def batch_bench(args, torch, dev):
                                f"N(0,1) planted factors, 1e-3 noise, eps={eps}, {sweeps} sweeps max, "
                                f"stop at |dfit| < {tol}, one HIP graph per batched sweep",
                    "count": count},
-        "roofline": roof, "cpu_baseline": cpu,
+        "roofline": roof, "cpu_baseline": cpu_line,
         "batch": {"converged": len(conv),
                   "time_to_converge_ms_p50": float(np.percentile(conv, 50)) if conv else None,
                   "time_to_converge_ms_p99": float(np.percentile(conv, 99)) if conv else None,
                   "sweep_kinds": kinds, "autotune": tune},
     }
-    print(json.dumps(line), flush=True)
+    del ws, b, X, A, init
+    torch.cuda.empty_cache()
+    return line
 
 
 def roof_of(stat, bound, peak, traffic=None):
@@ -614,6 +622,10 @@ def main():
     ap.add_argument("--collinearity", type=float, default=0.9,
                     help="column collinearity of the planted factors (< 0: i.i.d. N(0,1) factors)")
     ap.add_argument("--order", type=int, default=3)
+    ap.add_argument("--shape", default=None,
+                    help="comma-separated mode sizes (overrides --size and --order)")
+    ap.add_argument("--dist", default="normal", choices=["normal", "uniform"],
+                    help="distribution of the planted factors when --collinearity < 0")
     ap.add_argument("--eta", type=float, default=1e-3, help="relative noise level")
     ap.add_argument("--device-gen", action="store_true",
                     help="assemble the tensor on the GPU (tensorgen.make_problem_device)")
@@ -663,16 +675,20 @@ def main():
         return
     s, R = args.size, args.rank
     shape = (s,) * args.order
+    if args.shape:
+        shape = tuple(int(v) for v in args.shape.split(","))
+        s = max(shape)
     coll = args.collinearity if args.collinearity >= 0 else None
-    log(f"generating {shape} rank-{R} planted tensor (collinearity {coll}, noise {args.eta}, "
-        f"seed {args.seed})")
+    log(f"generating {shape} rank-{R} planted tensor ({args.dist} factors, collinearity {coll}, "
+        f"noise {args.eta}, seed {args.seed})")
     t0 = time.perf_counter()
     if args.device_gen:
         prob = tensorgen.make_problem_device(shape, R, args.seed, eta=args.eta, collinearity=coll,
-                                             dtype="f64", device=dev)
+                                             dist=args.dist, dtype="f64", device=dev)
         X64 = prob.X.reshape(-1)
     else:
-        prob = tensorgen.make_problem(shape, R, seed=args.seed, eta=args.eta, collinearity=coll)
+        prob = tensorgen.make_problem(shape, R, seed=args.seed, eta=args.eta, collinearity=coll,
+                                      dist=args.dist)
         X64 = None
     log(f"generated in {time.perf_counter() - t0:.1f} s")
 
@@ -842,9 +858,9 @@ def main():
         del ws64, X64
     # further legs of the default workload: the FP64 tier on the same decomposition, the
     # 64^3 ALS configuration and the first-level contractions of the 160^4 configuration
-    extras = (not args.no_extras and args.tier == "f32" and args.order == 3 and s == 800
+    extras = (not args.no_extras and args.tier == "f32" and shape == (800, 800, 800)
               and R == 50 and not args.device_gen)
-    f64 = c1 = c3 = None
+    f64 = c1 = c3 = batch = None
     A_f64_replay = c1prob = None
     if extras:
         del ws
@@ -853,6 +869,10 @@ def main():
                                     warmup=1, steps=2)
         c1, c1prob = c1_leg(pp, torch, dev, tensorgen)
         c3 = c3_level1_leg(pp, torch, dev, tensorgen)
+        bl = batch_leg(args, torch, dev, cpu=False, warmup=1)
+        batch = {k: bl[k] for k in ("value", "unit", "ms_per_step", "roofline", "batch")}
+        batch["workload"] = bl["config"]["workload"]
+        batch["batch"] = {k: v for k, v in batch["batch"].items() if k != "autotune"}
 
     cpu = None
     vs_oracle = None
@@ -921,7 +941,7 @@ def main():
         "config": {
             "workload": (f"PP-CP-ALS, order-{len(shape)} {'x'.join(map(str, shape))} {tdt.upper()} "
                          f"tensor, planted rank-{R} CP with "
-                         f"{'collinearity ' + str(coll) if coll is not None else 'N(0,1) factors'}, "
+                         f"{'collinearity ' + str(coll) if coll is not None else ('U[0,1) factors' if args.dist == 'uniform' else 'N(0,1) factors')}, "
                          f"{args.eta:g} noise, decomposition rank {R}, eps={args.eps}, "
                          f"{args.sweeps} sweeps per step"),
             "shape": list(shape), "rank": R, "eps": args.eps, "sweeps_per_step": args.sweeps,
@@ -938,6 +958,7 @@ def main():
         "f64_tier": f64,
         "c1_als": c1,
         "c3_level1": c3,
+        "c5_batch": batch,
         "paper_reference": PAPER_NUMBERS,
         "kernels": kernels,
     }

@@ -322,3 +322,43 @@ def test_pp_sweep_after_pp_rhs_uses_every_correction(dims, R):
     for n in range(len(dims)):
         assert rel(G[n], A_or[n]) < tol, (n, rel(G[n], A_or[n]), tol)
     assert abs(pp.read_record(r.rec)["fit_est"] - rec.fit_est) < max(1e-11, tol)
+
+
+# ---------------------------------------------------------------------------
+# Shapes of the paper's real-data experiments, scaled down (uniform factors)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("tier", ["f64", "f32"])
+@pytest.mark.parametrize("dims,R", [((16, 16, 3, 120), 15), ((48, 64, 33, 9), 20),
+                                    ((113, 14, 14), 40)])
+def test_paper_shaped_runs_match_oracle(dims, R, tier):
+    """Non-equidimensional tensors shaped like the image and chemistry experiments of
+    Section 5.1 (a mode of 3 below the rank; modes of 33 and 9; rank above two mode
+    sizes), planted with U[0,1) factors and 1e-2 noise: free PP-ALS (eps = 0.1, 30
+    sweeps) replayed by the oracle.  FP64 within the sensitivity bound.  FP32: final fit
+    within max(1e-5, 100 x the oracle's own fit change when its start moves by 2^-24);
+    these runs are still in their transient after 30 sweeps (the image-shaped one
+    oscillates between PP phases for 80 sweeps), where FP32 rounding at every
+    contraction moves the fit further than one rounding of the start does."""
+    prob = tensorgen.make_problem(dims, R, seed=51, eta=1e-2, dist="uniform")
+    r = Run(prob, tier)
+    recs, _ = r.run(eps=0.1, max_sweeps=30)
+    kinds = kinds_of(recs)
+    A_or, ref = opp.pp_als(prob.X, prob.init, eps=0.1, sweeps=30, replay=kinds)
+    if tier == "f64":
+        sens = oracle_sensitivity(
+            lambda A: opp.pp_als(prob.X, A, eps=0.1, sweeps=30, replay=kinds)[0], prob.init)
+        tol = max(1e-8, 1e3 * sens)
+        G = r.factors()
+        for n in range(len(dims)):
+            assert rel(G[n], A_or[n]) < tol, (n, rel(G[n], A_or[n]), tol)
+        for g, o in zip(recs, ref):
+            assert abs(g["fit_est"] - o.fit_est) <= max(1e-10, tol) * abs(o.fit_est)
+    else:
+        f_gpu = oracle_fit(prob.X, r.factors())
+        f_or = oracle_fit(prob.X, A_or)
+        rng = np.random.default_rng(0)
+        A_pt, _ = opp.pp_als(prob.X, [a * (1 + U32 * rng.standard_normal(a.shape)) for a in prob.init],
+                             eps=0.1, sweeps=30, replay=kinds)
+        sens32 = abs(oracle_fit(prob.X, A_pt) - f_or) / abs(f_or)
+        assert abs(f_gpu - f_or) <= max(1e-5, 100 * sens32) * abs(f_or), (kinds, f_gpu, f_or, sens32)
