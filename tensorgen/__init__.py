@@ -11,7 +11,8 @@ Workload families (Section 5.1 of the paper, "Sequential Experimental Results"):
   prescribed collinearity (the paper defines collinearity as the common cosine
   between distinct columns of each factor);
 * planted tensors built from uniformly distributed factors in [0, 1];
-* planted tensors with i.i.d. standard normal factors.
+* planted tensors with i.i.d. standard normal factors;
+* planted Tucker tensors: factors with orthonormal columns and an i.i.d. normal core.
 
 Noise is added as eta * ||T||_F * E / ||E||_F with E i.i.d. N(0, 1), so the
 relative noise level is exactly eta.  Initial factors for ALS are uniform in
@@ -35,6 +36,9 @@ __all__ = [
     "make_problem",
     "DeviceProblem",
     "make_problem_device",
+    "tucker_reconstruct",
+    "TuckerProblem",
+    "make_tucker_problem",
 ]
 
 
@@ -176,3 +180,40 @@ def make_problem_device(shape, rank, seed, eta=1e-3, dist="normal", collinearity
     X = T.to(torch.float32) if dtype == "f32" else T
     return DeviceProblem(X=X.contiguous(), planted=planted, init=init, rank=rank, eta=eta,
                          seed=seed, shape=tuple(shape))
+
+
+def tucker_reconstruct(core, factors):
+    """Dense tensor core x_1 A^(1) x_2 .. x_N A^(N), row-major."""
+    T = core
+    for n, a in enumerate(factors):
+        T = np.moveaxis(np.tensordot(a, T, axes=([1], [n])), 0, n)
+    return np.ascontiguousarray(T)
+
+
+@dataclasses.dataclass
+class TuckerProblem:
+    X: np.ndarray            # float64 tensor, row-major
+    core: np.ndarray         # planted core
+    planted: list            # planted factors (orthonormal columns)
+    ranks: tuple
+    eta: float
+    seed: int
+
+    @property
+    def shape(self):
+        return self.X.shape
+
+
+def make_tucker_problem(shape, ranks, seed, eta=1e-3):
+    """Planted Tucker tensor plus noise: factors with orthonormal columns (QR of i.i.d.
+    N(0,1) matrices, stream 0), an i.i.d. N(0,1) core (stream 0 after the factors) and
+    noise eta ||T|| E / ||E|| (stream 1)."""
+    g_fac, g_noise, _ = streams(seed)
+    planted = []
+    for s, r in zip(shape, ranks):
+        q, _ = np.linalg.qr(g_fac.standard_normal((s, r)))
+        planted.append(np.ascontiguousarray(q))
+    core = g_fac.standard_normal(tuple(ranks))
+    T = tucker_reconstruct(core, planted)
+    X = add_noise(T, eta, g_noise)
+    return TuckerProblem(X=X, core=core, planted=planted, ranks=tuple(ranks), eta=eta, seed=seed)
