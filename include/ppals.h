@@ -426,6 +426,120 @@ ppals_status ppals_set_profiling(ppals_plan* plan, int32_t enable);
 ppals_status ppals_get_profile(ppals_plan* plan, ppals_kernel_stat* out, int32_t max_entries,
                                int32_t* n_out, int32_t reset);
 
+/* ---------------------------------------------------------------------------
+ * Tucker decomposition of an order-3 tensor by ALS (HOOI, Algorithm 2) and by
+ * pairwise perturbation (PP-Tucker-ALS, Algorithm 4 with the first-order
+ * approximation of Section 3.2.2), FP64 throughout.
+ *
+ *   X       s_1 x s_2 x s_3 doubles, row-major (device).
+ *   A[n]    s_n x R doubles, orthonormal columns (device), updated in place.
+ *   G       the core, R x R x R doubles, index order (r_1, r_2, r_3) (device).
+ *   ws      caller-allocated workspace of tucker_workspace_bytes() bytes, 256-byte
+ *           aligned; it holds the PP operators between tucker_pp_build and later
+ *           tucker_pp_sweep calls.
+ * The TTMc Y^(n) = X x_{i != n} A^(i)T (Section 2.4) is stored as an s_n x R x R
+ * array whose two rank indices are, for n = 1, 2, 3: (r_3, r_2), (r_3, r_1),
+ * (r_1, r_2).
+ *
+ * Factor update.  A^(n) <- the R leading left singular vectors of Y^(n)_(n), i.e.
+ * the eigenvectors of W = Y_(n) Y_(n)^T for its R largest eigenvalues (the
+ * Gram-matrix route of Section 2.4), found by subspace iteration started from the
+ * current A^(n): C = W V applied as Y_(n) (Y_(n)^T V) without forming W, a
+ * Rayleigh-Ritz step on span(V) (Cholesky of V^T V, Jacobi rotations of the
+ * projected R x R matrix), the next basis C T Lambda^-1, until the largest Ritz
+ * residual ||W u_j - lambda_j u_j|| / lambda_1 is at most `tol` or after
+ * `max_iters` iterations.  Columns are in decreasing eigenvalue order; each new
+ * column is oriented to a non-negative inner product with the column it replaces.
+ * The iteration synchronises the stream once per iteration to read the residual,
+ * so every entry point below that updates factors returns with the stream idle.
+ *
+ * Limits: 1 <= R <= 64, R <= s_n for every n.
+ * ------------------------------------------------------------------------- */
+#define TUCKER_MAX_RANK 64
+typedef struct tucker_plan tucker_plan;
+
+typedef struct {
+  int32_t kind;             /* PPALS_SWEEP_ALS / _PP_INIT / _PP_APPROX               */
+  int32_t iters[3];         /* subspace iterations of the update of A^(n)           */
+  int32_t converged[3];     /* 1 if the Ritz residual reached tol                   */
+  int32_t rr_status[3];     /* 1 if a Rayleigh-Ritz step met a V^T V that was not
+                               positive definite                                     */
+  double fit;               /* 1 - sqrt(max(0, ||X||^2 - ||G||^2)) / ||X||           */
+  double core_norm;         /* ||G||_F of the core this sweep formed                 */
+  double f_norm;            /* ||F||_F, F = G_new - G_old (Algorithm 4)              */
+  double rel_change[3];     /* ||dA^(n)||_F / ||A^(n)||_F: the change over the sweep
+                               (ALS) or since the operator build (PP)                */
+  double ritz_residual[3];  /* final Ritz residual of each update                    */
+  double ms;                /* host wall time of the sweep (enqueue to completion)   */
+} tucker_sweep_record;
+
+/* Host only: checks the sizes and lays out the workspace. */
+ppals_status tucker_plan_create(const int64_t dims[3], int32_t rank, tucker_plan** out);
+void tucker_plan_destroy(tucker_plan* plan);
+size_t tucker_workspace_bytes(const tucker_plan* plan);
+/* Subspace-iteration limits (defaults: tol 1e-12, 500 iterations for sweeps, 5000 for
+ * the HOSVD). */
+ppals_status tucker_set_solver(tucker_plan* plan, double tol, int32_t max_iters,
+                               int32_t hosvd_max_iters);
+
+/* Y^(mode) = X x_{i != mode} A^(i)T into Y (s_mode x R x R, layout above); mode is
+ * 0-based.  Enqueues only. */
+ppals_status tucker_ttmc(tucker_plan* plan, void* ws, const double* X, double* const* A,
+                         int32_t mode, double* Y, hipStream_t stream);
+
+/* Factor update of mode `mode` from a TTMc Y (s_mode x R^2, rows indexed by the mode):
+ * A_out <- leading eigenvectors of Y Y^T, started from and oriented against A_prev.
+ * A_out may equal A_prev.  info (host, may be NULL) receives {iterations, converged,
+ * rr_status} and *residual the final Ritz residual.  Synchronises the stream. */
+ppals_status tucker_factor_update(tucker_plan* plan, void* ws, const double* Y, int32_t mode,
+                                  const double* A_prev, double* A_out, int32_t* info,
+                                  double* residual, hipStream_t stream);
+
+/* Classical HOSVD start (Section 2.4): A^(n) <- leading eigenvectors of
+ * X_(n) X_(n)^T (formed explicitly, then subspace iteration from the caller's start
+ * V0[n], s_n x R, full column rank), the entry of largest magnitude of every column
+ * made positive; G <- X x_1 A^(1)T x_2 A^(2)T x_3 A^(3)T.  info (host, 3 x 3 ints, may
+ * be NULL) as in tucker_factor_update per mode.  Synchronises the stream. */
+ppals_status tucker_hosvd(tucker_plan* plan, void* ws, const double* X, double* const* V0,
+                          double* const* A, double* G, int32_t* info, hipStream_t stream);
+
+/* One Tucker-ALS sweep (Algorithm 2 loop body) with the order-3 TTMc tree: T = X x_3
+ * A^(3)T serves the updates of A^(1) and A^(2), X x_1 A^(1)T that of A^(3); then G from
+ * the last TTMc.  G holds the previous core on entry (for ||F||).  normX2 = ||X||^2. */
+ppals_status tucker_als_sweep(tucker_plan* plan, void* ws, const double* X, double* const* A,
+                              double* G, double normX2, tucker_sweep_record* rec,
+                              hipStream_t stream);
+
+/* PP-Tucker operator build (Algorithm 4): with A_p = A, the three pairwise operators
+ * Y_p^(i,n) = X x_j A_p^(j)T (j the third mode) and Y_p^(n) for every n; dA <- 0.
+ * Enqueues only. */
+ppals_status tucker_pp_build(tucker_plan* plan, void* ws, const double* X, double* const* A,
+                             hipStream_t stream);
+
+/* First-order PP TTMc of Section 3.2.2 with the workspace's current dA:
+ * Y~^(mode) = Y_p^(mode) + sum_{i != mode} Y_p^(i,mode) x_i dA^(i)T, into Y (layout of
+ * tucker_ttmc).  PPALS_E_STATE before a build.  Enqueues only. */
+ppals_status tucker_pp_rhs(tucker_plan* plan, void* ws, int32_t mode, double* Y,
+                           hipStream_t stream);
+
+/* One PP-Tucker sweep (Algorithm 4 inner loop body): for every mode the approximated
+ * TTMc, the factor update and dA^(n) = A^(n) - A_p^(n); then G from Y~^(3).  kind is
+ * recorded as given (PP_INIT or PP_APPROX).  PPALS_E_STATE before a build. */
+ppals_status tucker_pp_sweep(tucker_plan* plan, void* ws, double* const* A, double* G,
+                             double normX2, int32_t kind, tucker_sweep_record* rec,
+                             hipStream_t stream);
+
+/* PP-Tucker-ALS control (Algorithm 4) for at most `sweeps` sweeps from A and G (the
+ * HOSVD start, normally).  PP is entered after a sweep in which every
+ * ||dA^(n)|| < eps ||A^(n)|| and ||F|| < eps ||X||, and PP sweeps continue while
+ * ||F|| < eps ||X||; eps = 0 gives plain Tucker-ALS.  delta > 0 stops once
+ * ||F|| <= delta ||X||.  replay (host, may be NULL): replay_len sweep kinds to follow
+ * instead of deciding.  recs (host) receives one record per sweep, *n_out their number. */
+ppals_status tucker_run(tucker_plan* plan, void* ws, const double* X, double* const* A,
+                        double* G, double eps, int32_t sweeps, double delta,
+                        const int32_t* replay, int32_t replay_len, tucker_sweep_record* recs,
+                        int32_t* n_out, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

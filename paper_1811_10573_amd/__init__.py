@@ -5,7 +5,10 @@ This module only marshals arguments: device buffers are PyTorch tensors
 The function names mirror the C ABI declared in include/ppals.h:
 cp_als_sweep, pp_build_operators, pp_sweep, gram_solve, plus the auxiliary
 entry points (norm, bf16 cast, MTTKRP, first-level contraction, PP right-hand
-side, operators, exact residual and the native decomposition driver).
+side, operators, exact residual and the native decomposition driver), the
+batched engine and the order-3 Tucker path (TuckerPlan: tucker_ttmc,
+tucker_factor_update, tucker_hosvd, tucker_als_sweep, tucker_pp_build,
+tucker_pp_rhs, tucker_pp_sweep, tucker_run).
 """
 from __future__ import annotations
 
@@ -498,3 +501,143 @@ class Batch:
 
 
 BATCH_KIND_NAMES = {1: "als", 2: "pp_init", 3: "pp_approx"}
+
+
+# ---- Tucker (order 3) -----------------------------------------------------------
+
+TUCKER_RECORD_FIELDS = ("iters", "converged", "rr_status", "fit", "core_norm", "f_norm",
+                        "rel_change", "ritz_residual", "ms")
+
+
+def tucker_record_dict(r):
+    d = {"kind": KIND_NAMES.get(r.kind, str(r.kind))}
+    for f in TUCKER_RECORD_FIELDS:
+        v = getattr(r, f)
+        d[f] = list(v) if hasattr(v, "__len__") else v
+    return d
+
+
+class TuckerPlan:
+    """Order-3 Tucker plan (HOOI and PP-Tucker-ALS, FP64): sizes, solver limits and the
+    workspace layout.  Tensors and factors are float64 device tensors."""
+
+    def __init__(self, dims, rank, tol=None, max_iters=None, hosvd_max_iters=None):
+        dims = [int(d) for d in dims]
+        if len(dims) != 3:
+            raise ValueError("the Tucker path takes order-3 tensors")
+        arr = (ctypes.c_int64 * 3)(*dims)
+        h = ctypes.c_void_p()
+        _lib.check(lib().tucker_plan_create(arr, int(rank), ctypes.byref(h)))
+        self._h = h
+        self.dims = dims
+        self.rank = int(rank)
+        if tol is not None or max_iters is not None or hosvd_max_iters is not None:
+            self.set_solver(1e-12 if tol is None else tol, 500 if max_iters is None else max_iters,
+                            5000 if hosvd_max_iters is None else hosvd_max_iters)
+
+    def set_solver(self, tol, max_iters, hosvd_max_iters):
+        _lib.check(lib().tucker_set_solver(self._h, float(tol), int(max_iters),
+                                           int(hosvd_max_iters)))
+
+    @property
+    def workspace_bytes(self):
+        return int(lib().tucker_workspace_bytes(self._h))
+
+    def workspace(self, device="cuda"):
+        return torch.empty(max(1, self.workspace_bytes), dtype=torch.uint8, device=device)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        try:
+            if h is not None and h.value:
+                lib().tucker_plan_destroy(h)
+                self._h = None
+        except Exception:
+            pass
+
+    def _X(self, X):
+        return _dev(X, "X", torch.float64, self.dims[0] * self.dims[1] * self.dims[2])
+
+    def _A(self, A, name="A"):
+        if len(A) != 3:
+            raise ValueError(f"{name} needs three factors")
+        for n, a in enumerate(A):
+            _dev(a, f"{name}[{n}]", torch.float64, self.dims[n] * self.rank)
+        return (ctypes.c_void_p * 3)(*[a.data_ptr() for a in A])
+
+    def _ws(self, ws):
+        return _dev(ws, "ws", min_bytes=self.workspace_bytes)
+
+    def _G(self, G):
+        return _dev(G, "G", torch.float64, self.rank ** 3)
+
+    def _Y(self, Y, mode):
+        return _dev(Y, "Y", torch.float64, self.dims[mode] * self.rank ** 2)
+
+
+def tucker_ttmc(plan, ws, X, A, mode, Y, stream=None):
+    _lib.check(lib().tucker_ttmc(plan._h, _p(plan._ws(ws)), _p(plan._X(X)), plan._A(A), int(mode),
+                                 _p(plan._Y(Y, mode)), _stream(stream)))
+
+
+def tucker_factor_update(plan, ws, Y, mode, A_prev, A_out, stream=None):
+    """Returns {iterations, converged, rr_status, residual}."""
+    _dev(A_prev, "A_prev", torch.float64, plan.dims[mode] * plan.rank)
+    _dev(A_out, "A_out", torch.float64, plan.dims[mode] * plan.rank)
+    info = (ctypes.c_int32 * 3)()
+    res = ctypes.c_double()
+    _lib.check(lib().tucker_factor_update(plan._h, _p(plan._ws(ws)), _p(plan._Y(Y, mode)),
+                                          int(mode), _p(A_prev), _p(A_out), info,
+                                          ctypes.byref(res), _stream(stream)))
+    return {"iterations": info[0], "converged": info[1], "rr_status": info[2],
+            "residual": res.value}
+
+
+def tucker_hosvd(plan, ws, X, V0, A, G, stream=None):
+    """Returns the per-mode [iterations, converged, rr_status]."""
+    info = (ctypes.c_int32 * 9)()
+    _lib.check(lib().tucker_hosvd(plan._h, _p(plan._ws(ws)), _p(plan._X(X)), plan._A(V0, "V0"),
+                                  plan._A(A), _p(plan._G(G)), info, _stream(stream)))
+    return [list(info[3 * n:3 * n + 3]) for n in range(3)]
+
+
+def tucker_als_sweep(plan, ws, X, A, G, normX2, stream=None):
+    rec = _lib.TuckerRecord()
+    _lib.check(lib().tucker_als_sweep(plan._h, _p(plan._ws(ws)), _p(plan._X(X)), plan._A(A),
+                                      _p(plan._G(G)), float(normX2), ctypes.byref(rec),
+                                      _stream(stream)))
+    return tucker_record_dict(rec)
+
+
+def tucker_pp_build(plan, ws, X, A, stream=None):
+    _lib.check(lib().tucker_pp_build(plan._h, _p(plan._ws(ws)), _p(plan._X(X)), plan._A(A),
+                                     _stream(stream)))
+
+
+def tucker_pp_rhs(plan, ws, mode, Y, stream=None):
+    _lib.check(lib().tucker_pp_rhs(plan._h, _p(plan._ws(ws)), int(mode), _p(plan._Y(Y, mode)),
+                                   _stream(stream)))
+
+
+def tucker_pp_sweep(plan, ws, A, G, normX2, kind="pp_approx", stream=None):
+    rec = _lib.TuckerRecord()
+    _lib.check(lib().tucker_pp_sweep(plan._h, _p(plan._ws(ws)), plan._A(A), _p(plan._G(G)),
+                                     float(normX2), KIND_CODES[kind], ctypes.byref(rec),
+                                     _stream(stream)))
+    return tucker_record_dict(rec)
+
+
+def tucker_run(plan, ws, X, A, G, eps, sweeps, delta=0.0, replay=None, stream=None):
+    """PP-Tucker-ALS control (eps = 0: plain Tucker-ALS); returns the list of records."""
+    recs = (_lib.TuckerRecord * max(1, int(sweeps)))()
+    n_out = ctypes.c_int32()
+    if replay is not None:
+        codes = [KIND_CODES[k] for k in replay]
+        rp = (ctypes.c_int32 * max(1, len(codes)))(*codes)
+        rlen = len(codes)
+    else:
+        rp, rlen = None, 0
+    _lib.check(lib().tucker_run(plan._h, _p(plan._ws(ws)), _p(plan._X(X)), plan._A(A),
+                                _p(plan._G(G)), float(eps), int(sweeps), float(delta), rp, rlen,
+                                recs, ctypes.byref(n_out), _stream(stream)))
+    return [tucker_record_dict(recs[i]) for i in range(n_out.value)]

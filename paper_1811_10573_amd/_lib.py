@@ -87,6 +87,21 @@ class Controller(ctypes.Structure):
 PROF_CLASSES = 8
 
 
+class TuckerRecord(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32),
+        ("iters", ctypes.c_int32 * 3),
+        ("converged", ctypes.c_int32 * 3),
+        ("rr_status", ctypes.c_int32 * 3),
+        ("fit", ctypes.c_double),
+        ("core_norm", ctypes.c_double),
+        ("f_norm", ctypes.c_double),
+        ("rel_change", ctypes.c_double * 3),
+        ("ritz_residual", ctypes.c_double * 3),
+        ("ms", ctypes.c_double),
+    ]
+
+
 class KernelStat(ctypes.Structure):
     _fields_ = [
         ("name", ctypes.c_char * 32),
@@ -145,6 +160,20 @@ SIGNATURES = {
     "ppals_batch_kind_log": (_i32, [_vp, _vp, ctypes.POINTER(ctypes.c_uint8), _vp]),
     "ppals_batch_describe": (_i32, [_vp, ctypes.c_char_p, _sz]),
     "ppals_set_profiling": (_i32, [_vp, _i32]),
+    "tucker_plan_create": (_i32, [ctypes.POINTER(_i64), _i32, ctypes.POINTER(_vp)]),
+    "tucker_plan_destroy": (None, [_vp]),
+    "tucker_workspace_bytes": (_sz, [_vp]),
+    "tucker_set_solver": (_i32, [_vp, _dbl, _i32, _i32]),
+    "tucker_ttmc": (_i32, [_vp, _vp, _vp, _ptrs, _i32, _vp, _vp]),
+    "tucker_factor_update": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp, ctypes.POINTER(_i32),
+                                    ctypes.POINTER(_dbl), _vp]),
+    "tucker_hosvd": (_i32, [_vp, _vp, _vp, _ptrs, _ptrs, _vp, ctypes.POINTER(_i32), _vp]),
+    "tucker_als_sweep": (_i32, [_vp, _vp, _vp, _ptrs, _vp, _dbl, ctypes.POINTER(TuckerRecord), _vp]),
+    "tucker_pp_build": (_i32, [_vp, _vp, _vp, _ptrs, _vp]),
+    "tucker_pp_rhs": (_i32, [_vp, _vp, _i32, _vp, _vp]),
+    "tucker_pp_sweep": (_i32, [_vp, _vp, _ptrs, _vp, _dbl, _i32, ctypes.POINTER(TuckerRecord), _vp]),
+    "tucker_run": (_i32, [_vp, _vp, _vp, _ptrs, _vp, _dbl, _i32, _dbl, ctypes.POINTER(_i32), _i32,
+                          ctypes.POINTER(TuckerRecord), ctypes.POINTER(_i32), _vp]),
     "ppals_get_profile": (_i32, [_vp, ctypes.POINTER(KernelStat), _i32, ctypes.POINTER(_i32), _i32]),
 }
 

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(CSRC, "_build")
 LIB = os.path.join(HERE, "libppals.so")
-SOURCES = ["k_level1.hip", "k_ttv.hip", "k_small.hip", "k_tail.hip", "k_mlp.hip", "k_batch.hip", "ppals.cpp", "batch.cpp"]
+SOURCES = ["k_level1.hip", "k_ttv.hip", "k_small.hip", "k_tail.hip", "k_mlp.hip", "k_batch.hip", "k_tucker.hip", "ppals.cpp", "batch.cpp", "tucker.cpp"]
 ARCH = "gfx950"
 
 

@@ -289,26 +289,26 @@ void ttv_config(TtvJob& J, int64_t P, int64_t X, int64_t Q, int R, int es, int64
 
 constexpr int64_t kL1Workgroups = 1536;
 
-Level1Geom l1_config(const ppals_plan* p, int lo, int hi) {
+}  // namespace
+
+// Geometry of a first-level contraction of a P x K x Q tensor (K contracted) with a
+// K x R operand in the given dtype tier.
+Level1Geom l1_geom(int64_t P, int64_t K, int64_t Q, int R, int l1dt) {
   Level1Geom g;
   memset(&g, 0, sizeof(g));
-  int64_t P = 1, K = 1, Q = 1;
-  for (int i = 0; i < lo; ++i) P *= p->dims[i];
-  for (int i = lo; i < hi; ++i) K *= p->dims[i];
-  for (int i = hi; i < p->N; ++i) Q *= p->dims[i];
   g.M = P * Q;
   g.K = K;
   g.Q = Q;
-  g.R = p->R;
-  const int nbt = (p->R + 15) / 16;
+  g.R = R;
+  const int nbt = (R + 15) / 16;
   g.nslices = (nbt + 3) / 4;
   g.NB = (nbt + g.nslices - 1) / g.nslices;
-  const int KC = p->l1dt == DT_BF16 ? 64 : 32;
+  const int KC = l1dt == DT_BF16 ? 64 : 32;
   g.Kpad = (K + KC - 1) / KC * KC;
   g.kc_mode = (Q == 1) ? 1 : 0;
   int BM;
-  if (p->l1dt == DT_F64) BM = 128;
-  else if (p->l1dt == DT_F32) BM = 256;
+  if (l1dt == DT_F64) BM = 128;
+  else if (l1dt == DT_F32) BM = 256;
   else BM = g.kc_mode ? 256 : 128;
   const int64_t mtiles = (g.M + BM - 1) / BM;
   const int64_t nchunks = g.Kpad / KC;
@@ -322,6 +322,16 @@ Level1Geom l1_config(const ppals_plan* p, int lo, int hi) {
   g.kchunk = cps * KC;
   g.ksplit = (int)((g.K + g.kchunk - 1) / g.kchunk);
   return g;
+}
+
+namespace {
+
+Level1Geom l1_config(const ppals_plan* p, int lo, int hi) {
+  int64_t P = 1, K = 1, Q = 1;
+  for (int i = 0; i < lo; ++i) P *= p->dims[i];
+  for (int i = lo; i < hi; ++i) K *= p->dims[i];
+  for (int i = hi; i < p->N; ++i) Q *= p->dims[i];
+  return l1_geom(P, K, Q, p->R, p->l1dt);
 }
 
 int new_buf(ppals_plan* p, size_t bytes) {

@@ -1,0 +1,50 @@
+// Device-side interface of the Tucker kernels (k_tucker.hip) and the host plan helpers.
+#pragma once
+
+#include "common.h"
+
+namespace ppk {
+
+struct GemmArgs {
+  const double* A;
+  const double* B;
+  double* C;
+  int64_t M, N, K;
+  int64_t sam, sak;  // A(m, k) = A[m * sam + k * sak]
+  int64_t sbk, sbn;  // B(k, n) = B[k * sbk + n * sbn]
+  int64_t ldc;
+  double alpha, beta;
+  int64_t kin;       // 0: k contiguous as above; else k = k_out * kin + k_in with
+  int64_t sak2;      //   A offset k_out * sak + k_in * sak2 and
+  int64_t sbk2;      //   B offset k_out * sbk + k_in * sbk2
+  int ks;            // K split over workgroups (>= 1); ks > 1 needs alpha 1, beta 0, ldc N
+  double* part;      //   and ks x M x N doubles of partial sums here
+};
+// Minimum k-values per split of launch_gemm_f64.
+constexpr int64_t kGemmSplitMin = 128;
+hipError_t launch_gemm_f64(const GemmArgs& g, hipStream_t s);
+
+struct RRArgs {
+  int R;
+  const double* B;   // R x R, V^T V
+  const double* H;   // R x R, V^T W V
+  const double* P;   // R x R, V^T A_prev (NULL: no sign alignment)
+  double* T;         // R x R out: V T are the Ritz vectors, decreasing order
+  double* lam;       // R out: Ritz values, decreasing
+  int* status;       // [0] 1 if V^T V was not positive definite, [1] Jacobi sweeps
+};
+hipError_t launch_rayleigh_ritz(const RRArgs& a, hipStream_t s);
+hipError_t launch_ritz_residual(const double* C, const double* V, const double* lam, int64_t rows,
+                                int R, double* out, hipStream_t s);
+hipError_t launch_sign_by_max(double* V, int64_t rows, int R, hipStream_t s);
+hipError_t launch_scale_cols(double* out, const double* in, const double* lam, int64_t rows, int R,
+                             hipStream_t s);
+hipError_t launch_pp_tucker_combine(double* out, const double* Yp, const double* T1,
+                                    const double* T2, int64_t rows, int R, hipStream_t s);
+hipError_t launch_core_stats(const double* Gn, const double* Go, int64_t n, double* out,
+                             hipStream_t s);
+
+}  // namespace ppk
+
+// first-level contraction geometry (ppals.cpp)
+ppk::Level1Geom l1_geom(int64_t P, int64_t K, int64_t Q, int R, int l1dt);

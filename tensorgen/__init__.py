@@ -217,3 +217,10 @@ def make_tucker_problem(shape, ranks, seed, eta=1e-3):
     T = tucker_reconstruct(core, planted)
     X = add_noise(T, eta, g_noise)
     return TuckerProblem(X=X, core=core, planted=planted, ranks=tuple(ranks), eta=eta, seed=seed)
+
+
+def subspace_start(shape, rank, seed):
+    """Starting bases for the subspace iteration of the HOSVD: one s_n x rank matrix of
+    i.i.d. N(0,1) entries per mode (stream 2)."""
+    _, _, g = streams(seed)
+    return [np.ascontiguousarray(g.standard_normal((s, rank))) for s in shape]

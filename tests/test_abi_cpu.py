@@ -286,3 +286,45 @@ def test_batch_create_validates_and_describes(lib):
         assert lib.ppals_batch_autotune(h, fake, 1, None) == _lib.PPALS_E_STATE
     finally:
         lib.ppals_batch_destroy(h)
+
+
+def test_tucker_plan_validates_and_refuses_before_device_work(lib):
+    """Tucker plan limits (1 <= R <= 64, R <= every s_n) and the entry points' host
+    checks: null arguments, workspace alignment, PP sweeps or right-hand sides before an
+    operator build, unknown kinds."""
+    from paper_1811_10573_amd import _lib
+    h = ctypes.c_void_p()
+    dims = (ctypes.c_int64 * 3)(30, 20, 10)
+    assert lib.tucker_plan_create(dims, 0, ctypes.byref(h)) == _lib.PPALS_E_UNSUPPORTED
+    assert lib.tucker_plan_create(dims, 65, ctypes.byref(h)) == _lib.PPALS_E_UNSUPPORTED
+    assert lib.tucker_plan_create(dims, 11, ctypes.byref(h)) == _lib.PPALS_E_UNSUPPORTED
+    bad = (ctypes.c_int64 * 3)(30, 0, 10)
+    assert lib.tucker_plan_create(bad, 3, ctypes.byref(h)) == _lib.PPALS_E_ARG
+    assert lib.tucker_plan_create(dims, 10, ctypes.byref(h)) == 0
+    try:
+        R = 10
+        ws_bytes = lib.tucker_workspace_bytes(h)
+        # at least the three pairwise operators, the three Y_p^(n) and the Gram W
+        assert ws_bytes >= 8 * ((30 * 20 + 30 * 10 + 20 * 10) * R + (30 + 20 + 10) * R * R + 30 * 30)
+        assert lib.tucker_set_solver(h, 0.0, 10, 10) == _lib.PPALS_E_ARG
+        assert lib.tucker_set_solver(h, 1e-10, 0, 10) == _lib.PPALS_E_ARG
+        assert lib.tucker_set_solver(h, 1e-12, 500, 5000) == 0
+        fake = ctypes.c_void_p(0x1000)
+        arr = (ctypes.c_void_p * 3)(0x2000, 0x3000, 0x4000)
+        rec = _lib.TuckerRecord()
+        nul = ctypes.c_void_p()
+        assert lib.tucker_pp_sweep(h, fake, arr, fake, 1.0, 2, ctypes.byref(rec), nul) == _lib.PPALS_E_STATE
+        assert lib.tucker_pp_rhs(h, fake, 0, fake, nul) == _lib.PPALS_E_STATE
+        assert lib.tucker_pp_sweep(h, fake, arr, fake, 1.0, 0, ctypes.byref(rec), nul) == _lib.PPALS_E_ARG
+        assert lib.tucker_pp_sweep(h, ctypes.c_void_p(0x1008), arr, fake, 1.0, 2, ctypes.byref(rec),
+                                   nul) == _lib.PPALS_E_WORKSPACE
+        assert lib.tucker_ttmc(h, fake, fake, arr, 3, fake, nul) == _lib.PPALS_E_ARG
+        assert lib.tucker_als_sweep(h, fake, nul, arr, fake, 1.0, ctypes.byref(rec), nul) == _lib.PPALS_E_ARG
+        assert lib.tucker_als_sweep(h, fake, fake, arr, fake, 0.0, ctypes.byref(rec), nul) == _lib.PPALS_E_ARG
+        part = (ctypes.c_void_p * 3)(0x2000, None, 0x4000)
+        assert lib.tucker_pp_build(h, fake, fake, part, nul) == _lib.PPALS_E_ARG
+        n_out = ctypes.c_int32()
+        assert lib.tucker_run(h, fake, fake, arr, fake, -1.0, 5, 0.0, None, 0, ctypes.byref(rec),
+                              ctypes.byref(n_out), nul) == _lib.PPALS_E_ARG
+    finally:
+        lib.tucker_plan_destroy(h)

@@ -1,0 +1,213 @@
+"""GPU parity of the order-3 Tucker path (Tucker-ALS, Algorithm 2; PP-Tucker-ALS,
+Algorithm 4 with the first-order TTMc of Section 3.2.2) against the float64 oracle.
+
+Layouts: the library stores Y^(n) as s_n x R x R with rank indices (r3, r2), (r3, r1),
+(r1, r2) for n = 0, 1, 2; the oracle's ttmc keeps the natural mode order, so the
+comparison transposes.  Tolerances: TTMc and core are contractions of length <= s^2
+accumulated in FP64 (relative 1e-12 of the |.|-weighted sum is far above gamma_K u);
+factors come from a subspace iteration stopped at a Ritz residual of 1e-12 relative to
+the largest eigenvalue, whose eigenvector error is that residual times
+lambda_1 / (lambda_R - lambda_{R+1}); the planted problems keep that ratio below 1e3,
+so factor entries are compared at 1e-8."""
+import numpy as np
+import pytest
+
+import tensorgen
+from oracle import tucker as ot
+
+from gpu_util import to_dev
+
+pytestmark = pytest.mark.gpu
+
+pk = pytest.importorskip("paper_1811_10573_amd")
+
+# oracle Y^(n) (natural order) -> library layout
+TO_LIB = [(0, 2, 1), (1, 2, 0), (2, 0, 1)]
+
+
+def lib_layout(Y, n):
+    return np.ascontiguousarray(np.transpose(Y, TO_LIB[n]))
+
+
+def host(t, shape=None):
+    a = t.detach().cpu().numpy()
+    return a.reshape(shape) if shape is not None else a
+
+
+class TRun:
+    def __init__(self, shape, R, seed=0, eta=0.1):
+        self.prob = tensorgen.make_tucker_problem(shape, (R, R, R), seed=seed, eta=eta)
+        self.shape = tuple(shape)
+        self.R = R
+        self.plan = pk.TuckerPlan(shape, R)
+        self.X = to_dev(self.prob.X)
+        self.ws = self.plan.workspace(self.X.device)
+        self.normX2 = float(np.sum(self.prob.X ** 2))
+
+    def upload(self, A, G):
+        self.A = [to_dev(a) for a in A]
+        self.G = to_dev(G)
+
+    def factors(self):
+        return [host(a, (s, self.R)) for a, s in zip(self.A, self.shape)]
+
+    def core(self):
+        return host(self.G, (self.R,) * 3)
+
+
+def assert_rel(got, want, tol, what):
+    err = np.max(np.abs(got - want)) / max(np.max(np.abs(want)), 1e-300)
+    assert err <= tol, f"{what}: relative error {err:.3e} > {tol:.1e}"
+
+
+@pytest.mark.parametrize("shape,R", [((37, 29, 23), 5), ((70, 64, 66), 16), ((96, 80, 72), 64)])
+def test_ttmc_matches_oracle(shape, R):
+    """Y^(n) = X x_{i != n} A^(i)T for every mode: ragged sizes, several level-1 tiles,
+    the largest rank."""
+    r = TRun(shape, R, seed=1)
+    rng = np.random.default_rng(2)
+    A = [np.linalg.qr(rng.standard_normal((s, R)))[0] for s in shape]
+    r.upload(A, np.zeros((R, R, R)))
+    for n in range(3):
+        Y = to_dev(np.zeros((shape[n], R, R)))
+        pk.tucker_ttmc(r.plan, r.ws, r.X, r.A, n, Y)
+        want = lib_layout(ot.ttmc(r.prob.X, A, n), n)
+        assert_rel(host(Y, want.shape), want, 1e-12, f"Y^({n})")
+
+
+@pytest.mark.parametrize("shape,R", [((37, 29, 23), 5), ((96, 80, 72), 64)])
+def test_factor_update_matches_eigh(shape, R):
+    """Leading eigenvectors of Y_(n) Y_(n)^T, oriented against the previous factor, from a
+    TTMc the oracle made (one HOOI step past the HOSVD)."""
+    r = TRun(shape, R, seed=3)
+    A0, _ = ot.hosvd(r.prob.X, (R, R, R))
+    A1, _, _ = ot.tucker_als(r.prob.X, A0, ot.hosvd(r.prob.X, (R, R, R))[1], 1)
+    for n in range(3):
+        Yn = ot.ttmc(r.prob.X, A1, n)
+        want, _ = ot.leading_eigvecs(Yn, n, R, prev=A0[n])
+        Y = to_dev(lib_layout(Yn, n))
+        prev = to_dev(A0[n])
+        out = to_dev(np.zeros_like(A0[n]))
+        info = pk.tucker_factor_update(r.plan, r.ws, Y, n, prev, out)
+        assert info["converged"] == 1 and info["rr_status"] == 0, info
+        np.testing.assert_allclose(host(out, want.shape), want, atol=1e-8, rtol=0)
+        # in place (A_out == A_prev)
+        pk.tucker_factor_update(r.plan, r.ws, Y, n, prev, prev)
+        np.testing.assert_allclose(host(prev, want.shape), want, atol=1e-8, rtol=0)
+
+
+@pytest.mark.parametrize("shape,R", [((41, 33, 27), 4), ((90, 84, 70), 20)])
+def test_hosvd_matches_oracle(shape, R):
+    """HOSVD from random starting bases: factors (largest-magnitude entry positive) and
+    core against the oracle's eigh-based HOSVD."""
+    r = TRun(shape, R, seed=5)
+    A_want, G_want = ot.hosvd(r.prob.X, (R, R, R))
+    V0 = [to_dev(v) for v in tensorgen.subspace_start(shape, R, seed=6)]
+    r.upload([np.zeros_like(a) for a in A_want], np.zeros((R, R, R)))
+    info = pk.tucker_hosvd(r.plan, r.ws, r.X, V0, r.A, r.G)
+    assert all(i[1] == 1 and i[2] == 0 for i in info), info
+    for n, (got, want) in enumerate(zip(r.factors(), A_want)):
+        np.testing.assert_allclose(got, want, atol=1e-8, rtol=0, err_msg=f"A^({n})")
+    assert_rel(r.core(), G_want, 1e-8, "core")
+
+
+@pytest.mark.parametrize("shape,R", [((37, 29, 23), 5), ((96, 80, 72), 24)])
+def test_als_sweeps_match_oracle(shape, R):
+    """Six HOOI sweeps from the oracle's HOSVD: factors, core and every record field."""
+    r = TRun(shape, R, seed=7, eta=0.3)
+    A0, G0 = ot.hosvd(r.prob.X, (R, R, R))
+    r.upload(A0, G0)
+    A_w, G_w, recs_w = ot.tucker_als(r.prob.X, A0, G0, 6)
+    for k in range(6):
+        rec = pk.tucker_als_sweep(r.plan, r.ws, r.X, r.A, r.G, r.normX2)
+        w = recs_w[k]
+        assert rec["kind"] == "als"
+        assert all(rec["converged"]) and not any(rec["rr_status"]), rec
+        assert abs(rec["fit"] - w.fit) <= 1e-10, (k, rec["fit"], w.fit)
+        assert abs(rec["core_norm"] - w.core_norm) <= 1e-10 * w.core_norm
+        assert abs(rec["f_norm"] - w.f_norm) <= 1e-7 * w.core_norm + 1e-9 * w.f_norm
+        np.testing.assert_allclose(rec["rel_change"], w.rel_change, rtol=1e-5, atol=1e-9)
+    for n, (got, want) in enumerate(zip(r.factors(), A_w)):
+        np.testing.assert_allclose(got, want, atol=1e-8, rtol=0, err_msg=f"A^({n})")
+    assert_rel(r.core(), G_w, 1e-8, "core")
+
+
+def test_pp_operators_and_rhs_match_oracle():
+    """Build at the HOSVD factors, one PP-init sweep (which sets dA), then the
+    first-order TTMc of every mode against the oracle's from the same dA."""
+    shape, R = (60, 52, 47), 8
+    r = TRun(shape, R, seed=9, eta=0.2)
+    A0, G0 = ot.hosvd(r.prob.X, (R, R, R))
+    A1, G1, _ = ot.tucker_als(r.prob.X, A0, G0, 1)
+    r.upload(A1, G1)
+    pk.tucker_pp_build(r.plan, r.ws, r.X, r.A)
+    st = ot.build_operators(r.prob.X, A1)
+    # zero perturbation: the approximated TTMc is the exact one at A_p
+    for n in range(3):
+        Y = to_dev(np.zeros((shape[n], R, R)))
+        pk.tucker_pp_rhs(r.plan, r.ws, n, Y)
+        want = lib_layout(ot.pp_rhs(st, n), n)
+        assert_rel(host(Y, want.shape), want, 1e-12, f"Y_p^({n})")
+    rec = pk.tucker_pp_sweep(r.plan, r.ws, r.A, r.G, r.normX2, "pp_init")
+    A_or = [a.copy() for a in A1]
+    _, rec_w = ot.pp_sweep(st, A_or, G1, r.normX2, "pp_init")
+    assert rec["kind"] == "pp_init"
+    assert abs(rec["fit"] - rec_w.fit) <= 1e-10
+    # the oracle's dA and the library's agree to the factor tolerance; compare the rhs
+    # with the oracle evaluated at the library's dA
+    st.dA = [got - ap for got, ap in zip(r.factors(), A1)]
+    for n in range(3):
+        Y = to_dev(np.zeros((shape[n], R, R)))
+        pk.tucker_pp_rhs(r.plan, r.ws, n, Y)
+        want = lib_layout(ot.pp_rhs(st, n), n)
+        assert_rel(host(Y, want.shape), want, 1e-11, f"Y~^({n})")
+    for n, (got, want) in enumerate(zip(r.factors(), A_or)):
+        np.testing.assert_allclose(got, want, atol=1e-8, rtol=0, err_msg=f"A^({n})")
+
+
+@pytest.mark.parametrize("shape,R,sweeps", [((48, 44, 40), 6, 14), ((120, 110, 100), 12, 12)])
+def test_pp_tucker_run_matches_oracle(shape, R, sweeps):
+    """Algorithm 4 with eps = 0.3 (the paper's Tucker setting): the library's own
+    decisions give the oracle's sweep-kind sequence, and the replayed path ends at the
+    oracle's factors and core; every record's fit within 1e-10."""
+    r = TRun(shape, R, seed=11, eta=0.05)
+    A0, G0 = ot.hosvd(r.prob.X, (R, R, R))
+    A_w, G_w, recs_w = ot.pp_tucker_als(r.prob.X, A0, G0, eps=0.3, sweeps=sweeps)
+    kinds_w = [w.kind for w in recs_w]
+    assert "pp_approx" in kinds_w
+    r.upload(A0, G0)
+    recs = pk.tucker_run(r.plan, r.ws, r.X, r.A, r.G, eps=0.3, sweeps=sweeps)
+    assert [x["kind"] for x in recs] == kinds_w
+    for x, w in zip(recs, recs_w):
+        assert abs(x["fit"] - w.fit) <= 1e-10, (x, w.fit)
+    for n, (got, want) in enumerate(zip(r.factors(), A_w)):
+        np.testing.assert_allclose(got, want, atol=1e-8, rtol=0, err_msg=f"A^({n})")
+    assert_rel(r.core(), G_w, 1e-8, "core")
+    # replay of the same kinds from the start reproduces the free run
+    r.upload(A0, G0)
+    recs2 = pk.tucker_run(r.plan, r.ws, r.X, r.A, r.G, eps=0.3, sweeps=sweeps, replay=kinds_w)
+    assert [x["kind"] for x in recs2] == kinds_w
+    for n, (got, want) in enumerate(zip(r.factors(), A_w)):
+        np.testing.assert_allclose(got, want, atol=1e-8, rtol=0, err_msg=f"replay A^({n})")
+
+
+def test_eps_zero_is_hooi():
+    shape, R = (40, 38, 36), 5
+    r = TRun(shape, R, seed=13, eta=0.1)
+    A0, G0 = ot.hosvd(r.prob.X, (R, R, R))
+    A_w, G_w, _ = ot.tucker_als(r.prob.X, A0, G0, 5)
+    r.upload(A0, G0)
+    recs = pk.tucker_run(r.plan, r.ws, r.X, r.A, r.G, eps=0.0, sweeps=5)
+    assert [x["kind"] for x in recs] == ["als"] * 5
+    for got, want in zip(r.factors(), A_w):
+        np.testing.assert_allclose(got, want, atol=1e-8, rtol=0)
+
+
+def test_pp_sweep_needs_a_build():
+    shape, R = (20, 18, 16), 3
+    r = TRun(shape, R, seed=15)
+    A0, G0 = ot.hosvd(r.prob.X, (R, R, R))
+    r.upload(A0, G0)
+    with pytest.raises(pk.PPALSError) as e:
+        pk.tucker_pp_sweep(r.plan, r.ws, r.A, r.G, r.normX2)
+    assert e.value.status == -5
