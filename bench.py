@@ -46,7 +46,10 @@ PAPER_NUMBERS = {
     "pp_approx_vs_dt_sweep": {"order3_R_eq_s": 6.3, "orders3to6_R50": 33.0},
     "pp_init_over_dt_sweep": [1.5, 2.0],
     "time_to_solution_collinear_synthetic": 2.0,
-    "source": "Section 5.1 (per-sweep comparison and synthetic collinearity experiments)",
+    "tucker_pp_approx_vs_hooi_sweep_order6_R5": 10.6,
+    "tucker_time_to_solution_images": [1.05, 1.13],
+    "source": "Section 5.1 (per-sweep comparison, synthetic collinearity and image-data "
+              "experiments)",
 }
 
 
@@ -467,6 +470,113 @@ def c3_level1_leg(pp, torch, dev, tensorgen, reps=5):
     return out
 
 
+def tucker_leg(pp, torch, dev, tensorgen, s=800, R=40, eta=0.1, eps=0.3, sweeps=12, reps=3,
+               cpu_seconds=0.0):
+    """Order-3 Tucker (Algorithms 2 and 4) on an s^3 FP64 planted Tucker tensor (orthonormal
+    factors, N(0,1) core of rank R = 0.05 s, noise eta): HOSVD from seeded random bases,
+    the mean time of HOOI, PP-initialisation and PP-approximated sweeps, the TTMc
+    contraction rate, and whole runs of `sweeps` sweeps of HOOI (eps = 0) and
+    PP-Tucker-ALS (eps) from the same HOSVD."""
+    from oracle import tucker as ot
+    shape = (s, s, s)
+    t0 = time.perf_counter()
+    prob = tensorgen.make_tucker_problem(shape, (R, R, R), seed=0, eta=eta)
+    log(f"Tucker: generated {shape} rank-{R} in {time.perf_counter() - t0:.1f} s")
+    plan = pp.TuckerPlan(shape, R)
+    X = torch.from_numpy(prob.X.reshape(-1)).to(dev)
+    ws = plan.workspace(dev)
+    normX2 = float(np.sum(prob.X ** 2))
+    V0 = [torch.from_numpy(v).to(dev) for v in tensorgen.subspace_start(shape, R, seed=1)]
+    A = [torch.empty(n * R, dtype=torch.float64, device=dev) for n in shape]
+    G = torch.empty(R ** 3, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hinfo = pp.tucker_hosvd(plan, ws, X, V0, A, G)
+    hosvd_ms = (time.perf_counter() - t0) * 1e3
+    A0 = [a.clone() for a in A]
+    G0 = G.clone()
+    out = {"workload": f"Tucker, {s}^3 FP64 planted rank ({R},{R},{R}) orthonormal factors, "
+                       f"N(0,1) core, {eta:g} noise; R = 0.05 s as in the paper's order-3 "
+                       f"per-sweep comparison; eps = {eps}",
+           "hosvd_ms": hosvd_ms, "hosvd_iterations": [h[0] for h in hinfo]}
+
+    def reset():
+        for a, a0 in zip(A, A0):
+            a.copy_(a0)
+        G.copy_(G0)
+
+    # per-sweep times (each call synchronises; ms is the host wall time of the sweep)
+    reset()
+    als = [pp.tucker_als_sweep(plan, ws, X, A, G, normX2) for _ in range(reps + 1)][1:]
+    pp.tucker_pp_build(plan, ws, X, A)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pp.tucker_pp_build(plan, ws, X, A)
+    init = pp.tucker_pp_sweep(plan, ws, A, G, normX2, "pp_init")
+    init_ms = (time.perf_counter() - t0) * 1e3
+    appr = [pp.tucker_pp_sweep(plan, ws, A, G, normX2, "pp_approx") for _ in range(reps)]
+    mean = lambda xs: float(sum(xs) / len(xs))
+    als_ms = mean([r["ms"] for r in als])
+    appr_ms = mean([r["ms"] for r in appr])
+    out["per_sweep_ms"] = {"hooi": als_ms, "pp_init": init_ms, "pp_approx": appr_ms}
+    out["pp_approx_speedup_vs_hooi_sweep"] = als_ms / appr_ms
+    out["pp_init_over_hooi_sweep"] = init_ms / als_ms
+    out["subspace_iterations"] = {"hooi": [r["iters"] for r in als],
+                                  "pp_approx": [r["iters"] for r in appr]}
+    # TTMc rate: Y^(1) = (X x_3 A3^T) x_2 A2^T, 2 s^3 R + 2 s^2 R^2 flops, X read once
+    Y = torch.empty(s * R * R, dtype=torch.float64, device=dev)
+    pp.tucker_ttmc(plan, ws, X, A, 0, Y)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        pp.tucker_ttmc(plan, ws, X, A, 0, Y)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ttmc_ms = ev[0].elapsed_time(ev[1]) / reps
+    flops = 2.0 * s ** 3 * R + 2.0 * s ** 2 * R * R
+    out["ttmc_mode1"] = {"avg_ms": ttmc_ms, "TFLOP_s": flops / (ttmc_ms * 1e-3) / 1e12,
+                         "mfma_frac": flops / (ttmc_ms * 1e-3) / 1e12 / PEAK["f64_TFs"],
+                         "HBM_GB_s": 8.0 * s ** 3 / (ttmc_ms * 1e-3) / 1e9}
+    # whole runs from the HOSVD
+    runs = {}
+    for name, e in (("hooi", 0.0), ("pp", eps)):
+        reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        recs = pp.tucker_run(plan, ws, X, A, G, eps=e, sweeps=sweeps)
+        runs[name] = {"seconds": time.perf_counter() - t0,
+                      "kinds": [r["kind"] for r in recs],
+                      "fit": [r["fit"] for r in recs],
+                      "ms": [r["ms"] for r in recs]}
+    out["runs"] = {k: {"seconds": v["seconds"], "final_fit": v["fit"][-1],
+                       "kinds": {kk: v["kinds"].count(kk) for kk in set(v["kinds"])}}
+                   for k, v in runs.items()}
+    out["pp_vs_hooi_run_speedup"] = runs["hooi"]["seconds"] / runs["pp"]["seconds"]
+    out["final_fit_diff_pp_vs_hooi"] = runs["pp"]["fit"][-1] - runs["hooi"]["fit"][-1]
+    log(f"Tucker {s}^3 R {R}: HOSVD {hosvd_ms:.0f} ms; sweep HOOI {als_ms:.2f} ms, PP init "
+        f"{init_ms:.2f} ms, PP approx {appr_ms:.2f} ms ({als_ms / appr_ms:.2f}x); TTMc "
+        f"{out['ttmc_mode1']['TFLOP_s']:.1f} TF/s; runs HOOI {runs['hooi']['seconds']:.3f} s, "
+        f"PP {runs['pp']['seconds']:.3f} s")
+    if cpu_seconds > 0:
+        # float64 oracle: HOOI sweeps on the same tensor from the oracle's own HOSVD
+        t0 = time.perf_counter()
+        Ao, Go = ot.hosvd(prob.X, (R, R, R))
+        t_hosvd = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        n = 0
+        while n < 1 or (time.perf_counter() - t0 < cpu_seconds and n < 5):
+            Go, _, _ = ot.tucker_sweep(prob.X, Ao, Go, normX2)
+            n += 1
+        per = (time.perf_counter() - t0) / n
+        out["cpu_oracle"] = {"hooi_sweep_s": per, "hosvd_s": t_hosvd, "sweeps": n,
+                             "threads": torch.get_num_threads(),
+                             "gpu_hooi_sweep_speedup": per / (als_ms * 1e-3)}
+        log(f"Tucker oracle: HOSVD {t_hosvd:.1f} s, HOOI sweep {per:.2f} s")
+    del X, ws, Y
+    torch.cuda.empty_cache()
+    return out
+
+
 def ablation_bench(args, torch, dev):
     """The second-order correction ablation of the synthetic collinearity experiments
     (Section 5.1): fit against time for dimension-tree ALS, PP with the second-order
@@ -635,7 +745,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dt", action="store_true")
-    ap.add_argument("--workload", default="pp", choices=["pp", "batch", "ablation"],
+    ap.add_argument("--workload", default="pp", choices=["pp", "batch", "ablation", "tucker"],
                     help="pp: the 800^3 decomposition (default); batch: 512 independent problems; "
                          "ablation: PP with and without the second-order term against DT-ALS")
     ap.add_argument("--abl-size", type=int, default=64)
@@ -672,6 +782,13 @@ def main():
         return
     if args.workload == "ablation":
         ablation_bench(args, torch, dev)
+        return
+    if args.workload == "tucker":
+        s = args.size
+        R = args.rank if args.rank != 50 else max(1, round(0.05 * s))
+        out = tucker_leg(pp, torch, dev, tensorgen, s=s, R=R,
+                         cpu_seconds=0.0 if args.no_cpu_baseline else args.cpu_seconds)
+        print(json.dumps(out), flush=True)
         return
     s, R = args.size, args.rank
     shape = (s,) * args.order

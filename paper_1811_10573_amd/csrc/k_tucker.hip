@@ -26,12 +26,14 @@ namespace ppk {
 // ---------------------------------------------------------------------------
 constexpr int GT = 64, GK = 16;
 
-__global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g, int64_t kchunk) {
+__global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g, int64_t kchunk, int nz) {
   __shared__ double As[GK][GT + 1];
   __shared__ double Bs[GK][GT + 1];
   const int tid = threadIdx.x;
   const int64_t m0 = (int64_t)blockIdx.y * GT, n0 = (int64_t)blockIdx.x * GT;
-  const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+  const int split = (int)blockIdx.z % nz, batch = (int)blockIdx.z / nz;
+  const double* Bp = g.B + batch * g.sbb;
+  const int64_t kbeg = (int64_t)split * kchunk;
   const int64_t kend = kbeg + kchunk < g.K ? kbeg + kchunk : g.K;
   const int tm = (tid / 16) * 4, tn = (tid % 16) * 4;
   const bool a_kfast = g.kin ? g.sak2 == 1 : g.sak == 1;
@@ -54,7 +56,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g, int64_t kchunk) {
       const int nn = b_kfast ? e / GK : e % GT;
       const int64_t n = n0 + nn, k = k0 + kk;
       const int64_t kb = g.kin ? (k / g.kin) * g.sbk + (k % g.kin) * g.sbk2 : k * g.sbk;
-      Bs[kk][nn] = (n < g.N && k < kend) ? g.B[kb + n * g.sbn] : 0.0;
+      Bs[kk][nn] = (n < g.N && k < kend) ? Bp[kb + n * g.sbn] : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -71,7 +73,8 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g, int64_t kchunk) {
     }
     __syncthreads();
   }
-  double* C = g.ks > 1 ? g.part + (int64_t)blockIdx.z * g.M * g.N : g.C;
+  double* C = g.ks > 1 ? g.part + ((int64_t)split * g.nb + batch) * g.M * g.N
+                       : g.C + batch * g.M * g.N;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int64_t m = m0 + tm + i;
@@ -88,18 +91,20 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g, int64_t kchunk) {
 
 hipError_t launch_gemm_f64(const GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
-  if (g.ks > 1 && (g.alpha != 1.0 || g.beta != 0.0 || g.ldc != g.N || !g.part))
+  if (g.nb < 1 || (g.ks > 1 && (g.alpha != 1.0 || g.beta != 0.0 || !g.part)) ||
+      ((g.ks > 1 || g.nb > 1) && g.ldc != g.N))
     return hipErrorInvalidValue;
   const int ks = g.ks > 1 ? g.ks : 1;
   int64_t kchunk = (g.K + ks - 1) / ks;
   kchunk = (kchunk + GK - 1) / GK * GK;
   // splits that hold k-values (at most ks after the rounding of kchunk)
   const int nz = g.K > 0 ? (int)((g.K + kchunk - 1) / kchunk) : 1;
-  const dim3 grid((unsigned)((g.N + GT - 1) / GT), (unsigned)((g.M + GT - 1) / GT), (unsigned)nz);
-  hipLaunchKernelGGL(k_gemm_f64, grid, dim3(256), 0, s, g, g.K > 0 ? kchunk : (int64_t)0);
+  const dim3 grid((unsigned)((g.N + GT - 1) / GT), (unsigned)((g.M + GT - 1) / GT),
+                  (unsigned)(nz * g.nb));
+  hipLaunchKernelGGL(k_gemm_f64, grid, dim3(256), 0, s, g, g.K > 0 ? kchunk : (int64_t)0, nz);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || ks == 1) return e;
-  return launch_reduce_splits_to(g.C, 0, g.part, 0, nz, g.M * g.N, s);
+  return launch_reduce_splits_to(g.C, 0, g.part, 0, nz, g.nb * g.M * g.N, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -108,27 +113,66 @@ hipError_t launch_gemm_f64(const GemmArgs& g, hipStream_t s) {
 // cyclic Jacobi rotations (parallel round-robin pairing), decreasing lam, and
 // T = L^-T Q, so that V T are orthonormal Ritz vectors.  With P = V^T A_prev, column j
 // of T is negated when (V T)_j . A_prev_j = (T^T P)_jj < 0.
+//
+// The Cholesky factorisation takes one barrier per column (the trailing update reads
+// the unscaled pivot column while the scaled column goes to a second array), L^-1 is
+// formed column by column by quads of lanes, and the three products with L^-1 are
+// dense LDS products with 2 x 2 register blocks.
 // ---------------------------------------------------------------------------
 constexpr int RRS = 65;  // LDS row stride
 
+// out[a][b] = sum_k X(a, k) Y(k, b) for a, b < R with X(a, k) = Xs[a * xa + k * xk] and
+// Y(k, b) = Ys[k * yk + b * yb]; 2 x 2 outputs per thread.
+__device__ __forceinline__ void rr_product(double* out, const double* Xs, int xa, int xk,
+                                           const double* Ys, int yk, int yb, int R) {
+  const int Rh = (R + 1) / 2;
+  for (int e = threadIdx.x; e < Rh * Rh; e += blockDim.x) {
+    const int a0 = 2 * (e / Rh), b0 = 2 * (e % Rh);
+    const int a1 = a0 + 1 < R ? a0 + 1 : a0, b1 = b0 + 1 < R ? b0 + 1 : b0;
+    double c00 = 0.0, c01 = 0.0, c10 = 0.0, c11 = 0.0;
+    for (int k = 0; k < R; ++k) {
+      const double x0 = Xs[a0 * xa + k * xk], x1 = Xs[a1 * xa + k * xk];
+      const double y0 = Ys[k * yk + b0 * yb], y1 = Ys[k * yk + b1 * yb];
+      c00 = fma(x0, y0, c00);
+      c01 = fma(x0, y1, c01);
+      c10 = fma(x1, y0, c10);
+      c11 = fma(x1, y1, c11);
+    }
+    out[a0 * RRS + b0] = c00;
+    if (b1 != b0) out[a0 * RRS + b1] = c01;
+    if (a1 != a0) out[a1 * RRS + b0] = c10;
+    if (a1 != a0 && b1 != b0) out[a1 * RRS + b1] = c11;
+  }
+}
+
+// Sum of v over the workgroup (256 threads, four waves); every thread gets the total.
+__device__ __forceinline__ double rr_block_sum(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double t = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return t;
+}
+
 __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs a) {
-  __shared__ double L[64 * RRS];
-  __shared__ double H[64 * RRS];
-  __shared__ double Q[64 * RRS];
+  __shared__ double L[64 * RRS];   // B, trailing updates; later scratch (Z, T)
+  __shared__ double Lc[64 * RRS];  // Cholesky factor; later the Jacobi eigenvectors
+  __shared__ double Li[64 * RRS];  // L^-1 (lower)
+  __shared__ double H[64 * RRS];   // H, then H' (rotated in place)
   __shared__ double lam[64];
   __shared__ double cs[32], sn[32];
   __shared__ int pr[32], qr[32];
+  __shared__ double red[4];
   __shared__ int bad;
-  __shared__ double offn, diagn;
   const int tid = threadIdx.x;
   const int R = a.R;
   const int RP = R + (R & 1);  // even, for the round-robin pairing
   for (int e = tid; e < 64 * RRS; e += 256) {
-    L[e] = 0.0;
-    H[e] = 0.0;
-    Q[e] = 0.0;
+    Lc[e] = 0.0;
+    Li[e] = 0.0;
   }
-  __syncthreads();
   for (int e = tid; e < R * R; e += 256) {
     const int i = e / R, k = e - i * R;
     L[i * RRS + k] = a.B[e];
@@ -136,47 +180,48 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs a) {
   }
   if (tid == 0) bad = 0;
   __syncthreads();
-  // Cholesky of B (lower, in place)
+  // Cholesky of B: Lc = L with L L^T = B (lower)
   for (int j = 0; j < R; ++j) {
-    if (tid == 0) {
-      const double d = L[j * RRS + j];
-      if (!(d > 0.0) || !isfinite(d)) bad = 1;
-      L[j * RRS + j] = sqrt(d > 0.0 ? d : 1.0);
-    }
-    __syncthreads();
-    const double inv = 1.0 / L[j * RRS + j];
-    for (int i = j + 1 + tid; i < R; i += 256) L[i * RRS + j] *= inv;
-    __syncthreads();
+    const double d0 = L[j * RRS + j];
+    const bool ok = d0 > 0.0 && isfinite(d0);
+    if (tid == 0 && !ok) bad = 1;
+    const double d = ok ? d0 : 1.0;
+    const double inv_sd = 1.0 / sqrt(d);
+    const double inv_d = 1.0 / d;
     const int m = R - j - 1;
     for (int e = tid; e < m * m; e += 256) {
       const int ii = e / m, kk = e - ii * m;
       if (kk <= ii) {
         const int i = j + 1 + ii, k = j + 1 + kk;
-        L[i * RRS + k] -= L[i * RRS + j] * L[k * RRS + j];
+        L[i * RRS + k] -= L[i * RRS + j] * L[k * RRS + j] * inv_d;
       }
     }
+    for (int i = j + tid; i < R; i += 256) Lc[i * RRS + j] = (i == j) ? sqrt(d) : L[i * RRS + j] * inv_sd;
     __syncthreads();
   }
-  // Z = L^-1 H (column j by thread j), then H' = L^-1 Z^T (symmetric)
-  if (tid < R) {
-    const int j = tid;
-    for (int i = 0; i < R; ++i) {
-      double z = H[i * RRS + j];
-      for (int k = 0; k < i; ++k) z -= L[i * RRS + k] * Q[k * RRS + j];
-      Q[i * RRS + j] = z / L[i * RRS + i];
+  // Li = Lc^-1, column j by the quad of lanes 4j..4j+3 (k split by k mod 4)
+  {
+    const int j = tid >> 2, l = tid & 3;
+    if (j < R) {
+      if (l == 0) Li[j * RRS + j] = 1.0 / Lc[j * RRS + j];
+      for (int i = j + 1; i < R; ++i) {
+        double s = 0.0;
+        for (int k = j + l; k < i; k += 4) s = fma(Lc[i * RRS + k], Li[k * RRS + j], s);
+        s += __shfl_xor(s, 1);
+        s += __shfl_xor(s, 2);
+        // every lane of the quad has the sum; lane (i - j) mod 4 stores it and is the only
+        // lane that reads it again (k - j = l mod 4 above), later in program order
+        if (l == ((i - j) & 3)) Li[i * RRS + j] = -s / Lc[i * RRS + i];
+      }
     }
   }
   __syncthreads();
-  if (tid < R) {
-    const int j = tid;  // column j of H' = L^-1 (row j of Z)^T
-    for (int i = 0; i < R; ++i) {
-      double z = Q[j * RRS + i];
-      for (int k = 0; k < i; ++k) z -= L[i * RRS + k] * H[k * RRS + j];
-      H[i * RRS + j] = z / L[i * RRS + i];
-    }
-  }
+  // H' = Li H Li^T: Z = Li H into L, then H = Z Li^T
+  rr_product(L, Li, RRS, 1, H, RRS, 1, R);
   __syncthreads();
-  for (int e = tid; e < R * R; e += 256) {  // symmetrise, eigenvectors start at I
+  rr_product(H, L, RRS, 1, Li, 1, RRS, R);
+  __syncthreads();
+  for (int e = tid; e < R * R; e += 256) {  // symmetrise; eigenvectors start at I
     const int i = e / R, k = e - i * R;
     if (k < i) {
       const double v = 0.5 * (H[i * RRS + k] + H[k * RRS + i]);
@@ -184,25 +229,23 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs a) {
       H[k * RRS + i] = v;
     }
   }
-  for (int e = tid; e < 64 * RRS; e += 256) Q[e] = 0.0;
+  for (int e = tid; e < 64 * RRS; e += 256) Lc[e] = 0.0;
   __syncthreads();
+  double* Q = Lc;
   for (int i = tid; i < R; i += 256) Q[i * RRS + i] = 1.0;
   __syncthreads();
   // cyclic Jacobi, round-robin pairs (index RP-1 fixed, the others rotate)
   int sweep = 0;
   for (; sweep < 40; ++sweep) {
-    if (tid == 0) {
-      double o = 0.0, d = 0.0;
-      for (int i = 0; i < R; ++i)
-        for (int k = 0; k < R; ++k) {
-          const double v = H[i * RRS + k];
-          if (i == k) d += v * v;
-          else o += v * v;
-        }
-      offn = o;
-      diagn = d;
+    double o = 0.0, dg = 0.0;
+    for (int e = tid; e < R * R; e += 256) {
+      const int i = e / R, k = e - i * R;
+      const double v = H[i * RRS + k];
+      if (i == k) dg = fma(v, v, dg);
+      else o = fma(v, v, o);
     }
-    __syncthreads();
+    const double offn = rr_block_sum(o, red);
+    const double diagn = rr_block_sum(dg, red);
     if (!(offn > 1e-30 * diagn)) break;
     for (int round = 0; round < RP - 1; ++round) {
       if (tid < RP / 2) {
@@ -239,27 +282,37 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs a) {
         sn[tid] = s;
       }
       __syncthreads();
-      // rows: H <- J^T H
-      for (int e = tid; e < (RP / 2) * R; e += 256) {
-        const int w = e / R, k = e - w * R;
-        const int p = pr[w], q = qr[w];
-        if (q < R) {
-          const double c = cs[w], s = sn[w];
-          const double hp = H[p * RRS + k], hq = H[q * RRS + k];
-          H[p * RRS + k] = c * hp - s * hq;
-          H[q * RRS + k] = s * hp + c * hq;
-        }
+      // H <- J^T H J one 2 x 2 block (rows of pair w1, columns of pair w2) per step: the
+      // pairs of a round partition the indices, so the blocks are disjoint.  A pair whose
+      // partner is the padding index R has a single row or column.
+      const int np = RP / 2;
+      for (int e = tid; e < np * np; e += 256) {
+        const int w1 = e / np, w2 = e - w1 * np;
+        const double s1 = sn[w1], s2 = sn[w2];
+        if (s1 == 0.0 && s2 == 0.0) continue;
+        const double c1 = cs[w1], c2 = cs[w2];
+        const int p1 = pr[w1], q1 = qr[w1], p2 = pr[w2], q2 = qr[w2];
+        const bool r1 = q1 < R, r2 = q2 < R;
+        const double hpp = H[p1 * RRS + p2];
+        const double hpq = r2 ? H[p1 * RRS + q2] : 0.0;
+        const double hqp = r1 ? H[q1 * RRS + p2] : 0.0;
+        const double hqq = (r1 && r2) ? H[q1 * RRS + q2] : 0.0;
+        // rows: p' = c1 p - s1 q, q' = s1 p + c1 q
+        const double app = c1 * hpp - s1 * hqp, apq = c1 * hpq - s1 * hqq;
+        const double aqp = s1 * hpp + c1 * hqp, aqq = s1 * hpq + c1 * hqq;
+        // columns: p' = c2 p - s2 q, q' = s2 p + c2 q
+        H[p1 * RRS + p2] = c2 * app - s2 * apq;
+        if (r2) H[p1 * RRS + q2] = s2 * app + c2 * apq;
+        if (r1) H[q1 * RRS + p2] = c2 * aqp - s2 * aqq;
+        if (r1 && r2) H[q1 * RRS + q2] = s2 * aqp + c2 * aqq;
       }
-      __syncthreads();
-      // columns: H <- H J, eigenvectors Q <- Q J
-      for (int e = tid; e < (RP / 2) * R; e += 256) {
-        const int w = e / R, k = e - w * R;
-        const int p = pr[w], q = qr[w];
-        if (q < R) {
-          const double c = cs[w], s = sn[w];
-          const double hp = H[k * RRS + p], hq = H[k * RRS + q];
-          H[k * RRS + p] = c * hp - s * hq;
-          H[k * RRS + q] = s * hp + c * hq;
+      // eigenvectors Q <- Q J
+      for (int e = tid; e < np * R; e += 256) {
+        const int k = e / np, w = e - k * np;
+        const double s = sn[w];
+        if (s != 0.0) {
+          const int p = pr[w], q = qr[w];
+          const double c = cs[w];
           const double vp = Q[k * RRS + p], vq = Q[k * RRS + q];
           Q[k * RRS + p] = c * vp - s * vq;
           Q[k * RRS + q] = s * vp + c * vq;
@@ -268,32 +321,24 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs a) {
       __syncthreads();
     }
   }
-  // decreasing order: rank of each eigenvalue (ties by index)
+  // T = Li^T Q into L
   if (tid < R) lam[tid] = H[tid * RRS + tid];
+  rr_product(L, Li, 1, RRS, Q, RRS, 1, R);
   __syncthreads();
-  int pos = 0;
-  if (tid < R) {
-    const double v = lam[tid];
-    for (int k = 0; k < R; ++k) pos += (lam[k] > v) || (lam[k] == v && k < tid);
-  }
-  __syncthreads();
-  // T = L^-T Q (column j by thread j) written to its sorted position
+  // decreasing order (ties by index), sign against A_prev, written to sorted position
   if (tid < R) {
     const int j = tid;
-    double t[64];
-    for (int i = R - 1; i >= 0; --i) {
-      double z = Q[i * RRS + j];
-      for (int k = i + 1; k < R; ++k) z -= L[k * RRS + i] * t[k];
-      t[i] = z / L[i * RRS + i];
-    }
+    const double v = lam[j];
+    int pos = 0;
+    for (int k = 0; k < R; ++k) pos += (lam[k] > v) || (lam[k] == v && k < j);
     double sgn = 1.0;
     if (a.P) {
       double d = 0.0;
-      for (int m = 0; m < R; ++m) d += t[m] * a.P[m * R + pos];  // the column it replaces
+      for (int m = 0; m < R; ++m) d = fma(L[m * RRS + j], a.P[m * R + pos], d);  // the column it replaces
       sgn = d < 0.0 ? -1.0 : 1.0;
     }
-    for (int i = 0; i < R; ++i) a.T[i * R + pos] = sgn * t[i];
-    a.lam[pos] = lam[j];
+    for (int i = 0; i < R; ++i) a.T[i * R + pos] = sgn * L[i * RRS + j];
+    a.lam[pos] = v;
   }
   if (tid == 0) {
     a.status[0] = bad;
@@ -302,41 +347,82 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs a) {
 }
 
 hipError_t launch_rayleigh_ritz(const RRArgs& a, hipStream_t s) {
+  if (a.R < 1 || a.R > 64) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_rayleigh_ritz, dim3(1), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
-// max_j ||C_j - lam_j V_j|| / lam_0 (one workgroup); C = W V.
-__global__ __launch_bounds__(256) void k_ritz_residual(const double* __restrict__ C,
-                                                       const double* __restrict__ V,
-                                                       const double* __restrict__ lam, int64_t rows,
-                                                       int R, double* out) {
-  __shared__ double red[256];
-  double mx = 0.0;
-  for (int j = 0; j < R; ++j) {
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < rows; i += 256) {
-      const double d = C[i * R + j] - lam[j] * V[i * R + j];
-      s = fma(d, d, s);
-    }
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-      __syncthreads();
-    }
-    mx = fmax(mx, red[0]);
-    __syncthreads();
+// Ritz update over a block of RU rows: U = V T (the Ritz vectors), CT = C T (W applied
+// to them), the per-column partial sums of ||CT_j - lam_j U_j||^2 into part[block][j],
+// and V <- CT diag(lam)^-1 (the next basis; columns with lam_j = 0 keep CT_j).
+constexpr int RU = 32;
+
+__global__ __launch_bounds__(256) void k_ritz_update(double* V, const double* C, const double* T,
+                                                     const double* lam, double* U, double* part,
+                                                     int64_t rows, int R) {
+  __shared__ double Ts[64 * 64];
+  __shared__ double Vs[RU * 65], Cs[RU * 65], D[RU * 65];
+  __shared__ double ls[64];
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * RU;
+  const int nr = (int)((rows - r0) < RU ? (rows - r0) : RU);
+  for (int e = tid; e < R * R; e += 256) Ts[e] = T[e];
+  if (tid < R) ls[tid] = lam[tid];
+  for (int e = tid; e < RU * R; e += 256) {
+    const int i = e / R, j = e - i * R;
+    const bool ok = i < nr;
+    Vs[i * 65 + j] = ok ? V[(r0 + i) * R + j] : 0.0;
+    Cs[i * 65 + j] = ok ? C[(r0 + i) * R + j] : 0.0;
   }
-  if (threadIdx.x == 0) {
-    const double l0 = fabs(lam[0]) > 0.0 ? fabs(lam[0]) : 1.0;
-    *out = sqrt(mx) / l0;
+  __syncthreads();
+  for (int e = tid; e < RU * R; e += 256) {
+    const int i = e / R, j = e - i * R;
+    double u = 0.0, ct = 0.0;
+    for (int m = 0; m < R; ++m) {
+      const double t = Ts[m * R + j];
+      u = fma(Vs[i * 65 + m], t, u);
+      ct = fma(Cs[i * 65 + m], t, ct);
+    }
+    const double d = ct - ls[j] * u;
+    D[i * 65 + j] = i < nr ? d * d : 0.0;
+    if (i < nr) {
+      U[(r0 + i) * R + j] = u;
+      V[(r0 + i) * R + j] = ls[j] != 0.0 ? ct / ls[j] : ct;
+    }
+  }
+  __syncthreads();
+  if (tid < R) {
+    double s = 0.0;
+    for (int i = 0; i < RU; ++i) s += D[i * 65 + tid];
+    part[(int64_t)blockIdx.x * R + tid] = s;
   }
 }
 
-hipError_t launch_ritz_residual(const double* C, const double* V, const double* lam, int64_t rows,
-                                int R, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_ritz_residual, dim3(1), dim3(256), 0, s, C, V, lam, rows, R, out);
+// max_j sqrt(sum_b part[b][j]) / |lam_0| (one workgroup, blocks in a fixed order).
+__global__ __launch_bounds__(64) void k_ritz_residual(const double* part, int nblocks, int R,
+                                                      const double* lam, double* out) {
+  const int j = threadIdx.x;
+  double s = 0.0;
+  if (j < R)
+    for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * R + j];
+  double m = j < R ? sqrt(s) : 0.0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if (j == 0) {
+    const double l0 = fabs(lam[0]) > 0.0 ? fabs(lam[0]) : 1.0;
+    *out = m / l0;
+  }
+}
+
+hipError_t launch_ritz_update(double* V, const double* C, const double* T, const double* lam,
+                              double* U, double* part, int64_t rows, int R, double* residual,
+                              hipStream_t s) {
+  if (R < 1 || R > 64) return hipErrorInvalidValue;
+  const int nb = (int)((rows + RU - 1) / RU);
+  hipLaunchKernelGGL(k_ritz_update, dim3(nb), dim3(256), 0, s, V, C, T, lam, U, part, rows, R);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ritz_residual, dim3(1), dim3(64), 0, s, part, nb, R, lam, residual);
   return hipGetLastError();
 }
 
@@ -398,25 +484,6 @@ __global__ __launch_bounds__(256) void k_pp_tucker_combine(double* out, const do
   }
 }
 
-// out[i][j] = in[i][j] / lam[j] (columns with lam[j] = 0 are copied).
-__global__ __launch_bounds__(256) void k_scale_cols(double* out, const double* in,
-                                                    const double* lam, int64_t rows, int R) {
-  const int64_t n = rows * R;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
-    const double l = lam[e % R];
-    out[e] = l != 0.0 ? in[e] / l : in[e];
-  }
-}
-
-hipError_t launch_scale_cols(double* out, const double* in, const double* lam, int64_t rows, int R,
-                             hipStream_t s) {
-  int64_t blocks = (rows * R + 255) / 256;
-  if (blocks > 1024) blocks = 1024;
-  hipLaunchKernelGGL(k_scale_cols, dim3((unsigned)std::max<int64_t>(1, blocks)), dim3(256), 0, s,
-                     out, in, lam, rows, R);
-  return hipGetLastError();
-}
-
 hipError_t launch_pp_tucker_combine(double* out, const double* Yp, const double* T1,
                                     const double* T2, int64_t rows, int R, hipStream_t s) {
   const int64_t n = rows * (int64_t)R * R;
@@ -427,36 +494,46 @@ hipError_t launch_pp_tucker_combine(double* out, const double* Yp, const double*
   return hipGetLastError();
 }
 
-// Core statistics: out[0] = ||Gn||^2, out[1] = ||Gn - Go||^2 (one workgroup).
-__global__ __launch_bounds__(256) void k_core_stats(const double* Gn, const double* Go, int64_t n,
-                                                    double* out) {
-  __shared__ double r0[256], r1[256];
+// Norm statistics: out[0] = ||Gn||^2, out[1] = ||Gn - Go||^2 (one workgroup of 1024
+// threads, two elements per thread and step; a fixed reduction order).
+__global__ __launch_bounds__(1024) void k_core_stats(const double* Gn, const double* Go, int64_t n,
+                                                     double* out) {
+  __shared__ double r0[16], r1[16];
   double a = 0.0, b = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) {
-    const double g = Gn[i];
-    const double d = g - Go[i];
-    a = fma(g, g, a);
-    b = fma(d, d, b);
-  }
-  r0[threadIdx.x] = a;
-  r1[threadIdx.x] = b;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      r0[threadIdx.x] += r0[threadIdx.x + w];
-      r1[threadIdx.x] += r1[threadIdx.x + w];
+  for (int64_t i = threadIdx.x; i < n; i += 2048) {
+    const double g0 = Gn[i], d0 = g0 - Go[i];
+    double g1 = 0.0, d1 = 0.0;
+    if (i + 1024 < n) {
+      g1 = Gn[i + 1024];
+      d1 = g1 - Go[i + 1024];
     }
-    __syncthreads();
+    a = fma(g0, g0, fma(g1, g1, a));
+    b = fma(d0, d0, fma(d1, d1, b));
   }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o);
+    b += __shfl_xor(b, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    r0[threadIdx.x >> 6] = a;
+    r1[threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    out[0] = r0[0];
-    out[1] = r1[0];
+    double sa = 0.0, sb = 0.0;
+    for (int w = 0; w < 16; ++w) {
+      sa += r0[w];
+      sb += r1[w];
+    }
+    out[0] = sa;
+    out[1] = sb;
   }
 }
 
 hipError_t launch_core_stats(const double* Gn, const double* Go, int64_t n, double* out,
                              hipStream_t s) {
-  hipLaunchKernelGGL(k_core_stats, dim3(1), dim3(256), 0, s, Gn, Go, n, out);
+  hipLaunchKernelGGL(k_core_stats, dim3(1), dim3(1024), 0, s, Gn, Go, n, out);
   return hipGetLastError();
 }
 

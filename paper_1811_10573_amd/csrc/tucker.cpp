@@ -56,8 +56,9 @@ struct tucker_plan {
   int hosvd_iters = 5000;
   // workspace regions (byte offsets)
   size_t o_T3, o_T1, o_op01, o_op02, o_op12, o_Yp[3], o_Y, o_Ta, o_Tb, o_Gn, o_Ap[3], o_dA[3],
-      o_Aold, o_V, o_C, o_U, o_CT, o_Z, o_B, o_H, o_P, o_T, o_lam, o_info, o_stats, o_prep, o_part,
-      o_gpart, o_W;
+      o_Aold, o_V, o_C, o_U, o_Z, o_B, o_H, o_P, o_T, o_lam, o_info, o_stats, o_prep, o_part,
+      o_gpart, o_W, o_rpart;
+  size_t slot = 0;  // bytes between the basis slots V, C, A_prev
   size_t ws_bytes = 0;
   bool built = false;
   bool dA_zero[3] = {true, true, true};
@@ -128,33 +129,26 @@ GemmArgs gemm_args(const double* A, const double* B, double* C, int64_t M, int64
   g.alpha = 1.0;
   g.beta = 0.0;
   g.ks = 1;
+  g.nb = 1;
   return g;
 }
 
 constexpr int kMaxGemmSplit = 32;
 
-// C (R x R) = V^T F with V, F both rows x R
-ppals_status gram_tn(const TCtx& c, const double* V, const double* F, int64_t rows, double* C) {
+// The projections of the Rayleigh-Ritz step in one launch: V^T V, V^T C and (nb = 3)
+// V^T A_prev into the consecutive R x R blocks B, H, P.  V, C and A_prev are the
+// consecutive slots of the basis region.
+ppals_status projections(const TCtx& c, int64_t rows, int nb) {
   const int R = c.p->R;
-  GemmArgs g = gemm_args(V, F, C, R, R, rows);
+  GemmArgs g = gemm_args(c.d(c.p->o_V), c.d(c.p->o_V), c.d(c.p->o_B), R, R, rows);
   g.sam = 1;
   g.sak = R;
   g.sbk = R;
   g.sbn = 1;
+  g.nb = nb;
+  g.sbb = (int64_t)(c.p->slot / sizeof(double));
   g.ks = (int)std::min<int64_t>(kMaxGemmSplit, std::max<int64_t>(1, rows / kGemmSplitMin));
   g.part = c.d(c.p->o_gpart);
-  THIPCHK(launch_gemm_f64(g, c.s));
-  return PPALS_OK;
-}
-
-// C (rows x R) = V (rows x R) T (R x R)
-ppals_status right_mul(const TCtx& c, const double* V, const double* T, int64_t rows, double* C) {
-  const int R = c.p->R;
-  GemmArgs g = gemm_args(V, T, C, rows, R, R);
-  g.sam = R;
-  g.sak = 1;
-  g.sbk = R;
-  g.sbn = 1;
   THIPCHK(launch_gemm_f64(g, c.s));
   return PPALS_OK;
 }
@@ -208,14 +202,12 @@ ppals_status subspace(const TCtx& c, int n, const double* Y, const double* Wexp,
   double* V = c.d(p->o_V);
   double* C = c.d(p->o_C);
   double* U = c.d(p->o_U);
-  double* CT = c.d(p->o_CT);
   double* Z = c.d(p->o_Z);
-  double* Bm = c.d(p->o_B);
-  double* H = c.d(p->o_H);
-  double* P = c.d(p->o_P);
   double* T = c.d(p->o_T);
   double* lam = c.d(p->o_lam);
+  double* Aold = c.d(p->o_Aold);
   IterInfo* dinfo = reinterpret_cast<IterInfo*>(c.ws + p->o_info);
+  if (A_prev && A_prev != Aold) THIPCHK(launch_copy(Aold, A_prev, sn * R, c.s));
   THIPCHK(launch_copy(V, V0, sn * R, c.s));
   IterInfo hinfo;
   memset(&hinfo, 0, sizeof(hinfo));
@@ -235,21 +227,18 @@ ppals_status subspace(const TCtx& c, int n, const double* Y, const double* Wexp,
       TCHK(ttm(c, Y, {1, sn, (int64_t)R * R}, V, Z));  // Z = Y^T V   (R^2 x R)
       TCHK(ttm(c, Y, {sn, (int64_t)R * R, 1}, Z, C));  // C = Y Z     (s_n x R)
     }
-    TCHK(gram_tn(c, V, V, sn, Bm));
-    TCHK(gram_tn(c, V, C, sn, H));
-    if (A_prev) TCHK(gram_tn(c, V, A_prev, sn, P));
+    TCHK(projections(c, sn, A_prev ? 3 : 2));
     RRArgs rr;
     rr.R = R;
-    rr.B = Bm;
-    rr.H = H;
-    rr.P = A_prev ? P : nullptr;
+    rr.B = c.d(p->o_B);
+    rr.H = c.d(p->o_H);
+    rr.P = A_prev ? c.d(p->o_P) : nullptr;
     rr.T = T;
     rr.lam = lam;
     rr.status = &dinfo->rr_bad;
     THIPCHK(launch_rayleigh_ritz(rr, c.s));
-    TCHK(right_mul(c, V, T, sn, U));   // Ritz vectors
-    TCHK(right_mul(c, C, T, sn, CT));  // W applied to them
-    THIPCHK(launch_ritz_residual(CT, U, lam, sn, R, &dinfo->residual, c.s));
+    // Ritz vectors U, the residual, and the next basis V <- W U diag(lam)^-1
+    THIPCHK(launch_ritz_update(V, C, T, lam, U, c.d(p->o_rpart), sn, R, &dinfo->residual, c.s));
     THIPCHK(hipMemcpyAsync(&hinfo, dinfo, sizeof(hinfo), hipMemcpyDeviceToHost, c.s));
     THIPCHK(hipStreamSynchronize(c.s));
     bad |= hinfo.rr_bad;
@@ -257,7 +246,6 @@ ppals_status subspace(const TCtx& c, int n, const double* Y, const double* Wexp,
       conv = true;
       break;
     }
-    if (it < max_iters) THIPCHK(launch_scale_cols(V, CT, lam, sn, R, c.s));  // next basis
   }
   THIPCHK(launch_copy(A_out, U, sn * R, c.s));
   if (!A_prev) THIPCHK(launch_sign_by_max(A_out, sn, R, c.s));
@@ -402,15 +390,18 @@ ppals_status tucker_plan_create(const int64_t dims[3], int32_t rank, tucker_plan
   p->o_Gn = take(R * R * R);
   for (int n = 0; n < 3; ++n) p->o_Ap[n] = take(dims[n] * R);
   for (int n = 0; n < 3; ++n) p->o_dA[n] = take(dims[n] * R);
-  p->o_Aold = take(smax * R);
+  // basis slots V, C, A_prev at equal spacing (one batched projection launch)
+  p->slot = al256((size_t)smax * R * sizeof(double));
   p->o_V = take(smax * R);
   p->o_C = take(smax * R);
+  p->o_Aold = take(smax * R);
   p->o_U = take(smax * R);
-  p->o_CT = take(smax * R);
   p->o_Z = take(R * R * R);
-  p->o_B = take(R * R);
-  p->o_H = take(R * R);
-  p->o_P = take(R * R);
+  // B, H, P consecutive R x R blocks
+  p->o_B = take(3 * R * R);
+  p->o_H = p->o_B + (size_t)R * R * sizeof(double);
+  p->o_P = p->o_H + (size_t)R * R * sizeof(double);
+  p->o_rpart = take(((smax + kRitzRows - 1) / kRitzRows) * R);
   p->o_T = take(R * R);
   p->o_lam = take(R);
   p->o_info = take(4);
@@ -423,7 +414,7 @@ ppals_status tucker_plan_create(const int64_t dims[3], int32_t rank, tucker_plan
   }
   p->o_prep = take(prep);
   p->o_part = take(std::max<size_t>(part, 1024));
-  p->o_gpart = take((size_t)kMaxGemmSplit * R * R);
+  p->o_gpart = take((size_t)kMaxGemmSplit * 3 * R * R);
   p->o_W = take(smax * smax);
   p->ws_bytes = off;
   *out = p;

@@ -18,10 +18,12 @@ struct GemmArgs {
   int64_t sak2;      //   A offset k_out * sak + k_in * sak2 and
   int64_t sbk2;      //   B offset k_out * sbk + k_in * sbk2
   int ks;            // K split over workgroups (>= 1); ks > 1 needs alpha 1, beta 0, ldc N
-  double* part;      //   and ks x M x N doubles of partial sums here
+  double* part;      //   and ks x nb x M x N doubles of partial sums here
+  int nb;            // batch of products sharing A (>= 1): B_x = B + x sbb, C_x = C + x M N
+  int64_t sbb;       //   (nb > 1 needs ldc N)
 };
 // Minimum k-values per split of launch_gemm_f64.
-constexpr int64_t kGemmSplitMin = 128;
+constexpr int64_t kGemmSplitMin = 32;
 hipError_t launch_gemm_f64(const GemmArgs& g, hipStream_t s);
 
 struct RRArgs {
@@ -34,11 +36,13 @@ struct RRArgs {
   int* status;       // [0] 1 if V^T V was not positive definite, [1] Jacobi sweeps
 };
 hipError_t launch_rayleigh_ritz(const RRArgs& a, hipStream_t s);
-hipError_t launch_ritz_residual(const double* C, const double* V, const double* lam, int64_t rows,
-                                int R, double* out, hipStream_t s);
+// U = V T, CT = C T, V <- CT diag(lam)^-1 and *residual = max_j ||CT_j - lam_j U_j|| / |lam_0|;
+// part holds ceil(rows / 32) x R doubles.
+constexpr int kRitzRows = 32;
+hipError_t launch_ritz_update(double* V, const double* C, const double* T, const double* lam,
+                              double* U, double* part, int64_t rows, int R, double* residual,
+                              hipStream_t s);
 hipError_t launch_sign_by_max(double* V, int64_t rows, int R, hipStream_t s);
-hipError_t launch_scale_cols(double* out, const double* in, const double* lam, int64_t rows, int R,
-                             hipStream_t s);
 hipError_t launch_pp_tucker_combine(double* out, const double* Yp, const double* T1,
                                     const double* T2, int64_t rows, int R, hipStream_t s);
 hipError_t launch_core_stats(const double* Gn, const double* Go, int64_t n, double* out,
