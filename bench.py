@@ -977,7 +977,7 @@ def main():
     # 64^3 ALS configuration and the first-level contractions of the 160^4 configuration
     extras = (not args.no_extras and args.tier == "f32" and shape == (800, 800, 800)
               and R == 50 and not args.device_gen)
-    f64 = c1 = c3 = batch = None
+    f64 = c1 = c3 = batch = tucker = None
     A_f64_replay = c1prob = None
     if extras:
         del ws
@@ -990,6 +990,8 @@ def main():
         batch = {k: bl[k] for k in ("value", "unit", "ms_per_step", "roofline", "batch")}
         batch["workload"] = bl["config"]["workload"]
         batch["batch"] = {k: v for k, v in batch["batch"].items() if k != "autotune"}
+        tucker = tucker_leg(pp, torch, dev, tensorgen, s=800, R=40,
+                            cpu_seconds=0.0 if args.no_cpu_baseline else 4.0)
 
     cpu = None
     vs_oracle = None
@@ -1076,6 +1078,7 @@ def main():
         "c1_als": c1,
         "c3_level1": c3,
         "c5_batch": batch,
+        "f1_tucker": tucker,
         "paper_reference": PAPER_NUMBERS,
         "kernels": kernels,
     }
