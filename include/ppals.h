@@ -78,7 +78,12 @@ typedef struct {
   int32_t tensor_dtype;
   int32_t level1_dtype;
   int32_t use_second_order;
-  int32_t reserved;
+  /* Operator build (Section 3.2.3, memory footprint): 0 runs the PP dimension tree, which
+   * keeps first-level intermediates of O(s^(N-1) R) elements; 1 contracts X directly with
+   * the Khatri-Rao product of the other N-2 factors for every operator M_p^(i,j) (one pass
+   * over X per operator, no intermediates).  Order 3 builds the same either way.  1 needs
+   * the FP64 or FP32 first level and prod of the contracted dims below 2^31 - 64. */
+  int32_t pp_build_direct;
   /* Update step size lambda of the step-size variant of ALS (Section 5.1): every factor
    * update of the ALS and PP sweeps is A_new = (1 - lambda) A + lambda M Gamma^-1; the
    * record's gradient stays the one at A before the update, (A - M Gamma^-1) Gamma.

@@ -69,7 +69,7 @@ class Plan:
     """Host plan: dimension-tree schedules and the workspace layout."""
 
     def __init__(self, dims, rank, tensor_dtype="f64", level1_dtype=None, second_order=True,
-                 step_size=1.0):
+                 step_size=1.0, pp_build="tree"):
         dims = [int(d) for d in dims]
         if level1_dtype is None:
             level1_dtype = tensor_dtype
@@ -82,6 +82,9 @@ class Plan:
         d.level1_dtype = _DTYPES[level1_dtype]
         d.use_second_order = 1 if second_order else 0
         d.step_size = float(step_size)
+        if pp_build not in ("tree", "direct"):
+            raise ValueError("pp_build must be 'tree' or 'direct'")
+        d.pp_build_direct = 1 if pp_build == "direct" else 0
         h = ctypes.c_void_p()
         _lib.check(lib().ppals_plan_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
@@ -92,6 +95,7 @@ class Plan:
         self.level1_dtype = level1_dtype
         self.second_order = bool(second_order)
         self.step_size = float(step_size)
+        self.pp_build = pp_build
         self.torch_dtype = torch.float64 if tensor_dtype == "f64" else torch.float32
 
     @property

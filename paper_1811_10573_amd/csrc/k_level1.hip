@@ -153,7 +153,12 @@ struct BStage {
 // Zeros read in place of X entries outside the tensor (64 bytes covers the widest read).
 __device__ __attribute__((aligned(16))) double l1_zero[8];
 
-template <int DT, int MB, int NB, bool KCM, bool VEC, bool TAIL = false>
+// n / d for n < 2^31 with the precomputed multiplier of d (Level1Geom).
+__device__ __forceinline__ uint32_t l1_magic_div(uint32_t n, uint64_t mag, int sh) {
+  return (uint32_t)(((uint64_t)n * mag) >> (32 + sh));
+}
+
+template <int DT, int MB, int NB, bool KCM, bool VEC, bool TAIL = false, bool STR = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DT == DT_F32 && (KCM || VEC) ? 3 : 1))) void k_level1_reg(const typename L1T<DT>::T* __restrict__ X,
                                                     const typename L1T<DT>::T* __restrict__ B,
                                                     Level1Geom g,
@@ -167,6 +172,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DT == DT_F3
   constexpr int BM = 4 * 16 * MB;
   constexpr int CHUNK_ELEMS = KC * 16 * NB;
   static_assert(!( !KCM && VEC) || MB == TR::VW, "vector path needs MB == VW");
+  static_assert(!STR || (!KCM && !VEC && !TAIL), "strided addressing uses the scalar loads");
   __shared__ __attribute__((aligned(16))) T ldsB[2][CHUNK_ELEMS];
 
   const int tid = threadIdx.x;
@@ -204,6 +210,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DT == DT_F3
     base[0] = rowok[0] ? p * gK * gQ + q : 0;
 #pragma unroll
     for (int b = 1; b < MB; ++b) { rowok[b] = rowok[0]; base[b] = base[0]; }
+  } else if (STR) {
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+      const int64_t gr = g0w + 16 * b + i;
+      rowok[b] = gr < gM;
+      const int64_t m0 = gr / g.mrad, m1 = gr - m0 * g.mrad;
+      base[b] = rowok[b] ? m0 * g.ms0 + m1 * g.ms1 : 0;
+    }
   } else {
 #pragma unroll
     for (int b = 0; b < MB; ++b) {
@@ -254,6 +268,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DT == DT_F3
         const VT val = *reinterpret_cast<const VT*>((rowok[0] && k < kb1) ? X + base[0] + k * gQ : zero);
 #pragma unroll
         for (int b = 0; b < MB; ++b) xr[b][t] = val[b];
+      }
+    } else if (STR) {
+#pragma unroll
+      for (int t = 0; t < NSTEP; ++t) {
+        const int64_t k = kbase + 4 * t + kk;
+        const uint32_t ku = (uint32_t)k;
+        const uint32_t q2 = l1_magic_div(ku, g.kmag2, g.ksh2);
+        const uint32_t k2 = ku - q2 * g.kr2;
+        const uint32_t k0 = l1_magic_div(q2, g.kmag1, g.ksh1);
+        const uint32_t k1 = q2 - k0 * g.kr1;
+        const int64_t koff = (int64_t)k0 * g.ks0 + (int64_t)k1 * g.ks1 + (int64_t)k2 * g.ks2;
+#pragma unroll
+        for (int b = 0; b < MB; ++b) xr[b][t] = *((rowok[b] && k < kb1) ? X + base[b] + koff : zero);
       }
     } else {
 #pragma unroll
@@ -623,6 +650,23 @@ static void launch_reg_nb(const void* X, const void* B, const Level1Geom& g, voi
   }
 }
 
+// Strided addressing (direct operator build): scalar loads, no tail shape.
+template <int DT, int MB>
+static void launch_reg_str(const void* X, const void* B, const Level1Geom& g, void* C,
+                           int64_t stride, hipStream_t s) {
+  using TR = L1T<DT>;
+  using T = typename TR::T;
+  using Acc = typename TR::Acc;
+  constexpr int BM = 4 * 16 * MB;
+  dim3 grid((unsigned)((g.M + BM - 1) / BM), g.nslices, g.ksplit), block(256);
+  switch (g.NB) {
+    case 1: hipLaunchKernelGGL((k_level1_reg<DT, MB, 1, false, false, false, true>), grid, block, 0, s, (const T*)X, (const T*)B, g, (Acc*)C, stride); break;
+    case 2: hipLaunchKernelGGL((k_level1_reg<DT, MB, 2, false, false, false, true>), grid, block, 0, s, (const T*)X, (const T*)B, g, (Acc*)C, stride); break;
+    case 3: hipLaunchKernelGGL((k_level1_reg<DT, MB, 3, false, false, false, true>), grid, block, 0, s, (const T*)X, (const T*)B, g, (Acc*)C, stride); break;
+    default: hipLaunchKernelGGL((k_level1_reg<DT, MB, 4, false, false, false, true>), grid, block, 0, s, (const T*)X, (const T*)B, g, (Acc*)C, stride); break;
+  }
+}
+
 template <int MB, bool KCM, bool VEC>
 static void launch_bf16_nb(const void* X, const void* B, const Level1Geom& g, void* C,
                            int64_t stride, hipStream_t s) {
@@ -653,7 +697,11 @@ hipError_t launch_level1(const void* X, int dt, const void* B, const Level1Geom&
   void* dst = split ? partial : C;
   const int64_t stride = split ? g.M * (int64_t)g.R : 0;
   const bool vec = vec_ok(dt, g);
-  if (dt == DT_F64) {
+  if (g.strided) {
+    if (dt == DT_F64) launch_reg_str<DT_F64, 2>(X, B, g, dst, stride, s);
+    else if (dt == DT_F32) launch_reg_str<DT_F32, 4>(X, B, g, dst, stride, s);
+    else return hipErrorInvalidValue;  // the BF16 kernel has no strided addressing
+  } else if (dt == DT_F64) {
     if (g.kc_mode) { if (vec) launch_reg_nb<DT_F64, 2, true, true>(X, B, g, dst, stride, s); else launch_reg_nb<DT_F64, 2, true, false>(X, B, g, dst, stride, s); }
     else { if (vec) launch_reg_nb<DT_F64, 2, false, true>(X, B, g, dst, stride, s); else launch_reg_nb<DT_F64, 2, false, false>(X, B, g, dst, stride, s); }
   } else if (dt == DT_F32) {

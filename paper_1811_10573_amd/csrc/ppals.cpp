@@ -71,7 +71,8 @@ namespace {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct L1Step {
-  int lo, hi;           // contracted modes [lo, hi)
+  int lo, hi;           // contracted modes [lo, hi); -1, -1 for a strided step
+  std::vector<int> cmodes;  // strided step: the contracted modes, increasing
   Level1Geom geom;
   int out_buf;          // intermediate buffer id (bulk dtype), or -1: write FP64 M
   std::vector<int> kept;
@@ -149,6 +150,7 @@ struct ppals_plan {
   bool la_cur = false, la_gate_fused = false;
   double la_eps_cur = 0.0;
   bool fast = false;                   // rank <= 64: fused head/solve tail
+  bool direct = false;                 // operators straight from X (no tree intermediates)
   hipStream_t aux = nullptr;           // stream for the head kernel (default priority)
   ppals_sweep_record* pinned_rec = nullptr;  // pinned host staging of the sweep record
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -467,6 +469,61 @@ void prune_dt(ppals_plan* p) {
   p->dt_ops.swap(out);
 }
 
+// Multiplier and shift of the division by d used by the strided first-level loads:
+// q = (n * mag) >> (32 + sh) with sh = ceil(log2 d) and mag = ceil(2^(32+sh) / d) is
+// floor(n / d) for every n < 2^32 (Granlund and Montgomery, division by invariant
+// integers); the kernel keeps n < 2^31 so that n * mag fits in 64 bits.
+void magic_div(uint32_t d, uint64_t* mag, int* sh) {
+  int l = 0;
+  while ((1ull << l) < d) ++l;
+  const unsigned __int128 num = (unsigned __int128)1 << (32 + l);
+  *mag = (uint64_t)((num + d - 1) / d);
+  *sh = l;
+}
+
+// Operator M_p^(i,j) (i < j) straight from X: the other N - 2 modes are contracted with
+// their Khatri-Rao product.  A contiguous block of contracted modes is a plain first-level
+// step; otherwise the contracted modes form up to three blocks (before i, between i and j,
+// after j) and the step reads X through strided row and k offsets.
+int add_direct_leaf(ppals_plan* p, int i, int j, int out_buf) {
+  const int N = p->N;
+  std::vector<int> cm;
+  for (int m = 0; m < N; ++m)
+    if (m != i && m != j) cm.push_back(m);
+  bool contiguous = true;
+  for (size_t a = 1; a < cm.size(); ++a) contiguous = contiguous && cm[a] == cm[a - 1] + 1;
+  if (contiguous) return add_l1(p, cm.front(), cm.back() + 1, out_buf);
+  auto prod = [&](int lo, int hi) {  // dims[lo..hi)
+    int64_t v = 1;
+    for (int m = lo; m < hi; ++m) v *= p->dims[m];
+    return v;
+  };
+  L1Step s;
+  s.lo = s.hi = -1;
+  s.cmodes = cm;
+  s.kept = {i, j};
+  s.out_buf = out_buf;
+  const int64_t n1 = prod(0, i), n2 = prod(i + 1, j), n3 = prod(j + 1, N);
+  const int64_t K = n1 * n2 * n3, M = p->dims[i] * p->dims[j];
+  Level1Geom g = l1_geom(M, K, 1, p->R, p->l1dt);
+  g.kc_mode = 0;
+  g.Q = 1;
+  g.strided = 1;
+  g.mrad = p->dims[j];
+  g.ms0 = prod(i + 1, N);
+  g.ms1 = prod(j + 1, N);
+  g.kr1 = (uint32_t)n2;
+  g.kr2 = (uint32_t)n3;
+  magic_div(g.kr1, &g.kmag1, &g.ksh1);
+  magic_div(g.kr2, &g.kmag2, &g.ksh2);
+  g.ks0 = prod(i, N);
+  g.ks1 = prod(j, N);
+  g.ks2 = 1;
+  s.geom = g;
+  p->l1.push_back(s);
+  return (int)p->l1.size() - 1;
+}
+
 void build_pp(ppals_plan* p) {
   const int N = p->N;
   // node store: mode list -> buffer id
@@ -478,8 +535,16 @@ void build_pp(ppals_plan* p) {
   };
   for (int i = 0; i < N; ++i)
     for (int j = 0; j < N; ++j) p->leaf_buf[i][j] = -1;
+  if (p->direct) {
+    for (int i = 0; i < N; ++i)
+      for (int j = i + 1; j < N; ++j) {
+        const int ob = new_buf(p, node_bytes(p, {i, j}));
+        p->pp_ops.push_back({OP_L1, add_direct_leaf(p, i, j, ob)});
+        p->leaf_buf[i][j] = ob;
+      }
+  }
   // level 2 (paper numbering, modes 1-based in the text; 0-based here)
-  for (int l = 2; l <= N - 1; ++l) {
+  for (int l = 2; l <= N - 1 && !p->direct; ++l) {
     std::vector<int> tail;
     for (int m = l + 2; m <= N; ++m) tail.push_back(m - 1);
     for (int i = 1; i <= l + 1; ++i)
@@ -651,13 +716,18 @@ std::string json_ops(const ppals_plan* p, const std::vector<Op>& ops, double* fl
       const L1Step& st = p->l1[o.idx];
       const double f = 2.0 * (double)st.geom.M * (double)st.geom.K * p->R;
       *flops_l1 += f;
-      std::string kept;
+      std::string kept, contr;
       for (size_t i = 0; i < st.kept.size(); ++i) kept += (i ? "," : "") + std::to_string(st.kept[i]);
+      if (st.cmodes.empty()) {
+        contr = std::to_string(st.lo) + "," + std::to_string(st.hi);
+      } else {
+        for (size_t i = 0; i < st.cmodes.size(); ++i) contr += (i ? "," : "") + std::to_string(st.cmodes[i]);
+      }
       snprintf(tmp, sizeof(tmp),
-               "{\"op\":\"level1\",\"contract\":[%d,%d],\"kept\":[%s],\"M\":%lld,\"K\":%lld,"
-               "\"Q\":%lld,\"ksplit\":%d,\"kc_mode\":%d,\"flops\":%.0f}",
-               st.lo, st.hi, kept.c_str(), (long long)st.geom.M, (long long)st.geom.K,
-               (long long)st.geom.Q, st.geom.ksplit, st.geom.kc_mode, f);
+               "{\"op\":\"level1\",\"contract\":[%s],\"kept\":[%s],\"M\":%lld,\"K\":%lld,"
+               "\"Q\":%lld,\"ksplit\":%d,\"kc_mode\":%d,\"strided\":%d,\"flops\":%.0f}",
+               contr.c_str(), kept.c_str(), (long long)st.geom.M, (long long)st.geom.K,
+               (long long)st.geom.Q, st.geom.ksplit, st.geom.kc_mode, st.geom.strided, f);
     } else if (o.kind == OP_TTV) {
       const TtvStep& t = p->ttv[o.idx];
       const double f = 2.0 * (double)t.P * t.X * t.Q * p->R;
@@ -706,7 +776,21 @@ void make_describe(ppals_plan* p) {
   for (int n = 0; n < p->N; ++n)
     ranges += (n ? "," : "") + std::to_string(p->fast ? gram_ranges(p->dims[n]) : 0);
   ranges += "]";
+  size_t inter = 0;  // bulk bytes of the build's buffers that are not operators (tree nodes)
+  for (size_t b = 0; b < p->bufs.size(); ++b) {
+    bool leaf = false;
+    for (int i = 0; i < p->N; ++i)
+      for (int j = 0; j < p->N; ++j) leaf = leaf || p->leaf_buf[i][j] == (int)b;
+    bool pp_node = false;
+    for (const Op& o : p->pp_ops) {
+      if (o.kind == OP_L1) pp_node = pp_node || p->l1[o.idx].out_buf == (int)b;
+      if (o.kind == OP_TTV) pp_node = pp_node || p->ttv[o.idx].out_buf == (int)b;
+    }
+    if (pp_node && !leaf) inter += p->bufs[b].bytes;
+  }
   p->describe = std::string("{") + tmp + ",\"dt_ops\":" + dt + ",\"pp_build_ops\":" + pp +
+                ",\"pp_build\":\"" + (p->direct ? "direct" : "tree") +
+                "\",\"pp_build_intermediate_bytes\":" + std::to_string(inter) +
                 ",\"pp_build_reused_after_als\":" + reuse + ",\"fused_tail\":" +
                 (p->fast ? "true" : "false") + ",\"pp_gram_ranges\":" + ranges + "}";
 }
@@ -793,11 +877,19 @@ ppals_status run_l1(const Ctx& c, const L1Step& st, const void* X, const void* X
   ppals_plan* p = c.p;
   KrpDesc krp;
   memset(&krp, 0, sizeof(krp));
-  krp.nf = st.hi - st.lo;
   krp.R = p->R;
-  for (int f = 0; f < krp.nf; ++f) {
-    krp.A[f] = A[st.lo + f];
-    krp.dim[f] = p->dims[st.lo + f];
+  if (!st.cmodes.empty()) {
+    krp.nf = (int)st.cmodes.size();
+    for (int f = 0; f < krp.nf; ++f) {
+      krp.A[f] = A[st.cmodes[f]];
+      krp.dim[f] = p->dims[st.cmodes[f]];
+    }
+  } else {
+    krp.nf = st.hi - st.lo;
+    for (int f = 0; f < krp.nf; ++f) {
+      krp.A[f] = A[st.lo + f];
+      krp.dim[f] = p->dims[st.lo + f];
+    }
   }
   void* B = c.ws + p->off_B;
   {
@@ -1658,6 +1750,18 @@ ppals_status ppals_plan_create(const ppals_desc* d, ppals_plan** out) {
   if (!tier_ok) return fail(PPALS_E_UNSUPPORTED, "unsupported (tensor_dtype, level1_dtype) pair");
   const double step = d->step_size == 0.0 ? 1.0 : d->step_size;
   if (!(step > 0.0 && step <= 1.0)) return fail(PPALS_E_ARG, "step_size must be in (0, 1] (or 0 for 1)");
+  if (d->pp_build_direct && d->order > 3) {
+    if (d->level1_dtype == PPALS_BF16)
+      return fail(PPALS_E_UNSUPPORTED, "the direct operator build needs the FP64 or FP32 first level");
+    for (int i = 0; i < d->order; ++i)
+      for (int j = i + 1; j < d->order; ++j) {
+        double K = 1.0;
+        for (int m = 0; m < d->order; ++m)
+          if (m != i && m != j) K *= (double)d->dims[m];
+        if (K > 2147483647.0 - 64.0)
+          return fail(PPALS_E_UNSUPPORTED, "direct operator build: contracted extent above 2^31 - 64");
+      }
+  }
   ppals_plan* p = new ppals_plan();
   p->step = step;
   p->N = d->order;
@@ -1668,6 +1772,7 @@ ppals_status ppals_plan_create(const ppals_desc* d, ppals_plan** out) {
   p->bulk = d->tensor_dtype == PPALS_FP64 ? DT_F64 : DT_F32;
   p->second_order = d->use_second_order ? 1 : 0;
   p->fast = p->R <= 64;
+  p->direct = d->pp_build_direct != 0 && d->order > 3;
   p->mode_off.resize(p->N);
   for (int i = 0; i < p->N; ++i) {
     p->mode_off[i] = (size_t)p->sum_s * p->R;

@@ -108,7 +108,7 @@ def oracle_sensitivity(fn, A0, rel_pert=1e-15, seed=0):
 class Run:
     """Device copies of one problem plus the library state (plan, workspace, record)."""
 
-    def __init__(self, prob, tier="f64", second_order=True, init=None, X=None):
+    def __init__(self, prob, tier="f64", second_order=True, init=None, X=None, pp_build="tree"):
         import paper_1811_10573_amd as pp
         self.pp = pp
         self.prob = prob
@@ -116,7 +116,7 @@ class Run:
         dims = prob.shape
         R = prob.rank
         tdt = "f64" if tier == "f64" else "f32"
-        self.plan = pp.Plan(dims, R, tdt, tier, second_order)
+        self.plan = pp.Plan(dims, R, tdt, tier, second_order, pp_build=pp_build)
         X = prob.X if X is None else X
         self.Xh = X if tier == "f64" else fp32_round(X)
         self.X = to_dev(self.Xh, self.plan.torch_dtype)

@@ -328,3 +328,41 @@ def test_tucker_plan_validates_and_refuses_before_device_work(lib):
                               ctypes.byref(n_out), nul) == _lib.PPALS_E_ARG
     finally:
         lib.tucker_plan_destroy(h)
+
+
+def test_direct_build_plan(lib):
+    """The direct operator build keeps no tree intermediate, contracts each of the
+    N(N-1)/2 operators from X (2 s^N R flops each), refuses the BF16 first level, and
+    leaves order 3 as it is."""
+    import json
+    from paper_1811_10573_amd import _lib
+
+    def describe(dims, R, tdt, l1, direct):
+        d = _desc(dims, R, tdt, l1)
+        d.pp_build_direct = direct
+        h = ctypes.c_void_p()
+        st = lib.ppals_plan_create(ctypes.byref(d), ctypes.byref(h))
+        if st != 0:
+            return st, None
+        buf = ctypes.create_string_buffer(1 << 20)
+        assert lib.ppals_plan_describe(h, buf, len(buf)) == 0
+        lib.ppals_plan_destroy(h)
+        return 0, json.loads(buf.value.decode())
+
+    s, R = 20, 6
+    st, tree = describe((s,) * 4, R, 0, 0, 0)
+    st2, direct = describe((s,) * 4, R, 0, 0, 1)
+    assert st == 0 and st2 == 0
+    assert tree["pp_build"] == "tree" and direct["pp_build"] == "direct"
+    assert tree["pp_build_intermediate_bytes"] == 3 * s ** 3 * R * 8
+    assert direct["pp_build_intermediate_bytes"] == 0
+    assert direct["workspace_bytes"] < tree["workspace_bytes"]
+    l1 = [o for o in direct["pp_build_ops"] if o["op"] == "level1"]
+    assert len(l1) == 6 and all(o["flops"] == 2 * s ** 4 * R for o in l1)
+    assert sorted(tuple(o["kept"]) for o in l1) == [(i, j) for i in range(4) for j in range(i + 1, 4)]
+    assert sum(1 for o in l1 if o["strided"]) == 3      # (0,2), (1,2), (1,3)
+    assert direct["pp_build_tree_ttv_flops"] == 0
+    st, _ = describe((s,) * 4, R, 1, 2, 1)
+    assert st == _lib.PPALS_E_UNSUPPORTED
+    st, o3 = describe((s,) * 3, R, 0, 0, 1)
+    assert st == 0 and o3["pp_build"] == "tree"
