@@ -577,6 +577,46 @@ def tucker_leg(pp, torch, dev, tensorgen, s=800, R=40, eta=0.1, eps=0.3, sweeps=
     return out
 
 
+def build_leg(pp, torch, dev, tensorgen, shape=(160, 160, 160, 160), R=64, tier="f32", reps=3):
+    """PP operator build of Section 3.2.3 on one configuration, with the dimension tree and
+    with the direct build (every operator from X and the Khatri-Rao product of the other
+    N - 2 factors): workspace, bytes of the tree's intermediates, build time (HIP events
+    around pp_build_operators) and first-level rate."""
+    prob = tensorgen.make_problem_device(shape, R, 0, eta=1e-2, dtype=tier, device=dev)
+    X = prob.X.reshape(-1)
+    A = [torch.from_numpy(a).to(dev) for a in prob.init]
+    out = {"workload": f"PP operator build, order {len(shape)} {'x'.join(map(str, shape))} "
+                       f"{tier.upper()}, R = {R}"}
+    for build in ("tree", "direct"):
+        plan = pp.Plan(shape, R, tier, tier, True, pp_build=build)
+        d = plan.describe()
+        ws = plan.workspace(dev)
+        pp.pp_build_operators(plan, X, None, A, ws)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(reps):
+            pp.pp_build_operators(plan, X, None, A, ws)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / reps
+        fl = d["pp_build_level1_flops"] + d["pp_build_tree_ttv_flops"] + d["pp_build_mp_flops"]
+        out[build] = {"ms": ms, "workspace_GB": plan.workspace_bytes / 1e9,
+                      "intermediate_GB": d["pp_build_intermediate_bytes"] / 1e9,
+                      "level1_launches": sum(1 for o in d["pp_build_ops"] if o["op"] == "level1"),
+                      "strided_launches": sum(1 for o in d["pp_build_ops"] if o.get("strided")),
+                      "GFLOP": fl / 1e9, "TFLOP_s": fl / (ms * 1e-3) / 1e12}
+        del ws, plan
+        torch.cuda.empty_cache()
+    out["direct_over_tree_time"] = out["direct"]["ms"] / out["tree"]["ms"]
+    out["workspace_saved_GB"] = out["tree"]["workspace_GB"] - out["direct"]["workspace_GB"]
+    log(f"build {shape} R {R} {tier}: tree {out['tree']['ms']:.2f} ms ws {out['tree']['workspace_GB']:.2f} GB; "
+        f"direct {out['direct']['ms']:.2f} ms ws {out['direct']['workspace_GB']:.2f} GB")
+    del X, prob
+    torch.cuda.empty_cache()
+    return out
+
+
 def ablation_bench(args, torch, dev):
     """The second-order correction ablation of the synthetic collinearity experiments
     (Section 5.1): fit against time for dimension-tree ALS, PP with the second-order
@@ -745,7 +785,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dt", action="store_true")
-    ap.add_argument("--workload", default="pp", choices=["pp", "batch", "ablation", "tucker"],
+    ap.add_argument("--workload", default="pp",
+                    choices=["pp", "batch", "ablation", "tucker", "build"],
                     help="pp: the 800^3 decomposition (default); batch: 512 independent problems; "
                          "ablation: PP with and without the second-order term against DT-ALS")
     ap.add_argument("--abl-size", type=int, default=64)
@@ -782,6 +823,13 @@ def main():
         return
     if args.workload == "ablation":
         ablation_bench(args, torch, dev)
+        return
+    if args.workload == "build":
+        res = [build_leg(pp, torch, dev, tensorgen, (160,) * 4, 64, "f32"),
+               build_leg(pp, torch, dev, tensorgen, (160,) * 4, 64, "f64"),
+               build_leg(pp, torch, dev, tensorgen, (48,) * 5, 32, "f32"),
+               build_leg(pp, torch, dev, tensorgen, (24,) * 6, 16, "f32")]
+        print(json.dumps(res), flush=True)
         return
     if args.workload == "tucker":
         s = args.size
