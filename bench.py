@@ -1025,7 +1025,7 @@ def main():
     # 64^3 ALS configuration and the first-level contractions of the 160^4 configuration
     extras = (not args.no_extras and args.tier == "f32" and shape == (800, 800, 800)
               and R == 50 and not args.device_gen)
-    f64 = c1 = c3 = batch = tucker = None
+    f64 = c1 = c3 = batch = tucker = build = None
     A_f64_replay = c1prob = None
     if extras:
         del ws
@@ -1040,6 +1040,7 @@ def main():
         batch["batch"] = {k: v for k, v in batch["batch"].items() if k != "autotune"}
         tucker = tucker_leg(pp, torch, dev, tensorgen, s=800, R=40,
                             cpu_seconds=0.0 if args.no_cpu_baseline else 4.0)
+        build = build_leg(pp, torch, dev, tensorgen, (160,) * 4, 64, "f32")
 
     cpu = None
     vs_oracle = None
@@ -1127,6 +1128,7 @@ def main():
         "c3_level1": c3,
         "c5_batch": batch,
         "f1_tucker": tucker,
+        "f2_direct_build": build,
         "paper_reference": PAPER_NUMBERS,
         "kernels": kernels,
     }
