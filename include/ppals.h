@@ -458,7 +458,7 @@ ppals_status ppals_get_profile(ppals_plan* plan, ppals_kernel_stat* out, int32_t
  * The iteration synchronises the stream once per iteration to read the residual,
  * so every entry point below that updates factors returns with the stream idle.
  *
- * Limits: 1 <= R <= 64, R <= s_n for every n.
+ * Limits: 1 <= R <= 64, R <= s_n for every n, s_1 s_3 < 2^31 - 64.
  * ------------------------------------------------------------------------- */
 #define TUCKER_MAX_RANK 64
 typedef struct tucker_plan tucker_plan;
@@ -501,10 +501,11 @@ ppals_status tucker_factor_update(tucker_plan* plan, void* ws, const double* Y, 
                                   double* residual, hipStream_t stream);
 
 /* Classical HOSVD start (Section 2.4): A^(n) <- leading eigenvectors of
- * X_(n) X_(n)^T (formed explicitly, then subspace iteration from the caller's start
- * V0[n], s_n x R, full column rank), the entry of largest magnitude of every column
- * made positive; G <- X x_1 A^(1)T x_2 A^(2)T x_3 A^(3)T.  info (host, 3 x 3 ints, may
- * be NULL) as in tucker_factor_update per mode.  Synchronises the stream. */
+ * X_(n) X_(n)^T by the same subspace iteration, started from the caller's V0[n]
+ * (s_n x R, full column rank), with W applied through X (X_(n)^T V, then X_(n) times
+ * it; W is never formed); the entry of largest magnitude of every column made positive;
+ * G <- X x_1 A^(1)T x_2 A^(2)T x_3 A^(3)T.  info (host, 3 x 3 ints, may be NULL) as in
+ * tucker_factor_update per mode.  Synchronises the stream.  Needs s_1 s_3 < 2^31 - 64. */
 ppals_status tucker_hosvd(tucker_plan* plan, void* ws, const double* X, double* const* V0,
                           double* const* A, double* G, int32_t* info, hipStream_t stream);
 

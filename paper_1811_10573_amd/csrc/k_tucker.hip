@@ -1,7 +1,7 @@
 // Kernels of the Tucker-ALS and PP-Tucker-ALS path (Algorithms 2 and 4), FP64:
 //
-//  * a strided FP64 GEMM for the Gram matrix of an unfolding, W = Y_(n) Y_(n)^T, the
-//    products of the subspace iteration and the core G = A^(N)T Y^(N)_(N);
+//  * a strided, split-K, batched FP64 GEMM for the small products of the subspace
+//    iteration (V^T V, V^T W V, V^T A_prev);
 //  * the Rayleigh-Ritz step of the subspace iteration that gives the leading
 //    eigenvectors of W (one workgroup: Cholesky of V^T V, the projected matrix, cyclic
 //    Jacobi rotations, decreasing order, column signs);
@@ -17,9 +17,6 @@ namespace ppk {
 // ---------------------------------------------------------------------------
 // C[m][n] = alpha * sum_k A(m, k) B(k, n) (+ beta C[m][n]) with
 // A(m, k) = A[m * sam + k * sak] and B(k, n) = B[k * sbk + n * sbn]; C row-major (ldc).
-// With kin > 0 the contracted index is two-level, k = k_out * kin + k_in, and
-// A(m, k) = A[m * sam + k_out * sak + k_in * sak2] (same for B): the unfolding of a
-// middle mode of a three-way tensor.
 // 64 x 64 tiles, 256 threads with 4 x 4 outputs each, K in chunks of 16 through LDS;
 // workgroup z takes the z-th of ks consecutive K ranges.  A tile is read with the
 // operand's unit-stride index fastest across threads.
@@ -36,8 +33,8 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g, int64_t kchunk, in
   const int64_t kbeg = (int64_t)split * kchunk;
   const int64_t kend = kbeg + kchunk < g.K ? kbeg + kchunk : g.K;
   const int tm = (tid / 16) * 4, tn = (tid % 16) * 4;
-  const bool a_kfast = g.kin ? g.sak2 == 1 : g.sak == 1;
-  const bool b_kfast = g.kin ? g.sbk2 == 1 : g.sbk == 1;
+  const bool a_kfast = g.sak == 1;
+  const bool b_kfast = g.sbk == 1;
   double acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -48,15 +45,13 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g, int64_t kchunk, in
       const int kk = a_kfast ? e % GK : e / GT;
       const int mm = a_kfast ? e / GK : e % GT;
       const int64_t m = m0 + mm, k = k0 + kk;
-      const int64_t ka = g.kin ? (k / g.kin) * g.sak + (k % g.kin) * g.sak2 : k * g.sak;
-      As[kk][mm] = (m < g.M && k < kend) ? g.A[m * g.sam + ka] : 0.0;
+      As[kk][mm] = (m < g.M && k < kend) ? g.A[m * g.sam + k * g.sak] : 0.0;
     }
     for (int e = tid; e < GK * GT; e += 256) {
       const int kk = b_kfast ? e % GK : e / GT;
       const int nn = b_kfast ? e / GK : e % GT;
       const int64_t n = n0 + nn, k = k0 + kk;
-      const int64_t kb = g.kin ? (k / g.kin) * g.sbk + (k % g.kin) * g.sbk2 : k * g.sbk;
-      Bs[kk][nn] = (n < g.N && k < kend) ? Bp[kb + n * g.sbn] : 0.0;
+      Bs[kk][nn] = (n < g.N && k < kend) ? Bp[k * g.sbk + n * g.sbn] : 0.0;
     }
     __syncthreads();
 #pragma unroll

@@ -469,17 +469,21 @@ void prune_dt(ppals_plan* p) {
   p->dt_ops.swap(out);
 }
 
+}  // namespace
+
 // Multiplier and shift of the division by d used by the strided first-level loads:
 // q = (n * mag) >> (32 + sh) with sh = ceil(log2 d) and mag = ceil(2^(32+sh) / d) is
 // floor(n / d) for every n < 2^32 (Granlund and Montgomery, division by invariant
 // integers); the kernel keeps n < 2^31 so that n * mag fits in 64 bits.
-void magic_div(uint32_t d, uint64_t* mag, int* sh) {
+void l1_magic(uint32_t d, uint64_t* mag, int* sh) {
   int l = 0;
   while ((1ull << l) < d) ++l;
   const unsigned __int128 num = (unsigned __int128)1 << (32 + l);
   *mag = (uint64_t)((num + d - 1) / d);
   *sh = l;
 }
+
+namespace {
 
 // Operator M_p^(i,j) (i < j) straight from X: the other N - 2 modes are contracted with
 // their Khatri-Rao product.  A contiguous block of contracted modes is a plain first-level
@@ -514,8 +518,8 @@ int add_direct_leaf(ppals_plan* p, int i, int j, int out_buf) {
   g.ms1 = prod(j + 1, N);
   g.kr1 = (uint32_t)n2;
   g.kr2 = (uint32_t)n3;
-  magic_div(g.kr1, &g.kmag1, &g.ksh1);
-  magic_div(g.kr2, &g.kmag2, &g.ksh2);
+  l1_magic(g.kr1, &g.kmag1, &g.ksh1);
+  l1_magic(g.kr2, &g.kmag2, &g.ksh2);
   g.ks0 = prod(i, N);
   g.ks1 = prod(j, N);
   g.ks2 = 1;

@@ -57,7 +57,7 @@ struct tucker_plan {
   // workspace regions (byte offsets)
   size_t o_T3, o_T1, o_op01, o_op02, o_op12, o_Yp[3], o_Y, o_Ta, o_Tb, o_Gn, o_Ap[3], o_dA[3],
       o_Aold, o_V, o_C, o_U, o_Z, o_B, o_H, o_P, o_T, o_lam, o_info, o_stats, o_prep, o_part,
-      o_gpart, o_W, o_rpart;
+      o_gpart, o_Zx, o_rpart;
   size_t slot = 0;  // bytes between the basis slots V, C, A_prev
   size_t ws_bytes = 0;
   bool built = false;
@@ -93,6 +93,8 @@ std::vector<Contr> all_contractions(const tucker_plan* p) {
     v.push_back({1, p->s[n], R * R});  // Y_(n)^T V
     v.push_back({p->s[n], R * R, 1});  // Y_(n) Z
   }
+  v.push_back({s0, s1 * s2, 1});       // HOSVD: X_(1) Z
+  v.push_back({1, s0 * s1, s2});       // HOSVD: X_(3) Z
   return v;
 }
 
@@ -153,34 +155,68 @@ ppals_status projections(const TCtx& c, int64_t rows, int nb) {
   return PPALS_OK;
 }
 
-// W (s_n x s_n) = X_(n) X_(n)^T
-ppals_status unfolding_gram(const TCtx& c, const double* X, int n, double* W) {
-  const int64_t s0 = c.p->s[0], s1 = c.p->s[1], s2 = c.p->s[2];
-  const int64_t sn = c.p->s[n];
-  GemmArgs g = gemm_args(X, X, W, sn, sn, 0);
-  if (n == 0) {  // rows x1, columns (x2, x3) contiguous
-    g.K = s1 * s2;
-    g.sam = s1 * s2;
-    g.sak = 1;
-    g.sbk = 1;
-    g.sbn = s1 * s2;
-  } else if (n == 2) {  // rows x3, columns (x1, x2) with stride s3
-    g.K = s0 * s1;
-    g.sam = 1;
-    g.sak = s2;
-    g.sbk = s2;
-    g.sbn = 1;
-  } else {  // rows x2, columns (x1, x3): x1 stride s2 s3, x3 unit
-    g.K = s0 * s2;
-    g.kin = s2;
-    g.sam = s2;
-    g.sak = s1 * s2;
-    g.sak2 = 1;
-    g.sbk = s1 * s2;
-    g.sbk2 = 1;
-    g.sbn = s2;
+// The product X_(1) Z of the HOSVD of the middle mode: C[x2][r] = sum over (x1, x3) of
+// X[x1][x2][x3] Z[x1 s3 + x3][r], a first-level contraction whose rows (x2) and
+// contracted index (x1, x3) reach X through strided offsets.
+Level1Geom middle_unfolding_geom(const tucker_plan* p) {
+  const int64_t s0 = p->s[0], s1 = p->s[1], s2 = p->s[2];
+  Level1Geom g = l1_geom(s1, s0 * s2, 1, p->R, DT_F64);
+  g.kc_mode = 0;
+  g.Q = 1;
+  g.strided = 1;
+  g.mrad = s1;  // row m = x2: offset x2 s3
+  g.ms0 = 0;
+  g.ms1 = s2;
+  g.kr1 = 1;    // k = x1 s3 + x3: offset x1 s2 s3 + x3
+  g.kr2 = (uint32_t)s2;
+  l1_magic(g.kr1, &g.kmag1, &g.ksh1);
+  l1_magic(g.kr2, &g.kmag2, &g.ksh2);
+  g.ks0 = s1 * s2;
+  g.ks1 = 0;
+  g.ks2 = 1;
+  return g;
+}
+
+// out (M x R) = first-level contraction of T with the K x R factor F under geometry g
+ppals_status ttm_geom(const TCtx& c, const double* T, const Level1Geom& g, const double* F,
+                      double* out) {
+  KrpDesc krp;
+  memset(&krp, 0, sizeof(krp));
+  krp.nf = 1;
+  krp.R = c.p->R;
+  krp.A[0] = F;
+  krp.dim[0] = g.K;
+  void* B = c.ws + c.p->o_prep;
+  THIPCHK(launch_prep_operand(krp, g, DT_F64, B, c.s));
+  THIPCHK(launch_level1(T, DT_F64, B, g, out, c.ws + c.p->o_part, c.s));
+  return PPALS_OK;
+}
+
+// C = W V for the subspace iteration of mode n: through a TTMc Y (W = Y_(n) Y_(n)^T,
+// Y given) or, for the HOSVD (Y null), through X itself (W = X_(n) X_(n)^T) with the
+// intermediate Z = X_(n)^T V in the scratch region Zx.
+ppals_status apply_w(const TCtx& c, int n, const double* Y, const double* X, const double* V,
+                     double* C) {
+  tucker_plan* p = c.p;
+  const int64_t s0 = p->s[0], s1 = p->s[1], s2 = p->s[2], R = p->R;
+  const int64_t sn = p->s[n];
+  if (Y) {
+    double* Z = c.d(p->o_Z);
+    TCHK(ttm(c, Y, {1, sn, R * R}, V, Z));  // Z = Y^T V   (R^2 x R)
+    TCHK(ttm(c, Y, {sn, R * R, 1}, Z, C));  // C = Y Z     (s_n x R)
+    return PPALS_OK;
   }
-  THIPCHK(launch_gemm_f64(g, c.s));
+  double* Zx = c.d(p->o_Zx);
+  if (n == 0) {
+    TCHK(ttm(c, X, {1, s0, s1 * s2}, V, Zx));  // (x2, x3, r)
+    TCHK(ttm(c, X, {s0, s1 * s2, 1}, Zx, C));  // (x1, r)
+  } else if (n == 2) {
+    TCHK(ttm(c, X, {s0 * s1, s2, 1}, V, Zx));  // (x1, x2, r)
+    TCHK(ttm(c, X, {1, s0 * s1, s2}, Zx, C));  // (x3, r)
+  } else {
+    TCHK(ttm(c, X, {s0, s1, s2}, V, Zx));      // (x1, x3, r)
+    TCHK(ttm_geom(c, X, middle_unfolding_geom(p), Zx, C));  // (x2, r)
+  }
   return PPALS_OK;
 }
 
@@ -190,10 +226,10 @@ struct IterInfo {
   int32_t jacobi_sweeps;
 };
 
-// Subspace iteration for the R leading eigenvectors of W (s_n x s_n), given either as
-// an explicit matrix (Wexp) or through a TTMc Y (s_n x R^2, W = Y Y^T).  V starts from
-// V0; A_prev (may be null) orients the columns.  Result into A_out.
-ppals_status subspace(const TCtx& c, int n, const double* Y, const double* Wexp, const double* V0,
+// Subspace iteration for the R leading eigenvectors of W (s_n x s_n), W = Y_(n) Y_(n)^T
+// for a TTMc Y or, with Y null, X_(n) X_(n)^T (the HOSVD).  V starts from V0; A_prev (may
+// be null) orients the columns.  Result into A_out.
+ppals_status subspace(const TCtx& c, int n, const double* Y, const double* X, const double* V0,
                       const double* A_prev, double* A_out, int max_iters, int32_t* info,
                       double* residual) {
   tucker_plan* p = c.p;
@@ -202,7 +238,6 @@ ppals_status subspace(const TCtx& c, int n, const double* Y, const double* Wexp,
   double* V = c.d(p->o_V);
   double* C = c.d(p->o_C);
   double* U = c.d(p->o_U);
-  double* Z = c.d(p->o_Z);
   double* T = c.d(p->o_T);
   double* lam = c.d(p->o_lam);
   double* Aold = c.d(p->o_Aold);
@@ -215,18 +250,7 @@ ppals_status subspace(const TCtx& c, int n, const double* Y, const double* Wexp,
   bool conv = false;
   while (it < max_iters) {
     ++it;
-    // C = W V
-    if (Wexp) {
-      GemmArgs g = gemm_args(Wexp, V, C, sn, R, sn);
-      g.sam = sn;
-      g.sak = 1;
-      g.sbk = R;
-      g.sbn = 1;
-      THIPCHK(launch_gemm_f64(g, c.s));
-    } else {
-      TCHK(ttm(c, Y, {1, sn, (int64_t)R * R}, V, Z));  // Z = Y^T V   (R^2 x R)
-      TCHK(ttm(c, Y, {sn, (int64_t)R * R, 1}, Z, C));  // C = Y Z     (s_n x R)
-    }
+    TCHK(apply_w(c, n, Y, X, V, C));  // C = W V
     TCHK(projections(c, sn, A_prev ? 3 : 2));
     RRArgs rr;
     rr.R = R;
@@ -367,6 +391,8 @@ ppals_status tucker_plan_create(const int64_t dims[3], int32_t rank, tucker_plan
     if (dims[n] < rank)
       return set_error(PPALS_E_UNSUPPORTED, "Tucker rank must not exceed any dimension");
   }
+  if ((double)dims[0] * (double)dims[2] > 2147483647.0 - 64.0)
+    return set_error(PPALS_E_UNSUPPORTED, "s1 * s3 must stay below 2^31 - 64 (strided HOSVD product)");
   tucker_plan* p = new tucker_plan();
   for (int n = 0; n < 3; ++n) p->s[n] = dims[n];
   p->R = rank;
@@ -412,10 +438,16 @@ ppals_status tucker_plan_create(const int64_t dims[3], int32_t rank, tucker_plan
     prep = std::max(prep, prep_elems(g));
     part = std::max(part, part_elems(g));
   }
+  {
+    const Level1Geom g = middle_unfolding_geom(p);
+    prep = std::max(prep, prep_elems(g));
+    part = std::max(part, part_elems(g));
+  }
   p->o_prep = take(prep);
   p->o_part = take(std::max<size_t>(part, 1024));
   p->o_gpart = take((size_t)kMaxGemmSplit * 3 * R * R);
-  p->o_W = take(smax * smax);
+  // HOSVD intermediate X_(n)^T V: the largest of s2 s3, s1 s3, s1 s2 times R
+  p->o_Zx = take(std::max(s1 * s2, std::max(s0 * s2, s0 * s1)) * R);
   p->ws_bytes = off;
   *out = p;
   return PPALS_OK;
@@ -465,12 +497,9 @@ ppals_status tucker_hosvd(tucker_plan* plan, void* ws, const double* X, double* 
   TCHK(check_factors(plan, V0));
   if (!X || !G) return set_error(PPALS_E_ARG, "NULL argument");
   TCtx c{plan, (char*)ws, stream};
-  double* W = c.d(plan->o_W);
-  for (int n = 0; n < 3; ++n) {
-    TCHK(unfolding_gram(c, X, n, W));
-    TCHK(subspace(c, n, nullptr, W, V0[n], nullptr, A[n], plan->hosvd_iters,
+  for (int n = 0; n < 3; ++n)
+    TCHK(subspace(c, n, nullptr, X, V0[n], nullptr, A[n], plan->hosvd_iters,
                   info ? info + 3 * n : nullptr, nullptr));
-  }
   const int64_t s0 = plan->s[0], s1 = plan->s[1], s2 = plan->s[2], R = plan->R;
   double* T1 = c.d(plan->o_T1);
   double* Y = c.d(plan->o_Y);

@@ -14,9 +14,6 @@ struct GemmArgs {
   int64_t sbk, sbn;  // B(k, n) = B[k * sbk + n * sbn]
   int64_t ldc;
   double alpha, beta;
-  int64_t kin;       // 0: k contiguous as above; else k = k_out * kin + k_in with
-  int64_t sak2;      //   A offset k_out * sak + k_in * sak2 and
-  int64_t sbk2;      //   B offset k_out * sbk + k_in * sbk2
   int ks;            // K split over workgroups (>= 1); ks > 1 needs alpha 1, beta 0, ldc N
   double* part;      //   and ks x nb x M x N doubles of partial sums here
   int nb;            // batch of products sharing A (>= 1): B_x = B + x sbb, C_x = C + x M N
@@ -50,5 +47,7 @@ hipError_t launch_core_stats(const double* Gn, const double* Go, int64_t n, doub
 
 }  // namespace ppk
 
-// first-level contraction geometry (ppals.cpp)
+// first-level contraction geometry and the multiplier of the strided loads' divisions
+// (ppals.cpp)
 ppk::Level1Geom l1_geom(int64_t P, int64_t K, int64_t Q, int R, int l1dt);
+void l1_magic(uint32_t d, uint64_t* mag, int* sh);
