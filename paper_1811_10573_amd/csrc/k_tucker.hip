@@ -151,6 +151,20 @@ __device__ __forceinline__ double rr_block_sum(double v, double* red) {
   return t;
 }
 
+// Maximum of v over the workgroup (256 threads); every thread gets it.
+__device__ __forceinline__ double rr_block_max(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double t = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  __syncthreads();
+  return t;
+}
+
+// Below this max |B - I| the inverse square root series replaces the Cholesky factor.
+constexpr double kRRSeriesTol = 1e-6;
+
 __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs a) {
   __shared__ double L[64 * RRS];   // B, trailing updates; later scratch (Z, T)
   __shared__ double Lc[64 * RRS];  // Cholesky factor; later the Jacobi eigenvectors
@@ -175,6 +189,32 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs a) {
   }
   if (tid == 0) bad = 0;
   __syncthreads();
+  double em = 0.0;
+  for (int e = tid; e < R * R; e += 256) {
+    const int i = e / R, k = e - i * R;
+    em = fmax(em, fabs(L[i * RRS + k] - (i == k ? 1.0 : 0.0)));
+  }
+  em = rr_block_max(em, red);
+  if (em < kRRSeriesTol) {
+    // V is orthonormal up to E = B - I: Li = B^-1/2 = I - E/2 + 3/8 E^2 - 5/16 E^3 (the
+    // next term is O(|E|^4) < 1e-22 R^4), symmetric, so that Li B Li^T = I as with the
+    // Cholesky factor below.  Horner form: Li = I + E (-I/2 + E (3/8 I - 5/16 E)).
+    for (int e = tid; e < R * R; e += 256) {
+      const int i = e / R, k = e - i * R;
+      const double ev = L[i * RRS + k] - (i == k ? 1.0 : 0.0);
+      L[i * RRS + k] = ev;
+      Li[i * RRS + k] = (i == k ? 0.375 : 0.0) - 0.3125 * ev;
+    }
+    __syncthreads();
+    rr_product(Lc, L, RRS, 1, Li, RRS, 1, R);
+    __syncthreads();
+    for (int i = tid; i < R; i += 256) Lc[i * RRS + i] -= 0.5;
+    __syncthreads();
+    rr_product(Li, L, RRS, 1, Lc, RRS, 1, R);
+    __syncthreads();
+    for (int i = tid; i < R; i += 256) Li[i * RRS + i] += 1.0;
+    __syncthreads();
+  } else {
   // Cholesky of B: Lc = L with L L^T = B (lower)
   for (int j = 0; j < R; ++j) {
     const double d0 = L[j * RRS + j];
@@ -211,6 +251,7 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs a) {
     }
   }
   __syncthreads();
+  }
   // H' = Li H Li^T: Z = Li H into L, then H = Z Li^T
   rr_product(L, Li, RRS, 1, H, RRS, 1, R);
   __syncthreads();

@@ -62,6 +62,8 @@ struct tucker_plan {
   size_t ws_bytes = 0;
   bool built = false;
   bool dA_zero[3] = {true, true, true};
+  bool pp_optimistic = true;  // PP sweeps: one unchecked subspace iteration per mode first
+  size_t o_Astart[3];
   void* built_ws = nullptr;
 };
 
@@ -226,6 +228,33 @@ struct IterInfo {
   int32_t jacobi_sweeps;
 };
 
+// One subspace iteration on the basis V of the workspace: C = W V, the projections, the
+// Rayleigh-Ritz step and the Ritz update (U, residual into info, next basis in V).
+// Enqueues only.  has_prev: A_prev is in the basis region's third slot.
+ppals_status subspace_step(const TCtx& c, int n, const double* Y, const double* X, bool has_prev,
+                           IterInfo* info) {
+  tucker_plan* p = c.p;
+  const int R = p->R;
+  const int64_t sn = p->s[n];
+  double* V = c.d(p->o_V);
+  double* C = c.d(p->o_C);
+  TCHK(apply_w(c, n, Y, X, V, C));  // C = W V
+  TCHK(projections(c, sn, has_prev ? 3 : 2));
+  RRArgs rr;
+  rr.R = R;
+  rr.B = c.d(p->o_B);
+  rr.H = c.d(p->o_H);
+  rr.P = has_prev ? c.d(p->o_P) : nullptr;
+  rr.T = c.d(p->o_T);
+  rr.lam = c.d(p->o_lam);
+  rr.status = &info->rr_bad;
+  THIPCHK(launch_rayleigh_ritz(rr, c.s));
+  // Ritz vectors U, the residual, and the next basis V <- W U diag(lam)^-1
+  THIPCHK(launch_ritz_update(V, C, rr.T, rr.lam, c.d(p->o_U), c.d(p->o_rpart), sn, R,
+                             &info->residual, c.s));
+  return PPALS_OK;
+}
+
 // Subspace iteration for the R leading eigenvectors of W (s_n x s_n), W = Y_(n) Y_(n)^T
 // for a TTMc Y or, with Y null, X_(n) X_(n)^T (the HOSVD).  V starts from V0; A_prev (may
 // be null) orients the columns.  Result into A_out.
@@ -241,7 +270,7 @@ ppals_status subspace(const TCtx& c, int n, const double* Y, const double* X, co
   double* T = c.d(p->o_T);
   double* lam = c.d(p->o_lam);
   double* Aold = c.d(p->o_Aold);
-  IterInfo* dinfo = reinterpret_cast<IterInfo*>(c.ws + p->o_info);
+  IterInfo* dinfo = reinterpret_cast<IterInfo*>(c.ws + p->o_info) + n;
   if (A_prev && A_prev != Aold) THIPCHK(launch_copy(Aold, A_prev, sn * R, c.s));
   THIPCHK(launch_copy(V, V0, sn * R, c.s));
   IterInfo hinfo;
@@ -250,19 +279,7 @@ ppals_status subspace(const TCtx& c, int n, const double* Y, const double* X, co
   bool conv = false;
   while (it < max_iters) {
     ++it;
-    TCHK(apply_w(c, n, Y, X, V, C));  // C = W V
-    TCHK(projections(c, sn, A_prev ? 3 : 2));
-    RRArgs rr;
-    rr.R = R;
-    rr.B = c.d(p->o_B);
-    rr.H = c.d(p->o_H);
-    rr.P = A_prev ? c.d(p->o_P) : nullptr;
-    rr.T = T;
-    rr.lam = lam;
-    rr.status = &dinfo->rr_bad;
-    THIPCHK(launch_rayleigh_ritz(rr, c.s));
-    // Ritz vectors U, the residual, and the next basis V <- W U diag(lam)^-1
-    THIPCHK(launch_ritz_update(V, C, T, lam, U, c.d(p->o_rpart), sn, R, &dinfo->residual, c.s));
+    TCHK(subspace_step(c, n, Y, X, A_prev != nullptr, dinfo));
     THIPCHK(hipMemcpyAsync(&hinfo, dinfo, sizeof(hinfo), hipMemcpyDeviceToHost, c.s));
     THIPCHK(hipStreamSynchronize(c.s));
     bad |= hinfo.rr_bad;
@@ -271,6 +288,10 @@ ppals_status subspace(const TCtx& c, int n, const double* Y, const double* X, co
       break;
     }
   }
+  (void)V;
+  (void)C;
+  (void)T;
+  (void)lam;
   THIPCHK(launch_copy(A_out, U, sn * R, c.s));
   if (!A_prev) THIPCHK(launch_sign_by_max(A_out, sn, R, c.s));
   if (info) {
@@ -306,13 +327,14 @@ ppals_status als_ttmc(const TCtx& c, const double* X, double* const* A, int n, b
 
 // Core from Y^(3) (x3, r1, r2) and A^(3): G (r1, r2, r3); stats[6..7] = ||G||^2, ||G - G_old||^2;
 // G_old <- G.
-ppals_status finish_core(const TCtx& c, const double* Y3, const double* A3, double* G) {
+ppals_status finish_core(const TCtx& c, const double* Y3, const double* A3, double* G,
+                         bool commit = true) {
   tucker_plan* p = c.p;
   const int64_t R = p->R;
   double* Gn = c.d(p->o_Gn);
   TCHK(ttm(c, Y3, {1, p->s[2], R * R}, A3, Gn));
   THIPCHK(launch_core_stats(Gn, G, R * R * R, c.d(p->o_stats) + 6, c.s));
-  THIPCHK(launch_copy(G, Gn, R * R * R, c.s));
+  if (commit) THIPCHK(launch_copy(G, Gn, R * R * R, c.s));
   return PPALS_OK;
 }
 
@@ -430,7 +452,8 @@ ppals_status tucker_plan_create(const int64_t dims[3], int32_t rank, tucker_plan
   p->o_rpart = take(((smax + kRitzRows - 1) / kRitzRows) * R);
   p->o_T = take(R * R);
   p->o_lam = take(R);
-  p->o_info = take(4);
+  p->o_info = take(8);  // an iteration record per mode
+  for (int n = 0; n < 3; ++n) p->o_Astart[n] = take(dims[n] * R);
   p->o_stats = take(8);
   size_t prep = 1, part = 1;
   for (const Contr& k : all_contractions(p)) {
@@ -568,6 +591,7 @@ ppals_status tucker_pp_build(tucker_plan* plan, void* ws, const double* X, doubl
   TCHK(ttm(c, op12, {1, s1, s2 * R}, A[1], c.d(plan->o_Yp[2])));  // (x3, r1, r2)
   plan->built = true;
   plan->built_ws = ws;
+  plan->pp_optimistic = true;
   return PPALS_OK;
 }
 
@@ -600,22 +624,74 @@ ppals_status tucker_pp_sweep(tucker_plan* plan, void* ws, double* const* A, doub
   double* Aold = c.d(plan->o_Aold);
   double* stats = c.d(plan->o_stats);
   const int R = plan->R;
-  for (int n = 0; n < 3; ++n) {
-    TCHK(pp_rhs_impl(c, n, Y));
-    THIPCHK(launch_copy(Aold, A[n], plan->s[n] * R, stream));
-    int32_t info[3];
-    TCHK(subspace(c, n, Y, nullptr, Aold, Aold, A[n], plan->max_iters, info,
-                  &rec->ritz_residual[n]));
-    rec->iters[n] = info[0];
-    rec->converged[n] = info[1];
-    rec->rr_status[n] = info[2];
-    double* dA = c.d(plan->o_dA[n]);
-    const double* Ap = c.d(plan->o_Ap[n]);
-    THIPCHK(launch_sub(dA, A[n], Ap, plan->s[n] * R, stream));
-    plan->dA_zero[n] = false;
-    THIPCHK(launch_core_stats(A[n], Ap, plan->s[n] * R, stats + 2 * n, stream));
+  IterInfo* dinfo = reinterpret_cast<IterInfo*>(c.ws + plan->o_info);
+  int n0 = 0;  // first mode of the synchronised pass
+  if (plan->pp_optimistic) {
+    // One subspace iteration per mode with no host synchronisation; the residuals are
+    // read once at the end.  If a mode did not converge, that mode and the later ones are
+    // restored and redone below with a check after every iteration (same launches in the
+    // same order, so the result does not depend on the path).
+    bool zero_start[3];
+    for (int n = 0; n < 3; ++n) {
+      zero_start[n] = plan->dA_zero[n];
+      THIPCHK(launch_copy(c.d(plan->o_Astart[n]), A[n], plan->s[n] * R, stream));
+    }
+    for (int n = 0; n < 3; ++n) {
+      TCHK(pp_rhs_impl(c, n, Y));
+      THIPCHK(launch_copy(Aold, A[n], plan->s[n] * R, stream));
+      THIPCHK(launch_copy(c.d(plan->o_V), Aold, plan->s[n] * R, stream));
+      TCHK(subspace_step(c, n, Y, nullptr, true, dinfo + n));
+      THIPCHK(launch_copy(A[n], c.d(plan->o_U), plan->s[n] * R, stream));
+      double* dA = c.d(plan->o_dA[n]);
+      const double* Ap = c.d(plan->o_Ap[n]);
+      THIPCHK(launch_sub(dA, A[n], Ap, plan->s[n] * R, stream));
+      plan->dA_zero[n] = false;
+      THIPCHK(launch_core_stats(A[n], Ap, plan->s[n] * R, stats + 2 * n, stream));
+    }
+    TCHK(finish_core(c, Y, A[2], G, false));
+    IterInfo hi[3];
+    THIPCHK(hipMemcpyAsync(hi, dinfo, sizeof(hi), hipMemcpyDeviceToHost, stream));
+    THIPCHK(hipStreamSynchronize(stream));
+    n0 = 3;
+    for (int n = 2; n >= 0; --n)
+      if (!(hi[n].residual <= plan->tol)) n0 = n;
+    for (int n = 0; n < n0; ++n) {
+      rec->iters[n] = 1;
+      rec->converged[n] = 1;
+      rec->rr_status[n] = hi[n].rr_bad;
+      rec->ritz_residual[n] = hi[n].residual;
+    }
+    if (n0 == 3) {
+      THIPCHK(launch_copy(G, c.d(plan->o_Gn), (int64_t)R * R * R, stream));
+    } else {
+      plan->pp_optimistic = false;
+      for (int n = n0; n < 3; ++n) {
+        THIPCHK(launch_copy(A[n], c.d(plan->o_Astart[n]), plan->s[n] * R, stream));
+        THIPCHK(launch_sub(c.d(plan->o_dA[n]), A[n], c.d(plan->o_Ap[n]), plan->s[n] * R, stream));
+        plan->dA_zero[n] = zero_start[n];
+      }
+    }
   }
-  TCHK(finish_core(c, Y, A[2], G));
+  if (n0 < 3) {
+    for (int n = n0; n < 3; ++n) {
+      TCHK(pp_rhs_impl(c, n, Y));
+      THIPCHK(launch_copy(Aold, A[n], plan->s[n] * R, stream));
+      int32_t info[3];
+      TCHK(subspace(c, n, Y, nullptr, Aold, Aold, A[n], plan->max_iters, info,
+                    &rec->ritz_residual[n]));
+      rec->iters[n] = info[0];
+      rec->converged[n] = info[1];
+      rec->rr_status[n] = info[2];
+      double* dA = c.d(plan->o_dA[n]);
+      const double* Ap = c.d(plan->o_Ap[n]);
+      THIPCHK(launch_sub(dA, A[n], Ap, plan->s[n] * R, stream));
+      plan->dA_zero[n] = false;
+      THIPCHK(launch_core_stats(A[n], Ap, plan->s[n] * R, stats + 2 * n, stream));
+    }
+    TCHK(finish_core(c, Y, A[2], G));
+    // back to the unsynchronised pass once a sweep needs a single iteration everywhere
+    plan->pp_optimistic = rec->iters[0] == 1 && rec->iters[1] == 1 && rec->iters[2] == 1;
+  }
   double h[8];
   THIPCHK(hipMemcpyAsync(h, stats, sizeof(h), hipMemcpyDeviceToHost, stream));
   THIPCHK(hipStreamSynchronize(stream));

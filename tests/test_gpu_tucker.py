@@ -211,3 +211,33 @@ def test_pp_sweep_needs_a_build():
     with pytest.raises(pk.PPALSError) as e:
         pk.tucker_pp_sweep(r.plan, r.ws, r.A, r.G, r.normX2)
     assert e.value.status == -5
+
+
+def test_pp_sweeps_through_every_solver_path_match_oracle():
+    """PP sweeps run one unchecked subspace iteration per mode first and redo from the
+    first mode that did not converge.  A tolerance the first iteration cannot meet forces
+    the redo (all modes, capped iteration count); the following sweeps run checked until
+    one needs a single iteration in every mode, and the sweep after such a sweep runs
+    unchecked again.  Every sweep's factors and fit against the oracle's."""
+    shape, R = (60, 52, 47), 8
+    r = TRun(shape, R, seed=17, eta=0.2)
+    A0, G0 = ot.hosvd(r.prob.X, (R, R, R))
+    A1, G1, _ = ot.tucker_als(r.prob.X, A0, G0, 2)
+    r.upload(A1, G1)
+    pk.tucker_pp_build(r.plan, r.ws, r.X, r.A)
+    st = ot.build_operators(r.prob.X, A1)
+    A_or, G_or = [a.copy() for a in A1], G1.copy()
+    plan_iters = []
+    for k, tol in enumerate([1e-30, 1e-12, 1e-12, 1e-12, 1e-12]):
+        r.plan.set_solver(tol, 4 if tol < 1e-20 else 500, 5000)
+        kind = "pp_init" if k == 0 else "pp_approx"
+        rec = pk.tucker_pp_sweep(r.plan, r.ws, r.A, r.G, r.normX2, kind)
+        G_or, w = ot.pp_sweep(st, A_or, G_or, r.normX2, kind)
+        plan_iters.append(rec["iters"])
+        assert abs(rec["fit"] - w.fit) <= 1e-10, (k, rec, w.fit)
+        for n, (got, want) in enumerate(zip(r.factors(), A_or)):
+            np.testing.assert_allclose(got, want, atol=1e-8, rtol=0, err_msg=f"sweep {k} A^({n})")
+        assert_rel(r.core(), G_or, 1e-8, f"sweep {k} core")
+    assert plan_iters[0] == [4, 4, 4], plan_iters
+    # the last sweep follows a sweep with one iteration per mode: the unchecked pass
+    assert plan_iters[-2] == [1, 1, 1] and plan_iters[-1] == [1, 1, 1], plan_iters
