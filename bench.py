@@ -617,6 +617,46 @@ def build_leg(pp, torch, dev, tensorgen, shape=(160, 160, 160, 160), R=64, tier=
     return out
 
 
+def sweep_kinds_leg(pp, torch, dev, tensorgen, shape, R, tier, n_approx=6):
+    """Per-sweep device time of each sweep kind on one configuration, with the kinds forced
+    (three ALS sweeps, a PP initialisation, n_approx PP-approximated sweeps; the first ALS
+    sweep is a warm-up), as in the paper's per-sweep comparison of Section 5.1."""
+    prob = tensorgen.make_problem_device(shape, R, 0, eta=1e-2, dtype=tier, device=dev)
+    X = prob.X.reshape(-1)
+    plan = pp.Plan(shape, R, tier, tier, True)
+    ws = plan.workspace(dev)
+    A = [torch.from_numpy(a).to(dev) for a in prob.init]
+    S = torch.zeros(len(shape) * R * R, dtype=torch.float64, device=dev)
+    rec = pp.new_record(dev)
+    nrm = torch.zeros(1, dtype=torch.float64, device=dev)
+    pp.tensor_norm2(X, nrm)
+    kinds = ["als"] * 3 + ["pp_init"] + ["pp_approx"] * n_approx
+    recs, ms = pp.run(plan, X, None, A, S, float(nrm.item()), ws, rec, eps=0.1,
+                      max_sweeps=len(kinds), replay=kinds, timing=True)
+    got = [r["kind"] for r in recs]
+    assert got == kinds, got
+    per = {}
+    for k in ("als", "pp_init", "pp_approx"):
+        t = [m for i, (r, m) in enumerate(zip(recs, ms)) if r["kind"] == k and i > 0]
+        per[k] = float(np.mean(t))
+    out = {"shape": list(shape), "rank": R, "tier": tier, "ms": per,
+           "pp_approx_speedup_vs_dt_sweep": per["als"] / per["pp_approx"],
+           "pp_init_over_dt_sweep": per["pp_init"] / per["als"]}
+    log(f"sweep kinds {shape} R {R} {tier}: DT {per['als']:.3f} ms, PP-init {per['pp_init']:.3f} ms, "
+        f"PP-approx {per['pp_approx']:.3f} ms ({out['pp_approx_speedup_vs_dt_sweep']:.1f}x)")
+    del X, ws, plan, prob
+    torch.cuda.empty_cache()
+    return out
+
+
+PAPER_SWEEP_CONFIGS = (
+    # order 3 with R = s (the rank cap is 128)
+    ((64, 64, 64), 64), ((128, 128, 128), 128),
+    # s = 960^(3/N), R = 50 for N = 3..6
+    ((960,) * 3, 50), ((172,) * 4, 50), ((62,) * 5, 50), ((31,) * 6, 50),
+)
+
+
 def ablation_bench(args, torch, dev):
     """The second-order correction ablation of the synthetic collinearity experiments
     (Section 5.1): fit against time for dimension-tree ALS, PP with the second-order
@@ -786,7 +826,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dt", action="store_true")
     ap.add_argument("--workload", default="pp",
-                    choices=["pp", "batch", "ablation", "tucker", "build"],
+                    choices=["pp", "batch", "ablation", "tucker", "build", "sweeps"],
                     help="pp: the 800^3 decomposition (default); batch: 512 independent problems; "
                          "ablation: PP with and without the second-order term against DT-ALS")
     ap.add_argument("--abl-size", type=int, default=64)
@@ -823,6 +863,11 @@ def main():
         return
     if args.workload == "ablation":
         ablation_bench(args, torch, dev)
+        return
+    if args.workload == "sweeps":
+        res = [sweep_kinds_leg(pp, torch, dev, tensorgen, shape, R, tier)
+               for tier in ("f64", "f32") for shape, R in PAPER_SWEEP_CONFIGS]
+        print(json.dumps(res), flush=True)
         return
     if args.workload == "build":
         res = [build_leg(pp, torch, dev, tensorgen, (160,) * 4, 64, "f32"),
@@ -1025,7 +1070,7 @@ def main():
     # 64^3 ALS configuration and the first-level contractions of the 160^4 configuration
     extras = (not args.no_extras and args.tier == "f32" and shape == (800, 800, 800)
               and R == 50 and not args.device_gen)
-    f64 = c1 = c3 = batch = tucker = build = None
+    f64 = c1 = c3 = batch = tucker = build = sweep_cfgs = None
     A_f64_replay = c1prob = None
     if extras:
         del ws
@@ -1041,6 +1086,8 @@ def main():
         tucker = tucker_leg(pp, torch, dev, tensorgen, s=800, R=40,
                             cpu_seconds=0.0 if args.no_cpu_baseline else 4.0)
         build = build_leg(pp, torch, dev, tensorgen, (160,) * 4, 64, "f32")
+        sweep_cfgs = [sweep_kinds_leg(pp, torch, dev, tensorgen, shape, R, "f64")
+                      for shape, R in PAPER_SWEEP_CONFIGS]
 
     cpu = None
     vs_oracle = None
@@ -1129,6 +1176,7 @@ def main():
         "c5_batch": batch,
         "f1_tucker": tucker,
         "f2_direct_build": build,
+        "paper_sweep_configs_f64": sweep_cfgs,
         "paper_reference": PAPER_NUMBERS,
         "kernels": kernels,
     }

@@ -38,31 +38,35 @@ __device__ double block_sum(double v, double* red) {
 // Cholesky (lower) of the R x R matrix a (row-major, in LDS), right-looking.
 // Returns -1 on success, else the 0-based index of the first pivot that is not positive
 // and finite.  All threads of the block participate.
-__device__ int chol_lds(double* a, int R, int* flag) {
+// Cholesky factorisation in place (lower) of the R x R matrix a with row stride LS (R + 1:
+// consecutive rows fall in different LDS banks).  Returns -1, or the index of the first
+// pivot that is not positive and finite (the matrix is then left partly factorised).
+// One barrier per column: at step j every thread reads the pivot, updates the trailing
+// block with column j scaled on the fly (the same roundings as scaling the column first),
+// and scales column j - 1, which no longer takes part.  16 x 16 thread grid, no divisions.
+__device__ int chol_lds(double* a, int R, int LS) {
   const int tid = threadIdx.x;
-  if (tid == 0) *flag = 0;
+  const int ti = tid >> 4, tk = tid & 15;
+  double prev_inv = 0.0, prev_sd = 0.0;
   __syncthreads();
   for (int j = 0; j < R; ++j) {
-    if (tid == 0) {
-      const double d = a[j * R + j];
-      if (!(d > 0.0) || !isfinite(d)) *flag = 1;
-      else a[j * R + j] = sqrt(d);
+    const double d = a[j * LS + j];
+    if (!(d > 0.0) || !isfinite(d)) return j;  // the same value in every thread
+    const double sd = sqrt(d);
+    const double inv = 1.0 / sd;
+    if (j > 0)
+      for (int i = j - 1 + tid; i < R; i += blockDim.x)
+        a[i * LS + j - 1] = (i == j - 1) ? prev_sd : a[i * LS + j - 1] * prev_inv;
+    for (int i = j + 1 + ti; i < R; i += 16) {
+      const double lij = a[i * LS + j] * inv;
+      for (int k = j + 1 + tk; k <= i; k += 16) a[i * LS + k] -= lij * (a[k * LS + j] * inv);
     }
-    __syncthreads();
-    if (*flag) return j;
-    const double inv = 1.0 / a[j * R + j];
-    for (int i = j + 1 + tid; i < R; i += blockDim.x) a[i * R + j] *= inv;
-    __syncthreads();
-    const int m = R - j - 1;
-    for (int e = tid; e < m * m; e += blockDim.x) {
-      const int ii = e / m, kk = e - ii * m;
-      if (kk <= ii) {
-        const int i = j + 1 + ii, k = j + 1 + kk;
-        a[i * R + k] -= a[i * R + j] * a[k * R + j];
-      }
-    }
+    prev_inv = inv;
+    prev_sd = sd;
     __syncthreads();
   }
+  if (tid == 0) a[(R - 1) * LS + R - 1] = prev_sd;  // the last column is its diagonal
+  __syncthreads();
   return -1;
 }
 
@@ -74,11 +78,10 @@ __device__ __forceinline__ int chol_status_lds(int code, int pivot) { return cod
 // One workgroup: finish mode `prev` (record entries, fit) and prepare mode `n`
 // (Gamma, W, Cholesky with the diagonal-shift retry).
 __global__ __launch_bounds__(256) void k_mode_begin(ModeArgs a) {
-  extern __shared__ double sm[];  // R*R
+  extern __shared__ double sm[];  // R x R, row stride R + 1
   __shared__ double red[8];
-  __shared__ int flag;
   const int tid = threadIdx.x;
-  const int R = a.R, RR = R * R;
+  const int R = a.R, RR = R * R, LS = R + 1;
   ppals_sweep_record* rec = (ppals_sweep_record*)a.rec;
 
   if (a.prev >= 0) {
@@ -122,7 +125,7 @@ __global__ __launch_bounds__(256) void k_mode_begin(ModeArgs a) {
     double v = 1.0;
     for (int i = 0; i < N; ++i)
       if (i != n) v *= a.S[(int64_t)i * RR + e];
-    sm[e] = v;
+    sm[(e / R) * LS + e % R] = v;
     a.gamma[e] = v;
     if (a.pp && a.second_order) {
       double w = 0.0;
@@ -141,7 +144,7 @@ __global__ __launch_bounds__(256) void k_mode_begin(ModeArgs a) {
   }
   __syncthreads();
   int st = 0;
-  const int piv0 = chol_lds(sm, R, &flag);
+  const int piv0 = chol_lds(sm, R, LS);
   if (piv0 >= 0) {
     // retry with Gamma + delta I, delta = R 2^-52 max(diag Gamma)
     double mx = 0.0;
@@ -160,14 +163,13 @@ __global__ __launch_bounds__(256) void k_mode_begin(ModeArgs a) {
     const double delta = (double)R * 0x1p-52 * mxs[0];
     for (int e = tid; e < RR; e += blockDim.x) {
       const int i = e / R, k = e - (e / R) * R;
-      sm[e] = a.gamma[e] + (i == k ? delta : 0.0);
+      sm[i * LS + k] = a.gamma[e] + (i == k ? delta : 0.0);
     }
-    __syncthreads();
-    st = chol_lds(sm, R, &flag) < 0 ? 1 : 2;
+    st = chol_lds(sm, R, LS) < 0 ? 1 : 2;
   }
   for (int e = tid; e < RR; e += blockDim.x) {
     const int i = e / R, k = e - (e / R) * R;
-    a.L[e] = (k <= i) ? sm[e] : 0.0;
+    a.L[e] = (k <= i) ? sm[i * LS + k] : 0.0;
   }
   if (tid == 0) a.status[n] = chol_status_lds(st, piv0);
 }
@@ -425,14 +427,12 @@ __global__ void k_finish_gram_solve(const double* __restrict__ rowpart, int64_t 
 
 __global__ __launch_bounds__(256) void k_chol_standalone(const double* gamma, int R, double* L,
                                                          int* status) {
-  extern __shared__ double sm[];
-  __shared__ int flag;
+  extern __shared__ double sm[];  // R x R, row stride R + 1
   __shared__ double mxs;
-  const int RR = R * R;
-  for (int e = threadIdx.x; e < RR; e += blockDim.x) sm[e] = gamma[e];
-  __syncthreads();
+  const int RR = R * R, LS = R + 1;
+  for (int e = threadIdx.x; e < RR; e += blockDim.x) sm[(e / R) * LS + e % R] = gamma[e];
   int st = 0;
-  const int piv0 = chol_lds(sm, R, &flag);
+  const int piv0 = chol_lds(sm, R, LS);
   if (piv0 >= 0) {
     if (threadIdx.x == 0) {
       double m2 = 0.0;
@@ -443,14 +443,13 @@ __global__ __launch_bounds__(256) void k_chol_standalone(const double* gamma, in
     const double delta = (double)R * 0x1p-52 * mxs;
     for (int e = threadIdx.x; e < RR; e += blockDim.x) {
       const int i = e / R, k = e - (e / R) * R;
-      sm[e] = gamma[e] + (i == k ? delta : 0.0);
+      sm[i * LS + k] = gamma[e] + (i == k ? delta : 0.0);
     }
-    __syncthreads();
-    st = chol_lds(sm, R, &flag) < 0 ? 1 : 2;
+    st = chol_lds(sm, R, LS) < 0 ? 1 : 2;
   }
   for (int e = threadIdx.x; e < RR; e += blockDim.x) {
     const int i = e / R, k = e - (e / R) * R;
-    L[e] = (k <= i) ? sm[e] : 0.0;
+    L[e] = (k <= i) ? sm[i * LS + k] : 0.0;
   }
   if (threadIdx.x == 0) *status = chol_status_lds(st, piv0);
 }
@@ -465,7 +464,7 @@ static hipError_t allow_lds(K kernel, size_t bytes) {
 }
 
 hipError_t launch_mode_begin(const ModeArgs& a, hipStream_t s) {
-  size_t lds = (size_t)a.R * a.R * sizeof(double);
+  size_t lds = (size_t)a.R * (a.R + 1) * sizeof(double);
   hipError_t e = allow_lds(k_mode_begin, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_mode_begin, dim3(1), dim3(256), lds, s, a);
@@ -550,9 +549,9 @@ hipError_t launch_finish_gram_solve(const double* rowpart, int64_t rows, double*
 
 hipError_t launch_chol_standalone(const double* gamma, int R, double* L, int* status,
                                   hipStream_t s) {
-  hipError_t e = allow_lds(k_chol_standalone, (size_t)R * R * sizeof(double));
+  hipError_t e = allow_lds(k_chol_standalone, (size_t)R * (R + 1) * sizeof(double));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_chol_standalone, dim3(1), dim3(256), (size_t)R * R * sizeof(double), s,
+  hipLaunchKernelGGL(k_chol_standalone, dim3(1), dim3(256), (size_t)R * (R + 1) * sizeof(double), s,
                      gamma, R, L, status);
   return hipGetLastError();
 }
