@@ -617,13 +617,13 @@ def build_leg(pp, torch, dev, tensorgen, shape=(160, 160, 160, 160), R=64, tier=
     return out
 
 
-def sweep_kinds_leg(pp, torch, dev, tensorgen, shape, R, tier, n_approx=6):
+def sweep_kinds_leg(pp, torch, dev, tensorgen, shape, R, tier, n_approx=6, pp_build="auto"):
     """Per-sweep device time of each sweep kind on one configuration, with the kinds forced
     (three ALS sweeps, a PP initialisation, n_approx PP-approximated sweeps; the first ALS
     sweep is a warm-up), as in the paper's per-sweep comparison of Section 5.1."""
     prob = tensorgen.make_problem_device(shape, R, 0, eta=1e-2, dtype=tier, device=dev)
     X = prob.X.reshape(-1)
-    plan = pp.Plan(shape, R, tier, tier, True)
+    plan = pp.Plan(shape, R, tier, tier, True, pp_build=pp_build)
     ws = plan.workspace(dev)
     A = [torch.from_numpy(a).to(dev) for a in prob.init]
     S = torch.zeros(len(shape) * R * R, dtype=torch.float64, device=dev)
@@ -639,7 +639,9 @@ def sweep_kinds_leg(pp, torch, dev, tensorgen, shape, R, tier, n_approx=6):
     for k in ("als", "pp_init", "pp_approx"):
         t = [m for i, (r, m) in enumerate(zip(recs, ms)) if r["kind"] == k and i > 0]
         per[k] = float(np.mean(t))
+    d = plan.describe()
     out = {"shape": list(shape), "rank": R, "tier": tier, "ms": per,
+           "pp_build_levels": d["pp_build_levels"], "workspace_GB": plan.workspace_bytes / 1e9,
            "pp_approx_speedup_vs_dt_sweep": per["als"] / per["pp_approx"],
            "pp_init_over_dt_sweep": per["pp_init"] / per["als"]}
     log(f"sweep kinds {shape} R {R} {tier}: DT {per['als']:.3f} ms, PP-init {per['pp_init']:.3f} ms, "
@@ -867,6 +869,8 @@ def main():
     if args.workload == "sweeps":
         res = [sweep_kinds_leg(pp, torch, dev, tensorgen, shape, R, tier)
                for tier in ("f64", "f32") for shape, R in PAPER_SWEEP_CONFIGS]
+        res += [sweep_kinds_leg(pp, torch, dev, tensorgen, shape, R, "f64", pp_build="tree")
+                for shape, R in PAPER_SWEEP_CONFIGS[3:]]
         print(json.dumps(res), flush=True)
         return
     if args.workload == "build":

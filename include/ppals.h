@@ -78,12 +78,16 @@ typedef struct {
   int32_t tensor_dtype;
   int32_t level1_dtype;
   int32_t use_second_order;
-  /* Operator build (Section 3.2.3, memory footprint): 0 runs the PP dimension tree, which
-   * keeps first-level intermediates of O(s^(N-1) R) elements; 1 contracts X directly with
-   * the Khatri-Rao product of the other N-2 factors for every operator M_p^(i,j) (one pass
-   * over X per operator, no intermediates).  Order 3 builds the same either way.  1 needs
-   * the FP64 or FP32 first level and prod of the contracted dims below 2^31 - 64. */
-  int32_t pp_build_direct;
+  /* Operator build (Section 3.2.3, cost and memory footprint): the number l of leading
+   * levels of the PP dimension tree to combine.  0 or 1 runs the tree, whose first level
+   * keeps intermediates of O(s^(N-1) R) elements; l >= 2 computes the nodes of tree level
+   * l + 1 straight from X, contracting l modes at once with their Khatri-Rao product (one
+   * pass over X per node), and only the later levels from parents; l >= N - 2 computes
+   * every operator M_p^(i,j) from X (no intermediates).  -1 lets the plan choose l from a
+   * roofline model of the build (ppals_plan_describe reports it).  l >= 2 needs the FP64
+   * or FP32 first level and contracted extents below 2^31 - 64.  Order 3 always runs
+   * the tree (its first level holds the operators). */
+  int32_t pp_build_levels;
   /* Update step size lambda of the step-size variant of ALS (Section 5.1): every factor
    * update of the ALS and PP sweeps is A_new = (1 - lambda) A + lambda M Gamma^-1; the
    * record's gradient stays the one at A before the update, (A - M Gamma^-1) Gamma.

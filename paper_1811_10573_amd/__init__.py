@@ -82,9 +82,18 @@ class Plan:
         d.level1_dtype = _DTYPES[level1_dtype]
         d.use_second_order = 1 if second_order else 0
         d.step_size = float(step_size)
-        if pp_build not in ("tree", "direct"):
-            raise ValueError("pp_build must be 'tree' or 'direct'")
-        d.pp_build_direct = 1 if pp_build == "direct" else 0
+        # "tree", "direct" (every operator from X), "auto" (the plan's cost model) or the
+        # number of leading tree levels to combine
+        if pp_build == "tree":
+            d.pp_build_levels = 0
+        elif pp_build == "direct":
+            d.pp_build_levels = max(1, len(dims) - 2)
+        elif pp_build == "auto":
+            d.pp_build_levels = -1
+        elif isinstance(pp_build, int) and pp_build >= 0:
+            d.pp_build_levels = pp_build
+        else:
+            raise ValueError("pp_build must be 'tree', 'direct', 'auto' or a level count")
         h = ctypes.c_void_p()
         _lib.check(lib().ppals_plan_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h

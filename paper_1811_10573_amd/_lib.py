@@ -28,7 +28,7 @@ class Desc(ctypes.Structure):
         ("tensor_dtype", ctypes.c_int32),
         ("level1_dtype", ctypes.c_int32),
         ("use_second_order", ctypes.c_int32),
-        ("pp_build_direct", ctypes.c_int32),
+        ("pp_build_levels", ctypes.c_int32),
         ("step_size", ctypes.c_double),
     ]
 

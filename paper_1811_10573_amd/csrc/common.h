@@ -32,12 +32,12 @@ struct Level1Geom {
   int ksplit;      // split of K across workgroups
   int64_t kchunk;  // k-values per split (multiple of KC)
   // Strided rows and contracted index (direct operator build, FP64/FP32, scalar loads).
-  // When strided != 0, row m = m0 * mrad + m1 (m1 < mrad) starts at X offset
-  // m0 * ms0 + m1 * ms1, and k = (k0 * kr1 + k1) * kr2 + k2 (k1 < kr1, k2 < kr2) adds
-  // k0 * ks0 + k1 * ks1 + k2 * ks2.  kmag1/ksh1 and kmag2/ksh2 divide by kr1 and kr2:
-  // q = (n * kmag) >> (32 + ksh), exact for n < 2^31.
+  // When strided != 0, row m = (m0 * mrad + m1) * mrad2 + m2 (m1 < mrad, m2 < mrad2)
+  // starts at X offset m0 * ms0 + m1 * ms1 + m2 * ms2, and k = (k0 * kr1 + k1) * kr2 + k2
+  // (k1 < kr1, k2 < kr2) adds k0 * ks0 + k1 * ks1 + k2 * ks2.  kmag1/ksh1 and kmag2/ksh2
+  // divide by kr1 and kr2: q = (n * kmag) >> (32 + ksh), exact for n < 2^31.
   int strided;
-  int64_t mrad, ms0, ms1;
+  int64_t mrad, ms0, ms1, mrad2, ms2;
   uint32_t kr1, kr2;
   uint64_t kmag1, kmag2;
   int ksh1, ksh2;

@@ -215,8 +215,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DT == DT_F3
     for (int b = 0; b < MB; ++b) {
       const int64_t gr = g0w + 16 * b + i;
       rowok[b] = gr < gM;
-      const int64_t m0 = gr / g.mrad, m1 = gr - m0 * g.mrad;
-      base[b] = rowok[b] ? m0 * g.ms0 + m1 * g.ms1 : 0;
+      const int64_t q = gr / g.mrad2, m2 = gr - q * g.mrad2;
+      const int64_t m0 = q / g.mrad, m1 = q - m0 * g.mrad;
+      base[b] = rowok[b] ? m0 * g.ms0 + m1 * g.ms1 + m2 * g.ms2 : 0;
     }
   } else {
 #pragma unroll

@@ -150,7 +150,9 @@ struct ppals_plan {
   bool la_cur = false, la_gate_fused = false;
   double la_eps_cur = 0.0;
   bool fast = false;                   // rank <= 64: fused head/solve tail
-  bool direct = false;                 // operators straight from X (no tree intermediates)
+  int combine = 1;                     // leading PP tree levels combined (1: the plain tree)
+  bool combine_auto = false;           // chosen by the cost model
+  std::string combine_model = "null";  // modelled build time per candidate (ms), JSON
   hipStream_t aux = nullptr;           // stream for the head kernel (default priority)
   ppals_sweep_record* pinned_rec = nullptr;  // pinned host staging of the sweep record
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -485,14 +487,17 @@ void l1_magic(uint32_t d, uint64_t* mag, int* sh) {
 
 namespace {
 
-// Operator M_p^(i,j) (i < j) straight from X: the other N - 2 modes are contracted with
-// their Khatri-Rao product.  A contiguous block of contracted modes is a plain first-level
-// step; otherwise the contracted modes form up to three blocks (before i, between i and j,
-// after j) and the step reads X through strided row and k offsets.
-int add_direct_leaf(ppals_plan* p, int i, int j, int out_buf) {
+// Node of the PP tree at paper level lv (2 <= lv <= N - 1) for the pair (i, j), i < j <= lv
+// (0-based): the tensor with modes i, j and the tail lv + 1 .. N - 1, straight from X by
+// contracting the other lv - 1 modes (all <= lv) with their Khatri-Rao product.  At
+// lv = N - 1 it is the operator M_p^(i,j); at lv = 2 it is a first-level node of the tree.
+// A contiguous block of contracted modes is a plain first-level step; otherwise the
+// contracted modes form up to three blocks (before i, between i and j, after j) and the
+// step reads X through strided offsets: rows (x_i, x_j, tail), k over the three blocks.
+int add_direct_node(ppals_plan* p, int lv, int i, int j, int out_buf) {
   const int N = p->N;
   std::vector<int> cm;
-  for (int m = 0; m < N; ++m)
+  for (int m = 0; m <= lv; ++m)
     if (m != i && m != j) cm.push_back(m);
   bool contiguous = true;
   for (size_t a = 1; a < cm.size(); ++a) contiguous = contiguous && cm[a] == cm[a - 1] + 1;
@@ -506,26 +511,97 @@ int add_direct_leaf(ppals_plan* p, int i, int j, int out_buf) {
   s.lo = s.hi = -1;
   s.cmodes = cm;
   s.kept = {i, j};
+  for (int m = lv + 1; m < N; ++m) s.kept.push_back(m);
   s.out_buf = out_buf;
-  const int64_t n1 = prod(0, i), n2 = prod(i + 1, j), n3 = prod(j + 1, N);
-  const int64_t K = n1 * n2 * n3, M = p->dims[i] * p->dims[j];
+  const int64_t tail = prod(lv + 1, N);
+  const int64_t n1 = prod(0, i), n2 = prod(i + 1, j), n3 = prod(j + 1, lv + 1);
+  const int64_t K = n1 * n2 * n3, M = p->dims[i] * p->dims[j] * tail;
   Level1Geom g = l1_geom(M, K, 1, p->R, p->l1dt);
   g.kc_mode = 0;
   g.Q = 1;
   g.strided = 1;
   g.mrad = p->dims[j];
+  g.mrad2 = tail;
   g.ms0 = prod(i + 1, N);
   g.ms1 = prod(j + 1, N);
+  g.ms2 = 1;
   g.kr1 = (uint32_t)n2;
   g.kr2 = (uint32_t)n3;
   l1_magic(g.kr1, &g.kmag1, &g.ksh1);
   l1_magic(g.kr2, &g.kmag2, &g.ksh2);
   g.ks0 = prod(i, N);
   g.ks1 = prod(j, N);
-  g.ks2 = 1;
+  g.ks2 = tail;
   s.geom = g;
   p->l1.push_back(s);
   return (int)p->l1.size() - 1;
+}
+
+// Operator build with the first l levels combined (Section 3.2.3): the C(l + 2, 2) nodes
+// of paper level l + 1 each contract l modes of X at once, the later levels contract one
+// mode of a parent each.  Modelled time, per node, from the rates the first-level kernel
+// and the multi-TTV reach here: a contraction of X at 0.6 of the tier's MFMA peak (0.45
+// when the contracted modes are not one block and the loads are strided) or 0.6 of 8 TB/s
+// for X, whichever is slower; a tree contraction at 0.55 of 8 TB/s for its parent.
+double model_build_ms(const ppals_desc* d, int l) {
+  const int N = d->order;
+  double nX = 1.0;
+  for (int m = 0; m < N; ++m) nX *= (double)d->dims[m];
+  const double peak = d->level1_dtype == PPALS_FP64 ? 78.6e12 : (d->level1_dtype == PPALS_FP32 ? 157.3e12 : 2500e12);
+  const double xsz = d->level1_dtype == PPALS_FP64 ? 8.0 : (d->level1_dtype == PPALS_FP32 ? 4.0 : 2.0);
+  const double bulk = d->tensor_dtype == PPALS_FP64 ? 8.0 : 4.0;
+  const double R = d->rank;
+  double t = 0.0;
+  for (int lv = l + 1; lv <= N - 1; ++lv) {
+    double tail = 1.0;
+    for (int m = lv + 1; m < N; ++m) tail *= (double)d->dims[m];
+    for (int i = 0; i <= lv; ++i)
+      for (int j = i + 1; j <= lv; ++j) {
+        if (lv == l + 1) {
+          // contracted modes {0..lv} minus {i, j}: one block unless i, j split them
+          const bool block = (i == 0 && j == 1) || (j == lv && i == lv - 1) || (i == 0 && j == lv);
+          const double f = 2.0 * nX * R / ((block || lv == 2 ? 0.6 : 0.45) * peak);
+          const double b = nX * xsz / (0.6 * 8e12);
+          t += std::max(f, b);
+        } else {
+          // parent: modes i, j, one more below lv + 1, and the tail
+          const double parent = (double)d->dims[i] * d->dims[j] * tail * R *
+                                (double)d->dims[lv] * bulk;
+          t += parent / (0.55 * 8e12);
+        }
+      }
+  }
+  return t * 1e3;
+}
+
+// Levels to combine: requested (clamped to N - 2) or, for -1, the candidate with the least
+// modelled time.  Returns -1 if combining needs the FP64/FP32 first level, -2 if a strided
+// node would exceed the 31-bit contracted extent; est receives the model per candidate.
+int choose_combine(const ppals_desc* d, int req, std::vector<double>* est) {
+  const int N = d->order;
+  auto fits = [&](int l) {
+    const int lv = l + 1;
+    for (int i = 0; i <= lv; ++i)
+      for (int j = i + 1; j <= lv; ++j) {
+        double K = 1.0;
+        for (int m = 0; m <= lv; ++m)
+          if (m != i && m != j) K *= (double)d->dims[m];
+        if (K > 2147483647.0 - 64.0) return false;
+      }
+    return true;
+  };
+  for (int l = 1; l <= N - 2; ++l) est->push_back(model_build_ms(d, l));
+  if (req == -1) {
+    if (d->level1_dtype == PPALS_BF16) return 1;
+    int best = 1;
+    for (int l = 2; l <= N - 2; ++l)
+      if (fits(l) && (*est)[l - 1] < (*est)[best - 1]) best = l;
+    return best;
+  }
+  const int l = std::min(req, N - 2);
+  if (l >= 2 && d->level1_dtype == PPALS_BF16) return -1;
+  if (l >= 2 && !fits(l)) return -2;
+  return l;
 }
 
 void build_pp(ppals_plan* p) {
@@ -539,16 +615,11 @@ void build_pp(ppals_plan* p) {
   };
   for (int i = 0; i < N; ++i)
     for (int j = 0; j < N; ++j) p->leaf_buf[i][j] = -1;
-  if (p->direct) {
-    for (int i = 0; i < N; ++i)
-      for (int j = i + 1; j < N; ++j) {
-        const int ob = new_buf(p, node_bytes(p, {i, j}));
-        p->pp_ops.push_back({OP_L1, add_direct_leaf(p, i, j, ob)});
-        p->leaf_buf[i][j] = ob;
-      }
-  }
-  // level 2 (paper numbering, modes 1-based in the text; 0-based here)
-  for (int l = 2; l <= N - 1 && !p->direct; ++l) {
+  // Paper numbering (modes 1-based in the text; 0-based here).  The nodes of level
+  // first = combine + 1 come straight from X (combine modes contracted at once; 1 is the
+  // plain tree), the later levels from their parents by one contraction each.
+  const int first = p->combine + 1;
+  for (int l = first; l <= N - 1; ++l) {
     std::vector<int> tail;
     for (int m = l + 2; m <= N; ++m) tail.push_back(m - 1);
     for (int i = 1; i <= l + 1; ++i)
@@ -560,9 +631,8 @@ void build_pp(ppals_plan* p) {
         parent.push_back(w - 1);
         std::sort(parent.begin(), parent.end());
         const int ob = new_buf(p, node_bytes(p, child));
-        if (l == 2) {
-          const int s = add_l1(p, w - 1, w, ob);
-          p->pp_ops.push_back({OP_L1, s});
+        if (l == first) {
+          p->pp_ops.push_back({OP_L1, add_direct_node(p, l, i - 1, j - 1, ob)});
         } else {
           const int pb = find(parent);
           const int pos = (int)(std::find(parent.begin(), parent.end(), w - 1) - parent.begin());
@@ -793,8 +863,11 @@ void make_describe(ppals_plan* p) {
     if (pp_node && !leaf) inter += p->bufs[b].bytes;
   }
   p->describe = std::string("{") + tmp + ",\"dt_ops\":" + dt + ",\"pp_build_ops\":" + pp +
-                ",\"pp_build\":\"" + (p->direct ? "direct" : "tree") +
-                "\",\"pp_build_intermediate_bytes\":" + std::to_string(inter) +
+                ",\"pp_build\":\"" +
+                (p->combine == 1 ? "tree" : (p->combine == p->N - 2 ? "direct" : "combined")) +
+                "\",\"pp_build_levels\":" + std::to_string(p->combine) + ",\"pp_build_auto\":" +
+                (p->combine_auto ? "true" : "false") + ",\"pp_build_model_ms\":" + p->combine_model +
+                ",\"pp_build_intermediate_bytes\":" + std::to_string(inter) +
                 ",\"pp_build_reused_after_als\":" + reuse + ",\"fused_tail\":" +
                 (p->fast ? "true" : "false") + ",\"pp_gram_ranges\":" + ranges + "}";
 }
@@ -1754,19 +1827,32 @@ ppals_status ppals_plan_create(const ppals_desc* d, ppals_plan** out) {
   if (!tier_ok) return fail(PPALS_E_UNSUPPORTED, "unsupported (tensor_dtype, level1_dtype) pair");
   const double step = d->step_size == 0.0 ? 1.0 : d->step_size;
   if (!(step > 0.0 && step <= 1.0)) return fail(PPALS_E_ARG, "step_size must be in (0, 1] (or 0 for 1)");
-  if (d->pp_build_direct && d->order > 3) {
-    if (d->level1_dtype == PPALS_BF16)
-      return fail(PPALS_E_UNSUPPORTED, "the direct operator build needs the FP64 or FP32 first level");
-    for (int i = 0; i < d->order; ++i)
-      for (int j = i + 1; j < d->order; ++j) {
-        double K = 1.0;
-        for (int m = 0; m < d->order; ++m)
-          if (m != i && m != j) K *= (double)d->dims[m];
-        if (K > 2147483647.0 - 64.0)
-          return fail(PPALS_E_UNSUPPORTED, "direct operator build: contracted extent above 2^31 - 64");
+  int combine = 1;
+  std::string model = "null";
+  if (d->order > 3 && d->pp_build_levels != 0) {
+    if (d->pp_build_levels < -1)
+      return fail(PPALS_E_ARG, "pp_build_levels must be -1 (automatic), 0 or >= 1");
+    std::vector<double> est;
+    combine = choose_combine(d, d->pp_build_levels, &est);
+    if (combine < 0) {
+      return fail(PPALS_E_UNSUPPORTED,
+                  combine == -1 ? "combined operator build needs the FP64 or FP32 first level"
+                                : "combined operator build: contracted extent above 2^31 - 64");
+    }
+    if (!est.empty()) {
+      model = "[";
+      for (size_t l = 0; l < est.size(); ++l) {
+        char t[64];
+        snprintf(t, sizeof(t), "%s%.4g", l ? "," : "", est[l]);
+        model += t;
       }
+      model += "]";
+    }
   }
   ppals_plan* p = new ppals_plan();
+  p->combine = combine;
+  p->combine_auto = d->order > 3 && d->pp_build_levels == -1;
+  p->combine_model = model;
   p->step = step;
   p->N = d->order;
   p->R = d->rank;
@@ -1776,7 +1862,6 @@ ppals_status ppals_plan_create(const ppals_desc* d, ppals_plan** out) {
   p->bulk = d->tensor_dtype == PPALS_FP64 ? DT_F64 : DT_F32;
   p->second_order = d->use_second_order ? 1 : 0;
   p->fast = p->R <= 64;
-  p->direct = d->pp_build_direct != 0 && d->order > 3;
   p->mode_off.resize(p->N);
   for (int i = 0; i < p->N; ++i) {
     p->mode_off[i] = (size_t)p->sum_s * p->R;

@@ -169,6 +169,8 @@ Level1Geom middle_unfolding_geom(const tucker_plan* p) {
   g.mrad = s1;  // row m = x2: offset x2 s3
   g.ms0 = 0;
   g.ms1 = s2;
+  g.mrad2 = 1;
+  g.ms2 = 0;
   g.kr1 = 1;    // k = x1 s3 + x3: offset x1 s2 s3 + x3
   g.kr2 = (uint32_t)s2;
   l1_magic(g.kr1, &g.kmag1, &g.ksh1);

@@ -339,7 +339,7 @@ def test_direct_build_plan(lib):
 
     def describe(dims, R, tdt, l1, direct):
         d = _desc(dims, R, tdt, l1)
-        d.pp_build_direct = direct
+        d.pp_build_levels = direct
         h = ctypes.c_void_p()
         st = lib.ppals_plan_create(ctypes.byref(d), ctypes.byref(h))
         if st != 0:
@@ -351,7 +351,7 @@ def test_direct_build_plan(lib):
 
     s, R = 20, 6
     st, tree = describe((s,) * 4, R, 0, 0, 0)
-    st2, direct = describe((s,) * 4, R, 0, 0, 1)
+    st2, direct = describe((s,) * 4, R, 0, 0, 2)
     assert st == 0 and st2 == 0
     assert tree["pp_build"] == "tree" and direct["pp_build"] == "direct"
     assert tree["pp_build_intermediate_bytes"] == 3 * s ** 3 * R * 8
@@ -362,7 +362,7 @@ def test_direct_build_plan(lib):
     assert sorted(tuple(o["kept"]) for o in l1) == [(i, j) for i in range(4) for j in range(i + 1, 4)]
     assert sum(1 for o in l1 if o["strided"]) == 3      # (0,2), (1,2), (1,3)
     assert direct["pp_build_tree_ttv_flops"] == 0
-    st, _ = describe((s,) * 4, R, 1, 2, 1)
+    st, _ = describe((s,) * 4, R, 1, 2, 2)
     assert st == _lib.PPALS_E_UNSUPPORTED
-    st, o3 = describe((s,) * 3, R, 0, 0, 1)
+    st, o3 = describe((s,) * 3, R, 0, 0, 2)
     assert st == 0 and o3["pp_build"] == "tree"

@@ -1,9 +1,9 @@
-"""GPU parity of the direct (memory-reduced) operator build of Section 3.2.3: every
-operator M_p^(i,j) is X contracted with the Khatri-Rao product of the other N - 2
-factors in one first-level launch, through strided row and k offsets when the
-contracted modes are not one contiguous block, so that no O(s^(N-1) R) intermediate is
-stored.  Operators against their definition, whole runs against the oracle, and the
-direct build against the tree build."""
+"""GPU parity of the combined operator builds of Section 3.2.3: the nodes of tree level
+l + 1 are X contracted with the Khatri-Rao product of l factors in one first-level launch
+(through strided row and k offsets when the contracted modes are not one contiguous
+block), the later levels come from their parents; l = N - 2 computes every operator
+M_p^(i,j) from X and stores no O(s^(N-1) R) intermediate.  Operators against their
+definition, whole runs against the oracle, and combined against tree builds."""
 import numpy as np
 import pytest
 import torch
@@ -20,17 +20,22 @@ pp = pytest.importorskip("paper_1811_10573_amd")
 
 
 @pytest.mark.parametrize("tier", ["f64", "f32"])
-@pytest.mark.parametrize("dims,R", [((9, 8, 7, 10), 5), ((20, 22, 18, 16), 7), ((5, 4, 6, 5, 4), 3),
-                                    ((4, 3, 5, 3, 4, 3), 4), ((66, 65, 64, 64), 50)])
-def test_direct_operators_match_definition(tier, dims, R):
-    """Every operator of the direct build against the definition (partial MTTKRP),
-    Higham bound for a K-term sum; the plan keeps no intermediate and uses strided steps
-    for the non-contiguous contracted sets."""
+@pytest.mark.parametrize("dims,R,build", [((9, 8, 7, 10), 5, "direct"), ((20, 22, 18, 16), 7, "direct"),
+                                          ((5, 4, 6, 5, 4), 3, "direct"), ((5, 4, 6, 5, 4), 3, 2),
+                                          ((4, 3, 5, 3, 4, 3), 4, "direct"), ((4, 3, 5, 3, 4, 3), 4, 2),
+                                          ((4, 3, 5, 3, 4, 3), 4, 3), ((66, 65, 64, 64), 50, "direct")])
+def test_direct_operators_match_definition(tier, dims, R, build):
+    """Every operator of a combined build against the definition (partial MTTKRP),
+    Higham bound for a K-term sum; strided steps for the non-contiguous contracted sets;
+    the full direct build keeps no intermediate."""
     prob = tensorgen.make_problem(dims, R, seed=4, eta=1e-2)
     A = [fp32_round(a) for a in prob.init] if tier == "f32" else prob.init
-    r = Run(prob, tier, init=A, pp_build="direct")
+    r = Run(prob, tier, init=A, pp_build=build)
     d = r.plan.describe()
-    assert d["pp_build"] == "direct" and d["pp_build_intermediate_bytes"] == 0
+    want_levels = len(dims) - 2 if build == "direct" else build
+    assert d["pp_build_levels"] == want_levels
+    if build == "direct":
+        assert d["pp_build"] == "direct" and d["pp_build_intermediate_bytes"] == 0
     assert any(o.get("strided") for o in d["pp_build_ops"])
     pp.pp_build_operators(r.plan, r.X, r.Xb, r.A, r.ws)
     st = opp.build_operators(r.Xh, A)
@@ -45,14 +50,17 @@ def test_direct_operators_match_definition(tier, dims, R):
                       f"{tier} direct operator ({i},{j}) {dims}")
 
 
-@pytest.mark.parametrize("dims,R,eps", [((12, 14, 11, 13), 5, 0.2), ((7, 6, 8, 5, 6), 3, 0.2),
-                                        ((40, 36, 34, 32), 12, 0.1)])
-def test_direct_build_run_matches_oracle(dims, R, eps):
-    """Free PP-ALS with the direct build; the oracle replays the sweep kinds.  Factors
+@pytest.mark.parametrize("dims,R,eps,build", [((12, 14, 11, 13), 5, 0.2, "direct"),
+                                              ((7, 6, 8, 5, 6), 3, 0.2, "direct"),
+                                              ((7, 6, 8, 5, 6), 3, 0.2, 2),
+                                              ((6, 5, 4, 5, 4, 5), 3, 0.2, "auto"),
+                                              ((40, 36, 34, 32), 12, 0.1, "direct")])
+def test_direct_build_run_matches_oracle(dims, R, eps, build):
+    """Free PP-ALS with a combined build; the oracle replays the sweep kinds.  Factors
     within the sensitivity bound, last fit within 1e-10; the oracle's free run takes the
     same decisions."""
     prob = tensorgen.make_problem(dims, R, seed=8, eta=1e-3, collinearity=0.5)
-    r = Run(prob, pp_build="direct")
+    r = Run(prob, pp_build=build)
     recs, _ = pp.run(r.plan, r.X, None, r.A, r.S, r.normX2, r.ws, r.rec, eps=eps, max_sweeps=40)
     kinds = [x["kind"] for x in recs]
     assert "pp_approx" in kinds, kinds
