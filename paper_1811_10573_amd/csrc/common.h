@@ -66,7 +66,7 @@ struct TtvJob {
   int Jb;              // j-width per group (j = q*R + r)
   int64_t blocks;      // workgroups of this job
   int t_is_f32;
-  int kind;            // TTV_SCALAR, TTV_SLAB or TTV_ROWS (vector kernel, 256 threads)
+  int kind;            // TTV_SCALAR, TTV_SLAB, TTV_ROWS or TTV_ROWS2 (vector kernel, 256 threads)
   int lanes;           // TTV_SLAB: active lanes per wave (VEC * lanes is a multiple of R)
   int xs;              // TTV_ROWS: x-rows per split
   int f_vec;           // TTV_SLAB: F is 16-byte aligned (vector weight loads)
@@ -76,7 +76,9 @@ struct TtvJob {
 // loads by lanes whose rank indices stay fixed.  TTV_ROWS (Q*R a multiple of the vector
 // width): each x-row of Q*R elements is streamed with 16-byte loads, F's rows of the
 // split staged in LDS.
-enum { TTV_SCALAR = 0, TTV_SLAB = 1, TTV_ROWS = 2 };
+// TTV_ROWS2: TTV_ROWS with 8-byte vectors (two FP32 elements), for FP32 rows whose Q*R is
+// even but not a multiple of four (16-byte vectors would straddle rows).
+enum { TTV_SCALAR = 0, TTV_SLAB = 1, TTV_ROWS = 2, TTV_ROWS2 = 3 };
 constexpr int TTV_VTHREADS = 256;
 constexpr int TTV_SLAB_PB = 2;  // slabs per TTV_SLAB workgroup (they share the weight loads)
 

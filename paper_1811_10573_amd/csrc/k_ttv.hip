@@ -96,6 +96,14 @@ template <> struct TtvVecT<float> {
     o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
   }
 };
+// Two FP32 elements per 8-byte vector (TTV_ROWS2).
+struct TtvVec2F {
+  static constexpr int VEC = 2;
+  typedef float2 V;
+  __device__ static __forceinline__ void get(const V& v, double (&o)[2]) {
+    o[0] = v.x; o[1] = v.y;
+  }
+};
 template <> struct TtvVecT<double> {
   static constexpr int VEC = 2;
   typedef double2 V;
@@ -204,9 +212,8 @@ __device__ __forceinline__ void ttv_slab(const TtvJob& J, int R, int64_t bid, do
 
 // TTV_ROWS: workgroup (jb, p, split) covers VEC * TTV_VTHREADS consecutive j of the rows
 // x in [x0, x1); F's rows x0..x1-1 are staged in LDS first.
-template <typename T>
+template <typename T, typename TV = TtvVecT<T>>
 __device__ __forceinline__ void ttv_rows(const TtvJob& J, int R, int64_t bid, double* fl) {
-  using TV = TtvVecT<T>;
   constexpr int VEC = TV::VEC;
   const int64_t QR = J.Q * R;
   const int64_t jb = bid % J.jblocks;
@@ -267,6 +274,8 @@ __global__ __launch_bounds__(TTV_VTHREADS) void k_ttv_vec(TtvBatch b) {
   if (J.kind == TTV_SLAB) {
     if (J.t_is_f32) ttv_slab<float>(J, b.R, bid, red);
     else ttv_slab<double>(J, b.R, bid, red);
+  } else if (J.kind == TTV_ROWS2) {
+    ttv_rows<float, TtvVec2F>(J, b.R, bid, fl);
   } else {
     if (J.t_is_f32) ttv_rows<float>(J, b.R, bid, fl);
     else ttv_rows<double>(J, b.R, bid, fl);
@@ -331,6 +340,8 @@ __global__ __launch_bounds__(TTV_VTHREADS) void k_ttv_tail(TtvBatch b, GramArgs 
   if (J.kind == TTV_SLAB) {
     if (J.t_is_f32) ttv_slab<float>(J, b.R, bid, red);
     else ttv_slab<double>(J, b.R, bid, red);
+  } else if (J.kind == TTV_ROWS2) {
+    ttv_rows<float, TtvVec2F>(J, b.R, bid, fl);
   } else {
     if (J.t_is_f32) ttv_rows<float>(J, b.R, bid, fl);
     else ttv_rows<double>(J, b.R, bid, fl);
@@ -456,7 +467,8 @@ hipError_t launch_ttv(const TtvBatch& b, hipStream_t s) {
       V = J;
       V.f_vec = (uintptr_t)J.F % 16 == 0;
       vtotal += J.blocks;
-      if (J.kind == TTV_ROWS) lds = std::max(lds, (size_t)J.xs * b.R * sizeof(double));
+      if (J.kind == TTV_ROWS || J.kind == TTV_ROWS2)
+        lds = std::max(lds, (size_t)J.xs * b.R * sizeof(double));
     }
   }
   if (stotal > 0) {
@@ -501,7 +513,7 @@ hipError_t launch_ttv_tail(const TtvBatch& b, const GramArgs* g, const HeadArgs&
     V = J;
     V.f_vec = (uintptr_t)J.F % 16 == 0;
     vtotal += J.blocks;
-    if (J.kind == TTV_ROWS) fl = std::max(fl, (size_t)J.xs * b.R);
+    if (J.kind == TTV_ROWS || J.kind == TTV_ROWS2) fl = std::max(fl, (size_t)J.xs * b.R);
   }
   const int NBR = (b.R + 15) / 16;
   const int ngram = g ? NBR * NBR * (g->nsplit > 1 ? g->nsplit : 1) : 0;

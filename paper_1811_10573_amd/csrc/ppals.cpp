@@ -256,9 +256,13 @@ void ttv_config(TtvJob& J, int64_t P, int64_t X, int64_t Q, int R, int es, int64
     J.out_split_stride = P * QR;
     return;
   }
-  if (QR % VEC == 0 && QR >= (int64_t)VEC * 64) {
-    J.kind = TTV_ROWS;
-    J.jblocks = (int)((QR + (int64_t)VEC * TTV_VTHREADS - 1) / ((int64_t)VEC * TTV_VTHREADS));
+  // rows of 16-byte vectors, or for FP32 rows of even length 8-byte vectors
+  const bool rows16 = QR % VEC == 0 && QR >= (int64_t)VEC * 64;
+  const bool rows8 = !rows16 && es == 4 && QR % 2 == 0 && QR >= 2 * 64;
+  if (rows16 || rows8) {
+    const int RV = rows16 ? VEC : 2;
+    J.kind = rows16 ? TTV_ROWS : TTV_ROWS2;
+    J.jblocks = (int)((QR + (int64_t)RV * TTV_VTHREADS - 1) / ((int64_t)RV * TTV_VTHREADS));
     const int64_t base = P * J.jblocks;
     int64_t xsplit = (target * 2 / 5 + base - 1) / base;
     xsplit = std::max<int64_t>(1, std::min<int64_t>(xsplit, X / 8));

@@ -53,7 +53,7 @@ def f32_operator_unit(dims):
 
 @pytest.mark.parametrize("second_order", [True, False])
 @pytest.mark.parametrize("dims,R", [((13, 11, 12), 3), ((9, 8, 7, 10), 5), ((400, 30, 28), 8),
-                                    ((30, 20, 25), 16), ((6, 5, 7, 5, 4), 3)])
+                                    ((30, 20, 25), 16), ((6, 5, 7, 5, 4), 3), ((30, 26, 34), 5)])
 def test_pp_rhs_f32_matches_oracle(dims, R, second_order):
     """General PP update (Section 3.2.1) in the FP32 tier, every entry of every mode:
     the operators are FP32 sums of FP32-exact inputs (X and A_p rounded to FP32 on both
@@ -105,7 +105,8 @@ def perturbed_state(st, Xh, Ap, dims, scale, rng):
     return opp.PPState(Ap=[a.copy() for a in st.Ap], dA=[d.copy() for d in st.dA], ops=ops, Mp=Mp)
 
 
-@pytest.mark.parametrize("dims,R", [((23, 19, 21), 4), ((400, 30, 28), 8), ((8, 9, 7, 8), 6)])
+@pytest.mark.parametrize("dims,R", [((23, 19, 21), 4), ((400, 30, 28), 8), ((8, 9, 7, 8), 6),
+                                    ((30, 26, 34), 5)])
 def test_pp_sweeps_f32_match_oracle(dims, R):
     """Operator build and four PP sweeps in the FP32 tier from the same FP32-exact start on
     both sides (after eight oracle ALS sweeps on float64(float32(X))), every factor entry
