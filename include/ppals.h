@@ -436,54 +436,64 @@ ppals_status ppals_get_profile(ppals_plan* plan, ppals_kernel_stat* out, int32_t
                                int32_t* n_out, int32_t reset);
 
 /* ---------------------------------------------------------------------------
- * Tucker decomposition of an order-3 tensor by ALS (HOOI, Algorithm 2) and by
- * pairwise perturbation (PP-Tucker-ALS, Algorithm 4 with the first-order
- * approximation of Section 3.2.2), FP64 throughout.
+ * Tucker decomposition of an order-N tensor (3 <= N <= 8) by ALS (HOOI, Algorithm 2) and
+ * by pairwise perturbation (PP-Tucker-ALS, Algorithm 4 with the first-order approximation
+ * of Section 3.2.2), FP64 throughout.
  *
- *   X       s_1 x s_2 x s_3 doubles, row-major (device).
+ *   X       s_1 x .. x s_N doubles, row-major (device).
  *   A[n]    s_n x R doubles, orthonormal columns (device), updated in place.
- *   G       the core, R x R x R doubles, index order (r_1, r_2, r_3) (device).
+ *   G       the core, R^N doubles, index order (r_1, .., r_N) (device).
  *   ws      caller-allocated workspace of tucker_workspace_bytes() bytes, 256-byte
  *           aligned; it holds the PP operators between tucker_pp_build and later
  *           tucker_pp_sweep calls.
- * The TTMc Y^(n) = X x_{i != n} A^(i)T (Section 2.4) is stored as an s_n x R x R
- * array whose two rank indices are, for n = 1, 2, 3: (r_3, r_2), (r_3, r_1),
- * (r_1, r_2).
+ * The TTMc Y^(n) = X x_{i != n} A^(i)T (Section 2.4) is stored as s_n x R^(N-1) doubles:
+ * x_n first, then the rank indices of the other modes in increasing mode order.
+ *
+ * HOOI sweep: Y^(1) from X; then the prefix P_n = X x_1 A^(1)T .. x_(n-1) A^(n-1)T, with
+ * the factors already updated in the sweep, grows by one contraction per mode and gives
+ * Y^(n) with the later modes contracted: two passes over X per sweep.  Operator build:
+ * Y_p^(i,n) for every pair, from the three first-level contractions X x_c A_p^(c)T,
+ * c = 1, 2, 3.
  *
  * Factor update.  A^(n) <- the R leading left singular vectors of Y^(n)_(n), i.e.
  * the eigenvectors of W = Y_(n) Y_(n)^T for its R largest eigenvalues (the
  * Gram-matrix route of Section 2.4), found by subspace iteration started from the
  * current A^(n): C = W V applied as Y_(n) (Y_(n)^T V) without forming W, a
- * Rayleigh-Ritz step on span(V) (Cholesky of V^T V, Jacobi rotations of the
- * projected R x R matrix), the next basis C T Lambda^-1, until the largest Ritz
- * residual ||W u_j - lambda_j u_j|| / lambda_1 is at most `tol` or after
- * `max_iters` iterations.  Columns are in decreasing eigenvalue order; each new
- * column is oriented to a non-negative inner product with the column it replaces.
- * The iteration synchronises the stream once per iteration to read the residual,
- * so every entry point below that updates factors returns with the stream idle.
+ * Rayleigh-Ritz step on span(V) (V^T V normalised by its inverse square root or
+ * Cholesky factor, Jacobi rotations of the projected R x R matrix), the next basis
+ * C T Lambda^-1, until the largest Ritz residual ||W u_j - lambda_j u_j|| / lambda_1 is
+ * at most `tol` or after `max_iters` iterations.  Columns are in decreasing eigenvalue
+ * order; each new column is oriented to a non-negative inner product with the column it
+ * replaces.  The entry points that update factors synchronise the stream (once per
+ * iteration, or once per PP sweep when every mode converges in one iteration) and
+ * return with it idle.
  *
- * Limits: 1 <= R <= 64, R <= s_n for every n, s_1 s_3 < 2^31 - 64.
+ * Limits: 1 <= R <= 64, R <= s_n for every n; for every inner mode n the product of the
+ * other dimensions is below 2^31 - 64; R^N <= 10^12.
  * ------------------------------------------------------------------------- */
 #define TUCKER_MAX_RANK 64
 typedef struct tucker_plan tucker_plan;
 
 typedef struct {
-  int32_t kind;             /* PPALS_SWEEP_ALS / _PP_INIT / _PP_APPROX               */
-  int32_t iters[3];         /* subspace iterations of the update of A^(n)           */
-  int32_t converged[3];     /* 1 if the Ritz residual reached tol                   */
-  int32_t rr_status[3];     /* 1 if a Rayleigh-Ritz step met a V^T V that was not
-                               positive definite                                     */
+  int32_t kind;                          /* PPALS_SWEEP_ALS / _PP_INIT / _PP_APPROX   */
+  int32_t iters[PPALS_MAX_ORDER];        /* subspace iterations of the update of A^(n) */
+  int32_t converged[PPALS_MAX_ORDER];    /* 1 if the Ritz residual reached tol       */
+  int32_t rr_status[PPALS_MAX_ORDER];    /* 1 if a Rayleigh-Ritz step met a V^T V that
+                                            was not positive definite                */
+  int32_t pad;
   double fit;               /* 1 - sqrt(max(0, ||X||^2 - ||G||^2)) / ||X||           */
   double core_norm;         /* ||G||_F of the core this sweep formed                 */
   double f_norm;            /* ||F||_F, F = G_new - G_old (Algorithm 4)              */
-  double rel_change[3];     /* ||dA^(n)||_F / ||A^(n)||_F: the change over the sweep
-                               (ALS) or since the operator build (PP)                */
-  double ritz_residual[3];  /* final Ritz residual of each update                    */
+  double rel_change[PPALS_MAX_ORDER];    /* ||dA^(n)||_F / ||A^(n)||_F: the change over
+                                            the sweep (ALS) or since the operator build
+                                            (PP)                                       */
+  double ritz_residual[PPALS_MAX_ORDER]; /* final Ritz residual of each update        */
   double ms;                /* host wall time of the sweep (enqueue to completion)   */
 } tucker_sweep_record;
 
-/* Host only: checks the sizes and lays out the workspace. */
-ppals_status tucker_plan_create(const int64_t dims[3], int32_t rank, tucker_plan** out);
+/* Host only: checks the sizes and lays out the workspace.  dims holds `order` sizes. */
+ppals_status tucker_plan_create(int32_t order, const int64_t* dims, int32_t rank,
+                                tucker_plan** out);
 void tucker_plan_destroy(tucker_plan* plan);
 size_t tucker_workspace_bytes(const tucker_plan* plan);
 /* Subspace-iteration limits (defaults: tol 1e-12, 500 iterations for sweeps, 5000 for
@@ -491,12 +501,12 @@ size_t tucker_workspace_bytes(const tucker_plan* plan);
 ppals_status tucker_set_solver(tucker_plan* plan, double tol, int32_t max_iters,
                                int32_t hosvd_max_iters);
 
-/* Y^(mode) = X x_{i != mode} A^(i)T into Y (s_mode x R x R, layout above); mode is
+/* Y^(mode) = X x_{i != mode} A^(i)T into Y (s_mode x R^(N-1), layout above); mode is
  * 0-based.  Enqueues only. */
 ppals_status tucker_ttmc(tucker_plan* plan, void* ws, const double* X, double* const* A,
                          int32_t mode, double* Y, hipStream_t stream);
 
-/* Factor update of mode `mode` from a TTMc Y (s_mode x R^2, rows indexed by the mode):
+/* Factor update of mode `mode` from a TTMc Y (s_mode x R^(N-1), rows indexed by the mode):
  * A_out <- leading eigenvectors of Y Y^T, started from and oriented against A_prev.
  * A_out may equal A_prev.  info (host, may be NULL) receives {iterations, converged,
  * rr_status} and *residual the final Ritz residual.  Synchronises the stream. */
@@ -508,21 +518,20 @@ ppals_status tucker_factor_update(tucker_plan* plan, void* ws, const double* Y, 
  * X_(n) X_(n)^T by the same subspace iteration, started from the caller's V0[n]
  * (s_n x R, full column rank), with W applied through X (X_(n)^T V, then X_(n) times
  * it; W is never formed); the entry of largest magnitude of every column made positive;
- * G <- X x_1 A^(1)T x_2 A^(2)T x_3 A^(3)T.  info (host, 3 x 3 ints, may be NULL) as in
- * tucker_factor_update per mode.  Synchronises the stream.  Needs s_1 s_3 < 2^31 - 64. */
+ * G <- X x_1 A^(1)T .. x_N A^(N)T.  info (host, N x 3 ints, may be NULL) as in
+ * tucker_factor_update per mode.  Synchronises the stream. */
 ppals_status tucker_hosvd(tucker_plan* plan, void* ws, const double* X, double* const* V0,
                           double* const* A, double* G, int32_t* info, hipStream_t stream);
 
-/* One Tucker-ALS sweep (Algorithm 2 loop body) with the order-3 TTMc tree: T = X x_3
- * A^(3)T serves the updates of A^(1) and A^(2), X x_1 A^(1)T that of A^(3); then G from
+/* One Tucker-ALS sweep (Algorithm 2 loop body) with the prefix chain above; then G from
  * the last TTMc.  G holds the previous core on entry (for ||F||).  normX2 = ||X||^2. */
 ppals_status tucker_als_sweep(tucker_plan* plan, void* ws, const double* X, double* const* A,
                               double* G, double normX2, tucker_sweep_record* rec,
                               hipStream_t stream);
 
-/* PP-Tucker operator build (Algorithm 4): with A_p = A, the three pairwise operators
- * Y_p^(i,n) = X x_j A_p^(j)T (j the third mode) and Y_p^(n) for every n; dA <- 0.
- * Enqueues only. */
+/* PP-Tucker operator build (Algorithm 4): with A_p = A, the pairwise operators
+ * Y_p^(i,n) = X x_{j not in {i,n}} A_p^(j)T (i < n; layout x_i, x_n, then the ranks of the
+ * other modes in increasing order) and Y_p^(n) for every n; dA <- 0.  Enqueues only. */
 ppals_status tucker_pp_build(tucker_plan* plan, void* ws, const double* X, double* const* A,
                              hipStream_t stream);
 

@@ -522,27 +522,26 @@ TUCKER_RECORD_FIELDS = ("iters", "converged", "rr_status", "fit", "core_norm", "
                         "rel_change", "ritz_residual", "ms")
 
 
-def tucker_record_dict(r):
+def tucker_record_dict(r, order=3):
     d = {"kind": KIND_NAMES.get(r.kind, str(r.kind))}
     for f in TUCKER_RECORD_FIELDS:
         v = getattr(r, f)
-        d[f] = list(v) if hasattr(v, "__len__") else v
+        d[f] = list(v)[:order] if hasattr(v, "__len__") else v
     return d
 
 
 class TuckerPlan:
-    """Order-3 Tucker plan (HOOI and PP-Tucker-ALS, FP64): sizes, solver limits and the
-    workspace layout.  Tensors and factors are float64 device tensors."""
+    """Tucker plan of order 3 to 8 (HOOI and PP-Tucker-ALS, FP64): sizes, solver limits
+    and the workspace layout.  Tensors and factors are float64 device tensors."""
 
     def __init__(self, dims, rank, tol=None, max_iters=None, hosvd_max_iters=None):
         dims = [int(d) for d in dims]
-        if len(dims) != 3:
-            raise ValueError("the Tucker path takes order-3 tensors")
-        arr = (ctypes.c_int64 * 3)(*dims)
+        arr = (ctypes.c_int64 * len(dims))(*dims)
         h = ctypes.c_void_p()
-        _lib.check(lib().tucker_plan_create(arr, int(rank), ctypes.byref(h)))
+        _lib.check(lib().tucker_plan_create(len(dims), arr, int(rank), ctypes.byref(h)))
         self._h = h
         self.dims = dims
+        self.order = len(dims)
         self.rank = int(rank)
         if tol is not None or max_iters is not None or hosvd_max_iters is not None:
             self.set_solver(1e-12 if tol is None else tol, 500 if max_iters is None else max_iters,
@@ -569,23 +568,26 @@ class TuckerPlan:
             pass
 
     def _X(self, X):
-        return _dev(X, "X", torch.float64, self.dims[0] * self.dims[1] * self.dims[2])
+        n = 1
+        for s in self.dims:
+            n *= s
+        return _dev(X, "X", torch.float64, n)
 
     def _A(self, A, name="A"):
-        if len(A) != 3:
-            raise ValueError(f"{name} needs three factors")
+        if len(A) != self.order:
+            raise ValueError(f"{name} needs {self.order} factors")
         for n, a in enumerate(A):
             _dev(a, f"{name}[{n}]", torch.float64, self.dims[n] * self.rank)
-        return (ctypes.c_void_p * 3)(*[a.data_ptr() for a in A])
+        return (ctypes.c_void_p * self.order)(*[a.data_ptr() for a in A])
 
     def _ws(self, ws):
         return _dev(ws, "ws", min_bytes=self.workspace_bytes)
 
     def _G(self, G):
-        return _dev(G, "G", torch.float64, self.rank ** 3)
+        return _dev(G, "G", torch.float64, self.rank ** self.order)
 
     def _Y(self, Y, mode):
-        return _dev(Y, "Y", torch.float64, self.dims[mode] * self.rank ** 2)
+        return _dev(Y, "Y", torch.float64, self.dims[mode] * self.rank ** (self.order - 1))
 
 
 def tucker_ttmc(plan, ws, X, A, mode, Y, stream=None):
@@ -608,10 +610,10 @@ def tucker_factor_update(plan, ws, Y, mode, A_prev, A_out, stream=None):
 
 def tucker_hosvd(plan, ws, X, V0, A, G, stream=None):
     """Returns the per-mode [iterations, converged, rr_status]."""
-    info = (ctypes.c_int32 * 9)()
+    info = (ctypes.c_int32 * (3 * plan.order))()
     _lib.check(lib().tucker_hosvd(plan._h, _p(plan._ws(ws)), _p(plan._X(X)), plan._A(V0, "V0"),
                                   plan._A(A), _p(plan._G(G)), info, _stream(stream)))
-    return [list(info[3 * n:3 * n + 3]) for n in range(3)]
+    return [list(info[3 * n:3 * n + 3]) for n in range(plan.order)]
 
 
 def tucker_als_sweep(plan, ws, X, A, G, normX2, stream=None):
@@ -619,7 +621,7 @@ def tucker_als_sweep(plan, ws, X, A, G, normX2, stream=None):
     _lib.check(lib().tucker_als_sweep(plan._h, _p(plan._ws(ws)), _p(plan._X(X)), plan._A(A),
                                       _p(plan._G(G)), float(normX2), ctypes.byref(rec),
                                       _stream(stream)))
-    return tucker_record_dict(rec)
+    return tucker_record_dict(rec, plan.order)
 
 
 def tucker_pp_build(plan, ws, X, A, stream=None):
@@ -637,7 +639,7 @@ def tucker_pp_sweep(plan, ws, A, G, normX2, kind="pp_approx", stream=None):
     _lib.check(lib().tucker_pp_sweep(plan._h, _p(plan._ws(ws)), plan._A(A), _p(plan._G(G)),
                                      float(normX2), KIND_CODES[kind], ctypes.byref(rec),
                                      _stream(stream)))
-    return tucker_record_dict(rec)
+    return tucker_record_dict(rec, plan.order)
 
 
 def tucker_run(plan, ws, X, A, G, eps, sweeps, delta=0.0, replay=None, stream=None):
@@ -653,4 +655,4 @@ def tucker_run(plan, ws, X, A, G, eps, sweeps, delta=0.0, replay=None, stream=No
     _lib.check(lib().tucker_run(plan._h, _p(plan._ws(ws)), _p(plan._X(X)), plan._A(A),
                                 _p(plan._G(G)), float(eps), int(sweeps), float(delta), rp, rlen,
                                 recs, ctypes.byref(n_out), _stream(stream)))
-    return [tucker_record_dict(recs[i]) for i in range(n_out.value)]
+    return [tucker_record_dict(recs[i], plan.order) for i in range(n_out.value)]

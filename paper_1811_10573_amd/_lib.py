@@ -90,14 +90,15 @@ PROF_CLASSES = 8
 class TuckerRecord(ctypes.Structure):
     _fields_ = [
         ("kind", ctypes.c_int32),
-        ("iters", ctypes.c_int32 * 3),
-        ("converged", ctypes.c_int32 * 3),
-        ("rr_status", ctypes.c_int32 * 3),
+        ("iters", ctypes.c_int32 * MAX_ORDER),
+        ("converged", ctypes.c_int32 * MAX_ORDER),
+        ("rr_status", ctypes.c_int32 * MAX_ORDER),
+        ("pad", ctypes.c_int32),
         ("fit", ctypes.c_double),
         ("core_norm", ctypes.c_double),
         ("f_norm", ctypes.c_double),
-        ("rel_change", ctypes.c_double * 3),
-        ("ritz_residual", ctypes.c_double * 3),
+        ("rel_change", ctypes.c_double * MAX_ORDER),
+        ("ritz_residual", ctypes.c_double * MAX_ORDER),
         ("ms", ctypes.c_double),
     ]
 
@@ -160,7 +161,7 @@ SIGNATURES = {
     "ppals_batch_kind_log": (_i32, [_vp, _vp, ctypes.POINTER(ctypes.c_uint8), _vp]),
     "ppals_batch_describe": (_i32, [_vp, ctypes.c_char_p, _sz]),
     "ppals_set_profiling": (_i32, [_vp, _i32]),
-    "tucker_plan_create": (_i32, [ctypes.POINTER(_i64), _i32, ctypes.POINTER(_vp)]),
+    "tucker_plan_create": (_i32, [_i32, ctypes.POINTER(_i64), _i32, ctypes.POINTER(_vp)]),
     "tucker_plan_destroy": (None, [_vp]),
     "tucker_workspace_bytes": (_sz, [_vp]),
     "tucker_set_solver": (_i32, [_vp, _dbl, _i32, _i32]),

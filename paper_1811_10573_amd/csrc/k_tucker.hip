@@ -502,31 +502,34 @@ hipError_t launch_sign_by_max(double* V, int64_t rows, int R, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Y~[x][a][b] = Yp[x][a][b] + T1[x][a][b] + T2[x][b][a] (R x R trailing block):
-// the first-order PP-Tucker combination, one of the two terms with its rank indices
-// in the other order.  A null T1 or T2 is a term that is known to be zero.
-__global__ __launch_bounds__(256) void k_pp_tucker_combine(double* out, const double* Yp,
-                                                           const double* T1, const double* T2,
-                                                           int64_t rows, int R) {
-  const int64_t n = rows * R * R;
-  const int64_t RR = (int64_t)R * R;
+// PP-Tucker combination (Section 3.2.2): out[x][c] = base[x][c] + sum_t term_t[x][p_t(c)].
+// c runs over the rank multi-index of a TTMc in canonical order (the rank indices of the
+// other modes in increasing mode order, nd digits base R, the first most significant);
+// a first-order term contracts its mode last, so its rank digit is the last one there:
+// p_t moves digit pos_t of c to the end.
+__global__ __launch_bounds__(256) void k_tucker_combine(TuckerCombine a) {
+  const int64_t n = a.rows * a.cols;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
-    const int64_t x = e / RR, r = e - x * RR;
-    const int64_t a = r / R, b = r - a * R;
-    double v = Yp[e];
-    if (T1) v += T1[e];
-    if (T2) v += T2[x * RR + b * R + a];
-    out[e] = v;
+    const int64_t x = e / a.cols, c = e - x * a.cols;
+    double v = a.base ? a.base[e] : 0.0;
+    for (int t = 0; t < a.nterms; ++t) {
+      const int64_t w = a.rpow[a.nd - 1 - a.pos[t]];  // weight of the moved digit
+      const int64_t high = c / (w * a.R);
+      const int64_t rem = c - high * w * a.R;
+      const int64_t dp = rem / w;
+      const int64_t low = rem - dp * w;
+      v += a.term[t][x * a.cols + (high * w + low) * a.R + dp];
+    }
+    a.out[e] = v;
   }
 }
 
-hipError_t launch_pp_tucker_combine(double* out, const double* Yp, const double* T1,
-                                    const double* T2, int64_t rows, int R, hipStream_t s) {
-  const int64_t n = rows * (int64_t)R * R;
+hipError_t launch_tucker_combine(const TuckerCombine& a, hipStream_t s) {
+  const int64_t n = a.rows * a.cols;
   int64_t blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_pp_tucker_combine, dim3((unsigned)std::max<int64_t>(1, blocks)), dim3(256), 0,
-                     s, out, Yp, T1, T2, rows, R);
+  hipLaunchKernelGGL(k_tucker_combine, dim3((unsigned)std::max<int64_t>(1, blocks)), dim3(256), 0,
+                     s, a);
   return hipGetLastError();
 }
 

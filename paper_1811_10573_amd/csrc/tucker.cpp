@@ -1,12 +1,15 @@
-// Tucker-ALS and PP-Tucker-ALS for order-3 tensors (Algorithms 2 and 4), FP64.
+// Tucker-ALS and PP-Tucker-ALS for tensors of order 3 to 8 (Algorithms 2 and 4), FP64.
 //
-// Every TTM runs on the first-level MFMA contraction kernel: a P x K x Q tensor
-// contracted over its middle index with a K x R factor, written P x Q x R.  The three
-// modes of an order-3 tensor are all reachable that way without transposing X, and
-// the rank indices of each TTMc come out in a fixed order per mode (documented with
-// tucker_ttmc).  The factor update is a subspace iteration on W = Y_(n) Y_(n)^T whose
-// products W V are applied as Y_(n) (Y_(n)^T V), two more first-level contractions;
-// the small R x R algebra (Rayleigh-Ritz with Jacobi rotations) is one workgroup.
+// Every TTM is a first-level contraction (k_level1.hip).  A partly contracted tensor is
+// kept as its remaining original modes, in order, followed by the rank indices made so
+// far; contracting original mode m is then a P x K x Q contraction (P: the remaining modes
+// before m; K = s_m; Q: the remaining modes after m times the ranks) whose new rank index
+// lands last.  Contracting modes in increasing order gives every TTMc its canonical
+// layout: the kept mode(s) first, then the rank indices in increasing mode order.
+//
+// The factor update is a subspace iteration on W = Y_(n) Y_(n)^T whose products W V are
+// applied as Y_(n) (Y_(n)^T V), two more first-level contractions; the small R x R algebra
+// (Rayleigh-Ritz with Jacobi rotations) is one workgroup (k_tucker.hip).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -40,30 +43,50 @@ using namespace ppk;
 
 namespace {
 
+constexpr int TMAX = PPALS_MAX_ORDER;
+
 size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct Contr {  // a first-level contraction P x K x Q (K contracted)
   int64_t P, K, Q;
 };
 
+// Layout of a partly contracted tensor: the remaining original modes (increasing) and
+// the number of rank indices appended after them.
+struct Lay {
+  std::vector<int> modes;
+  int nr = 0;
+};
+
+// What a schedule would launch, gathered without launching (workspace sizes).
+struct Collector {
+  size_t prep = 1, part = 1024;  // elements of the operand and split-partial regions
+  int64_t tmp = 1;               // largest intermediate of a contraction chain
+};
+
 }  // namespace
 
 struct tucker_plan {
-  int64_t s[3];
-  int R;
+  int N = 0;
+  int64_t s[TMAX] = {0};
+  int R = 0;
+  int64_t rpow[TMAX + 1] = {0};  // R^k
   double tol = 1e-12;
   int max_iters = 500;
   int hosvd_iters = 5000;
   // workspace regions (byte offsets)
-  size_t o_T3, o_T1, o_op01, o_op02, o_op12, o_Yp[3], o_Y, o_Ta, o_Tb, o_Gn, o_Ap[3], o_dA[3],
-      o_Aold, o_V, o_C, o_U, o_Z, o_B, o_H, o_P, o_T, o_lam, o_info, o_stats, o_prep, o_part,
-      o_gpart, o_Zx, o_rpart;
+  size_t o_pre[2], o_tmp[2];       // prefix chain and chain temporaries
+  size_t o_F[3];                   // X x_c A_p^(c), c = 0, 1, 2 (operator build)
+  size_t o_op[TMAX][TMAX];         // Y_p^(i,n), i < n
+  size_t o_Yp[TMAX], o_Y, o_term[TMAX], o_Gn;
+  size_t o_Ap[TMAX], o_dA[TMAX], o_Astart[TMAX];
+  size_t o_V, o_C, o_Aold, o_U, o_Z, o_B, o_H, o_P, o_T, o_lam, o_info, o_stats;
+  size_t o_prep, o_part, o_gpart, o_rpart;
   size_t slot = 0;  // bytes between the basis slots V, C, A_prev
   size_t ws_bytes = 0;
   bool built = false;
-  bool dA_zero[3] = {true, true, true};
+  bool dA_zero[TMAX];
   bool pp_optimistic = true;  // PP sweeps: one unchecked subspace iteration per mode first
-  size_t o_Astart[3];
   void* built_ws = nullptr;
 };
 
@@ -73,31 +96,38 @@ struct TCtx {
   tucker_plan* p;
   char* ws;
   hipStream_t s;
+  Collector* col = nullptr;  // set: gather sizes only, launch nothing
   double* d(size_t off) const { return reinterpret_cast<double*>(ws + off); }
 };
 
-// Contractions the plan runs, for the workspace size of the operand and partial buffers.
-std::vector<Contr> all_contractions(const tucker_plan* p) {
-  const int64_t s0 = p->s[0], s1 = p->s[1], s2 = p->s[2], R = p->R;
-  std::vector<Contr> v = {
-      {s0 * s1, s2, 1},   // X x_3            -> (x1, x2, r3)
-      {1, s0, s1 * s2},   // X x_1            -> (x2, x3, r1)
-      {s0, s1, s2},       // X x_2            -> (x1, x3, r2)
-      {s0, s1, R},        // (x1,x2,r3) x x2  -> (x1, r3, r2)
-      {1, s0, s1 * R},    // (x1,x2,r3) x x1  -> (x2, r3, r1)
-      {1, s1, s2 * R},    // (x2,x3,r1) x x2  -> (x3, r1, r2)
-      {s0, s2, R},        // (x1,x3,r2) x x3  -> (x1, r2, r3)
-      {s1, s2, R},        // (x2,x3,r1) x x3  -> (x2, r1, r3)
-      {1, s0, s2 * R},    // (x1,x3,r2) x x1  -> (x3, r2, r1)
-      {1, s2, R * R},     // core from (x3, r1, r2)
-  };
-  for (int n = 0; n < 3; ++n) {
-    v.push_back({1, p->s[n], R * R});  // Y_(n)^T V
-    v.push_back({p->s[n], R * R, 1});  // Y_(n) Z
-  }
-  v.push_back({s0, s1 * s2, 1});       // HOSVD: X_(1) Z
-  v.push_back({1, s0 * s1, s2});       // HOSVD: X_(3) Z
+int64_t numel(const tucker_plan* p, const Lay& L) {
+  int64_t v = p->rpow[L.nr];
+  for (int m : L.modes) v *= p->s[m];
   return v;
+}
+
+// Contracting original mode m of a tensor with layout L, and the layout after it.
+Contr contr_of(const tucker_plan* p, const Lay& L, int m) {
+  Contr k{1, p->s[m], p->rpow[L.nr]};
+  bool after = false;
+  for (int q : L.modes) {
+    if (q == m) after = true;
+    else if (after) k.Q *= p->s[q];
+    else k.P *= p->s[q];
+  }
+  return k;
+}
+Lay lay_after(const Lay& L, int m) {
+  Lay o;
+  for (int q : L.modes)
+    if (q != m) o.modes.push_back(q);
+  o.nr = L.nr + 1;
+  return o;
+}
+Lay lay_all(const tucker_plan* p) {
+  Lay L;
+  for (int m = 0; m < p->N; ++m) L.modes.push_back(m);
+  return L;
 }
 
 size_t prep_elems(const Level1Geom& g) { return (size_t)g.nslices * g.Kpad * 16 * g.NB; }
@@ -105,18 +135,43 @@ size_t part_elems(const Level1Geom& g) {
   return g.ksplit > 1 ? (size_t)g.ksplit * g.M * g.R : 0;
 }
 
-// out (P x Q x R) = sum_k T(p, k, q) F(k, r)
-ppals_status ttm(const TCtx& c, const double* T, Contr k, const double* F, double* out) {
-  const Level1Geom g = l1_geom(k.P, k.K, k.Q, c.p->R, DT_F64);
+// out (M x R) = first-level contraction of T with the K x R factor F under geometry g
+ppals_status ttm_geom(const TCtx& c, const double* T, const Level1Geom& g, const double* F,
+                      double* out) {
+  if (c.col) {
+    c.col->prep = std::max(c.col->prep, prep_elems(g));
+    c.col->part = std::max(c.col->part, part_elems(g));
+    return PPALS_OK;
+  }
   KrpDesc krp;
   memset(&krp, 0, sizeof(krp));
   krp.nf = 1;
   krp.R = c.p->R;
   krp.A[0] = F;
-  krp.dim[0] = k.K;
+  krp.dim[0] = g.K;
   void* B = c.ws + c.p->o_prep;
   THIPCHK(launch_prep_operand(krp, g, DT_F64, B, c.s));
   THIPCHK(launch_level1(T, DT_F64, B, g, out, c.ws + c.p->o_part, c.s));
+  return PPALS_OK;
+}
+
+ppals_status ttm(const TCtx& c, const double* T, Contr k, const double* F, double* out) {
+  return ttm_geom(c, T, l1_geom(k.P, k.K, k.Q, c.p->R, DT_F64), F, out);
+}
+
+// Contract the modes ms (increasing) of src (layout L) with the factors F[m]: the result
+// goes to dst, the intermediate steps alternate between the two temporaries.
+ppals_status chain(const TCtx& c, const double* src, Lay L, const std::vector<int>& ms,
+                   const double* const* F, double* dst) {
+  const double* cur = src;
+  for (size_t k = 0; k < ms.size(); ++k) {
+    const bool last = k + 1 == ms.size();
+    double* out = last ? dst : c.d(c.p->o_tmp[k & 1]);
+    TCHK(ttm(c, cur, contr_of(c.p, L, ms[k]), F[ms[k]], out));
+    L = lay_after(L, ms[k]);
+    if (!last && c.col) c.col->tmp = std::max(c.col->tmp, numel(c.p, L));
+    cur = out;
+  }
   return PPALS_OK;
 }
 
@@ -143,6 +198,7 @@ constexpr int kMaxGemmSplit = 32;
 // V^T A_prev into the consecutive R x R blocks B, H, P.  V, C and A_prev are the
 // consecutive slots of the basis region.
 ppals_status projections(const TCtx& c, int64_t rows, int nb) {
+  if (c.col) return PPALS_OK;
   const int R = c.p->R;
   GemmArgs g = gemm_args(c.d(c.p->o_V), c.d(c.p->o_V), c.d(c.p->o_B), R, R, rows);
   g.sam = 1;
@@ -157,70 +213,56 @@ ppals_status projections(const TCtx& c, int64_t rows, int nb) {
   return PPALS_OK;
 }
 
-// The product X_(1) Z of the HOSVD of the middle mode: C[x2][r] = sum over (x1, x3) of
-// X[x1][x2][x3] Z[x1 s3 + x3][r], a first-level contraction whose rows (x2) and
-// contracted index (x1, x3) reach X through strided offsets.
-Level1Geom middle_unfolding_geom(const tucker_plan* p) {
-  const int64_t s0 = p->s[0], s1 = p->s[1], s2 = p->s[2];
-  Level1Geom g = l1_geom(s1, s0 * s2, 1, p->R, DT_F64);
+// The product X_(n) Z of the HOSVD for a mode n strictly inside: C[x_n][r] = sum over the
+// other modes of X[.., x_n, ..] Z[(before, after)][r], a first-level contraction whose rows
+// (x_n) and contracted index (the modes before n, then the modes after n) reach X through
+// strided offsets.
+Level1Geom inner_unfolding_geom(const tucker_plan* p, int n) {
+  int64_t before = 1, after = 1;
+  for (int m = 0; m < n; ++m) before *= p->s[m];
+  for (int m = n + 1; m < p->N; ++m) after *= p->s[m];
+  Level1Geom g = l1_geom(p->s[n], before * after, 1, p->R, DT_F64);
   g.kc_mode = 0;
   g.Q = 1;
   g.strided = 1;
-  g.mrad = s1;  // row m = x2: offset x2 s3
-  g.ms0 = 0;
-  g.ms1 = s2;
+  g.mrad = p->s[n];  // row m = x_n: offset x_n * after
   g.mrad2 = 1;
+  g.ms0 = 0;
+  g.ms1 = after;
   g.ms2 = 0;
-  g.kr1 = 1;    // k = x1 s3 + x3: offset x1 s2 s3 + x3
-  g.kr2 = (uint32_t)s2;
+  g.kr1 = 1;         // k = c_before * after + c_after: offset c_before s_n after + c_after
+  g.kr2 = (uint32_t)after;
   l1_magic(g.kr1, &g.kmag1, &g.ksh1);
   l1_magic(g.kr2, &g.kmag2, &g.ksh2);
-  g.ks0 = s1 * s2;
+  g.ks0 = p->s[n] * after;
   g.ks1 = 0;
   g.ks2 = 1;
   return g;
 }
 
-// out (M x R) = first-level contraction of T with the K x R factor F under geometry g
-ppals_status ttm_geom(const TCtx& c, const double* T, const Level1Geom& g, const double* F,
-                      double* out) {
-  KrpDesc krp;
-  memset(&krp, 0, sizeof(krp));
-  krp.nf = 1;
-  krp.R = c.p->R;
-  krp.A[0] = F;
-  krp.dim[0] = g.K;
-  void* B = c.ws + c.p->o_prep;
-  THIPCHK(launch_prep_operand(krp, g, DT_F64, B, c.s));
-  THIPCHK(launch_level1(T, DT_F64, B, g, out, c.ws + c.p->o_part, c.s));
-  return PPALS_OK;
-}
-
-// C = W V for the subspace iteration of mode n: through a TTMc Y (W = Y_(n) Y_(n)^T,
-// Y given) or, for the HOSVD (Y null), through X itself (W = X_(n) X_(n)^T) with the
-// intermediate Z = X_(n)^T V in the scratch region Zx.
+// C = W V for the subspace iteration of mode n: through a TTMc Y (W = Y_(n) Y_(n)^T, Y
+// given) or, for the HOSVD (Y null), through X itself (W = X_(n) X_(n)^T) with the
+// intermediate Z = X_(n)^T V in a chain temporary.
 ppals_status apply_w(const TCtx& c, int n, const double* Y, const double* X, const double* V,
                      double* C) {
   tucker_plan* p = c.p;
-  const int64_t s0 = p->s[0], s1 = p->s[1], s2 = p->s[2], R = p->R;
-  const int64_t sn = p->s[n];
+  const int N = p->N;
+  const int64_t sn = p->s[n], RN1 = p->rpow[N - 1];
   if (Y) {
     double* Z = c.d(p->o_Z);
-    TCHK(ttm(c, Y, {1, sn, R * R}, V, Z));  // Z = Y^T V   (R^2 x R)
-    TCHK(ttm(c, Y, {sn, R * R, 1}, Z, C));  // C = Y Z     (s_n x R)
+    TCHK(ttm(c, Y, {1, sn, RN1}, V, Z));  // Z = Y^T V   (R^(N-1) x R)
+    TCHK(ttm(c, Y, {sn, RN1, 1}, Z, C));  // C = Y Z     (s_n x R)
     return PPALS_OK;
   }
-  double* Zx = c.d(p->o_Zx);
-  if (n == 0) {
-    TCHK(ttm(c, X, {1, s0, s1 * s2}, V, Zx));  // (x2, x3, r)
-    TCHK(ttm(c, X, {s0, s1 * s2, 1}, Zx, C));  // (x1, r)
-  } else if (n == 2) {
-    TCHK(ttm(c, X, {s0 * s1, s2, 1}, V, Zx));  // (x1, x2, r)
-    TCHK(ttm(c, X, {1, s0 * s1, s2}, Zx, C));  // (x3, r)
-  } else {
-    TCHK(ttm(c, X, {s0, s1, s2}, V, Zx));      // (x1, x3, r)
-    TCHK(ttm_geom(c, X, middle_unfolding_geom(p), Zx, C));  // (x2, r)
-  }
+  double* Zx = c.d(p->o_tmp[0]);
+  const Lay L = lay_all(p);
+  const Contr k = contr_of(p, L, n);
+  if (c.col) c.col->tmp = std::max(c.col->tmp, k.P * k.Q * p->R);
+  TCHK(ttm(c, X, k, V, Zx));  // (other modes, r)
+  const int64_t others = k.P * k.Q;
+  if (n == 0) TCHK(ttm(c, X, {sn, others, 1}, Zx, C));
+  else if (n == N - 1) TCHK(ttm(c, X, {1, others, sn}, Zx, C));
+  else TCHK(ttm_geom(c, X, inner_unfolding_geom(p, n), Zx, C));
   return PPALS_OK;
 }
 
@@ -241,6 +283,7 @@ ppals_status subspace_step(const TCtx& c, int n, const double* Y, const double* 
   double* V = c.d(p->o_V);
   double* C = c.d(p->o_C);
   TCHK(apply_w(c, n, Y, X, V, C));  // C = W V
+  if (c.col) return PPALS_OK;
   TCHK(projections(c, sn, has_prev ? 3 : 2));
   RRArgs rr;
   rr.R = R;
@@ -257,24 +300,23 @@ ppals_status subspace_step(const TCtx& c, int n, const double* Y, const double* 
   return PPALS_OK;
 }
 
-// Subspace iteration for the R leading eigenvectors of W (s_n x s_n), W = Y_(n) Y_(n)^T
-// for a TTMc Y or, with Y null, X_(n) X_(n)^T (the HOSVD).  V starts from V0; A_prev (may
-// be null) orients the columns.  Result into A_out.
+// Subspace iteration for the R leading eigenvectors of W (s_n x s_n), W = Y_(n) Y_(n)^T for
+// a TTMc Y or, with Y null, X_(n) X_(n)^T (the HOSVD).  V starts from V0; A_prev (may be
+// null) orients the columns.  Result into A_out.  Synchronises once per iteration.
 ppals_status subspace(const TCtx& c, int n, const double* Y, const double* X, const double* V0,
                       const double* A_prev, double* A_out, int max_iters, int32_t* info,
                       double* residual) {
   tucker_plan* p = c.p;
+  if (c.col) {
+    IterInfo dummy;
+    return subspace_step(c, n, Y, X, A_prev != nullptr, &dummy);
+  }
   const int R = p->R;
   const int64_t sn = p->s[n];
-  double* V = c.d(p->o_V);
-  double* C = c.d(p->o_C);
-  double* U = c.d(p->o_U);
-  double* T = c.d(p->o_T);
-  double* lam = c.d(p->o_lam);
   double* Aold = c.d(p->o_Aold);
   IterInfo* dinfo = reinterpret_cast<IterInfo*>(c.ws + p->o_info) + n;
   if (A_prev && A_prev != Aold) THIPCHK(launch_copy(Aold, A_prev, sn * R, c.s));
-  THIPCHK(launch_copy(V, V0, sn * R, c.s));
+  THIPCHK(launch_copy(c.d(p->o_V), V0, sn * R, c.s));
   IterInfo hinfo;
   memset(&hinfo, 0, sizeof(hinfo));
   int it = 0, bad = 0;
@@ -290,11 +332,7 @@ ppals_status subspace(const TCtx& c, int n, const double* Y, const double* X, co
       break;
     }
   }
-  (void)V;
-  (void)C;
-  (void)T;
-  (void)lam;
-  THIPCHK(launch_copy(A_out, U, sn * R, c.s));
+  THIPCHK(launch_copy(A_out, c.d(p->o_U), sn * R, c.s));
   if (!A_prev) THIPCHK(launch_sign_by_max(A_out, sn, R, c.s));
   if (info) {
     info[0] = it;
@@ -305,53 +343,68 @@ ppals_status subspace(const TCtx& c, int n, const double* Y, const double* X, co
   return PPALS_OK;
 }
 
-// The TTMc Y^(n) needed by mode n of a sweep.  For an ALS sweep with the order-3
-// tree: mode 0 and 1 from T3 = X x_3 A^(3)T (computed at mode 0), mode 2 from
-// T1 = X x_1 A^(1)T.
-ppals_status als_ttmc(const TCtx& c, const double* X, double* const* A, int n, bool make_t3,
-                      double* Y) {
+// The prefix chain P_n = X x_0 A^(0)T .. x_(n-1) A^(n-1)T, held in o_pre[n % 2], layout
+// (x_n, .., x_(N-1), r_0, .., r_(n-1)).
+Lay prefix_lay(const tucker_plan* p, int n) {
+  Lay L;
+  for (int m = n; m < p->N; ++m) L.modes.push_back(m);
+  L.nr = n;
+  return L;
+}
+
+// Y^(n) of an ALS sweep from the prefix P_n (X for n = 0), the later modes contracted
+// with their current factors.  For n = N - 1 the prefix itself is Y^(N-1): *Y points to it.
+ppals_status als_ttmc(const TCtx& c, const double* X, const double* const* A, int n,
+                      const double** Y) {
   tucker_plan* p = c.p;
-  const int64_t s0 = p->s[0], s1 = p->s[1], s2 = p->s[2], R = p->R;
-  double* T3 = c.d(p->o_T3);
-  double* T1 = c.d(p->o_T1);
-  if (n == 0) {
-    if (make_t3) TCHK(ttm(c, X, {s0 * s1, s2, 1}, A[2], T3));
-    TCHK(ttm(c, T3, {s0, s1, R}, A[1], Y));  // (x1, r3, r2)
-  } else if (n == 1) {
-    if (make_t3) TCHK(ttm(c, X, {s0 * s1, s2, 1}, A[2], T3));
-    TCHK(ttm(c, T3, {1, s0, s1 * R}, A[0], Y));  // (x2, r3, r1)
-  } else {
-    TCHK(ttm(c, X, {1, s0, s1 * s2}, A[0], T1));
-    TCHK(ttm(c, T1, {1, s1, s2 * R}, A[1], Y));  // (x3, r1, r2)
+  const int N = p->N;
+  if (n == N - 1) {
+    *Y = c.d(p->o_pre[n & 1]);
+    return PPALS_OK;
   }
+  const double* src = n == 0 ? X : c.d(p->o_pre[n & 1]);
+  std::vector<int> ms;
+  for (int m = n + 1; m < N; ++m) ms.push_back(m);
+  TCHK(chain(c, src, prefix_lay(p, n), ms, A, c.d(p->o_Y)));
+  *Y = c.d(p->o_Y);
   return PPALS_OK;
 }
 
-// Core from Y^(3) (x3, r1, r2) and A^(3): G (r1, r2, r3); stats[6..7] = ||G||^2, ||G - G_old||^2;
-// G_old <- G.
-ppals_status finish_core(const TCtx& c, const double* Y3, const double* A3, double* G,
+// P_(n+1) = P_n x_n A^(n)T (P_0 = X).
+ppals_status extend_prefix(const TCtx& c, const double* X, const double* const* A, int n) {
+  tucker_plan* p = c.p;
+  const double* src = n == 0 ? X : c.d(p->o_pre[n & 1]);
+  const Lay L = prefix_lay(p, n);
+  return ttm(c, src, contr_of(p, L, n), A[n], c.d(p->o_pre[(n + 1) & 1]));
+}
+
+// Core from Y^(N-1) (x_(N-1), r_0 .. r_(N-2)) and A^(N-1): G (r_0 .. r_(N-1)); stats[2N],
+// stats[2N+1] = ||G||^2, ||G - G_old||^2; G_old <- G when commit.
+ppals_status finish_core(const TCtx& c, const double* Y, const double* A_last, double* G,
                          bool commit = true) {
   tucker_plan* p = c.p;
-  const int64_t R = p->R;
+  const int N = p->N;
+  const int64_t RN = p->rpow[N];
   double* Gn = c.d(p->o_Gn);
-  TCHK(ttm(c, Y3, {1, p->s[2], R * R}, A3, Gn));
-  THIPCHK(launch_core_stats(Gn, G, R * R * R, c.d(p->o_stats) + 6, c.s));
-  if (commit) THIPCHK(launch_copy(G, Gn, R * R * R, c.s));
+  TCHK(ttm(c, Y, {1, p->s[N - 1], p->rpow[N - 1]}, A_last, Gn));
+  if (c.col) return PPALS_OK;
+  THIPCHK(launch_core_stats(Gn, G, RN, c.d(p->o_stats) + 2 * N, c.s));
+  if (commit) THIPCHK(launch_copy(G, Gn, RN, c.s));
   return PPALS_OK;
 }
 
 void fill_record(const tucker_plan* p, const double* stats, double normX2, int kind,
                  tucker_sweep_record* rec) {
+  const int N = p->N;
   rec->kind = kind;
-  for (int n = 0; n < 3; ++n) {
+  for (int n = 0; n < N; ++n) {
     const double a2 = stats[2 * n], d2 = stats[2 * n + 1];
     rec->rel_change[n] = a2 > 0.0 ? std::sqrt(d2) / std::sqrt(a2) : 0.0;
   }
-  const double g2 = stats[6];
+  const double g2 = stats[2 * N];
   rec->core_norm = std::sqrt(g2);
-  rec->f_norm = std::sqrt(stats[7]);
+  rec->f_norm = std::sqrt(stats[2 * N + 1]);
   rec->fit = 1.0 - std::sqrt(std::max(0.0, normX2 - g2)) / std::sqrt(normX2);
-  (void)p;
 }
 
 ppals_status check_common(tucker_plan* p, void* ws) {
@@ -363,9 +416,8 @@ ppals_status check_common(tucker_plan* p, void* ws) {
 
 ppals_status check_factors(const tucker_plan* p, double* const* A) {
   if (!A) return set_error(PPALS_E_ARG, "NULL factor array");
-  for (int n = 0; n < 3; ++n)
+  for (int n = 0; n < p->N; ++n)
     if (!A[n]) return set_error(PPALS_E_ARG, "NULL factor " + std::to_string(n));
-  (void)p;
   return PPALS_OK;
 }
 
@@ -375,104 +427,230 @@ double now_ms() {
       .count();
 }
 
-// First-order PP TTMc of mode n into Y from the operators and dA.
+// Position of mode i among the rank indices of Y^(n) (the modes other than n, increasing).
+int rank_pos(int i, int n) { return i < n ? i : i - 1; }
+
+// Y_p^(i,n) (i != n) contracted over x_i with an s_i x R factor: result (x_n, ranks of
+// the modes other than i and n, r_i).
+Contr op_contr(const tucker_plan* p, int i, int n) {
+  const int64_t RN2 = p->rpow[p->N - 2];
+  if (i < n) return {1, p->s[i], p->s[n] * RN2};  // operator (x_i, x_n, ..)
+  return {p->s[n], p->s[i], RN2};                 // operator (x_n, x_i, ..)
+}
+
+TuckerCombine combine_args(const tucker_plan* p, int n, double* out, const double* base) {
+  TuckerCombine a;
+  memset(&a, 0, sizeof(a));
+  a.out = out;
+  a.base = base;
+  a.nd = p->N - 1;
+  a.R = p->R;
+  a.rows = p->s[n];
+  a.cols = p->rpow[p->N - 1];
+  for (int k = 0; k <= TMAX; ++k) a.rpow[k] = p->rpow[k];
+  return a;
+}
+
+// First-order PP TTMc of mode n into Y from the operators and dA (Section 3.2.2):
+// Y~^(n) = Y_p^(n) + sum_{i != n} Y_p^(i,n) x_i dA^(i)T; terms whose dA is still the zero
+// of the build are skipped.
 ppals_status pp_rhs_impl(const TCtx& c, int n, double* Y) {
   tucker_plan* p = c.p;
-  const int64_t s0 = p->s[0], s1 = p->s[1], s2 = p->s[2], R = p->R;
-  double* op01 = c.d(p->o_op01);  // (x1, x2, r3)
-  double* op02 = c.d(p->o_op02);  // (x1, x3, r2)
-  double* op12 = c.d(p->o_op12);  // (x2, x3, r1)
-  double* Ta = c.d(p->o_Ta);
-  double* Tb = c.d(p->o_Tb);
-  const double* dA[3] = {c.d(p->o_dA[0]), c.d(p->o_dA[1]), c.d(p->o_dA[2])};
-  const double* ta = nullptr;  // same rank order as Y_p^(n)
-  const double* tb = nullptr;  // rank indices swapped
-  if (n == 0) {
-    if (!p->dA_zero[1]) { TCHK(ttm(c, op01, {s0, s1, R}, dA[1], Ta)); ta = Ta; }       // (x1, r3, r2)
-    if (!p->dA_zero[2]) { TCHK(ttm(c, op02, {s0, s2, R}, dA[2], Tb)); tb = Tb; }       // (x1, r2, r3)
-  } else if (n == 1) {
-    if (!p->dA_zero[0]) { TCHK(ttm(c, op01, {1, s0, s1 * R}, dA[0], Ta)); ta = Ta; }   // (x2, r3, r1)
-    if (!p->dA_zero[2]) { TCHK(ttm(c, op12, {s1, s2, R}, dA[2], Tb)); tb = Tb; }       // (x2, r1, r3)
-  } else {
-    if (!p->dA_zero[1]) { TCHK(ttm(c, op12, {1, s1, s2 * R}, dA[1], Ta)); ta = Ta; }   // (x3, r1, r2)
-    if (!p->dA_zero[0]) { TCHK(ttm(c, op02, {1, s0, s2 * R}, dA[0], Tb)); tb = Tb; }   // (x3, r2, r1)
+  const int N = p->N;
+  TuckerCombine a = combine_args(p, n, Y, c.d(p->o_Yp[n]));
+  for (int i = 0; i < N; ++i) {
+    if (i == n || p->dA_zero[i]) continue;
+    double* T = c.d(p->o_term[a.nterms]);
+    TCHK(ttm(c, c.d(p->o_op[std::min(i, n)][std::max(i, n)]), op_contr(p, i, n),
+             c.d(p->o_dA[i]), T));
+    a.term[a.nterms] = T;
+    a.pos[a.nterms] = rank_pos(i, n);
+    ++a.nterms;
   }
-  THIPCHK(launch_pp_tucker_combine(Y, c.d(p->o_Yp[n]), ta, tb, p->s[n], (int)R, c.s));
+  if (c.col) return PPALS_OK;
+  THIPCHK(launch_tucker_combine(a, c.s));
   return PPALS_OK;
+}
+
+// PP operator build (Algorithm 4): with A_p = A, Y_p^(i,n) for every pair i < n, the other
+// modes contracted in increasing order; the first of them is 0, 1 or 2, so three passes
+// over X (F_c = X x_c A_p^(c)T) serve every operator.  Y_p^(n) from an operator.
+ppals_status build_impl(const TCtx& c, const double* X, double* const* A) {
+  tucker_plan* p = c.p;
+  const int N = p->N;
+  const double* Ap[TMAX];
+  for (int n = 0; n < N; ++n) {
+    if (!c.col) {
+      THIPCHK(launch_copy(c.d(p->o_Ap[n]), A[n], p->s[n] * p->R, c.s));
+      THIPCHK(launch_fill(c.d(p->o_dA[n]), 0.0, p->s[n] * p->R, c.s));
+    }
+    Ap[n] = c.d(p->o_Ap[n]);
+  }
+  for (int c0 = 0; c0 < 3; ++c0) {
+    const Lay L = lay_all(p);
+    TCHK(ttm(c, X, contr_of(p, L, c0), Ap[c0], c.d(p->o_F[c0])));
+    for (int i = 0; i < N; ++i)
+      for (int n = i + 1; n < N; ++n) {
+        std::vector<int> ms;
+        for (int m = 0; m < N; ++m)
+          if (m != i && m != n) ms.push_back(m);
+        if (ms.front() != c0) continue;
+        ms.erase(ms.begin());
+        double* op = c.d(p->o_op[i][n]);
+        if (ms.empty()) {
+          if (!c.col) THIPCHK(launch_copy(op, c.d(p->o_F[c0]), p->s[i] * p->s[n] * p->R, c.s));
+        } else {
+          TCHK(chain(c, c.d(p->o_F[c0]), lay_after(L, c0), ms, Ap, op));
+        }
+      }
+  }
+  for (int n = 0; n < N; ++n) {
+    const int i = n == 0 ? 1 : 0;  // Y_p^(n) = Y_p^(0,n) x_0 A_p^(0)T (n = 0: Y_p^(0,1) x_1)
+    TuckerCombine a = combine_args(p, n, c.d(p->o_Yp[n]), nullptr);
+    double* T = c.d(p->o_term[0]);
+    TCHK(ttm(c, c.d(p->o_op[std::min(i, n)][std::max(i, n)]), op_contr(p, i, n), Ap[i], T));
+    a.term[0] = T;
+    a.pos[0] = rank_pos(i, n);
+    a.nterms = 1;
+    if (!c.col) THIPCHK(launch_tucker_combine(a, c.s));
+  }
+  return PPALS_OK;
+}
+
+// HOSVD core: G = X x_0 A^(0)T .. x_(N-1) A^(N-1)T.
+ppals_status hosvd_core(const TCtx& c, const double* X, const double* const* A, double* G) {
+  std::vector<int> ms;
+  for (int m = 0; m < c.p->N; ++m) ms.push_back(m);
+  return chain(c, X, lay_all(c.p), ms, A, G);
+}
+
+// ALS sweep schedule (also run in collecting mode for the workspace sizes).
+ppals_status als_impl(const TCtx& c, const double* X, double* const* A, double* G,
+                      tucker_sweep_record* rec) {
+  tucker_plan* p = c.p;
+  const int N = p->N;
+  const int R = p->R;
+  double* Aold = c.d(p->o_Aold);
+  double* stats = c.d(p->o_stats);
+  const double* Y = nullptr;
+  for (int n = 0; n < N; ++n) {
+    TCHK(als_ttmc(c, X, A, n, &Y));
+    if (!c.col) THIPCHK(launch_copy(Aold, A[n], p->s[n] * R, c.s));
+    int32_t info[3] = {0, 0, 0};
+    TCHK(subspace(c, n, Y, nullptr, Aold, Aold, A[n], p->max_iters, info,
+                  rec ? &rec->ritz_residual[n] : nullptr));
+    if (rec) {
+      rec->iters[n] = info[0];
+      rec->converged[n] = info[1];
+      rec->rr_status[n] = info[2];
+    }
+    if (!c.col) THIPCHK(launch_core_stats(A[n], Aold, p->s[n] * R, stats + 2 * n, c.s));
+    if (n < N - 1) TCHK(extend_prefix(c, X, A, n));
+  }
+  return finish_core(c, Y, A[N - 1], G);
 }
 
 }  // namespace
 
 extern "C" {
 
-ppals_status tucker_plan_create(const int64_t dims[3], int32_t rank, tucker_plan** out) {
+ppals_status tucker_plan_create(int32_t order, const int64_t* dims, int32_t rank,
+                                tucker_plan** out) {
   if (!dims || !out) return set_error(PPALS_E_ARG, "NULL argument");
   *out = nullptr;
+  if (order < 3 || order > TMAX) return set_error(PPALS_E_UNSUPPORTED, "order must be in [3, 8]");
   if (rank < 1 || rank > TUCKER_MAX_RANK)
     return set_error(PPALS_E_UNSUPPORTED, "Tucker rank must be in [1, 64]");
-  for (int n = 0; n < 3; ++n) {
+  double total = 1.0;
+  for (int n = 0; n < order; ++n) {
     if (dims[n] < 1) return set_error(PPALS_E_ARG, "dims must be >= 1");
     if (dims[n] < rank)
       return set_error(PPALS_E_UNSUPPORTED, "Tucker rank must not exceed any dimension");
+    total *= (double)dims[n];
   }
-  if ((double)dims[0] * (double)dims[2] > 2147483647.0 - 64.0)
-    return set_error(PPALS_E_UNSUPPORTED, "s1 * s3 must stay below 2^31 - 64 (strided HOSVD product)");
+  for (int n = 1; n < order - 1; ++n)
+    if (total / (double)dims[n] > 2147483647.0 - 64.0)
+      return set_error(PPALS_E_UNSUPPORTED,
+                       "the product of the other dimensions of an inner mode must stay below "
+                       "2^31 - 64 (strided HOSVD product)");
+  if (std::pow((double)rank, order) > 1.0e12)
+    return set_error(PPALS_E_UNSUPPORTED, "R^N too large");
   tucker_plan* p = new tucker_plan();
-  for (int n = 0; n < 3; ++n) p->s[n] = dims[n];
+  p->N = order;
   p->R = rank;
-  const int64_t s0 = dims[0], s1 = dims[1], s2 = dims[2], R = rank;
-  const int64_t smax = std::max(s0, std::max(s1, s2));
+  for (int n = 0; n < order; ++n) {
+    p->s[n] = dims[n];
+    p->dA_zero[n] = true;
+  }
+  p->rpow[0] = 1;
+  for (int k = 1; k <= TMAX; ++k) p->rpow[k] = p->rpow[k - 1] * (k <= order ? rank : 1);
+  const int N = order;
+  const int64_t R = rank;
+  int64_t smax = 0;
+  for (int n = 0; n < N; ++n) smax = std::max(smax, dims[n]);
+  // gather the schedules' sizes without launching
+  Collector col;
+  {
+    TCtx c{p, nullptr, nullptr, &col};
+    double* fake[TMAX];
+    for (int n = 0; n < N; ++n) fake[n] = nullptr;
+    const double* some = reinterpret_cast<const double*>(p);  // any non-null Y: sweep form
+    for (int n = 0; n < N; ++n) {
+      apply_w(c, n, nullptr, nullptr, nullptr, nullptr);  // HOSVD
+      apply_w(c, n, some, nullptr, nullptr, nullptr);     // sweeps
+    }
+    hosvd_core(c, nullptr, fake, nullptr);
+    for (int n = 0; n < N; ++n) {  // tucker_ttmc
+      std::vector<int> ms;
+      for (int m = 0; m < N; ++m)
+        if (m != n) ms.push_back(m);
+      chain(c, nullptr, lay_all(p), ms, fake, nullptr);
+    }
+    als_impl(c, nullptr, fake, nullptr, nullptr);
+    build_impl(c, nullptr, fake);
+    for (int n = 0; n < N; ++n) p->dA_zero[n] = false;  // every correction term
+    for (int n = 0; n < N; ++n) pp_rhs_impl(c, n, nullptr);
+    for (int n = 0; n < N; ++n) p->dA_zero[n] = true;
+  }
+  int64_t pre = 1;  // largest prefix P_n, n >= 1
+  for (int n = 1; n < N; ++n) pre = std::max(pre, numel(p, prefix_lay(p, n)));
   size_t off = 0;
   auto take = [&](size_t elems) {
     const size_t o = off;
     off += al256(std::max<size_t>(elems, 1) * sizeof(double));
     return o;
   };
-  p->o_T3 = take(s0 * s1 * R);
-  p->o_T1 = take(s1 * s2 * R);
-  p->o_op01 = take(s0 * s1 * R);
-  p->o_op02 = take(s0 * s2 * R);
-  p->o_op12 = take(s1 * s2 * R);
-  for (int n = 0; n < 3; ++n) p->o_Yp[n] = take(dims[n] * R * R);
-  p->o_Y = take(smax * R * R);
-  p->o_Ta = take(smax * R * R);
-  p->o_Tb = take(smax * R * R);
-  p->o_Gn = take(R * R * R);
-  for (int n = 0; n < 3; ++n) p->o_Ap[n] = take(dims[n] * R);
-  for (int n = 0; n < 3; ++n) p->o_dA[n] = take(dims[n] * R);
+  for (int k = 0; k < 2; ++k) p->o_pre[k] = take(pre);
+  for (int k = 0; k < 2; ++k) p->o_tmp[k] = take(col.tmp);
+  for (int c0 = 0; c0 < 3; ++c0) p->o_F[c0] = take(numel(p, lay_after(lay_all(p), c0)));
+  for (int i = 0; i < N; ++i)
+    for (int n = i + 1; n < N; ++n) p->o_op[i][n] = take(dims[i] * dims[n] * p->rpow[N - 2]);
+  for (int n = 0; n < N; ++n) p->o_Yp[n] = take(dims[n] * p->rpow[N - 1]);
+  p->o_Y = take(smax * p->rpow[N - 1]);
+  for (int t = 0; t < N - 1; ++t) p->o_term[t] = take(smax * p->rpow[N - 1]);
+  p->o_Gn = take(p->rpow[N]);
+  for (int n = 0; n < N; ++n) p->o_Ap[n] = take(dims[n] * R);
+  for (int n = 0; n < N; ++n) p->o_dA[n] = take(dims[n] * R);
+  for (int n = 0; n < N; ++n) p->o_Astart[n] = take(dims[n] * R);
   // basis slots V, C, A_prev at equal spacing (one batched projection launch)
   p->slot = al256((size_t)smax * R * sizeof(double));
   p->o_V = take(smax * R);
   p->o_C = take(smax * R);
   p->o_Aold = take(smax * R);
   p->o_U = take(smax * R);
-  p->o_Z = take(R * R * R);
+  p->o_Z = take(p->rpow[N - 1] * R);
   // B, H, P consecutive R x R blocks
   p->o_B = take(3 * R * R);
   p->o_H = p->o_B + (size_t)R * R * sizeof(double);
   p->o_P = p->o_H + (size_t)R * R * sizeof(double);
-  p->o_rpart = take(((smax + kRitzRows - 1) / kRitzRows) * R);
   p->o_T = take(R * R);
   p->o_lam = take(R);
-  p->o_info = take(8);  // an iteration record per mode
-  for (int n = 0; n < 3; ++n) p->o_Astart[n] = take(dims[n] * R);
-  p->o_stats = take(8);
-  size_t prep = 1, part = 1;
-  for (const Contr& k : all_contractions(p)) {
-    const Level1Geom g = l1_geom(k.P, k.K, k.Q, p->R, DT_F64);
-    prep = std::max(prep, prep_elems(g));
-    part = std::max(part, part_elems(g));
-  }
-  {
-    const Level1Geom g = middle_unfolding_geom(p);
-    prep = std::max(prep, prep_elems(g));
-    part = std::max(part, part_elems(g));
-  }
-  p->o_prep = take(prep);
-  p->o_part = take(std::max<size_t>(part, 1024));
+  p->o_info = take(2 * TMAX);  // an iteration record per mode
+  p->o_stats = take(2 * TMAX + 2);
+  p->o_rpart = take(((smax + kRitzRows - 1) / kRitzRows) * R);
+  p->o_prep = take(col.prep);
+  p->o_part = take(col.part);
   p->o_gpart = take((size_t)kMaxGemmSplit * 3 * R * R);
-  // HOSVD intermediate X_(n)^T V: the largest of s2 s3, s1 s3, s1 s2 times R
-  p->o_Zx = take(std::max(s1 * s2, std::max(s0 * s2, s0 * s1)) * R);
   p->ws_bytes = off;
   *out = p;
   return PPALS_OK;
@@ -498,9 +676,12 @@ ppals_status tucker_ttmc(tucker_plan* plan, void* ws, const double* X, double* c
   TCHK(check_common(plan, ws));
   TCHK(check_factors(plan, A));
   if (!X || !Y) return set_error(PPALS_E_ARG, "NULL argument");
-  if (mode < 0 || mode > 2) return set_error(PPALS_E_ARG, "mode must be 0, 1 or 2");
+  if (mode < 0 || mode >= plan->N) return set_error(PPALS_E_ARG, "mode out of range");
   TCtx c{plan, (char*)ws, stream};
-  return als_ttmc(c, X, A, mode, true, Y);
+  std::vector<int> ms;
+  for (int m = 0; m < plan->N; ++m)
+    if (m != mode) ms.push_back(m);
+  return chain(c, X, lay_all(plan), ms, A, Y);
 }
 
 ppals_status tucker_factor_update(tucker_plan* plan, void* ws, const double* Y, int32_t mode,
@@ -508,7 +689,7 @@ ppals_status tucker_factor_update(tucker_plan* plan, void* ws, const double* Y, 
                                   double* residual, hipStream_t stream) {
   TCHK(check_common(plan, ws));
   if (!Y || !A_prev || !A_out) return set_error(PPALS_E_ARG, "NULL argument");
-  if (mode < 0 || mode > 2) return set_error(PPALS_E_ARG, "mode must be 0, 1 or 2");
+  if (mode < 0 || mode >= plan->N) return set_error(PPALS_E_ARG, "mode out of range");
   TCtx c{plan, (char*)ws, stream};
   double* Aold = c.d(plan->o_Aold);
   THIPCHK(launch_copy(Aold, A_prev, plan->s[mode] * plan->R, stream));
@@ -522,15 +703,10 @@ ppals_status tucker_hosvd(tucker_plan* plan, void* ws, const double* X, double* 
   TCHK(check_factors(plan, V0));
   if (!X || !G) return set_error(PPALS_E_ARG, "NULL argument");
   TCtx c{plan, (char*)ws, stream};
-  for (int n = 0; n < 3; ++n)
+  for (int n = 0; n < plan->N; ++n)
     TCHK(subspace(c, n, nullptr, X, V0[n], nullptr, A[n], plan->hosvd_iters,
                   info ? info + 3 * n : nullptr, nullptr));
-  const int64_t s0 = plan->s[0], s1 = plan->s[1], s2 = plan->s[2], R = plan->R;
-  double* T1 = c.d(plan->o_T1);
-  double* Y = c.d(plan->o_Y);
-  TCHK(ttm(c, X, {1, s0, s1 * s2}, A[0], T1));    // (x2, x3, r1)
-  TCHK(ttm(c, T1, {1, s1, s2 * R}, A[1], Y));     // (x3, r1, r2)
-  TCHK(ttm(c, Y, {1, s2, R * R}, A[2], G));       // (r1, r2, r3)
+  TCHK(hosvd_core(c, X, A, G));
   THIPCHK(hipStreamSynchronize(stream));
   plan->built = false;
   return PPALS_OK;
@@ -546,24 +722,10 @@ ppals_status tucker_als_sweep(tucker_plan* plan, void* ws, const double* X, doub
   const double t0 = now_ms();
   TCtx c{plan, (char*)ws, stream};
   memset(rec, 0, sizeof(*rec));
-  double* Y = c.d(plan->o_Y);
-  double* Aold = c.d(plan->o_Aold);
-  double* stats = c.d(plan->o_stats);
-  const int R = plan->R;
-  for (int n = 0; n < 3; ++n) {
-    TCHK(als_ttmc(c, X, A, n, n == 0, Y));
-    THIPCHK(launch_copy(Aold, A[n], plan->s[n] * R, stream));
-    int32_t info[3];
-    TCHK(subspace(c, n, Y, nullptr, Aold, Aold, A[n], plan->max_iters, info,
-                  &rec->ritz_residual[n]));
-    rec->iters[n] = info[0];
-    rec->converged[n] = info[1];
-    rec->rr_status[n] = info[2];
-    THIPCHK(launch_core_stats(A[n], Aold, plan->s[n] * R, stats + 2 * n, stream));
-  }
-  TCHK(finish_core(c, Y, A[2], G));
-  double h[8];
-  THIPCHK(hipMemcpyAsync(h, stats, sizeof(h), hipMemcpyDeviceToHost, stream));
+  TCHK(als_impl(c, X, A, G, rec));
+  double h[2 * TMAX + 2];
+  THIPCHK(hipMemcpyAsync(h, c.d(plan->o_stats), sizeof(double) * (2 * plan->N + 2),
+                         hipMemcpyDeviceToHost, stream));
   THIPCHK(hipStreamSynchronize(stream));
   fill_record(plan, h, normX2, PPALS_SWEEP_ALS, rec);
   rec->ms = now_ms() - t0;
@@ -576,21 +738,8 @@ ppals_status tucker_pp_build(tucker_plan* plan, void* ws, const double* X, doubl
   TCHK(check_factors(plan, A));
   if (!X) return set_error(PPALS_E_ARG, "NULL argument");
   TCtx c{plan, (char*)ws, stream};
-  const int64_t s0 = plan->s[0], s1 = plan->s[1], s2 = plan->s[2], R = plan->R;
-  double* op01 = c.d(plan->o_op01);
-  double* op02 = c.d(plan->o_op02);
-  double* op12 = c.d(plan->o_op12);
-  for (int n = 0; n < 3; ++n) {
-    THIPCHK(launch_copy(c.d(plan->o_Ap[n]), A[n], plan->s[n] * R, stream));
-    THIPCHK(launch_fill(c.d(plan->o_dA[n]), 0.0, plan->s[n] * R, stream));
-    plan->dA_zero[n] = true;
-  }
-  TCHK(ttm(c, X, {s0 * s1, s2, 1}, A[2], op01));          // (x1, x2, r3)
-  TCHK(ttm(c, X, {s0, s1, s2}, A[1], op02));              // (x1, x3, r2)
-  TCHK(ttm(c, X, {1, s0, s1 * s2}, A[0], op12));          // (x2, x3, r1)
-  TCHK(ttm(c, op01, {s0, s1, R}, A[1], c.d(plan->o_Yp[0])));      // (x1, r3, r2)
-  TCHK(ttm(c, op01, {1, s0, s1 * R}, A[0], c.d(plan->o_Yp[1])));  // (x2, r3, r1)
-  TCHK(ttm(c, op12, {1, s1, s2 * R}, A[1], c.d(plan->o_Yp[2])));  // (x3, r1, r2)
+  TCHK(build_impl(c, X, A));
+  for (int n = 0; n < plan->N; ++n) plan->dA_zero[n] = true;
   plan->built = true;
   plan->built_ws = ws;
   plan->pp_optimistic = true;
@@ -601,7 +750,7 @@ ppals_status tucker_pp_rhs(tucker_plan* plan, void* ws, int32_t mode, double* Y,
                            hipStream_t stream) {
   TCHK(check_common(plan, ws));
   if (!Y) return set_error(PPALS_E_ARG, "NULL argument");
-  if (mode < 0 || mode > 2) return set_error(PPALS_E_ARG, "mode must be 0, 1 or 2");
+  if (mode < 0 || mode >= plan->N) return set_error(PPALS_E_ARG, "mode out of range");
   if (!plan->built || plan->built_ws != ws)
     return set_error(PPALS_E_STATE, "tucker_pp_rhs before tucker_pp_build on this workspace");
   TCtx c{plan, (char*)ws, stream};
@@ -622,6 +771,7 @@ ppals_status tucker_pp_sweep(tucker_plan* plan, void* ws, double* const* A, doub
   const double t0 = now_ms();
   TCtx c{plan, (char*)ws, stream};
   memset(rec, 0, sizeof(*rec));
+  const int N = plan->N;
   double* Y = c.d(plan->o_Y);
   double* Aold = c.d(plan->o_Aold);
   double* stats = c.d(plan->o_stats);
@@ -633,12 +783,12 @@ ppals_status tucker_pp_sweep(tucker_plan* plan, void* ws, double* const* A, doub
     // read once at the end.  If a mode did not converge, that mode and the later ones are
     // restored and redone below with a check after every iteration (same launches in the
     // same order, so the result does not depend on the path).
-    bool zero_start[3];
-    for (int n = 0; n < 3; ++n) {
+    bool zero_start[TMAX];
+    for (int n = 0; n < N; ++n) {
       zero_start[n] = plan->dA_zero[n];
       THIPCHK(launch_copy(c.d(plan->o_Astart[n]), A[n], plan->s[n] * R, stream));
     }
-    for (int n = 0; n < 3; ++n) {
+    for (int n = 0; n < N; ++n) {
       TCHK(pp_rhs_impl(c, n, Y));
       THIPCHK(launch_copy(Aold, A[n], plan->s[n] * R, stream));
       THIPCHK(launch_copy(c.d(plan->o_V), Aold, plan->s[n] * R, stream));
@@ -650,12 +800,12 @@ ppals_status tucker_pp_sweep(tucker_plan* plan, void* ws, double* const* A, doub
       plan->dA_zero[n] = false;
       THIPCHK(launch_core_stats(A[n], Ap, plan->s[n] * R, stats + 2 * n, stream));
     }
-    TCHK(finish_core(c, Y, A[2], G, false));
-    IterInfo hi[3];
-    THIPCHK(hipMemcpyAsync(hi, dinfo, sizeof(hi), hipMemcpyDeviceToHost, stream));
+    TCHK(finish_core(c, Y, A[N - 1], G, false));
+    IterInfo hi[TMAX];
+    THIPCHK(hipMemcpyAsync(hi, dinfo, sizeof(IterInfo) * N, hipMemcpyDeviceToHost, stream));
     THIPCHK(hipStreamSynchronize(stream));
-    n0 = 3;
-    for (int n = 2; n >= 0; --n)
+    n0 = N;
+    for (int n = N - 1; n >= 0; --n)
       if (!(hi[n].residual <= plan->tol)) n0 = n;
     for (int n = 0; n < n0; ++n) {
       rec->iters[n] = 1;
@@ -663,19 +813,19 @@ ppals_status tucker_pp_sweep(tucker_plan* plan, void* ws, double* const* A, doub
       rec->rr_status[n] = hi[n].rr_bad;
       rec->ritz_residual[n] = hi[n].residual;
     }
-    if (n0 == 3) {
-      THIPCHK(launch_copy(G, c.d(plan->o_Gn), (int64_t)R * R * R, stream));
+    if (n0 == N) {
+      THIPCHK(launch_copy(G, c.d(plan->o_Gn), plan->rpow[N], stream));
     } else {
       plan->pp_optimistic = false;
-      for (int n = n0; n < 3; ++n) {
+      for (int n = n0; n < N; ++n) {
         THIPCHK(launch_copy(A[n], c.d(plan->o_Astart[n]), plan->s[n] * R, stream));
         THIPCHK(launch_sub(c.d(plan->o_dA[n]), A[n], c.d(plan->o_Ap[n]), plan->s[n] * R, stream));
         plan->dA_zero[n] = zero_start[n];
       }
     }
   }
-  if (n0 < 3) {
-    for (int n = n0; n < 3; ++n) {
+  if (n0 < N) {
+    for (int n = n0; n < N; ++n) {
       TCHK(pp_rhs_impl(c, n, Y));
       THIPCHK(launch_copy(Aold, A[n], plan->s[n] * R, stream));
       int32_t info[3];
@@ -690,12 +840,14 @@ ppals_status tucker_pp_sweep(tucker_plan* plan, void* ws, double* const* A, doub
       plan->dA_zero[n] = false;
       THIPCHK(launch_core_stats(A[n], Ap, plan->s[n] * R, stats + 2 * n, stream));
     }
-    TCHK(finish_core(c, Y, A[2], G));
+    TCHK(finish_core(c, Y, A[N - 1], G));
     // back to the unsynchronised pass once a sweep needs a single iteration everywhere
-    plan->pp_optimistic = rec->iters[0] == 1 && rec->iters[1] == 1 && rec->iters[2] == 1;
+    bool ones = true;
+    for (int n = 0; n < N; ++n) ones = ones && rec->iters[n] == 1;
+    plan->pp_optimistic = ones;
   }
-  double h[8];
-  THIPCHK(hipMemcpyAsync(h, stats, sizeof(h), hipMemcpyDeviceToHost, stream));
+  double h[2 * TMAX + 2];
+  THIPCHK(hipMemcpyAsync(h, stats, sizeof(double) * (2 * N + 2), hipMemcpyDeviceToHost, stream));
   THIPCHK(hipStreamSynchronize(stream));
   fill_record(plan, h, normX2, kind, rec);
   rec->ms = now_ms() - t0;
@@ -712,13 +864,14 @@ ppals_status tucker_run(tucker_plan* plan, void* ws, const double* X, double* co
   if (sweeps < 0) return set_error(PPALS_E_ARG, "sweeps must be >= 0");
   if (!(eps >= 0.0)) return set_error(PPALS_E_ARG, "eps must be >= 0");
   *n_out = 0;
-  const int64_t count = plan->s[0] * plan->s[1] * plan->s[2];
-  const int64_t R3 = (int64_t)plan->R * plan->R * plan->R;
+  const int N = plan->N;
+  int64_t count = 1;
+  for (int n = 0; n < N; ++n) count *= plan->s[n];
   double* stats = reinterpret_cast<double*>((char*)ws + plan->o_stats);
   // ||X||^2 with the multi-workgroup reduction (partials in the level-1 partial region)
   THIPCHK(launch_norm2(X, DT_F64, count, reinterpret_cast<double*>((char*)ws + plan->o_part), 1024,
                        stats, stream));
-  THIPCHK(launch_core_stats(G, G, R3, stats + 2, stream));
+  THIPCHK(launch_core_stats(G, G, plan->rpow[N], stats + 2, stream));
   double h[4];
   THIPCHK(hipMemcpyAsync(h, stats, sizeof(h), hipMemcpyDeviceToHost, stream));
   THIPCHK(hipStreamSynchronize(stream));
@@ -744,17 +897,23 @@ ppals_status tucker_run(tucker_plan* plan, void* ws, const double* X, double* co
     }
     return PPALS_OK;
   }
-  double rel[3] = {1.0, 1.0, 1.0};  // dA = A initially
+  double rel[TMAX];
+  for (int i = 0; i < N; ++i) rel[i] = 1.0;  // dA = A initially
   double f_norm = std::sqrt(h[2]);
   auto stopped = [&]() { return delta > 0.0 && n > 0 && recs[n - 1].f_norm <= delta * normX; };
+  auto small = [&]() {
+    for (int i = 0; i < N; ++i)
+      if (!(rel[i] < eps)) return false;
+    return true;
+  };
   while (n < sweeps && !stopped()) {
-    if (rel[0] < eps && rel[1] < eps && rel[2] < eps && f_norm < eps * normX) {
+    if (small() && f_norm < eps * normX) {
       TCHK(tucker_pp_build(plan, ws, X, A, stream));
       int kind = PPALS_SWEEP_PP_INIT;
       while (n < sweeps && f_norm < eps * normX && !stopped()) {
         TCHK(tucker_pp_sweep(plan, ws, A, G, normX2, kind, &recs[n], stream));
         f_norm = recs[n].f_norm;
-        for (int i = 0; i < 3; ++i) rel[i] = recs[n].rel_change[i];
+        for (int i = 0; i < N; ++i) rel[i] = recs[n].rel_change[i];
         *n_out = ++n;
         kind = PPALS_SWEEP_PP_APPROX;
       }
@@ -762,7 +921,7 @@ ppals_status tucker_run(tucker_plan* plan, void* ws, const double* X, double* co
     }
     TCHK(tucker_als_sweep(plan, ws, X, A, G, normX2, &recs[n], stream));
     f_norm = recs[n].f_norm;
-    for (int i = 0; i < 3; ++i) rel[i] = recs[n].rel_change[i];
+    for (int i = 0; i < N; ++i) rel[i] = recs[n].rel_change[i];
     *n_out = ++n;
   }
   return PPALS_OK;

@@ -40,8 +40,18 @@ hipError_t launch_ritz_update(double* V, const double* C, const double* T, const
                               double* U, double* part, int64_t rows, int R, double* residual,
                               hipStream_t s);
 hipError_t launch_sign_by_max(double* V, int64_t rows, int R, hipStream_t s);
-hipError_t launch_pp_tucker_combine(double* out, const double* Yp, const double* T1,
-                                    const double* T2, int64_t rows, int R, hipStream_t s);
+struct TuckerCombine {
+  double* out;              // rows x cols
+  const double* base;       // rows x cols, or null
+  const double* term[7];    // rows x cols each, rank digit pos[t] moved last
+  int pos[7];
+  int nterms;
+  int nd;                   // rank digits (N - 1)
+  int R;
+  int64_t rows, cols;       // s_n, R^(N-1)
+  int64_t rpow[9];          // R^k
+};
+hipError_t launch_tucker_combine(const TuckerCombine& a, hipStream_t s);
 hipError_t launch_core_stats(const double* Gn, const double* Go, int64_t n, double* out,
                              hipStream_t s);
 

@@ -295,17 +295,19 @@ def test_tucker_plan_validates_and_refuses_before_device_work(lib):
     from paper_1811_10573_amd import _lib
     h = ctypes.c_void_p()
     dims = (ctypes.c_int64 * 3)(30, 20, 10)
-    assert lib.tucker_plan_create(dims, 0, ctypes.byref(h)) == _lib.PPALS_E_UNSUPPORTED
-    assert lib.tucker_plan_create(dims, 65, ctypes.byref(h)) == _lib.PPALS_E_UNSUPPORTED
-    assert lib.tucker_plan_create(dims, 11, ctypes.byref(h)) == _lib.PPALS_E_UNSUPPORTED
+    assert lib.tucker_plan_create(3, dims, 0, ctypes.byref(h)) == _lib.PPALS_E_UNSUPPORTED
+    assert lib.tucker_plan_create(3, dims, 65, ctypes.byref(h)) == _lib.PPALS_E_UNSUPPORTED
+    assert lib.tucker_plan_create(3, dims, 11, ctypes.byref(h)) == _lib.PPALS_E_UNSUPPORTED
+    assert lib.tucker_plan_create(2, dims, 3, ctypes.byref(h)) == _lib.PPALS_E_UNSUPPORTED
+    assert lib.tucker_plan_create(9, dims, 3, ctypes.byref(h)) == _lib.PPALS_E_UNSUPPORTED
     bad = (ctypes.c_int64 * 3)(30, 0, 10)
-    assert lib.tucker_plan_create(bad, 3, ctypes.byref(h)) == _lib.PPALS_E_ARG
-    assert lib.tucker_plan_create(dims, 10, ctypes.byref(h)) == 0
+    assert lib.tucker_plan_create(3, bad, 3, ctypes.byref(h)) == _lib.PPALS_E_ARG
+    assert lib.tucker_plan_create(3, dims, 10, ctypes.byref(h)) == 0
     try:
         R = 10
         ws_bytes = lib.tucker_workspace_bytes(h)
-        # at least the three pairwise operators, the three Y_p^(n) and the Gram W
-        assert ws_bytes >= 8 * ((30 * 20 + 30 * 10 + 20 * 10) * R + (30 + 20 + 10) * R * R + 30 * 30)
+        # at least the three pairwise operators and the three Y_p^(n)
+        assert ws_bytes >= 8 * ((30 * 20 + 30 * 10 + 20 * 10) * R + (30 + 20 + 10) * R * R)
         assert lib.tucker_set_solver(h, 0.0, 10, 10) == _lib.PPALS_E_ARG
         assert lib.tucker_set_solver(h, 1e-10, 0, 10) == _lib.PPALS_E_ARG
         assert lib.tucker_set_solver(h, 1e-12, 500, 5000) == 0
@@ -318,7 +320,7 @@ def test_tucker_plan_validates_and_refuses_before_device_work(lib):
         assert lib.tucker_pp_sweep(h, fake, arr, fake, 1.0, 0, ctypes.byref(rec), nul) == _lib.PPALS_E_ARG
         assert lib.tucker_pp_sweep(h, ctypes.c_void_p(0x1008), arr, fake, 1.0, 2, ctypes.byref(rec),
                                    nul) == _lib.PPALS_E_WORKSPACE
-        assert lib.tucker_ttmc(h, fake, fake, arr, 3, fake, nul) == _lib.PPALS_E_ARG
+        assert lib.tucker_ttmc(h, fake, fake, arr, 3, fake, nul) == _lib.PPALS_E_ARG  # mode 3 of 3
         assert lib.tucker_als_sweep(h, fake, nul, arr, fake, 1.0, ctypes.byref(rec), nul) == _lib.PPALS_E_ARG
         assert lib.tucker_als_sweep(h, fake, fake, arr, fake, 0.0, ctypes.byref(rec), nul) == _lib.PPALS_E_ARG
         part = (ctypes.c_void_p * 3)(0x2000, None, 0x4000)

@@ -1,9 +1,9 @@
 """GPU parity of the order-3 Tucker path (Tucker-ALS, Algorithm 2; PP-Tucker-ALS,
 Algorithm 4 with the first-order TTMc of Section 3.2.2) against the float64 oracle.
 
-Layouts: the library stores Y^(n) as s_n x R x R with rank indices (r3, r2), (r3, r1),
-(r1, r2) for n = 0, 1, 2; the oracle's ttmc keeps the natural mode order, so the
-comparison transposes.  Tolerances: TTMc and core are contractions of length <= s^2
+Layouts: the library stores Y^(n) as s_n x R^(N-1) with x_n first and the rank indices of
+the other modes in increasing mode order (the oracle's ttmc with mode n moved to the
+front); the core is (r_1, .., r_N) on both sides.  Tolerances: TTMc and core are contractions of length <= s^2
 accumulated in FP64 (relative 1e-12 of the |.|-weighted sum is far above gamma_K u);
 factors come from a subspace iteration stopped at a Ritz residual of 1e-12 relative to
 the largest eigenvalue, whose eigenvector error is that residual times
@@ -21,12 +21,9 @@ pytestmark = pytest.mark.gpu
 
 pk = pytest.importorskip("paper_1811_10573_amd")
 
-# oracle Y^(n) (natural order) -> library layout
-TO_LIB = [(0, 2, 1), (1, 2, 0), (2, 0, 1)]
-
-
 def lib_layout(Y, n):
-    return np.ascontiguousarray(np.transpose(Y, TO_LIB[n]))
+    """Oracle Y^(n) (natural order) -> library layout (x_n first)."""
+    return np.ascontiguousarray(np.moveaxis(Y, n, 0))
 
 
 def host(t, shape=None):
@@ -36,8 +33,9 @@ def host(t, shape=None):
 
 class TRun:
     def __init__(self, shape, R, seed=0, eta=0.1):
-        self.prob = tensorgen.make_tucker_problem(shape, (R, R, R), seed=seed, eta=eta)
+        self.prob = tensorgen.make_tucker_problem(shape, (R,) * len(shape), seed=seed, eta=eta)
         self.shape = tuple(shape)
+        self.N = len(shape)
         self.R = R
         self.plan = pk.TuckerPlan(shape, R)
         self.X = to_dev(self.prob.X)
@@ -52,7 +50,16 @@ class TRun:
         return [host(a, (s, self.R)) for a, s in zip(self.A, self.shape)]
 
     def core(self):
-        return host(self.G, (self.R,) * 3)
+        return host(self.G, (self.R,) * self.N)
+
+    def ranks(self):
+        return (self.R,) * self.N
+
+    def zero_core(self):
+        return np.zeros((self.R,) * self.N)
+
+    def zero_y(self, n):
+        return np.zeros((self.shape[n],) + (self.R,) * (self.N - 1))
 
 
 def assert_rel(got, want, tol, what):
@@ -60,16 +67,18 @@ def assert_rel(got, want, tol, what):
     assert err <= tol, f"{what}: relative error {err:.3e} > {tol:.1e}"
 
 
-@pytest.mark.parametrize("shape,R", [((37, 29, 23), 5), ((70, 64, 66), 16), ((96, 80, 72), 64)])
+@pytest.mark.parametrize("shape,R", [((37, 29, 23), 5), ((70, 64, 66), 16), ((96, 80, 72), 64),
+                                     ((14, 12, 11, 10), 3), ((9, 8, 7, 8, 6), 3),
+                                     ((6, 5, 6, 5, 6, 5), 2)])
 def test_ttmc_matches_oracle(shape, R):
     """Y^(n) = X x_{i != n} A^(i)T for every mode: ragged sizes, several level-1 tiles,
     the largest rank."""
     r = TRun(shape, R, seed=1)
     rng = np.random.default_rng(2)
     A = [np.linalg.qr(rng.standard_normal((s, R)))[0] for s in shape]
-    r.upload(A, np.zeros((R, R, R)))
-    for n in range(3):
-        Y = to_dev(np.zeros((shape[n], R, R)))
+    r.upload(A, r.zero_core())
+    for n in range(r.N):
+        Y = to_dev(r.zero_y(n))
         pk.tucker_ttmc(r.plan, r.ws, r.X, r.A, n, Y)
         want = lib_layout(ot.ttmc(r.prob.X, A, n), n)
         assert_rel(host(Y, want.shape), want, 1e-12, f"Y^({n})")
@@ -80,9 +89,9 @@ def test_factor_update_matches_eigh(shape, R):
     """Leading eigenvectors of Y_(n) Y_(n)^T, oriented against the previous factor, from a
     TTMc the oracle made (one HOOI step past the HOSVD)."""
     r = TRun(shape, R, seed=3)
-    A0, _ = ot.hosvd(r.prob.X, (R, R, R))
-    A1, _, _ = ot.tucker_als(r.prob.X, A0, ot.hosvd(r.prob.X, (R, R, R))[1], 1)
-    for n in range(3):
+    A0, _ = ot.hosvd(r.prob.X, r.ranks())
+    A1, _, _ = ot.tucker_als(r.prob.X, A0, ot.hosvd(r.prob.X, r.ranks())[1], 1)
+    for n in range(r.N):
         Yn = ot.ttmc(r.prob.X, A1, n)
         want, _ = ot.leading_eigvecs(Yn, n, R, prev=A0[n])
         Y = to_dev(lib_layout(Yn, n))
@@ -96,14 +105,15 @@ def test_factor_update_matches_eigh(shape, R):
         np.testing.assert_allclose(host(prev, want.shape), want, atol=1e-8, rtol=0)
 
 
-@pytest.mark.parametrize("shape,R", [((41, 33, 27), 4), ((90, 84, 70), 20)])
+@pytest.mark.parametrize("shape,R", [((41, 33, 27), 4), ((90, 84, 70), 20), ((14, 12, 11, 10), 3),
+                                     ((9, 8, 7, 8, 6), 3)])
 def test_hosvd_matches_oracle(shape, R):
     """HOSVD from random starting bases: factors (largest-magnitude entry positive) and
     core against the oracle's eigh-based HOSVD."""
     r = TRun(shape, R, seed=5)
-    A_want, G_want = ot.hosvd(r.prob.X, (R, R, R))
+    A_want, G_want = ot.hosvd(r.prob.X, r.ranks())
     V0 = [to_dev(v) for v in tensorgen.subspace_start(shape, R, seed=6)]
-    r.upload([np.zeros_like(a) for a in A_want], np.zeros((R, R, R)))
+    r.upload([np.zeros_like(a) for a in A_want], r.zero_core())
     info = pk.tucker_hosvd(r.plan, r.ws, r.X, V0, r.A, r.G)
     assert all(i[1] == 1 and i[2] == 0 for i in info), info
     for n, (got, want) in enumerate(zip(r.factors(), A_want)):
@@ -111,11 +121,12 @@ def test_hosvd_matches_oracle(shape, R):
     assert_rel(r.core(), G_want, 1e-8, "core")
 
 
-@pytest.mark.parametrize("shape,R", [((37, 29, 23), 5), ((96, 80, 72), 24)])
+@pytest.mark.parametrize("shape,R", [((37, 29, 23), 5), ((96, 80, 72), 24), ((14, 12, 11, 10), 3),
+                                     ((9, 8, 7, 8, 6), 2)])
 def test_als_sweeps_match_oracle(shape, R):
     """Six HOOI sweeps from the oracle's HOSVD: factors, core and every record field."""
     r = TRun(shape, R, seed=7, eta=0.3)
-    A0, G0 = ot.hosvd(r.prob.X, (R, R, R))
+    A0, G0 = ot.hosvd(r.prob.X, r.ranks())
     r.upload(A0, G0)
     A_w, G_w, recs_w = ot.tucker_als(r.prob.X, A0, G0, 6)
     for k in range(6):
@@ -132,19 +143,19 @@ def test_als_sweeps_match_oracle(shape, R):
     assert_rel(r.core(), G_w, 1e-8, "core")
 
 
-def test_pp_operators_and_rhs_match_oracle():
+@pytest.mark.parametrize("shape,R", [((60, 52, 47), 8), ((14, 12, 11, 10), 3), ((9, 8, 7, 8, 6), 2)])
+def test_pp_operators_and_rhs_match_oracle(shape, R):
     """Build at the HOSVD factors, one PP-init sweep (which sets dA), then the
     first-order TTMc of every mode against the oracle's from the same dA."""
-    shape, R = (60, 52, 47), 8
     r = TRun(shape, R, seed=9, eta=0.2)
-    A0, G0 = ot.hosvd(r.prob.X, (R, R, R))
+    A0, G0 = ot.hosvd(r.prob.X, r.ranks())
     A1, G1, _ = ot.tucker_als(r.prob.X, A0, G0, 1)
     r.upload(A1, G1)
     pk.tucker_pp_build(r.plan, r.ws, r.X, r.A)
     st = ot.build_operators(r.prob.X, A1)
     # zero perturbation: the approximated TTMc is the exact one at A_p
-    for n in range(3):
-        Y = to_dev(np.zeros((shape[n], R, R)))
+    for n in range(r.N):
+        Y = to_dev(r.zero_y(n))
         pk.tucker_pp_rhs(r.plan, r.ws, n, Y)
         want = lib_layout(ot.pp_rhs(st, n), n)
         assert_rel(host(Y, want.shape), want, 1e-12, f"Y_p^({n})")
@@ -156,8 +167,8 @@ def test_pp_operators_and_rhs_match_oracle():
     # the oracle's dA and the library's agree to the factor tolerance; compare the rhs
     # with the oracle evaluated at the library's dA
     st.dA = [got - ap for got, ap in zip(r.factors(), A1)]
-    for n in range(3):
-        Y = to_dev(np.zeros((shape[n], R, R)))
+    for n in range(r.N):
+        Y = to_dev(r.zero_y(n))
         pk.tucker_pp_rhs(r.plan, r.ws, n, Y)
         want = lib_layout(ot.pp_rhs(st, n), n)
         assert_rel(host(Y, want.shape), want, 1e-11, f"Y~^({n})")
@@ -165,13 +176,14 @@ def test_pp_operators_and_rhs_match_oracle():
         np.testing.assert_allclose(got, want, atol=1e-8, rtol=0, err_msg=f"A^({n})")
 
 
-@pytest.mark.parametrize("shape,R,sweeps", [((48, 44, 40), 6, 14), ((120, 110, 100), 12, 12)])
+@pytest.mark.parametrize("shape,R,sweeps", [((48, 44, 40), 6, 14), ((120, 110, 100), 12, 12),
+                                            ((18, 16, 15, 14), 3, 12), ((9, 8, 9, 8, 9), 2, 12)])
 def test_pp_tucker_run_matches_oracle(shape, R, sweeps):
     """Algorithm 4 with eps = 0.3 (the paper's Tucker setting): the library's own
     decisions give the oracle's sweep-kind sequence, and the replayed path ends at the
     oracle's factors and core; every record's fit within 1e-10."""
     r = TRun(shape, R, seed=11, eta=0.05)
-    A0, G0 = ot.hosvd(r.prob.X, (R, R, R))
+    A0, G0 = ot.hosvd(r.prob.X, r.ranks())
     A_w, G_w, recs_w = ot.pp_tucker_als(r.prob.X, A0, G0, eps=0.3, sweeps=sweeps)
     kinds_w = [w.kind for w in recs_w]
     assert "pp_approx" in kinds_w
@@ -194,7 +206,7 @@ def test_pp_tucker_run_matches_oracle(shape, R, sweeps):
 def test_eps_zero_is_hooi():
     shape, R = (40, 38, 36), 5
     r = TRun(shape, R, seed=13, eta=0.1)
-    A0, G0 = ot.hosvd(r.prob.X, (R, R, R))
+    A0, G0 = ot.hosvd(r.prob.X, r.ranks())
     A_w, G_w, _ = ot.tucker_als(r.prob.X, A0, G0, 5)
     r.upload(A0, G0)
     recs = pk.tucker_run(r.plan, r.ws, r.X, r.A, r.G, eps=0.0, sweeps=5)
@@ -206,7 +218,7 @@ def test_eps_zero_is_hooi():
 def test_pp_sweep_needs_a_build():
     shape, R = (20, 18, 16), 3
     r = TRun(shape, R, seed=15)
-    A0, G0 = ot.hosvd(r.prob.X, (R, R, R))
+    A0, G0 = ot.hosvd(r.prob.X, r.ranks())
     r.upload(A0, G0)
     with pytest.raises(pk.PPALSError) as e:
         pk.tucker_pp_sweep(r.plan, r.ws, r.A, r.G, r.normX2)
@@ -221,7 +233,7 @@ def test_pp_sweeps_through_every_solver_path_match_oracle():
     unchecked again.  Every sweep's factors and fit against the oracle's."""
     shape, R = (60, 52, 47), 8
     r = TRun(shape, R, seed=17, eta=0.2)
-    A0, G0 = ot.hosvd(r.prob.X, (R, R, R))
+    A0, G0 = ot.hosvd(r.prob.X, r.ranks())
     A1, G1, _ = ot.tucker_als(r.prob.X, A0, G0, 2)
     r.upload(A1, G1)
     pk.tucker_pp_build(r.plan, r.ws, r.X, r.A)
