@@ -577,6 +577,48 @@ def tucker_leg(pp, torch, dev, tensorgen, s=800, R=40, eta=0.1, eps=0.3, sweeps=
     return out
 
 
+def tucker_sweeps_leg(pp, torch, dev, tensorgen, shape, R, eta=0.1, n_approx=6):
+    """Per-sweep times of HOOI, PP-initialisation and PP-approximated Tucker sweeps on an
+    order-N FP64 planted Tucker tensor (device-generated), kinds forced from the HOSVD
+    start: three HOOI sweeps, a PP initialisation, n_approx PP sweeps (the paper's
+    per-sweep comparison, Section 5.1)."""
+    t0 = time.perf_counter()
+    X, _, _ = tensorgen.make_tucker_problem_device(shape, (R,) * len(shape), 0, eta=eta, device=dev)
+    X = X.reshape(-1)
+    gen_s = time.perf_counter() - t0
+    plan = pp.TuckerPlan(shape, R)
+    ws = plan.workspace(dev)
+    V0 = [torch.from_numpy(v).to(dev) for v in tensorgen.subspace_start(shape, R, seed=1)]
+    A = [torch.empty(n * R, dtype=torch.float64, device=dev) for n in shape]
+    G = torch.empty(R ** len(shape), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pp.tucker_hosvd(plan, ws, X, V0, A, G)
+    hosvd_ms = (time.perf_counter() - t0) * 1e3
+    kinds = ["als"] * 3 + ["pp_init"] + ["pp_approx"] * n_approx
+    recs = pp.tucker_run(plan, ws, X, A, G, eps=0.3, sweeps=len(kinds), replay=kinds)
+    per = {}
+    for k in ("als", "pp_init", "pp_approx"):
+        t = [r["ms"] for i, r in enumerate(recs) if r["kind"] == k and i > 0]
+        per[k] = float(np.mean(t))
+    out = {"shape": list(shape), "rank": R, "ms": per, "hosvd_ms": hosvd_ms,
+           "pp_approx_speedup_vs_hooi_sweep": per["als"] / per["pp_approx"],
+           "pp_init_over_hooi_sweep": per["pp_init"] / per["als"],
+           "iterations": {k: [r["iters"] for r in recs if r["kind"] == k][-1]
+                          for k in ("als", "pp_approx")},
+           "workspace_GB": plan.workspace_bytes / 1e9, "generation_s": gen_s}
+    log(f"Tucker sweep kinds {shape} R {R}: HOOI {per['als']:.2f} ms, PP-init {per['pp_init']:.2f} ms, "
+        f"PP-approx {per['pp_approx']:.3f} ms ({out['pp_approx_speedup_vs_hooi_sweep']:.1f}x); "
+        f"HOSVD {hosvd_ms:.0f} ms")
+    del X, ws, plan
+    torch.cuda.empty_cache()
+    return out
+
+
+# the paper's order-varying Tucker comparison: s = 1200^(3/N), R = 5
+PAPER_TUCKER_CONFIGS = (((1200,) * 3, 5), ((205,) * 4, 5), ((70,) * 5, 5), ((35,) * 6, 5))
+
+
 def build_leg(pp, torch, dev, tensorgen, shape=(160, 160, 160, 160), R=64, tier="f32", reps=3):
     """PP operator build of Section 3.2.3 on one configuration, with the dimension tree and
     with the direct build (every operator from X and the Khatri-Rao product of the other
@@ -828,7 +870,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dt", action="store_true")
     ap.add_argument("--workload", default="pp",
-                    choices=["pp", "batch", "ablation", "tucker", "build", "sweeps"],
+                    choices=["pp", "batch", "ablation", "tucker", "build", "sweeps", "tucker_sweeps"],
                     help="pp: the 800^3 decomposition (default); batch: 512 independent problems; "
                          "ablation: PP with and without the second-order term against DT-ALS")
     ap.add_argument("--abl-size", type=int, default=64)
@@ -871,6 +913,10 @@ def main():
                for tier in ("f64", "f32") for shape, R in PAPER_SWEEP_CONFIGS]
         res += [sweep_kinds_leg(pp, torch, dev, tensorgen, shape, R, "f64", pp_build="tree")
                 for shape, R in PAPER_SWEEP_CONFIGS[3:]]
+        print(json.dumps(res), flush=True)
+        return
+    if args.workload == "tucker_sweeps":
+        res = [tucker_sweeps_leg(pp, torch, dev, tensorgen, shape, R) for shape, R in PAPER_TUCKER_CONFIGS]
         print(json.dumps(res), flush=True)
         return
     if args.workload == "build":
@@ -1074,7 +1120,7 @@ def main():
     # 64^3 ALS configuration and the first-level contractions of the 160^4 configuration
     extras = (not args.no_extras and args.tier == "f32" and shape == (800, 800, 800)
               and R == 50 and not args.device_gen)
-    f64 = c1 = c3 = batch = tucker = build = sweep_cfgs = None
+    f64 = c1 = c3 = batch = tucker = build = sweep_cfgs = tucker_orders = None
     A_f64_replay = c1prob = None
     if extras:
         del ws
@@ -1092,6 +1138,8 @@ def main():
         build = build_leg(pp, torch, dev, tensorgen, (160,) * 4, 64, "f32")
         sweep_cfgs = [sweep_kinds_leg(pp, torch, dev, tensorgen, shape, R, "f64")
                       for shape, R in PAPER_SWEEP_CONFIGS]
+        tucker_orders = [tucker_sweeps_leg(pp, torch, dev, tensorgen, shp, r)
+                         for shp, r in PAPER_TUCKER_CONFIGS]
 
     cpu = None
     vs_oracle = None
@@ -1181,6 +1229,7 @@ def main():
         "f1_tucker": tucker,
         "f2_direct_build": build,
         "paper_sweep_configs_f64": sweep_cfgs,
+        "paper_tucker_configs_f64": tucker_orders,
         "paper_reference": PAPER_NUMBERS,
         "kernels": kernels,
     }

@@ -224,3 +224,28 @@ def subspace_start(shape, rank, seed):
     i.i.d. N(0,1) entries per mode (stream 2)."""
     _, _, g = streams(seed)
     return [np.ascontiguousarray(g.standard_normal((s, rank))) for s in shape]
+
+
+def make_tucker_problem_device(shape, ranks, seed, eta=1e-3, device="cuda"):
+    """make_tucker_problem with the dense tensor assembled on the GPU (FP64): the planted
+    factors and core come from the same numpy stream; the noise is drawn by torch's device
+    generator seeded from the noise stream.  Returns (X on the device, planted, core)."""
+    import torch
+    g_fac, g_noise, _ = streams(seed)
+    planted = []
+    for s, r in zip(shape, ranks):
+        q, _ = np.linalg.qr(g_fac.standard_normal((s, r)))
+        planted.append(np.ascontiguousarray(q))
+    core = g_fac.standard_normal(tuple(ranks))
+    dev = torch.device(device)
+    T = torch.from_numpy(core).to(dev)
+    for n, a in enumerate(planted):
+        T = torch.movedim(torch.tensordot(torch.from_numpy(a).to(dev), T, dims=([1], [n])), 0, n)
+    T = T.contiguous()
+    if eta > 0.0:
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(int(g_noise.integers(0, 2**62)))
+        E = torch.randn(tuple(shape), generator=gen, dtype=torch.float64, device=dev)
+        T.add_(E, alpha=float(eta * torch.linalg.vector_norm(T) / torch.linalg.vector_norm(E)))
+        del E
+    return T, planted, core
