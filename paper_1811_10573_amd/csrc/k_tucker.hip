@@ -576,4 +576,72 @@ hipError_t launch_core_stats(const double* Gn, const double* Go, int64_t n, doub
   return hipGetLastError();
 }
 
+// k_core_stats on (U, Ap) that also stores A = U and dA = U - Ap (one workgroup).  A may
+// alias U.
+__global__ __launch_bounds__(1024) void k_mode_end(const double* U, const double* __restrict__ Ap,
+                                                   double* A, double* __restrict__ dA, int64_t n,
+                                                   double* out) {
+  __shared__ double r0[16], r1[16];
+  double a = 0.0, b = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 2048) {
+    const double g0 = U[i], d0 = g0 - Ap[i];
+    double g1 = 0.0, d1 = 0.0;
+    const bool two = i + 1024 < n;
+    if (two) {
+      g1 = U[i + 1024];
+      d1 = g1 - Ap[i + 1024];
+    }
+    a = fma(g0, g0, fma(g1, g1, a));
+    b = fma(d0, d0, fma(d1, d1, b));
+    dA[i] = d0;
+    if (A) A[i] = g0;
+    if (two) {
+      dA[i + 1024] = d1;
+      if (A) A[i + 1024] = g1;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o);
+    b += __shfl_xor(b, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    r0[threadIdx.x >> 6] = a;
+    r1[threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sa = 0.0, sb = 0.0;
+    for (int w = 0; w < 16; ++w) {
+      sa += r0[w];
+      sb += r1[w];
+    }
+    out[0] = sa;
+    out[1] = sb;
+  }
+}
+
+hipError_t launch_mode_end(const double* U, const double* Ap, double* A, double* dA, int64_t n,
+                           double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_mode_end, dim3(1), dim3(1024), 0, s, U, Ap, A, dA, n, out);
+  return hipGetLastError();
+}
+
+__global__ void k_copy2(double* __restrict__ o1, double* __restrict__ o2,
+                        const double* __restrict__ in, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = in[i];
+    o1[i] = v;
+    o2[i] = v;
+  }
+}
+
+hipError_t launch_copy2(double* out1, double* out2, const double* in, int64_t n, hipStream_t s) {
+  int64_t blocks = (n + 255) / 256;
+  blocks = blocks < 1 ? 1 : (blocks > 4096 ? 4096 : blocks);
+  hipLaunchKernelGGL(k_copy2, dim3((unsigned)blocks), dim3(256), 0, s, out1, out2, in, n);
+  return hipGetLastError();
+}
+
 }  // namespace ppk

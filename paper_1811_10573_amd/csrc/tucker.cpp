@@ -80,6 +80,7 @@ struct tucker_plan {
   size_t o_op[TMAX][TMAX];         // Y_p^(i,n), i < n
   size_t o_Yp[TMAX], o_Y, o_term[TMAX], o_Gn;
   size_t o_Ap[TMAX], o_dA[TMAX], o_Astart[TMAX];
+  size_t o_dAprep[TMAX];           // dA^(i) in the first-level operand order (dA_geom)
   size_t o_V, o_C, o_Aold, o_U, o_Z, o_B, o_H, o_P, o_T, o_lam, o_info, o_stats;
   size_t o_prep, o_part, o_gpart, o_rpart;
   size_t slot = 0;  // bytes between the basis slots V, C, A_prev
@@ -157,6 +158,26 @@ ppals_status ttm_geom(const TCtx& c, const double* T, const Level1Geom& g, const
 
 ppals_status ttm(const TCtx& c, const double* T, Contr k, const double* F, double* out) {
   return ttm_geom(c, T, l1_geom(k.P, k.K, k.Q, c.p->R, DT_F64), F, out);
+}
+
+// Operand order of dA^(i) kept between its update and the correction terms that read it:
+// the order of a contraction over s_i whose trailing extent is not 1.  The operand order
+// depends only on K, R and whether that extent is 1.
+Level1Geom dA_geom(const tucker_plan* p, int i) { return l1_geom(1, p->s[i], 2, p->R, DT_F64); }
+bool same_operand_order(const Level1Geom& a, const Level1Geom& b) {
+  return a.K == b.K && a.Kpad == b.Kpad && a.nslices == b.nslices && a.NB == b.NB &&
+         a.kc_mode == b.kc_mode;
+}
+ppals_status prep_dA(const TCtx& c, int i) {
+  if (c.col) return PPALS_OK;
+  KrpDesc krp;
+  memset(&krp, 0, sizeof(krp));
+  krp.nf = 1;
+  krp.R = c.p->R;
+  krp.A[0] = c.d(c.p->o_dA[i]);
+  krp.dim[0] = c.p->s[i];
+  THIPCHK(launch_prep_operand(krp, dA_geom(c.p, i), DT_F64, c.ws + c.p->o_dAprep[i], c.s));
+  return PPALS_OK;
 }
 
 // Contract the modes ms (increasing) of src (layout L) with the factors F[m]: the result
@@ -461,8 +482,18 @@ ppals_status pp_rhs_impl(const TCtx& c, int n, double* Y) {
   for (int i = 0; i < N; ++i) {
     if (i == n || p->dA_zero[i]) continue;
     double* T = c.d(p->o_term[a.nterms]);
-    TCHK(ttm(c, c.d(p->o_op[std::min(i, n)][std::max(i, n)]), op_contr(p, i, n),
-             c.d(p->o_dA[i]), T));
+    const Contr k = op_contr(p, i, n);
+    const Level1Geom g = l1_geom(k.P, k.K, k.Q, p->R, DT_F64);
+    const double* op = c.d(p->o_op[std::min(i, n)][std::max(i, n)]);
+    if (same_operand_order(g, dA_geom(p, i))) {
+      if (c.col) {
+        c.col->part = std::max(c.col->part, part_elems(g));
+      } else {
+        THIPCHK(launch_level1(op, DT_F64, c.ws + p->o_dAprep[i], g, T, c.ws + p->o_part, c.s));
+      }
+    } else {
+      TCHK(ttm_geom(c, op, g, c.d(p->o_dA[i]), T));
+    }
     a.term[a.nterms] = T;
     a.pos[a.nterms] = rank_pos(i, n);
     ++a.nterms;
@@ -632,6 +663,7 @@ ppals_status tucker_plan_create(int32_t order, const int64_t* dims, int32_t rank
   for (int n = 0; n < N; ++n) p->o_Ap[n] = take(dims[n] * R);
   for (int n = 0; n < N; ++n) p->o_dA[n] = take(dims[n] * R);
   for (int n = 0; n < N; ++n) p->o_Astart[n] = take(dims[n] * R);
+  for (int n = 0; n < N; ++n) p->o_dAprep[n] = take(prep_elems(dA_geom(p, n)));
   // basis slots V, C, A_prev at equal spacing (one batched projection launch)
   p->slot = al256((size_t)smax * R * sizeof(double));
   p->o_V = take(smax * R);
@@ -790,15 +822,13 @@ ppals_status tucker_pp_sweep(tucker_plan* plan, void* ws, double* const* A, doub
     }
     for (int n = 0; n < N; ++n) {
       TCHK(pp_rhs_impl(c, n, Y));
-      THIPCHK(launch_copy(Aold, A[n], plan->s[n] * R, stream));
-      THIPCHK(launch_copy(c.d(plan->o_V), Aold, plan->s[n] * R, stream));
+      THIPCHK(launch_copy2(Aold, c.d(plan->o_V), A[n], plan->s[n] * R, stream));
       TCHK(subspace_step(c, n, Y, nullptr, true, dinfo + n));
-      THIPCHK(launch_copy(A[n], c.d(plan->o_U), plan->s[n] * R, stream));
-      double* dA = c.d(plan->o_dA[n]);
-      const double* Ap = c.d(plan->o_Ap[n]);
-      THIPCHK(launch_sub(dA, A[n], Ap, plan->s[n] * R, stream));
+      // A = U, dA = A - A_p, the norms; dA in operand order for the later modes' terms
+      THIPCHK(launch_mode_end(c.d(plan->o_U), c.d(plan->o_Ap[n]), A[n], c.d(plan->o_dA[n]),
+                              plan->s[n] * R, stats + 2 * n, stream));
+      TCHK(prep_dA(c, n));
       plan->dA_zero[n] = false;
-      THIPCHK(launch_core_stats(A[n], Ap, plan->s[n] * R, stats + 2 * n, stream));
     }
     TCHK(finish_core(c, Y, A[N - 1], G, false));
     IterInfo hi[TMAX];
@@ -820,6 +850,7 @@ ppals_status tucker_pp_sweep(tucker_plan* plan, void* ws, double* const* A, doub
       for (int n = n0; n < N; ++n) {
         THIPCHK(launch_copy(A[n], c.d(plan->o_Astart[n]), plan->s[n] * R, stream));
         THIPCHK(launch_sub(c.d(plan->o_dA[n]), A[n], c.d(plan->o_Ap[n]), plan->s[n] * R, stream));
+        TCHK(prep_dA(c, n));
         plan->dA_zero[n] = zero_start[n];
       }
     }
@@ -834,11 +865,10 @@ ppals_status tucker_pp_sweep(tucker_plan* plan, void* ws, double* const* A, doub
       rec->iters[n] = info[0];
       rec->converged[n] = info[1];
       rec->rr_status[n] = info[2];
-      double* dA = c.d(plan->o_dA[n]);
-      const double* Ap = c.d(plan->o_Ap[n]);
-      THIPCHK(launch_sub(dA, A[n], Ap, plan->s[n] * R, stream));
+      THIPCHK(launch_mode_end(A[n], c.d(plan->o_Ap[n]), nullptr, c.d(plan->o_dA[n]),
+                              plan->s[n] * R, stats + 2 * n, stream));
+      TCHK(prep_dA(c, n));
       plan->dA_zero[n] = false;
-      THIPCHK(launch_core_stats(A[n], Ap, plan->s[n] * R, stats + 2 * n, stream));
     }
     TCHK(finish_core(c, Y, A[N - 1], G));
     // back to the unsynchronised pass once a sweep needs a single iteration everywhere

@@ -54,6 +54,12 @@ struct TuckerCombine {
 hipError_t launch_tucker_combine(const TuckerCombine& a, hipStream_t s);
 hipError_t launch_core_stats(const double* Gn, const double* Go, int64_t n, double* out,
                              hipStream_t s);
+// End of a factor update: A = U (skipped when A is null), dA = U - Ap, and out[0], out[1] =
+// ||U||^2, ||U - Ap||^2 summed in the order of launch_core_stats(U, Ap).
+hipError_t launch_mode_end(const double* U, const double* Ap, double* A, double* dA, int64_t n,
+                           double* out, hipStream_t s);
+// out1 = out2 = in (n doubles)
+hipError_t launch_copy2(double* out1, double* out2, const double* in, int64_t n, hipStream_t s);
 
 }  // namespace ppk
 
