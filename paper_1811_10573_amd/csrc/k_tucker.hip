@@ -165,6 +165,108 @@ __device__ __forceinline__ double rr_block_max(double v, double* red) {
 // Below this max |B - I| the inverse square root series replaces the Cholesky factor.
 constexpr double kRRSeriesTol = 1e-6;
 
+// dst[e] = src[e] for e < n into LDS, eight loads in flight per thread before the stores.
+__device__ __forceinline__ void stage_rows(double* dst, const double* __restrict__ src, int n) {
+  for (int e0 = threadIdx.x; e0 < n; e0 += 8 * 256) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = e0 + 256 * q;
+      v[q] = e < n ? src[e] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = e0 + 256 * q;
+      if (e < n) dst[e] = v[q];
+    }
+  }
+}
+
+// o1 = X^T Y1 and (Y2 non-null) o2 = X^T Y2 for rows x R matrices, into LDS arrays of row
+// stride RRS: rows staged in chunks through Xs (and Ys, Y2s: 64 x RRS doubles each, rows
+// packed at stride R).  With G = rr_project_groups(R) > 1, thread t sums entry t % R^2 over
+// the rows x = t / R^2 (mod G) in increasing order and the G partial sums are added in
+// group order (through red, 256 doubles); with G = 1 a thread sums up to 16 entries.
+__device__ __forceinline__ void rr_project(const double* X, const double* Y1, const double* Y2,
+                                           int64_t rows, int R, double* Xs, double* Ys,
+                                           double* Y2s, double* red, double* o1, double* o2) {
+  constexpr int NE = 16;  // entries per thread (R^2 <= 4096)
+  const int tid = threadIdx.x;
+  const int RR = R * R;
+  int G = 1;
+  while (2 * G * RR <= 256) G *= 2;
+  const int grp = G > 1 ? tid / RR : 0;
+  const int nent = G > 1 ? (tid < G * RR ? 1 : 0) : NE;
+  const int64_t CR = (64 * RRS) / R;  // rows per chunk
+  double acc1[NE], acc2[NE];
+#pragma unroll
+  for (int u = 0; u < NE; ++u) acc1[u] = acc2[u] = 0.0;
+  const bool same = Y1 == X;
+  const double* Y1s = same ? Xs : Ys;
+  for (int64_t x0 = 0; x0 < rows; x0 += CR) {
+    const int nr = (int)(rows - x0 < CR ? rows - x0 : CR);
+    const int ne = nr * R;
+    stage_rows(Xs, X + x0 * R, ne);
+    if (!same) stage_rows(Ys, Y1 + x0 * R, ne);
+    if (Y2) stage_rows(Y2s, Y2 + x0 * R, ne);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int e = G > 1 ? tid - grp * RR : tid + 256 * u;
+      if (u < nent && e < RR) {
+        const int i = e / R, k = e - i * R;
+        double s1 = acc1[u], s2 = acc2[u];
+        int x = grp;
+        for (; x + 3 * G < nr; x += 4 * G) {
+          double xv[4], y1[4], y2[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            xv[v] = Xs[(x + v * G) * R + i];
+            y1[v] = Y1s[(x + v * G) * R + k];
+            y2[v] = Y2 ? Y2s[(x + v * G) * R + k] : 0.0;
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            s1 = fma(xv[v], y1[v], s1);
+            if (Y2) s2 = fma(xv[v], y2[v], s2);
+          }
+        }
+        for (; x < nr; x += G) {
+          const double xv = Xs[x * R + i];
+          s1 = fma(xv, Y1s[x * R + k], s1);
+          if (Y2) s2 = fma(xv, Y2s[x * R + k], s2);
+        }
+        acc1[u] = s1;
+        acc2[u] = s2;
+      }
+    }
+    __syncthreads();
+  }
+  if (G > 1) {
+    for (int pass = 0; pass < (Y2 ? 2 : 1); ++pass) {
+      if (tid < G * RR) red[tid] = pass ? acc2[0] : acc1[0];
+      __syncthreads();
+      if (tid < RR) {
+        double s = 0.0;
+        for (int q = 0; q < G; ++q) s += red[q * RR + tid];
+        const int i = tid / R, k = tid - i * R;
+        (pass ? o2 : o1)[i * RRS + k] = s;
+      }
+      __syncthreads();
+    }
+    return;
+  }
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int e = tid + 256 * u;
+    if (e < RR) {
+      const int i = e / R, k = e - i * R;
+      o1[i * RRS + k] = acc1[u];
+      if (Y2) o2[i * RRS + k] = acc2[u];
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs a) {
   __shared__ double L[64 * RRS];   // B, trailing updates; later scratch (Z, T)
   __shared__ double Lc[64 * RRS];  // Cholesky factor; later the Jacobi eigenvectors
@@ -178,14 +280,20 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs a) {
   const int tid = threadIdx.x;
   const int R = a.R;
   const int RP = R + (R & 1);  // even, for the round-robin pairing
+  if (a.V) {  // B into L, H into H, staged through Lc (V) and Li (C)
+    rr_project(a.V, a.V, a.C, a.rows, R, Lc, nullptr, Li, Li + 64 * RRS - 256, L, H);
+    __syncthreads();
+  }
   for (int e = tid; e < 64 * RRS; e += 256) {
     Lc[e] = 0.0;
     Li[e] = 0.0;
   }
-  for (int e = tid; e < R * R; e += 256) {
-    const int i = e / R, k = e - i * R;
-    L[i * RRS + k] = a.B[e];
-    H[i * RRS + k] = a.H[e];
+  if (!a.V) {
+    for (int e = tid; e < R * R; e += 256) {
+      const int i = e / R, k = e - i * R;
+      L[i * RRS + k] = a.B[e];
+      H[i * RRS + k] = a.H[e];
+    }
   }
   if (tid == 0) bad = 0;
   __syncthreads();
@@ -361,6 +469,12 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs a) {
   if (tid < R) lam[tid] = H[tid * RRS + tid];
   rr_product(L, Li, 1, RRS, Q, RRS, 1, R);
   __syncthreads();
+  // in-kernel projections: P = V^T Ap into H (free now), staged through Li and Lc
+  const bool p_lds = a.V && a.Ap;
+  if (p_lds) {
+    rr_project(a.V, a.Ap, nullptr, a.rows, R, Li, Lc, nullptr, Lc + 64 * RRS - 256, H, nullptr);
+    __syncthreads();
+  }
   // decreasing order (ties by index), sign against A_prev, written to sorted position
   if (tid < R) {
     const int j = tid;
@@ -368,9 +482,10 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs a) {
     int pos = 0;
     for (int k = 0; k < R; ++k) pos += (lam[k] > v) || (lam[k] == v && k < j);
     double sgn = 1.0;
-    if (a.P) {
+    if (p_lds || (!a.V && a.P)) {
       double d = 0.0;
-      for (int m = 0; m < R; ++m) d = fma(L[m * RRS + j], a.P[m * R + pos], d);  // the column it replaces
+      for (int m = 0; m < R; ++m)  // the column it replaces
+        d = fma(L[m * RRS + j], p_lds ? H[m * RRS + pos] : a.P[m * R + pos], d);
       sgn = d < 0.0 ? -1.0 : 1.0;
     }
     for (int i = 0; i < R; ++i) a.T[i * R + pos] = sgn * L[i * RRS + j];
@@ -625,6 +740,127 @@ hipError_t launch_mode_end(const double* U, const double* Ap, double* A, double*
                            double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_mode_end, dim3(1), dim3(1024), 0, s, U, Ap, A, dA, n, out);
   return hipGetLastError();
+}
+
+// C = Y (Y^T V), chunk of Y's columns [j0, j0 + wc) per workgroup.  Z = Y_chunk^T V: each
+// entry (j, r) summed over the rows by G interleaved groups of threads (as in rr_project),
+// then out[x][r] = sum_j Y[x][j0 + j] Z[j][r] in increasing j.
+constexpr int WA_NE = 16;
+constexpr int WA_LDS = 18000;  // doubles of dynamic LDS at most (144 KB)
+constexpr int64_t kWApplyChunks = 32;
+
+int w_apply_width(int64_t s, int64_t m, int R) {
+  if (R < 1 || R > 64 || s < 1 || m < 1) return 0;
+  const int64_t free_ = WA_LDS - 256 - s * R;
+  if (free_ <= 0) return 0;
+  int64_t w = free_ / (s + R);
+  w = std::min<int64_t>(w, 4096 / R);  // Z entries: at most 16 per thread
+  w = std::min<int64_t>(w, 256);
+  // about kWApplyChunks workgroups: a chunk's sums are short and run side by side
+  w = std::min<int64_t>(w, (m + kWApplyChunks - 1) / kWApplyChunks);
+  return w >= 1 ? (int)w : 0;
+}
+
+__global__ __launch_bounds__(256) void k_w_apply(const double* __restrict__ Y,
+                                                 const double* __restrict__ V, int s, int64_t m,
+                                                 int R, int w, double* __restrict__ out) {
+  extern __shared__ double sm[];
+  const int tid = threadIdx.x;
+  const int64_t j0 = (int64_t)blockIdx.x * w;
+  const int wc = (int)(m - j0 < w ? m - j0 : w);
+  double* Ys = sm;           // s x wc
+  double* Vs = Ys + s * w;   // s x R
+  double* Zs = Vs + s * R;   // wc x R
+  double* red = Zs + w * R;
+  const int ny = s * wc;  // < 2^15 (LDS)
+  for (int e0 = tid; e0 < ny; e0 += 8 * 256) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = e0 + 256 * q;
+      const int x = e / wc;
+      v[q] = e < ny ? Y[x * m + j0 + (e - x * wc)] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = e0 + 256 * q;
+      if (e < ny) Ys[e] = v[q];
+    }
+  }
+  stage_rows(Vs, V, s * R);
+  __syncthreads();
+  const int ZE = wc * R;
+  int G = 1;
+  while (2 * G * ZE <= 256) G *= 2;
+  const int grp = G > 1 ? tid / ZE : 0;
+  const int nent = G > 1 ? (tid < G * ZE ? 1 : 0) : (ZE + 255) / 256;
+  double acc[WA_NE];
+#pragma unroll
+  for (int u = 0; u < WA_NE; ++u) acc[u] = 0.0;
+#pragma unroll
+  for (int u = 0; u < WA_NE; ++u) {
+    const int e = G > 1 ? tid - grp * ZE : tid + 256 * u;
+    if (u < nent && e < ZE) {
+      const int j = e / R, r = e - j * R;
+      double sum = 0.0;
+      int x = grp;
+      for (; x + 3 * G < s; x += 4 * G) {
+        double yv[4], vv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          yv[q] = Ys[(x + q * G) * wc + j];
+          vv[q] = Vs[(x + q * G) * R + r];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sum = fma(yv[q], vv[q], sum);
+      }
+      for (; x < s; x += G) sum = fma(Ys[x * wc + j], Vs[x * R + r], sum);
+      acc[u] = sum;
+    }
+  }
+  if (G > 1) {
+    if (tid < G * ZE) red[tid] = acc[0];
+    __syncthreads();
+    if (tid < ZE) {
+      double z = 0.0;
+      for (int q = 0; q < G; ++q) z += red[q * ZE + tid];
+      Zs[tid] = z;
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < WA_NE; ++u) {
+      const int e = tid + 256 * u;
+      if (e < ZE) Zs[e] = acc[u];
+    }
+  }
+  __syncthreads();
+  double* o = out + (int64_t)blockIdx.x * s * R;
+  for (int e = tid; e < s * R; e += 256) {
+    const int x = e / R;
+    const int r = e - x * R;
+    const double* yr = Ys + x * wc;
+    double c = 0.0;
+#pragma unroll 8
+    for (int j = 0; j < wc; ++j) c = fma(yr[j], Zs[j * R + r], c);
+    o[e] = c;
+  }
+}
+
+hipError_t launch_w_apply(const double* Y, const double* V, int64_t s, int64_t m, int R, int w,
+                          double* part, double* C, hipStream_t st) {
+  if (w < 1 || w != w_apply_width(s, m, R)) return hipErrorInvalidValue;
+  const int64_t nchunk = (m + w - 1) / w;
+  const size_t lds = (size_t)(s * w + s * R + (int64_t)w * R + 256) * sizeof(double);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_w_apply),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_w_apply, dim3((unsigned)nchunk), dim3(256), lds, st, Y, V, (int)s, m, R,
+                     w, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_reduce_splits_to(C, 0, part, 0, (int)nchunk, s * R, st);
 }
 
 __global__ void k_copy2(double* __restrict__ o1, double* __restrict__ o2,

@@ -270,6 +270,16 @@ ppals_status apply_w(const TCtx& c, int n, const double* Y, const double* X, con
   const int N = p->N;
   const int64_t sn = p->s[n], RN1 = p->rpow[N - 1];
   if (Y) {
+    const int w = w_apply_width(sn, RN1, p->R);
+    if (w > 0) {  // one pass over the small TTMc: C = Y (Y^T V) chunk by chunk
+      const int64_t nchunk = (RN1 + w - 1) / w;
+      if (c.col) {
+        c.col->part = std::max(c.col->part, (size_t)(nchunk * sn * p->R));
+        return PPALS_OK;
+      }
+      THIPCHK(launch_w_apply(Y, V, sn, RN1, p->R, w, c.d(p->o_part), C, c.s));
+      return PPALS_OK;
+    }
     double* Z = c.d(p->o_Z);
     TCHK(ttm(c, Y, {1, sn, RN1}, V, Z));  // Z = Y^T V   (R^(N-1) x R)
     TCHK(ttm(c, Y, {sn, RN1, 1}, Z, C));  // C = Y Z     (s_n x R)
@@ -305,8 +315,16 @@ ppals_status subspace_step(const TCtx& c, int n, const double* Y, const double* 
   double* C = c.d(p->o_C);
   TCHK(apply_w(c, n, Y, X, V, C));  // C = W V
   if (c.col) return PPALS_OK;
-  TCHK(projections(c, sn, has_prev ? 3 : 2));
   RRArgs rr;
+  memset(&rr, 0, sizeof(rr));
+  if (rr_project_inline(sn, R)) {  // projections inside the Rayleigh-Ritz step
+    rr.V = V;
+    rr.C = C;
+    rr.Ap = has_prev ? c.d(p->o_Aold) : nullptr;
+    rr.rows = sn;
+  } else {
+    TCHK(projections(c, sn, has_prev ? 3 : 2));
+  }
   rr.R = R;
   rr.B = c.d(p->o_B);
   rr.H = c.d(p->o_H);

@@ -1,5 +1,5 @@
-"""GPU parity of the order-3 Tucker path (Tucker-ALS, Algorithm 2; PP-Tucker-ALS,
-Algorithm 4 with the first-order TTMc of Section 3.2.2) against the float64 oracle.
+"""GPU parity of the Tucker path (Tucker-ALS, Algorithm 2; PP-Tucker-ALS, Algorithm 4 with
+the first-order TTMc of Section 3.2.2) against the float64 oracle, at orders 3 to 6.
 
 Layouts: the library stores Y^(n) as s_n x R^(N-1) with x_n first and the rank indices of
 the other modes in increasing mode order (the oracle's ttmc with mode n moved to the
@@ -122,9 +122,12 @@ def test_hosvd_matches_oracle(shape, R):
 
 
 @pytest.mark.parametrize("shape,R", [((37, 29, 23), 5), ((96, 80, 72), 24), ((14, 12, 11, 10), 3),
-                                     ((9, 8, 7, 8, 6), 2)])
+                                     ((9, 8, 7, 8, 6), 2), ((1400, 20, 18), 12)])
 def test_als_sweeps_match_oracle(shape, R):
-    """Six HOOI sweeps from the oracle's HOSVD: factors, core and every record field."""
+    """Six HOOI sweeps from the oracle's HOSVD: factors, core and every record field.
+    W V = Y (Y^T V) runs in one chunked kernel while Y's chunk, V and Y_chunk^T V fit a
+    workgroup's LDS, else as two first-level contractions (mode 0 of 1400 x 20 x 18 at
+    R = 12)."""
     r = TRun(shape, R, seed=7, eta=0.3)
     A0, G0 = ot.hosvd(r.prob.X, r.ranks())
     r.upload(A0, G0)
