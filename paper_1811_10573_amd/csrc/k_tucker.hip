@@ -114,14 +114,16 @@ hipError_t launch_gemm_f64(const GemmArgs& g, hipStream_t s) {
 // formed column by column by quads of lanes, and the three products with L^-1 are
 // dense LDS products with 2 x 2 register blocks.
 // ---------------------------------------------------------------------------
-constexpr int RRS = 65;  // LDS row stride
+// The R x R arrays of the kernels below have row stride RM + 1: 65 for R <= 64, 17 in the
+// small-rank kernel.
 
 // out[a][b] = sum_k X(a, k) Y(k, b) for a, b < R with X(a, k) = Xs[a * xa + k * xk] and
-// Y(k, b) = Ys[k * yk + b * yb]; 2 x 2 outputs per thread.
+// Y(k, b) = Ys[k * yk + b * yb]; 2 x 2 outputs per thread of NT; out has row stride LS.
+template <int LS, int NT>
 __device__ __forceinline__ void rr_product(double* out, const double* Xs, int xa, int xk,
                                            const double* Ys, int yk, int yb, int R) {
   const int Rh = (R + 1) / 2;
-  for (int e = threadIdx.x; e < Rh * Rh; e += blockDim.x) {
+  for (int e = threadIdx.x; e < Rh * Rh; e += NT) {
     const int a0 = 2 * (e / Rh), b0 = 2 * (e % Rh);
     const int a1 = a0 + 1 < R ? a0 + 1 : a0, b1 = b0 + 1 < R ? b0 + 1 : b0;
     double c00 = 0.0, c01 = 0.0, c10 = 0.0, c11 = 0.0;
@@ -133,17 +135,27 @@ __device__ __forceinline__ void rr_product(double* out, const double* Xs, int xa
       c10 = fma(x1, y0, c10);
       c11 = fma(x1, y1, c11);
     }
-    out[a0 * RRS + b0] = c00;
-    if (b1 != b0) out[a0 * RRS + b1] = c01;
-    if (a1 != a0) out[a1 * RRS + b0] = c10;
-    if (a1 != a0 && b1 != b0) out[a1 * RRS + b1] = c11;
+    out[a0 * LS + b0] = c00;
+    if (b1 != b0) out[a0 * LS + b1] = c01;
+    if (a1 != a0) out[a1 * LS + b0] = c10;
+    if (a1 != a0 && b1 != b0) out[a1 * LS + b1] = c11;
   }
 }
 
-// Sum of v over the workgroup (256 threads, four waves); every thread gets the total.
+// Barrier of the NT threads that run the Rayleigh-Ritz algebra: the workgroup (256), or one
+// wave (64), whose LDS operations complete in program order.
+template <int NT>
+__device__ __forceinline__ void rr_sync() {
+  if (NT == 64) __builtin_amdgcn_wave_barrier();
+  else __syncthreads();
+}
+
+// Sum of v over the NT threads (four waves, or one); every thread gets the total.
+template <int NT>
 __device__ __forceinline__ double rr_block_sum(double v, double* red) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if (NT == 64) return v;
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
   const double t = (red[0] + red[1]) + (red[2] + red[3]);
@@ -151,10 +163,12 @@ __device__ __forceinline__ double rr_block_sum(double v, double* red) {
   return t;
 }
 
-// Maximum of v over the workgroup (256 threads); every thread gets it.
+// Maximum of v over the NT threads; every thread gets it.
+template <int NT>
 __device__ __forceinline__ double rr_block_max(double v, double* red) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  if (NT == 64) return v;
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
   const double t = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
@@ -182,14 +196,14 @@ __device__ __forceinline__ void stage_rows(double* dst, const double* __restrict
   }
 }
 
-// o1 = X^T Y1 and (Y2 non-null) o2 = X^T Y2 for rows x R matrices, into LDS arrays of row
-// stride RRS: rows staged in chunks through Xs (and Ys, Y2s: 64 x RRS doubles each, rows
-// packed at stride R).  With G = rr_project_groups(R) > 1, thread t sums entry t % R^2 over
-// the rows x = t / R^2 (mod G) in increasing order and the G partial sums are added in
-// group order (through red, 256 doubles); with G = 1 a thread sums up to 16 entries.
-__device__ __forceinline__ void rr_project(const double* X, const double* Y1, const double* Y2,
-                                           int64_t rows, int R, double* Xs, double* Ys,
-                                           double* Y2s, double* red, double* o1, double* o2) {
+// o1 = X^T Y1 and (Y2 non-null) o2 = X^T Y2 for rows x R matrices held in LDS (row stride
+// R), into LDS arrays of row stride LS.  With G the largest power of two with G R^2 <= 256
+// (at least 1), thread t sums entry t % R^2 over the rows x = t / R^2 (mod G) in increasing
+// order and the G partial sums are added in group order (through red, 256 doubles); with
+// G = 1 a thread sums up to 16 entries.
+template <int LS>
+__device__ __forceinline__ void rr_project(const double* Xs, const double* Y1s, const double* Y2s,
+                                           int rows, int R, double* red, double* o1, double* o2) {
   constexpr int NE = 16;  // entries per thread (R^2 <= 4096)
   const int tid = threadIdx.x;
   const int RR = R * R;
@@ -197,60 +211,48 @@ __device__ __forceinline__ void rr_project(const double* X, const double* Y1, co
   while (2 * G * RR <= 256) G *= 2;
   const int grp = G > 1 ? tid / RR : 0;
   const int nent = G > 1 ? (tid < G * RR ? 1 : 0) : NE;
-  const int64_t CR = (64 * RRS) / R;  // rows per chunk
   double acc1[NE], acc2[NE];
 #pragma unroll
   for (int u = 0; u < NE; ++u) acc1[u] = acc2[u] = 0.0;
-  const bool same = Y1 == X;
-  const double* Y1s = same ? Xs : Ys;
-  for (int64_t x0 = 0; x0 < rows; x0 += CR) {
-    const int nr = (int)(rows - x0 < CR ? rows - x0 : CR);
-    const int ne = nr * R;
-    stage_rows(Xs, X + x0 * R, ne);
-    if (!same) stage_rows(Ys, Y1 + x0 * R, ne);
-    if (Y2) stage_rows(Y2s, Y2 + x0 * R, ne);
-    __syncthreads();
 #pragma unroll
-    for (int u = 0; u < NE; ++u) {
-      const int e = G > 1 ? tid - grp * RR : tid + 256 * u;
-      if (u < nent && e < RR) {
-        const int i = e / R, k = e - i * R;
-        double s1 = acc1[u], s2 = acc2[u];
-        int x = grp;
-        for (; x + 3 * G < nr; x += 4 * G) {
-          double xv[4], y1[4], y2[4];
+  for (int u = 0; u < NE; ++u) {
+    const int e = G > 1 ? tid - grp * RR : tid + 256 * u;
+    if (u < nent && e < RR) {
+      const int i = e / R, k = e - i * R;
+      double s1 = 0.0, s2 = 0.0;
+      int x = grp;
+      for (; x + 3 * G < rows; x += 4 * G) {
+        double xv[4], y1[4], y2[4];
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            xv[v] = Xs[(x + v * G) * R + i];
-            y1[v] = Y1s[(x + v * G) * R + k];
-            y2[v] = Y2 ? Y2s[(x + v * G) * R + k] : 0.0;
-          }
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            s1 = fma(xv[v], y1[v], s1);
-            if (Y2) s2 = fma(xv[v], y2[v], s2);
-          }
+        for (int v = 0; v < 4; ++v) {
+          xv[v] = Xs[(x + v * G) * R + i];
+          y1[v] = Y1s[(x + v * G) * R + k];
+          y2[v] = Y2s ? Y2s[(x + v * G) * R + k] : 0.0;
         }
-        for (; x < nr; x += G) {
-          const double xv = Xs[x * R + i];
-          s1 = fma(xv, Y1s[x * R + k], s1);
-          if (Y2) s2 = fma(xv, Y2s[x * R + k], s2);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          s1 = fma(xv[v], y1[v], s1);
+          if (Y2s) s2 = fma(xv[v], y2[v], s2);
         }
-        acc1[u] = s1;
-        acc2[u] = s2;
       }
+      for (; x < rows; x += G) {
+        const double xv = Xs[x * R + i];
+        s1 = fma(xv, Y1s[x * R + k], s1);
+        if (Y2s) s2 = fma(xv, Y2s[x * R + k], s2);
+      }
+      acc1[u] = s1;
+      acc2[u] = s2;
     }
-    __syncthreads();
   }
   if (G > 1) {
-    for (int pass = 0; pass < (Y2 ? 2 : 1); ++pass) {
+    for (int pass = 0; pass < (Y2s ? 2 : 1); ++pass) {
       if (tid < G * RR) red[tid] = pass ? acc2[0] : acc1[0];
       __syncthreads();
       if (tid < RR) {
         double s = 0.0;
         for (int q = 0; q < G; ++q) s += red[q * RR + tid];
         const int i = tid / R, k = tid - i * R;
-        (pass ? o2 : o1)[i * RRS + k] = s;
+        (pass ? o2 : o1)[i * LS + k] = s;
       }
       __syncthreads();
     }
@@ -261,135 +263,116 @@ __device__ __forceinline__ void rr_project(const double* X, const double* Y1, co
     const int e = tid + 256 * u;
     if (e < RR) {
       const int i = e / R, k = e - i * R;
-      o1[i * RRS + k] = acc1[u];
-      if (Y2) o2[i * RRS + k] = acc2[u];
+      o1[i * LS + k] = acc1[u];
+      if (Y2s) o2[i * LS + k] = acc2[u];
     }
   }
 }
 
-__global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs a) {
-  __shared__ double L[64 * RRS];   // B, trailing updates; later scratch (Z, T)
-  __shared__ double Lc[64 * RRS];  // Cholesky factor; later the Jacobi eigenvectors
-  __shared__ double Li[64 * RRS];  // L^-1 (lower)
-  __shared__ double H[64 * RRS];   // H, then H' (rotated in place)
-  __shared__ double lam[64];
-  __shared__ double cs[32], sn[32];
-  __shared__ int pr[32], qr[32];
-  __shared__ double red[4];
-  __shared__ int bad;
+// The Rayleigh-Ritz algebra on R x R arrays of row stride LS = RM + 1, with B in L, H in H
+// and Lc, Li zero: leaves T = L^-T Q (columns in Jacobi order) in L, the Ritz values in
+// lam and Q in Lc; *bad = 1 when B was not positive definite.  Returns the Jacobi sweeps.
+template <int RM, int NT>
+__device__ __forceinline__ int rr_core(int R, double* L, double* Lc, double* Li, double* H,
+                                       double* lam, double* cs, double* sn, int* pr, int* qr,
+                                       double* red, int* bad) {
+  constexpr int LS = RM + 1;
+  static_assert(NT == 256 || (NT == 64 && RM <= 16), "four waves, or one wave for R <= 16");
   const int tid = threadIdx.x;
-  const int R = a.R;
   const int RP = R + (R & 1);  // even, for the round-robin pairing
-  if (a.V) {  // B into L, H into H, staged through Lc (V) and Li (C)
-    rr_project(a.V, a.V, a.C, a.rows, R, Lc, nullptr, Li, Li + 64 * RRS - 256, L, H);
-    __syncthreads();
-  }
-  for (int e = tid; e < 64 * RRS; e += 256) {
-    Lc[e] = 0.0;
-    Li[e] = 0.0;
-  }
-  if (!a.V) {
-    for (int e = tid; e < R * R; e += 256) {
-      const int i = e / R, k = e - i * R;
-      L[i * RRS + k] = a.B[e];
-      H[i * RRS + k] = a.H[e];
-    }
-  }
-  if (tid == 0) bad = 0;
-  __syncthreads();
   double em = 0.0;
-  for (int e = tid; e < R * R; e += 256) {
+  for (int e = tid; e < R * R; e += NT) {
     const int i = e / R, k = e - i * R;
-    em = fmax(em, fabs(L[i * RRS + k] - (i == k ? 1.0 : 0.0)));
+    em = fmax(em, fabs(L[i * LS + k] - (i == k ? 1.0 : 0.0)));
   }
-  em = rr_block_max(em, red);
+  em = rr_block_max<NT>(em, red);
   if (em < kRRSeriesTol) {
     // V is orthonormal up to E = B - I: Li = B^-1/2 = I - E/2 + 3/8 E^2 - 5/16 E^3 (the
     // next term is O(|E|^4) < 1e-22 R^4), symmetric, so that Li B Li^T = I as with the
     // Cholesky factor below.  Horner form: Li = I + E (-I/2 + E (3/8 I - 5/16 E)).
-    for (int e = tid; e < R * R; e += 256) {
+    for (int e = tid; e < R * R; e += NT) {
       const int i = e / R, k = e - i * R;
-      const double ev = L[i * RRS + k] - (i == k ? 1.0 : 0.0);
-      L[i * RRS + k] = ev;
-      Li[i * RRS + k] = (i == k ? 0.375 : 0.0) - 0.3125 * ev;
+      const double ev = L[i * LS + k] - (i == k ? 1.0 : 0.0);
+      L[i * LS + k] = ev;
+      Li[i * LS + k] = (i == k ? 0.375 : 0.0) - 0.3125 * ev;
     }
-    __syncthreads();
-    rr_product(Lc, L, RRS, 1, Li, RRS, 1, R);
-    __syncthreads();
-    for (int i = tid; i < R; i += 256) Lc[i * RRS + i] -= 0.5;
-    __syncthreads();
-    rr_product(Li, L, RRS, 1, Lc, RRS, 1, R);
-    __syncthreads();
-    for (int i = tid; i < R; i += 256) Li[i * RRS + i] += 1.0;
-    __syncthreads();
+    rr_sync<NT>();
+    rr_product<LS, NT>(Lc, L, LS, 1, Li, LS, 1, R);
+    rr_sync<NT>();
+    for (int i = tid; i < R; i += NT) Lc[i * LS + i] -= 0.5;
+    rr_sync<NT>();
+    rr_product<LS, NT>(Li, L, LS, 1, Lc, LS, 1, R);
+    rr_sync<NT>();
+    for (int i = tid; i < R; i += NT) Li[i * LS + i] += 1.0;
+    rr_sync<NT>();
   } else {
   // Cholesky of B: Lc = L with L L^T = B (lower)
   for (int j = 0; j < R; ++j) {
-    const double d0 = L[j * RRS + j];
+    const double d0 = L[j * LS + j];
     const bool ok = d0 > 0.0 && isfinite(d0);
-    if (tid == 0 && !ok) bad = 1;
+    if (tid == 0 && !ok) *bad = 1;
     const double d = ok ? d0 : 1.0;
     const double inv_sd = 1.0 / sqrt(d);
     const double inv_d = 1.0 / d;
     const int m = R - j - 1;
-    for (int e = tid; e < m * m; e += 256) {
+    for (int e = tid; e < m * m; e += NT) {
       const int ii = e / m, kk = e - ii * m;
       if (kk <= ii) {
         const int i = j + 1 + ii, k = j + 1 + kk;
-        L[i * RRS + k] -= L[i * RRS + j] * L[k * RRS + j] * inv_d;
+        L[i * LS + k] -= L[i * LS + j] * L[k * LS + j] * inv_d;
       }
     }
-    for (int i = j + tid; i < R; i += 256) Lc[i * RRS + j] = (i == j) ? sqrt(d) : L[i * RRS + j] * inv_sd;
-    __syncthreads();
+    for (int i = j + tid; i < R; i += NT) Lc[i * LS + j] = (i == j) ? sqrt(d) : L[i * LS + j] * inv_sd;
+    rr_sync<NT>();
   }
   // Li = Lc^-1, column j by the quad of lanes 4j..4j+3 (k split by k mod 4)
   {
     const int j = tid >> 2, l = tid & 3;
     if (j < R) {
-      if (l == 0) Li[j * RRS + j] = 1.0 / Lc[j * RRS + j];
+      if (l == 0) Li[j * LS + j] = 1.0 / Lc[j * LS + j];
       for (int i = j + 1; i < R; ++i) {
         double s = 0.0;
-        for (int k = j + l; k < i; k += 4) s = fma(Lc[i * RRS + k], Li[k * RRS + j], s);
+        for (int k = j + l; k < i; k += 4) s = fma(Lc[i * LS + k], Li[k * LS + j], s);
         s += __shfl_xor(s, 1);
         s += __shfl_xor(s, 2);
         // every lane of the quad has the sum; lane (i - j) mod 4 stores it and is the only
         // lane that reads it again (k - j = l mod 4 above), later in program order
-        if (l == ((i - j) & 3)) Li[i * RRS + j] = -s / Lc[i * RRS + i];
+        if (l == ((i - j) & 3)) Li[i * LS + j] = -s / Lc[i * LS + i];
       }
     }
   }
-  __syncthreads();
+  rr_sync<NT>();
   }
   // H' = Li H Li^T: Z = Li H into L, then H = Z Li^T
-  rr_product(L, Li, RRS, 1, H, RRS, 1, R);
-  __syncthreads();
-  rr_product(H, L, RRS, 1, Li, 1, RRS, R);
-  __syncthreads();
-  for (int e = tid; e < R * R; e += 256) {  // symmetrise; eigenvectors start at I
+  rr_product<LS, NT>(L, Li, LS, 1, H, LS, 1, R);
+  rr_sync<NT>();
+  rr_product<LS, NT>(H, L, LS, 1, Li, 1, LS, R);
+  rr_sync<NT>();
+  for (int e = tid; e < R * R; e += NT) {  // symmetrise; eigenvectors start at I
     const int i = e / R, k = e - i * R;
     if (k < i) {
-      const double v = 0.5 * (H[i * RRS + k] + H[k * RRS + i]);
-      H[i * RRS + k] = v;
-      H[k * RRS + i] = v;
+      const double v = 0.5 * (H[i * LS + k] + H[k * LS + i]);
+      H[i * LS + k] = v;
+      H[k * LS + i] = v;
     }
   }
-  for (int e = tid; e < 64 * RRS; e += 256) Lc[e] = 0.0;
-  __syncthreads();
+  for (int e = tid; e < RM * LS; e += NT) Lc[e] = 0.0;
+  rr_sync<NT>();
   double* Q = Lc;
-  for (int i = tid; i < R; i += 256) Q[i * RRS + i] = 1.0;
-  __syncthreads();
+  for (int i = tid; i < R; i += NT) Q[i * LS + i] = 1.0;
+  rr_sync<NT>();
   // cyclic Jacobi, round-robin pairs (index RP-1 fixed, the others rotate)
   int sweep = 0;
   for (; sweep < 40; ++sweep) {
     double o = 0.0, dg = 0.0;
-    for (int e = tid; e < R * R; e += 256) {
+    for (int e = tid; e < R * R; e += NT) {
       const int i = e / R, k = e - i * R;
-      const double v = H[i * RRS + k];
+      const double v = H[i * LS + k];
       if (i == k) dg = fma(v, v, dg);
       else o = fma(v, v, o);
     }
-    const double offn = rr_block_sum(o, red);
-    const double diagn = rr_block_sum(dg, red);
+    const double offn = rr_block_sum<NT>(o, red);
+    const double diagn = rr_block_sum<NT>(dg, red);
     if (!(offn > 1e-30 * diagn)) break;
     for (int round = 0; round < RP - 1; ++round) {
       if (tid < RP / 2) {
@@ -408,9 +391,9 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs a) {
         }
         double c = 1.0, s = 0.0;
         if (q < R) {
-          const double apq = H[p * RRS + q];
+          const double apq = H[p * LS + q];
           if (apq != 0.0) {
-            const double theta = (H[q * RRS + q] - H[p * RRS + p]) / (2.0 * apq);
+            const double theta = (H[q * LS + q] - H[p * LS + p]) / (2.0 * apq);
             // tan of the rotation angle, the smaller root; 1 / (2 theta) once theta^2
             // would overflow
             const double t = fabs(theta) > 1e150
@@ -425,56 +408,78 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs a) {
         cs[tid] = c;
         sn[tid] = s;
       }
-      __syncthreads();
+      rr_sync<NT>();
       // H <- J^T H J one 2 x 2 block (rows of pair w1, columns of pair w2) per step: the
       // pairs of a round partition the indices, so the blocks are disjoint.  A pair whose
       // partner is the padding index R has a single row or column.
       const int np = RP / 2;
-      for (int e = tid; e < np * np; e += 256) {
+      for (int e = tid; e < np * np; e += NT) {
         const int w1 = e / np, w2 = e - w1 * np;
         const double s1 = sn[w1], s2 = sn[w2];
         if (s1 == 0.0 && s2 == 0.0) continue;
         const double c1 = cs[w1], c2 = cs[w2];
         const int p1 = pr[w1], q1 = qr[w1], p2 = pr[w2], q2 = qr[w2];
         const bool r1 = q1 < R, r2 = q2 < R;
-        const double hpp = H[p1 * RRS + p2];
-        const double hpq = r2 ? H[p1 * RRS + q2] : 0.0;
-        const double hqp = r1 ? H[q1 * RRS + p2] : 0.0;
-        const double hqq = (r1 && r2) ? H[q1 * RRS + q2] : 0.0;
+        const double hpp = H[p1 * LS + p2];
+        const double hpq = r2 ? H[p1 * LS + q2] : 0.0;
+        const double hqp = r1 ? H[q1 * LS + p2] : 0.0;
+        const double hqq = (r1 && r2) ? H[q1 * LS + q2] : 0.0;
         // rows: p' = c1 p - s1 q, q' = s1 p + c1 q
         const double app = c1 * hpp - s1 * hqp, apq = c1 * hpq - s1 * hqq;
         const double aqp = s1 * hpp + c1 * hqp, aqq = s1 * hpq + c1 * hqq;
         // columns: p' = c2 p - s2 q, q' = s2 p + c2 q
-        H[p1 * RRS + p2] = c2 * app - s2 * apq;
-        if (r2) H[p1 * RRS + q2] = s2 * app + c2 * apq;
-        if (r1) H[q1 * RRS + p2] = c2 * aqp - s2 * aqq;
-        if (r1 && r2) H[q1 * RRS + q2] = s2 * aqp + c2 * aqq;
+        H[p1 * LS + p2] = c2 * app - s2 * apq;
+        if (r2) H[p1 * LS + q2] = s2 * app + c2 * apq;
+        if (r1) H[q1 * LS + p2] = c2 * aqp - s2 * aqq;
+        if (r1 && r2) H[q1 * LS + q2] = s2 * aqp + c2 * aqq;
       }
       // eigenvectors Q <- Q J
-      for (int e = tid; e < np * R; e += 256) {
+      for (int e = tid; e < np * R; e += NT) {
         const int k = e / np, w = e - k * np;
         const double s = sn[w];
         if (s != 0.0) {
           const int p = pr[w], q = qr[w];
           const double c = cs[w];
-          const double vp = Q[k * RRS + p], vq = Q[k * RRS + q];
-          Q[k * RRS + p] = c * vp - s * vq;
-          Q[k * RRS + q] = s * vp + c * vq;
+          const double vp = Q[k * LS + p], vq = Q[k * LS + q];
+          Q[k * LS + p] = c * vp - s * vq;
+          Q[k * LS + q] = s * vp + c * vq;
         }
       }
-      __syncthreads();
+      rr_sync<NT>();
     }
   }
   // T = Li^T Q into L
-  if (tid < R) lam[tid] = H[tid * RRS + tid];
-  rr_product(L, Li, 1, RRS, Q, RRS, 1, R);
-  __syncthreads();
-  // in-kernel projections: P = V^T Ap into H (free now), staged through Li and Lc
-  const bool p_lds = a.V && a.Ap;
-  if (p_lds) {
-    rr_project(a.V, a.Ap, nullptr, a.rows, R, Li, Lc, nullptr, Lc + 64 * RRS - 256, H, nullptr);
-    __syncthreads();
+  if (tid < R) lam[tid] = H[tid * LS + tid];
+  rr_product<LS, NT>(L, Li, 1, LS, Q, LS, 1, R);
+  rr_sync<NT>();
+  return sweep;
+}
+
+__global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs a) {
+  constexpr int RM = 64, LS = RM + 1;
+  __shared__ double L[RM * LS];   // B, trailing updates; later scratch (Z, T)
+  __shared__ double Lc[RM * LS];  // Cholesky factor; later the Jacobi eigenvectors
+  __shared__ double Li[RM * LS];  // L^-1 (lower)
+  __shared__ double H[RM * LS];   // H, then H' (rotated in place)
+  __shared__ double lam[RM];
+  __shared__ double cs[RM / 2], sn[RM / 2];
+  __shared__ int pr[RM / 2], qr[RM / 2];
+  __shared__ double red[4];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  const int R = a.R;
+  for (int e = tid; e < RM * LS; e += 256) {
+    Lc[e] = 0.0;
+    Li[e] = 0.0;
   }
+  for (int e = tid; e < R * R; e += 256) {
+    const int i = e / R, k = e - i * R;
+    L[i * LS + k] = a.B[e];
+    H[i * LS + k] = a.H[e];
+  }
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  const int sweep = rr_core<RM, 256>(R, L, Lc, Li, H, lam, cs, sn, pr, qr, red, &bad);
   // decreasing order (ties by index), sign against A_prev, written to sorted position
   if (tid < R) {
     const int j = tid;
@@ -482,13 +487,12 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs a) {
     int pos = 0;
     for (int k = 0; k < R; ++k) pos += (lam[k] > v) || (lam[k] == v && k < j);
     double sgn = 1.0;
-    if (p_lds || (!a.V && a.P)) {
+    if (a.P) {
       double d = 0.0;
-      for (int m = 0; m < R; ++m)  // the column it replaces
-        d = fma(L[m * RRS + j], p_lds ? H[m * RRS + pos] : a.P[m * R + pos], d);
+      for (int m = 0; m < R; ++m) d = fma(L[m * LS + j], a.P[m * R + pos], d);  // the column it replaces
       sgn = d < 0.0 ? -1.0 : 1.0;
     }
-    for (int i = 0; i < R; ++i) a.T[i * R + pos] = sgn * L[i * RRS + j];
+    for (int i = 0; i < R; ++i) a.T[i * R + pos] = sgn * L[i * LS + j];
     a.lam[pos] = v;
   }
   if (tid == 0) {
@@ -500,6 +504,185 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs a) {
 hipError_t launch_rayleigh_ritz(const RRArgs& a, hipStream_t s) {
   if (a.R < 1 || a.R > 64) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_rayleigh_ritz, dim3(1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// dst[e] = sum_{c < np} src[c * stride + e] for e < n into LDS, slots added in order: each
+// thread issues the loads of SB slots of EB elements before adding them.
+template <int EB, int SB>
+__device__ __forceinline__ void stage_sum_t(double* dst, const double* __restrict__ src, int np,
+                                            int64_t stride, int n) {
+  for (int e0 = threadIdx.x; e0 < n; e0 += EB * 256) {
+    double acc[EB];
+#pragma unroll
+    for (int b = 0; b < EB; ++b) acc[b] = 0.0;
+    for (int c0 = 0; c0 < np; c0 += SB) {
+      double v[EB][SB];
+#pragma unroll
+      for (int b = 0; b < EB; ++b)
+#pragma unroll
+        for (int q = 0; q < SB; ++q) {
+          const int e = e0 + 256 * b, c = c0 + q;
+          v[b][q] = (e < n && c < np) ? src[c * stride + e] : 0.0;
+        }
+#pragma unroll
+      for (int b = 0; b < EB; ++b)
+#pragma unroll
+        for (int q = 0; q < SB; ++q)
+          if (c0 + q < np) acc[b] += v[b][q];
+    }
+#pragma unroll
+    for (int b = 0; b < EB; ++b) {
+      const int e = e0 + 256 * b;
+      if (e < n) dst[e] = acc[b];
+    }
+  }
+}
+
+// stage_sum_t with the shape that needs the fewest rounds of loads (uniform choice)
+__device__ __forceinline__ void stage_sum(double* dst, const double* __restrict__ src, int np,
+                                          int64_t stride, int n) {
+  auto rounds = [&](int eb, int sb) { return ((n + 256 * eb - 1) / (256 * eb)) * ((np + sb - 1) / sb); };
+  if (rounds(2, 16) <= rounds(8, 8)) stage_sum_t<2, 16>(dst, src, np, stride, n);
+  else stage_sum_t<8, 8>(dst, src, np, stride, n);
+}
+
+// dst1[e] = src1[e] and (src2 non-null) dst2[e] = src2[e] for e < n into LDS, sixteen loads
+// in flight per thread before the stores.
+__device__ __forceinline__ void stage_two(double* dst1, const double* __restrict__ src1,
+                                          double* dst2, const double* __restrict__ src2, int n) {
+  for (int e0 = threadIdx.x; e0 < n; e0 += 8 * 256) {
+    double v[8], w[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = e0 + 256 * q;
+      v[q] = e < n ? src1[e] : 0.0;
+      w[q] = (src2 && e < n) ? src2[e] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = e0 + 256 * q;
+      if (e < n) {
+        dst1[e] = v[q];
+        if (src2) dst2[e] = w[q];
+      }
+    }
+  }
+}
+
+// The whole subspace step after C = W V for R <= 16 in one workgroup, with V, C and A_prev
+// resident in LDS (rows x R each, at most kRRSmallElems): C is the sum of npart partial
+// slots in slot order (or C itself), then the projections, the Rayleigh-Ritz algebra, the
+// sorted and signed T and lam, and the Ritz update: U = V T, V <- C T diag(lam)^-1 and
+// *residual = max_j ||C T_j - lam_j U_j|| / |lam_0| (column sums of squares by interleaved
+// row groups added in group order).
+__global__ __launch_bounds__(256) void k_rr_small(RRArgs a) {
+  constexpr int RM = 16, LS = RM + 1;
+  __shared__ double L[RM * LS], Lc[RM * LS], Li[RM * LS], H[RM * LS], P[RM * LS], Tf[RM * LS];
+  __shared__ double lam[RM], lams[RM];
+  __shared__ double cs[RM / 2], sn[RM / 2];
+  __shared__ int pr[RM / 2], qr[RM / 2];
+  __shared__ double red[256];
+  __shared__ int bad;
+  extern __shared__ double dyn[];
+  const int tid = threadIdx.x;
+  const int R = a.R;
+  const int rows = (int)a.rows;
+  const int n = rows * R;
+  double* Vs = dyn;
+  double* Cs = Vs + n;
+  double* As = Cs + n;
+  if (a.cpart) {
+    stage_sum(Cs, a.cpart, a.npart, a.pstride, n);
+    stage_two(Vs, a.V, As, a.Ap, n);
+  } else {
+    stage_two(Vs, a.V, Cs, a.C, n);
+    if (a.Ap) stage_rows(As, a.Ap, n);
+  }
+  for (int e = tid; e < RM * LS; e += 256) {
+    Lc[e] = 0.0;
+    Li[e] = 0.0;
+  }
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  rr_project<LS>(Vs, Vs, Cs, rows, R, red, L, H);
+  if (a.Ap) rr_project<LS>(Vs, As, nullptr, rows, R, red, P, nullptr);
+  __syncthreads();
+  // the algebra in wave 0 (R <= 16: no workgroup barriers), the other waves wait
+  int sweep = 0;
+  if (tid < 64) sweep = rr_core<RM, 64>(R, L, Lc, Li, H, lam, cs, sn, pr, qr, red, &bad);
+  __syncthreads();
+  if (tid < R) {
+    const int j = tid;
+    const double v = lam[j];
+    int pos = 0;
+    for (int k = 0; k < R; ++k) pos += (lam[k] > v) || (lam[k] == v && k < j);
+    double sgn = 1.0;
+    if (a.Ap) {
+      double d = 0.0;
+      for (int m = 0; m < R; ++m) d = fma(L[m * LS + j], P[m * LS + pos], d);
+      sgn = d < 0.0 ? -1.0 : 1.0;
+    }
+    for (int i = 0; i < R; ++i) {
+      const double t = sgn * L[i * LS + j];
+      Tf[i * LS + pos] = t;
+      a.T[i * R + pos] = t;
+    }
+    lams[pos] = v;
+    a.lam[pos] = v;
+  }
+  if (tid == 0) {
+    a.status[0] = bad;
+    a.status[1] = sweep;
+  }
+  __syncthreads();
+  double* D = As;  // A_prev is no longer needed
+  for (int e = tid; e < n; e += 256) {
+    const int x = e / R, j = e - x * R;
+    double u = 0.0, ct = 0.0;
+    for (int m = 0; m < R; ++m) {
+      const double t = Tf[m * LS + j];
+      u = fma(Vs[x * R + m], t, u);
+      ct = fma(Cs[x * R + m], t, ct);
+    }
+    const double d = ct - lams[j] * u;
+    D[e] = d * d;
+    a.U[e] = u;
+    a.Vout[e] = lams[j] != 0.0 ? ct / lams[j] : ct;
+  }
+  __syncthreads();
+  const int G = 256 / R;
+  const int g = tid / R, j = tid - g * R;
+  double s = 0.0;
+  if (g < G)
+    for (int x = g; x < rows; x += G) s += D[x * R + j];
+  red[tid] = s;
+  __syncthreads();
+  if (tid == 0) {
+    double mx = 0.0;
+    for (int jj = 0; jj < R; ++jj) {
+      double t = 0.0;
+      for (int q = 0; q < G; ++q) t += red[q * R + jj];
+      mx = fmax(mx, sqrt(t));
+    }
+    const double l0 = fabs(lams[0]) > 0.0 ? fabs(lams[0]) : 1.0;
+    *a.residual = mx / l0;
+  }
+}
+
+bool rr_small_fits(int64_t rows, int R) { return R >= 1 && R <= 16 && rows * R <= kRRSmallElems; }
+
+hipError_t launch_rr_small(const RRArgs& a, hipStream_t s) {
+  if (!rr_small_fits(a.rows, a.R) || !a.V || !a.Vout || !a.U || !a.residual || (!a.C && !a.cpart) ||
+      (a.cpart && (a.npart < 1 || a.npart > kRRSmallParts)))
+    return hipErrorInvalidValue;
+  const size_t lds = (size_t)3 * a.rows * a.R * sizeof(double);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_rr_small),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_rr_small, dim3(1), dim3(256), lds, s, a);
   return hipGetLastError();
 }
 
@@ -846,8 +1029,8 @@ __global__ __launch_bounds__(256) void k_w_apply(const double* __restrict__ Y,
   }
 }
 
-hipError_t launch_w_apply(const double* Y, const double* V, int64_t s, int64_t m, int R, int w,
-                          double* part, double* C, hipStream_t st) {
+hipError_t launch_w_apply_parts(const double* Y, const double* V, int64_t s, int64_t m, int R,
+                                int w, double* part, hipStream_t st) {
   if (w < 1 || w != w_apply_width(s, m, R)) return hipErrorInvalidValue;
   const int64_t nchunk = (m + w - 1) / w;
   const size_t lds = (size_t)(s * w + s * R + (int64_t)w * R + 256) * sizeof(double);
@@ -858,9 +1041,14 @@ hipError_t launch_w_apply(const double* Y, const double* V, int64_t s, int64_t m
   }
   hipLaunchKernelGGL(k_w_apply, dim3((unsigned)nchunk), dim3(256), lds, st, Y, V, (int)s, m, R,
                      w, part);
-  hipError_t e = hipGetLastError();
+  return hipGetLastError();
+}
+
+hipError_t launch_w_apply(const double* Y, const double* V, int64_t s, int64_t m, int R, int w,
+                          double* part, double* C, hipStream_t st) {
+  hipError_t e = launch_w_apply_parts(Y, V, s, m, R, w, part, st);
   if (e != hipSuccess) return e;
-  return launch_reduce_splits_to(C, 0, part, 0, (int)nchunk, s * R, st);
+  return launch_reduce_splits_to(C, 0, part, 0, (int)((m + w - 1) / w), s * R, st);
 }
 
 __global__ void k_copy2(double* __restrict__ o1, double* __restrict__ o2,

@@ -264,11 +264,14 @@ Level1Geom inner_unfolding_geom(const tucker_plan* p, int n) {
 // C = W V for the subspace iteration of mode n: through a TTMc Y (W = Y_(n) Y_(n)^T, Y
 // given) or, for the HOSVD (Y null), through X itself (W = X_(n) X_(n)^T) with the
 // intermediate Z = X_(n)^T V in a chain temporary.
+// With npart non-null the chunked product may leave C as *npart <= kRRSmallParts slots in
+// the partial region (*npart = 0: C written).
 ppals_status apply_w(const TCtx& c, int n, const double* Y, const double* X, const double* V,
-                     double* C) {
+                     double* C, int* npart = nullptr) {
   tucker_plan* p = c.p;
   const int N = p->N;
   const int64_t sn = p->s[n], RN1 = p->rpow[N - 1];
+  if (npart) *npart = 0;
   if (Y) {
     const int w = w_apply_width(sn, RN1, p->R);
     if (w > 0) {  // one pass over the small TTMc: C = Y (Y^T V) chunk by chunk
@@ -277,7 +280,12 @@ ppals_status apply_w(const TCtx& c, int n, const double* Y, const double* X, con
         c.col->part = std::max(c.col->part, (size_t)(nchunk * sn * p->R));
         return PPALS_OK;
       }
-      THIPCHK(launch_w_apply(Y, V, sn, RN1, p->R, w, c.d(p->o_part), C, c.s));
+      if (npart && nchunk <= kRRSmallParts) {
+        THIPCHK(launch_w_apply_parts(Y, V, sn, RN1, p->R, w, c.d(p->o_part), c.s));
+        *npart = (int)nchunk;
+      } else {
+        THIPCHK(launch_w_apply(Y, V, sn, RN1, p->R, w, c.d(p->o_part), C, c.s));
+      }
       return PPALS_OK;
     }
     double* Z = c.d(p->o_Z);
@@ -313,18 +321,33 @@ ppals_status subspace_step(const TCtx& c, int n, const double* Y, const double* 
   const int64_t sn = p->s[n];
   double* V = c.d(p->o_V);
   double* C = c.d(p->o_C);
-  TCHK(apply_w(c, n, Y, X, V, C));  // C = W V
+  const bool small = rr_small_fits(sn, R);
+  int npart = 0;
+  TCHK(apply_w(c, n, Y, X, V, C, small ? &npart : nullptr));  // C = W V
   if (c.col) return PPALS_OK;
   RRArgs rr;
   memset(&rr, 0, sizeof(rr));
-  if (rr_project_inline(sn, R)) {  // projections inside the Rayleigh-Ritz step
+  if (small) {  // projections, Rayleigh-Ritz and Ritz update in one workgroup
+    rr.R = R;
     rr.V = V;
+    rr.Vout = V;
     rr.C = C;
     rr.Ap = has_prev ? c.d(p->o_Aold) : nullptr;
     rr.rows = sn;
-  } else {
-    TCHK(projections(c, sn, has_prev ? 3 : 2));
+    rr.T = c.d(p->o_T);
+    rr.lam = c.d(p->o_lam);
+    rr.status = &info->rr_bad;
+    rr.U = c.d(p->o_U);
+    rr.residual = &info->residual;
+    if (npart > 0) {
+      rr.cpart = c.d(p->o_part);
+      rr.npart = npart;
+      rr.pstride = sn * R;
+    }
+    THIPCHK(launch_rr_small(rr, c.s));
+    return PPALS_OK;
   }
+  TCHK(projections(c, sn, has_prev ? 3 : 2));
   rr.R = R;
   rr.B = c.d(p->o_B);
   rr.H = c.d(p->o_H);

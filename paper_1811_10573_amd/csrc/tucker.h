@@ -31,27 +31,27 @@ struct RRArgs {
   double* T;         // R x R out: V T are the Ritz vectors, decreasing order
   double* lam;       // R out: Ritz values, decreasing
   int* status;       // [0] 1 if V^T V was not positive definite, [1] Jacobi sweeps
-  // In-kernel projections (V non-null; B, H and P are then not read): V and C (rows x R)
-  // give B = V^T V and H = V^T C, Ap (rows x R, may be null) gives P = V^T Ap.
+  // launch_rr_small only (B, H and P are then not read): V and C (rows x R) give
+  // B = V^T V and H = V^T C, Ap (rows x R, may be null) gives P = V^T Ap; the Ritz update's
+  // outputs (U, the next basis Vout = V, the residual); C is the sum of npart slots of
+  // pstride doubles at cpart (null: C itself).
   const double* V;
   const double* C;
   const double* Ap;
   int64_t rows;
+  double* U;
+  double* Vout;
+  double* residual;
+  const double* cpart;
+  int npart;
+  int64_t pstride;
 };
-// In-kernel projections: each of the R^2 entries is summed by G groups of threads over
-// interleaved rows (G = the largest power of two with G R^2 <= 256, at least 1; a thread
-// holds up to 16 entries when G = 1).  They pay off against a split GEMM launch while a
-// thread's share of the rows stays short.
-inline int rr_project_groups(int R) {
-  int g = 1;
-  while (2 * g * R * R <= 256) g *= 2;
-  return g;
-}
-inline bool rr_project_inline(int64_t rows, int R) {
-  const int G = rr_project_groups(R);
-  const int64_t ne = G > 1 ? 1 : (R * R + 255) / 256;
-  return (rows + G - 1) / G * ne <= 64;
-}
+// The whole subspace step after C = W V (projections, Rayleigh-Ritz, Ritz update, residual)
+// in one workgroup, for R <= 16 and rows R <= kRRSmallElems (V, C, A_prev held in LDS).
+constexpr int64_t kRRSmallElems = 2048;
+constexpr int kRRSmallParts = 32;  // partial slots of C it adds at most
+bool rr_small_fits(int64_t rows, int R);
+hipError_t launch_rr_small(const RRArgs& a, hipStream_t s);
 hipError_t launch_rayleigh_ritz(const RRArgs& a, hipStream_t s);
 // U = V T, CT = C T, V <- CT diag(lam)^-1 and *residual = max_j ||CT_j - lam_j U_j|| / |lam_0|;
 // part holds ceil(rows / 32) x R doubles.
@@ -80,11 +80,15 @@ hipError_t launch_mode_end(const double* U, const double* Ap, double* A, double*
                            double* out, hipStream_t s);
 // C = Y (Y^T V) for a small TTMc Y (s x m, row-major), V (s x R): the columns of Y in chunks
 // of w, one workgroup each, whose s x R results go to part[chunk] and are added in chunk
-// order by a second launch.  w_apply_width gives w (about 32 chunks), or 0 when a chunk
-// (s x w), V and Z = Y_chunk^T V (w x R) do not fit the workgroup's LDS.
+// order by a second launch.  w_apply_width gives w (about 32 chunks, more when LDS bounds
+// w), or 0 when a chunk (s x w), V and Z = Y_chunk^T V (w x R) do not fit the workgroup's
+// LDS.
 int w_apply_width(int64_t s, int64_t m, int R);
 hipError_t launch_w_apply(const double* Y, const double* V, int64_t s, int64_t m, int R, int w,
                           double* part, double* C, hipStream_t st);
+// the same without the second launch: C is left as the (m + w - 1) / w slots of s x R in part
+hipError_t launch_w_apply_parts(const double* Y, const double* V, int64_t s, int64_t m, int R,
+                                int w, double* part, hipStream_t st);
 // out1 = out2 = in (n doubles)
 hipError_t launch_copy2(double* out1, double* out2, const double* in, int64_t n, hipStream_t s);
 

@@ -122,12 +122,15 @@ def test_hosvd_matches_oracle(shape, R):
 
 
 @pytest.mark.parametrize("shape,R", [((37, 29, 23), 5), ((96, 80, 72), 24), ((14, 12, 11, 10), 3),
-                                     ((9, 8, 7, 8, 6), 2), ((1400, 20, 18), 12)])
+                                     ((9, 8, 7, 8, 6), 2), ((1400, 20, 18), 12),
+                                     ((120, 20, 20, 20), 16)])
 def test_als_sweeps_match_oracle(shape, R):
     """Six HOOI sweeps from the oracle's HOSVD: factors, core and every record field.
     W V = Y (Y^T V) runs in one chunked kernel while Y's chunk, V and Y_chunk^T V fit a
     workgroup's LDS, else as two first-level contractions (mode 0 of 1400 x 20 x 18 at
-    R = 12)."""
+    R = 12).  For R <= 16 and s_n R <= 2048 one workgroup takes the rest of the step,
+    adding the chunks itself when there are at most 32 (mode 0 of 120 x 20^3 at R = 16
+    has 36, added by a separate launch first)."""
     r = TRun(shape, R, seed=7, eta=0.3)
     A0, G0 = ot.hosvd(r.prob.X, r.ranks())
     r.upload(A0, G0)
