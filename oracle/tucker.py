@@ -22,7 +22,9 @@ Readings where the paper is silent:
   across sweeps; dA = A - A_p needs them consistent).  For the HOSVD start, where
   nothing is replaced, the entry of largest magnitude is made positive (the first
   one on ties).
-* HOSVD is the classical one: A^(n) from X_(n) for every n.
+* HOSVD: the classical one (A^(n) from X_(n) for every n) and the interlaced one
+  (Section 2.4: A^(n) from Z^(n)_(n), Z^(n+1) = Z^(n) x_n A^(n)T, Z^(1) = X); the
+  paper's error bound for the TTMc assumes the interlaced start.
 * Switching (Algorithm 4).  PP is entered after a sweep in which every
   ||dA^(i)||_F < eps ||A^(i)||_F (strict), and PP sweeps run while
   ||F||_F < eps ||X||_F; a build is made only when at least one PP sweep follows
@@ -98,6 +100,20 @@ def hosvd(X, ranks):
     for n in range(X.ndim):
         G = ttm(G, A[n], n)
     return A, G
+
+
+def hosvd_interlaced(X, ranks):
+    """Interlaced HOSVD start (Section 2.4): with Z^(1) = X, A^(n) = the leading left
+    singular vectors of Z^(n)_(n) and Z^(n+1) = Z^(n) x_n A^(n)T (the truncated
+    Sigma V^T of that SVD), so Z^(n) keeps the modes from n on and the ranks of the
+    modes before; the core is the last Z.  Signs as in hosvd."""
+    A = []
+    Z = X
+    for n in range(X.ndim):
+        a, _ = leading_eigvecs(Z, n, ranks[n])
+        A.append(a)
+        Z = ttm(Z, a, n)
+    return A, Z
 
 
 @dataclasses.dataclass

@@ -72,6 +72,48 @@ def test_hosvd_recovers_an_exact_tucker_tensor():
         np.testing.assert_allclose(a @ a.T, q @ q.T, atol=1e-12)
 
 
+def test_interlaced_hosvd_recovers_an_exact_tucker_tensor():
+    p = tensorgen.make_tucker_problem((9, 10, 8, 7), (3, 4, 2, 3), seed=5, eta=0.0)
+    A, G = ot.hosvd_interlaced(p.X, p.ranks)
+    assert G.shape == p.ranks
+    np.testing.assert_allclose(ot.reconstruct(G, A), p.X, atol=1e-11 * np.abs(p.X).max())
+    for a, q in zip(A, p.planted):
+        np.testing.assert_allclose(a @ a.T, q @ q.T, atol=1e-12)
+
+
+def test_interlaced_hosvd_steps_are_truncated_svds():
+    """Each step keeps the leading singular subspace of the current Z's unfolding: the
+    kept energy is the sum of the R_n largest squared singular values (numpy's SVD of
+    the unfolding, independent of the Gram route), the next Z's mode-n unfolding has
+    orthogonal rows of those norms (Sigma V^T), it has the modes from n + 1 on and the
+    ranks before (sizes s^(N-n) R^n), and the first factor is the classical one."""
+    X = tensorgen.make_tucker_problem((8, 7, 9, 6), (3, 2, 4, 3), seed=6, eta=0.4).X
+    ranks = (3, 2, 4, 3)
+    A, G = ot.hosvd_interlaced(X, ranks)
+    A_cl, _ = ot.hosvd(X, ranks)
+    np.testing.assert_allclose(A[0], A_cl[0], atol=1e-12)
+    Z = X
+    for n in range(X.ndim):
+        sv = np.linalg.svd(ot.unfold(Z, n), compute_uv=False)
+        Zn = ot.ttm(Z, A[n], n)
+        assert Zn.shape == tuple(ranks[:n + 1]) + X.shape[n + 1:]
+        gram = ot.unfold(Zn, n) @ ot.unfold(Zn, n).T
+        np.testing.assert_allclose(np.diag(gram), sv[:ranks[n]] ** 2, rtol=1e-10)
+        off = gram - np.diag(np.diag(gram))
+        assert np.abs(off).max() <= 1e-10 * sv[0] ** 2
+        Z = Zn
+    np.testing.assert_allclose(G, Z, rtol=0, atol=1e-12 * np.abs(Z).max())
+    # the residual is the energy dropped at each step
+    dropped = 0.0
+    Z = X
+    for n in range(X.ndim):
+        sv = np.linalg.svd(ot.unfold(Z, n), compute_uv=False)
+        dropped += float(np.sum(sv[ranks[n]:] ** 2))
+        Z = ot.ttm(Z, A[n], n)
+    res = float(np.linalg.norm(X - ot.reconstruct(G, A)) ** 2)
+    assert abs(res - dropped) <= 1e-10 * float(np.sum(X * X))
+
+
 def test_hooi_core_norm_never_decreases_and_fit_identity_holds():
     """Each Tucker-ALS factor update maximises ||Y^(n) x_n A^T|| over orthonormal A, so
     ||G|| cannot decrease (the paper states it strictly increases); the fit from ||G||
