@@ -523,6 +523,17 @@ ppals_status tucker_factor_update(tucker_plan* plan, void* ws, const double* Y, 
 ppals_status tucker_hosvd(tucker_plan* plan, void* ws, const double* X, double* const* V0,
                           double* const* A, double* G, int32_t* info, hipStream_t stream);
 
+/* Interlaced HOSVD start (Section 2.4; the start the paper's TTMc error bound assumes):
+ * with Z^(1) = X, A^(n) <- leading eigenvectors of Z^(n)_(n) Z^(n)_(n)^T by the subspace
+ * iteration above (W applied through Z^(n), started from V0[n]) and
+ * Z^(n+1) = Z^(n) x_n A^(n)T, which has the ranks of the modes before n + 1 in place of
+ * their sizes; G <- the last Z.  Each Z^(n) after the first is s_n / R times smaller than
+ * the one before, so the factor updates after the first cost little.  Signs, info,
+ * arguments and errors as in tucker_hosvd.  Synchronises the stream. */
+ppals_status tucker_hosvd_interlaced(tucker_plan* plan, void* ws, const double* X,
+                                    double* const* V0, double* const* A, double* G,
+                                    int32_t* info, hipStream_t stream);
+
 /* One Tucker-ALS sweep (Algorithm 2 loop body) with the prefix chain above; then G from
  * the last TTMc.  G holds the previous core on entry (for ||F||).  normX2 = ||X||^2. */
 ppals_status tucker_als_sweep(tucker_plan* plan, void* ws, const double* X, double* const* A,

@@ -6,9 +6,9 @@ The function names mirror the C ABI declared in include/ppals.h:
 cp_als_sweep, pp_build_operators, pp_sweep, gram_solve, plus the auxiliary
 entry points (norm, bf16 cast, MTTKRP, first-level contraction, PP right-hand
 side, operators, exact residual and the native decomposition driver), the
-batched engine and the order-3 Tucker path (TuckerPlan: tucker_ttmc,
-tucker_factor_update, tucker_hosvd, tucker_als_sweep, tucker_pp_build,
-tucker_pp_rhs, tucker_pp_sweep, tucker_run).
+batched engine and the Tucker path of orders 3 to 8 (TuckerPlan: tucker_ttmc,
+tucker_factor_update, tucker_hosvd, tucker_hosvd_interlaced, tucker_als_sweep,
+tucker_pp_build, tucker_pp_rhs, tucker_pp_sweep, tucker_run).
 """
 from __future__ import annotations
 
@@ -613,6 +613,15 @@ def tucker_hosvd(plan, ws, X, V0, A, G, stream=None):
     info = (ctypes.c_int32 * (3 * plan.order))()
     _lib.check(lib().tucker_hosvd(plan._h, _p(plan._ws(ws)), _p(plan._X(X)), plan._A(V0, "V0"),
                                   plan._A(A), _p(plan._G(G)), info, _stream(stream)))
+    return [list(info[3 * n:3 * n + 3]) for n in range(plan.order)]
+
+
+def tucker_hosvd_interlaced(plan, ws, X, V0, A, G, stream=None):
+    """Returns the per-mode [iterations, converged, rr_status]."""
+    info = (ctypes.c_int32 * (3 * plan.order))()
+    _lib.check(lib().tucker_hosvd_interlaced(plan._h, _p(plan._ws(ws)), _p(plan._X(X)),
+                                             plan._A(V0, "V0"), plan._A(A), _p(plan._G(G)),
+                                             info, _stream(stream)))
     return [list(info[3 * n:3 * n + 3]) for n in range(plan.order)]
 
 

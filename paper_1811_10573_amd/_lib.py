@@ -169,6 +169,8 @@ SIGNATURES = {
     "tucker_factor_update": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp, ctypes.POINTER(_i32),
                                     ctypes.POINTER(_dbl), _vp]),
     "tucker_hosvd": (_i32, [_vp, _vp, _vp, _ptrs, _ptrs, _vp, ctypes.POINTER(_i32), _vp]),
+    "tucker_hosvd_interlaced": (_i32, [_vp, _vp, _vp, _ptrs, _ptrs, _vp, ctypes.POINTER(_i32),
+                                       _vp]),
     "tucker_als_sweep": (_i32, [_vp, _vp, _vp, _ptrs, _vp, _dbl, ctypes.POINTER(TuckerRecord), _vp]),
     "tucker_pp_build": (_i32, [_vp, _vp, _vp, _ptrs, _vp]),
     "tucker_pp_rhs": (_i32, [_vp, _vp, _i32, _vp, _vp]),

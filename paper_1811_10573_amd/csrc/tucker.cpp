@@ -266,8 +266,10 @@ Level1Geom inner_unfolding_geom(const tucker_plan* p, int n) {
 // intermediate Z = X_(n)^T V in a chain temporary.
 // With npart non-null the chunked product may leave C as *npart <= kRRSmallParts slots in
 // the partial region (*npart = 0: C written).
+// X: the tensor with layout XL (null: X itself, every mode), mode n contracted around;
+// n is the first remaining mode of XL unless XL is null.
 ppals_status apply_w(const TCtx& c, int n, const double* Y, const double* X, const double* V,
-                     double* C, int* npart = nullptr) {
+                     double* C, int* npart = nullptr, const Lay* XL = nullptr) {
   tucker_plan* p = c.p;
   const int N = p->N;
   const int64_t sn = p->s[n], RN1 = p->rpow[N - 1];
@@ -294,13 +296,13 @@ ppals_status apply_w(const TCtx& c, int n, const double* Y, const double* X, con
     return PPALS_OK;
   }
   double* Zx = c.d(p->o_tmp[0]);
-  const Lay L = lay_all(p);
+  const Lay L = XL ? *XL : lay_all(p);
   const Contr k = contr_of(p, L, n);
   if (c.col) c.col->tmp = std::max(c.col->tmp, k.P * k.Q * p->R);
   TCHK(ttm(c, X, k, V, Zx));  // (other modes, r)
   const int64_t others = k.P * k.Q;
-  if (n == 0) TCHK(ttm(c, X, {sn, others, 1}, Zx, C));
-  else if (n == N - 1) TCHK(ttm(c, X, {1, others, sn}, Zx, C));
+  if (k.P == 1) TCHK(ttm(c, X, {sn, others, 1}, Zx, C));       // n first
+  else if (k.Q == 1) TCHK(ttm(c, X, {1, others, sn}, Zx, C));  // n last, no ranks after
   else TCHK(ttm_geom(c, X, inner_unfolding_geom(p, n), Zx, C));
   return PPALS_OK;
 }
@@ -315,7 +317,7 @@ struct IterInfo {
 // Rayleigh-Ritz step and the Ritz update (U, residual into info, next basis in V).
 // Enqueues only.  has_prev: A_prev is in the basis region's third slot.
 ppals_status subspace_step(const TCtx& c, int n, const double* Y, const double* X, bool has_prev,
-                           IterInfo* info) {
+                           IterInfo* info, const Lay* XL = nullptr) {
   tucker_plan* p = c.p;
   const int R = p->R;
   const int64_t sn = p->s[n];
@@ -323,7 +325,7 @@ ppals_status subspace_step(const TCtx& c, int n, const double* Y, const double* 
   double* C = c.d(p->o_C);
   const bool small = rr_small_fits(sn, R);
   int npart = 0;
-  TCHK(apply_w(c, n, Y, X, V, C, small ? &npart : nullptr));  // C = W V
+  TCHK(apply_w(c, n, Y, X, V, C, small ? &npart : nullptr, XL));  // C = W V
   if (c.col) return PPALS_OK;
   RRArgs rr;
   memset(&rr, 0, sizeof(rr));
@@ -367,11 +369,11 @@ ppals_status subspace_step(const TCtx& c, int n, const double* Y, const double* 
 // null) orients the columns.  Result into A_out.  Synchronises once per iteration.
 ppals_status subspace(const TCtx& c, int n, const double* Y, const double* X, const double* V0,
                       const double* A_prev, double* A_out, int max_iters, int32_t* info,
-                      double* residual) {
+                      double* residual, const Lay* XL = nullptr) {
   tucker_plan* p = c.p;
   if (c.col) {
     IterInfo dummy;
-    return subspace_step(c, n, Y, X, A_prev != nullptr, &dummy);
+    return subspace_step(c, n, Y, X, A_prev != nullptr, &dummy, XL);
   }
   const int R = p->R;
   const int64_t sn = p->s[n];
@@ -385,7 +387,7 @@ ppals_status subspace(const TCtx& c, int n, const double* Y, const double* X, co
   bool conv = false;
   while (it < max_iters) {
     ++it;
-    TCHK(subspace_step(c, n, Y, X, A_prev != nullptr, dinfo));
+    TCHK(subspace_step(c, n, Y, X, A_prev != nullptr, dinfo, XL));
     THIPCHK(hipMemcpyAsync(&hinfo, dinfo, sizeof(hinfo), hipMemcpyDeviceToHost, c.s));
     THIPCHK(hipStreamSynchronize(c.s));
     bad |= hinfo.rr_bad;
@@ -596,6 +598,24 @@ ppals_status hosvd_core(const TCtx& c, const double* X, const double* const* A, 
   return chain(c, X, lay_all(c.p), ms, A, G);
 }
 
+// Interlaced HOSVD (Section 2.4): A^(n) from the prefix Z^(n) = P_n (X for n = 0, then
+// P_(n+1) = P_n x_n A^(n)T), whose first mode is n; the core from P_(N-1).  info as in
+// tucker_hosvd.
+ppals_status hosvd_interlaced_impl(const TCtx& c, const double* X, double* const* V0,
+                                   double* const* A, double* G, int32_t* info) {
+  tucker_plan* p = c.p;
+  const int N = p->N;
+  for (int n = 0; n < N; ++n) {
+    const double* Z = n == 0 ? X : c.d(p->o_pre[n & 1]);
+    const Lay L = prefix_lay(p, n);
+    TCHK(subspace(c, n, nullptr, Z, c.col ? nullptr : V0[n], nullptr, c.col ? nullptr : A[n],
+                  p->hosvd_iters, info ? info + 3 * n : nullptr, nullptr, &L));
+    if (n < N - 1) TCHK(extend_prefix(c, X, A, n));
+  }
+  return ttm(c, c.d(p->o_pre[(N - 1) & 1]), {1, p->s[N - 1], p->rpow[N - 1]},
+             c.col ? nullptr : A[N - 1], G);
+}
+
 // ALS sweep schedule (also run in collecting mode for the workspace sizes).
 ppals_status als_impl(const TCtx& c, const double* X, double* const* A, double* G,
                       tucker_sweep_record* rec) {
@@ -672,6 +692,7 @@ ppals_status tucker_plan_create(int32_t order, const int64_t* dims, int32_t rank
       apply_w(c, n, some, nullptr, nullptr, nullptr);     // sweeps
     }
     hosvd_core(c, nullptr, fake, nullptr);
+    hosvd_interlaced_impl(c, nullptr, fake, fake, nullptr, nullptr);
     for (int n = 0; n < N; ++n) {  // tucker_ttmc
       std::vector<int> ms;
       for (int m = 0; m < N; ++m)
@@ -780,6 +801,20 @@ ppals_status tucker_hosvd(tucker_plan* plan, void* ws, const double* X, double* 
     TCHK(subspace(c, n, nullptr, X, V0[n], nullptr, A[n], plan->hosvd_iters,
                   info ? info + 3 * n : nullptr, nullptr));
   TCHK(hosvd_core(c, X, A, G));
+  THIPCHK(hipStreamSynchronize(stream));
+  plan->built = false;
+  return PPALS_OK;
+}
+
+ppals_status tucker_hosvd_interlaced(tucker_plan* plan, void* ws, const double* X,
+                                    double* const* V0, double* const* A, double* G,
+                                    int32_t* info, hipStream_t stream) {
+  TCHK(check_common(plan, ws));
+  TCHK(check_factors(plan, A));
+  TCHK(check_factors(plan, V0));
+  if (!X || !G) return set_error(PPALS_E_ARG, "NULL argument");
+  TCtx c{plan, (char*)ws, stream};
+  TCHK(hosvd_interlaced_impl(c, X, V0, A, G, info));
   THIPCHK(hipStreamSynchronize(stream));
   plan->built = false;
   return PPALS_OK;

@@ -121,6 +121,22 @@ def test_hosvd_matches_oracle(shape, R):
     assert_rel(r.core(), G_want, 1e-8, "core")
 
 
+@pytest.mark.parametrize("shape,R", [((41, 33, 27), 4), ((90, 84, 70), 20), ((14, 12, 11, 10), 3),
+                                     ((9, 8, 7, 8, 6), 3), ((6, 5, 6, 5, 6, 5), 2)])
+def test_interlaced_hosvd_matches_oracle(shape, R):
+    """Interlaced HOSVD (each factor from the prefix Z^(n) = X x_0 A^(0)T .. x_(n-1)
+    A^(n-1)T, whose first mode is n) against the oracle's."""
+    r = TRun(shape, R, seed=5)
+    A_want, G_want = ot.hosvd_interlaced(r.prob.X, r.ranks())
+    V0 = [to_dev(v) for v in tensorgen.subspace_start(shape, R, seed=6)]
+    r.upload([np.zeros_like(a) for a in A_want], r.zero_core())
+    info = pk.tucker_hosvd_interlaced(r.plan, r.ws, r.X, V0, r.A, r.G)
+    assert all(i[1] == 1 and i[2] == 0 for i in info), info
+    for n, (got, want) in enumerate(zip(r.factors(), A_want)):
+        np.testing.assert_allclose(got, want, atol=1e-8, rtol=0, err_msg=f"A^({n})")
+    assert_rel(r.core(), G_want, 1e-8, "core")
+
+
 @pytest.mark.parametrize("shape,R", [((37, 29, 23), 5), ((96, 80, 72), 24), ((14, 12, 11, 10), 3),
                                      ((9, 8, 7, 8, 6), 2), ((1400, 20, 18), 12),
                                      ((120, 20, 20, 20), 16)])
