@@ -1,5 +1,5 @@
 """GPU parity of the Tucker path (Tucker-ALS, Algorithm 2; PP-Tucker-ALS, Algorithm 4 with
-the first-order TTMc of Section 3.2.2) against the float64 oracle, at orders 3 to 6.
+the first-order TTMc of Section 3.2.2) against the float64 oracle, at orders 3 to 8.
 
 Layouts: the library stores Y^(n) as s_n x R^(N-1) with x_n first and the rank indices of
 the other modes in increasing mode order (the oracle's ttmc with mode n moved to the
@@ -69,7 +69,7 @@ def assert_rel(got, want, tol, what):
 
 @pytest.mark.parametrize("shape,R", [((37, 29, 23), 5), ((70, 64, 66), 16), ((96, 80, 72), 64),
                                      ((14, 12, 11, 10), 3), ((9, 8, 7, 8, 6), 3),
-                                     ((6, 5, 6, 5, 6, 5), 2)])
+                                     ((6, 5, 6, 5, 6, 5), 2), ((5, 4, 5, 4, 5, 4, 3), 2), ((4, 3, 4, 3, 4, 3, 4, 3), 2)])
 def test_ttmc_matches_oracle(shape, R):
     """Y^(n) = X x_{i != n} A^(i)T for every mode: ragged sizes, several level-1 tiles,
     the largest rank."""
@@ -106,7 +106,8 @@ def test_factor_update_matches_eigh(shape, R):
 
 
 @pytest.mark.parametrize("shape,R", [((41, 33, 27), 4), ((90, 84, 70), 20), ((14, 12, 11, 10), 3),
-                                     ((9, 8, 7, 8, 6), 3)])
+                                     ((9, 8, 7, 8, 6), 3), ((5, 4, 5, 4, 5, 4, 3), 2),
+                                     ((4, 3, 4, 3, 4, 3, 4, 3), 2)])
 def test_hosvd_matches_oracle(shape, R):
     """HOSVD from random starting bases: factors (largest-magnitude entry positive) and
     core against the oracle's eigh-based HOSVD."""
@@ -122,7 +123,7 @@ def test_hosvd_matches_oracle(shape, R):
 
 
 @pytest.mark.parametrize("shape,R", [((41, 33, 27), 4), ((90, 84, 70), 20), ((14, 12, 11, 10), 3),
-                                     ((9, 8, 7, 8, 6), 3), ((6, 5, 6, 5, 6, 5), 2)])
+                                     ((9, 8, 7, 8, 6), 3), ((6, 5, 6, 5, 6, 5), 2), ((5, 4, 5, 4, 5, 4, 3), 2), ((4, 3, 4, 3, 4, 3, 4, 3), 2)])
 def test_interlaced_hosvd_matches_oracle(shape, R):
     """Interlaced HOSVD (each factor from the prefix Z^(n) = X x_0 A^(0)T .. x_(n-1)
     A^(n-1)T, whose first mode is n) against the oracle's."""
@@ -139,7 +140,7 @@ def test_interlaced_hosvd_matches_oracle(shape, R):
 
 @pytest.mark.parametrize("shape,R", [((37, 29, 23), 5), ((96, 80, 72), 24), ((14, 12, 11, 10), 3),
                                      ((9, 8, 7, 8, 6), 2), ((1400, 20, 18), 12),
-                                     ((120, 20, 20, 20), 16)])
+                                     ((120, 20, 20, 20), 16), ((5, 4, 5, 4, 5, 4, 3), 2), ((4, 3, 4, 3, 4, 3, 4, 3), 2)])
 def test_als_sweeps_match_oracle(shape, R):
     """Six HOOI sweeps from the oracle's HOSVD: factors, core and every record field.
     W V = Y (Y^T V) runs in one chunked kernel while Y's chunk, V and Y_chunk^T V fit a
@@ -165,7 +166,8 @@ def test_als_sweeps_match_oracle(shape, R):
     assert_rel(r.core(), G_w, 1e-8, "core")
 
 
-@pytest.mark.parametrize("shape,R", [((60, 52, 47), 8), ((14, 12, 11, 10), 3), ((9, 8, 7, 8, 6), 2)])
+@pytest.mark.parametrize("shape,R", [((60, 52, 47), 8), ((14, 12, 11, 10), 3), ((9, 8, 7, 8, 6), 2),
+                                     ((5, 4, 5, 4, 5, 4, 3), 2), ((4, 3, 4, 3, 4, 3, 4, 3), 2)])
 def test_pp_operators_and_rhs_match_oracle(shape, R):
     """Build at the HOSVD factors, one PP-init sweep (which sets dA), then the
     first-order TTMc of every mode against the oracle's from the same dA."""
@@ -199,7 +201,9 @@ def test_pp_operators_and_rhs_match_oracle(shape, R):
 
 
 @pytest.mark.parametrize("shape,R,sweeps", [((48, 44, 40), 6, 14), ((120, 110, 100), 12, 12),
-                                            ((18, 16, 15, 14), 3, 12), ((9, 8, 9, 8, 9), 2, 12)])
+                                            ((18, 16, 15, 14), 3, 12), ((9, 8, 9, 8, 9), 2, 12),
+                                            ((5, 4, 5, 4, 5, 4, 3), 2, 12),
+                                            ((4, 3, 4, 3, 4, 3, 4, 3), 2, 12)])
 def test_pp_tucker_run_matches_oracle(shape, R, sweeps):
     """Algorithm 4 with eps = 0.3 (the paper's Tucker setting): the library's own
     decisions give the oracle's sweep-kind sequence, and the replayed path ends at the
