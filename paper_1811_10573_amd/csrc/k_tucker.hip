@@ -831,6 +831,69 @@ hipError_t launch_tucker_combine(const TuckerCombine& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// k_tucker_combine with each term's contraction done in place (small operators): G lanes
+// (a power of two <= 16, within one wave) take one output element; lane q sums the
+// contracted indices k = q, q + G, .. in increasing order, the G partial sums are added
+// by butterfly shuffles, and the terms are added to the base in term order.
+__global__ __launch_bounds__(256) void k_tucker_pp_rhs(TuckerPPRhs a, int G) {
+  const int64_t n = a.rows * a.cols;
+  const int64_t gt = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t e = gt / G;
+  const int q = (int)(gt - e * G);
+  const bool valid = e < n;
+  const int64_t ee = valid ? e : 0;
+  const int64_t x = ee / a.cols, c = ee - x * a.cols;
+  double v = (valid && a.base) ? a.base[ee] : 0.0;
+  for (int t = 0; t < a.nterms; ++t) {
+    const int64_t w = a.rpow[a.nd - 1 - a.pos[t]];  // weight of the contracted rank digit
+    const int64_t high = c / (w * a.R);
+    const int64_t rem = c - high * w * a.R;
+    const int64_t r = rem / w;
+    const int64_t rest = high * w + (rem - r * w);
+    const double* o = a.op[t] + x * a.nstride[t] + rest;
+    const double* f = a.F[t] + r;
+    const int64_t ks = a.kstride[t] * G, len = valid ? a.klen[t] : 0;
+    const int64_t fs = (int64_t)a.R * G;
+    o += q * a.kstride[t];
+    f += (int64_t)q * a.R;
+    double acc = 0.0;
+    int64_t k = q;
+    for (; k + 3 * G < len; k += 4 * G) {
+      const double o0 = o[0], o1 = o[ks], o2 = o[2 * ks], o3 = o[3 * ks];
+      const double f0 = f[0], f1 = f[fs], f2 = f[2 * fs], f3 = f[3 * fs];
+      acc = fma(o0, f0, acc);
+      acc = fma(o1, f1, acc);
+      acc = fma(o2, f2, acc);
+      acc = fma(o3, f3, acc);
+      o += 4 * ks;
+      f += 4 * fs;
+    }
+    for (; k < len; k += G) {
+      acc = fma(o[0], f[0], acc);
+      o += ks;
+      f += fs;
+    }
+    for (int off = G >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    v += acc;
+  }
+  if (valid && q == 0) a.out[ee] = v;
+}
+
+int pp_rhs_lanes(int64_t elems) {
+  int G = 1;
+  while (G < 16 && elems * G < 98304) G *= 2;
+  return G;
+}
+
+hipError_t launch_tucker_pp_rhs(const TuckerPPRhs& a, hipStream_t s) {
+  const int64_t n = a.rows * a.cols;
+  const int G = pp_rhs_lanes(n);
+  const int64_t blocks = (n * G + 255) / 256;
+  if (blocks < 1 || blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_tucker_pp_rhs, dim3((unsigned)blocks), dim3(256), 0, s, a, G);
+  return hipGetLastError();
+}
+
 // Norm statistics: out[0] = ||Gn||^2, out[1] = ||Gn - Go||^2 (one workgroup of 1024
 // threads, two elements per thread and step; a fixed reduction order).
 __global__ __launch_bounds__(1024) void k_core_stats(const double* Gn, const double* Go, int64_t n,

@@ -515,12 +515,66 @@ TuckerCombine combine_args(const tucker_plan* p, int n, double* out, const doubl
   return a;
 }
 
+// out = base + the terms Y_p^(i,n) x_i F_i^T (terms in list order, F_i an s_i x R matrix)
+// in one in-place launch when its multiply-adds stay below kPPRhsInPlaceMax (*done), else
+// nothing (the caller contracts term by term).
+ppals_status pp_rhs_in_place(const TCtx& c, int n, const int* is, const double* const* F, int nt,
+                             const double* base, double* out, bool* done) {
+  tucker_plan* p = c.p;
+  const int N = p->N;
+  const int64_t RN2 = p->rpow[N - 2], cols = p->rpow[N - 1];
+  int64_t work = 0;
+  for (int t = 0; t < nt; ++t) work += p->s[is[t]] * p->s[n] * cols;
+  *done = work <= kPPRhsInPlaceMax;
+  if (!*done || c.col) return PPALS_OK;
+  TuckerPPRhs a;
+  memset(&a, 0, sizeof(a));
+  a.out = out;
+  a.base = base;
+  a.nd = N - 1;
+  a.R = p->R;
+  a.rows = p->s[n];
+  a.cols = cols;
+  for (int k = 0; k <= TMAX; ++k) a.rpow[k] = p->rpow[k];
+  for (int t = 0; t < nt; ++t) {
+    const int i = is[t];
+    a.op[t] = c.d(p->o_op[std::min(i, n)][std::max(i, n)]);
+    a.F[t] = F[t];
+    a.klen[t] = p->s[i];
+    if (i < n) {  // operator (x_i, x_n, ..)
+      a.kstride[t] = p->s[n] * RN2;
+      a.nstride[t] = RN2;
+    } else {      // operator (x_n, x_i, ..)
+      a.kstride[t] = RN2;
+      a.nstride[t] = p->s[i] * RN2;
+    }
+    a.pos[t] = rank_pos(i, n);
+  }
+  a.nterms = nt;
+  THIPCHK(launch_tucker_pp_rhs(a, c.s));
+  return PPALS_OK;
+}
+
 // First-order PP TTMc of mode n into Y from the operators and dA (Section 3.2.2):
 // Y~^(n) = Y_p^(n) + sum_{i != n} Y_p^(i,n) x_i dA^(i)T; terms whose dA is still the zero
 // of the build are skipped.
 ppals_status pp_rhs_impl(const TCtx& c, int n, double* Y) {
   tucker_plan* p = c.p;
   const int N = p->N;
+  {
+    int is[TMAX];
+    const double* F[TMAX];
+    int nt = 0;
+    for (int i = 0; i < N; ++i) {
+      if (i == n || p->dA_zero[i]) continue;
+      is[nt] = i;
+      F[nt] = c.d(p->o_dA[i]);
+      ++nt;
+    }
+    bool done = false;
+    TCHK(pp_rhs_in_place(c, n, is, F, nt, c.d(p->o_Yp[n]), Y, &done));
+    if (done) return PPALS_OK;
+  }
   TuckerCombine a = combine_args(p, n, Y, c.d(p->o_Yp[n]));
   for (int i = 0; i < N; ++i) {
     if (i == n || p->dA_zero[i]) continue;
@@ -580,6 +634,9 @@ ppals_status build_impl(const TCtx& c, const double* X, double* const* A) {
   }
   for (int n = 0; n < N; ++n) {
     const int i = n == 0 ? 1 : 0;  // Y_p^(n) = Y_p^(0,n) x_0 A_p^(0)T (n = 0: Y_p^(0,1) x_1)
+    bool done = false;
+    TCHK(pp_rhs_in_place(c, n, &i, &Ap[i], 1, nullptr, c.d(p->o_Yp[n]), &done));
+    if (done) continue;
     TuckerCombine a = combine_args(p, n, c.d(p->o_Yp[n]), nullptr);
     double* T = c.d(p->o_term[0]);
     TCHK(ttm(c, c.d(p->o_op[std::min(i, n)][std::max(i, n)]), op_contr(p, i, n), Ap[i], T));

@@ -72,6 +72,29 @@ struct TuckerCombine {
   int64_t rpow[9];          // R^k
 };
 hipError_t launch_tucker_combine(const TuckerCombine& a, hipStream_t s);
+// The same sum with every term contracted in place: term t of output (x, c) is
+// sum_{k < klen[t]} op[t][x nstride[t] + rest + k kstride[t]] F[t][k R + r], where (rest, r)
+// is c with the rank digit at pos[t] taken out (r) and the others kept in order (rest).
+// For small operators, where one launch beats a contraction launch per term.  Each output
+// element takes pp_rhs_lanes(rows cols) lanes (1 to 16, at least 98304 lanes in all when
+// 16 per element reach it).
+struct TuckerPPRhs {
+  double* out;
+  const double* base;
+  const double* op[7];
+  const double* F[7];       // klen[t] x R
+  int64_t klen[7], kstride[7], nstride[7];
+  int pos[7];
+  int nterms;
+  int nd;
+  int R;
+  int64_t rows, cols;
+  int64_t rpow[9];
+};
+int pp_rhs_lanes(int64_t elems);
+hipError_t launch_tucker_pp_rhs(const TuckerPPRhs& a, hipStream_t s);
+// Total multiply-adds below which the in-place form is used.
+constexpr int64_t kPPRhsInPlaceMax = int64_t(1) << 25;
 hipError_t launch_core_stats(const double* Gn, const double* Go, int64_t n, double* out,
                              hipStream_t s);
 // End of a factor update: A = U (skipped when A is null), dA = U - Ap, and out[0], out[1] =

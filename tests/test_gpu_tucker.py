@@ -167,10 +167,14 @@ def test_als_sweeps_match_oracle(shape, R):
 
 
 @pytest.mark.parametrize("shape,R", [((60, 52, 47), 8), ((14, 12, 11, 10), 3), ((9, 8, 7, 8, 6), 2),
-                                     ((5, 4, 5, 4, 5, 4, 3), 2), ((4, 3, 4, 3, 4, 3, 4, 3), 2)])
+                                     ((5, 4, 5, 4, 5, 4, 3), 2), ((4, 3, 4, 3, 4, 3, 4, 3), 2),
+                                     ((13,) * 6, 6), ((330, 320, 310), 20)])
 def test_pp_operators_and_rhs_match_oracle(shape, R):
     """Build at the HOSVD factors, one PP-init sweep (which sets dA), then the
-    first-order TTMc of every mode against the oracle's from the same dA."""
+    first-order TTMc of every mode against the oracle's from the same dA.  Small
+    operators take the in-place sum of the terms (one launch; 2 to 16 lanes per output
+    element, one at 13^6, R = 6); 330 x 320 x 310 at R = 20 (about 8e7 multiply-adds per
+    mode) contracts term by term on the first-level kernel."""
     r = TRun(shape, R, seed=9, eta=0.2)
     A0, G0 = ot.hosvd(r.prob.X, r.ranks())
     A1, G1, _ = ot.tucker_als(r.prob.X, A0, G0, 1)
