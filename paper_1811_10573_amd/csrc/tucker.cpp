@@ -62,6 +62,7 @@ struct Lay {
 struct Collector {
   size_t prep = 1, part = 1024;  // elements of the operand and split-partial regions
   int64_t tmp = 1;               // largest intermediate of a contraction chain
+  int64_t lvl[8] = {1, 1, 1, 1, 1, 1, 1, 1};  // largest node of the operator tree per depth
 };
 
 }  // namespace
@@ -77,6 +78,7 @@ struct tucker_plan {
   // workspace regions (byte offsets)
   size_t o_pre[2], o_tmp[2];       // prefix chain and chain temporaries
   size_t o_F[3];                   // X x_c A_p^(c), c = 0, 1, 2 (operator build)
+  size_t o_lvl[8] = {0};           // operator tree: one node of each depth >= 2 at a time
   size_t o_op[TMAX][TMAX];         // Y_p^(i,n), i < n
   size_t o_Yp[TMAX], o_Y, o_term[TMAX], o_Gn;
   size_t o_Ap[TMAX], o_dA[TMAX], o_Astart[TMAX];
@@ -600,9 +602,50 @@ ppals_status pp_rhs_impl(const TCtx& c, int n, double* Y) {
   return PPALS_OK;
 }
 
+// Operator tree below a node T (layout L, d modes contracted): the operators in ops contract
+// the modes other than i and n in increasing order, and their first d are the node's.
+// Operators that contract the same next mode share that child node (in o_lvl[d + 1]);
+// children are made depth first, so one buffer per depth suffices (the tree of the PP
+// operators, Section 3.2.3).
+ppals_status build_subtree(const TCtx& c, const double* T, const Lay& L, int d,
+                           const std::vector<std::pair<int, int>>& ops, const double* const* Ap) {
+  tucker_plan* p = c.p;
+  const int N = p->N;
+  auto next_mode = [&](const std::pair<int, int>& o) {
+    int k = 0;
+    for (int m = 0; m < N; ++m)
+      if (m != o.first && m != o.second && k++ == d) return m;
+    return -1;
+  };
+  std::vector<int> done(ops.size(), 0);
+  for (size_t a = 0; a < ops.size(); ++a) {
+    if (done[a]) continue;
+    const int m = next_mode(ops[a]);
+    std::vector<std::pair<int, int>> group;
+    for (size_t b = a; b < ops.size(); ++b)
+      if (!done[b] && next_mode(ops[b]) == m) {
+        group.push_back(ops[b]);
+        done[b] = 1;
+      }
+    const Contr k = contr_of(p, L, m);
+    if (d + 1 == N - 2) {  // the operator itself (one per group: its modes are fixed)
+      const std::pair<int, int> o = group.front();
+      TCHK(ttm(c, T, k, Ap[m], c.d(p->o_op[o.first][o.second])));
+      continue;
+    }
+    const Lay Lc = lay_after(L, m);
+    if (c.col) c.col->lvl[d + 1] = std::max(c.col->lvl[d + 1], numel(p, Lc));
+    double* child = c.d(p->o_lvl[d + 1]);
+    TCHK(ttm(c, T, k, Ap[m], child));
+    TCHK(build_subtree(c, child, Lc, d + 1, group, Ap));
+  }
+  return PPALS_OK;
+}
+
 // PP operator build (Algorithm 4): with A_p = A, Y_p^(i,n) for every pair i < n, the other
 // modes contracted in increasing order; the first of them is 0, 1 or 2, so three passes
-// over X (F_c = X x_c A_p^(c)T) serve every operator.  Y_p^(n) from an operator.
+// over X (F_c = X x_c A_p^(c)T) serve every operator, and the later contractions follow
+// the operator tree (build_subtree).  Y_p^(n) from an operator.
 ppals_status build_impl(const TCtx& c, const double* X, double* const* A) {
   tucker_plan* p = c.p;
   const int N = p->N;
@@ -617,20 +660,21 @@ ppals_status build_impl(const TCtx& c, const double* X, double* const* A) {
   for (int c0 = 0; c0 < 3; ++c0) {
     const Lay L = lay_all(p);
     TCHK(ttm(c, X, contr_of(p, L, c0), Ap[c0], c.d(p->o_F[c0])));
+    std::vector<std::pair<int, int>> ops;
     for (int i = 0; i < N; ++i)
       for (int n = i + 1; n < N; ++n) {
-        std::vector<int> ms;
-        for (int m = 0; m < N; ++m)
-          if (m != i && m != n) ms.push_back(m);
-        if (ms.front() != c0) continue;
-        ms.erase(ms.begin());
-        double* op = c.d(p->o_op[i][n]);
-        if (ms.empty()) {
-          if (!c.col) THIPCHK(launch_copy(op, c.d(p->o_F[c0]), p->s[i] * p->s[n] * p->R, c.s));
-        } else {
-          TCHK(chain(c, c.d(p->o_F[c0]), lay_after(L, c0), ms, Ap, op));
-        }
+        int first = 0;
+        while (first == i || first == n) ++first;
+        if (first == c0) ops.push_back({i, n});
       }
+    if (N == 3) {  // the operator is F_c itself
+      for (const auto& o : ops)
+        if (!c.col)
+          THIPCHK(launch_copy(c.d(p->o_op[o.first][o.second]), c.d(p->o_F[c0]),
+                              p->s[o.first] * p->s[o.second] * p->R, c.s));
+      continue;
+    }
+    TCHK(build_subtree(c, c.d(p->o_F[c0]), lay_after(L, c0), 1, ops, Ap));
   }
   for (int n = 0; n < N; ++n) {
     const int i = n == 0 ? 1 : 0;  // Y_p^(n) = Y_p^(0,n) x_0 A_p^(0)T (n = 0: Y_p^(0,1) x_1)
@@ -773,6 +817,7 @@ ppals_status tucker_plan_create(int32_t order, const int64_t* dims, int32_t rank
   for (int k = 0; k < 2; ++k) p->o_pre[k] = take(pre);
   for (int k = 0; k < 2; ++k) p->o_tmp[k] = take(col.tmp);
   for (int c0 = 0; c0 < 3; ++c0) p->o_F[c0] = take(numel(p, lay_after(lay_all(p), c0)));
+  for (int d = 0; d < 8; ++d) p->o_lvl[d] = d >= 2 && d <= N - 3 ? take(col.lvl[d]) : 0;
   for (int i = 0; i < N; ++i)
     for (int n = i + 1; n < N; ++n) p->o_op[i][n] = take(dims[i] * dims[n] * p->rpow[N - 2]);
   for (int n = 0; n < N; ++n) p->o_Yp[n] = take(dims[n] * p->rpow[N - 1]);
