@@ -997,7 +997,7 @@ constexpr int64_t kWApplyChunks = 32;
 
 int w_apply_width(int64_t s, int64_t m, int R) {
   if (R < 1 || R > 64 || s < 1 || m < 1) return 0;
-  const int64_t free_ = WA_LDS - 256 - s * R;
+  const int64_t free_ = WA_LDS - 256 - s * R - s;  // the chunk's rows are padded by one
   if (free_ <= 0) return 0;
   int64_t w = free_ / (s + R);
   w = std::min<int64_t>(w, 4096 / R);  // Z entries: at most 16 per thread
@@ -1014,8 +1014,9 @@ __global__ __launch_bounds__(256) void k_w_apply(const double* __restrict__ Y,
   const int tid = threadIdx.x;
   const int64_t j0 = (int64_t)blockIdx.x * w;
   const int wc = (int)(m - j0 < w ? m - j0 : w);
-  double* Ys = sm;           // s x wc
-  double* Vs = Ys + s * w;   // s x R
+  const int ld = wc | 1;           // odd row stride: the rows of one column in different banks
+  double* Ys = sm;                 // s x wc, row stride ld
+  double* Vs = Ys + s * (w + 1);   // s x R
   double* Zs = Vs + s * R;   // wc x R
   double* red = Zs + w * R;
   const int ny = s * wc;  // < 2^15 (LDS)
@@ -1030,7 +1031,10 @@ __global__ __launch_bounds__(256) void k_w_apply(const double* __restrict__ Y,
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int e = e0 + 256 * q;
-      if (e < ny) Ys[e] = v[q];
+      if (e < ny) {
+        const int x = e / wc;
+        Ys[x * ld + (e - x * wc)] = v[q];
+      }
     }
   }
   stage_rows(Vs, V, s * R);
@@ -1054,13 +1058,13 @@ __global__ __launch_bounds__(256) void k_w_apply(const double* __restrict__ Y,
         double yv[4], vv[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          yv[q] = Ys[(x + q * G) * wc + j];
+          yv[q] = Ys[(x + q * G) * ld + j];
           vv[q] = Vs[(x + q * G) * R + r];
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) sum = fma(yv[q], vv[q], sum);
       }
-      for (; x < s; x += G) sum = fma(Ys[x * wc + j], Vs[x * R + r], sum);
+      for (; x < s; x += G) sum = fma(Ys[x * ld + j], Vs[x * R + r], sum);
       acc[u] = sum;
     }
   }
@@ -1084,7 +1088,7 @@ __global__ __launch_bounds__(256) void k_w_apply(const double* __restrict__ Y,
   for (int e = tid; e < s * R; e += 256) {
     const int x = e / R;
     const int r = e - x * R;
-    const double* yr = Ys + x * wc;
+    const double* yr = Ys + x * ld;
     double c = 0.0;
 #pragma unroll 8
     for (int j = 0; j < wc; ++j) c = fma(yr[j], Zs[j * R + r], c);
@@ -1096,7 +1100,7 @@ hipError_t launch_w_apply_parts(const double* Y, const double* V, int64_t s, int
                                 int w, double* part, hipStream_t st) {
   if (w < 1 || w != w_apply_width(s, m, R)) return hipErrorInvalidValue;
   const int64_t nchunk = (m + w - 1) / w;
-  const size_t lds = (size_t)(s * w + s * R + (int64_t)w * R + 256) * sizeof(double);
+  const size_t lds = (size_t)(s * (w + 1) + s * R + (int64_t)w * R + 256) * sizeof(double);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_w_apply),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

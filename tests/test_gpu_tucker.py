@@ -107,10 +107,12 @@ def test_factor_update_matches_eigh(shape, R):
 
 @pytest.mark.parametrize("shape,R", [((41, 33, 27), 4), ((90, 84, 70), 20), ((14, 12, 11, 10), 3),
                                      ((9, 8, 7, 8, 6), 3), ((5, 4, 5, 4, 5, 4, 3), 2),
-                                     ((4, 3, 4, 3, 4, 3, 4, 3), 2)])
+                                     ((4, 3, 4, 3, 4, 3, 4, 3), 2), ((600, 20, 18), 4),
+                                     ((20, 600, 18), 4)])
 def test_hosvd_matches_oracle(shape, R):
     """HOSVD from random starting bases: factors (largest-magnitude entry positive) and
-    core against the oracle's eigh-based HOSVD."""
+    core against the oracle's eigh-based HOSVD (the first, inner and last modes' products,
+    the inner one on the strided first-level kernel; 600-row modes split k)."""
     r = TRun(shape, R, seed=5)
     A_want, G_want = ot.hosvd(r.prob.X, r.ranks())
     V0 = [to_dev(v) for v in tensorgen.subspace_start(shape, R, seed=6)]
@@ -123,7 +125,8 @@ def test_hosvd_matches_oracle(shape, R):
 
 
 @pytest.mark.parametrize("shape,R", [((41, 33, 27), 4), ((90, 84, 70), 20), ((14, 12, 11, 10), 3),
-                                     ((9, 8, 7, 8, 6), 3), ((6, 5, 6, 5, 6, 5), 2), ((5, 4, 5, 4, 5, 4, 3), 2), ((4, 3, 4, 3, 4, 3, 4, 3), 2)])
+                                     ((9, 8, 7, 8, 6), 3), ((6, 5, 6, 5, 6, 5), 2), ((5, 4, 5, 4, 5, 4, 3), 2), ((4, 3, 4, 3, 4, 3, 4, 3), 2),
+                                     ((600, 20, 18), 4)])
 def test_interlaced_hosvd_matches_oracle(shape, R):
     """Interlaced HOSVD (each factor from the prefix Z^(n) = X x_0 A^(0)T .. x_(n-1)
     A^(n-1)T, whose first mode is n) against the oracle's."""
