@@ -108,7 +108,7 @@ def test_factor_update_matches_eigh(shape, R):
 @pytest.mark.parametrize("shape,R", [((41, 33, 27), 4), ((90, 84, 70), 20), ((14, 12, 11, 10), 3),
                                      ((9, 8, 7, 8, 6), 3), ((5, 4, 5, 4, 5, 4, 3), 2),
                                      ((4, 3, 4, 3, 4, 3, 4, 3), 2), ((600, 20, 18), 4),
-                                     ((20, 600, 18), 4)])
+                                     ((20, 600, 18), 4), ((20, 18, 16), 1)])
 def test_hosvd_matches_oracle(shape, R):
     """HOSVD from random starting bases: factors (largest-magnitude entry positive) and
     core against the oracle's eigh-based HOSVD (the first, inner and last modes' products,
@@ -210,7 +210,8 @@ def test_pp_operators_and_rhs_match_oracle(shape, R):
 @pytest.mark.parametrize("shape,R,sweeps", [((48, 44, 40), 6, 14), ((120, 110, 100), 12, 12),
                                             ((18, 16, 15, 14), 3, 12), ((9, 8, 9, 8, 9), 2, 12),
                                             ((5, 4, 5, 4, 5, 4, 3), 2, 12),
-                                            ((4, 3, 4, 3, 4, 3, 4, 3), 2, 12)])
+                                            ((4, 3, 4, 3, 4, 3, 4, 3), 2, 12),
+                                            ((20, 18, 16), 1, 8), ((9, 8, 7, 8), 1, 8)])
 def test_pp_tucker_run_matches_oracle(shape, R, sweeps):
     """Algorithm 4 with eps = 0.3 (the paper's Tucker setting): the library's own
     decisions give the oracle's sweep-kind sequence, and the replayed path ends at the
