@@ -1135,4 +1135,108 @@ hipError_t launch_copy2(double* out1, double* out2, const double* in, int64_t n,
   return hipGetLastError();
 }
 
+// First-level contraction at rank R <= 8 on the vector units.  The matrix-core kernel pads
+// the rank to a 16-column block and the contracted extent to 32-step chunks, so at R = 5
+// over K = 35 it issues 5.9 times the useful multiply-adds (on this chip the FP64 matrix
+// cores and the FP64 vector units have the same peak), and at an odd Q it cannot pair rows
+// into 16-byte loads.  Here each thread owns TTM_RPT rows m = p Q + q spaced by
+// the workgroup width (the lanes of a wave read 64 consecutive q: one 512-byte run per load
+// instruction, across slices too), walks k in steps of TTM_KU with the next step's loads
+// issued before the current step's multiply-adds (the last step reloads itself: the loads
+// are unconditional, so their completion can be counted), and adds the k terms of a row in
+// increasing k.  The first step takes K mod TTM_KU entries (all TTM_KU when it divides K).
+// F's entries are the same for every lane.
+constexpr int TTM_RPT = 4, TTM_KU = 4, TTM_THREADS = 256;
+constexpr int64_t TTM_ROWS_PER_BLOCK = (int64_t)TTM_RPT * TTM_THREADS;
+
+template <int RT>
+__global__ __launch_bounds__(TTM_THREADS) void k_ttm_small_r(const double* __restrict__ T,
+                                                             const double* __restrict__ F,
+                                                             int64_t M, int64_t K, int64_t Q,
+                                                             double* __restrict__ C) {
+  const int64_t m0 = (int64_t)blockIdx.x * TTM_ROWS_PER_BLOCK + threadIdx.x;
+  int64_t base[TTM_RPT];
+#pragma unroll
+  for (int j = 0; j < TTM_RPT; ++j) {
+    const int64_t m = m0 + (int64_t)j * TTM_THREADS;
+    const int64_t mm = m < M ? m : M - 1;  // rows past M read row M - 1 and store nothing
+    const int64_t p = mm / Q, q = mm - p * Q;
+    base[j] = p * K * Q + q;
+  }
+  const int64_t kr = K % TTM_KU;
+  const int64_t nsteps = K / TTM_KU + (kr > 0 ? 1 : 0);
+  auto kb_of = [&](int64_t t) -> int64_t {
+    return kr > 0 ? (t == 0 ? 0 : kr + (t - 1) * TTM_KU) : t * TTM_KU;
+  };
+  auto nu_of = [&](int64_t t) -> int { return (kr > 0 && t == 0) ? (int)kr : TTM_KU; };
+  auto load = [&](double (&x)[TTM_KU][TTM_RPT], int64_t t) {
+    const int64_t kb = kb_of(t);
+    const int nu = nu_of(t);
+#pragma unroll
+    for (int u = 0; u < TTM_KU; ++u) {
+      const int64_t off = (kb + (u < nu ? u : 0)) * Q;
+#pragma unroll
+      for (int j = 0; j < TTM_RPT; ++j) x[u][j] = T[base[j] + off];
+    }
+  };
+  double acc[TTM_RPT][RT];
+#pragma unroll
+  for (int j = 0; j < TTM_RPT; ++j)
+#pragma unroll
+    for (int r = 0; r < RT; ++r) acc[j][r] = 0.0;
+  double xc[TTM_KU][TTM_RPT], xn[TTM_KU][TTM_RPT];
+  load(xc, 0);
+  for (int64_t t = 0; t < nsteps; ++t) {
+    load(xn, t + 1 < nsteps ? t + 1 : t);
+    const int64_t kb = kb_of(t);
+    const int nu = nu_of(t);
+#pragma unroll
+    for (int u = 0; u < TTM_KU; ++u) {
+      if (u < nu) {
+        const double* f = F + (kb + u) * RT;
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+          const double fr = f[r];
+#pragma unroll
+          for (int j = 0; j < TTM_RPT; ++j) acc[j][r] = fma(xc[u][j], fr, acc[j][r]);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < TTM_KU; ++u)
+#pragma unroll
+      for (int j = 0; j < TTM_RPT; ++j) xc[u][j] = xn[u][j];
+  }
+#pragma unroll
+  for (int j = 0; j < TTM_RPT; ++j) {
+    const int64_t m = m0 + (int64_t)j * TTM_THREADS;
+    if (m < M) {
+#pragma unroll
+      for (int r = 0; r < RT; ++r) C[m * RT + r] = acc[j][r];
+    }
+  }
+}
+
+// Odd Q > 1 (an even Q gives the matrix-core kernel its 16-byte loads, and there the two
+// measured within 2% of each other; Q > 1 keeps the lanes' loads consecutive) and rows
+// for at least 1024 workgroups (the kernel does not split K).
+bool ttm_small_r_fits(int64_t M, int64_t K, int64_t Q, int R) {
+  return R >= 1 && R <= 8 && K >= 1 && Q > 1 && (Q & 1) == 1 &&
+         M >= 1024 * TTM_ROWS_PER_BLOCK && M / TTM_ROWS_PER_BLOCK < (int64_t(1) << 31);
+}
+
+hipError_t launch_ttm_small_r(const double* T, const double* F, int64_t M, int64_t K, int64_t Q,
+                              int R, double* C, hipStream_t s) {
+  if (!ttm_small_r_fits(M, K, Q, R) || M % Q != 0) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((M + TTM_ROWS_PER_BLOCK - 1) / TTM_ROWS_PER_BLOCK)), block(TTM_THREADS);
+  switch (R) {
+#define PPK_TTM_CASE(RV) \
+  case RV: hipLaunchKernelGGL(k_ttm_small_r<RV>, grid, block, 0, s, T, F, M, K, Q, C); break;
+    PPK_TTM_CASE(1) PPK_TTM_CASE(2) PPK_TTM_CASE(3) PPK_TTM_CASE(4)
+    PPK_TTM_CASE(5) PPK_TTM_CASE(6) PPK_TTM_CASE(7) PPK_TTM_CASE(8)
+#undef PPK_TTM_CASE
+  }
+  return hipGetLastError();
+}
+
 }  // namespace ppk

@@ -146,6 +146,10 @@ ppals_status ttm_geom(const TCtx& c, const double* T, const Level1Geom& g, const
     c.col->part = std::max(c.col->part, part_elems(g));
     return PPALS_OK;
   }
+  if (!g.strided && ttm_small_r_fits(g.M, g.K, g.Q, c.p->R)) {
+    THIPCHK(launch_ttm_small_r(T, F, g.M, g.K, g.Q, c.p->R, out, c.s));
+    return PPALS_OK;
+  }
   KrpDesc krp;
   memset(&krp, 0, sizeof(krp));
   krp.nf = 1;

@@ -114,6 +114,13 @@ hipError_t launch_w_apply_parts(const double* Y, const double* V, int64_t s, int
                                 int w, double* part, hipStream_t st);
 // out1 = out2 = in (n doubles)
 hipError_t launch_copy2(double* out1, double* out2, const double* in, int64_t n, hipStream_t s);
+// First-level contraction at small rank on the vector units: C (M x R, row-major) with
+// C[p Q + q][r] = sum_k T[(p K + k) Q + q] F[k R + r] (T of P x K x Q, Q > 1; F of K x R,
+// row-major).  ttm_small_r_fits says when it is used in place of the matrix-core kernel
+// (R <= 8, odd Q > 1, M >= 2^20).
+bool ttm_small_r_fits(int64_t M, int64_t K, int64_t Q, int R);
+hipError_t launch_ttm_small_r(const double* T, const double* F, int64_t M, int64_t K, int64_t Q,
+                              int R, double* C, hipStream_t s);
 
 }  // namespace ppk
 

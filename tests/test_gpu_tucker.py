@@ -237,6 +237,55 @@ def test_pp_tucker_run_matches_oracle(shape, R, sweeps):
         np.testing.assert_allclose(got, want, atol=1e-8, rtol=0, err_msg=f"replay A^({n})")
 
 
+@pytest.mark.parametrize("shape,R", [((16, 1031, 1021), 5), ((11, 13, 97, 1001), 3),
+                                     ((12, 1101, 999), 8)])
+def test_small_rank_vector_contractions_match_oracle(shape, R):
+    """Contractions of more than 2^20 rows over an odd trailing extent at R <= 8 run on the
+    vector-unit kernel: the prefix X x_0 A^(0)T at every size (K = 16, 11, 12: steps of 4
+    with remainders 0, 3, 0) and at order 4 the first step of mode 0's chain, X x_1
+    A^(1)T (K = 13, remainder 1; 11 slices of an odd trailing extent 97097, so a wave's
+    rows cross slices); no row count is a multiple of the 1024 rows of a workgroup.  TTMc
+    of every mode, two HOOI sweeps, the interlaced HOSVD and a PP-Tucker run (eps = 0.3)
+    against the oracle."""
+    r = TRun(shape, R, seed=17, eta=0.05)
+    rng = np.random.default_rng(18)
+    A = [np.linalg.qr(rng.standard_normal((s, R)))[0] for s in shape]
+    r.upload(A, r.zero_core())
+    for n in range(r.N):
+        Y = to_dev(r.zero_y(n))
+        pk.tucker_ttmc(r.plan, r.ws, r.X, r.A, n, Y)
+        want = lib_layout(ot.ttmc(r.prob.X, A, n), n)
+        assert_rel(host(Y, want.shape), want, 1e-12, f"Y^({n})")
+    A0, G0 = ot.hosvd(r.prob.X, r.ranks())
+    A_w, G_w, recs_w = ot.tucker_als(r.prob.X, A0, G0, 2)
+    r.upload(A0, G0)
+    for k in range(2):
+        rec = pk.tucker_als_sweep(r.plan, r.ws, r.X, r.A, r.G, r.normX2)
+        assert abs(rec["fit"] - recs_w[k].fit) <= 1e-10, (k, rec["fit"], recs_w[k].fit)
+    for n, (got, want) in enumerate(zip(r.factors(), A_w)):
+        np.testing.assert_allclose(got, want, atol=1e-8, rtol=0, err_msg=f"HOOI A^({n})")
+    assert_rel(r.core(), G_w, 1e-8, "HOOI core")
+    A_i, G_i = ot.hosvd_interlaced(r.prob.X, r.ranks())
+    V0 = [to_dev(v) for v in tensorgen.subspace_start(shape, R, seed=19)]
+    r.upload([np.zeros_like(a) for a in A_i], r.zero_core())
+    info = pk.tucker_hosvd_interlaced(r.plan, r.ws, r.X, V0, r.A, r.G)
+    assert all(i[1] == 1 and i[2] == 0 for i in info), info
+    for n, (got, want) in enumerate(zip(r.factors(), A_i)):
+        np.testing.assert_allclose(got, want, atol=1e-8, rtol=0, err_msg=f"HOSVD A^({n})")
+    assert_rel(r.core(), G_i, 1e-8, "HOSVD core")
+    A_p, G_p, recs_p = ot.pp_tucker_als(r.prob.X, A0, G0, eps=0.3, sweeps=8)
+    kinds = [w.kind for w in recs_p]
+    assert "pp_approx" in kinds
+    r.upload(A0, G0)
+    recs = pk.tucker_run(r.plan, r.ws, r.X, r.A, r.G, eps=0.3, sweeps=8)
+    assert [x["kind"] for x in recs] == kinds
+    for x, w in zip(recs, recs_p):
+        assert abs(x["fit"] - w.fit) <= 1e-10, (x, w.fit)
+    for n, (got, want) in enumerate(zip(r.factors(), A_p)):
+        np.testing.assert_allclose(got, want, atol=1e-8, rtol=0, err_msg=f"PP A^({n})")
+    assert_rel(r.core(), G_p, 1e-8, "PP core")
+
+
 def test_eps_zero_is_hooi():
     shape, R = (40, 38, 36), 5
     r = TRun(shape, R, seed=13, eta=0.1)
