@@ -150,6 +150,14 @@ ppals_status ttm_geom(const TCtx& c, const double* T, const Level1Geom& g, const
     THIPCHK(launch_ttm_small_r(T, F, g.M, g.K, g.Q, c.p->R, out, c.s));
     return PPALS_OK;
   }
+  // the part region holds ksplit x M x R doubles (sized from this geometry)
+  const int nparts = !g.strided && g.Q == 1 && g.ksplit > 1
+                         ? ttm_rows_small_r_parts(g.M, g.K, c.p->R, g.ksplit) : 0;
+  if (nparts > 0) {
+    THIPCHK(launch_ttm_rows_small_r(T, F, g.M, g.K, c.p->R, nparts,
+                                    reinterpret_cast<double*>(c.ws + c.p->o_part), out, c.s));
+    return PPALS_OK;
+  }
   KrpDesc krp;
   memset(&krp, 0, sizeof(krp));
   krp.nf = 1;

@@ -244,9 +244,11 @@ def test_small_rank_vector_contractions_match_oracle(shape, R):
     vector-unit kernel: the prefix X x_0 A^(0)T at every size (K = 16, 11, 12: steps of 4
     with remainders 0, 3, 0) and at order 4 the first step of mode 0's chain, X x_1
     A^(1)T (K = 13, remainder 1; 11 slices of an odd trailing extent 97097, so a wave's
-    rows cross slices); no row count is a multiple of the 1024 rows of a workgroup.  TTMc
-    of every mode, two HOOI sweeps, the interlaced HOSVD and a PP-Tucker run (eps = 0.3)
-    against the oracle."""
+    rows cross slices); no row count is a multiple of the 1024 rows of a workgroup.  The
+    HOSVDs' product X_(0) Z (16, 11 and 12 rows of more than 2^20 contiguous k) runs on the
+    rows kernel (k split over workgroups, the parts added in order).  TTMc of every mode,
+    two HOOI sweeps, the classical and the interlaced HOSVD and a PP-Tucker run
+    (eps = 0.3) against the oracle."""
     r = TRun(shape, R, seed=17, eta=0.05)
     rng = np.random.default_rng(18)
     A = [np.linalg.qr(rng.standard_normal((s, R)))[0] for s in shape]
@@ -265,6 +267,13 @@ def test_small_rank_vector_contractions_match_oracle(shape, R):
     for n, (got, want) in enumerate(zip(r.factors(), A_w)):
         np.testing.assert_allclose(got, want, atol=1e-8, rtol=0, err_msg=f"HOOI A^({n})")
     assert_rel(r.core(), G_w, 1e-8, "HOOI core")
+    V0 = [to_dev(v) for v in tensorgen.subspace_start(shape, R, seed=19)]
+    r.upload([np.zeros_like(a) for a in A0], r.zero_core())
+    info = pk.tucker_hosvd(r.plan, r.ws, r.X, V0, r.A, r.G)
+    assert all(i[1] == 1 and i[2] == 0 for i in info), info
+    for n, (got, want) in enumerate(zip(r.factors(), A0)):
+        np.testing.assert_allclose(got, want, atol=1e-8, rtol=0, err_msg=f"classical HOSVD A^({n})")
+    assert_rel(r.core(), G0, 1e-8, "classical HOSVD core")
     A_i, G_i = ot.hosvd_interlaced(r.prob.X, r.ranks())
     V0 = [to_dev(v) for v in tensorgen.subspace_start(shape, R, seed=19)]
     r.upload([np.zeros_like(a) for a in A_i], r.zero_core())
