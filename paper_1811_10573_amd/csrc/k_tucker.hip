@@ -1239,14 +1239,17 @@ hipError_t launch_ttm_small_r(const double* T, const double* F, int64_t M, int64
   return hipGetLastError();
 }
 
-// The same contraction when the contracted index is the contiguous one (Q = 1) and the
-// rows are few (the HOSVD's C = X_(n) Z with n first: M = s_n rows of length K = the
-// product of the other sizes).  The matrix-core kernel pads M to 128-row tiles and R to
-// 16 columns there (11.7 times the useful multiply-adds at M = 35, R = 5).  Here workgroup
+// The same contraction for a few rows over a long k (the HOSVD's C = X_(n) Z: M = s_n
+// rows, K = the product of the other sizes, k = c_before * after + c_after with `after`
+// the product of the sizes after n, so T[m][k] sits at (k / after) M after + m after +
+// k mod after; after = K when n is first).  The matrix-core kernel pads M to 128-row
+// tiles and R to 16 columns there (11.7 times the useful multiply-adds at M = 35, R = 5).
+// Here workgroup
 // z takes k in [z kper, (z + 1) kper), in blocks of TR_THREADS TR_KPT: thread t holds F's
 // rows k = k0 + t + TR_THREADS i (i < TR_KPT) in registers and, row by row, loads
 // T[m][k] for them (consecutive lanes on consecutive k: one 512-byte run per load
-// instruction), the next row's loads issued before this row's multiply-adds; the R
+// instruction while k mod after runs on), the next row's loads issued before this row's
+// multiply-adds; the R
 // per-lane sums of a row are added across the wave by a butterfly and wave w's lane 0
 // adds them to its own LDS slot [w][m][r].  At the end the slots are added in wave order
 // into part[z] (M x R); a second launch adds the workgroups' parts in z order.  k past
@@ -1257,7 +1260,8 @@ constexpr int64_t TR_KBLOCK = (int64_t)TR_THREADS * TR_KPT;
 template <int RT>
 __global__ __launch_bounds__(TR_THREADS) void k_ttm_rows_small_r(const double* __restrict__ T,
                                                                  const double* __restrict__ F,
-                                                                 int M, int64_t K, int64_t kper,
+                                                                 int M, int64_t K, int64_t after,
+                                                                 int64_t kper,
                                                                  double* __restrict__ part) {
   extern __shared__ double slot[];  // [TR_WAVES][M][RT]
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
@@ -1266,26 +1270,28 @@ __global__ __launch_bounds__(TR_THREADS) void k_ttm_rows_small_r(const double* _
   const int64_t kb = (int64_t)blockIdx.x * kper;
   const int64_t ke = kb + kper < K ? kb + kper : K;
   for (int64_t k0 = kb; k0 < ke; k0 += TR_KBLOCK) {
-    int64_t kk[TR_KPT];
+    int64_t koff[TR_KPT];  // offset of T[0][k]
     double z[TR_KPT][RT];
 #pragma unroll
     for (int i = 0; i < TR_KPT; ++i) {
       const int64_t k = k0 + tid + (int64_t)TR_THREADS * i;
       const bool ok = k < ke;
-      kk[i] = ok ? k : ke - 1;
+      const int64_t kc = ok ? k : ke - 1;
+      const int64_t hi = kc / after;
+      koff[i] = hi * M * after + (kc - hi * after);
 #pragma unroll
       for (int r = 0; r < RT; ++r) {
-        const double f = F[kk[i] * RT + r];
+        const double f = F[kc * RT + r];
         z[i][r] = ok ? f : 0.0;
       }
     }
     double xc[TR_KPT], xn[TR_KPT];
 #pragma unroll
-    for (int i = 0; i < TR_KPT; ++i) xc[i] = T[kk[i]];
+    for (int i = 0; i < TR_KPT; ++i) xc[i] = T[koff[i]];
     for (int m = 0; m < M; ++m) {
-      const int64_t mn = (m + 1 < M ? m + 1 : m) * K;
+      const int64_t mn = (m + 1 < M ? m + 1 : m) * after;
 #pragma unroll
-      for (int i = 0; i < TR_KPT; ++i) xn[i] = T[mn + kk[i]];
+      for (int i = 0; i < TR_KPT; ++i) xn[i] = T[mn + koff[i]];
       double a[RT];
 #pragma unroll
       for (int r = 0; r < RT; ++r) a[r] = 0.0;
@@ -1324,9 +1330,11 @@ int ttm_rows_small_r_parts(int64_t M, int64_t K, int R, int max_parts) {
   return (int)((K + kper - 1) / kper);
 }
 
-hipError_t launch_ttm_rows_small_r(const double* T, const double* F, int64_t M, int64_t K, int R,
-                                   int nparts, double* part, double* C, hipStream_t s) {
-  if (nparts < 1 || R < 1 || R > 8 || M < 1 || M * R > 2048) return hipErrorInvalidValue;
+hipError_t launch_ttm_rows_small_r(const double* T, const double* F, int64_t M, int64_t K,
+                                   int64_t after, int R, int nparts, double* part, double* C,
+                                   hipStream_t s) {
+  if (nparts < 1 || R < 1 || R > 8 || M < 1 || M * R > 2048 || after < 1 || K % after != 0)
+    return hipErrorInvalidValue;
   const int64_t kper = ((K + nparts - 1) / nparts + TR_KBLOCK - 1) / TR_KBLOCK * TR_KBLOCK;
   const int nz = (int)((K + kper - 1) / kper);
   if (nz > nparts) return hipErrorInvalidValue;
@@ -1335,7 +1343,7 @@ hipError_t launch_ttm_rows_small_r(const double* T, const double* F, int64_t M, 
 #define PPK_TR_CASE(RV)                                                                       \
   case RV:                                                                                    \
     hipLaunchKernelGGL(k_ttm_rows_small_r<RV>, dim3((unsigned)nz), dim3(TR_THREADS), lds, s, T, \
-                       F, (int)M, K, kper, part);                                             \
+                       F, (int)M, K, after, kper, part);                                      \
     break;
     PPK_TR_CASE(1) PPK_TR_CASE(2) PPK_TR_CASE(3) PPK_TR_CASE(4)
     PPK_TR_CASE(5) PPK_TR_CASE(6) PPK_TR_CASE(7) PPK_TR_CASE(8)

@@ -150,11 +150,17 @@ ppals_status ttm_geom(const TCtx& c, const double* T, const Level1Geom& g, const
     THIPCHK(launch_ttm_small_r(T, F, g.M, g.K, g.Q, c.p->R, out, c.s));
     return PPALS_OK;
   }
-  // the part region holds ksplit x M x R doubles (sized from this geometry)
-  const int nparts = !g.strided && g.Q == 1 && g.ksplit > 1
+  // Few rows over a long k: rows contiguous (Q = 1), or the inner-mode unfolding of
+  // inner_unfolding_geom (row stride `after` = ms1, k = c_before after + c_after).  The
+  // part region holds ksplit x M x R doubles (sized from this geometry).
+  const bool inner = g.strided && g.ms0 == 0 && g.ms2 == 0 && g.mrad2 == 1 && g.ks1 == 0 &&
+                     g.ks2 == 1 && g.ms1 >= 1 && g.ks0 == g.M * g.ms1 && g.kr1 == 1 &&
+                     (int64_t)g.kr2 == g.ms1;
+  const int64_t after = inner ? g.ms1 : g.K;
+  const int nparts = (inner || (!g.strided && g.Q == 1)) && g.ksplit > 1
                          ? ttm_rows_small_r_parts(g.M, g.K, c.p->R, g.ksplit) : 0;
   if (nparts > 0) {
-    THIPCHK(launch_ttm_rows_small_r(T, F, g.M, g.K, c.p->R, nparts,
+    THIPCHK(launch_ttm_rows_small_r(T, F, g.M, g.K, after, c.p->R, nparts,
                                     reinterpret_cast<double*>(c.ws + c.p->o_part), out, c.s));
     return PPALS_OK;
   }

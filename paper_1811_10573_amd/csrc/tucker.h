@@ -121,13 +121,15 @@ hipError_t launch_copy2(double* out1, double* out2, const double* in, int64_t n,
 bool ttm_small_r_fits(int64_t M, int64_t K, int64_t Q, int R);
 hipError_t launch_ttm_small_r(const double* T, const double* F, int64_t M, int64_t K, int64_t Q,
                               int R, double* C, hipStream_t s);
-// The same with Q = 1 and few rows: C[m][r] = sum_k T[m K + k] F[k R + r], k split over
-// workgroups whose M x R parts go to part and are added in order by a second launch.
-// ttm_rows_small_r_parts gives the number of parts (at most max_parts), or 0 when the
-// kernel does not apply (R <= 8, M R <= 2048, K >= 2^20, max_parts >= 256).
+// The same for few rows over a long k: C[m][r] = sum_k T[(k / after) M after + m after +
+// k mod after] F[k R + r] (after = K: rows contiguous; K a multiple of after), k split
+// over workgroups whose M x R parts go to part and are added in order by a second
+// launch.  ttm_rows_small_r_parts gives the number of parts (at most max_parts), or 0
+// when the kernel does not apply (R <= 8, M R <= 2048, K >= 2^20, max_parts >= 256).
 int ttm_rows_small_r_parts(int64_t M, int64_t K, int R, int max_parts);
-hipError_t launch_ttm_rows_small_r(const double* T, const double* F, int64_t M, int64_t K, int R,
-                                   int nparts, double* part, double* C, hipStream_t s);
+hipError_t launch_ttm_rows_small_r(const double* T, const double* F, int64_t M, int64_t K,
+                                   int64_t after, int R, int nparts, double* part, double* C,
+                                   hipStream_t s);
 
 }  // namespace ppk
 

@@ -238,15 +238,17 @@ def test_pp_tucker_run_matches_oracle(shape, R, sweeps):
 
 
 @pytest.mark.parametrize("shape,R", [((16, 1031, 1021), 5), ((11, 13, 97, 1001), 3),
-                                     ((12, 1101, 999), 8)])
+                                     ((12, 1101, 999), 8), ((40, 9, 10, 11, 300), 4)])
 def test_small_rank_vector_contractions_match_oracle(shape, R):
     """Contractions of more than 2^20 rows over an odd trailing extent at R <= 8 run on the
     vector-unit kernel: the prefix X x_0 A^(0)T at every size (K = 16, 11, 12: steps of 4
     with remainders 0, 3, 0) and at order 4 the first step of mode 0's chain, X x_1
     A^(1)T (K = 13, remainder 1; 11 slices of an odd trailing extent 97097, so a wave's
     rows cross slices); no row count is a multiple of the 1024 rows of a workgroup.  The
-    HOSVDs' product X_(0) Z (16, 11 and 12 rows of more than 2^20 contiguous k) runs on the
-    rows kernel (k split over workgroups, the parts added in order).  TTMc of every mode,
+    HOSVDs' product X_(0) Z (16, 11 and 12 rows of more than 2^20 contiguous k) and the
+    classical HOSVD's X_(n) Z for the inner modes of 13 rows at order 4 and of 9, 10 and 11
+    rows at order 5 (row strides 97097, 33000, 3300 and 300) run on the rows kernel (k
+    split over workgroups, the parts added in order).  TTMc of every mode,
     two HOOI sweeps, the classical and the interlaced HOSVD and a PP-Tucker run
     (eps = 0.3) against the oracle."""
     r = TRun(shape, R, seed=17, eta=0.05)
