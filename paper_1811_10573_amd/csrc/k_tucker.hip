@@ -1244,16 +1244,15 @@ hipError_t launch_ttm_small_r(const double* T, const double* F, int64_t M, int64
 // the product of the sizes after n, so T[m][k] sits at (k / after) M after + m after +
 // k mod after; after = K when n is first).  The matrix-core kernel pads M to 128-row
 // tiles and R to 16 columns there (11.7 times the useful multiply-adds at M = 35, R = 5).
-// Here workgroup
-// z takes k in [z kper, (z + 1) kper), in blocks of TR_THREADS TR_KPT: thread t holds F's
-// rows k = k0 + t + TR_THREADS i (i < TR_KPT) in registers and, row by row, loads
-// T[m][k] for them (consecutive lanes on consecutive k: one 512-byte run per load
-// instruction while k mod after runs on), the next row's loads issued before this row's
-// multiply-adds; the R
-// per-lane sums of a row are added across the wave by a butterfly and wave w's lane 0
-// adds them to its own LDS slot [w][m][r].  At the end the slots are added in wave order
-// into part[z] (M x R); a second launch adds the workgroups' parts in z order.  k past
-// the range reads a valid entry of the range with F's row taken as zero.
+// Here workgroup z takes k in [z kper, (z + 1) kper), in blocks of TR_THREADS TR_KPT:
+// thread t holds F's rows k = k0 + t + TR_THREADS i (i < TR_KPT) in registers and, row by
+// row, loads T[m][k] for them (consecutive lanes on consecutive k: one 512-byte run per
+// load instruction while k mod after runs on), the next row's loads issued before this
+// row's multiply-adds; the R per-lane sums of a row are added across the wave by a
+// butterfly and wave w's lane 0 adds them to its own LDS slot [w][m][r].  At the end the
+// slots are added in wave order into part[z] (M x R); a second launch adds the
+// workgroups' parts in z order.  k past the range reads a valid entry of the range with
+// F's row taken as zero.
 constexpr int TR_KPT = 8, TR_THREADS = 256, TR_WAVES = TR_THREADS / 64;
 constexpr int64_t TR_KBLOCK = (int64_t)TR_THREADS * TR_KPT;
 
