@@ -83,7 +83,3 @@ def dt_als_level1_flops(shape, R):
     equidimensional tensor (Section 2.5)."""
     return 4 * R * prod(shape)
 
-
-def pp_approx_flops_formula(s, N, R):
-    """Table 1: one PP-approximated sweep costs 2 N^2 (s^2 R + s R^2)."""
-    return 2 * N * N * (s * s * R + s * R * R)
