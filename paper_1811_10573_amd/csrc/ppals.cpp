@@ -568,9 +568,11 @@ double model_build_ms(const ppals_desc* d, int l) {
           const double b = nX * xsz / (0.6 * 8e12);
           t += std::max(f, b);
         } else {
-          // parent: modes i, j, one more below lv + 1, and the tail
+          // parent: modes i, j, the mode w the tree rule contracts (build_pp: lv while
+          // j < lv, else lv - 1, or lv - 2 when i = lv - 1), and the tail
+          const int w = j < lv ? lv : (i == lv - 1 ? lv - 2 : lv - 1);
           const double parent = (double)d->dims[i] * d->dims[j] * tail * R *
-                                (double)d->dims[lv] * bulk;
+                                (double)d->dims[w] * bulk;
           t += parent / (0.55 * 8e12);
         }
       }

@@ -368,3 +368,41 @@ def test_direct_build_plan(lib):
     assert st == _lib.PPALS_E_UNSUPPORTED
     st, o3 = describe((s,) * 3, R, 0, 0, 2)
     assert st == 0 and o3["pp_build"] == "tree"
+
+
+@pytest.mark.parametrize("dims,R,tdt", [((128, 128, 3, 7200), 15, 1), ((1024, 1344, 33, 9), 50, 1),
+                                        ((40, 30, 20, 50, 10), 12, 0), ((9, 14, 6, 11, 7, 5), 8, 0)])
+def test_build_model_prices_the_scheduled_nodes(lib, dims, R, tdt):
+    """The cost model behind the automatic choice of combined levels (Section 3.2.3)
+    prices exactly the nodes the schedule builds: for every level count l, each
+    contraction of X at the slower of its MFMA time (0.6 of the tier's peak, 0.45 when
+    strided) and one read of X (0.6 of 8 TB/s), and each tree contraction by its parent's
+    size (elements = flops / 2) at 0.55 of 8 TB/s.  Unequal mode sizes tell the parents
+    apart: a parent priced with the wrong third mode misses by orders of magnitude."""
+    import json
+    from math import prod
+
+    def describe(levels):
+        d = _desc(dims, R, tdt, tdt)
+        d.pp_build_levels = levels
+        h = ctypes.c_void_p()
+        assert lib.ppals_plan_create(ctypes.byref(d), ctypes.byref(h)) == 0
+        buf = ctypes.create_string_buffer(1 << 20)
+        assert lib.ppals_plan_describe(h, buf, len(buf)) == 0
+        lib.ppals_plan_destroy(h)
+        return json.loads(buf.value.decode())
+
+    N = len(dims)
+    peak, xsz = (78.6e12, 8.0) if tdt == 0 else (157.3e12, 4.0)
+    model = describe(-1)["pp_build_model_ms"]
+    assert len(model) == N - 2
+    for l in range(1, N - 1):
+        plan = describe(l)
+        want = 0.0
+        for o in plan["pp_build_ops"]:
+            if o["op"] == "level1":
+                eff = 0.45 if (l >= 2 and o["strided"]) else 0.6
+                want += max(o["flops"] / (eff * peak), prod(dims) * xsz / (0.6 * 8e12))
+            elif o["op"] == "ttv" and o["out_mode"] == -1:
+                want += (o["flops"] / 2) * xsz / (0.55 * 8e12)
+        assert model[l - 1] == pytest.approx(want * 1e3, rel=2e-3), (l, model, want * 1e3)
