@@ -866,6 +866,9 @@ def main():
     ap.add_argument("--order", type=int, default=3)
     ap.add_argument("--shape", default=None,
                     help="comma-separated mode sizes (overrides --size and --order)")
+    ap.add_argument("--pp-build", default="auto", choices=["tree", "direct", "auto"],
+                    help="operator build of the PP-ALS run (orders >= 4): the PP tree, every "
+                         "operator straight from X, or the level count the plan's cost model picks")
     ap.add_argument("--dist", default="normal", choices=["normal", "uniform"],
                     help="distribution of the planted factors when --collinearity < 0")
     ap.add_argument("--eta", type=float, default=1e-3, help="relative noise level")
@@ -961,7 +964,9 @@ def main():
     log(f"generated in {time.perf_counter() - t0:.1f} s")
 
     tdt = "f64" if args.tier == "f64" else "f32"
-    plan = pp.Plan(shape, R, tdt, args.tier, True)
+    plan = pp.Plan(shape, R, tdt, args.tier, True, pp_build=args.pp_build)
+    build_levels = plan.describe()["pp_build_levels"]
+    log(f"operator build: {args.pp_build} -> {build_levels} combined level(s)")
     if args.device_gen:
         X = X64 if tdt == "f64" else X64.to(torch.float32)
     elif tdt == "f64":
@@ -1221,6 +1226,7 @@ def main():
                          f"{args.sweeps} sweeps per step"),
             "shape": list(shape), "rank": R, "eps": args.eps, "sweeps_per_step": args.sweeps,
             "tier": args.tier, "seed": args.seed,
+            "pp_build": args.pp_build, "pp_build_levels": build_levels,
             "generator": "device" if args.device_gen else "host",
         },
         "roofline": roof,

@@ -363,3 +363,49 @@ def test_paper_shaped_runs_match_oracle(dims, R, tier):
                              eps=0.1, sweeps=30, replay=kinds)
         sens32 = abs(oracle_fit(prob.X, A_pt) - f_or) / abs(f_or)
         assert abs(f_gpu - f_or) <= max(1e-5, 100 * sens32) * abs(f_or), (kinds, f_gpu, f_or, sens32)
+
+
+@pytest.mark.parametrize("build", ["tree", "direct"])
+def test_image_shaped_operators_at_full_size(build):
+    """The PP operators of the full-size image-shaped stand-in (128 x 128 x 3 x 7200,
+    R = 15, FP32; Section 3.2.3), built by the PP tree (a level-2 node of 7 GB) and
+    straight from X (first-level contractions over up to 128 x 7200 strided k), on
+    sampled entries (x_i, x_j, :) that include both ends of every mode.  Each entry is
+    the oracle's partial MTTKRP of the slice of X through (x_i, x_j).  Bound per entry:
+    Higham's gamma_K for the longest FP32 sum of the build, K * u32 times the same
+    contraction of |X| and |A|; and over the samples, the relative error within
+    30 sqrt(K) u32 (the typical accumulation error)."""
+    shape, R = (128, 128, 3, 7200), 15
+    prob = tensorgen.make_problem_device(shape, R, seed=7, eta=1e-2, dist="uniform", dtype="f32",
+                                         device=dev())
+    A = [fp32_round(a) for a in prob.init]
+    plan = pp.Plan(shape, R, "f32", "f32", True, pp_build=build)
+    assert plan.describe()["pp_build_levels"] == (1 if build == "tree" else 2)
+    ws = plan.workspace(dev())
+    pp.pp_build_operators(plan, prob.X.reshape(-1), None, [to_dev(a) for a in A], ws)
+    torch.cuda.synchronize()
+    Xh = prob.X.reshape(shape).cpu().numpy()
+    rng = np.random.default_rng(11)
+    for i in range(4):
+        for j in range(i + 1, 4):
+            out = torch.empty(shape[i] * shape[j] * R, dtype=torch.float32, device=dev())
+            pp.get_operator(plan, ws, i, j, out)
+            op = out.cpu().numpy().astype(np.float64).reshape(shape[i], shape[j], R)
+            K = max(shape) if build == "tree" else int(np.prod(shape)) // (shape[i] * shape[j])
+            picks = [(0, 0), (shape[i] - 1, shape[j] - 1)] + [
+                (int(rng.integers(shape[i])), int(rng.integers(shape[j]))) for _ in range(6)]
+            got, want = [], []
+            for xi, xj in picks:
+                idx = [slice(None)] * 4
+                idx[i], idx[j] = slice(xi, xi + 1), slice(xj, xj + 1)
+                sub = Xh[tuple(idx)].astype(np.float64)
+                Asub = list(A)
+                Asub[i], Asub[j] = A[i][xi:xi + 1], A[j][xj:xj + 1]
+                ref = ocp.partial_mttkrp(sub, Asub, (i, j)).reshape(R)
+                base = ocp.partial_mttkrp(np.abs(sub), [np.abs(a) for a in Asub], (i, j)).reshape(R)
+                assert_within(op[xi, xj], ref, (K + 12) * U32 * base,
+                              f"{build} operator ({i},{j}) entry ({xi},{xj})")
+                got.append(op[xi, xj])
+                want.append(ref)
+            err = rel(np.array(got), np.array(want))
+            assert err < 30 * np.sqrt(K) * U32, (build, i, j, err)
