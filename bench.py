@@ -281,7 +281,9 @@ def batch_leg(args, torch, dev, cpu=True, warmup=None):
     ms = sum(bk[f"ms_{bk['tile_rows']}"] for bk in tune["buckets"])
     achieved = nbytes / (ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
-            "frac": achieved / PEAK["hbm_GBs"], "traffic": None, "kernel": "k_b_gemm",
+            "frac": achieved / PEAK["hbm_GBs"],
+            "traffic": measured_traffic("k_b_gemm", None, None, None, workload=f"f32_batch{count}"),
+            "kernel": "k_b_gemm",
             "avg_ms": ms / 2, "work_per_launch": nbytes / 2,
             "TFLOP_s": flops / (ms * 1e-3) / 1e12}
     cpu_line = None
@@ -822,14 +824,17 @@ def ablation_bench(args, torch, dev):
 
 # source file of each kernel class whose HBM traffic has a committed counter summary
 # sources whose SHA-256 (of their concatenation, in this order) the counter summary names
-TRAFFIC_SOURCE = {"level1_gemm": ["k_level1.hip"], "pp_correct_ttv": ["k_ttv.hip", "tail_bodies.h"]}
+TRAFFIC_SOURCE = {"level1_gemm": ["k_level1.hip"], "pp_correct_ttv": ["k_ttv.hip", "tail_bodies.h"],
+                  "k_b_gemm": ["k_batch.hip"]}
 
 
-def measured_traffic(kernel, tier, shape, rank):
+def measured_traffic(kernel, tier, shape, rank, workload=None):
     """HBM bytes per launch from the committed counter summary of this kernel and
-    workload, or None when there is none or the kernel source changed since."""
+    workload (named by tier, shape and rank, or by ``workload``), or None when there is
+    none or the kernel source changed since."""
     import re
-    fn = os.path.join(ROOT, "profiles", f"{kernel}_{tier}_{'x'.join(map(str, shape))}_r{rank}_counters.md")
+    stem = workload if workload is not None else f"{tier}_{'x'.join(map(str, shape))}_r{rank}"
+    fn = os.path.join(ROOT, "profiles", f"{kernel}_{stem}_counters.md")
     if kernel not in TRAFFIC_SOURCE or not os.path.exists(fn):
         return None
     txt = open(fn).read()
