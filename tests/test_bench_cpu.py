@@ -40,7 +40,9 @@ def test_committed_summaries_name_their_sources():
     import re
     names = {"level1_gemm": "level1_gemm_f32_800x800x800_r50", "pp_correct_ttv": "pp_correct_ttv_f32_800x800x800_r50",
              "k_b_gemm": "k_b_gemm_f32_batch512"}
-    for kernel, stem in names.items():
+    stems = list(names.items()) + [("level1_gemm", "level1_gemm_f64_800x800x800_r50"),
+                                   ("pp_correct_ttv", "pp_correct_ttv_f64_800x800x800_r50")]
+    for kernel, stem in stems:
         assert kernel in bench.TRAFFIC_SOURCE
         txt = open(os.path.join(ROOT, "profiles", f"{stem}_counters.md")).read()
         assert re.search(r"hbm_bytes_per_launch:\s*[0-9.eE+]+", txt), stem
