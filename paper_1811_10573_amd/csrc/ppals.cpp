@@ -546,7 +546,8 @@ int add_direct_node(ppals_plan* p, int lv, int i, int j, int out_buf) {
 // mode of a parent each.  Modelled time, per node, from the rates the first-level kernel
 // and the multi-TTV reach here: a contraction of X at 0.6 of the tier's MFMA peak (0.45
 // when the contracted modes are not one block and the loads are strided) or 0.6 of 8 TB/s
-// for X, whichever is slower; a tree contraction at 0.55 of 8 TB/s for its parent.
+// for reading X and writing the node, whichever is slower; a tree contraction at 0.55 of
+// 8 TB/s for reading its parent and writing the node.
 double model_build_ms(const ppals_desc* d, int l) {
   const int N = d->order;
   double nX = 1.0;
@@ -565,15 +566,17 @@ double model_build_ms(const ppals_desc* d, int l) {
           // contracted modes {0..lv} minus {i, j}: one block unless i, j split them
           const bool block = (i == 0 && j == 1) || (j == lv && i == lv - 1) || (i == 0 && j == lv);
           const double f = 2.0 * nX * R / ((block || lv == 2 ? 0.6 : 0.45) * peak);
-          const double b = nX * xsz / (0.6 * 8e12);
+          // X read once, the node (modes i, j, the tail, the rank) written once
+          const double node = (double)d->dims[i] * d->dims[j] * tail * R;
+          const double b = (nX * xsz + node * bulk) / (0.6 * 8e12);
           t += std::max(f, b);
         } else {
           // parent: modes i, j, the mode w the tree rule contracts (build_pp: lv while
           // j < lv, else lv - 1, or lv - 2 when i = lv - 1), and the tail
           const int w = j < lv ? lv : (i == lv - 1 ? lv - 2 : lv - 1);
-          const double parent = (double)d->dims[i] * d->dims[j] * tail * R *
-                                (double)d->dims[w] * bulk;
-          t += parent / (0.55 * 8e12);
+          const double child = (double)d->dims[i] * d->dims[j] * tail * R * bulk;
+          const double parent = child * (double)d->dims[w];
+          t += (parent + child) / (0.55 * 8e12);
         }
       }
   }

@@ -376,8 +376,9 @@ def test_build_model_prices_the_scheduled_nodes(lib, dims, R, tdt):
     """The cost model behind the automatic choice of combined levels (Section 3.2.3)
     prices exactly the nodes the schedule builds: for every level count l, each
     contraction of X at the slower of its MFMA time (0.6 of the tier's peak, 0.45 when
-    strided) and one read of X (0.6 of 8 TB/s), and each tree contraction by its parent's
-    size (elements = flops / 2) at 0.55 of 8 TB/s.  Unequal mode sizes tell the parents
+    strided) and one read of X plus one write of the node (0.6 of 8 TB/s), and each tree
+    contraction by its parent (elements = flops / 2) read and its node (the parent over
+    the contracted extent) written at 0.55 of 8 TB/s.  Unequal mode sizes tell the parents
     apart: a parent priced with the wrong third mode misses by orders of magnitude."""
     import json
     from math import prod
@@ -402,7 +403,9 @@ def test_build_model_prices_the_scheduled_nodes(lib, dims, R, tdt):
         for o in plan["pp_build_ops"]:
             if o["op"] == "level1":
                 eff = 0.45 if (l >= 2 and o["strided"]) else 0.6
-                want += max(o["flops"] / (eff * peak), prod(dims) * xsz / (0.6 * 8e12))
+                want += max(o["flops"] / (eff * peak),
+                            (prod(dims) * xsz + o["M"] * R * xsz) / (0.6 * 8e12))
             elif o["op"] == "ttv" and o["out_mode"] == -1:
-                want += (o["flops"] / 2) * xsz / (0.55 * 8e12)
+                parent = o["flops"] / 2
+                want += (parent + parent / o["X"]) * xsz / (0.55 * 8e12)
         assert model[l - 1] == pytest.approx(want * 1e3, rel=2e-3), (l, model, want * 1e3)
